@@ -1,0 +1,400 @@
+"""Superfast-LSE estimator driver on top of the dense oracle numerics.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Follows the block-coordinate descent of Sec. II-C/E step by step:
+
+  1. activation (Sec. II-D "Component Activation"; the approximate scheme of
+     Sec. II-F for the first iterations),
+  2. zeta update (eq. zetaUpdate),
+  3. beta update (eq. betaUpdate, mu and Sigma by eqs. bmu / bSigma),
+  4. up to 5 x { one L-BFGS step on (theta, gamma) with a diagonal-Hessian
+     initialisation (Sec. II-D), deactivation by eq. deactivate },
+  stop when the objective changes by less than N * 1e-7 between iterations,
+
+followed by a final Newton-type polish of (theta, gamma) with z, beta, zeta
+held fixed.  The paper leaves several points open; each reading taken here is
+a field of :class:`Params` and is listed in DESIGN.md ("Readings").
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import numerics as nm
+
+
+@dataclass
+class Params:
+    L_mult: float = 8.0          # L = 2^round(log2(L_mult N)) (footnote, Sec. II-F)
+    tau: float = 5.0             # eq. activate_criterion
+    lbfgs_J: int = 10            # L-BFGS memory (Sec. II-D)
+    max_inner: int = 5           # step 4 repetitions (Sec. II-E)
+    max_outer: int = 200
+    tol_obj: float = 1e-7        # |L_i - L_{i-1}| < N tol_obj (Sec. II-E)
+    tol_newton: float = 1e-8     # squared Newton decrement < N tol_newton (Sec. II-E)
+    eps_beta_rel: float = 1e-10  # eps_beta = eps_beta_rel ||y||^2 / N
+    eps_L: float = 2.220446049250313e-16
+    approx_max_iters: int = 10   # iterations that may use the approximate scheme
+    approx_use_tau: bool = True
+    approx_ratio: float = 5.0    # Delta L <= Delta L_min / 5
+    approx_min_dist: float = 0.05  # wrap distance >= 0.05 / N
+    ls_c1: float = 1e-4
+    ls_max: int = 30
+    curv_eps: float = 1e-12
+    polish_max_iters: int = 30
+    polish_tol: float = 1e-12    # stop polish when max |dtheta| < polish_tol / N
+    polish_ftol: float = 1e-13   # relative objective slack for polish steps
+    kcap: int = 0                # 0: K_max = N
+
+    def grid_size(self, N: int) -> int:
+        return int(2 ** int(round(math.log2(self.L_mult * N))))
+
+
+STATUS_OK = 0
+STATUS_NOTCONV = 1
+STATUS_ECAPACITY = -5
+
+
+@dataclass
+class Result:
+    K: int
+    theta: np.ndarray
+    alpha: np.ndarray
+    gamma: np.ndarray
+    beta: float
+    zeta: float
+    objective: float
+    iterations: int
+    evaluations: int
+    status: int
+    trace: list = field(default_factory=list)
+
+
+class _Memory:
+    """L-BFGS curvature pairs (Nocedal & Wright, Alg. 7.4) with a diagonal H0."""
+
+    def __init__(self, J: int):
+        self.J = J
+        self.S: list[np.ndarray] = []
+        self.Y: list[np.ndarray] = []
+
+    def reset(self):
+        self.S.clear()
+        self.Y.clear()
+
+    def push(self, s, y, eps):
+        sy = float(np.dot(s, y))
+        if sy > eps * float(np.linalg.norm(s)) * float(np.linalg.norm(y)):
+            self.S.append(s.copy())
+            self.Y.append(y.copy())
+            if len(self.S) > self.J:
+                self.S.pop(0)
+                self.Y.pop(0)
+
+    def direction(self, g, h):
+        qv = g.copy()
+        alphas = []
+        for s, y in zip(reversed(self.S), reversed(self.Y)):
+            rho = 1.0 / float(np.dot(y, s))
+            a = rho * float(np.dot(s, qv))
+            alphas.append((a, rho))
+            qv = qv - a * y
+        r = qv / h
+        for (s, y), (a, rho) in zip(zip(self.S, self.Y), reversed(alphas)):
+            b = rho * float(np.dot(y, r))
+            r = r + (a - b) * s
+        return -r
+
+
+class OracleEstimator:
+    def __init__(self, y, params: Params | None = None, check_blocks: bool = False):
+        self.check_blocks = check_blocks
+        self.y = np.asarray(y, dtype=np.complex128)
+        self.N = len(self.y)
+        self.p = params or Params()
+        self.L = self.p.grid_size(self.N)
+        self.kcap = self.N if self.p.kcap <= 0 else min(self.p.kcap, self.N)
+        self.n_evals = 0
+        self.cap_hit = False
+        self.trace: list = []
+
+    # ------------------------------------------------------------------
+    def _block(self, name, before, after):
+        """Debug aid: objective before/after a block update (each a tuple
+        (theta, gamma, beta, zeta)); recorded only with check_blocks."""
+        if not self.check_blocks:
+            return
+        fb, fa = (nm.Evaluation(self.y, t, g, b).f(len(t), z) for (t, g, b, z) in (before, after))
+        self.trace.append(("block", name, fb, fa))
+
+    def evaluate(self, theta, gamma, beta) -> nm.Evaluation:
+        self.n_evals += 1
+        return nm.Evaluation(self.y, theta, gamma, beta)
+
+    def _derivs(self, ev: nm.Evaluation, gamma):
+        gth, gga = nm.gradient(gamma, ev.act)
+        hth, hga = nm.hessian_diag(gamma, ev.act)
+        N = self.N
+        hth = np.where(hth > 0, hth, (50.0 * N) ** 2)
+        safe_g = np.where(gamma > 0, gamma, 1.0)
+        hga = np.where(hga > 0, hga, safe_g ** -2.0)
+        return np.concatenate([gth, gga]), np.concatenate([hth, hga])
+
+    def _gbar(self, gamma):
+        return float(np.mean(gamma)) if len(gamma) else None
+
+    def _decision_quantities(self, q, s, gamma, zeta):
+        """(gbar used, gamma_hat, Delta L, criterion with tau, criterion tau-free)."""
+        gh = float(nm.gamma_hat(q, s))
+        gb = self._gbar(gamma)
+        if gb is None:       # empty active set: per-theta optimum (reading R4)
+            gb = gh
+        dl = float(nm.delta_L(q, s, gb, zeta))
+        return gb, gh, dl
+
+    def _grid_delta_L(self, ev: nm.Evaluation, gamma, zeta):
+        qG, sG = ev.grid(self.L)
+        gb = self._gbar(gamma)
+        if gb is None:
+            gbv = nm.gamma_hat(qG, sG)
+        else:
+            gbv = np.full(self.L, gb)
+        return qG, sG, nm.delta_L(qG, sG, gbv, zeta)
+
+    # ------------------------------------------------------------------
+    def _exact_activation_round(self, ev, theta, gamma, zeta):
+        """One pass of step 1: argmin of Delta L on the grid, accept or stop."""
+        p = self.p
+        qG, sG, dl = self._grid_delta_L(ev, gamma, zeta)
+        l = int(np.argmin(dl))                       # lowest index on ties
+        th = l / self.L
+        q = complex(nm.q_at(ev.w, [th])[0])
+        s = float(nm.s_at(ev.omega[0], [th])[0])
+        gb, gh, dlv = self._decision_quantities(q, s, gamma, zeta)
+        ok = (gh > 0 and zeta > 0
+              and bool(nm.activation_criterion(q, s, gb, zeta, p.tau)) and dlv < -p.eps_L)
+        self.trace.append(("exact", l, dlv, ok))
+        if ok and len(theta) >= self.kcap:
+            self.cap_hit = True
+            return None
+        if ok:
+            return th, gh
+        return None
+
+    def _approx_activation(self, ev, theta, gamma, zeta):
+        """Approximate scheme of Sec. II-F: all local minima of Delta L passing 4 filters."""
+        p = self.p
+        N, L = self.N, self.L
+        qG, sG, dl = self._grid_delta_L(ev, gamma, zeta)
+        lmin = int(np.argmin(dl))
+        locmin = np.nonzero((dl <= np.roll(dl, 1)) & (dl <= np.roll(dl, -1)))[0]
+        th_all = np.concatenate([[lmin / L], locmin / L])
+        q_all = nm.q_at(ev.w, th_all)
+        s_all = nm.s_at(ev.omega[0], th_all)
+        _, _, dl_min = self._decision_quantities(q_all[0], s_all[0], gamma, zeta)
+        cands = []
+        tau = p.tau if p.approx_use_tau else 0.0
+        for j, l in enumerate(locmin):
+            q, s = q_all[j + 1], s_all[j + 1]
+            gb, gh, dlv = self._decision_quantities(q, s, gamma, zeta)
+            if (gh > 0 and zeta > 0 and bool(nm.activation_criterion(q, s, gb, zeta, tau))
+                    and dlv <= dl_min / p.approx_ratio):
+                cands.append((dlv, int(l), gh))
+        cands.sort()
+        new_th, new_g = [], []
+        for dlv, l, gh in cands:
+            if len(theta) + len(new_th) >= self.kcap:
+                self.cap_hit = True
+                break
+            th = l / L
+            others = np.concatenate([np.asarray(theta), np.asarray(new_th)])
+            if len(others) == 0 or float(np.min(nm_wrap(th, others))) >= p.approx_min_dist / N:
+                new_th.append(th)
+                new_g.append(gh)
+        self.trace.append(("approx", len(locmin), len(cands), len(new_th)))
+        return new_th, new_g
+
+    # ------------------------------------------------------------------
+    def _line_search(self, ev, theta, gamma, beta, K, zeta, g, d, polish=False):
+        p = self.p
+        f0 = ev.f(K, zeta)
+        gd = float(np.dot(g, d))
+        dth, dga = d[:K], d[K:]
+        neg = dga < 0
+        amax = math.inf
+        kstar = -1
+        if np.any(neg):
+            ratios = np.where(neg, gamma / np.where(neg, -dga, 1.0), math.inf)
+            kstar = int(np.argmin(ratios))
+            amax = float(ratios[kstar])
+        if polish:
+            alpha = 1.0 if amax > 1.0 else 0.5 * amax
+        else:
+            alpha = min(1.0, amax)
+        slack = p.polish_ftol * (1.0 + abs(f0)) if polish else 0.0
+        for _ in range(p.ls_max):
+            th_t = np.mod(theta + alpha * dth, 1.0)
+            ga_t = np.maximum(gamma + alpha * dga, 0.0)
+            if (not polish) and alpha == amax and kstar >= 0:
+                ga_t[kstar] = 0.0
+            ev_t = self.evaluate(th_t, ga_t, beta)
+            f_t = ev_t.f(K, zeta)
+            if f_t <= f0 + p.ls_c1 * alpha * gd + slack:
+                return ev_t, th_t, ga_t, alpha
+            alpha *= 0.5
+        return None
+
+    def _direction(self, mem, g, h):
+        d = mem.direction(g, h)
+        if not np.all(np.isfinite(d)) or float(np.dot(g, d)) >= 0.0:
+            mem.reset()
+            d = -g / h
+        return d
+
+    # ------------------------------------------------------------------
+    def run(self) -> Result:
+        p, N, y = self.p, self.N, self.y
+        yy = float(np.vdot(y, y).real)
+        if yy == 0.0:
+            return Result(0, np.zeros(0), np.zeros(0, np.complex128), np.zeros(0), 0.0, 0.0,
+                          -math.inf, 0, 0, STATUS_OK)
+        beta = 0.01 * yy / N                      # initialisation (Sec. II-E)
+        zeta = 0.2
+        eps_beta = p.eps_beta_rel * yy / N
+        theta = np.zeros(0)
+        gamma = np.zeros(0)
+        approx_on = p.approx_max_iters > 0
+        L_prev = math.inf
+        mem = _Memory(p.lbfgs_J)
+        z_changed = True
+        cur = None
+        it = 0
+        converged = False
+
+        def ensure(ev):
+            return ev if ev is not None else self.evaluate(theta, gamma, beta)
+
+        for it in range(1, p.max_outer + 1):
+            # ---- step 1: activation ------------------------------------
+            run_exact = True
+            if approx_on and it <= p.approx_max_iters:
+                cur = ensure(cur)
+                new_th, new_g = self._approx_activation(cur, theta, gamma, zeta)
+                if new_th:
+                    self._block("approx", (theta, gamma, beta, zeta),
+                                (np.concatenate([theta, new_th]), np.concatenate([gamma, new_g]),
+                                 beta, zeta))
+                    theta = np.concatenate([theta, new_th])
+                    gamma = np.concatenate([gamma, new_g])
+                    cur = None
+                    z_changed = True
+                    run_exact = False
+                else:
+                    approx_on = False
+            if run_exact:
+                while True:
+                    cur = ensure(cur)
+                    got = self._exact_activation_round(cur, theta, gamma, zeta)
+                    if got is None:
+                        break
+                    self._block("activate", (theta, gamma, beta, zeta),
+                                (np.append(theta, got[0]), np.append(gamma, got[1]), beta, zeta))
+                    theta = np.append(theta, got[0])
+                    gamma = np.append(gamma, got[1])
+                    cur = None
+                    z_changed = True
+            K = len(theta)
+            # ---- step 2: zeta ------------------------------------------
+            self._block("zeta", (theta, gamma, beta, zeta), (theta, gamma, beta, min(0.5, K / N)))
+            zeta = min(0.5, K / N)
+            # ---- step 3: beta (EM bound) ----------------------------------
+            beta_new = nm.beta_update_definition(y, theta, gamma, beta, eps_beta)
+            self._block("beta", (theta, gamma, beta, zeta), (theta, gamma, beta_new, zeta))
+            if beta_new != beta:
+                beta = beta_new
+                cur = None
+            # ---- step 4: L-BFGS + deactivation ---------------------------
+            if z_changed:
+                mem.reset()
+                z_changed = False
+            for _inner in range(p.max_inner):
+                K = len(theta)
+                if K == 0:
+                    break
+                cur = ensure(cur)
+                g, h = self._derivs(cur, gamma)
+                d = self._direction(mem, g, h)
+                lam2 = -float(np.dot(g, d))
+                ls = self._line_search(cur, theta, gamma, beta, K, zeta, g, d)
+                if ls is None:
+                    self.trace.append(("ls_fail", it))
+                    break
+                ev_t, th_t, ga_t, alpha = ls
+                g_t, _ = self._derivs(ev_t, ga_t)
+                mem.push(alpha * d, g_t - g, p.curv_eps)
+                self._block("lbfgs", (theta, gamma, beta, zeta), (th_t, ga_t, beta, zeta))
+                theta, gamma, cur = th_t, ga_t, ev_t
+                # 4b: deactivation, one component at a time (largest margin first)
+                while len(theta) > 0:
+                    marg = nm.deactivation_margin(cur.act["q"], cur.act["s"].real, gamma, zeta)
+                    k = int(np.argmax(marg))
+                    if not marg[k] > 0:
+                        break
+                    self.trace.append(("deact", it, float(theta[k])))
+                    self._block("deact", (theta, gamma, beta, zeta),
+                                (np.delete(theta, k), np.delete(gamma, k), beta, zeta))
+                    theta = np.delete(theta, k)
+                    gamma = np.delete(gamma, k)
+                    mem.reset()
+                    cur = ensure(None)
+                if lam2 < N * p.tol_newton:
+                    break
+            # ---- termination ---------------------------------------------
+            K = len(theta)
+            cur = ensure(cur)
+            L_cur = cur.f(K, zeta)
+            self.trace.append(("iter", it, K, L_cur, beta))
+            if abs(L_cur - L_prev) < N * p.tol_obj:
+                converged = True
+                break
+            L_prev = L_cur
+
+        # ---- final polish of (theta, gamma) with z, beta, zeta fixed ---------
+        mem.reset()
+        cur = ensure(cur)
+        for _pit in range(p.polish_max_iters):
+            K = len(theta)
+            if K == 0:
+                break
+            g, h = self._derivs(cur, gamma)
+            d = self._direction(mem, g, h)
+            ls = self._line_search(cur, theta, gamma, beta, K, zeta, g, d, polish=True)
+            if ls is None:
+                break
+            ev_t, th_t, ga_t, alpha = ls
+            g_t, _ = self._derivs(ev_t, ga_t)
+            mem.push(alpha * d, g_t - g, p.curv_eps)
+            theta, gamma, cur = th_t, ga_t, ev_t
+            if float(np.max(np.abs(alpha * d[:K]))) < p.polish_tol / N:
+                break
+
+        K = len(theta)
+        alpha_hat = gamma * cur.act["q"] if K else np.zeros(0, np.complex128)
+        order = np.argsort(theta, kind="stable")
+        status = STATUS_OK if converged else STATUS_NOTCONV
+        if self.cap_hit:
+            status = STATUS_ECAPACITY
+        return Result(K, theta[order], alpha_hat[order], gamma[order], beta, zeta,
+                      cur.f(K, zeta), it, self.n_evals, status, self.trace)
+
+
+def nm_wrap(x, arr):
+    a = np.abs(np.asarray(arr, dtype=np.float64) - x) % 1.0
+    return np.minimum(a, 1.0 - a)
+
+
+def estimate(y, params: Params | None = None, check_blocks: bool = False) -> Result:
+    return OracleEstimator(y, params, check_blocks).run()

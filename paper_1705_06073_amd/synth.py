@@ -1,0 +1,175 @@
+"""Seeded synthetic signals for the line-spectral-estimation workloads.
+
+This module only draws inputs: frequencies, coefficients, noise and the
+observation y = sum_k alpha_k psi(theta_k) + w of the signal model (Sec. II,
+eq. "model", complete-data case Phi = I).  It holds none of the estimator's
+arithmetic, so the CPU oracle and the HIP path can both consume its output.
+
+Conventions
+-----------
+* psi(theta)_n = exp(j 2 pi n theta), n = 0..N-1 (the paper's 1-indexed
+  exp(j2pi(n-1)theta) shifted to 0-indexing).
+* Frequencies are drawn sequentially, each uniform on the part of [0,1) whose
+  wrap-around distance to every earlier frequency exceeds ``sep``
+  (Sec. VI-A; the wrap-around distance is the one of the footnote in Sec. II-F).
+* SNR is ||Psi alpha||^2 / (N beta) of the realised signal (Sec. VI-A);
+  an instance with K = 0 gets beta = 1.
+* Seeds: 1705060730 + 1_000_000 * config + instance, PCG64.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 1705060730
+
+
+def seed_for(config: int, instance: int) -> int:
+    return SEED_BASE + 1_000_000 * int(config) + int(instance)
+
+
+def wrap_distance(x, y):
+    """d(x, y) = min(|x - y|, 1 - |x - y|) on [0, 1)."""
+    a = np.abs(np.asarray(x, dtype=np.float64) - np.asarray(y, dtype=np.float64))
+    a = np.mod(a, 1.0)
+    return np.minimum(a, 1.0 - a)
+
+
+def draw_frequencies(rng: np.random.Generator, K: int, sep: float,
+                     max_tries: int = 10_000) -> np.ndarray:
+    """Sequential rejection sampling with minimum wrap-around separation."""
+    while True:
+        th: list[float] = []
+        ok = True
+        for _ in range(K):
+            for _try in range(max_tries):
+                cand = rng.random()
+                if all(wrap_distance(cand, t) > sep for t in th):
+                    th.append(cand)
+                    break
+            else:
+                ok = False
+                break
+        if ok:
+            return np.array(th, dtype=np.float64)
+
+
+def draw_alpha(rng: np.random.Generator, K: int, kind: str) -> np.ndarray:
+    """Coefficient distributions of the workloads.
+
+    * ``cn``: alpha ~ CN(0, 1).
+    * ``paper``: a ~ CN with standard deviation 0.8, alpha = a + 0.2 e^{j arg a}
+      (Sec. VI-A), so |alpha| >= 0.2.
+    * ``logamp20``: |alpha| = 10^{-U(0,1)} (20 dB power range), uniform phase.
+    """
+    if kind == "cn":
+        return (rng.standard_normal(K) + 1j * rng.standard_normal(K)) / math.sqrt(2.0)
+    if kind == "paper":
+        a = 0.8 * (rng.standard_normal(K) + 1j * rng.standard_normal(K)) / math.sqrt(2.0)
+        return a + 0.2 * np.exp(1j * np.angle(a))
+    if kind == "logamp20":
+        mag = 10.0 ** (-rng.random(K))
+        ph = 2.0 * math.pi * rng.random(K)
+        return mag * np.exp(1j * ph)
+    raise ValueError(f"unknown alpha kind {kind!r}")
+
+
+def clean_signal(theta: np.ndarray, alpha: np.ndarray, N: int) -> np.ndarray:
+    """h = Psi(theta) alpha, built term by term in FP64."""
+    n = np.arange(N, dtype=np.float64)
+    h = np.zeros(N, dtype=np.complex128)
+    for th, al in zip(theta, alpha):
+        # exact reduction of n*theta mod 1 keeps the phase accurate at large N
+        ph = np.mod(n * th, 1.0)
+        h += al * np.exp(2j * math.pi * ph)
+    return h
+
+
+@dataclass
+class Instance:
+    N: int
+    K: int
+    theta: np.ndarray
+    alpha: np.ndarray
+    beta: float
+    snr_db: float
+    y: np.ndarray           # complex128 or complex64, as the workload states
+    seed: int = 0
+    meta: dict = field(default_factory=dict)
+
+
+def make_instance(rng: np.random.Generator, N: int, K: int, sep: float,
+                  alpha_kind: str, snr_db: float, dtype=np.complex128,
+                  seed: int = 0) -> Instance:
+    theta = draw_frequencies(rng, K, sep) if K > 0 else np.zeros(0)
+    alpha = draw_alpha(rng, K, alpha_kind) if K > 0 else np.zeros(0, np.complex128)
+    h = clean_signal(theta, alpha, N)
+    if K > 0 and math.isfinite(snr_db):
+        beta = float(np.vdot(h, h).real / (N * 10.0 ** (snr_db / 10.0)))
+    elif K > 0:
+        beta = 0.0
+    else:
+        beta = 1.0
+    w = math.sqrt(beta / 2.0) * (rng.standard_normal(N) + 1j * rng.standard_normal(N))
+    y = (h + w).astype(dtype)
+    return Instance(N=N, K=K, theta=theta, alpha=alpha, beta=beta, snr_db=snr_db,
+                    y=y, seed=seed)
+
+
+# ---------------------------------------------------------------------------
+# The workloads.  Config numbering: 0 = small single instance (N=64),
+# 1 = single instance N=1024, 2 = batch of 256 at N=4096, 3 = uneven batch,
+# 4 = serving stream.
+# ---------------------------------------------------------------------------
+
+def workload_n64(instance: int = 0) -> Instance:
+    """N=64, K=3, separation 1/N, alpha ~ CN(0,1), SNR 20 dB, complex128."""
+    s = seed_for(0, instance)
+    rng = np.random.Generator(np.random.PCG64(s))
+    return make_instance(rng, 64, 3, 1.0 / 64, "cn", 20.0, np.complex128, s)
+
+
+def workload_n1024(instance: int = 0) -> Instance:
+    """N=1024, K=20, separation 2/N, |alpha| over 20 dB, SNR 15 dB, complex64."""
+    s = seed_for(1, instance)
+    rng = np.random.Generator(np.random.PCG64(s))
+    return make_instance(rng, 1024, 20, 2.0 / 1024, "logamp20", 15.0, np.complex64, s)
+
+
+def workload_n4096(instance: int) -> Instance:
+    """N=4096, K ~ Poisson(40), separation 1/N, alpha ~ CN(0,1), SNR ~ U[0,30] dB."""
+    s = seed_for(2, instance)
+    rng = np.random.Generator(np.random.PCG64(s))
+    K = int(rng.poisson(40))
+    snr = float(rng.uniform(0.0, 30.0))
+    return make_instance(rng, 4096, K, 1.0 / 4096, "cn", snr, np.complex128, s)
+
+
+def workload_uneven(instance: int) -> Instance:
+    """N log-uniform on [128, 16384], K ~ Poisson(N/64), SNR ~ U[5,30] dB."""
+    s = seed_for(3, instance)
+    rng = np.random.Generator(np.random.PCG64(s))
+    N = int(round(math.exp(rng.uniform(math.log(128), math.log(16384)))))
+    K = int(rng.poisson(N / 64.0))
+    snr = float(rng.uniform(5.0, 30.0))
+    return make_instance(rng, N, K, 1.0 / N, "cn", snr, np.complex128, s)
+
+
+def workload_paper_snr(instance: int, snr_db: float, N: int = 128, K: int = 10) -> Instance:
+    """The accuracy-vs-SNR experiment: N=128, K=10, separation 2/N, paper's alpha."""
+    s = seed_for(7, instance) + int(round(snr_db * 1000))
+    rng = np.random.Generator(np.random.PCG64(s))
+    return make_instance(rng, N, K, 2.0 / N, "paper", snr_db, np.complex128, s)
+
+
+def pack_batch(instances, dtype=np.complex128):
+    """Concatenate y of a ragged batch; returns (y_flat, n, off)."""
+    n = np.array([inst.N for inst in instances], dtype=np.int64)
+    off = np.zeros(len(instances), dtype=np.int64)
+    if len(instances) > 1:
+        off[1:] = np.cumsum(n)[:-1]
+    y = np.concatenate([inst.y.astype(dtype) for inst in instances]) if instances else \
+        np.zeros(0, dtype)
+    return y, n, off
