@@ -1,0 +1,220 @@
+/*
+ * sfls.h -- C ABI of the MI355X (gfx950) superfast line-spectral-estimation
+ * library.
+ *
+ * The method is T. L. Hansen, B. H. Fleury, B. D. Rao, "Superfast Line
+ * Spectral Estimation", IEEE Trans. Signal Process., 2018 (complete-data
+ * case, Phi = I, M = N).  Given y in C^N the estimator returns the model order
+ * K, frequencies theta_k in [0,1), amplitudes alpha_k and the noise variance
+ * beta (Sec. II-A problem statement; alpha = gamma .* q, Sec. II-B footnote).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - psi(theta)_n = exp(j 2 pi n theta), n = 0..N-1 (0-indexed form of Sec. II-A).
+ *  - Complex data are interleaved (re, im) pairs: "c128" = 2 doubles per
+ *    element, "c64" = 2 floats per element.
+ *  - Ragged batches: instance b occupies elements [off[b], off[b] + n[b]) of
+ *    every flat per-sample array.  n[] and off[] (and every other array whose
+ *    description says "host") are HOST arrays read synchronously; all data
+ *    arrays are DEVICE pointers on the context's device.
+ *  - All work is enqueued on `stream` (a hipStream_t, NULL = the legacy
+ *    default stream) and is asynchronous: outputs are valid once the stream
+ *    has been synchronised.  The caller owns every buffer it passes; the
+ *    library owns its workspace (kept in the context, grown on demand).
+ *  - Argument errors are detected on the host before anything is enqueued
+ *    and return SFLS_EINVAL with a message retrievable by sfls_last_error().
+ *    Numerical failures are reported per instance through `status` arrays.
+ *  - A context is not thread-safe; use one context per host thread.  Calls
+ *    on one context must not overlap (they share its workspace).
+ */
+#ifndef SFLS_H
+#define SFLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SFLS_OK = 0,
+    SFLS_NOTCONV = 1,     /* per instance: iteration cap reached, estimate returned */
+    SFLS_EINVAL = -1,     /* bad argument (host-side check) */
+    SFLS_ENOMEM = -2,     /* device allocation failed */
+    SFLS_EDEVICE = -3,    /* HIP runtime error */
+    SFLS_ENOTPD = -4,     /* per instance: Toeplitz matrix not positive definite */
+    SFLS_ECAPACITY = -5,  /* per instance: more components wanted than kcap */
+    SFLS_EUNSUPPORTED = -6 /* size outside what this build handles */
+} sfls_status;
+
+typedef enum { SFLS_FP64 = 0, SFLS_MIXED = 1 } sfls_precision; /* MIXED: FP32 grid FFTs */
+typedef enum { SFLS_C64 = 0, SFLS_C128 = 1 } sfls_dtype;
+
+/* Largest N accepted by the factorisation kernels of this build. */
+#define SFLS_MAX_N 4096
+
+typedef struct sfls_ctx sfls_ctx;
+
+/* Estimator parameters.  sfls_params_default() fills the paper's values:
+ * tau = 5 (eq. activate_criterion), J = 10 (Sec. II-D), at most 5 inner
+ * L-BFGS steps and a squared-Newton-decrement stop at N*1e-8, outer stop at
+ * |dL| < N*1e-7 (Sec. II-E), L = 2^round(log2(8N)) (footnote, Sec. II-F),
+ * approximate activation filters Delta L <= Delta L_min / 5 and wrap
+ * distance >= 0.05/N (Sec. II-F). */
+typedef struct {
+    double L_mult;          /* grid oversampling: L = 2^round(log2(L_mult*N)) */
+    double tau;             /* activation threshold adjustment */
+    int32_t lbfgs_J;        /* L-BFGS memory, 1..16 */
+    int32_t max_inner;      /* step-4 repetitions per outer iteration */
+    int32_t max_outer;      /* outer iteration cap (then status SFLS_NOTCONV) */
+    int32_t approx_max_iters; /* outer iterations that may use approximate activation (0: never) */
+    int32_t approx_use_tau; /* 1: tau in the approximate scheme's criterion */
+    int32_t ls_max;         /* backtracking trials per line search */
+    int32_t polish_max_iters; /* final (theta,gamma) polish iterations */
+    int32_t cand_cap;       /* max candidates re-checked per approximate sweep */
+    double tol_obj;         /* outer stop: |L_i - L_{i-1}| < N*tol_obj */
+    double tol_newton;      /* inner stop: lambda^2 < N*tol_newton */
+    double eps_beta_rel;    /* beta >= eps_beta_rel * ||y||^2 / N */
+    double eps_L;           /* activation needs Delta L < -eps_L */
+    double approx_ratio;    /* Delta L <= Delta L_min / approx_ratio */
+    double approx_min_dist; /* wrap distance >= approx_min_dist / N */
+    double ls_c1;           /* Armijo constant */
+    double curv_eps;        /* keep an L-BFGS pair only if s'y > curv_eps |s||y| */
+    double polish_tol;      /* polish stops when max |dtheta| < polish_tol / N */
+    double polish_ftol;     /* polish accepts f_new <= f + c1 a g'd + polish_ftol (1+|f|) */
+    int32_t precision;      /* sfls_precision of the grid stage */
+    int32_t reserved;
+} sfls_params;
+
+void sfls_params_default(sfls_params* p);
+
+/* Create a context on HIP device `device`.  Returns SFLS_EDEVICE if the
+ * device cannot be used. */
+sfls_status sfls_create(sfls_ctx** ctx, int device);
+sfls_status sfls_destroy(sfls_ctx* ctx);
+const char* sfls_strerror(sfls_status s);
+/* Message of the last error on this context ("" if none).  Valid until the
+ * next call on the context. */
+const char* sfls_last_error(const sfls_ctx* ctx);
+/* Library version string. */
+const char* sfls_version(void);
+
+/* ---------------------------------------------------------------------------
+ * a1. Toeplitz generator of the covariance (Sec. II-B eq. py; Sec. III):
+ *     c_i = beta [i = 0] + sum_k gamma_k exp(j 2 pi i theta_k), i = 0..N-1,
+ * the first column of C = beta I + Psi(theta) diag(gamma) Psi(theta)^H.
+ *   B instances; n/off (host) describe c; theta, gamma (device, f64) hold
+ *   K[b] entries from koff[b] (host arrays K, koff); beta (device, f64 [B]).
+ *   c (device, c128, sum n) is written.
+ * ------------------------------------------------------------------------- */
+sfls_status sfls_toeplitz_column(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                                 const int64_t* K, const int64_t* koff, const double* theta,
+                                 const double* gamma, const double* beta, double* c,
+                                 void* stream);
+
+/* ---------------------------------------------------------------------------
+ * a2. sfls_factor: Gohberg-Semencul generator of a Hermitian positive-definite
+ * Toeplitz matrix C with first column c (Sec. III, eq. gohberg-semencul):
+ *     C^{-1} = delta_{N-1}^{-1} (T1^H T1 - T0 T0^H),
+ *     [T0]_{ik} = rho_{i-k-1}, [T1]_{ik} = rho_{N-1+i-k}, rho_{N-1} = 1,
+ * computed by the Levinson-Durbin recursion (Sec. III, the O(N^2) option).
+ *   c      device c128 [sum n]   first columns; c_0 must be real and > 0
+ *   rho    device c128 [sum n]   out: generator rho_0..rho_{N-1}
+ *   delta  device f64  [sum n]   out: pivots delta_0..delta_{N-1} of C = L diag(delta) L^H
+ *   logdet device f64  [B]       out: ln|C| = sum_i ln delta_i (Sec. III-A)
+ *   status device i32  [B]       out: SFLS_OK or SFLS_ENOTPD
+ *   failed_step device i64 [B]   out: first step n with delta_n <= 0 (or -1)
+ * 1 <= n[b] <= SFLS_MAX_N, else SFLS_EUNSUPPORTED.
+ * ------------------------------------------------------------------------- */
+sfls_status sfls_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                        const double* c, double* rho, double* delta, double* logdet,
+                        int32_t* status, int64_t* failed_step, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * a4. w = C^{-1} y from the generator by four triangular-Toeplitz products
+ * done as FFT convolutions (Sec. III-A); yCy[b] = Re(y^H w), ww[b] = ||w||^2.
+ *   y device (ydtype) [sum n]; rho device c128; delta device f64 (only
+ *   delta_{N-1} of each instance is read); w device c128 out; yCy, ww device
+ *   f64 [B] out (either may be NULL).
+ * ------------------------------------------------------------------------- */
+sfls_status sfls_gs_apply(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                          const void* y, int32_t ydtype, const double* rho, const double* delta,
+                          double* w, double* yCy, double* ww, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * a5. Diagonal sums (Sec. III-C, eqs. omega_s, omega_t, omega_v, omega_x):
+ *   omega_s(i) = sum_q [C^{-1}]_{q,q+i},   omega_t: D C^{-1},
+ *   omega_v: D^2 C^{-1},  omega_x: D C^{-1} D,   D = diag(2 pi n),
+ * for lags i = -(N-1)..N-1, computed from (rho, delta_{N-1}) as FFT
+ * correlations of rho with its moment sequences n^a rho_n (Appendix B).
+ *   out device c128 [sum (2 n - 1)] per requested array (NULL = not wanted);
+ *   instance b writes 2n[b]-1 entries from oout[b] (host), lag i at i+n-1.
+ * ------------------------------------------------------------------------- */
+sfls_status sfls_omega(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                       const int64_t* oout, const double* rho, const double* delta,
+                       double* omega_s, double* omega_t, double* omega_v, double* omega_x,
+                       void* stream);
+
+/* ---------------------------------------------------------------------------
+ * a4-a7. sfls_grid_eval: everything the activation step needs on the grid
+ * theta^G_l = l/L (Sec. III-D):
+ *   q^G_l = psi^H(l/L) C^{-1} y,   s^G_l = psi^H(l/L) C^{-1} psi(l/L),
+ *   Delta L_l = ln((1 + gb s)(1-zeta)/zeta) - |q|^2/(gb^{-1} + s)  (eq. delta_L)
+ * with gb = gamma_bar[b] (> 0), or the per-point optimum of eq. activate_gamma
+ * when gamma_bar[b] <= 0 (empty active set), and argmin_l Delta L (lowest l
+ * on ties).
+ *   L (host i64 [B]) grid sizes: powers of two with L >= 2n-1;
+ *   goff (host i64 [B]) offsets of each instance's grid in qG/sG/dL.
+ *   qG c128 or c64, sG f64 or f32, dL f64 or f32 (per `precision`: FP64 or
+ *   MIXED = FP32 grid); any output may be NULL.  argmin i64 [B] and
+ *   argmin_val f64 [B] may be NULL.
+ * ------------------------------------------------------------------------- */
+sfls_status sfls_grid_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                           const void* y, int32_t ydtype, const double* rho, const double* delta,
+                           const int64_t* L, const int64_t* goff, const double* gamma_bar,
+                           const double* zeta, void* qG, void* sG, void* dL, int64_t* argmin,
+                           double* argmin_val, int32_t precision, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * a8. Active-set vectors at K[b] frequencies theta (Sec. II-D, eqs. q-x):
+ *   q = Psi^H w, r = Psi^H D w, u = Psi^H D^2 w,
+ *   s, t, v, x = diag(Psi^H {I, D, D^2, D .. D} C^{-1} Psi)
+ * from w = C^{-1} y and the generator (rho, delta).  Outputs are c128 device
+ * arrays of sum K entries (instance b from koff[b], host); NULL skips one.
+ * ------------------------------------------------------------------------- */
+sfls_status sfls_active_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                             const double* w, const double* rho, const double* delta,
+                             const int64_t* K, const int64_t* koff, const double* theta,
+                             double* q, double* r, double* u, double* s, double* t, double* v,
+                             double* x, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * a1-a9. sfls_estimate: the full estimator (Sec. II-C..F, Sec. III) for a
+ * ragged batch, every step in device kernels, state resident on the device
+ * across iterations.
+ *   y      device (ydtype) [sum n]  observations
+ *   params host (NULL = defaults)
+ *   kcap   host i64 [B]  capacity of instance b's component outputs (>= 1)
+ *   koff   host i64 [B]  offset of instance b's outputs in theta/alpha/gamma
+ *   K      device i64 [B]        out: model order
+ *   theta  device f64 [sum kcap] out: frequencies, ascending in [0,1)
+ *   alpha  device c128 [sum kcap] out: amplitudes gamma .* q (eq. bmu footnote)
+ *   gamma  device f64 [sum kcap] out: component variances
+ *   beta, zeta, objective device f64 [B] out
+ *   iters  device i32 [B] out: outer iterations;  evals device i32 [B] (may be NULL)
+ *   status device i32 [B] out: SFLS_OK, SFLS_NOTCONV, SFLS_ECAPACITY, SFLS_ENOTPD
+ * 2 <= n[b] <= SFLS_MAX_N.  The call returns after the batch has finished on
+ * `stream` (it polls a device completion counter between iterations).
+ * ------------------------------------------------------------------------- */
+sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                          const void* y, int32_t ydtype, const sfls_params* params,
+                          const int64_t* kcap, const int64_t* koff, int64_t* K, double* theta,
+                          double* alpha, double* gamma, double* beta, double* zeta,
+                          double* objective, int32_t* iters, int32_t* evals, int32_t* status,
+                          void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFLS_H */

@@ -1,0 +1,287 @@
+"""Superfast line spectral estimation on MI355X (gfx950).
+
+Thin ctypes binding of the C ABI declared in ``include/sfls.h``.  Every
+function here only marshals arguments: device buffers are torch tensors on
+the GPU (``data_ptr()``), sizes and offsets are host int64 arrays, and the
+work is enqueued on torch's current stream.  All arithmetic runs in the HIP
+kernels of ``lib/libsfls.so``; if that library is missing the binding raises
+instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libsfls.so")
+
+SFLS_OK, SFLS_NOTCONV = 0, 1
+SFLS_EINVAL, SFLS_ENOMEM, SFLS_EDEVICE, SFLS_ENOTPD, SFLS_ECAPACITY, SFLS_EUNSUPPORTED = \
+    -1, -2, -3, -4, -5, -6
+SFLS_FP64, SFLS_MIXED = 0, 1
+SFLS_C64, SFLS_C128 = 0, 1
+SFLS_MAX_N = 4096
+
+EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror",
+           "sfls_last_error", "sfls_version", "sfls_toeplitz_column", "sfls_factor",
+           "sfls_gs_apply", "sfls_omega", "sfls_grid_eval", "sfls_active_eval", "sfls_estimate"]
+
+
+class SflsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"sfls status {status}: {msg}")
+        self.status = status
+
+
+class sfls_params(ctypes.Structure):
+    _fields_ = [
+        ("L_mult", ctypes.c_double), ("tau", ctypes.c_double),
+        ("lbfgs_J", ctypes.c_int32), ("max_inner", ctypes.c_int32),
+        ("max_outer", ctypes.c_int32), ("approx_max_iters", ctypes.c_int32),
+        ("approx_use_tau", ctypes.c_int32), ("ls_max", ctypes.c_int32),
+        ("polish_max_iters", ctypes.c_int32), ("cand_cap", ctypes.c_int32),
+        ("tol_obj", ctypes.c_double), ("tol_newton", ctypes.c_double),
+        ("eps_beta_rel", ctypes.c_double), ("eps_L", ctypes.c_double),
+        ("approx_ratio", ctypes.c_double), ("approx_min_dist", ctypes.c_double),
+        ("ls_c1", ctypes.c_double), ("curv_eps", ctypes.c_double),
+        ("polish_tol", ctypes.c_double), ("polish_ftol", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64P = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsfls.so (built by ``python -m paper_1705_06073_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                           "(python -m paper_1705_06073_amd.build); there is no fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, st = ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+    L.sfls_params_default.argtypes = [ctypes.POINTER(sfls_params)]
+    L.sfls_params_default.restype = None
+    L.sfls_create.argtypes = [ctypes.POINTER(_P), ctypes.c_int]
+    L.sfls_create.restype = st
+    L.sfls_destroy.argtypes = [_P]
+    L.sfls_destroy.restype = st
+    L.sfls_strerror.argtypes = [st]
+    L.sfls_strerror.restype = ctypes.c_char_p
+    L.sfls_last_error.argtypes = [_P]
+    L.sfls_last_error.restype = ctypes.c_char_p
+    L.sfls_version.argtypes = []
+    L.sfls_version.restype = ctypes.c_char_p
+    L.sfls_toeplitz_column.argtypes = [_P, i64, _I64P, _I64P, _I64P, _I64P, _P, _P, _P, _P, _P]
+    L.sfls_toeplitz_column.restype = st
+    L.sfls_factor.argtypes = [_P, i64, _I64P, _I64P, _P, _P, _P, _P, _P, _P, _P]
+    L.sfls_factor.restype = st
+    L.sfls_gs_apply.argtypes = [_P, i64, _I64P, _I64P, _P, i32, _P, _P, _P, _P, _P, _P]
+    L.sfls_gs_apply.restype = st
+    L.sfls_omega.argtypes = [_P, i64, _I64P, _I64P, _I64P, _P, _P, _P, _P, _P, _P, _P]
+    L.sfls_omega.restype = st
+    L.sfls_grid_eval.argtypes = [_P, i64, _I64P, _I64P, _P, i32, _P, _P, _I64P, _I64P, _P, _P,
+                                 _P, _P, _P, _P, _P, i32, _P]
+    L.sfls_grid_eval.restype = st
+    L.sfls_active_eval.argtypes = [_P, i64, _I64P, _I64P, _P, _P, _P, _I64P, _I64P, _P,
+                                   _P, _P, _P, _P, _P, _P, _P, _P]
+    L.sfls_active_eval.restype = st
+    L.sfls_estimate.argtypes = [_P, i64, _I64P, _I64P, _P, i32, ctypes.POINTER(sfls_params),
+                                _I64P, _I64P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.sfls_estimate.restype = st
+    _lib = L
+    return L
+
+
+def default_params(**overrides) -> sfls_params:
+    p = sfls_params()
+    lib().sfls_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+# ------------------------------------------------------------------ helpers --
+
+def _i64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+
+
+def _hp(a: np.ndarray):
+    return a.ctypes.data_as(_I64P)
+
+
+def _dp(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device buffers must be GPU tensors")
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """Owns one sfls_ctx on a HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._h = _P()
+        st = lib().sfls_create(ctypes.byref(self._h), int(device))
+        if st != SFLS_OK:
+            raise SflsError(st, lib().sfls_strerror(st).decode())
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def check(self, st: int):
+        if st != SFLS_OK:
+            msg = lib().sfls_last_error(self._h).decode() or lib().sfls_strerror(st).decode()
+            raise SflsError(st, msg)
+
+    def close(self):
+        if self._h:
+            lib().sfls_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------- C-ABI mirrors ------
+
+def sfls_toeplitz_column(ctx: Context, n, off, K, koff, theta, gamma, beta, c, stream=None):
+    n, off, K, koff = _i64(n), _i64(off), _i64(K), _i64(koff)
+    ctx.check(lib().sfls_toeplitz_column(ctx.handle, len(n), _hp(n), _hp(off), _hp(K), _hp(koff),
+                                         _dp(theta), _dp(gamma), _dp(beta), _dp(c),
+                                         _stream(stream)))
+
+
+def sfls_factor(ctx: Context, n, off, c, rho, delta, logdet, status, failed_step, stream=None):
+    n, off = _i64(n), _i64(off)
+    ctx.check(lib().sfls_factor(ctx.handle, len(n), _hp(n), _hp(off), _dp(c), _dp(rho),
+                                _dp(delta), _dp(logdet), _dp(status), _dp(failed_step),
+                                _stream(stream)))
+
+
+def sfls_gs_apply(ctx: Context, n, off, y, ydtype, rho, delta, w, yCy=None, ww=None, stream=None):
+    n, off = _i64(n), _i64(off)
+    ctx.check(lib().sfls_gs_apply(ctx.handle, len(n), _hp(n), _hp(off), _dp(y), int(ydtype),
+                                  _dp(rho), _dp(delta), _dp(w), _dp(yCy), _dp(ww),
+                                  _stream(stream)))
+
+
+def sfls_omega(ctx: Context, n, off, oout, rho, delta, omega_s=None, omega_t=None, omega_v=None,
+               omega_x=None, stream=None):
+    n, off, oout = _i64(n), _i64(off), _i64(oout)
+    ctx.check(lib().sfls_omega(ctx.handle, len(n), _hp(n), _hp(off), _hp(oout), _dp(rho),
+                               _dp(delta), _dp(omega_s), _dp(omega_t), _dp(omega_v),
+                               _dp(omega_x), _stream(stream)))
+
+
+def sfls_grid_eval(ctx: Context, n, off, y, ydtype, rho, delta, L, goff, gamma_bar, zeta,
+                   qG=None, sG=None, dL=None, argmin=None, argmin_val=None,
+                   precision=SFLS_FP64, stream=None):
+    n, off, L, goff = _i64(n), _i64(off), _i64(L), _i64(goff)
+    ctx.check(lib().sfls_grid_eval(ctx.handle, len(n), _hp(n), _hp(off), _dp(y), int(ydtype),
+                                   _dp(rho), _dp(delta), _hp(L), _hp(goff), _dp(gamma_bar),
+                                   _dp(zeta), _dp(qG), _dp(sG), _dp(dL), _dp(argmin),
+                                   _dp(argmin_val), int(precision), _stream(stream)))
+
+
+def sfls_active_eval(ctx: Context, n, off, w, rho, delta, K, koff, theta, q=None, r=None, u=None,
+                     s=None, t=None, v=None, x=None, stream=None):
+    n, off, K, koff = _i64(n), _i64(off), _i64(K), _i64(koff)
+    ctx.check(lib().sfls_active_eval(ctx.handle, len(n), _hp(n), _hp(off), _dp(w), _dp(rho),
+                                     _dp(delta), _hp(K), _hp(koff), _dp(theta), _dp(q), _dp(r),
+                                     _dp(u), _dp(s), _dp(t), _dp(v), _dp(x), _stream(stream)))
+
+
+def sfls_estimate(ctx: Context, n, off, y, ydtype, params, kcap, koff, K, theta, alpha, gamma,
+                  beta, zeta, objective, iters, evals, status, stream=None):
+    n, off, kcap, koff = _i64(n), _i64(off), _i64(kcap), _i64(koff)
+    pp = ctypes.byref(params) if params is not None else None
+    ctx.check(lib().sfls_estimate(ctx.handle, len(n), _hp(n), _hp(off), _dp(y), int(ydtype), pp,
+                                  _hp(kcap), _hp(koff), _dp(K), _dp(theta), _dp(alpha),
+                                  _dp(gamma), _dp(beta), _dp(zeta), _dp(objective), _dp(iters),
+                                  _dp(evals), _dp(status), _stream(stream)))
+
+
+# ------------------------------------------------- batch conveniences -------
+
+@dataclass
+class EstimateResult:
+    K: int
+    theta: np.ndarray
+    alpha: np.ndarray
+    gamma: np.ndarray
+    beta: float
+    zeta: float
+    objective: float
+    iterations: int
+    evaluations: int
+    status: int
+
+
+def estimate_batch(ctx: Context, ys, params: sfls_params | None = None, kcap: int | None = None,
+                   ydtype=None, stream=None, sync: bool = True):
+    """Run sfls_estimate on a list of 1-D complex arrays; returns EstimateResult per instance."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    if ydtype is None:
+        ydtype = SFLS_C64 if all(np.asarray(y).dtype == np.complex64 for y in ys) else SFLS_C128
+    npdt = np.complex64 if ydtype == SFLS_C64 else np.complex128
+    n = np.array([len(y) for y in ys], np.int64)
+    off = np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+    kc = np.array([min(int(k), int(m)) for k, m in zip(
+        [kcap if kcap else m for m in n], n)], np.int64)
+    koff = np.concatenate([[0], np.cumsum(kc)[:-1]]).astype(np.int64)
+    yflat = np.concatenate([np.asarray(y, npdt) for y in ys])
+    ydev = torch.from_numpy(yflat.view(np.float32 if ydtype == SFLS_C64 else np.float64)).to(dev)
+    B, KT = len(ys), int(kc.sum())
+    f64 = dict(dtype=torch.float64, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    out = dict(K=torch.zeros(B, dtype=torch.int64, device=dev), theta=torch.zeros(KT, **f64),
+               alpha=torch.zeros(2 * KT, **f64), gamma=torch.zeros(KT, **f64),
+               beta=torch.zeros(B, **f64), zeta=torch.zeros(B, **f64),
+               objective=torch.zeros(B, **f64), iters=torch.zeros(B, **i32),
+               evals=torch.zeros(B, **i32), status=torch.zeros(B, **i32))
+    sfls_estimate(ctx, n, off, ydev, ydtype, params, kc, koff, out["K"], out["theta"],
+                  out["alpha"], out["gamma"], out["beta"], out["zeta"], out["objective"],
+                  out["iters"], out["evals"], out["status"], stream=stream)
+    if not sync:
+        return out
+    torch.cuda.synchronize(dev)
+    h = {k: v.cpu().numpy() for k, v in out.items()}
+    alpha = h["alpha"].view(np.complex128)
+    res = []
+    for b in range(B):
+        k = int(h["K"][b])
+        o = int(koff[b])
+        res.append(EstimateResult(K=k, theta=h["theta"][o:o + k].copy(),
+                                  alpha=alpha[o:o + k].copy(), gamma=h["gamma"][o:o + k].copy(),
+                                  beta=float(h["beta"][b]), zeta=float(h["zeta"][b]),
+                                  objective=float(h["objective"][b]),
+                                  iterations=int(h["iters"][b]), evaluations=int(h["evals"][b]),
+                                  status=int(h["status"][b])))
+    return res

@@ -1,0 +1,659 @@
+// C-ABI of the superfast-LSE library: argument checks, workspace, launch
+// sequencing and the estimate round loop.  All arithmetic of the method runs
+// in the kernels of k_*.hip; this file only moves sizes and pointers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "k_launch.hpp"
+#include "sfls.h"
+
+using namespace sfls;
+
+static_assert(sizeof(sfls_params) == 136, "sfls_params layout is part of the ABI");
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+struct sfls_ctx {
+  int device = 0;
+  std::string err;
+  cd* tw64 = nullptr;
+  cf* tw32 = nullptr;
+  int logtw = 17;
+  std::map<std::string, DevBuf> bufs;
+  int32_t* host_flag = nullptr;  // pinned
+};
+
+namespace {
+
+const char* kVersion = "sfls 0.1 (gfx950)";
+
+sfls_status fail(sfls_ctx* ctx, sfls_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(ctx, SFLS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+// grow-only named workspace buffer
+sfls_status ws(sfls_ctx* ctx, const char* name, size_t bytes, void** out) {
+  DevBuf& b = ctx->bufs[name];
+  if (bytes == 0) bytes = 256;
+  if (b.n < bytes) {
+    if (b.p) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(b.p);
+      b.p = nullptr;
+      b.n = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+      b.p = nullptr;
+      return fail(ctx, SFLS_ENOMEM, "workspace allocation of %zu bytes for %s failed", want, name);
+    }
+    b.n = want;
+  }
+  *out = b.p;
+  return SFLS_OK;
+}
+
+template <typename T>
+sfls_status wsT(sfls_ctx* ctx, const char* name, size_t count, T** out) {
+  void* p = nullptr;
+  sfls_status s = ws(ctx, name, count * sizeof(T), &p);
+  *out = static_cast<T*>(p);
+  return s;
+}
+
+template <typename T>
+sfls_status upload(sfls_ctx* ctx, const char* name, const std::vector<T>& v, hipStream_t st,
+                   T** out) {
+  sfls_status s = wsT<T>(ctx, name, v.size() ? v.size() : 1, out);
+  if (s != SFLS_OK) return s;
+  if (!v.empty()) {
+    HIP_TRY(hipMemcpyAsync(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return SFLS_OK;
+}
+
+int ilog2_ceil(int64_t v) {
+  int l = 0;
+  while (((int64_t)1 << l) < v) ++l;
+  return l;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Polynomial coefficients of the diagonal-sum weights in centred variables
+// x = q - c, y = p - c (p = q + i, c = (N-1)/2).  With S_k(n) = sum_{a=0}^n a^k,
+// the Gohberg-Semencul form gives, for a row weight f,
+//   omega_f(i) = delta^{-1} sum_q [S_f(q) - S_f(N-2-p)] rho_q conj(rho_p)
+// (the ranges of the two triangular factors telescope; Appendix B):
+//   s: S_0,  t: 2pi S_1,  v: (2pi)^2 S_2,  x: (2pi)^2 [S_2 + i S_1] (row and column weight).
+void sep_coef(int N, SepCoef& out) {
+  const double c = 0.5 * (double)(N - 1);
+  const double d = (double)(N - 2) - c;
+  const double Sk[3][4] = {{1.0, 1.0, 0.0, 0.0}, {0.0, 0.5, 0.5, 0.0},
+                           {0.0, 1.0 / 6.0, 0.5, 1.0 / 3.0}};
+  const double binom[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+  double Sq[3][4] = {}, Sm[3][4] = {};
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 4; ++j)
+      for (int i = 0; i <= j; ++i) {
+        Sq[k][i] += Sk[k][j] * binom[j][i] * std::pow(c, j - i);
+        Sm[k][i] += Sk[k][j] * binom[j][i] * std::pow(d, j - i) * ((i & 1) ? -1.0 : 1.0);
+      }
+  const double tp = 2.0 * M_PI, tp2 = tp * tp;
+  std::memset(&out, 0, sizeof out);
+  auto diff = [&](double* C, int k, double sc) {
+    for (int i = 0; i < 4; ++i) {
+      C[i * 4 + 0] += sc * Sq[k][i];
+      C[0 * 4 + i] -= sc * Sm[k][i];
+    }
+  };
+  diff(out.c[0], 0, 1.0);
+  diff(out.c[1], 1, tp);
+  diff(out.c[2], 2, tp2);
+  diff(out.c[3], 2, tp2);
+  // x: + (y - x) (S_1(c + x) - S_1(d - y))
+  double* C = out.c[3];
+  for (int i = 0; i < 3; ++i) {
+    C[i * 4 + 1] += tp2 * Sq[1][i];        // a_i x^i y
+    C[(i + 1) * 4 + 0] -= tp2 * Sq[1][i];  // -a_i x^{i+1}
+    C[0 * 4 + (i + 1)] -= tp2 * Sm[1][i];  // -b_i y^{i+1}
+    C[1 * 4 + i] += tp2 * Sm[1][i];        // +b_i x y^i
+  }
+}
+
+struct Sizes {
+  int maxN = 0, maxP = 0, maxM = 0, Rmax = 1;
+};
+
+sfls_status check_batch(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                        int64_t nmin) {
+  if (B < 0) return fail(ctx, SFLS_EINVAL, "B = %lld < 0", (long long)B);
+  if (B > 0 && (!n || !off)) return fail(ctx, SFLS_EINVAL, "n and off must be non-NULL");
+  for (int64_t b = 0; b < B; ++b) {
+    if (n[b] < nmin) return fail(ctx, SFLS_EINVAL, "n[%lld] = %lld < %lld", (long long)b, (long long)n[b], (long long)nmin);
+    if (n[b] > SFLS_MAX_N)
+      return fail(ctx, SFLS_EUNSUPPORTED, "n[%lld] = %lld exceeds SFLS_MAX_N = %d", (long long)b,
+                  (long long)n[b], SFLS_MAX_N);
+    if (off[b] < 0) return fail(ctx, SFLS_EINVAL, "off[%lld] < 0", (long long)b);
+  }
+  return SFLS_OK;
+}
+
+// Base InstInfo: N, P, off, poff (4 P scratch per instance).
+std::vector<InstInfo> base_info(int64_t B, const int64_t* n, const int64_t* off, Sizes& sz,
+                                int64_t& ptotal) {
+  std::vector<InstInfo> v((size_t)B);
+  ptotal = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    InstInfo& in = v[(size_t)b];
+    std::memset(&in, 0, sizeof in);
+    in.N = (int32_t)n[b];
+    in.logP = ilog2_ceil(2 * n[b] - 1 > 1 ? 2 * n[b] - 1 : 2);
+    in.P = 1 << in.logP;
+    in.logM = ilog2_ceil(n[b]);
+    in.M = 1 << in.logM;
+    in.off = off[b];
+    in.poff = ptotal;
+    ptotal += 4 * (int64_t)in.P;
+    sz.maxN = std::max(sz.maxN, in.N);
+    sz.maxP = std::max(sz.maxP, in.P);
+    sz.maxM = std::max(sz.maxM, in.M);
+  }
+  return v;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+void sfls_params_default(sfls_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->L_mult = 8.0;
+  p->tau = 5.0;
+  p->lbfgs_J = 10;
+  p->max_inner = 5;
+  p->max_outer = 200;
+  p->approx_max_iters = 10;
+  p->approx_use_tau = 1;
+  p->ls_max = 30;
+  p->polish_max_iters = 30;
+  p->cand_cap = 256;
+  p->tol_obj = 1e-7;
+  p->tol_newton = 1e-8;
+  p->eps_beta_rel = 1e-10;
+  p->eps_L = 2.220446049250313e-16;
+  p->approx_ratio = 5.0;
+  p->approx_min_dist = 0.05;
+  p->ls_c1 = 1e-4;
+  p->curv_eps = 1e-12;
+  p->polish_tol = 1e-12;
+  p->polish_ftol = 1e-13;
+  p->precision = SFLS_FP64;
+}
+
+const char* sfls_version(void) { return kVersion; }
+
+const char* sfls_strerror(sfls_status s) {
+  switch (s) {
+    case SFLS_OK: return "ok";
+    case SFLS_NOTCONV: return "iteration cap reached before convergence";
+    case SFLS_EINVAL: return "invalid argument";
+    case SFLS_ENOMEM: return "device memory allocation failed";
+    case SFLS_EDEVICE: return "HIP runtime error";
+    case SFLS_ENOTPD: return "Toeplitz matrix not positive definite";
+    case SFLS_ECAPACITY: return "component capacity exceeded";
+    case SFLS_EUNSUPPORTED: return "size not supported by this build";
+  }
+  return "unknown status";
+}
+
+const char* sfls_last_error(const sfls_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+sfls_status sfls_create(sfls_ctx** out, int device) {
+  if (!out) return SFLS_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SFLS_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return SFLS_EDEVICE;
+  sfls_ctx* ctx = new sfls_ctx();
+  ctx->device = device;
+  const size_t nt = (size_t)1 << (ctx->logtw - 1);
+  if (hipMalloc(&ctx->tw64, nt * sizeof(cd)) != hipSuccess ||
+      hipMalloc(&ctx->tw32, nt * sizeof(cf)) != hipSuccess ||
+      hipHostMalloc(&ctx->host_flag, sizeof(int32_t)) != hipSuccess) {
+    sfls_destroy(ctx);
+    return SFLS_ENOMEM;
+  }
+  if (launch_twiddles(ctx->tw64, ctx->tw32, ctx->logtw, nullptr) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    sfls_destroy(ctx);
+    return SFLS_EDEVICE;
+  }
+  *out = ctx;
+  return SFLS_OK;
+}
+
+sfls_status sfls_destroy(sfls_ctx* ctx) {
+  if (!ctx) return SFLS_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (ctx->tw64) (void)hipFree(ctx->tw64);
+  if (ctx->tw32) (void)hipFree(ctx->tw32);
+  if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
+  delete ctx;
+  return SFLS_OK;
+}
+
+sfls_status sfls_toeplitz_column(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                                 const int64_t* K, const int64_t* koff, const double* theta,
+                                 const double* gamma, const double* beta, double* c,
+                                 void* stream) {
+  if (!ctx) return SFLS_EINVAL;
+  ctx->err.clear();
+  sfls_status s = check_batch(ctx, B, n, off, 1);
+  if (s != SFLS_OK || B == 0) return s;
+  if (!K || !koff || !beta || !c) return fail(ctx, SFLS_EINVAL, "NULL argument");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = as_stream(stream);
+  Sizes sz;
+  int64_t pt = 0;
+  std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
+  std::vector<int32_t> kc((size_t)B);
+  for (int64_t b = 0; b < B; ++b) {
+    if (K[b] < 0 || koff[b] < 0) return fail(ctx, SFLS_EINVAL, "K/koff[%lld] < 0", (long long)b);
+    if (K[b] > 0 && (!theta || !gamma)) return fail(ctx, SFLS_EINVAL, "theta/gamma NULL");
+    info[(size_t)b].koff = koff[b];
+    kc[(size_t)b] = (int32_t)K[b];
+  }
+  InstInfo* dinfo;
+  int32_t* dK;
+  if ((s = upload(ctx, "tc_info", info, st, &dinfo)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "tc_K", kc, st, &dK)) != SFLS_OK) return s;
+  HIP_TRY(launch_toeplitz_column(dinfo, nullptr, dK, theta, gamma, beta, (cd*)c, (int)B, sz.maxN, st));
+  return SFLS_OK;
+}
+
+sfls_status sfls_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                        const double* c, double* rho, double* delta, double* logdet,
+                        int32_t* status, int64_t* failed_step, void* stream) {
+  if (!ctx) return SFLS_EINVAL;
+  ctx->err.clear();
+  sfls_status s = check_batch(ctx, B, n, off, 1);
+  if (s != SFLS_OK || B == 0) return s;
+  if (!c || !rho) return fail(ctx, SFLS_EINVAL, "c and rho must be non-NULL");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = as_stream(stream);
+  Sizes sz;
+  int64_t pt = 0;
+  std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
+  InstInfo* dinfo;
+  if ((s = upload(ctx, "f_info", info, st, &dinfo)) != SFLS_OK) return s;
+  HIP_TRY(launch_levinson(dinfo, nullptr, (const cd*)c, (cd*)rho, delta, logdet, status,
+                          failed_step, (int)B, sz.maxN, st));
+  return SFLS_OK;
+}
+
+sfls_status sfls_gs_apply(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                          const void* y, int32_t ydtype, const double* rho, const double* delta,
+                          double* w, double* yCy, double* ww, void* stream) {
+  if (!ctx) return SFLS_EINVAL;
+  ctx->err.clear();
+  sfls_status s = check_batch(ctx, B, n, off, 1);
+  if (s != SFLS_OK || B == 0) return s;
+  if (!y || !rho || !delta || !w) return fail(ctx, SFLS_EINVAL, "NULL argument");
+  if (ydtype != SFLS_C64 && ydtype != SFLS_C128) return fail(ctx, SFLS_EINVAL, "bad ydtype");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = as_stream(stream);
+  Sizes sz;
+  int64_t pt = 0;
+  std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
+  InstInfo* dinfo;
+  cd* scratch;
+  if ((s = upload(ctx, "a_info", info, st, &dinfo)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "scratch", (size_t)pt, &scratch)) != SFLS_OK) return s;
+  HIP_TRY(launch_gs_apply(dinfo, nullptr, y, ydtype, (const cd*)rho, delta, ctx->tw64,
+                          ctx->logtw, scratch, (cd*)w, yCy, ww, (int)B, sz.maxP, st));
+  return SFLS_OK;
+}
+
+sfls_status sfls_omega(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                       const int64_t* oout, const double* rho, const double* delta,
+                       double* omega_s, double* omega_t, double* omega_v, double* omega_x,
+                       void* stream) {
+  if (!ctx) return SFLS_EINVAL;
+  ctx->err.clear();
+  sfls_status s = check_batch(ctx, B, n, off, 1);
+  if (s != SFLS_OK || B == 0) return s;
+  if (!oout || !rho || !delta) return fail(ctx, SFLS_EINVAL, "NULL argument");
+  const int which = (omega_s ? 1 : 0) | (omega_t ? 2 : 0) | (omega_v ? 4 : 0) | (omega_x ? 8 : 0);
+  if (!which) return SFLS_OK;
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = as_stream(stream);
+  Sizes sz;
+  int64_t pt = 0;
+  std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
+  std::vector<SepCoef> coef((size_t)B);
+  for (int64_t b = 0; b < B; ++b) {
+    if (oout[b] < 0) return fail(ctx, SFLS_EINVAL, "oout[%lld] < 0", (long long)b);
+    info[(size_t)b].ooff = oout[b];
+    sep_coef((int)n[b], coef[(size_t)b]);
+  }
+  InstInfo* dinfo;
+  SepCoef* dcoef;
+  cd* scratch;
+  if ((s = upload(ctx, "o_info", info, st, &dinfo)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "o_coef", coef, st, &dcoef)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "scratch", (size_t)pt, &scratch)) != SFLS_OK) return s;
+  HIP_TRY(launch_omega(dinfo, nullptr, (const cd*)rho, delta, dcoef, ctx->tw64, ctx->logtw,
+                       scratch, which, 0, nullptr, (cd*)omega_s, (cd*)omega_t, (cd*)omega_v,
+                       (cd*)omega_x, (int)B, sz.maxP, st));
+  return SFLS_OK;
+}
+
+sfls_status sfls_grid_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                           const void* y, int32_t ydtype, const double* rho, const double* delta,
+                           const int64_t* L, const int64_t* goff, const double* gamma_bar,
+                           const double* zeta, void* qG, void* sG, void* dL, int64_t* argmin,
+                           double* argmin_val, int32_t precision, void* stream) {
+  if (!ctx) return SFLS_EINVAL;
+  ctx->err.clear();
+  sfls_status s = check_batch(ctx, B, n, off, 1);
+  if (s != SFLS_OK || B == 0) return s;
+  if (!y || !rho || !delta || !L || !goff || !gamma_bar || !zeta)
+    return fail(ctx, SFLS_EINVAL, "NULL argument");
+  if (ydtype != SFLS_C64 && ydtype != SFLS_C128) return fail(ctx, SFLS_EINVAL, "bad ydtype");
+  if (precision != SFLS_FP64 && precision != SFLS_MIXED) return fail(ctx, SFLS_EINVAL, "bad precision");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = as_stream(stream);
+  Sizes sz;
+  int64_t pt = 0, ntot = 0;
+  std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
+  std::vector<SepCoef> coef((size_t)B);
+  std::vector<int32_t> req((size_t)B, REQ_EVAL | REQ_GRID);
+  for (int64_t b = 0; b < B; ++b) {
+    InstInfo& in = info[(size_t)b];
+    if (!is_pow2(L[b]) || L[b] < 2 * n[b] - 1 || L[b] < in.M)
+      return fail(ctx, SFLS_EINVAL, "L[%lld] = %lld must be a power of two >= 2n-1", (long long)b, (long long)L[b]);
+    if (goff[b] < 0) return fail(ctx, SFLS_EINVAL, "goff[%lld] < 0", (long long)b);
+    in.L = (int32_t)L[b];
+    in.R = (int32_t)(L[b] / in.M);
+    in.goff = goff[b];
+    sz.Rmax = std::max(sz.Rmax, in.R);
+    ntot = std::max(ntot, off[b] + n[b]);
+    sep_coef((int)n[b], coef[(size_t)b]);
+  }
+  InstInfo* dinfo;
+  SepCoef* dcoef;
+  int32_t* dreq;
+  cd *scratch, *w, *oms;
+  double *pv, *yCy;
+  int64_t* pi;
+  if ((s = upload(ctx, "g_info", info, st, &dinfo)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "g_coef", coef, st, &dcoef)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "g_req", req, st, &dreq)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "scratch", (size_t)pt, &scratch)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "g_w", (size_t)ntot, &w)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "g_oms", (size_t)pt, &oms)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "g_pv", (size_t)B * sz.Rmax, &pv)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "g_pi", (size_t)B * sz.Rmax, &pi)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "g_yCy", (size_t)B, &yCy)) != SFLS_OK) return s;
+  HIP_TRY(launch_gs_apply(dinfo, dreq, y, ydtype, (const cd*)rho, delta, ctx->tw64, ctx->logtw,
+                          scratch, w, yCy, nullptr, (int)B, sz.maxP, st));
+  HIP_TRY(launch_omega(dinfo, dreq, (const cd*)rho, delta, dcoef, ctx->tw64, ctx->logtw, scratch,
+                       1, 1, oms, nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st));
+  const void* tw = precision == SFLS_FP64 ? (const void*)ctx->tw64 : (const void*)ctx->tw32;
+  HIP_TRY(launch_grid(precision, dinfo, dreq, w, oms, gamma_bar, zeta, tw, ctx->logtw, sz.Rmax,
+                      (int)B, sz.maxM, qG, sG, dL, pv, pi, st));
+  if (argmin || argmin_val)
+    HIP_TRY(launch_argmin_out(dinfo, sz.Rmax, pv, pi, argmin, argmin_val, (int)B, st));
+  return SFLS_OK;
+}
+
+sfls_status sfls_active_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                             const double* w, const double* rho, const double* delta,
+                             const int64_t* K, const int64_t* koff, const double* theta,
+                             double* q, double* r, double* u, double* s_, double* t, double* v,
+                             double* x, void* stream) {
+  if (!ctx) return SFLS_EINVAL;
+  ctx->err.clear();
+  sfls_status s = check_batch(ctx, B, n, off, 1);
+  if (s != SFLS_OK || B == 0) return s;
+  if (!w || !rho || !delta || !K || !koff) return fail(ctx, SFLS_EINVAL, "NULL argument");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = as_stream(stream);
+  Sizes sz;
+  int64_t pt = 0, ktot = 0;
+  std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
+  std::vector<SepCoef> coef((size_t)B);
+  std::vector<int32_t> req((size_t)B, REQ_EVAL), kc((size_t)B);
+  for (int64_t b = 0; b < B; ++b) {
+    if (K[b] < 0 || koff[b] < 0) return fail(ctx, SFLS_EINVAL, "K/koff[%lld] < 0", (long long)b);
+    if (K[b] > 0 && !theta) return fail(ctx, SFLS_EINVAL, "theta NULL");
+    info[(size_t)b].koff = koff[b];
+    kc[(size_t)b] = (int32_t)K[b];
+    ktot = std::max(ktot, koff[b] + K[b]);
+    sep_coef((int)n[b], coef[(size_t)b]);
+  }
+  InstInfo* dinfo;
+  SepCoef* dcoef;
+  int32_t *dreq, *dK, *prefix;
+  if ((s = upload(ctx, "ae_info", info, st, &dinfo)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "ae_coef", coef, st, &dcoef)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "ae_req", req, st, &dreq)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "ae_K", kc, st, &dK)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "ae_prefix", (size_t)B + 1, &prefix)) != SFLS_OK) return s;
+  cd* dummy;
+  if ((s = wsT(ctx, "ae_dummy", (size_t)std::max<int64_t>(ktot, 1), &dummy)) != SFLS_OK) return s;
+  auto o = [&](double* p) { return p ? (cd*)p : dummy; };
+  HIP_TRY(launch_active(dinfo, dreq, dK, nullptr, prefix, (int)B, theta, nullptr, (const cd*)w,
+                        (const cd*)rho, delta, dcoef, o(q), o(r), o(u), o(s_), o(t), o(v), o(x),
+                        nullptr, nullptr, 2048, st));
+  return SFLS_OK;
+}
+
+sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                          const void* y, int32_t ydtype, const sfls_params* params,
+                          const int64_t* kcap, const int64_t* koff, int64_t* K, double* theta,
+                          double* alpha, double* gamma, double* beta, double* zeta,
+                          double* objective, int32_t* iters, int32_t* evals, int32_t* status,
+                          void* stream) {
+  if (!ctx) return SFLS_EINVAL;
+  ctx->err.clear();
+  sfls_status s = check_batch(ctx, B, n, off, 2);
+  if (s != SFLS_OK || B == 0) return s;
+  if (!y || !kcap || !koff || !K || !theta || !alpha || !gamma || !beta || !zeta || !objective ||
+      !iters || !status)
+    return fail(ctx, SFLS_EINVAL, "NULL argument");
+  if (ydtype != SFLS_C64 && ydtype != SFLS_C128) return fail(ctx, SFLS_EINVAL, "bad ydtype");
+  sfls_params p;
+  if (params) p = *params; else sfls_params_default(&p);
+  if (!(p.L_mult > 0) || p.lbfgs_J < 1 || p.lbfgs_J > 16 || p.max_inner < 0 || p.max_outer < 1 ||
+      p.ls_max < 1 || p.polish_max_iters < 0 || p.cand_cap < 1 || p.cand_cap > 2048 ||
+      (p.precision != SFLS_FP64 && p.precision != SFLS_MIXED))
+    return fail(ctx, SFLS_EINVAL, "invalid sfls_params");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = as_stream(stream);
+  Sizes sz;
+  int64_t pt = 0, ntot = 0, ktot = 0, gtot = 0, ctot = 0;
+  std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
+  std::vector<SepCoef> coef((size_t)B);
+  std::vector<int64_t> okoff((size_t)B);
+  const int cc = p.cand_cap + 1;
+  for (int64_t b = 0; b < B; ++b) {
+    InstInfo& in = info[(size_t)b];
+    if (kcap[b] < 1 || koff[b] < 0) return fail(ctx, SFLS_EINVAL, "kcap/koff[%lld]", (long long)b);
+    const int64_t Lb = (int64_t)1 << (int)std::lround(std::log2(p.L_mult * (double)n[b]));
+    if (Lb < 2 * n[b] - 1 || Lb < in.M)
+      return fail(ctx, SFLS_EINVAL, "grid L = %lld shorter than 2n-1 for n = %lld", (long long)Lb, (long long)n[b]);
+    if (Lb > (1 << 24)) return fail(ctx, SFLS_EUNSUPPORTED, "grid too large");
+    in.L = (int32_t)Lb;
+    in.R = (int32_t)(Lb / in.M);
+    in.kcap = (int32_t)std::min<int64_t>(kcap[b], n[b]);
+    in.koff = ktot;
+    ktot += in.kcap;
+    in.goff = gtot;
+    gtot += Lb;
+    in.coff = ctot;
+    ctot += cc;
+    sz.Rmax = std::max(sz.Rmax, in.R);
+    ntot = std::max(ntot, off[b] + n[b]);
+    okoff[(size_t)b] = koff[b];
+    sep_coef((int)n[b], coef[(size_t)b]);
+  }
+  DrvParams dp;
+  dp.tau = p.tau; dp.tol_obj = p.tol_obj; dp.tol_newton = p.tol_newton;
+  dp.eps_beta_rel = p.eps_beta_rel; dp.eps_L = p.eps_L; dp.approx_ratio = p.approx_ratio;
+  dp.approx_min_dist = p.approx_min_dist; dp.ls_c1 = p.ls_c1; dp.curv_eps = p.curv_eps;
+  dp.polish_tol = p.polish_tol; dp.polish_ftol = p.polish_ftol; dp.J = p.lbfgs_J;
+  dp.max_inner = p.max_inner; dp.max_outer = p.max_outer;
+  dp.approx_max_iters = p.approx_max_iters; dp.approx_use_tau = p.approx_use_tau;
+  dp.ls_max = p.ls_max; dp.polish_max_iters = p.polish_max_iters; dp.cand_cap = p.cand_cap;
+  std::vector<DrvParams> dpv(1, dp);
+
+  InstInfo* dinfo;
+  SepCoef* dcoef;
+  DrvParams* dprm;
+  int64_t* dokoff;
+  if ((s = upload(ctx, "e_info", info, st, &dinfo)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "e_coef", coef, st, &dcoef)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "e_prm", dpv, st, &dprm)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "e_okoff", okoff, st, &dokoff)) != SFLS_OK) return s;
+
+  const int J = p.lbfgs_J;
+  const size_t esz = p.precision == SFLS_FP64 ? sizeof(double) : sizeof(float);
+  cd *c, *rho, *w, *scratch, *oms;
+  double *delta, *logdet, *yCy, *ww, *pv;
+  int64_t *failed, *pi;
+  int32_t *lev_status, *prefix, *ovf;
+  void* dL;
+  DrvPools P{};
+#define WS(name, cnt, ptr) if ((s = wsT(ctx, name, (size_t)(cnt), &(ptr))) != SFLS_OK) return s
+  WS("e_c", ntot, c);
+  WS("e_rho", ntot, rho);
+  WS("e_w", ntot, w);
+  WS("e_delta", ntot, delta);
+  WS("scratch", pt, scratch);
+  WS("e_oms", pt, oms);
+  WS("e_logdet", B, logdet);
+  WS("e_yCy", B, yCy);
+  WS("e_ww", B, ww);
+  WS("e_failed", B, failed);
+  WS("e_levst", B, lev_status);
+  WS("e_prefix", B + 1, prefix);
+  WS("e_ovf", B, ovf);
+  WS("e_pv", B * sz.Rmax, pv);
+  WS("e_pi", B * sz.Rmax, pi);
+  if ((s = ws(ctx, "e_dL", (size_t)gtot * esz, &dL)) != SFLS_OK) return s;
+  DrvState* dst;
+  WS("e_state", B, dst);
+  P.st = dst;
+  WS("e_th", ktot, P.th);
+  WS("e_ga", ktot, P.ga);
+  WS("e_th_e", ktot, P.th_e);
+  WS("e_ga_e", ktot, P.ga_e);
+  WS("e_g", 2 * ktot, P.g);
+  WS("e_d", 2 * ktot, P.d);
+  WS("e_gt", 2 * ktot, P.gt);
+  WS("e_Sm", (size_t)J * 2 * ktot, P.Sm);
+  WS("e_Ym", (size_t)J * 2 * ktot, P.Ym);
+  WS("e_rhom", (size_t)J * B, P.rhom);
+  WS("e_am", (size_t)J * B, P.am);
+  WS("e_Ke", B, P.K_e);
+  WS("e_req", B, P.req);
+  WS("e_beta_e", B, P.beta_e);
+  WS("e_gbar_e", B, P.gbar_e);
+  WS("e_zeta_e", B, P.zeta_e);
+  cd *evq, *evr, *evu, *evs, *evt, *evv, *evx, *cq;
+  double* cs;
+  int32_t *cand, *ncand;
+  WS("e_evq", ktot, evq);
+  WS("e_evr", ktot, evr);
+  WS("e_evu", ktot, evu);
+  WS("e_evs", ktot, evs);
+  WS("e_evt", ktot, evt);
+  WS("e_evv", ktot, evv);
+  WS("e_evx", ktot, evx);
+  WS("e_cand", ctot, cand);
+  WS("e_ncand", B, ncand);
+  WS("e_cq", ctot, cq);
+  WS("e_cs", ctot, cs);
+  WS("e_cbdl", ctot, P.cbuf_dl);
+  WS("e_cbgh", ctot, P.cbuf_gh);
+  WS("e_cbl", ctot, P.cbuf_l);
+  int32_t* notdone;
+  WS("e_notdone", 1, notdone);
+#undef WS
+  P.ev_q = evq; P.ev_r = evr; P.ev_u = evu; P.ev_s = evs; P.ev_t = evt; P.ev_v = evv;
+  P.ev_x = evx; P.logdet = logdet; P.yCy = yCy; P.ww = ww; P.lev_status = lev_status;
+  P.cand = cand; P.ncand = ncand; P.cand_q = cq; P.cand_s = cs;
+  P.out_K = K; P.out_theta = theta; P.out_alpha = (cd*)alpha; P.out_gamma = gamma;
+  P.out_beta = beta; P.out_zeta = zeta; P.out_obj = objective; P.out_iters = iters;
+  P.out_evals = evals; P.out_status = status; P.out_koff = dokoff; P.notdone = notdone;
+
+  const int prec = p.precision;
+  const void* tw = prec == SFLS_FP64 ? (const void*)ctx->tw64 : (const void*)ctx->tw32;
+  const double slack = prec == SFLS_FP64 ? 1e-9 : 1e-3;
+  const int act_blocks = 2048;
+
+  HIP_TRY(launch_init_state(dinfo, y, ydtype, dst, P.req, (int)B, st));
+  HIP_TRY(launch_zero_i32(notdone, 1, st));
+  HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
+  HIP_TRY(hipMemcpyAsync(ctx->host_flag, notdone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  int64_t rounds = 0;
+  const int64_t max_rounds = 1000000;
+  while (*ctx->host_flag > 0 && rounds < max_rounds) {
+    ++rounds;
+    HIP_TRY(launch_toeplitz_column(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, c, (int)B,
+                                   sz.maxN, st));
+    HIP_TRY(launch_levinson(dinfo, P.req, c, rho, delta, logdet, lev_status, failed, (int)B,
+                            sz.maxN, st));
+    HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw, scratch,
+                            w, yCy, ww, (int)B, sz.maxP, st));
+    HIP_TRY(launch_omega(dinfo, P.req, rho, delta, dcoef, ctx->tw64, ctx->logtw, scratch, 1, 1,
+                         oms, nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st));
+    HIP_TRY(launch_grid(prec, dinfo, P.req, w, oms, P.gbar_e, P.zeta_e, tw, ctx->logtw, sz.Rmax,
+                        (int)B, sz.maxM, nullptr, nullptr, dL, pv, pi, st));
+    HIP_TRY(launch_select(prec, dinfo, P.req, dL, sz.Rmax, pv, pi, p.approx_ratio, slack,
+                          p.cand_cap, cand, ncand, ovf, (int)B, st));
+    HIP_TRY(launch_active(dinfo, P.req, P.K_e, ncand, prefix, (int)B, P.th_e, cand, w, rho, delta,
+                          dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks, st));
+    HIP_TRY(launch_zero_i32(notdone, 1, st));
+    HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
+    HIP_TRY(hipMemcpyAsync(ctx->host_flag, notdone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  if (rounds >= max_rounds) return fail(ctx, SFLS_EDEVICE, "estimate did not finish");
+  return SFLS_OK;
+}
+
+}  // extern "C"

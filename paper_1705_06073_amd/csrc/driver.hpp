@@ -1,0 +1,699 @@
+// a9: the estimator's block-coordinate descent (Sec. II-C/E) as a resumable
+// per-instance state machine.  One call consumes the results of the last
+// evaluation round (C at the requested point: ln|C|, y^H C^{-1} y, ||w||^2,
+// the active vectors q..x, and the FP64 q, s at grid candidates) and runs the
+// algorithm until it needs the next evaluation, which it requests by writing
+// the evaluation point and request bits; or it finishes and writes outputs.
+//
+// Plain C++ (no device intrinsics) so the same code runs in the device
+// driver kernel; all per-instance arrays live in device memory.
+#pragma once
+#include <math.h>
+#include <stdint.h>
+
+#ifndef SFLS_HD
+#define SFLS_HD __host__ __device__
+#endif
+
+namespace sfls {
+
+struct DrvParams {
+  double tau, tol_obj, tol_newton, eps_beta_rel, eps_L, approx_ratio, approx_min_dist, ls_c1,
+      curv_eps, polish_tol, polish_ftol;
+  int32_t J, max_inner, max_outer, approx_max_iters, approx_use_tau, ls_max, polish_max_iters,
+      cand_cap;
+};
+
+// phases
+enum : int32_t {
+  PH_START = 0,
+  PH_APPROX_WAIT,
+  PH_EXACT_WAIT,
+  PH_BETA_WAIT,
+  PH_INNER_WAIT,
+  PH_LS_WAIT,
+  PH_DEACT_WAIT,
+  PH_TERM_WAIT,
+  PH_POLISH_WAIT,
+  PH_DONE
+};
+
+// Scalar state of one instance.
+struct DrvState {
+  int32_t phase, it, inner, pit, ls_trial, K, approx_on, z_changed, cur_valid, converged,
+      cap_hit, polish, mem_n, mem_head, kstar, status, nevals, done;
+  double beta, zeta, eps_beta, yy, L_prev, f_cur, lam2, alpha, amax, gd;
+};
+
+// Per-instance array views (device pointers, offset to this instance).
+struct DrvArrays {
+  int N, L, kcap;
+  // current accepted point
+  double* th;
+  double* ga;
+  // evaluation point (read by the evaluation kernels)
+  double* th_e;
+  double* ga_e;
+  int32_t* K_e;     // number of components at the evaluation point
+  double* beta_e;   // beta at the evaluation point
+  int32_t* req;     // request bits for the next round
+  double* gbar_e;   // gamma_bar for the grid stage (<= 0: per-point optimum)
+  double* zeta_e;   // zeta for the grid stage
+  // L-BFGS storage
+  double* g;        // gradient at the current point [2 kcap]
+  double* d;        // direction [2 kcap]
+  double* Sm;       // [J][2 kcap]
+  double* Ym;       // [J][2 kcap]
+  double* rhom;     // [J]
+  double* am;       // [J] two-loop scratch
+  double* gt;       // gradient at the trial [2 kcap]
+  // evaluation results (written by the kernels, valid for the last request)
+  const double* ev_q;  // complex [kcap] interleaved
+  const double* ev_r;
+  const double* ev_u;
+  const double* ev_s;
+  const double* ev_t;
+  const double* ev_v;
+  const double* ev_x;
+  const double* logdet;
+  const double* yCy;
+  const double* ww;
+  const int32_t* lev_status;
+  const int32_t* cand;    // grid indices, cand[0] = argmin
+  const int32_t* ncand;
+  const double* cand_q;   // complex
+  const double* cand_s;
+  // approximate-scheme scratch [cand_cap + 1]
+  double* cbuf_dl;
+  double* cbuf_gh;
+  int32_t* cbuf_l;
+  // outputs
+  int64_t* out_K;
+  double* out_theta;
+  double* out_alpha;  // complex
+  double* out_gamma;
+  double* out_beta;
+  double* out_zeta;
+  double* out_obj;
+  int32_t* out_iters;
+  int32_t* out_evals;
+  int32_t* out_status;
+};
+
+SFLS_HD inline double xlogy_(double a, double b) { return a == 0.0 ? 0.0 : a * log(b); }
+SFLS_HD inline double prior_term(int K, int N, double z) {
+  return -(xlogy_((double)K, z) + xlogy_((double)(N - K), 1.0 - z));
+}
+SFLS_HD inline double wrapd(double a, double b) {
+  double d = fabs(a - b);
+  d = d - floor(d);
+  return fmin(d, 1.0 - d);
+}
+SFLS_HD inline double gamma_hat(double q2, double s) { return (q2 / s > 1.0) ? (q2 - s) / (s * s) : 0.0; }
+SFLS_HD inline double delta_L(double q2, double s, double gb, double zeta) {
+  const double lg = log((1.0 + gb * s) * ((1.0 - zeta) / zeta));
+  return lg - ((gb > 0.0) ? q2 / (1.0 / gb + s) : 0.0);
+}
+SFLS_HD inline bool act_criterion(double q2, double s, double gb, double zeta, double tau) {
+  const double kap = q2 / s;
+  const double rhs = (1.0 + 1.0 / (gb * s)) * log((1.0 + gb * s) * ((1.0 - zeta) / zeta)) + tau;
+  if (rhs != rhs) return false;
+  return kap > rhs;
+}
+
+struct Driver {
+  const DrvParams& P;
+  DrvState& S;
+  const DrvArrays& A;
+  int N, J;
+
+  SFLS_HD Driver(const DrvParams& p, DrvState& s, const DrvArrays& a)
+      : P(p), S(s), A(a), N(a.N), J(p.J) {}
+
+  SFLS_HD double f_of_eval() const { return *A.logdet + *A.yCy + prior_term(S.K, N, S.zeta); }
+
+  SFLS_HD double gbar() const {
+    if (S.K == 0) return -1.0;
+    double s = 0.0;
+    for (int k = 0; k < S.K; ++k) s += A.ga[k];
+    return s / (double)S.K;
+  }
+
+  // request an evaluation at the current point (th, ga, beta)
+  SFLS_HD void request_current(int32_t bits) {
+    for (int k = 0; k < S.K; ++k) { A.th_e[k] = A.th[k]; A.ga_e[k] = A.ga[k]; }
+    *A.K_e = S.K;
+    *A.beta_e = S.beta;
+    *A.gbar_e = gbar();
+    *A.zeta_e = S.zeta;
+    *A.req = bits;
+    S.nevals += 1;
+  }
+
+  // gradient and replaced diagonal Hessian from the evaluation results
+  // (eqs. derivative, derivative2; replacements (50N)^2 and gamma^-2)
+  SFLS_HD void derivs(const double* gam, double* g, double* h) const {
+    const int K = S.K;
+    for (int k = 0; k < K; ++k) {
+      const double qr = A.ev_q[2 * k], qi = A.ev_q[2 * k + 1];
+      const double rr = A.ev_r[2 * k], ri = A.ev_r[2 * k + 1];
+      const double ur = A.ev_u[2 * k], ui = A.ev_u[2 * k + 1];
+      const double s = A.ev_s[2 * k];
+      const double tr = A.ev_t[2 * k], ti = A.ev_t[2 * k + 1];
+      const double vr = A.ev_v[2 * k];
+      const double xr = A.ev_x[2 * k], xi = A.ev_x[2 * k + 1];
+      const double gk = gam[k];
+      const double q2 = qr * qr + qi * qi, r2 = rr * rr + ri * ri;
+      // Im(t - conj(q) r)
+      const double im_t_qr = ti - (qr * ri - qi * rr);
+      g[k] = 2.0 * gk * im_t_qr;
+      g[K + k] = s - q2;
+      if (h) {
+        // Re{ x - v + g(t^2 - x s) + g(x|q|^2 + s|r|^2 - 2 t r conj q) + (u conj q - |r|^2) }
+        const double t2r = tr * tr - ti * ti;
+        const double xsr = xr * s;
+        // t r conj(q)
+        const double trr = tr * rr - ti * ri, tri = tr * ri + ti * rr;
+        const double trq = trr * qr + tri * qi;
+        const double uq = ur * qr + ui * qi;
+        const double inner = xr - vr + gk * (t2r - xsr) + gk * (xr * q2 + s * r2 - 2.0 * trq) +
+                             (uq - r2);
+        double hth = 2.0 * gk * inner;
+        double hga = 2.0 * s * q2 - s * s;
+        if (!(hth > 0.0)) hth = (50.0 * N) * (50.0 * N);
+        if (!(hga > 0.0)) hga = (gk > 0.0) ? 1.0 / (gk * gk) : 1.0;
+        h[k] = hth;
+        h[K + k] = hga;
+        (void)xi;
+      }
+    }
+  }
+
+  SFLS_HD double dot(const double* a, const double* b, int n) const {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+  }
+
+  SFLS_HD void mem_reset() { S.mem_n = 0; S.mem_head = 0; }
+
+  SFLS_HD double* mem_s(int i) const { return A.Sm + (int64_t)i * 2 * A.kcap; }
+  SFLS_HD double* mem_y(int i) const { return A.Ym + (int64_t)i * 2 * A.kcap; }
+
+  // slot of the i-th oldest pair
+  SFLS_HD int mem_slot(int i) const { return (S.mem_head - S.mem_n + i + J) % J; }
+
+  SFLS_HD void mem_push(const double* s, const double* y, int n) {
+    double sy = dot(s, y, n), ss = dot(s, s, n), yy = dot(y, y, n);
+    if (!(sy > P.curv_eps * sqrt(ss) * sqrt(yy))) return;
+    const int slot = S.mem_head;
+    double* ds = mem_s(slot);
+    double* dy = mem_y(slot);
+    for (int i = 0; i < n; ++i) { ds[i] = s[i]; dy[i] = y[i]; }
+    A.rhom[slot] = 1.0 / sy;
+    S.mem_head = (S.mem_head + 1) % J;
+    if (S.mem_n < J) S.mem_n += 1;
+  }
+
+  // two-loop recursion with H0 = diag(1/h); d = -H g.  Falls back to -g/h
+  // (after a reset) when the result is not a descent direction.
+  SFLS_HD void direction(const double* g, const double* h, double* d, int n) {
+    for (int i = 0; i < n; ++i) d[i] = g[i];
+    for (int i = S.mem_n - 1; i >= 0; --i) {
+      const int sl = mem_slot(i);
+      const double a = A.rhom[sl] * dot(mem_s(sl), d, n);
+      A.am[sl] = a;
+      const double* y = mem_y(sl);
+      for (int e = 0; e < n; ++e) d[e] -= a * y[e];
+    }
+    for (int e = 0; e < n; ++e) d[e] /= h[e];
+    for (int i = 0; i < S.mem_n; ++i) {
+      const int sl = mem_slot(i);
+      const double bta = A.rhom[sl] * dot(mem_y(sl), d, n);
+      const double* s = mem_s(sl);
+      for (int e = 0; e < n; ++e) d[e] += (A.am[sl] - bta) * s[e];
+    }
+    bool ok = true;
+    double gd = 0.0;
+    for (int e = 0; e < n; ++e) {
+      d[e] = -d[e];
+      if (!(d[e] == d[e]) || isinf(d[e])) ok = false;
+      gd += g[e] * d[e];
+    }
+    if (!ok || gd >= 0.0) {
+      mem_reset();
+      for (int e = 0; e < n; ++e) d[e] = -g[e] / h[e];
+    }
+  }
+
+  // set up a line search from the current point along d
+  SFLS_HD void ls_begin(bool polish) {
+    const int K = S.K;
+    const double* d = A.d;
+    S.gd = dot(A.g, d, 2 * K);
+    double amax = INFINITY;
+    int kstar = -1;
+    for (int k = 0; k < K; ++k) {
+      const double dg = d[K + k];
+      if (dg < 0.0) {
+        const double r = A.ga[k] / (-dg);
+        if (r < amax) { amax = r; kstar = k; }
+      }
+    }
+    S.amax = amax;
+    S.kstar = kstar;
+    if (polish) S.alpha = (amax > 1.0) ? 1.0 : 0.5 * amax;
+    else S.alpha = fmin(1.0, amax);
+    S.ls_trial = 0;
+    S.polish = polish ? 1 : 0;
+  }
+
+  SFLS_HD void ls_request() {
+    const int K = S.K;
+    for (int k = 0; k < K; ++k) {
+      double t = A.th[k] + S.alpha * A.d[k];
+      t = t - floor(t);
+      if (t >= 1.0) t = 0.0;
+      A.th_e[k] = t;
+      double gk = A.ga[k] + S.alpha * A.d[K + k];
+      A.ga_e[k] = gk > 0.0 ? gk : 0.0;
+    }
+    if (!S.polish && S.alpha == S.amax && S.kstar >= 0) A.ga_e[S.kstar] = 0.0;
+    *A.K_e = K;
+    *A.beta_e = S.beta;
+    *A.gbar_e = gbar();
+    *A.zeta_e = S.zeta;
+    *A.req = 1;  // REQ_EVAL
+    S.nevals += 1;
+    S.cur_valid = 0;
+  }
+
+  SFLS_HD void remove_component(int k) {
+    for (int j = k; j + 1 < S.K; ++j) { A.th[j] = A.th[j + 1]; A.ga[j] = A.ga[j + 1]; }
+    S.K -= 1;
+  }
+
+  SFLS_HD int pick_deactivation() const {
+    const double thr = (S.zeta > 0.0) ? log((1.0 - S.zeta) / S.zeta) : INFINITY;
+    int best = -1;
+    double bm = 0.0;
+    for (int k = 0; k < S.K; ++k) {
+      const double gk = A.ga[k];
+      double margin;
+      if (!(gk > 0.0)) {
+        margin = INFINITY;
+      } else {
+        const double qr = A.ev_q[2 * k], qi = A.ev_q[2 * k + 1], s = A.ev_s[2 * k];
+        const double den = 1.0 - gk * s;
+        const double q2t = (qr * qr + qi * qi) / (den * den);
+        const double st = s / den;
+        const double lhs = q2t / (1.0 / gk + st) - log1p(gk * st);
+        margin = thr - lhs;
+      }
+      if (margin > 0.0 && (best < 0 || margin > bm)) { best = k; bm = margin; }
+    }
+    return best;
+  }
+
+  // FP64 decision quantities at candidate c (index into cand arrays)
+  SFLS_HD void cand_q2s(int c, double& q2, double& s) const {
+    const double qr = A.cand_q[2 * c], qi = A.cand_q[2 * c + 1];
+    q2 = qr * qr + qi * qi;
+    s = A.cand_s[c];
+  }
+
+  // exact activation decision on cand[0]; returns 1 if a component was added
+  SFLS_HD int exact_decide() {
+    double q2, s;
+    cand_q2s(0, q2, s);
+    const double gh = gamma_hat(q2, s);
+    const double gb = (S.K == 0) ? gh : gbar();
+    const double dl = delta_L(q2, s, gb, S.zeta);
+    const bool ok = gh > 0.0 && S.zeta > 0.0 && act_criterion(q2, s, gb, S.zeta, P.tau) &&
+                    dl < -P.eps_L;
+    if (!ok) return 0;
+    if (S.K >= A.kcap || S.K >= N) { S.cap_hit = 1; return 0; }
+    A.th[S.K] = (double)A.cand[0] / (double)A.L;
+    A.ga[S.K] = gh;
+    S.K += 1;
+    return 1;
+  }
+
+  // approximate sweep over cand[1..ncand-1]; returns number added
+  SFLS_HD int approx_decide() {
+    const int nc = *A.ncand;
+    double q2, s;
+    cand_q2s(0, q2, s);
+    const double gb0 = (S.K == 0) ? gamma_hat(q2, s) : gbar();
+    const double dlmin = delta_L(q2, s, gb0, S.zeta);
+    const double tau = P.approx_use_tau ? P.tau : 0.0;
+    const double gbf = gbar();
+    int m = 0;
+    for (int c = 1; c < nc; ++c) {
+      cand_q2s(c, q2, s);
+      const double gh = gamma_hat(q2, s);
+      const double gb = (S.K == 0) ? gh : gbf;
+      const double dl = delta_L(q2, s, gb, S.zeta);
+      if (gh > 0.0 && S.zeta > 0.0 && act_criterion(q2, s, gb, S.zeta, tau) &&
+          dl <= dlmin / P.approx_ratio) {
+        // insertion by (dl, l)
+        const int l = A.cand[c];
+        int pos = m;
+        while (pos > 0 && (A.cbuf_dl[pos - 1] > dl ||
+                           (A.cbuf_dl[pos - 1] == dl && A.cbuf_l[pos - 1] > l))) {
+          A.cbuf_dl[pos] = A.cbuf_dl[pos - 1];
+          A.cbuf_l[pos] = A.cbuf_l[pos - 1];
+          A.cbuf_gh[pos] = A.cbuf_gh[pos - 1];
+          --pos;
+        }
+        A.cbuf_dl[pos] = dl;
+        A.cbuf_l[pos] = l;
+        A.cbuf_gh[pos] = gh;
+        ++m;
+      }
+    }
+    const int K0 = S.K;
+    int added = 0;
+    const double mind = P.approx_min_dist / (double)N;
+    for (int i = 0; i < m; ++i) {
+      if (S.K >= A.kcap || S.K >= N) { S.cap_hit = 1; break; }
+      const double th = (double)A.cbuf_l[i] / (double)A.L;
+      bool far = true;
+      for (int k = 0; k < S.K; ++k)
+        if (!(wrapd(th, A.th[k]) >= mind)) { far = false; break; }
+      if (far) {
+        A.th[S.K] = th;
+        A.ga[S.K] = A.cbuf_gh[i];
+        S.K += 1;
+        ++added;
+      }
+    }
+    (void)K0;
+    return added;
+  }
+
+  SFLS_HD void finish() {
+    const int K = S.K;
+    // alpha = gamma .* q at the final evaluation; sort by theta (insertion)
+    for (int k = 0; k < K; ++k) {
+      A.out_theta[k] = A.th[k];
+      A.out_gamma[k] = A.ga[k];
+      A.out_alpha[2 * k] = A.ga[k] * A.ev_q[2 * k];
+      A.out_alpha[2 * k + 1] = A.ga[k] * A.ev_q[2 * k + 1];
+    }
+    for (int i = 1; i < K; ++i) {
+      const double t = A.out_theta[i], gg = A.out_gamma[i];
+      const double ar = A.out_alpha[2 * i], ai = A.out_alpha[2 * i + 1];
+      int j = i;
+      while (j > 0 && A.out_theta[j - 1] > t) {
+        A.out_theta[j] = A.out_theta[j - 1];
+        A.out_gamma[j] = A.out_gamma[j - 1];
+        A.out_alpha[2 * j] = A.out_alpha[2 * (j - 1)];
+        A.out_alpha[2 * j + 1] = A.out_alpha[2 * (j - 1) + 1];
+        --j;
+      }
+      A.out_theta[j] = t;
+      A.out_gamma[j] = gg;
+      A.out_alpha[2 * j] = ar;
+      A.out_alpha[2 * j + 1] = ai;
+    }
+    *A.out_K = K;
+    *A.out_beta = S.beta;
+    *A.out_zeta = S.zeta;
+    *A.out_obj = (S.yy == 0.0) ? -INFINITY : f_of_eval();
+    *A.out_iters = S.it;
+    if (A.out_evals) *A.out_evals = S.nevals;
+    int st = S.converged ? 0 : 1;
+    if (S.cap_hit) st = -5;
+    if (S.status != 0) st = S.status;
+    *A.out_status = st;
+    *A.req = 0;
+    S.phase = PH_DONE;
+    S.done = 1;
+  }
+
+  // -------------------------------------------------------------------------
+  // Advance until the next evaluation request (returns) or completion.
+  // -------------------------------------------------------------------------
+  SFLS_HD void step() {
+    enum Lbl {
+      L_OUTER, L_EXACT_BEGIN, L_EXACT_DECIDE, L_AFTER_ACT, L_BETA_DO, L_INNER_BEGIN, L_INNER_DIR,
+      L_LS_RESULT, L_DEACT_CHECK, L_INNER_END, L_TERM_BEGIN, L_TERM_DO, L_POLISH_BEGIN,
+      L_POLISH_STEP, L_FINAL
+    };
+    int lbl;
+    *A.req = 0;
+    if (S.phase != PH_START && S.phase != PH_DONE && *A.lev_status != 0) {
+      // the factorisation failed at the requested point: stop with what we have
+      S.status = -4;
+      *A.out_K = S.K;
+      for (int k = 0; k < S.K; ++k) {
+        A.out_theta[k] = A.th[k];
+        A.out_gamma[k] = A.ga[k];
+        A.out_alpha[2 * k] = 0.0;
+        A.out_alpha[2 * k + 1] = 0.0;
+      }
+      *A.out_beta = S.beta;
+      *A.out_zeta = S.zeta;
+      *A.out_obj = NAN;
+      *A.out_iters = S.it;
+      if (A.out_evals) *A.out_evals = S.nevals;
+      *A.out_status = -4;
+      S.phase = PH_DONE;
+      S.done = 1;
+      return;
+    }
+    switch (S.phase) {
+      case PH_DONE:
+        return;
+      case PH_START: {
+        // initialisation (Sec. II-E)
+        S.it = 0; S.inner = 0; S.pit = 0; S.K = 0; S.z_changed = 1; S.cur_valid = 0;
+        S.converged = 0; S.cap_hit = 0; S.polish = 0; S.mem_n = 0; S.mem_head = 0;
+        S.status = 0; S.nevals = 0; S.done = 0;
+        if (S.yy == 0.0) {
+          S.beta = 0.0; S.zeta = 0.0; S.converged = 1;
+          lbl = L_FINAL;
+          break;
+        }
+        S.beta = 0.01 * S.yy / (double)N;
+        S.zeta = 0.2;
+        S.eps_beta = P.eps_beta_rel * S.yy / (double)N;
+        S.approx_on = P.approx_max_iters > 0;
+        S.L_prev = INFINITY;
+        lbl = L_OUTER;
+        break;
+      }
+      case PH_APPROX_WAIT: {
+        S.cur_valid = 1;
+        const int added = approx_decide();
+        if (added > 0) {
+          S.cur_valid = 0;
+          S.z_changed = 1;
+          lbl = L_AFTER_ACT;
+        } else {
+          S.approx_on = 0;
+          lbl = L_EXACT_DECIDE;  // this grid evaluation is at the current state
+        }
+        break;
+      }
+      case PH_EXACT_WAIT: S.cur_valid = 1; lbl = L_EXACT_DECIDE; break;
+      case PH_BETA_WAIT: S.cur_valid = 1; lbl = L_BETA_DO; break;
+      case PH_INNER_WAIT: S.cur_valid = 1; lbl = L_INNER_DIR; break;
+      case PH_LS_WAIT: lbl = L_LS_RESULT; break;
+      case PH_DEACT_WAIT: S.cur_valid = 1; lbl = L_DEACT_CHECK; break;
+      case PH_TERM_WAIT: S.cur_valid = 1; lbl = L_TERM_DO; break;
+      case PH_POLISH_WAIT: S.cur_valid = 1; lbl = L_POLISH_STEP; break;
+      default: return;
+    }
+
+    for (;;) {
+      switch (lbl) {
+        case L_OUTER: {
+          S.it += 1;
+          if (S.it > P.max_outer) { S.it = P.max_outer; lbl = L_POLISH_BEGIN; break; }
+          if (S.approx_on && S.it <= P.approx_max_iters && S.zeta > 0.0) {
+            request_current(2 | 4 | 1);  // GRID | APPROX | EVAL
+            S.phase = PH_APPROX_WAIT;
+            return;
+          }
+          S.approx_on = S.approx_on && S.it <= P.approx_max_iters && S.zeta > 0.0;
+          lbl = L_EXACT_BEGIN;
+          break;
+        }
+        case L_EXACT_BEGIN: {
+          if (!(S.zeta > 0.0)) { lbl = L_AFTER_ACT; break; }  // nothing can activate
+          request_current(2 | 1);
+          S.phase = PH_EXACT_WAIT;
+          return;
+        }
+        case L_EXACT_DECIDE: {
+          if (exact_decide()) {
+            S.cur_valid = 0;
+            S.z_changed = 1;
+            lbl = L_EXACT_BEGIN;
+          } else {
+            lbl = L_AFTER_ACT;
+          }
+          break;
+        }
+        case L_AFTER_ACT: {
+          const double zn = (double)S.K / (double)N;  // eq. zetaUpdate
+          S.zeta = zn < 0.5 ? zn : 0.5;
+          if (!S.cur_valid) {
+            request_current(1);
+            S.phase = PH_BETA_WAIT;
+            return;
+          }
+          lbl = L_BETA_DO;
+          break;
+        }
+        case L_BETA_DO: {
+          // eq. betaUpdate with mu = gamma.q, tr = beta sum gamma s, ||y - A mu||^2 = beta^2 ||w||^2
+          double tr = 0.0;
+          for (int k = 0; k < S.K; ++k) tr += A.ga[k] * A.ev_s[2 * k];
+          double bn = (S.beta * tr + S.beta * S.beta * (*A.ww)) / (double)N;
+          if (!(bn > S.eps_beta)) bn = S.eps_beta;
+          if (bn != S.beta) { S.beta = bn; S.cur_valid = 0; }
+          if (S.z_changed) { mem_reset(); S.z_changed = 0; }
+          S.inner = 0;
+          lbl = L_INNER_BEGIN;
+          break;
+        }
+        case L_INNER_BEGIN: {
+          if (S.inner >= P.max_inner || S.K == 0) { lbl = L_TERM_BEGIN; break; }
+          if (!S.cur_valid) {
+            request_current(1);
+            S.phase = PH_INNER_WAIT;
+            return;
+          }
+          lbl = L_INNER_DIR;
+          break;
+        }
+        case L_INNER_DIR: {
+          const int n = 2 * S.K;
+          derivs(A.ga, A.g, A.gt);  // gt used as h scratch
+          direction(A.g, A.gt, A.d, n);
+          S.lam2 = -dot(A.g, A.d, n);
+          S.f_cur = f_of_eval();
+          ls_begin(false);
+          ls_request();
+          S.phase = PH_LS_WAIT;
+          return;
+        }
+        case L_LS_RESULT: {
+          const double ft = f_of_eval();
+          const double slack = S.polish ? P.polish_ftol * (1.0 + fabs(S.f_cur)) : 0.0;
+          if (ft <= S.f_cur + P.ls_c1 * S.alpha * S.gd + slack) {
+            // accept: pair (alpha d, g_t - g), move to the trial point
+            const int K = S.K, n = 2 * K;
+            derivs(A.ga_e, A.gt, nullptr);
+            for (int e = 0; e < n; ++e) { A.gt[e] -= A.g[e]; A.d[e] *= S.alpha; }
+            mem_push(A.d, A.gt, n);
+            double maxdth = 0.0;
+            for (int k = 0; k < K; ++k) {
+              maxdth = fmax(maxdth, fabs(A.d[k]));
+              A.th[k] = A.th_e[k];
+              A.ga[k] = A.ga_e[k];
+            }
+            S.cur_valid = 1;
+            if (S.polish) {
+              S.pit += 1;
+              if (maxdth < P.polish_tol / (double)N) { lbl = L_FINAL; break; }
+              lbl = L_POLISH_STEP;
+              break;
+            }
+            lbl = L_DEACT_CHECK;
+            break;
+          }
+          S.alpha *= 0.5;
+          S.ls_trial += 1;
+          if (S.ls_trial >= P.ls_max) {
+            // line search failed: current point unchanged (needs re-evaluation)
+            if (S.polish) { lbl = L_FINAL; break; }
+            lbl = L_TERM_BEGIN;
+            break;
+          }
+          ls_request();
+          S.phase = PH_LS_WAIT;
+          return;
+        }
+        case L_DEACT_CHECK: {
+          const int k = pick_deactivation();
+          if (k >= 0) {
+            remove_component(k);
+            mem_reset();
+            S.cur_valid = 0;
+            request_current(1);
+            S.phase = PH_DEACT_WAIT;
+            return;
+          }
+          lbl = L_INNER_END;
+          break;
+        }
+        case L_INNER_END: {
+          S.inner += 1;
+          if (S.lam2 < (double)N * P.tol_newton) { lbl = L_TERM_BEGIN; break; }
+          lbl = L_INNER_BEGIN;
+          break;
+        }
+        case L_TERM_BEGIN: {
+          if (!S.cur_valid) {
+            request_current(1);
+            S.phase = PH_TERM_WAIT;
+            return;
+          }
+          lbl = L_TERM_DO;
+          break;
+        }
+        case L_TERM_DO: {
+          const double Lc = f_of_eval();
+          if (fabs(Lc - S.L_prev) < (double)N * P.tol_obj) {
+            S.converged = 1;
+            lbl = L_POLISH_BEGIN;
+            break;
+          }
+          S.L_prev = Lc;
+          lbl = L_OUTER;
+          break;
+        }
+        case L_POLISH_BEGIN: {
+          mem_reset();
+          S.pit = 0;
+          if (!S.cur_valid) {
+            request_current(1);
+            S.phase = PH_POLISH_WAIT;
+            return;
+          }
+          lbl = L_POLISH_STEP;
+          break;
+        }
+        case L_POLISH_STEP: {
+          if (S.pit >= P.polish_max_iters || S.K == 0) { lbl = L_FINAL; break; }
+          const int n = 2 * S.K;
+          derivs(A.ga, A.g, A.gt);
+          direction(A.g, A.gt, A.d, n);
+          S.f_cur = f_of_eval();
+          ls_begin(true);
+          ls_request();
+          S.phase = PH_LS_WAIT;
+          return;
+        }
+        case L_FINAL: {
+          if (!S.cur_valid && S.yy != 0.0) {
+            request_current(1);
+            S.phase = PH_POLISH_WAIT;
+            S.pit = P.polish_max_iters;  // resumes into L_POLISH_STEP -> L_FINAL
+            return;
+          }
+          finish();
+          return;
+        }
+        default:
+          return;
+      }
+    }
+  }
+};
+
+}  // namespace sfls

@@ -1,0 +1,262 @@
+// a4: w = C^{-1} y through the Gohberg-Semencul factors as FFT convolutions;
+// a5: diagonal sums omega as FFT correlations of rho with its moments.
+// One workgroup per instance; the FFT array of P points lives in LDS.
+#include "sfls_kernels.hpp"
+#include "k_launch.hpp"
+
+namespace sfls {
+
+constexpr int CONV_NT = 256;
+
+// W_P^m = exp(-j 2 pi m / P) from the table tw[k] = exp(-j 2 pi k / 2^logtw), k < 2^(logtw-1)
+__device__ __forceinline__ cd tw_pow(const cd* __restrict__ tw, int logtw, int64_t m, int logP) {
+  const int64_t P = (int64_t)1 << logP;
+  m &= (P - 1);
+  const int64_t half = P >> 1;
+  if (m >= half) {
+    cd w = tw[(m - half) << (logtw - logP)];
+    return cd{-w.x, -w.y};
+  }
+  return tw[m << (logtw - logP)];
+}
+
+template <typename YT> __device__ __forceinline__ cd load_y(const YT* y, int64_t i);
+template <> __device__ __forceinline__ cd load_y<cd>(const cd* y, int64_t i) { return y[i]; }
+template <> __device__ __forceinline__ cd load_y<cf>(const cf* y, int64_t i) { return to_d(y[i]); }
+
+// ---------------------------------------------------------------------------
+// a4.  With rho~_m = rho_{N-1-m} and y^_k = y_{N-1-k} (reversals):
+//   u1 = T1 y      : u1_i = (rho~ * y^)_{N-1-i}
+//   v1 = T0^H y    : v1_i = (conj(rho) * y^)_{N-2-i}   (v1_{N-1} = 0)
+//   u2 = T1^H u1   = (conj(rho~) * u1)_i
+//   v2 = T0 v1     = (rho * v1)_{i-1}
+//   w  = (u2 - v2) / delta_{N-1}                       (eq. gohberg-semencul)
+// All convolutions are length-P circular ones (P >= 2N-1, no wrap into the
+// kept indices).  Spectra are kept in bit-reversed order (DIF forward, DIT
+// inverse), and the spectra of the reversed / conjugated rho are read off
+// A = FFT(rho) at the negated frequency:
+//   FFT(rho~)(f) = W^{f(N-1)} A(-f),  FFT(conj rho)(f) = conj A(-f),
+//   FFT(conj rho~)(f) = W^{f(N-1)} conj A(f),  delay by one: W^f.
+// Scratch per instance (4 P points): A, Y/U, X1, X2.  A stays for a5.
+// ---------------------------------------------------------------------------
+template <typename YT>
+__global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict__ info,
+                                                      const int32_t* __restrict__ req,
+                                                      const YT* __restrict__ y,
+                                                      const cd* __restrict__ rho,
+                                                      const double* __restrict__ delta,
+                                                      const cd* __restrict__ tw, int logtw,
+                                                      cd* __restrict__ scratch, cd* __restrict__ w,
+                                                      double* __restrict__ yCy,
+                                                      double* __restrict__ ww) {
+  const int bi = blockIdx.x;
+  if (req && !(req[bi] & REQ_EVAL)) return;
+  const InstInfo in = info[bi];
+  const int N = in.N, P = in.P, logP = in.logP;
+  extern __shared__ cd lds[];
+  __shared__ double red[2 * (CONV_NT / 64)];
+  const int tid = threadIdx.x;
+  const cd* rb = rho + in.off;
+  const YT* yb = y + in.off;
+  cd* A = scratch + in.poff;
+  cd* Y = A + P;
+  cd* X1 = Y + P;
+  cd* X2 = X1 + P;
+  const double invP = 1.0 / (double)P;
+
+  // (1) A = FFT(rho)
+  for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? rb[t] : cd{0.0, 0.0};
+  __syncthreads();
+  dif_fft<cd, CONV_NT>(lds, logP, -1, tw, logtw);
+  for (int t = tid; t < P; t += CONV_NT) A[t] = lds[t];
+  // (2) Y = FFT(y^)
+  for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? load_y(yb, N - 1 - t) : cd{0.0, 0.0};
+  __syncthreads();
+  dif_fft<cd, CONV_NT>(lds, logP, -1, tw, logtw);
+  for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[t];
+  __syncthreads();
+  // (3) u1 from FFT(rho~) . Y
+  for (int p = tid; p < P; p += CONV_NT) {
+    const int f = bitrev(p, logP);
+    const int pm = bitrev((P - f) & (P - 1), logP);
+    lds[p] = cmul(cmul(tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), A[pm]), Y[p]);
+  }
+  __syncthreads();
+  dit_fft<cd, CONV_NT>(lds, logP, +1, tw, logtw);
+  for (int i = tid; i < N; i += CONV_NT) X1[i] = cscale(lds[N - 1 - i], invP);
+  __syncthreads();
+  // (4) v1 from conj(A(-f)) . Y
+  for (int p = tid; p < P; p += CONV_NT) {
+    const int f = bitrev(p, logP);
+    const int pm = bitrev((P - f) & (P - 1), logP);
+    lds[p] = cmul(cconj(A[pm]), Y[p]);
+  }
+  __syncthreads();
+  dit_fft<cd, CONV_NT>(lds, logP, +1, tw, logtw);
+  for (int i = tid; i < N; i += CONV_NT)
+    X2[i] = (i <= N - 2) ? cscale(lds[N - 2 - i], invP) : cd{0.0, 0.0};
+  __syncthreads();
+  // (5) U = FFT(u1) -> Y
+  for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? X1[t] : cd{0.0, 0.0};
+  __syncthreads();
+  dif_fft<cd, CONV_NT>(lds, logP, -1, tw, logtw);
+  for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[t];
+  __syncthreads();
+  // (6) V = FFT(v1), kept in LDS
+  for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? X2[t] : cd{0.0, 0.0};
+  __syncthreads();
+  dif_fft<cd, CONV_NT>(lds, logP, -1, tw, logtw);
+  // (7) W = FFT(conj rho~) U - W^f A V
+  for (int p = tid; p < P; p += CONV_NT) {
+    const int f = bitrev(p, logP);
+    const cd a = A[p];
+    const cd t1 = cmul(cmul(tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), cconj(a)), Y[p]);
+    const cd t2 = cmul(cmul(tw_pow(tw, logtw, f, logP), a), lds[p]);
+    lds[p] = csub(t1, t2);
+  }
+  __syncthreads();
+  dit_fft<cd, CONV_NT>(lds, logP, +1, tw, logtw);
+  const double sc = invP / delta[in.off + N - 1];
+  double acc[2] = {0.0, 0.0};
+  for (int i = tid; i < N; i += CONV_NT) {
+    const cd wi = cscale(lds[i], sc);
+    w[in.off + i] = wi;
+    const cd yi = load_y(yb, i);
+    acc[0] += fma(yi.x, wi.x, yi.y * wi.y);  // Re(conj(y) w)
+    acc[1] += cabs2(wi);
+  }
+  block_sum<CONV_NT, 2>(acc, red);
+  if (tid == 0) {
+    if (yCy) yCy[bi] = acc[0];
+    if (ww) ww[bi] = acc[1];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a5.  Diagonal sums as correlations.  With G_a the spectra of
+// f_a(q) = (q - c)^a rho_q (c = (N-1)/2; f_0 spectrum = A from a4) and a
+// polynomial weight W(q, p) = sum_ab C[a][b] (q-c)^a (p-c)^b derived from the
+// Gohberg-Semencul structure (Appendix B):
+//   omega(i) = delta^{-1} sum_q W(q, q+i) rho_q conj(rho_{q+i})
+//            = delta^{-1} conj( IFFT( sum_ab C[a][b] G_b conj(G_a) ) (i) ).
+// `which` selects the outputs (bit0 s, bit1 t, bit2 v, bit3 x).  omega_s is
+// always written to oms (P points, lag i at i mod P) for the grid stage; the
+// API outputs (2N-1 points, lag i at i+N-1) are written when non-NULL.
+// Scratch: G_0 = A (from a4 when have_g0, else computed here) and the three
+// following P-blocks for G_1..G_3.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(CONV_NT) void k_omega(const InstInfo* __restrict__ info,
+                                                   const int32_t* __restrict__ req,
+                                                   const cd* __restrict__ rho,
+                                                   const double* __restrict__ delta,
+                                                   const SepCoef* __restrict__ coef,
+                                                   const cd* __restrict__ tw, int logtw,
+                                                   cd* __restrict__ scratch, int which,
+                                                   int have_g0,
+                                                   cd* __restrict__ oms, cd* __restrict__ o_s,
+                                                   cd* __restrict__ o_t, cd* __restrict__ o_v,
+                                                   cd* __restrict__ o_x) {
+  const int bi = blockIdx.x;
+  if (req && !(req[bi] & REQ_GRID)) return;
+  const InstInfo in = info[bi];
+  const int N = in.N, P = in.P, logP = in.logP;
+  extern __shared__ cd lds[];
+  const int tid = threadIdx.x;
+  const cd* rb = rho + in.off;
+  cd* G[4];
+  G[0] = scratch + in.poff;
+  G[1] = G[0] + P;
+  G[2] = G[1] + P;
+  G[3] = G[2] + P;
+  const int amax = (which & ~1) ? 3 : 1;
+  const double cN = 0.5 * (double)(N - 1);
+  for (int a = have_g0 ? 1 : 0; a <= amax; ++a) {
+    for (int t = tid; t < P; t += CONV_NT) {
+      cd v{0.0, 0.0};
+      if (t < N) {
+        const double x = (double)t - cN;
+        double m = 1.0;
+        for (int e = 0; e < a; ++e) m *= x;
+        v = cscale(rb[t], m);
+      }
+      lds[t] = v;
+    }
+    __syncthreads();
+    dif_fft<cd, CONV_NT>(lds, logP, -1, tw, logtw);
+    for (int t = tid; t < P; t += CONV_NT) G[a][t] = lds[t];
+    __syncthreads();
+  }
+  const SepCoef cf = coef[bi];
+  const double scale = 1.0 / ((double)P * delta[in.off + N - 1]);
+  cd* outs[4] = {o_s, o_t, o_v, o_x};
+  for (int qk = 0; qk < 4; ++qk) {
+    if (!(which & (1 << qk))) continue;
+    const double* C = cf.c[qk];
+    const int am = (qk == 0) ? 1 : 3;
+    for (int p = tid; p < P; p += CONV_NT) {
+      cd g[4];
+      for (int a = 0; a <= am; ++a) g[a] = G[a][p];
+      cd acc{0.0, 0.0};
+      for (int a = 0; a <= am; ++a)
+        for (int b2 = 0; b2 <= am; ++b2) {
+          const double cab = C[a * 4 + b2];
+          if (cab != 0.0) {
+            const cd pr = cmulc(g[b2], g[a]);  // G_b conj(G_a)
+            acc.x = fma(cab, pr.x, acc.x);
+            acc.y = fma(cab, pr.y, acc.y);
+          }
+        }
+      lds[p] = acc;
+    }
+    __syncthreads();
+    dit_fft<cd, CONV_NT>(lds, logP, +1, tw, logtw);
+    for (int t = tid; t < P; t += CONV_NT) {
+      // lag i = t for t < N, i = t - P for t > P - N
+      const bool pos = t < N, neg = t > P - N;
+      if (!pos && !neg) continue;
+      const cd om = cscale(cconj(lds[t]), scale);
+      if (qk == 0 && oms) oms[in.poff + t] = om;
+      if (outs[qk]) {
+        const int i = pos ? t : t - P;
+        outs[qk][in.ooff + i + N - 1] = om;
+      }
+    }
+    if (qk == 0 && oms) {
+      for (int t = tid; t < P; t += CONV_NT)
+        if (!(t < N) && !(t > P - N)) oms[in.poff + t] = cd{0.0, 0.0};
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void* y, int ydtype,
+                           const cd* rho, const double* delta, const cd* tw, int logtw,
+                           cd* scratch, cd* w, double* yCy, double* ww, int B, int maxP,
+                           hipStream_t st) {
+  const size_t shm = (size_t)maxP * sizeof(cd);
+  if (ydtype == 1) {
+    (void)hipFuncSetAttribute((const void*)k_gs_apply<cd>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)shm);
+    hipLaunchKernelGGL(k_gs_apply<cd>, dim3(B), dim3(CONV_NT), shm, st, info, req, (const cd*)y,
+                       rho, delta, tw, logtw, scratch, w, yCy, ww);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_gs_apply<cf>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)shm);
+    hipLaunchKernelGGL(k_gs_apply<cf>, dim3(B), dim3(CONV_NT), shm, st, info, req, (const cf*)y,
+                       rho, delta, tw, logtw, scratch, w, yCy, ww);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
+                        const double* delta, const SepCoef* coef, const cd* tw, int logtw,
+                        cd* scratch, int which, int have_g0, cd* oms, cd* o_s, cd* o_t,
+                        cd* o_v, cd* o_x, int B, int maxP, hipStream_t st) {
+  const size_t shm = (size_t)maxP * sizeof(cd);
+  (void)hipFuncSetAttribute((const void*)k_omega, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_omega, dim3(B), dim3(CONV_NT), shm, st, info, req, rho, delta, coef, tw,
+                     logtw, scratch, which, have_g0, oms, o_s, o_t, o_v, o_x);
+  return hipGetLastError();
+}
+
+}  // namespace sfls

@@ -1,0 +1,135 @@
+// a9 on the device: one wave per instance runs the estimator's state machine
+// between evaluation rounds; plus small setup kernels.
+#include "k_launch.hpp"
+
+namespace sfls {
+
+__global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info,
+                                               const DrvParams* __restrict__ prm, DrvPools p,
+                                               int B) {
+  const int b = blockIdx.x;
+  if (b >= B || threadIdx.x != 0) return;
+  const InstInfo in = info[b];
+  DrvState S = p.st[b];
+  if (S.phase == PH_DONE) return;
+  const int64_t ko = in.koff, k2 = 2 * in.koff, co = in.coff;
+  const int J = prm->J;
+  DrvArrays A;
+  A.N = in.N;
+  A.L = in.L;
+  A.kcap = in.kcap;
+  A.th = p.th + ko;
+  A.ga = p.ga + ko;
+  A.th_e = p.th_e + ko;
+  A.ga_e = p.ga_e + ko;
+  A.K_e = p.K_e + b;
+  A.beta_e = p.beta_e + b;
+  A.req = p.req + b;
+  A.gbar_e = p.gbar_e + b;
+  A.zeta_e = p.zeta_e + b;
+  A.g = p.g + k2;
+  A.d = p.d + k2;
+  A.gt = p.gt + k2;
+  A.Sm = p.Sm + (int64_t)J * k2;
+  A.Ym = p.Ym + (int64_t)J * k2;
+  A.rhom = p.rhom + (int64_t)J * b;
+  A.am = p.am + (int64_t)J * b;
+  A.ev_q = reinterpret_cast<const double*>(p.ev_q + ko);
+  A.ev_r = reinterpret_cast<const double*>(p.ev_r + ko);
+  A.ev_u = reinterpret_cast<const double*>(p.ev_u + ko);
+  A.ev_s = reinterpret_cast<const double*>(p.ev_s + ko);
+  A.ev_t = reinterpret_cast<const double*>(p.ev_t + ko);
+  A.ev_v = reinterpret_cast<const double*>(p.ev_v + ko);
+  A.ev_x = reinterpret_cast<const double*>(p.ev_x + ko);
+  A.logdet = p.logdet + b;
+  A.yCy = p.yCy + b;
+  A.ww = p.ww + b;
+  A.lev_status = p.lev_status + b;
+  A.cand = p.cand + co;
+  A.ncand = p.ncand + b;
+  A.cand_q = reinterpret_cast<const double*>(p.cand_q + co);
+  A.cand_s = p.cand_s + co;
+  A.cbuf_dl = p.cbuf_dl + co;
+  A.cbuf_gh = p.cbuf_gh + co;
+  A.cbuf_l = p.cbuf_l + co;
+  const int64_t oo = p.out_koff[b];
+  A.out_K = p.out_K + b;
+  A.out_theta = p.out_theta + oo;
+  A.out_alpha = reinterpret_cast<double*>(p.out_alpha + oo);
+  A.out_gamma = p.out_gamma + oo;
+  A.out_beta = p.out_beta + b;
+  A.out_zeta = p.out_zeta + b;
+  A.out_obj = p.out_obj + b;
+  A.out_iters = p.out_iters + b;
+  A.out_evals = p.out_evals ? p.out_evals + b : nullptr;
+  A.out_status = p.out_status + b;
+  Driver drv(*prm, S, A);
+  drv.step();
+  p.st[b] = S;
+  if (S.phase != PH_DONE) atomicAdd(p.notdone, 1);
+}
+
+// ||y||^2 per instance and the initial state (phase START).
+template <typename YT>
+__global__ __launch_bounds__(256) void k_init_state(const InstInfo* __restrict__ info,
+                                                    const YT* __restrict__ y,
+                                                    DrvState* __restrict__ st,
+                                                    int32_t* __restrict__ req) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  const InstInfo in = info[b];
+  double acc[1] = {0.0};
+  for (int i = threadIdx.x; i < in.N; i += 256) {
+    const double re = (double)y[in.off + i].x, im = (double)y[in.off + i].y;
+    acc[0] = fma(re, re, fma(im, im, acc[0]));
+  }
+  block_sum<256, 1>(acc, red);
+  if (threadIdx.x == 0) {
+    DrvState s = {};
+    s.phase = PH_START;
+    s.yy = acc[0];
+    st[b] = s;
+    req[b] = 0;
+  }
+}
+
+__global__ void k_twiddles(cd* tw64, cf* tw32, int logtw) {
+  const int64_t n = (int64_t)1 << logtw;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n / 2;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const cd e = cis_frac(k, n);
+    tw64[k] = cd{e.x, -e.y};
+    tw32[k] = cf{(float)e.x, (float)-e.y};
+  }
+}
+
+__global__ void k_zero_i32(int32_t* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_driver(const InstInfo* info, const DrvParams* prm, DrvPools pools, int B,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_driver, dim3(B), dim3(64), 0, st, info, prm, pools, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(const InstInfo* info, const void* y, int ydtype, DrvState* st,
+                             int32_t* req, int B, hipStream_t s) {
+  if (ydtype == 1)
+    hipLaunchKernelGGL(k_init_state<cd>, dim3(B), dim3(256), 0, s, info, (const cd*)y, st, req);
+  else
+    hipLaunchKernelGGL(k_init_state<cf>, dim3(B), dim3(256), 0, s, info, (const cf*)y, st, req);
+  return hipGetLastError();
+}
+
+hipError_t launch_twiddles(cd* tw64, cf* tw32, int logtw, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddles, dim3(128), dim3(256), 0, st, tw64, tw32, logtw);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace sfls

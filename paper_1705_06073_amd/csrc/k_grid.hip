@@ -1,0 +1,287 @@
+// a6: q^G and s^G on the grid theta_l = l/L, and Delta L;  a7: selection
+// (argmin for the exact activation step, local minima for the approximate
+// scheme).
+#include "sfls_kernels.hpp"
+#include "k_launch.hpp"
+
+namespace sfls {
+
+constexpr int GRID_NT = 256;
+constexpr int SEL_NT = 256;
+constexpr int SEL_COLLECT = 2048;  // local minima gathered before sorting
+
+template <typename R> __device__ __forceinline__ R rinf();
+template <> __device__ __forceinline__ double rinf<double>() { return __builtin_inf(); }
+template <> __device__ __forceinline__ float rinf<float>() { return __builtin_inff(); }
+
+// Delta L of eq. delta_L at one grid point in precision R.  gb > 0: fixed
+// average variance; gb <= 0: the per-point optimum of eq. activate_gamma
+// (empty active set), for which Delta L = ln(kappa odds) - (kappa - 1).
+template <typename R>
+__device__ __forceinline__ R delta_L_point(R q2, R s, R gb, R odds) {
+  if (!(s > (R)0)) return rinf<R>();
+  if (gb > (R)0) return log(fma(gb, s, (R)1) * odds) - q2 / ((R)1 / gb + s);
+  const R kap = q2 / s;
+  if (kap > (R)1) return log(kap * odds) - (kap - (R)1);
+  return log(odds);
+}
+
+// ---------------------------------------------------------------------------
+// a6.  Grid of L = R M points split by residue r = l mod R (M >= N a power
+// of two):  with l = R f + r,
+//   q^G_l = sum_n [w_n e^{-j2pi n r/L}] e^{-j2pi n f/M}           (M-point DFT)
+//   s^G_l = sum_m [sum_{i = m mod M} omega_s(i) e^{j2pi i r/L}] e^{+j2pi m f/M}
+// so each workgroup (instance, r) runs two M-point FFTs in LDS.  The
+// residue twiddles come from exact fractions (n r mod L)/L.  Outputs per
+// point: optional q^G, s^G, Delta L; always a per-workgroup argmin
+// (lowest l on ties).  Blocks of one instance sit on one XCD:
+// blockIdx.x = xcd + 8 j  ->  instance-group j/R... see host mapping.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ info,
+                                                  const int32_t* __restrict__ req,
+                                                  const cd* __restrict__ w,
+                                                  const cd* __restrict__ oms,
+                                                  const double* __restrict__ gbar,
+                                                  const double* __restrict__ zeta,
+                                                  const typename cpx<R>::T* __restrict__ tw,
+                                                  int logtw, int Rmax, int B,
+                                                  typename cpx<R>::T* __restrict__ qG,
+                                                  R* __restrict__ sG, R* __restrict__ dL,
+                                                  double* __restrict__ part_val,
+                                                  int64_t* __restrict__ part_idx) {
+  using C = typename cpx<R>::T;
+  // XCD-aware mapping: consecutive block ids go round-robin over 8 XCDs; give
+  // all residues of one instance the same id mod 8 so they share an L2.
+  const int id = blockIdx.x;
+  const int xcd = id & 7, slot = id >> 3;
+  const int bi = xcd + 8 * (slot / Rmax);
+  const int r = slot % Rmax;
+  if (bi >= B) return;
+  if (req && !(req[bi] & REQ_GRID)) return;
+  const InstInfo in = info[bi];
+  if (r >= in.R) {
+    if (threadIdx.x == 0) { part_val[(int64_t)bi * Rmax + r] = __builtin_inf(); part_idx[(int64_t)bi * Rmax + r] = -1; }
+    return;
+  }
+  const int N = in.N, M = in.M, logM = in.logM, L = in.L, P = in.P;
+  extern __shared__ unsigned char smem[];
+  C* lq = reinterpret_cast<C*>(smem);
+  C* ls = lq + M;
+  __shared__ double rv[GRID_NT / 64];
+  __shared__ int64_t ri[GRID_NT / 64];
+  const int tid = threadIdx.x;
+  const cd* wb = w + in.off;
+  const cd* ob = oms + in.poff;
+  for (int m = tid; m < M; m += GRID_NT) {
+    cd qv{0.0, 0.0}, sv{0.0, 0.0};
+    if (m < N) qv = cmul(wb[m], cconj(cis_frac(((int64_t)m * r) % L, L)));
+    if (m < N) sv = cmul(ob[m], cis_frac(((int64_t)m * r) % L, L));
+    const int i2 = m - M;  // negative lag folded onto m
+    if (i2 > -N) {
+      const int64_t ph = (((int64_t)i2 % L + L) % L) * r % L;
+      sv = cfma(ob[(i2 + P) & (P - 1)], cis_frac(ph, L), sv);
+    }
+    lq[m] = C{(decltype(C{}.x))qv.x, (decltype(C{}.x))qv.y};
+    ls[m] = C{(decltype(C{}.x))sv.x, (decltype(C{}.x))sv.y};
+  }
+  __syncthreads();
+  dif_fft<C, GRID_NT>(lq, logM, -1, tw, logtw);
+  dif_fft<C, GRID_NT>(ls, logM, +1, tw, logtw);
+  const R gb = (R)gbar[bi];
+  const double z = zeta[bi];
+  const R odds = (R)((1.0 - z) / z);
+  double best = __builtin_inf();
+  int64_t bidx = INT64_MAX;
+  for (int p = tid; p < M; p += GRID_NT) {
+    const int f = bitrev(p, logM);
+    const int64_t l = (int64_t)f * in.R + r;
+    const C qv = lq[p];
+    const R sv = ls[p].x;
+    const R q2 = cabs2(qv);
+    R d = delta_L_point<R>(q2, sv, gb, odds);
+    if (d != d) d = rinf<R>();
+    if (qG) qG[in.goff + l] = qv;
+    if (sG) sG[in.goff + l] = sv;
+    if (dL) dL[in.goff + l] = d;
+    const double dd = (double)d;
+    if (dd < best || (dd == best && l < bidx)) { best = dd; bidx = l; }
+  }
+  // block argmin, lowest index on ties
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double ov = __shfl_xor(best, o);
+    const int64_t oi = __shfl_xor(bidx, o);
+    if (ov < best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+  }
+  if (lane == 0) { rv[wv] = best; ri[wv] = bidx; }
+  __syncthreads();
+  if (tid == 0) {
+    for (int k = 1; k < GRID_NT / 64; ++k)
+      if (rv[k] < best || (rv[k] == best && ri[k] < bidx)) { best = rv[k]; bidx = ri[k]; }
+    part_val[(int64_t)bi * Rmax + r] = best;
+    part_idx[(int64_t)bi * Rmax + r] = bidx;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a7.  Selection, one workgroup per instance.
+//   exact:        cand[0] = argmin over the residue partials (lowest l).
+//   approximate:  cand[0] = argmin; cand[1..] = local minima of Delta L
+//                 (cyclic neighbours, <= on both sides) with
+//                 Delta L <= Delta L_min / ratio + slack, sorted by
+//                 (Delta L, l), at most cand_cap of them.
+// The slack keeps every point the FP64 re-check could accept when the grid is
+// FP32.  ncand[b] = number of entries written; overflow[b] = 1 if more local
+// minima passed the pre-filter than could be kept.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(SEL_NT) void k_select(const InstInfo* __restrict__ info,
+                                                   const int32_t* __restrict__ req,
+                                                   const R* __restrict__ dL, int Rmax,
+                                                   const double* __restrict__ part_val,
+                                                   const int64_t* __restrict__ part_idx,
+                                                   double approx_ratio, double slack_rel,
+                                                   int cand_cap, int32_t* __restrict__ cand,
+                                                   int32_t* __restrict__ ncand,
+                                                   int32_t* __restrict__ overflow) {
+  const int bi = blockIdx.x;
+  if (!(req[bi] & REQ_GRID)) return;
+  const InstInfo in = info[bi];
+  const int tid = threadIdx.x;
+  __shared__ double best_v;
+  __shared__ int64_t best_i;
+  __shared__ double key_d[SEL_COLLECT];
+  __shared__ int32_t key_l[SEL_COLLECT];
+  __shared__ int cnt;
+  if (tid == 0) {
+    double bv = __builtin_inf();
+    int64_t bx = INT64_MAX;
+    for (int r = 0; r < in.R; ++r) {
+      const double v = part_val[(int64_t)bi * Rmax + r];
+      const int64_t ix = part_idx[(int64_t)bi * Rmax + r];
+      if (v < bv || (v == bv && ix < bx)) { bv = v; bx = ix; }
+    }
+    if (bx == INT64_MAX) bx = 0;
+    best_v = bv;
+    best_i = bx;
+    cnt = 0;
+  }
+  __syncthreads();
+  int32_t* cb = cand + in.coff;
+  if (!(req[bi] & REQ_APPROX)) {
+    if (tid == 0) { cb[0] = (int32_t)best_i; ncand[bi] = 1; overflow[bi] = 0; }
+    return;
+  }
+  const double dmin = best_v;
+  const int L = in.L;
+  const R* d = dL + in.goff;
+  if (dmin < 0.0) {
+    const double thr = dmin / approx_ratio + slack_rel * fabs(dmin);
+    for (int l = tid; l < L; l += SEL_NT) {
+      const double v = (double)d[l];
+      if (!(v <= thr)) continue;
+      const double vl = (double)d[(l - 1 + L) & (L - 1)];
+      const double vr = (double)d[(l + 1) & (L - 1)];
+      if (v <= vl && v <= vr) {
+        const int slot = atomicAdd(&cnt, 1);
+        if (slot < SEL_COLLECT) { key_d[slot] = v; key_l[slot] = l; }
+      }
+    }
+  }
+  __syncthreads();
+  const int total = cnt;
+  const int kept = min(total, SEL_COLLECT);
+  // bitonic sort of (value, index) over the next power of two
+  int n2 = 1;
+  while (n2 < kept) n2 <<= 1;
+  for (int i = kept + tid; i < n2; i += SEL_NT) { key_d[i] = __builtin_inf(); key_l[i] = INT32_MAX; }
+  __syncthreads();
+  for (int k = 2; k <= n2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < n2; i += SEL_NT) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const bool up = (i & k) == 0;
+          const double a = key_d[i], b2 = key_d[ixj];
+          const int la = key_l[i], lb = key_l[ixj];
+          const bool gt = (a > b2) || (a == b2 && la > lb);
+          if (gt == up) { key_d[i] = b2; key_d[ixj] = a; key_l[i] = lb; key_l[ixj] = la; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int nout = min(kept, cand_cap);
+  if (tid == 0) { cb[0] = (int32_t)best_i; ncand[bi] = 1 + nout; overflow[bi] = (total > nout) ? 1 : 0; }
+  for (int i = tid; i < nout; i += SEL_NT) cb[1 + i] = key_l[i];
+}
+
+// argmin over the residue partials (lowest l on ties) for the API call
+__global__ void k_argmin_out(const InstInfo* __restrict__ info, int Rmax,
+                             const double* __restrict__ part_val,
+                             const int64_t* __restrict__ part_idx, int64_t* __restrict__ amin,
+                             double* __restrict__ aval, int B) {
+  const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (bi >= B) return;
+  const int R = info[bi].R;
+  double bv = __builtin_inf();
+  int64_t bx = INT64_MAX;
+  for (int r = 0; r < R; ++r) {
+    const double v = part_val[(int64_t)bi * Rmax + r];
+    const int64_t ix = part_idx[(int64_t)bi * Rmax + r];
+    if (v < bv || (v == bv && ix < bx)) { bv = v; bx = ix; }
+  }
+  if (bx == INT64_MAX) bx = 0;
+  if (amin) amin[bi] = bx;
+  if (aval) aval[bi] = bv;
+}
+
+hipError_t launch_argmin_out(const InstInfo* info, int Rmax, const double* part_val,
+                             const int64_t* part_idx, int64_t* amin, double* aval, int B,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_argmin_out, dim3((B + 63) / 64), dim3(64), 0, st, info, Rmax, part_val,
+                     part_idx, amin, aval, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid(int prec, const InstInfo* info, const int32_t* req, const cd* w,
+                       const cd* oms, const double* gbar, const double* zeta, const void* tw,
+                       int logtw, int Rmax, int B, int maxM, void* qG, void* sG, void* dL,
+                       double* part_val, int64_t* part_idx, hipStream_t st) {
+  const int nslots = ((B + 7) / 8) * Rmax;  // per XCD
+  dim3 grid(8 * nslots);
+  if (prec == 0) {
+    const size_t shm = 2 * (size_t)maxM * sizeof(cd);
+    (void)hipFuncSetAttribute((const void*)k_grid<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)shm);
+    hipLaunchKernelGGL(k_grid<double>, grid, dim3(GRID_NT), shm, st, info, req, w, oms, gbar,
+                       zeta, (const cd*)tw, logtw, Rmax, B, (cd*)qG, (double*)sG, (double*)dL,
+                       part_val, part_idx);
+  } else {
+    const size_t shm = 2 * (size_t)maxM * sizeof(cf);
+    (void)hipFuncSetAttribute((const void*)k_grid<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)shm);
+    hipLaunchKernelGGL(k_grid<float>, grid, dim3(GRID_NT), shm, st, info, req, w, oms, gbar,
+                       zeta, (const cf*)tw, logtw, Rmax, B, (cf*)qG, (float*)sG, (float*)dL,
+                       part_val, part_idx);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_select(int prec, const InstInfo* info, const int32_t* req, const void* dL,
+                         int Rmax, const double* part_val, const int64_t* part_idx,
+                         double approx_ratio, double slack_rel, int cand_cap, int32_t* cand,
+                         int32_t* ncand, int32_t* overflow, int B, hipStream_t st) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_select<double>, dim3(B), dim3(SEL_NT), 0, st, info, req,
+                       (const double*)dL, Rmax, part_val, part_idx, approx_ratio, slack_rel,
+                       cand_cap, cand, ncand, overflow);
+  else
+    hipLaunchKernelGGL(k_select<float>, dim3(B), dim3(SEL_NT), 0, st, info, req,
+                       (const float*)dL, Rmax, part_val, part_idx, approx_ratio, slack_rel,
+                       cand_cap, cand, ncand, overflow);
+  return hipGetLastError();
+}
+
+}  // namespace sfls

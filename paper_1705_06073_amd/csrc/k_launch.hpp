@@ -1,0 +1,99 @@
+// Host-callable launch wrappers of the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "driver.hpp"
+#include "sfls_kernels.hpp"
+
+namespace sfls {
+
+// Base pointers of every per-instance pool the driver kernel touches.
+struct DrvPools {
+  DrvState* st;
+  double* th;
+  double* ga;
+  double* th_e;
+  double* ga_e;
+  double* g;
+  double* d;
+  double* gt;
+  double* Sm;
+  double* Ym;
+  double* rhom;
+  double* am;
+  int32_t* K_e;
+  int32_t* req;
+  double* beta_e;
+  double* gbar_e;
+  double* zeta_e;
+  const cd* ev_q;
+  const cd* ev_r;
+  const cd* ev_u;
+  const cd* ev_s;
+  const cd* ev_t;
+  const cd* ev_v;
+  const cd* ev_x;
+  const double* logdet;
+  const double* yCy;
+  const double* ww;
+  const int32_t* lev_status;
+  const int32_t* cand;
+  const int32_t* ncand;
+  const cd* cand_q;
+  const double* cand_s;
+  double* cbuf_dl;
+  double* cbuf_gh;
+  int32_t* cbuf_l;
+  int64_t* out_K;
+  double* out_theta;
+  cd* out_alpha;
+  double* out_gamma;
+  double* out_beta;
+  double* out_zeta;
+  double* out_obj;
+  int32_t* out_iters;
+  int32_t* out_evals;
+  int32_t* out_status;
+  const int64_t* out_koff;
+  int32_t* notdone;
+};
+
+hipError_t launch_twiddles(cd* tw64, cf* tw32, int logtw, hipStream_t st);
+hipError_t launch_toeplitz_column(const InstInfo* info, const int32_t* req, const int32_t* Kcnt,
+                                  const double* theta, const double* gamma, const double* beta,
+                                  cd* c, int B, int maxN, hipStream_t st);
+hipError_t launch_levinson(const InstInfo* info, const int32_t* req, const cd* c, cd* rho,
+                           double* delta, double* logdet, int32_t* status, int64_t* failed, int B,
+                           int maxN, hipStream_t st);
+hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void* y, int ydtype,
+                           const cd* rho, const double* delta, const cd* tw, int logtw,
+                           cd* scratch, cd* w, double* yCy, double* ww, int B, int maxP,
+                           hipStream_t st);
+hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
+                        const double* delta, const SepCoef* coef, const cd* tw, int logtw,
+                        cd* scratch, int which, int have_g0, cd* oms, cd* o_s, cd* o_t,
+                        cd* o_v, cd* o_x, int B, int maxP, hipStream_t st);
+hipError_t launch_grid(int prec, const InstInfo* info, const int32_t* req, const cd* w,
+                       const cd* oms, const double* gbar, const double* zeta, const void* tw,
+                       int logtw, int Rmax, int B, int maxM, void* qG, void* sG, void* dL,
+                       double* part_val, int64_t* part_idx, hipStream_t st);
+hipError_t launch_argmin_out(const InstInfo* info, int Rmax, const double* part_val,
+                             const int64_t* part_idx, int64_t* amin, double* aval, int B,
+                             hipStream_t st);
+hipError_t launch_select(int prec, const InstInfo* info, const int32_t* req, const void* dL,
+                         int Rmax, const double* part_val, const int64_t* part_idx,
+                         double approx_ratio, double slack_rel, int cand_cap, int32_t* cand,
+                         int32_t* ncand, int32_t* overflow, int B, hipStream_t st);
+hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t* Keval,
+                         const int32_t* ncand, int32_t* prefix, int B, const double* theta,
+                         const int32_t* cand, const cd* w, const cd* rho, const double* delta,
+                         const SepCoef* coef, cd* oq, cd* orr, cd* ou, cd* os, cd* ot, cd* ov,
+                         cd* ox, cd* cq, double* cs, int nblocks, hipStream_t st);
+hipError_t launch_init_state(const InstInfo* info, const void* y, int ydtype, DrvState* st,
+                             int32_t* req, int B, hipStream_t s);
+hipError_t launch_driver(const InstInfo* info, const DrvParams* prm, DrvPools pools, int B,
+                         hipStream_t st);
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
+
+}  // namespace sfls

@@ -1,0 +1,38 @@
+// Kernel-side data structures and launch wrappers of the superfast-LSE path.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dev_common.hpp"
+
+namespace sfls {
+
+// Per-instance sizes and offsets, prepared on the host for every call.
+struct InstInfo {
+  int32_t N;      // samples
+  int32_t P;      // convolution FFT size, power of two >= 2N-1
+  int32_t logP;
+  int32_t M;      // grid sub-FFT size, power of two >= N
+  int32_t logM;
+  int32_t R;      // L / M residues
+  int32_t L;      // grid size
+  int32_t kcap;   // component capacity
+  int64_t off;    // per-sample arrays (y, c, rho, delta, w)
+  int64_t poff;   // P-length scratch
+  int64_t goff;   // L-length grid arrays
+  int64_t koff;   // component arrays
+  int64_t ooff;   // 2N-1 omega arrays (sfls_omega)
+  int64_t coff;   // candidate arrays
+};
+
+// Request bits of one instance for the current evaluation round.
+enum : int32_t { REQ_EVAL = 1, REQ_GRID = 2, REQ_APPROX = 4 };
+
+// Coefficients of the separable forms of s, t, v, x: for each quantity a 4x4
+// matrix C[a][b] with  Q = delta^{-1} sum_ab C[a][b] G_a conj(G_b),
+// G_a(theta) = sum_q (q-c)^a rho_q e^{-j 2 pi q theta}, c = (N-1)/2.
+struct SepCoef {
+  double c[4][16];  // s, t, v, x
+};
+
+}  // namespace sfls
