@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: estimation solves/sec at N=4096 on one MI355X.
+
+A step is one batch of 256 full solves (sfls_estimate: every evaluation, the
+Levinson factorisation, the grid stage and the device-side driver) of
+synthetic signals with N=4096, K~Poisson(40), minimum separation 1/N,
+alpha~CN(0,1), SNR~U[0,30] dB, grid L=8N=32768, FP64 recursion and FP32 grid
+FFTs.  Inputs are resident in HBM before timing starts.
+
+Also reported: the plain FP64 method launched one instance at a time, p50/p99
+per-instance latency, the roofline position of the dominant kernel (from HIP
+events the library records on its stream), and the CPU oracle timed on a
+bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "estimation solves/sec at N=4096 (batched vs plain FP64); p50/p99 latency"
+FP64_PEAK = 78.6e12   # MI355X dense FP64 vector, FLOP/s
+HBM_PEAK = 8.0e12     # B/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(B):
+    import numpy as np
+    from paper_1705_06073_amd import synth
+    insts = [synth.workload_n4096(i) for i in range(B)]
+    return insts, np
+
+
+def cpu_baseline(insts, per_solve_active, per_solve_grid, L_mult=8.0):
+    """Time the oracle on a bounded sample of the workload: one evaluation with
+    the grid stage and two without, at the first instance's true state, then
+    scale by the evaluations a solve takes (counted on the GPU run)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import numerics as nm
+    from oracle.estimator import OracleEstimator, Params
+
+    inst = insts[0]
+    th, ga, be = inst.theta, np.abs(inst.alpha) ** 2, inst.beta
+    est = OracleEstimator(inst.y, Params(L_mult=L_mult))
+    t0 = time.perf_counter()
+    ev = nm.Evaluation(inst.y, th, ga, be)
+    est._exact_activation_round(ev, th, ga, min(0.5, len(th) / inst.N))  # grid stage
+    t_grid = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    for _ in range(2):
+        nm.Evaluation(inst.y, th, ga, be)
+    t_active = (time.perf_counter() - t1) / 2
+    t_solve = per_solve_grid * t_grid + per_solve_active * t_active
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {
+        "value": 1.0 / t_solve,
+        "unit": "solves/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"dense FP64 oracle on instance 0 (N={inst.N}, K={inst.K}): one grid "
+                   f"evaluation {t_grid:.2f} s, active evaluations {t_active:.2f} s each; "
+                   f"per solve {per_solve_grid:.1f} grid + {per_solve_active:.1f} active "
+                   f"evaluations (mean over the GPU batch) -> {t_solve:.1f} s/solve"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--plain", type=int, default=8,
+                    help="instances for the plain FP64 one-per-launch baseline (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: the estimator's instances are independent, so a "
+              f"multi-GPU run is N copies of this one (got --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1705_06073_amd as sf
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    log(f"generating {args.batch} instances (N=4096)")
+    insts, _ = make_workload(args.batch)
+    B = len(insts)
+    n = np.array([i.N for i in insts], np.int64)
+    off = np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+    kcap = np.full(B, 256, np.int64)
+    koff = np.concatenate([[0], np.cumsum(kcap)[:-1]]).astype(np.int64)
+    yflat = np.concatenate([i.y.astype(np.complex128) for i in insts])
+    y = torch.from_numpy(yflat.view(np.float64).copy()).to(dev)
+    KT = int(kcap.sum())
+    f64 = dict(dtype=torch.float64, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    out = dict(K=torch.zeros(B, dtype=torch.int64, device=dev), theta=torch.zeros(KT, **f64),
+               alpha=torch.zeros(2 * KT, **f64), gamma=torch.zeros(KT, **f64),
+               beta=torch.zeros(B, **f64), zeta=torch.zeros(B, **f64),
+               objective=torch.zeros(B, **f64), iters=torch.zeros(B, **i32),
+               evals=torch.zeros(B, **i32), status=torch.zeros(B, **i32))
+    prec = sf.SFLS_MIXED if args.precision == "mixed" else sf.SFLS_FP64
+    params = sf.default_params(precision=prec)
+    ctx = sf.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def run_batch():
+        sf.sfls_estimate(ctx, n, off, y, sf.SFLS_C128, params, kcap, koff, out["K"],
+                         out["theta"], out["alpha"], out["gamma"], out["beta"], out["zeta"],
+                         out["objective"], out["iters"], out["evals"], out["status"],
+                         stream=stream)
+
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        run_batch()
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup}: {time.perf_counter() - t:.3f} s")
+
+    ctx.reset_stats()
+    ctx.set_timing(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ts = time.perf_counter()
+        run_batch()
+        torch.cuda.synchronize()
+        run, timeline = ctx.last_run()
+        ev = out["evals"].cpu().numpy()
+        lat.extend(timeline[np.clip(ev, 0, len(timeline) - 1)].tolist())
+        log(f"step {s + 1}/{args.steps}: {time.perf_counter() - ts:.3f} s, rounds={run['rounds']}, "
+            f"evals={run['evals']} (grid {run['grid_evals']})")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_timing(False)
+    kst = ctx.kernel_stats()
+    run, _ = ctx.last_run()
+    st = out["status"].cpu().numpy()
+    Kh = out["K"].cpu().numpy()
+    its = out["iters"].cpu().numpy()
+    solves = args.steps * B
+    value = solves / elapsed
+
+    # dominant kernel and its roofline position
+    dom = max(kst.items(), key=lambda kv: kv[1]["seconds"])
+    name, ks = dom
+    if ks["flops"] > 0:
+        achieved = ks["flops"] / ks["seconds"]
+        roof = {"bound": "alu", "kernel": name, "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": None,
+                "avg_launch_ms": 1e3 * ks["seconds"] / max(1, ks["launches"]),
+                "algorithmic_per_launch": ks["flops"] / max(1, ks["launches"])}
+    else:
+        achieved = ks["bytes"] / ks["seconds"]
+        roof = {"bound": "hbm", "kernel": name, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
+                "avg_launch_ms": 1e3 * ks["seconds"] / max(1, ks["launches"]),
+                "algorithmic_per_launch": ks["bytes"] / max(1, ks["launches"])}
+    kernels = {k: {"launches": v["launches"], "ms_total": 1e3 * v["seconds"] / args.steps,
+                   "share": v["seconds"] / max(1e-30, sum(x["seconds"] for x in kst.values()))}
+               for k, v in kst.items()}
+
+    # plain FP64, one instance per launch, no batching
+    plain = None
+    if args.plain > 0:
+        pp = sf.default_params(precision=sf.SFLS_FP64)
+        nb = min(args.plain, B)
+        times = []
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for b in range(nb):
+            tb = time.perf_counter()
+            sf.sfls_estimate(ctx, n[b:b + 1], np.zeros(1, np.int64), y[2 * off[b]:2 * (off[b] + n[b])],
+                             sf.SFLS_C128, pp, kcap[b:b + 1], np.zeros(1, np.int64), out["K"],
+                             out["theta"], out["alpha"], out["gamma"], out["beta"], out["zeta"],
+                             out["objective"], out["iters"], out["evals"], out["status"],
+                             stream=stream)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - tb)
+        tp = time.perf_counter() - tp0
+        plain = {"value": nb / tp, "unit": "solves/s", "instances": nb,
+                 "latency_ms": {"p50": 1e3 * float(np.percentile(times, 50)),
+                                "p99": 1e3 * float(np.percentile(times, 99))}}
+        log(f"plain FP64: {nb} solves in {tp:.2f} s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        g_per = run["grid_evals"] / B
+        a_per = (run["evals"] - run["grid_evals"]) / B
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(insts, a_per, g_per)
+
+    lat = np.array(lat)
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32grid" if prec == sf.SFLS_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": "256 independent instances, N=4096, K~Poisson(40), separation "
+                               "1/N, alpha~CN(0,1), SNR~U[0,30] dB, grid L=8N=32768; FP64 "
+                               "recursion, " + ("FP32" if prec == sf.SFLS_MIXED else "FP64")
+                               + " grid; one batched estimate per step",
+                   "batch": B, "N": 4096, "L": 32768,
+                   "precision": "mixed" if prec == sf.SFLS_MIXED else "fp64"},
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                       "p99": 1e3 * float(np.percentile(lat, 99))},
+        "plain_fp64": plain,
+        "per_solve": {"evals_mean": run["evals"] / B, "grid_evals_mean": run["grid_evals"] / B,
+                      "rounds": run["rounds"], "iters_mean": float(np.mean(its)),
+                      "K_mean": float(np.mean(Kh)),
+                      "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}},
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -214,6 +214,42 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
                           double* objective, int32_t* iters, int32_t* evals, int32_t* status,
                           void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Measurement of sfls_estimate (no effect on results).
+ *
+ * sfls_set_timing(ctx, 1) brackets every kernel launch of the estimate round
+ * loop with HIP events on the call's stream; per kernel the context then
+ * accumulates the launch count, the summed event durations, and the
+ * algorithmic work of those launches (FP64 flops of the Levinson recursion,
+ * 8 N^2 per instance; HBM bytes of the streamed arrays), counted from the
+ * request bits of each round.  sfls_kernel_stats copies up to `cap` entries
+ * and returns the number of kernels tracked; sfls_reset_stats zeroes them.
+ * sfls_last_run returns the round / evaluation counts of the last estimate
+ * and the host wall time at the end of each round (entry r = after round r,
+ * entry 0 = after the initial driver call), so instance b with evals[b] = r
+ * completed at timeline[r].
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    char name[24];
+    int64_t launches;
+    double seconds;
+    double flops;
+    double bytes;
+} sfls_kernel_stat;
+
+typedef struct {
+    int64_t rounds;      /* evaluation rounds */
+    int64_t evals;       /* instance evaluations, summed over rounds */
+    int64_t grid_evals;  /* of which ran the grid stage */
+    double wall_seconds; /* host wall time of the call */
+} sfls_run_stats;
+
+sfls_status sfls_set_timing(sfls_ctx* ctx, int32_t enable);
+void sfls_reset_stats(sfls_ctx* ctx);
+int32_t sfls_kernel_stats(const sfls_ctx* ctx, sfls_kernel_stat* out, int32_t cap);
+sfls_status sfls_last_run(const sfls_ctx* ctx, sfls_run_stats* stats, double* timeline,
+                          int64_t cap, int64_t* ntimeline);
+
 #ifdef __cplusplus
 }
 #endif

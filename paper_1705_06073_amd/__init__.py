@@ -27,7 +27,8 @@ SFLS_MAX_N = 4096
 
 EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror",
            "sfls_last_error", "sfls_version", "sfls_toeplitz_column", "sfls_factor",
-           "sfls_gs_apply", "sfls_omega", "sfls_grid_eval", "sfls_active_eval", "sfls_estimate"]
+           "sfls_gs_apply", "sfls_omega", "sfls_grid_eval", "sfls_active_eval", "sfls_estimate",
+           "sfls_set_timing", "sfls_reset_stats", "sfls_kernel_stats", "sfls_last_run"]
 
 
 class SflsError(RuntimeError):
@@ -50,6 +51,17 @@ class sfls_params(ctypes.Structure):
         ("polish_tol", ctypes.c_double), ("polish_ftol", ctypes.c_double),
         ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
+
+
+class sfls_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
+                ("seconds", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+class sfls_run_stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("evals", ctypes.c_int64),
+                ("grid_evals", ctypes.c_int64), ("wall_seconds", ctypes.c_double)]
 
 
 _lib = None
@@ -96,6 +108,15 @@ def lib() -> ctypes.CDLL:
     L.sfls_estimate.argtypes = [_P, i64, _I64P, _I64P, _P, i32, ctypes.POINTER(sfls_params),
                                 _I64P, _I64P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.sfls_estimate.restype = st
+    L.sfls_set_timing.argtypes = [_P, i32]
+    L.sfls_set_timing.restype = st
+    L.sfls_reset_stats.argtypes = [_P]
+    L.sfls_reset_stats.restype = None
+    L.sfls_kernel_stats.argtypes = [_P, ctypes.POINTER(sfls_kernel_stat), i32]
+    L.sfls_kernel_stats.restype = i32
+    L.sfls_last_run.argtypes = [_P, ctypes.POINTER(sfls_run_stats), ctypes.POINTER(ctypes.c_double),
+                                i64, _I64P]
+    L.sfls_last_run.restype = st
     _lib = L
     return L
 
@@ -155,6 +176,29 @@ class Context:
         if st != SFLS_OK:
             msg = lib().sfls_last_error(self._h).decode() or lib().sfls_strerror(st).decode()
             raise SflsError(st, msg)
+
+    def set_timing(self, enable: bool = True):
+        self.check(lib().sfls_set_timing(self._h, 1 if enable else 0))
+
+    def reset_stats(self):
+        lib().sfls_reset_stats(self._h)
+
+    def kernel_stats(self) -> dict:
+        arr = (sfls_kernel_stat * 32)()
+        n = lib().sfls_kernel_stats(self._h, arr, 32)
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, seconds=arr[i].seconds,
+                                           flops=arr[i].flops, bytes=arr[i].bytes)
+                for i in range(min(n, 32))}
+
+    def last_run(self):
+        st = sfls_run_stats()
+        nt = ctypes.c_int64(0)
+        self.check(lib().sfls_last_run(self._h, ctypes.byref(st), None, 0, ctypes.byref(nt)))
+        buf = (ctypes.c_double * max(1, nt.value))()
+        self.check(lib().sfls_last_run(self._h, ctypes.byref(st), buf, nt.value,
+                                       ctypes.byref(nt)))
+        return dict(rounds=st.rounds, evals=st.evals, grid_evals=st.grid_evals,
+                    wall_seconds=st.wall_seconds), np.array(buf[:nt.value])
 
     def close(self):
         if self._h:

@@ -3,6 +3,7 @@
 // in the kernels of k_*.hip; this file only moves sizes and pointers.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -23,6 +24,11 @@ struct DevBuf {
   size_t n = 0;
 };
 
+enum KernelId { KID_GEN = 0, KID_LEV, KID_APPLY, KID_OMEGA, KID_GRID, KID_SELECT, KID_ACTIVE,
+                KID_DRIVER, KID_COUNT };
+const char* const kKernelNames[KID_COUNT] = {"toeplitz_column", "levinson", "gs_apply", "omega",
+                                             "grid", "select", "active", "driver"};
+
 struct sfls_ctx {
   int device = 0;
   std::string err;
@@ -30,7 +36,13 @@ struct sfls_ctx {
   cf* tw32 = nullptr;
   int logtw = 17;
   std::map<std::string, DevBuf> bufs;
-  int32_t* host_flag = nullptr;  // pinned
+  int32_t* host_req = nullptr;  // pinned copy of the per-instance request bits
+  int64_t host_req_n = 0;
+  bool timing = false;
+  hipEvent_t ev[2 * KID_COUNT] = {};
+  sfls_kernel_stat kst[KID_COUNT] = {};
+  sfls_run_stats last = {};
+  std::vector<double> timeline;
 };
 
 namespace {
@@ -246,8 +258,7 @@ sfls_status sfls_create(sfls_ctx** out, int device) {
   ctx->device = device;
   const size_t nt = (size_t)1 << (ctx->logtw - 1);
   if (hipMalloc(&ctx->tw64, nt * sizeof(cd)) != hipSuccess ||
-      hipMalloc(&ctx->tw32, nt * sizeof(cf)) != hipSuccess ||
-      hipHostMalloc(&ctx->host_flag, sizeof(int32_t)) != hipSuccess) {
+      hipMalloc(&ctx->tw32, nt * sizeof(cf)) != hipSuccess) {
     sfls_destroy(ctx);
     return SFLS_ENOMEM;
   }
@@ -256,7 +267,46 @@ sfls_status sfls_create(sfls_ctx** out, int device) {
     sfls_destroy(ctx);
     return SFLS_EDEVICE;
   }
+  for (int k = 0; k < KID_COUNT; ++k)
+    std::snprintf(ctx->kst[k].name, sizeof ctx->kst[k].name, "%s", kKernelNames[k]);
   *out = ctx;
+  return SFLS_OK;
+}
+
+sfls_status sfls_set_timing(sfls_ctx* ctx, int32_t enable) {
+  if (!ctx) return SFLS_EINVAL;
+  if (enable && !ctx->ev[0]) {
+    for (auto& e : ctx->ev)
+      if (hipEventCreate(&e) != hipSuccess) return fail(ctx, SFLS_EDEVICE, "hipEventCreate failed");
+  }
+  ctx->timing = enable != 0;
+  return SFLS_OK;
+}
+
+void sfls_reset_stats(sfls_ctx* ctx) {
+  if (!ctx) return;
+  for (int k = 0; k < KID_COUNT; ++k) {
+    ctx->kst[k].launches = 0;
+    ctx->kst[k].seconds = 0.0;
+    ctx->kst[k].flops = 0.0;
+    ctx->kst[k].bytes = 0.0;
+  }
+}
+
+int32_t sfls_kernel_stats(const sfls_ctx* ctx, sfls_kernel_stat* out, int32_t cap) {
+  if (!ctx) return 0;
+  const int32_t n = cap < KID_COUNT ? cap : KID_COUNT;
+  for (int32_t k = 0; k < n && out; ++k) out[k] = ctx->kst[k];
+  return KID_COUNT;
+}
+
+sfls_status sfls_last_run(const sfls_ctx* ctx, sfls_run_stats* stats, double* timeline,
+                          int64_t cap, int64_t* ntimeline) {
+  if (!ctx) return SFLS_EINVAL;
+  if (stats) *stats = ctx->last;
+  const int64_t nt = (int64_t)ctx->timeline.size();
+  if (ntimeline) *ntimeline = nt;
+  for (int64_t i = 0; timeline && i < nt && i < cap; ++i) timeline[i] = ctx->timeline[(size_t)i];
   return SFLS_OK;
 }
 
@@ -268,7 +318,9 @@ sfls_status sfls_destroy(sfls_ctx* ctx) {
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (ctx->tw64) (void)hipFree(ctx->tw64);
   if (ctx->tw32) (void)hipFree(ctx->tw32);
-  if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
+  if (ctx->host_req) (void)hipHostFree(ctx->host_req);
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
   return SFLS_OK;
 }
@@ -624,35 +676,120 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   const double slack = prec == SFLS_FP64 ? 1e-9 : 1e-3;
   const int act_blocks = 2048;
 
+  // pinned host copy of the request bits, read back after every driver call
+  if (ctx->host_req_n < B) {
+    if (ctx->host_req) (void)hipHostFree(ctx->host_req);
+    ctx->host_req = nullptr;
+    ctx->host_req_n = 0;
+    if (hipHostMalloc(&ctx->host_req, (size_t)B * sizeof(int32_t)) != hipSuccess)
+      return fail(ctx, SFLS_ENOMEM, "pinned request buffer");
+    ctx->host_req_n = B;
+  }
+  int32_t* hreq = ctx->host_req;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto now_s = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  ctx->timeline.clear();
+  ctx->last = sfls_run_stats{};
+  const bool timing = ctx->timing;
+  bool launched[KID_COUNT];
+  double kflops[KID_COUNT], kbytes[KID_COUNT];
+  auto tstart = [&](int k) -> hipError_t {
+    launched[k] = true;
+    return timing ? hipEventRecord(ctx->ev[2 * k], st) : hipSuccess;
+  };
+  auto tstop = [&](int k) -> hipError_t {
+    return timing ? hipEventRecord(ctx->ev[2 * k + 1], st) : hipSuccess;
+  };
+
   HIP_TRY(launch_init_state(dinfo, y, ydtype, dst, P.req, (int)B, st));
   HIP_TRY(launch_zero_i32(notdone, 1, st));
   HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
-  HIP_TRY(hipMemcpyAsync(ctx->host_flag, notdone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hreq, P.req, (size_t)B * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  int64_t rounds = 0;
+  ctx->timeline.push_back(now_s());
+  int64_t rounds = 0, ev_total = 0, gevals = 0;
   const int64_t max_rounds = 1000000;
-  while (*ctx->host_flag > 0 && rounds < max_rounds) {
+  const double esz_d = (double)esz;
+  for (;;) {
+    int64_t nact = 0, ngrid = 0;
+    for (int k = 0; k < KID_COUNT; ++k) { launched[k] = false; kflops[k] = 0.0; kbytes[k] = 0.0; }
+    for (int64_t b = 0; b < B; ++b) {
+      const int32_t rq = hreq[b];
+      if (!(rq & REQ_EVAL)) continue;
+      const double N = (double)n[b];
+      ++nact;
+      // algorithmic work per evaluation (per-instance figures of the design)
+      kflops[KID_LEV] += 8.0 * N * N;
+      kbytes[KID_LEV] += 40.0 * N;                       // c in, rho and delta out
+      kbytes[KID_APPLY] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * N + 32.0 * N;  // y, rho in; w out
+      if (rq & REQ_GRID) {
+        ++ngrid;
+        const double Lb = (double)info[(size_t)b].L;
+        kbytes[KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz_d * Lb;  // w, omega_s in; Delta L out
+      }
+    }
+    if (nact == 0) break;
+    if (rounds >= max_rounds) return fail(ctx, SFLS_EDEVICE, "estimate did not finish");
     ++rounds;
+    ev_total += nact;
+    gevals += ngrid;
+    HIP_TRY(tstart(KID_GEN));
     HIP_TRY(launch_toeplitz_column(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, c, (int)B,
                                    sz.maxN, st));
+    HIP_TRY(tstop(KID_GEN));
+    HIP_TRY(tstart(KID_LEV));
     HIP_TRY(launch_levinson(dinfo, P.req, c, rho, delta, logdet, lev_status, failed, (int)B,
                             sz.maxN, st));
+    HIP_TRY(tstop(KID_LEV));
+    HIP_TRY(tstart(KID_APPLY));
     HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw, scratch,
                             w, yCy, ww, (int)B, sz.maxP, st));
-    HIP_TRY(launch_omega(dinfo, P.req, rho, delta, dcoef, ctx->tw64, ctx->logtw, scratch, 1, 1,
-                         oms, nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st));
-    HIP_TRY(launch_grid(prec, dinfo, P.req, w, oms, P.gbar_e, P.zeta_e, tw, ctx->logtw, sz.Rmax,
-                        (int)B, sz.maxM, nullptr, nullptr, dL, pv, pi, st));
-    HIP_TRY(launch_select(prec, dinfo, P.req, dL, sz.Rmax, pv, pi, p.approx_ratio, slack,
-                          p.cand_cap, cand, ncand, ovf, (int)B, st));
-    HIP_TRY(launch_active(dinfo, P.req, P.K_e, ncand, prefix, (int)B, P.th_e, cand, w, rho, delta,
-                          dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks, st));
-    HIP_TRY(launch_zero_i32(notdone, 1, st));
+    HIP_TRY(tstop(KID_APPLY));
+    if (ngrid > 0) {
+      HIP_TRY(tstart(KID_OMEGA));
+      HIP_TRY(launch_omega(dinfo, P.req, rho, delta, dcoef, ctx->tw64, ctx->logtw, scratch, 1, 1,
+                           oms, nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st));
+      HIP_TRY(tstop(KID_OMEGA));
+      HIP_TRY(tstart(KID_GRID));
+      HIP_TRY(launch_grid(prec, dinfo, P.req, w, oms, P.gbar_e, P.zeta_e, tw, ctx->logtw,
+                          sz.Rmax, (int)B, sz.maxM, nullptr, nullptr, dL, pv, pi, st));
+      HIP_TRY(tstop(KID_GRID));
+      HIP_TRY(tstart(KID_SELECT));
+      HIP_TRY(launch_select(prec, dinfo, P.req, dL, sz.Rmax, pv, pi, p.approx_ratio, slack,
+                            p.cand_cap, cand, ncand, ovf, (int)B, st));
+      HIP_TRY(tstop(KID_SELECT));
+    }
+    HIP_TRY(tstart(KID_ACTIVE));
+    HIP_TRY(launch_active(dinfo, P.req, P.K_e, ngrid > 0 ? ncand : nullptr, prefix, (int)B,
+                          P.th_e, cand, w, rho, delta, dcoef, evq, evr, evu, evs, evt, evv, evx,
+                          cq, cs, act_blocks, st));
+    HIP_TRY(tstop(KID_ACTIVE));
+    HIP_TRY(tstart(KID_DRIVER));
     HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
-    HIP_TRY(hipMemcpyAsync(ctx->host_flag, notdone, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(tstop(KID_DRIVER));
+    HIP_TRY(hipMemcpyAsync(hreq, P.req, (size_t)B * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    ctx->timeline.push_back(now_s());
+    if (timing) {
+      for (int k = 0; k < KID_COUNT; ++k) {
+        if (!launched[k]) continue;
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[2 * k], ctx->ev[2 * k + 1]));
+        ctx->kst[k].launches += 1;
+        ctx->kst[k].seconds += 1e-3 * (double)ms;
+        ctx->kst[k].flops += kflops[k];
+        ctx->kst[k].bytes += kbytes[k];
+      }
+    }
   }
-  if (rounds >= max_rounds) return fail(ctx, SFLS_EDEVICE, "estimate did not finish");
+  ctx->last.rounds = rounds;
+  ctx->last.evals = ev_total;
+  ctx->last.grid_evals = gevals;
+  ctx->last.wall_seconds = now_s();
+  (void)notdone;
+
   return SFLS_OK;
 }
 
