@@ -87,6 +87,8 @@ def main():
                     help="instances for the plain FP64 one-per-launch baseline (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--factor", choices=["auto", "levinson", "schur"], default="auto",
+                    help="generator recursion (auto: superfast Schur from N=256 on)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -121,6 +123,8 @@ def main():
     prec = sf.SFLS_MIXED if args.precision == "mixed" else sf.SFLS_FP64
     params = sf.default_params(precision=prec)
     ctx = sf.Context(0)
+    ctx.set_factor({"auto": sf.SFLS_FACTOR_AUTO, "levinson": sf.SFLS_FACTOR_LEVINSON,
+                    "schur": sf.SFLS_FACTOR_SCHUR}[args.factor])
     stream = torch.cuda.current_stream()
 
     def run_batch():
@@ -228,7 +232,8 @@ def main():
                                "recursion, " + ("FP32" if prec == sf.SFLS_MIXED else "FP64")
                                + " grid; one batched estimate per step",
                    "batch": B, "N": 4096, "L": 32768,
-                   "precision": "mixed" if prec == sf.SFLS_MIXED else "fp64"},
+                   "precision": "mixed" if prec == sf.SFLS_MIXED else "fp64",
+                   "factor": args.factor},
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                        "p99": 1e3 * float(np.percentile(lat, 99))},
         "plain_fp64": plain,

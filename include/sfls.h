@@ -118,7 +118,8 @@ sfls_status sfls_toeplitz_column(sfls_ctx* ctx, int64_t B, const int64_t* n, con
  * Toeplitz matrix C with first column c (Sec. III, eq. gohberg-semencul):
  *     C^{-1} = delta_{N-1}^{-1} (T1^H T1 - T0 T0^H),
  *     [T0]_{ik} = rho_{i-k-1}, [T1]_{ik} = rho_{N-1+i-k}, rho_{N-1} = 1,
- * computed by the Levinson-Durbin recursion (Sec. III, the O(N^2) option).
+ * computed by the Levinson-Durbin recursion or the superfast Schur recursion
+ * (sfls_set_factor).
  *   c      device c128 [sum n]   first columns; c_0 must be real and > 0
  *   rho    device c128 [sum n]   out: generator rho_0..rho_{N-1}
  *   delta  device f64  [sum n]   out: pivots delta_0..delta_{N-1} of C = L diag(delta) L^H
@@ -130,6 +131,18 @@ sfls_status sfls_toeplitz_column(sfls_ctx* ctx, int64_t B, const int64_t* n, con
 sfls_status sfls_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
                         const double* c, double* rho, double* delta, double* logdet,
                         int32_t* status, int64_t* failed_step, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * a3. Choice of the factorisation used by sfls_factor and sfls_estimate.  Both
+ * produce the same generator (rho, delta) of eq. gohberg-semencul:
+ *   SFLS_FACTOR_LEVINSON  Levinson-Durbin, O(N^2) (Sec. III);
+ *   SFLS_FACTOR_SCHUR     superfast doubling Schur recursion, O(N log^2 N)
+ *                         (the generalized Schur route of Sec. III): a 2x2
+ *                         polynomial-matrix recursion with FFT products;
+ *   SFLS_FACTOR_AUTO      Schur for batches whose largest N >= 256 (default).
+ * ------------------------------------------------------------------------- */
+typedef enum { SFLS_FACTOR_AUTO = 0, SFLS_FACTOR_LEVINSON = 1, SFLS_FACTOR_SCHUR = 2 } sfls_factor_algo;
+sfls_status sfls_set_factor(sfls_ctx* ctx, int32_t algo);
 
 /* ---------------------------------------------------------------------------
  * a4. w = C^{-1} y from the generator by four triangular-Toeplitz products

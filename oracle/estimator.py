@@ -235,7 +235,12 @@ class OracleEstimator:
         else:
             alpha = min(1.0, amax)
         slack = p.polish_ftol * (1.0 + abs(f0)) if polish else 0.0
-        for _ in range(p.ls_max):
+        dth_max = float(np.max(np.abs(dth))) if K else 0.0
+        for trial in range(p.ls_max):
+            # the polish gives up once a shortened step could no longer move any
+            # frequency by the polish tolerance (it would stop after it anyway)
+            if polish and trial > 0 and alpha * dth_max < p.polish_tol / self.N:
+                return None
             th_t = np.mod(theta + alpha * dth, 1.0)
             ga_t = np.maximum(gamma + alpha * dga, 0.0)
             if (not polish) and alpha == amax and kstar >= 0:

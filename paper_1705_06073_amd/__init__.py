@@ -28,7 +28,9 @@ SFLS_MAX_N = 4096
 EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror",
            "sfls_last_error", "sfls_version", "sfls_toeplitz_column", "sfls_factor",
            "sfls_gs_apply", "sfls_omega", "sfls_grid_eval", "sfls_active_eval", "sfls_estimate",
-           "sfls_set_timing", "sfls_reset_stats", "sfls_kernel_stats", "sfls_last_run"]
+           "sfls_set_timing", "sfls_reset_stats", "sfls_kernel_stats", "sfls_last_run",
+           "sfls_set_factor"]
+SFLS_FACTOR_AUTO, SFLS_FACTOR_LEVINSON, SFLS_FACTOR_SCHUR = 0, 1, 2
 
 
 class SflsError(RuntimeError):
@@ -108,6 +110,8 @@ def lib() -> ctypes.CDLL:
     L.sfls_estimate.argtypes = [_P, i64, _I64P, _I64P, _P, i32, ctypes.POINTER(sfls_params),
                                 _I64P, _I64P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.sfls_estimate.restype = st
+    L.sfls_set_factor.argtypes = [_P, i32]
+    L.sfls_set_factor.restype = st
     L.sfls_set_timing.argtypes = [_P, i32]
     L.sfls_set_timing.restype = st
     L.sfls_reset_stats.argtypes = [_P]
@@ -176,6 +180,9 @@ class Context:
         if st != SFLS_OK:
             msg = lib().sfls_last_error(self._h).decode() or lib().sfls_strerror(st).decode()
             raise SflsError(st, msg)
+
+    def set_factor(self, algo: int):
+        self.check(lib().sfls_set_factor(self._h, int(algo)))
 
     def set_timing(self, enable: bool = True):
         self.check(lib().sfls_set_timing(self._h, 1 if enable else 0))

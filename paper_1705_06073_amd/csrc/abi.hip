@@ -34,11 +34,14 @@ struct sfls_ctx {
   std::string err;
   cd* tw64 = nullptr;
   cf* tw32 = nullptr;
+  cd* tws64 = nullptr;  // stage-major FFT twiddles
+  cf* tws32 = nullptr;
   int logtw = 17;
   std::map<std::string, DevBuf> bufs;
   int32_t* host_req = nullptr;  // pinned copy of the per-instance request bits
   int64_t host_req_n = 0;
   bool timing = false;
+  int32_t factor_algo = 0;  // sfls_factor_algo
   hipEvent_t ev[2 * KID_COUNT] = {};
   sfls_kernel_stat kst[KID_COUNT] = {};
   sfls_run_stats last = {};
@@ -200,7 +203,124 @@ std::vector<InstInfo> base_info(int64_t B, const int64_t* n, const int64_t* off,
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// ----------------------------------------------------------------------------
+// Superfast Schur plans: the recursion of each N flattened into actions.
+// ----------------------------------------------------------------------------
+constexpr int kSchurMinN = 256;  // AUTO: superfast Schur from this N on
+
+struct SchurPlan {
+  std::vector<SchurAct> acts;
+  int32_t mmax[SCH_MAXL] = {};
+  int32_t fspec[SCH_MAXL] = {};
+  int nlev = 0;
+};
+
+void schur_rec(SchurPlan& P, int n0, int m, int level, int side, int win, int Nroot) {
+  const bool root = level == 0;
+  P.nlev = std::max(P.nlev, level + 1);
+  P.mmax[level] = std::max(P.mmax[level], m);
+  if (m <= 64 && !(root && m > 63)) {
+    P.acts.push_back(SchurAct{root ? SCH_ROOT_LEAF : SCH_LEAF_ACT, n0, m, 0, level, side, win, 0});
+    return;
+  }
+  const int m1 = m / 2, m2 = m - m1;
+  const int logF = ilog2_ceil(root ? Nroot : m);
+  P.fspec[level] = std::max(P.fspec[level], 1 << logF);
+  schur_rec(P, n0, m1, level + 1, 0, win, Nroot);
+  P.acts.push_back(SchurAct{SCH_MID, n0, m, m1, level, side, win, logF});
+  schur_rec(P, n0 + m1, m2, level + 1, 1, level + 1, Nroot);
+  P.acts.push_back(SchurAct{root ? SCH_ROOT : SCH_POST, n0, m, m1, level, side, win, logF});
+}
+
+// Build per-instance layouts and the action pool for a batch; returns the
+// scratch size (complex elements) and the largest FFT size.
+void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
+                 std::vector<SchurAct>& pool, int64_t& scr_total, int& Fmax) {
+  std::map<int64_t, std::pair<int64_t, SchurPlan>> byN;  // N -> (act offset, plan)
+  lay.assign((size_t)B, SchurLayout{});
+  pool.clear();
+  scr_total = 0;
+  Fmax = 2;
+  for (int64_t b = 0; b < B; ++b) {
+    const int64_t N = n[b];
+    auto it = byN.find(N);
+    if (it == byN.end()) {
+      SchurPlan P;
+      if (N > 1) schur_rec(P, 0, (int)N - 1, 0, 0, -1, (int)N);
+      const int64_t aoff = (int64_t)pool.size();
+      pool.insert(pool.end(), P.acts.begin(), P.acts.end());
+      it = byN.emplace(N, std::make_pair(aoff, P)).first;
+    }
+    const SchurPlan& P = it->second.second;
+    SchurLayout& L = lay[(size_t)b];
+    std::memset(&L, 0, sizeof L);
+    L.act_off = it->second.first;
+    L.nact = (int32_t)P.acts.size();
+    L.scr_off = scr_total;
+    int64_t o = 0;
+    int fm = 2;
+    for (int l = 0; l < P.nlev; ++l) {
+      L.mmax[l] = P.mmax[l];
+      L.win[l] = o;
+      o += 2 * (int64_t)P.mmax[l];
+      L.res[l] = o;
+      o += 8 * (int64_t)P.mmax[l];
+      L.spec[l] = o;
+      o += 4 * (int64_t)P.fspec[l];
+      fm = std::max(fm, P.fspec[l]);
+    }
+    L.Fmax = fm;
+    Fmax = std::max(Fmax, fm);
+    scr_total += o;
+  }
+  for (auto& L : lay) L.Fmax = Fmax;
+}
+
 }  // namespace
+
+// Factor a batch (Levinson or superfast Schur by the context's choice).
+static sfls_status run_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const InstInfo* dinfo,
+                              const int32_t* req, const cd* c, cd* rho, double* delta,
+                              double* logdet, int32_t* status, int64_t* failed, int maxN,
+                              hipStream_t st, const SchurLayout* dlay, const SchurAct* dacts,
+                              cd* sscr, int Fmax) {
+  if (dlay) {
+    HIP_TRY(launch_schur(dinfo, req, dlay, dacts, c, ctx->tw64, ctx->logtw, ctx->tws64, sscr, rho,
+                         delta,
+                         logdet, status, failed, (int)B, Fmax, st));
+  } else {
+    HIP_TRY(launch_levinson(dinfo, req, c, rho, delta, logdet, status, failed, (int)B, maxN, st));
+  }
+  return SFLS_OK;
+}
+
+static bool use_schur(const sfls_ctx* ctx, int maxN) {
+  if (ctx->factor_algo == SFLS_FACTOR_SCHUR) return maxN > 1;
+  if (ctx->factor_algo == SFLS_FACTOR_LEVINSON) return false;
+  return maxN >= kSchurMinN;
+}
+
+// Upload the Schur plans of a batch when the context uses that path.
+static sfls_status prepare_schur(sfls_ctx* ctx, int64_t B, const int64_t* n, int maxN,
+                                 hipStream_t st, const char* tag, SchurLayout** dlay,
+                                 SchurAct** dacts, cd** sscr, int* Fmax) {
+  *dlay = nullptr;
+  *dacts = nullptr;
+  *sscr = nullptr;
+  *Fmax = 0;
+  if (!use_schur(ctx, maxN)) return SFLS_OK;
+  std::vector<SchurLayout> lay;
+  std::vector<SchurAct> pool;
+  int64_t tot = 0;
+  schur_plans(B, n, lay, pool, tot, *Fmax);
+  if (pool.empty()) pool.push_back(SchurAct{});
+  sfls_status s;
+  std::string a = std::string(tag) + "_slay", b = std::string(tag) + "_sact";
+  if ((s = upload(ctx, a.c_str(), lay, st, dlay)) != SFLS_OK) return s;
+  if ((s = upload(ctx, b.c_str(), pool, st, dacts)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "schur_scr", (size_t)std::max<int64_t>(tot, 1), sscr)) != SFLS_OK) return s;
+  return SFLS_OK;
+}
 
 extern "C" {
 
@@ -258,11 +378,14 @@ sfls_status sfls_create(sfls_ctx** out, int device) {
   ctx->device = device;
   const size_t nt = (size_t)1 << (ctx->logtw - 1);
   if (hipMalloc(&ctx->tw64, nt * sizeof(cd)) != hipSuccess ||
-      hipMalloc(&ctx->tw32, nt * sizeof(cf)) != hipSuccess) {
+      hipMalloc(&ctx->tw32, nt * sizeof(cf)) != hipSuccess ||
+      hipMalloc(&ctx->tws64, 2 * nt * sizeof(cd)) != hipSuccess ||
+      hipMalloc(&ctx->tws32, 2 * nt * sizeof(cf)) != hipSuccess) {
     sfls_destroy(ctx);
     return SFLS_ENOMEM;
   }
-  if (launch_twiddles(ctx->tw64, ctx->tw32, ctx->logtw, nullptr) != hipSuccess ||
+  if (launch_twiddles(ctx->tw64, ctx->tw32, ctx->tws64, ctx->tws32, ctx->logtw, nullptr) !=
+          hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     sfls_destroy(ctx);
     return SFLS_EDEVICE;
@@ -270,6 +393,14 @@ sfls_status sfls_create(sfls_ctx** out, int device) {
   for (int k = 0; k < KID_COUNT; ++k)
     std::snprintf(ctx->kst[k].name, sizeof ctx->kst[k].name, "%s", kKernelNames[k]);
   *out = ctx;
+  return SFLS_OK;
+}
+
+sfls_status sfls_set_factor(sfls_ctx* ctx, int32_t algo) {
+  if (!ctx) return SFLS_EINVAL;
+  if (algo != SFLS_FACTOR_AUTO && algo != SFLS_FACTOR_LEVINSON && algo != SFLS_FACTOR_SCHUR)
+    return fail(ctx, SFLS_EINVAL, "unknown factorisation %d", algo);
+  ctx->factor_algo = algo;
   return SFLS_OK;
 }
 
@@ -318,6 +449,8 @@ sfls_status sfls_destroy(sfls_ctx* ctx) {
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (ctx->tw64) (void)hipFree(ctx->tw64);
   if (ctx->tw32) (void)hipFree(ctx->tw32);
+  if (ctx->tws64) (void)hipFree(ctx->tws64);
+  if (ctx->tws32) (void)hipFree(ctx->tws32);
   if (ctx->host_req) (void)hipHostFree(ctx->host_req);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
@@ -369,9 +502,14 @@ sfls_status sfls_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_
   std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
   InstInfo* dinfo;
   if ((s = upload(ctx, "f_info", info, st, &dinfo)) != SFLS_OK) return s;
-  HIP_TRY(launch_levinson(dinfo, nullptr, (const cd*)c, (cd*)rho, delta, logdet, status,
-                          failed_step, (int)B, sz.maxN, st));
-  return SFLS_OK;
+  SchurLayout* dlay;
+  SchurAct* dacts;
+  cd* sscr;
+  int Fmax;
+  if ((s = prepare_schur(ctx, B, n, sz.maxN, st, "f", &dlay, &dacts, &sscr, &Fmax)) != SFLS_OK)
+    return s;
+  return run_factor(ctx, B, n, dinfo, nullptr, (const cd*)c, (cd*)rho, delta, logdet, status,
+                    failed_step, sz.maxN, st, dlay, dacts, sscr, Fmax);
 }
 
 sfls_status sfls_gs_apply(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
@@ -393,7 +531,7 @@ sfls_status sfls_gs_apply(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   if ((s = upload(ctx, "a_info", info, st, &dinfo)) != SFLS_OK) return s;
   if ((s = wsT(ctx, "scratch", (size_t)pt, &scratch)) != SFLS_OK) return s;
   HIP_TRY(launch_gs_apply(dinfo, nullptr, y, ydtype, (const cd*)rho, delta, ctx->tw64,
-                          ctx->logtw, scratch, (cd*)w, yCy, ww, (int)B, sz.maxP, st));
+                          ctx->logtw, ctx->tws64, scratch, (cd*)w, yCy, ww, (int)B, sz.maxP, st));
   return SFLS_OK;
 }
 
@@ -425,7 +563,7 @@ sfls_status sfls_omega(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t
   if ((s = upload(ctx, "o_info", info, st, &dinfo)) != SFLS_OK) return s;
   if ((s = upload(ctx, "o_coef", coef, st, &dcoef)) != SFLS_OK) return s;
   if ((s = wsT(ctx, "scratch", (size_t)pt, &scratch)) != SFLS_OK) return s;
-  HIP_TRY(launch_omega(dinfo, nullptr, (const cd*)rho, delta, dcoef, ctx->tw64, ctx->logtw,
+  HIP_TRY(launch_omega(dinfo, nullptr, (const cd*)rho, delta, dcoef, ctx->tws64,
                        scratch, which, 0, nullptr, (cd*)omega_s, (cd*)omega_t, (cd*)omega_v,
                        (cd*)omega_x, (int)B, sz.maxP, st));
   return SFLS_OK;
@@ -479,10 +617,10 @@ sfls_status sfls_grid_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int
   if ((s = wsT(ctx, "g_pi", (size_t)B * sz.Rmax, &pi)) != SFLS_OK) return s;
   if ((s = wsT(ctx, "g_yCy", (size_t)B, &yCy)) != SFLS_OK) return s;
   HIP_TRY(launch_gs_apply(dinfo, dreq, y, ydtype, (const cd*)rho, delta, ctx->tw64, ctx->logtw,
-                          scratch, w, yCy, nullptr, (int)B, sz.maxP, st));
-  HIP_TRY(launch_omega(dinfo, dreq, (const cd*)rho, delta, dcoef, ctx->tw64, ctx->logtw, scratch,
+                          ctx->tws64, scratch, w, yCy, nullptr, (int)B, sz.maxP, st));
+  HIP_TRY(launch_omega(dinfo, dreq, (const cd*)rho, delta, dcoef, ctx->tws64, scratch,
                        1, 1, oms, nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st));
-  const void* tw = precision == SFLS_FP64 ? (const void*)ctx->tw64 : (const void*)ctx->tw32;
+  const void* tw = precision == SFLS_FP64 ? (const void*)ctx->tws64 : (const void*)ctx->tws32;
   HIP_TRY(launch_grid(precision, dinfo, dreq, w, oms, gamma_bar, zeta, tw, ctx->logtw, sz.Rmax,
                       (int)B, sz.maxM, qG, sG, dL, pv, pi, st));
   if (argmin || argmin_val)
@@ -671,8 +809,14 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   P.out_beta = beta; P.out_zeta = zeta; P.out_obj = objective; P.out_iters = iters;
   P.out_evals = evals; P.out_status = status; P.out_koff = dokoff; P.notdone = notdone;
 
+  SchurLayout* slay;
+  SchurAct* sacts;
+  cd* sscr;
+  int sFmax;
+  if ((s = prepare_schur(ctx, B, n, sz.maxN, st, "e", &slay, &sacts, &sscr, &sFmax)) != SFLS_OK)
+    return s;
   const int prec = p.precision;
-  const void* tw = prec == SFLS_FP64 ? (const void*)ctx->tw64 : (const void*)ctx->tw32;
+  const void* tw = prec == SFLS_FP64 ? (const void*)ctx->tws64 : (const void*)ctx->tws32;
   const double slack = prec == SFLS_FP64 ? 1e-9 : 1e-3;
   const int act_blocks = 2048;
 
@@ -740,16 +884,17 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
                                    sz.maxN, st));
     HIP_TRY(tstop(KID_GEN));
     HIP_TRY(tstart(KID_LEV));
-    HIP_TRY(launch_levinson(dinfo, P.req, c, rho, delta, logdet, lev_status, failed, (int)B,
-                            sz.maxN, st));
+    if ((s = run_factor(ctx, B, n, dinfo, P.req, c, rho, delta, logdet, lev_status, failed,
+                        sz.maxN, st, slay, sacts, sscr, sFmax)) != SFLS_OK)
+      return s;
     HIP_TRY(tstop(KID_LEV));
     HIP_TRY(tstart(KID_APPLY));
-    HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw, scratch,
-                            w, yCy, ww, (int)B, sz.maxP, st));
+    HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw,
+                            ctx->tws64, scratch, w, yCy, ww, (int)B, sz.maxP, st));
     HIP_TRY(tstop(KID_APPLY));
     if (ngrid > 0) {
       HIP_TRY(tstart(KID_OMEGA));
-      HIP_TRY(launch_omega(dinfo, P.req, rho, delta, dcoef, ctx->tw64, ctx->logtw, scratch, 1, 1,
+      HIP_TRY(launch_omega(dinfo, P.req, rho, delta, dcoef, ctx->tws64, scratch, 1, 1,
                            oms, nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st));
       HIP_TRY(tstop(KID_OMEGA));
       HIP_TRY(tstart(KID_GRID));

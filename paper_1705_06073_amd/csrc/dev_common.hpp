@@ -138,21 +138,21 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
 // In-LDS radix-2 FFT of n = 2^logn points with NT threads.
 //   dif_fft: natural order in -> bit-reversed order out, kernel exp(sgn j 2pi kn/n)
 //   dit_fft: bit-reversed in -> natural order out, kernel exp(sgn j 2pi kn/n)
-// Twiddles come from a table tw[k] = exp(-j 2 pi k / TW_N), k < TW_N/2, with
-// n <= TW_N.  No scaling.  Both end with a barrier.
+// Twiddles come from the stage-major table tws[h + pos] = exp(-j 2 pi pos / 2h)
+// (h a power of two, pos < h), so the twiddles of one stage are contiguous.
+// No scaling.  Both end with a barrier.
 // ---------------------------------------------------------------------------
 template <typename C, int NT>
-__device__ void dif_fft(C* x, int logn, int sgn, const C* __restrict__ tw, int logtw) {
+__device__ void dif_fft(C* x, int logn, int sgn, const C* __restrict__ tws) {
   const int n = 1 << logn;
   for (int lh = logn - 1; lh >= 0; --lh) {
     const int h = 1 << lh;
-    const int tshift = logtw - lh - 1;  // W_{2h}^pos = tw[pos << tshift]
     for (int b = threadIdx.x; b < (n >> 1); b += NT) {
       const int pos = b & (h - 1);
       const int i = ((b >> lh) << (lh + 1)) + pos;
       const int j = i + h;
       C u = x[i], v = x[j];
-      C w = tw[pos << tshift];
+      C w = tws[h + pos];
       if (sgn > 0) w.y = -w.y;
       x[i] = cadd(u, v);
       x[j] = cmul(csub(u, v), w);
@@ -162,16 +162,15 @@ __device__ void dif_fft(C* x, int logn, int sgn, const C* __restrict__ tw, int l
 }
 
 template <typename C, int NT>
-__device__ void dit_fft(C* x, int logn, int sgn, const C* __restrict__ tw, int logtw) {
+__device__ void dit_fft(C* x, int logn, int sgn, const C* __restrict__ tws) {
   const int n = 1 << logn;
   for (int lh = 0; lh < logn; ++lh) {
     const int h = 1 << lh;
-    const int tshift = logtw - lh - 1;
     for (int b = threadIdx.x; b < (n >> 1); b += NT) {
       const int pos = b & (h - 1);
       const int i = ((b >> lh) << (lh + 1)) + pos;
       const int j = i + h;
-      C w = tw[pos << tshift];
+      C w = tws[h + pos];
       if (sgn > 0) w.y = -w.y;
       C u = x[i], v = cmul(x[j], w);
       x[i] = cadd(u, v);

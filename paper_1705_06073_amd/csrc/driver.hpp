@@ -608,7 +608,15 @@ struct Driver {
           }
           S.alpha *= 0.5;
           S.ls_trial += 1;
-          if (S.ls_trial >= P.ls_max) {
+          bool give_up = S.ls_trial >= P.ls_max;
+          if (S.polish && !give_up) {
+            // the polish stops once the shortened step moves no frequency by
+            // the polish tolerance
+            double dmax = 0.0;
+            for (int k = 0; k < S.K; ++k) dmax = fmax(dmax, fabs(A.d[k]));
+            give_up = S.alpha * dmax < P.polish_tol / (double)N;
+          }
+          if (give_up) {
             // line search failed: current point unchanged (needs re-evaluation)
             if (S.polish) { lbl = L_FINAL; break; }
             lbl = L_TERM_BEGIN;

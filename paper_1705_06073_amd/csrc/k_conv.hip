@@ -46,6 +46,7 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
                                                       const cd* __restrict__ rho,
                                                       const double* __restrict__ delta,
                                                       const cd* __restrict__ tw, int logtw,
+                                                      const cd* __restrict__ tws,
                                                       cd* __restrict__ scratch, cd* __restrict__ w,
                                                       double* __restrict__ yCy,
                                                       double* __restrict__ ww) {
@@ -67,12 +68,12 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
   // (1) A = FFT(rho)
   for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? rb[t] : cd{0.0, 0.0};
   __syncthreads();
-  dif_fft<cd, CONV_NT>(lds, logP, -1, tw, logtw);
+  dif_fft<cd, CONV_NT>(lds, logP, -1, tws);
   for (int t = tid; t < P; t += CONV_NT) A[t] = lds[t];
   // (2) Y = FFT(y^)
   for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? load_y(yb, N - 1 - t) : cd{0.0, 0.0};
   __syncthreads();
-  dif_fft<cd, CONV_NT>(lds, logP, -1, tw, logtw);
+  dif_fft<cd, CONV_NT>(lds, logP, -1, tws);
   for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[t];
   __syncthreads();
   // (3) u1 from FFT(rho~) . Y
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
     lds[p] = cmul(cmul(tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), A[pm]), Y[p]);
   }
   __syncthreads();
-  dit_fft<cd, CONV_NT>(lds, logP, +1, tw, logtw);
+  dit_fft<cd, CONV_NT>(lds, logP, +1, tws);
   for (int i = tid; i < N; i += CONV_NT) X1[i] = cscale(lds[N - 1 - i], invP);
   __syncthreads();
   // (4) v1 from conj(A(-f)) . Y
@@ -92,20 +93,20 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
     lds[p] = cmul(cconj(A[pm]), Y[p]);
   }
   __syncthreads();
-  dit_fft<cd, CONV_NT>(lds, logP, +1, tw, logtw);
+  dit_fft<cd, CONV_NT>(lds, logP, +1, tws);
   for (int i = tid; i < N; i += CONV_NT)
     X2[i] = (i <= N - 2) ? cscale(lds[N - 2 - i], invP) : cd{0.0, 0.0};
   __syncthreads();
   // (5) U = FFT(u1) -> Y
   for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? X1[t] : cd{0.0, 0.0};
   __syncthreads();
-  dif_fft<cd, CONV_NT>(lds, logP, -1, tw, logtw);
+  dif_fft<cd, CONV_NT>(lds, logP, -1, tws);
   for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[t];
   __syncthreads();
   // (6) V = FFT(v1), kept in LDS
   for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? X2[t] : cd{0.0, 0.0};
   __syncthreads();
-  dif_fft<cd, CONV_NT>(lds, logP, -1, tw, logtw);
+  dif_fft<cd, CONV_NT>(lds, logP, -1, tws);
   // (7) W = FFT(conj rho~) U - W^f A V
   for (int p = tid; p < P; p += CONV_NT) {
     const int f = bitrev(p, logP);
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
     lds[p] = csub(t1, t2);
   }
   __syncthreads();
-  dit_fft<cd, CONV_NT>(lds, logP, +1, tw, logtw);
+  dit_fft<cd, CONV_NT>(lds, logP, +1, tws);
   const double sc = invP / delta[in.off + N - 1];
   double acc[2] = {0.0, 0.0};
   for (int i = tid; i < N; i += CONV_NT) {
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(CONV_NT) void k_omega(const InstInfo* __restrict__ 
                                                    const cd* __restrict__ rho,
                                                    const double* __restrict__ delta,
                                                    const SepCoef* __restrict__ coef,
-                                                   const cd* __restrict__ tw, int logtw,
+                                                   const cd* __restrict__ tws,
                                                    cd* __restrict__ scratch, int which,
                                                    int have_g0,
                                                    cd* __restrict__ oms, cd* __restrict__ o_s,
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(CONV_NT) void k_omega(const InstInfo* __restrict__ 
       lds[t] = v;
     }
     __syncthreads();
-    dif_fft<cd, CONV_NT>(lds, logP, -1, tw, logtw);
+    dif_fft<cd, CONV_NT>(lds, logP, -1, tws);
     for (int t = tid; t < P; t += CONV_NT) G[a][t] = lds[t];
     __syncthreads();
   }
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(CONV_NT) void k_omega(const InstInfo* __restrict__ 
       lds[p] = acc;
     }
     __syncthreads();
-    dit_fft<cd, CONV_NT>(lds, logP, +1, tw, logtw);
+    dit_fft<cd, CONV_NT>(lds, logP, +1, tws);
     for (int t = tid; t < P; t += CONV_NT) {
       // lag i = t for t < N, i = t - P for t > P - N
       const bool pos = t < N, neg = t > P - N;
@@ -231,31 +232,31 @@ __global__ __launch_bounds__(CONV_NT) void k_omega(const InstInfo* __restrict__ 
 
 hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void* y, int ydtype,
                            const cd* rho, const double* delta, const cd* tw, int logtw,
-                           cd* scratch, cd* w, double* yCy, double* ww, int B, int maxP,
+                           const cd* tws, cd* scratch, cd* w, double* yCy, double* ww, int B, int maxP,
                            hipStream_t st) {
   const size_t shm = (size_t)maxP * sizeof(cd);
   if (ydtype == 1) {
     (void)hipFuncSetAttribute((const void*)k_gs_apply<cd>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)shm);
     hipLaunchKernelGGL(k_gs_apply<cd>, dim3(B), dim3(CONV_NT), shm, st, info, req, (const cd*)y,
-                       rho, delta, tw, logtw, scratch, w, yCy, ww);
+                       rho, delta, tw, logtw, tws, scratch, w, yCy, ww);
   } else {
     (void)hipFuncSetAttribute((const void*)k_gs_apply<cf>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)shm);
     hipLaunchKernelGGL(k_gs_apply<cf>, dim3(B), dim3(CONV_NT), shm, st, info, req, (const cf*)y,
-                       rho, delta, tw, logtw, scratch, w, yCy, ww);
+                       rho, delta, tw, logtw, tws, scratch, w, yCy, ww);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
-                        const double* delta, const SepCoef* coef, const cd* tw, int logtw,
+                        const double* delta, const SepCoef* coef, const cd* tws,
                         cd* scratch, int which, int have_g0, cd* oms, cd* o_s, cd* o_t,
                         cd* o_v, cd* o_x, int B, int maxP, hipStream_t st) {
   const size_t shm = (size_t)maxP * sizeof(cd);
   (void)hipFuncSetAttribute((const void*)k_omega, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL(k_omega, dim3(B), dim3(CONV_NT), shm, st, info, req, rho, delta, coef, tw,
-                     logtw, scratch, which, have_g0, oms, o_s, o_t, o_v, o_x);
+  hipLaunchKernelGGL(k_omega, dim3(B), dim3(CONV_NT), shm, st, info, req, rho, delta, coef, tws,
+                     scratch, which, have_g0, oms, o_s, o_t, o_v, o_x);
   return hipGetLastError();
 }
 

@@ -93,13 +93,27 @@ __global__ __launch_bounds__(256) void k_init_state(const InstInfo* __restrict__
   }
 }
 
-__global__ void k_twiddles(cd* tw64, cf* tw32, int logtw) {
+// tw[k] = exp(-j 2 pi k / 2^logtw) for k < 2^(logtw-1) (natural order), and the
+// stage-major table tws[h + pos] = exp(-j 2 pi pos / 2h) for h = 1, 2, 4, ...
+__global__ void k_twiddles(cd* tw64, cf* tw32, cd* tws64, cf* tws32, int logtw) {
   const int64_t n = (int64_t)1 << logtw;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n / 2;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x) {
-    const cd e = cis_frac(k, n);
-    tw64[k] = cd{e.x, -e.y};
-    tw32[k] = cf{(float)e.x, (float)-e.y};
+    if (k < n / 2) {
+      const cd e = cis_frac(k, n);
+      tw64[k] = cd{e.x, -e.y};
+      tw32[k] = cf{(float)e.x, (float)-e.y};
+    }
+    if (k >= 1) {
+      int64_t h = 1;
+      while ((h << 1) <= k) h <<= 1;
+      const cd e = cis_frac(k - h, 2 * h);
+      tws64[k] = cd{e.x, -e.y};
+      tws32[k] = cf{(float)e.x, (float)-e.y};
+    } else {
+      tws64[0] = cd{1.0, 0.0};
+      tws32[0] = cf{1.0f, 0.0f};
+    }
   }
 }
 
@@ -122,8 +136,8 @@ hipError_t launch_init_state(const InstInfo* info, const void* y, int ydtype, Dr
   return hipGetLastError();
 }
 
-hipError_t launch_twiddles(cd* tw64, cf* tw32, int logtw, hipStream_t st) {
-  hipLaunchKernelGGL(k_twiddles, dim3(128), dim3(256), 0, st, tw64, tw32, logtw);
+hipError_t launch_twiddles(cd* tw64, cf* tw32, cd* tws64, cf* tws32, int logtw, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddles, dim3(256), dim3(256), 0, st, tw64, tw32, tws64, tws32, logtw);
   return hipGetLastError();
 }
 

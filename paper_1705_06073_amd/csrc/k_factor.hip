@@ -108,25 +108,32 @@ __global__ __launch_bounds__(T) void k_levinson(const InstInfo* __restrict__ inf
   cd eps = (N > 1) ? cb[1] : cd{0.0, 0.0};
   __syncthreads();
 
+  double inv = 1.0 / dlt;
   int n = 1;
   for (; n < N && fail < 0; ++n) {
     const int par = n & 1, ppar = par ^ 1;
-    const double inv = 1.0 / dlt;
     const cd k{-eps.x * inv, -eps.y * inv};
     const double dn = dlt * (1.0 - cabs2(k));
     if (!(dn > 0.0) || !isfinite(dn)) { fail = n; break; }
-    cd acc{0.0, 0.0};
+    // reciprocal for the next step, off the critical path of this one
+    const double inv_next = 1.0 / dn;
+    // hand-off values from the neighbouring wave (read for every slot at once)
+    cd inc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
+      if (wv > 0) inc[s] = xb[ppar][wv - 1][s];
+      else inc[s] = (s > 0) ? xb[ppar][W - 1][s - 1] : cd{0.0, 0.0};
+    }
+    cd part[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      part[s] = cd{0.0, 0.0};
       if (s * T <= n) {
-        cd inc;
-        if (wv > 0) inc = xb[ppar][wv - 1][s];
-        else inc = (s > 0) ? xb[ppar][W - 1][s - 1] : cd{0.0, 0.0};
-        cd sh{shr1_f64(bb[s].x, inc.x), shr1_f64(bb[s].y, inc.y)};
+        cd sh{shr1_f64(bb[s].x, inc[s].x), shr1_f64(bb[s].y, inc[s].y)};
         const cd ao = a[s];
         a[s] = cfma(k, sh, ao);                 // a_j + k b_{j-1}
         bb[s] = cfmac(ao, k, sh);               // b_{j-1} + conj(k) a_j
-        acc = cfmac(cc[s], bb[s], acc);         // c_{j+1} conj(b_j)
+        part[s] = cmulc(cc[s], bb[s]);          // c_{j+1} conj(b_j)
       }
     }
     if (lane == 63) {
@@ -134,7 +141,12 @@ __global__ __launch_bounds__(T) void k_levinson(const InstInfo* __restrict__ inf
       for (int s = 0; s < S; ++s)
         if (s * T <= n) xb[par][wv][s] = bb[s];
     }
-    acc = wave_sum(acc);
+    // pairwise sum of the slot partials, then across the wave
+#pragma unroll
+    for (int w2 = 1; w2 < S; w2 <<= 1)
+#pragma unroll
+      for (int s = 0; s + w2 < S; s += 2 * w2) part[s] = cadd(part[s], part[s + w2]);
+    const cd acc = wave_sum(part[0]);
     if (lane == 0) xp[par][wv] = acc;
     if (tid == 0) dl[n] = dn;
     __syncthreads();
@@ -143,6 +155,7 @@ __global__ __launch_bounds__(T) void k_levinson(const InstInfo* __restrict__ inf
     for (int w = 0; w < W; ++w) e = cadd(e, xp[par][w]);
     eps = e;
     dlt = dn;
+    inv = inv_next;
   }
   __syncthreads();
 
@@ -199,7 +212,7 @@ hipError_t launch_levinson(const InstInfo* info, const int32_t* req, const cd* c
   if (maxN <= 512) { LEV_GO(128, 4) }
   if (maxN <= 1024) { LEV_GO(256, 4) }
   if (maxN <= 2048) { LEV_GO(256, 8) }
-  if (maxN <= 4096) { LEV_GO(256, 16) }
+  if (maxN <= 4096) { LEV_GO(512, 8) }
 #undef LEV_GO
   return hipErrorInvalidValue;
 }

@@ -86,8 +86,8 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
     ls[m] = C{(decltype(C{}.x))sv.x, (decltype(C{}.x))sv.y};
   }
   __syncthreads();
-  dif_fft<C, GRID_NT>(lq, logM, -1, tw, logtw);
-  dif_fft<C, GRID_NT>(ls, logM, +1, tw, logtw);
+  dif_fft<C, GRID_NT>(lq, logM, -1, tw);
+  dif_fft<C, GRID_NT>(ls, logM, +1, tw);
   const R gb = (R)gbar[bi];
   const double z = zeta[bi];
   const R odds = (R)((1.0 - z) / z);

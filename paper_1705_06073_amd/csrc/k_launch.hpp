@@ -59,19 +59,25 @@ struct DrvPools {
   int32_t* notdone;
 };
 
-hipError_t launch_twiddles(cd* tw64, cf* tw32, int logtw, hipStream_t st);
+hipError_t launch_twiddles(cd* tw64, cf* tw32, cd* tws64, cf* tws32, int logtw, hipStream_t st);
 hipError_t launch_toeplitz_column(const InstInfo* info, const int32_t* req, const int32_t* Kcnt,
                                   const double* theta, const double* gamma, const double* beta,
                                   cd* c, int B, int maxN, hipStream_t st);
 hipError_t launch_levinson(const InstInfo* info, const int32_t* req, const cd* c, cd* rho,
                            double* delta, double* logdet, int32_t* status, int64_t* failed, int B,
                            int maxN, hipStream_t st);
+hipError_t launch_schur(const InstInfo* info, const int32_t* req, const SchurLayout* lay,
+                        const SchurAct* acts, const cd* c, const cd* tw, int logtw,
+                        const cd* tws, cd* scratch,
+                        cd* rho, double* delta, double* logdet, int32_t* status, int64_t* failed,
+                        int B, int Fmax, hipStream_t st);
 hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void* y, int ydtype,
                            const cd* rho, const double* delta, const cd* tw, int logtw,
-                           cd* scratch, cd* w, double* yCy, double* ww, int B, int maxP,
+                           const cd* tws, cd* scratch, cd* w, double* yCy, double* ww, int B,
+                           int maxP,
                            hipStream_t st);
 hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
-                        const double* delta, const SepCoef* coef, const cd* tw, int logtw,
+                        const double* delta, const SepCoef* coef, const cd* tws,
                         cd* scratch, int which, int have_g0, cd* oms, cd* o_s, cd* o_t,
                         cd* o_v, cd* o_x, int B, int maxP, hipStream_t st);
 hipError_t launch_grid(int prec, const InstInfo* info, const int32_t* req, const cd* w,

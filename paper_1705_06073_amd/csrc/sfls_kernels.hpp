@@ -35,4 +35,22 @@ struct SepCoef {
   double c[4][16];  // s, t, v, x
 };
 
+// Superfast Schur: one action of the flattened recursion.
+enum : int32_t { SCH_LEAF_ACT = 0, SCH_MID = 1, SCH_POST = 2, SCH_ROOT = 3, SCH_ROOT_LEAF = 4 };
+struct SchurAct {
+  int32_t type, n0, m, m1, level, side, win_level, logF;
+};
+constexpr int SCH_MAXL = 16;
+// Per-instance layout of the recursion's scratch (offsets in complex elements).
+struct SchurLayout {
+  int64_t scr_off;
+  int64_t act_off;
+  int32_t nact;
+  int32_t Fmax;
+  int64_t win[SCH_MAXL];   // right-child windows (u then v, mmax[l] each)
+  int64_t res[SCH_MAXL];   // Theta results, 2 sides x 4 polynomials x mmax[l]
+  int64_t spec[SCH_MAXL];  // Theta1 spectra, 4 x F
+  int32_t mmax[SCH_MAXL];
+};
+
 }  // namespace sfls
