@@ -240,7 +240,7 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
   lay.assign((size_t)B, SchurLayout{});
   pool.clear();
   scr_total = 0;
-  Fmax = 2;
+  Fmax = 64;  // the leaves use the transform buffers as 64-element scratch
   for (int64_t b = 0; b < B; ++b) {
     const int64_t N = n[b];
     auto it = byN.find(N);
@@ -258,7 +258,7 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
     L.nact = (int32_t)P.acts.size();
     L.scr_off = scr_total;
     int64_t o = 0;
-    int fm = 2;
+    int fm = 64;
     for (int l = 0; l < P.nlev; ++l) {
       L.mmax[l] = P.mmax[l];
       L.win[l] = o;
@@ -268,6 +268,7 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
       L.spec[l] = o;
       o += 4 * (int64_t)P.fspec[l];
       fm = std::max(fm, P.fspec[l]);
+      if (P.mmax[l] <= SCH_DIRECT) fm = std::max(fm, 8 * P.mmax[l] + 256);
     }
     L.Fmax = fm;
     Fmax = std::max(Fmax, fm);

@@ -31,7 +31,7 @@
 
 namespace sfls {
 
-constexpr int SCH_NT = 256;
+constexpr int SCH_NT = 512;
 constexpr int SCH_LEAF = 64;
 
 __device__ __forceinline__ double shr1d(double v) {
@@ -40,49 +40,272 @@ __device__ __forceinline__ double shr1d(double v) {
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ cd shr1c(cd v) { return cd{shr1d(v.x), shr1d(v.y)}; }
+// lane r <- lane r+1 (lane 63 <- 0)
+__device__ __forceinline__ double shl1d(double v) {
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, true);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ cd shl1c(cd v) { return cd{shl1d(v.x), shl1d(v.y)}; }
 __device__ __forceinline__ cd readlane_c(cd v, int l) { return cd{readlane_f64(v.x, l), readlane_f64(v.y, l)}; }
 
-// two radix-2 FFTs over the same stages (shared barriers)
+// LDS layout of a transform buffer: one 16-byte pad slot after every 16
+// elements, so that the strided and the unit-stride passes below both spread
+// over all banks.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded(int n) { return n + (n >> 4) + 1; }
+
+// Radix-2 transforms in the same stage order as a plain radix-2 network, with
+// KS consecutive stages fused per LDS pass: a group holds 2^KS elements at
+// stride s in registers.  Twiddle W_{2h}^pos = tws[h + pos] (stage-major
+// table); sgn > 0 uses the conjugate.  DIF: natural in, bit-reversed out;
+// DIT: bit-reversed in, natural out.
+template <int KS>
+__device__ __forceinline__ void dif_group(cd* z, int g, int lh_top, const cd* __restrict__ tws,
+                                          bool conj) {
+  constexpr int R = 1 << KS;
+  const int ls = lh_top - KS + 1;
+  const int s = 1 << ls;
+  const int gl = g & (s - 1);
+  const int base = gl + ((g >> ls) << (ls + KS));
+  cd x[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) x[j] = z[pidx(base + j * s)];
+#pragma unroll
+  for (int t = 0; t < KS; ++t) {
+    const int hj = R >> (t + 1);
+    const int h = hj << ls;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (j & hj) continue;
+      cd w = tws[h + gl + (j & (hj - 1)) * s];
+      if (conj) w.y = -w.y;
+      const cd u = x[j], v = x[j + hj];
+      x[j] = cadd(u, v);
+      x[j + hj] = cmul(csub(u, v), w);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) z[pidx(base + j * s)] = x[j];
+}
+
+template <int KS>
+__device__ __forceinline__ void dit_group(cd* z, int g, int lh_bot, const cd* __restrict__ tws,
+                                          bool conj) {
+  constexpr int R = 1 << KS;
+  const int ls = lh_bot;
+  const int s = 1 << ls;
+  const int gl = g & (s - 1);
+  const int base = gl + ((g >> ls) << (ls + KS));
+  cd x[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) x[j] = z[pidx(base + j * s)];
+#pragma unroll
+  for (int t = 0; t < KS; ++t) {
+    const int hj = 1 << t;
+    const int h = hj << ls;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (j & hj) continue;
+      cd w = tws[h + gl + (j & (hj - 1)) * s];
+      if (conj) w.y = -w.y;
+      const cd u = x[j], v = cmul(x[j + hj], w);
+      x[j] = cadd(u, v);
+      x[j + hj] = csub(u, v);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) z[pidx(base + j * s)] = x[j];
+}
+
+// Largest radix (stages per pass) for na transforms of size 2^logn: small
+// transforms use shorter groups so that more threads share a pass.
+__device__ __forceinline__ int ks_max(int na, int logn) {
+  const int tot = na << logn;
+  return tot >= 2048 ? 4 : (tot >= 512 ? 3 : 2);
+}
+
+// na (1 or 2) transforms of size 2^logn over the buffers x, y; ends with a
+// barrier.  Twiddles of the stages with 2h <= SCH_TWL come from the LDS copy tl,
+// the others (first DIF pass / last DIT pass of sizes > SCH_TWL, always 4
+// stages) from the global table tg.
 template <int NT>
-__device__ void dif_fft2(cd* x, cd* y, int logn, int sgn, const cd* __restrict__ tws) {
-  const int n = 1 << logn;
-  for (int lh = logn - 1; lh >= 0; --lh) {
-    const int h = 1 << lh;
-    for (int b = threadIdx.x; b < n; b += NT) {
-      cd* z = (b < (n >> 1)) ? x : y;
-      const int bb = b & ((n >> 1) - 1);
-      const int pos = bb & (h - 1);
-      const int i = ((bb >> lh) << (lh + 1)) + pos;
-      const int j = i + h;
-      cd u = z[i], v = z[j];
-      cd w = tws[h + pos];
-      if (sgn > 0) w.y = -w.y;
-      z[i] = cadd(u, v);
-      z[j] = cmul(csub(u, v), w);
+__device__ __forceinline__ void dif_fftn(cd* x, cd* y, int na, int logn, int sgn,
+                                         const cd* __restrict__ tl, const cd* __restrict__ tg) {
+  const bool conj = sgn > 0;
+  const int km = ks_max(na, logn);
+  int lh = logn - 1;
+  while (lh >= 0) {
+    const int ks = lh + 1 < km ? lh + 1 : km;
+    const int lg = logn - ks;  // log2(groups per transform)
+    const int tot = na << lg;
+    const bool lds_tw = (2 << lh) <= SCH_TWL;
+    for (int gi = threadIdx.x; gi < tot; gi += NT) {
+      cd* z = (gi >> lg) ? y : x;
+      const int g = gi & ((1 << lg) - 1);
+      if (!lds_tw) {
+        dif_group<4>(z, g, lh, tg, conj);
+        continue;
+      }
+      switch (ks) {
+        case 4: dif_group<4>(z, g, lh, tl, conj); break;
+        case 3: dif_group<3>(z, g, lh, tl, conj); break;
+        case 2: dif_group<2>(z, g, lh, tl, conj); break;
+        default: dif_group<1>(z, g, lh, tl, conj); break;
+      }
     }
     __syncthreads();
+    lh -= ks;
   }
 }
 
 template <int NT>
-__device__ void dit_fft2(cd* x, cd* y, int logn, int sgn, const cd* __restrict__ tws) {
-  const int n = 1 << logn;
-  for (int lh = 0; lh < logn; ++lh) {
-    const int h = 1 << lh;
-    for (int b = threadIdx.x; b < n; b += NT) {
-      cd* z = (b < (n >> 1)) ? x : y;
-      const int bb = b & ((n >> 1) - 1);
-      const int pos = bb & (h - 1);
-      const int i = ((bb >> lh) << (lh + 1)) + pos;
-      const int j = i + h;
-      cd w = tws[h + pos];
-      if (sgn > 0) w.y = -w.y;
-      cd u = z[i], v = cmul(z[j], w);
-      z[i] = cadd(u, v);
-      z[j] = csub(u, v);
+__device__ __forceinline__ void dit_fftn(cd* x, cd* y, int na, int logn, int sgn,
+                                         const cd* __restrict__ tl, const cd* __restrict__ tg) {
+  const bool conj = sgn > 0;
+  const int km = ks_max(na, logn);
+  int lb = 0;
+  while (lb < logn) {
+    // the shorter pass first, so that the last (largest-h) pass has km stages
+    const int rem = logn % km;
+    const int ks = (lb == 0 && rem) ? rem : km;
+    const int lg = logn - ks;
+    const int tot = na << lg;
+    const bool lds_tw = (2 << (lb + ks - 1)) <= SCH_TWL;
+    for (int gi = threadIdx.x; gi < tot; gi += NT) {
+      cd* z = (gi >> lg) ? y : x;
+      const int g = gi & ((1 << lg) - 1);
+      if (!lds_tw) {
+        dit_group<4>(z, g, lb, tg, conj);
+        continue;
+      }
+      switch (ks) {
+        case 4: dit_group<4>(z, g, lb, tl, conj); break;
+        case 3: dit_group<3>(z, g, lb, tl, conj); break;
+        case 2: dit_group<2>(z, g, lb, tl, conj); break;
+        default: dit_group<1>(z, g, lb, tl, conj); break;
+      }
     }
     __syncthreads();
+    lb += ks;
   }
+}
+
+// Sliding-window block of RB outputs t0..t0+RB-1 of two convolutions,
+//   acc[i] += sum_{j < J} a[j] x[t0+i-j] + b[j] y[t0+i-j],
+// over LDS operands; x and y must be readable (zero where outside the
+// polynomials) on [t0 - J - RB + 1, t0 + RB).
+// x and y are given as a row base and the padded index of the origin; element
+// i of a padded row is stored at skew(i) = i + i / RB, so that lanes at output
+// stride RB read distinct banks.
+template <int RB>
+__device__ __forceinline__ int skew(int i) {
+  return RB > 1 ? i + (i >> (RB == 2 ? 1 : 2)) : i;
+}
+template <int RB>
+__device__ __forceinline__ void conv2_block(const cd* a, const cd* xr, int xo, const cd* b,
+                                            const cd* yr, int yo, int J, int t0,
+                                            cd (&acc)[RB]) {
+  constexpr int W = 2 * RB - 1;
+  cd xv[W], yv[W];  // xv[k] = x[t0 - j0 + k - (RB - 1)]
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    xv[k] = xr[skew<RB>(xo + t0 + k - (RB - 1))];
+    yv[k] = yr[skew<RB>(yo + t0 + k - (RB - 1))];
+  }
+  for (int j0 = 0; j0 < J; j0 += RB) {
+#pragma unroll
+    for (int jj = 0; jj < RB; ++jj) {
+      if (j0 + jj < J) {
+        const cd aj = a[j0 + jj], bj = b[j0 + jj];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          acc[i] = cfma(aj, xv[RB - 1 + i - jj], acc[i]);
+          acc[i] = cfma(bj, yv[RB - 1 + i - jj], acc[i]);
+        }
+      }
+    }
+    if (j0 + RB < J) {
+#pragma unroll
+      for (int k = W - 1; k >= RB; --k) {
+        xv[k] = xv[k - RB];
+        yv[k] = yv[k - RB];
+      }
+#pragma unroll
+      for (int k = 0; k < RB; ++k) {
+        xv[k] = xr[skew<RB>(xo + t0 - j0 - 2 * RB + 1 + k)];
+        yv[k] = yr[skew<RB>(yo + t0 - j0 - 2 * RB + 1 + k)];
+      }
+    }
+  }
+}
+
+// sum_{j0 <= j < j1} a[j] x[-j] + b[j] y[-j] over LDS operands, unrolled by 8 so
+// that the loads of a block are in flight together
+__device__ __forceinline__ cd dot2(const cd* a, const cd* x, const cd* b, const cd* y, int j0,
+                                   int j1) {
+  cd s0{0.0, 0.0}, s1{0.0, 0.0}, s2{0.0, 0.0}, s3{0.0, 0.0};
+  int j = j0;
+  for (; j + 8 <= j1; j += 8) {
+    cd av[8], xv[8], bv[8], yv[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      av[i] = a[j + i];
+      xv[i] = x[-(j + i)];
+      bv[i] = b[j + i];
+      yv[i] = y[-(j + i)];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i += 2) {
+      s0 = cfma(av[i], xv[i], s0);
+      s1 = cfma(bv[i], yv[i], s1);
+      s2 = cfma(av[i + 1], xv[i + 1], s2);
+      s3 = cfma(bv[i + 1], yv[i + 1], s3);
+    }
+  }
+  for (; j < j1; ++j) {
+    s0 = cfma(a[j], x[-j], s0);
+    s1 = cfma(b[j], y[-j], s1);
+  }
+  return cadd(cadd(s0, s2), cadd(s1, s3));
+}
+
+// RB consecutive outputs t0.. of one polynomial of Theta2 Theta1 (shifted
+// form): R[t] = sum_j q1[j] p1[t-j] + q2[j] p2[t-1-j] with p1, p2 the padded
+// rows r1, r2 and origins o1, o2 (o2 already one lag back); the root adds the
+// second column one more lag back (rho = R21 + z R22), whose rows follow at
+// distance pe.
+template <int RB>
+__device__ __forceinline__ void post_block(const cd* q1, const cd* r1, int o1, const cd* q2,
+                                           const cd* r2, int o2, int J, int t0, bool root,
+                                           int pe, int nout, cd* out) {
+  cd acc[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) acc[i] = cd{0.0, 0.0};
+  conv2_block<RB>(q1, r1, o1, q2, r2, o2, J, t0, acc);
+  if (root) conv2_block<RB>(q1, r1 + pe, o1 - 1, q2, r2 + pe, o2 - 1, J, t0, acc);
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+    if (t0 + i < nout) out[t0 + i] = acc[i];
+}
+
+// One Schur step on the moving window (lane r: U(n+1+r), V(n+r) at order n):
+// k_n = -U(n+1)/delta_n, delta_{n+1} = delta_n (1 - |k|^2),
+// V <- V + conj(k) U,  U <- (U + k V) shifted down one lane.
+__device__ __forceinline__ void leaf_step(cd& U, cd& V, double& dlt, double& inv, cd& k,
+                                          double& dn) {
+  const cd U0 = readlane_c(U, 0);
+  k = cd{-U0.x * inv, -U0.y * inv};
+  const double q = 1.0 - cabs2(k);
+  dn = dlt * q;
+  // 1/delta_{n+1} = (1/delta_n) / q: hardware reciprocal + one Newton step
+  const double r0 = __builtin_amdgcn_rcp(q);
+  const double r1 = fma(r0, fma(-q, r0, 1.0), r0);
+  const cd W = cfma(k, V, U);  // U(i) + k V(i-1)
+  V = cfmac(U, k, V);          // V(i-1) + U(i) conj(k)
+  U = shl1c(W);
+  dlt = dn;
+  inv = inv * r1;
 }
 
 // W_F^f = exp(-j 2 pi f / F) for the bin at bit-reversed position p
@@ -116,12 +339,14 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   extern __shared__ cd lds[];
   cd* A = lds;
-  cd* Bf = lds + L.Fmax;
+  cd* Bf = lds + padded(L.Fmax);
   __shared__ double s_logdet;
   __shared__ int s_fail;
+  __shared__ cd s_tw[SCH_TWL];  // head of the stage-major twiddle table
   const cd* cb = c + in.off;
   cd* scr = scratch + L.scr_off;
   double* dl = delta_out ? delta_out + in.off : nullptr;
+  for (int t = tid; t < SCH_TWL; t += SCH_NT) s_tw[t] = tws[t];
   if (tid == 0) {
     s_logdet = log(cb[0].x);
     s_fail = (cb[0].x > 0.0 && isfinite(cb[0].x)) ? -1 : 0;
@@ -156,162 +381,230 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
     if (act.win_level < 0) { u = cb + 1; v = cb; }
     else { u = scr + L.win[act.win_level]; v = u + L.mmax[act.win_level]; }
     if (act.type == SCH_LEAF_ACT || act.type == SCH_ROOT_LEAF) {
-      if (wv == 0) {
+      // Waves 0-2 each run the m Schur steps on the window (the same code, so
+      // the same coefficients); wave 0 keeps the pivots, waves 1 and 2
+      // accumulate the two independent column pairs of Theta, (P11, P21) and
+      // (P12, P22).
+      if (wv <= 2) {
         cd U = (lane < m) ? u[lane] : cd{0.0, 0.0};
         cd V = (lane < m) ? v[lane] : cd{0.0, 0.0};
         double dlt = readlane_f64(V.x, 0);
         double inv = 1.0 / dlt;
-        double my_dn = 1.0;   // delta_{n0+1+lane}, kept by lane s at step s
-        int fail = -1;
-        cd T11{0.0, 0.0}, T12{0.0, 0.0}, T21{0.0, 0.0}, T22{0.0, 0.0};
-        for (int s = 0; s < m; ++s) {
-          const cd Us = readlane_c(U, s);
-          const cd k{-Us.x * inv, -Us.y * inv};
-          const double q = 1.0 - cabs2(k);
-          const double dn = dlt * q;
-          // 1/delta_{n+1} = (1/delta_n) / q: hardware reciprocal + one Newton step
-          const double r0 = __builtin_amdgcn_rcp(q);
-          const double r1 = fma(r0, fma(-q, r0, 1.0), r0);
-          const bool bad = !(dn > 0.0) || !isfinite(dn);
-          if (bad && fail < 0) fail = act.n0 + s + 1;
-          const cd Ush = shr1c(U), Vsh = shr1c(V);
-          U = cfma(k, V, U);            // U(i) + k V(i-1): same lane
-          V = cfmac(Ush, k, Vsh);       // V(i-1) + conj(k) U(i): both from lane r-1
-          if (s == 0) {
-            const bool l0 = lane == 0;
-            T11 = cd{l0 ? 1.0 : 0.0, 0.0};
-            T12 = l0 ? k : cd{0.0, 0.0};
-            T21 = l0 ? cconj(k) : cd{0.0, 0.0};
-            T22 = cd{l0 ? 1.0 : 0.0, 0.0};
-          } else {
-            const cd S21 = shr1c(T21), S22 = shr1c(T22);
-            const cd o11 = T11, o12 = T12;
-            T11 = cfma(k, S21, o11);      // P11 + k z P21
-            T12 = cfma(k, S22, o12);      // P12 + k z P22
-            T21 = cfmac(o11, k, S21);     // conj(k) P11 + z P21
-            T22 = cfmac(o12, k, S22);     // conj(k) P12 + z P22
+        cd k;
+        double dn;
+        if (wv == 0) {
+          double my_dn = 1.0;  // delta_{n0+1+lane}
+          for (int s = 0; s < m; ++s) {
+            leaf_step(U, V, dlt, inv, k, dn);
+            if (lane == s) my_dn = dn;
           }
-          if (lane == s) my_dn = dn;
-          dlt = dn;
-          inv = inv * r1;
-        }
-        // pivots and their logs, one per lane
-        double lg = 0.0;
-        if (lane < m) {
-          if (dl) dl[act.n0 + 1 + lane] = my_dn;
-          lg = log(my_dn);
-        }
-        const double lsum = wave_sum(lg);
-        if (lane == 0) {
-          s_logdet += lsum;
-          if (fail >= 0) s_fail = fail;
-        }
-        if (act.type == SCH_ROOT_LEAF) {
-          // rho = P21 + z P22 (degree <= m = N-1 <= 63 < 64 lanes)
-          const cd zP22 = shr1c(T22);
-          if (lane < N) rho[in.off + lane] = cadd(T21, zP22);
-        } else {
-          cd* R = scr + L.res[act.level] + (int64_t)act.side * 4 * L.mmax[act.level];
-          const int st = L.mmax[act.level];
+          // pivots, their logs and the first non-positive one, one per lane
+          double lg = 0.0;
+          bool bad = false;
           if (lane < m) {
-            R[lane] = T11;
-            R[st + lane] = T12;
-            R[2 * st + lane] = T21;
-            R[3 * st + lane] = T22;
+            if (dl) dl[act.n0 + 1 + lane] = my_dn;
+            bad = !(my_dn > 0.0) || !isfinite(my_dn);
+            lg = log(my_dn);
+          }
+          const double lsum = wave_sum(lg);
+          const unsigned long long badm = __ballot(bad);
+          if (lane == 0) {
+            s_logdet += lsum;
+            if (badm) s_fail = act.n0 + 1 + __builtin_ctzll(badm);
+          }
+        } else {
+          // column c = wv: after step 0 (1, conj k0) for c = 1 and (k0, 1) for
+          // c = 2 (shifted form); then (P1c, P2c) <- (P1c + k z P2c, conj(k) P1c + z P2c)
+          leaf_step(U, V, dlt, inv, k, dn);
+          const bool l0 = lane == 0;
+          const cd one{l0 ? 1.0 : 0.0, 0.0};
+          const cd kk = l0 ? k : cd{0.0, 0.0};
+          cd T1 = (wv == 1) ? one : kk;
+          cd T2 = (wv == 1) ? cconj(kk) : one;
+          for (int s = 1; s < m; ++s) {
+            leaf_step(U, V, dlt, inv, k, dn);
+            const cd S2 = shr1c(T2);
+            const cd o1 = T1;
+            T1 = cfma(k, S2, o1);
+            T2 = cfmac(o1, k, S2);
+          }
+          if (act.type == SCH_ROOT_LEAF) {
+            (wv == 1 ? A : Bf)[lane] = T2;  // P21, P22 (plain index)
+          } else {
+            cd* R = scr + L.res[act.level] + (int64_t)act.side * 4 * L.mmax[act.level];
+            const int st = L.mmax[act.level];
+            if (lane < m) {
+              const int c0 = wv - 1;  // column 0 -> P11/P21, column 1 -> P12/P22
+              R[c0 * st + lane] = T1;
+              R[(2 + c0) * st + lane] = T2;
+            }
           }
         }
       }
       __syncthreads();
       if (s_fail >= 0) break;
+      if (act.type == SCH_ROOT_LEAF) {
+        // rho = P21 + z P22 (degree <= m = N-1 <= 63)
+        if (tid < N) rho[in.off + tid] = cadd(tid < m ? A[tid] : cd{0.0, 0.0},
+                                             tid > 0 ? Bf[tid - 1] : cd{0.0, 0.0});
+        __syncthreads();
+      }
+      continue;
+    }
+    const int cl = act.level + 1;
+    const cd* T1 = scr + L.res[cl];              // left child's Theta (m1 coefficients each)
+    const cd* T2 = T1 + (int64_t)4 * L.mmax[cl];  // right child's Theta (m2 coefficients each)
+    const int st1 = L.mmax[cl];
+    const bool root = act.type == SCH_ROOT;
+    cd* R = scr + L.res[act.level] + (int64_t)act.side * 4 * L.mmax[act.level];
+    const int st = L.mmax[act.level];
+    if (m <= SCH_DIRECT) {
+      if (act.type == SCH_MID) {
+        // u2[r] = sum_j P11[j] u[m1+r-j] + P12[j] v[m1+r-j]
+        // v2[r] = sum_j P21[j] u[m1-1+r-j] + P22[j] v[m1-1+r-j],  j < m1;
+        // outputs with 2 m2 <= SCH_NT/2 split their sum in two halves.
+        for (int t = tid; t < 4 * m1; t += SCH_NT) A[t] = T1[(t / m1) * st1 + t % m1];
+        for (int t = tid; t < m; t += SCH_NT) {
+          Bf[t] = u[t];
+          Bf[m + t] = v[t];
+        }
+        __syncthreads();
+        const int nout = 2 * m2;
+        const int sp = nout <= SCH_NT / 2 ? 2 : 1;
+        const int jh = (m1 + sp - 1) / sp;
+        cd* part = Bf + 2 * m;
+        for (int it = tid; it < nout * sp; it += SCH_NT) {
+          const int o = it % nout, h = it / nout;
+          const bool isv = o >= m2;
+          const int r = isv ? o - m2 : o;
+          const cd* Pa = A + (isv ? 2 * m1 : 0);
+          const cd* Pb = Pa + m1;
+          const cd* xu = Bf + (isv ? m1 - 1 + r : m1 + r);
+          const cd* xv = xu + m;
+          const int j0 = h * jh, j1 = j0 + jh < m1 ? j0 + jh : m1;
+          part[it] = dot2(Pa, xu, Pb, xv, j0, j1);
+        }
+        __syncthreads();
+        cd* W2 = scr + L.win[cl];
+        const int stw = L.mmax[cl];
+        for (int o = tid; o < nout; o += SCH_NT) {
+          cd acc = part[o];
+          if (sp == 2) acc = cadd(acc, part[nout + o]);
+          const bool isv = o >= m2;
+          W2[(isv ? stw + o - m2 : o)] = acc;
+        }
+        __syncthreads();
+        continue;
+      }
+      // POST / ROOT: row r of Theta2 Theta1 in the shifted form,
+      //   R_r1 = Q_r1 P11' + z Q_r2 P21',  R_r2 = Q_r1 P12' + z Q_r2 P22',
+      // as sliding-window sums over j < m2 against zero-padded P'.
+      const int nout = root ? N : m;   // outputs per polynomial
+      const int npoly = root ? 1 : 4;
+      const int RB = (npoly * nout >= 1024) ? 4 : ((npoly * nout >= 512) ? 2 : 1);
+      const int lrb = RB == 4 ? 2 : (RB == 2 ? 1 : 0);
+      const int PL = m2 + 8;                 // zeros below each P'
+      const int pe = PL + m + 8;             // padded row length (multiple-of-RB skew)
+      const int pes = pe + (pe >> lrb) * (RB > 1);  // skewed row length
+      cd* Pext = A;                          // row q: P'_q(i) at skew(PL + i)
+      cd* Q = A + 4 * pes + 8;               // 4 x m2
+      for (int t = tid; t < 4 * pe; t += SCH_NT) {
+        const int q = t / pe, k = t % pe, i = k - PL;
+        const int sk = RB > 1 ? k + (k >> lrb) : k;
+        Pext[q * pes + sk] = (i >= 0 && i < m1) ? T1[q * st1 + i] : cd{0.0, 0.0};
+      }
+      for (int t = tid; t < 4 * m2; t += SCH_NT) Q[t] = T2[(t / m2) * st1 + t % m2];
+      __syncthreads();
+      const int nblk = (nout + RB - 1) / RB;
+      for (int it = tid; it < npoly * nblk; it += SCH_NT) {
+        const int poly = root ? 2 : it / nblk;  // root: row 1 (R21 + z R22)
+        const int row = poly >> 1, col = poly & 1;
+        const int t0 = (it % nblk) * RB;
+        const cd* q1 = Q + (2 * row) * m2;
+        const cd* q2 = q1 + m2;
+        const cd* r1 = Pext + col * pes;         // P11' or P12'
+        const cd* r2 = Pext + (2 + col) * pes;   // P21' or P22' (one lag)
+        cd* out = root ? rho + in.off : R + poly * st;
+        if (RB == 4) post_block<4>(q1, r1, PL, q2, r2, PL - 1, m2, t0, root, pes, nout, out);
+        else if (RB == 2) post_block<2>(q1, r1, PL, q2, r2, PL - 1, m2, t0, root, pes, nout, out);
+        else post_block<1>(q1, r1, PL, q2, r2, PL - 1, m2, t0, root, pes, nout, out);
+      }
+      __syncthreads();
       continue;
     }
     const int logF = act.logF, F = 1 << logF;
     const double invF = 1.0 / (double)F;
+    cd* S = scr + L.spec[act.level];  // Theta1 spectra, 4 x F
     if (act.type == SCH_MID) {
-      // spectra of Theta1 (left child, m1 coefficients per polynomial)
-      const int cl = act.level + 1;
-      const cd* T1 = scr + L.res[cl];
-      const int st1 = L.mmax[cl];
-      cd* S = scr + L.spec[act.level];
-      for (int q = 0; q < 4; q += 2) {
+      // jobs 0, 1: spectra of the Theta1 polynomial pairs (to S); job 2: the window
+      for (int job = 0; job < 3; ++job) {
+        const cd* pa = job < 2 ? T1 + (2 * job) * st1 : u;
+        const cd* pb = job < 2 ? T1 + (2 * job + 1) * st1 : v;
+        const int lim = job < 2 ? m1 : m;
         for (int t = tid; t < F; t += SCH_NT) {
-          A[t] = (t < m1) ? T1[q * st1 + t] : cd{0.0, 0.0};
-          Bf[t] = (t < m1) ? T1[(q + 1) * st1 + t] : cd{0.0, 0.0};
+          A[pidx(t)] = t < lim ? pa[t] : cd{0.0, 0.0};
+          Bf[pidx(t)] = t < lim ? pb[t] : cd{0.0, 0.0};
         }
         __syncthreads();
-        dif_fft2<SCH_NT>(A, Bf, logF, -1, tws);
-        for (int t = tid; t < F; t += SCH_NT) {
-          S[(int64_t)q * F + t] = A[t];
-          S[(int64_t)(q + 1) * F + t] = Bf[t];
+        dif_fftn<SCH_NT>(A, Bf, 2, logF, -1, s_tw, tws);
+        if (job < 2) {
+          for (int t = tid; t < F; t += SCH_NT) {
+            S[(int64_t)(2 * job) * F + t] = A[pidx(t)];
+            S[(int64_t)(2 * job + 1) * F + t] = Bf[pidx(t)];
+          }
+          __syncthreads();
         }
-        __syncthreads();
       }
-      // window spectra
-      for (int t = tid; t < F; t += SCH_NT) {
-        A[t] = (t < m) ? u[t] : cd{0.0, 0.0};
-        Bf[t] = (t < m) ? v[t] : cd{0.0, 0.0};
-      }
-      __syncthreads();
-      dif_fft2<SCH_NT>(A, Bf, logF, -1, tws);
       for (int p = tid; p < F; p += SCH_NT) {
-        const cd fu = A[p], fv = Bf[p];
+        const cd fu = A[pidx(p)], fv = Bf[pidx(p)];
         const cd s11 = S[p], s12 = S[F + p], s21 = S[2 * F + p], s22 = S[3 * F + p];
-        A[p] = cfma(s12, fv, cmul(s11, fu));
-        Bf[p] = cfma(s22, fv, cmul(s21, fu));
+        A[pidx(p)] = cfma(s12, fv, cmul(s11, fu));
+        Bf[pidx(p)] = cfma(s22, fv, cmul(s21, fu));
       }
       __syncthreads();
-      dit_fft2<SCH_NT>(A, Bf, logF, +1, tws);
+      dit_fftn<SCH_NT>(A, Bf, 2, logF, +1, s_tw, tws);
       // right child's window
       cd* W2 = scr + L.win[cl];
       const int stw = L.mmax[cl];
       for (int r = tid; r < m2; r += SCH_NT) {
-        W2[r] = cscale(A[m1 + r], invF);
-        W2[stw + r] = cscale(Bf[m1 - 1 + r], invF);
+        W2[r] = cscale(A[pidx(m1 + r)], invF);
+        W2[stw + r] = cscale(Bf[pidx(m1 - 1 + r)], invF);
       }
       __syncthreads();
       continue;
     }
-    // POST / ROOT: Theta = Theta2 Theta1
-    const int cl = act.level + 1;
-    const cd* T2 = scr + L.res[cl] + (int64_t)4 * L.mmax[cl];  // right child's result
-    const int st2 = L.mmax[cl];
-    const cd* S = scr + L.spec[act.level];
-    const bool root = act.type == SCH_ROOT;
+    // POST / ROOT: Theta = Theta2 Theta1, one row at a time (root: row 2 only)
     for (int row = root ? 1 : 0; row < 2; ++row) {
       for (int t = tid; t < F; t += SCH_NT) {
-        A[t] = (t < m2) ? T2[(2 * row) * st2 + t] : cd{0.0, 0.0};
-        Bf[t] = (t < m2) ? T2[(2 * row + 1) * st2 + t] : cd{0.0, 0.0};
+        A[pidx(t)] = (t < m2) ? T2[(2 * row) * st1 + t] : cd{0.0, 0.0};
+        Bf[pidx(t)] = (t < m2) ? T2[(2 * row + 1) * st1 + t] : cd{0.0, 0.0};
       }
       __syncthreads();
-      dif_fft2<SCH_NT>(A, Bf, logF, -1, tws);
+      dif_fftn<SCH_NT>(A, Bf, 2, logF, -1, s_tw, tws);
       for (int p = tid; p < F; p += SCH_NT) {
-        const cd a1 = A[p], a2 = cmul(Bf[p], zbin(tw, logtw, p, logF));  // z * second poly
+        const cd zb = zbin(tw, logtw, p, logF);
+        const cd a1 = A[pidx(p)], a2 = cmul(Bf[pidx(p)], zb);  // z * second poly
         const cd s11 = S[p], s12 = S[F + p], s21 = S[2 * F + p], s22 = S[3 * F + p];
         const cd r1 = cfma(a2, s21, cmul(a1, s11));   // row . column 1
         const cd r2 = cfma(a2, s22, cmul(a1, s12));   // row . column 2 (shifted)
         if (root) {
-          // rho = R21 + z R22'
-          A[p] = cfma(r2, zbin(tw, logtw, p, logF), r1);
+          A[pidx(p)] = cfma(r2, zb, r1);  // rho = R21 + z R22'
         } else {
-          A[p] = r1;
-          Bf[p] = r2;
+          A[pidx(p)] = r1;
+          Bf[pidx(p)] = r2;
         }
       }
       __syncthreads();
+      dit_fftn<SCH_NT>(A, Bf, root ? 1 : 2, logF, +1, s_tw, tws);
       if (root) {
-        dit_fft<cd, SCH_NT>(A, logF, +1, tws);
-        for (int t = tid; t < N; t += SCH_NT) rho[in.off + t] = cscale(A[t], invF);
-        __syncthreads();
+        for (int t = tid; t < N; t += SCH_NT) rho[in.off + t] = cscale(A[pidx(t)], invF);
       } else {
-        dit_fft2<SCH_NT>(A, Bf, logF, +1, tws);
-        cd* R = scr + L.res[act.level] + (int64_t)act.side * 4 * L.mmax[act.level];
-        const int st = L.mmax[act.level];
         for (int t = tid; t < m; t += SCH_NT) {
-          R[(2 * row) * st + t] = cscale(A[t], invF);
-          R[(2 * row + 1) * st + t] = cscale(Bf[t], invF);
+          R[(2 * row) * st + t] = cscale(A[pidx(t)], invF);
+          R[(2 * row + 1) * st + t] = cscale(Bf[pidx(t)], invF);
         }
-        __syncthreads();
       }
+      __syncthreads();
     }
   }
   if (tid == 0) {
@@ -327,7 +620,7 @@ hipError_t launch_schur(const InstInfo* info, const int32_t* req, const SchurLay
                         const cd* tws, cd* scratch,
                         cd* rho, double* delta, double* logdet, int32_t* status, int64_t* failed,
                         int B, int Fmax, hipStream_t st) {
-  const size_t shm = 2 * (size_t)Fmax * sizeof(cd);
+  const size_t shm = 2 * (size_t)padded(Fmax) * sizeof(cd);
   (void)hipFuncSetAttribute((const void*)k_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)shm);
   hipLaunchKernelGGL(k_schur, dim3(B), dim3(SCH_NT), shm, st, info, req, lay, acts, c, tw, logtw,
