@@ -167,9 +167,10 @@ def main():
     # dominant kernel and its roofline position
     dom = max(kst.items(), key=lambda kv: kv[1]["seconds"])
     name, ks = dom
+    algo = "levinson" if args.factor == "levinson" else "schur"  # AUTO: Schur from N=256 on
     if ks["flops"] > 0:
         achieved = ks["flops"] / ks["seconds"]
-        roof = {"bound": "alu", "kernel": name, "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12,
+        roof = {"bound": "alu", "kernel": name + (f" ({algo})" if name == "factor" else ""), "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": None,
                 "avg_launch_ms": 1e3 * ks["seconds"] / max(1, ks["launches"]),
                 "algorithmic_per_launch": ks["flops"] / max(1, ks["launches"])}

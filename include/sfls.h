@@ -233,9 +233,10 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
  * sfls_set_timing(ctx, 1) brackets every kernel launch of the estimate round
  * loop with HIP events on the call's stream; per kernel the context then
  * accumulates the launch count, the summed event durations, and the
- * algorithmic work of those launches (FP64 flops of the Levinson recursion,
- * 8 N^2 per instance; HBM bytes of the streamed arrays), counted from the
- * request bits of each round.  sfls_kernel_stats copies up to `cap` entries
+ * algorithmic work of those launches (FP64 flops of the factorisation: 8 N^2
+ * per instance for Levinson, the count of the superfast recursion's leaf
+ * steps, polynomial products and transforms for Schur; HBM bytes of the
+ * streamed arrays), counted from the request bits of each round.  sfls_kernel_stats copies up to `cap` entries
  * and returns the number of kernels tracked; sfls_reset_stats zeroes them.
  * sfls_last_run returns the round / evaluation counts of the last estimate
  * and the host wall time at the end of each round (entry r = after round r,

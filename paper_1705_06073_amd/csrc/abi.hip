@@ -24,9 +24,9 @@ struct DevBuf {
   size_t n = 0;
 };
 
-enum KernelId { KID_GEN = 0, KID_LEV, KID_APPLY, KID_OMEGA, KID_GRID, KID_SELECT, KID_ACTIVE,
+enum KernelId { KID_GEN = 0, KID_FACTOR, KID_APPLY, KID_OMEGA, KID_GRID, KID_SELECT, KID_ACTIVE,
                 KID_DRIVER, KID_COUNT };
-const char* const kKernelNames[KID_COUNT] = {"toeplitz_column", "levinson", "gs_apply", "omega",
+const char* const kKernelNames[KID_COUNT] = {"toeplitz_column", "factor", "gs_apply", "omega",
                                              "grid", "select", "active", "driver"};
 
 struct sfls_ctx {
@@ -232,12 +232,39 @@ void schur_rec(SchurPlan& P, int n0, int m, int level, int side, int win, int Nr
   P.acts.push_back(SchurAct{root ? SCH_ROOT : SCH_POST, n0, m, m1, level, side, win, logF});
 }
 
+// Algorithmic FP64 flops of one superfast factorisation (complex multiply-add
+// = 8 flops, a complex transform of size F = 5 F log2 F):
+//   leaf of m steps: 2 multiply-adds per live window entry (m - s at step s)
+//     and 4 per live Theta coefficient (s + 1), i.e. 24 m (m + 1);
+//   direct merge: window 4 m1 m2, product 8 m1 m2 multiply-adds (root: 4 m1 m2);
+//   transform merge: 8 transforms + 4 F multiply-adds (window), 8 transforms +
+//   10 F (product); root product 3 transforms + 6 F.
+double schur_flops(const SchurPlan& P) {
+  double f = 0.0;
+  for (const SchurAct& a : P.acts) {
+    const double m = a.m, m1 = a.m1, m2 = a.m - a.m1, F = std::ldexp(1.0, a.logF);
+    const double tr = 5.0 * F * a.logF;
+    switch (a.type) {
+      case SCH_LEAF_ACT:
+      case SCH_ROOT_LEAF: f += 24.0 * m * (m + 1.0); break;
+      case SCH_MID: f += (a.m <= SCH_DIRECT) ? 32.0 * m1 * m2 : 8.0 * tr + 32.0 * F; break;
+      case SCH_POST: f += (a.m <= SCH_DIRECT) ? 64.0 * m1 * m2 : 8.0 * tr + 80.0 * F; break;
+      case SCH_ROOT: f += (a.m <= SCH_DIRECT) ? 32.0 * m1 * m2 : 3.0 * tr + 48.0 * F; break;
+      default: break;
+    }
+  }
+  return f;
+}
+
 // Build per-instance layouts and the action pool for a batch; returns the
-// scratch size (complex elements) and the largest FFT size.
+// scratch size (complex elements), the largest FFT size and the algorithmic
+// flops of each instance.
 void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
-                 std::vector<SchurAct>& pool, int64_t& scr_total, int& Fmax) {
+                 std::vector<SchurAct>& pool, int64_t& scr_total, int& Fmax,
+                 std::vector<double>& flops) {
   std::map<int64_t, std::pair<int64_t, SchurPlan>> byN;  // N -> (act offset, plan)
   lay.assign((size_t)B, SchurLayout{});
+  flops.assign((size_t)B, 0.0);
   pool.clear();
   scr_total = 0;
   Fmax = 64;  // the leaves use the transform buffers as 64-element scratch
@@ -252,6 +279,7 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
       it = byN.emplace(N, std::make_pair(aoff, P)).first;
     }
     const SchurPlan& P = it->second.second;
+    flops[(size_t)b] = schur_flops(P);
     SchurLayout& L = lay[(size_t)b];
     std::memset(&L, 0, sizeof L);
     L.act_off = it->second.first;
@@ -304,7 +332,8 @@ static bool use_schur(const sfls_ctx* ctx, int maxN) {
 // Upload the Schur plans of a batch when the context uses that path.
 static sfls_status prepare_schur(sfls_ctx* ctx, int64_t B, const int64_t* n, int maxN,
                                  hipStream_t st, const char* tag, SchurLayout** dlay,
-                                 SchurAct** dacts, cd** sscr, int* Fmax) {
+                                 SchurAct** dacts, cd** sscr, int* Fmax,
+                                 std::vector<double>* flops = nullptr) {
   *dlay = nullptr;
   *dacts = nullptr;
   *sscr = nullptr;
@@ -312,8 +341,10 @@ static sfls_status prepare_schur(sfls_ctx* ctx, int64_t B, const int64_t* n, int
   if (!use_schur(ctx, maxN)) return SFLS_OK;
   std::vector<SchurLayout> lay;
   std::vector<SchurAct> pool;
+  std::vector<double> fl;
   int64_t tot = 0;
-  schur_plans(B, n, lay, pool, tot, *Fmax);
+  schur_plans(B, n, lay, pool, tot, *Fmax, fl);
+  if (flops) *flops = fl;
   if (pool.empty()) pool.push_back(SchurAct{});
   sfls_status s;
   std::string a = std::string(tag) + "_slay", b = std::string(tag) + "_sact";
@@ -814,7 +845,9 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   SchurAct* sacts;
   cd* sscr;
   int sFmax;
-  if ((s = prepare_schur(ctx, B, n, sz.maxN, st, "e", &slay, &sacts, &sscr, &sFmax)) != SFLS_OK)
+  std::vector<double> sflops;
+  if ((s = prepare_schur(ctx, B, n, sz.maxN, st, "e", &slay, &sacts, &sscr, &sFmax, &sflops)) !=
+      SFLS_OK)
     return s;
   const int prec = p.precision;
   const void* tw = prec == SFLS_FP64 ? (const void*)ctx->tws64 : (const void*)ctx->tws32;
@@ -866,8 +899,8 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
       const double N = (double)n[b];
       ++nact;
       // algorithmic work per evaluation (per-instance figures of the design)
-      kflops[KID_LEV] += 8.0 * N * N;
-      kbytes[KID_LEV] += 40.0 * N;                       // c in, rho and delta out
+      kflops[KID_FACTOR] += slay ? sflops[(size_t)b] : 8.0 * N * N;  // Schur or Levinson
+      kbytes[KID_FACTOR] += 40.0 * N;                       // c in, rho and delta out
       kbytes[KID_APPLY] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * N + 32.0 * N;  // y, rho in; w out
       if (rq & REQ_GRID) {
         ++ngrid;
@@ -884,11 +917,11 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
     HIP_TRY(launch_toeplitz_column(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, c, (int)B,
                                    sz.maxN, st));
     HIP_TRY(tstop(KID_GEN));
-    HIP_TRY(tstart(KID_LEV));
+    HIP_TRY(tstart(KID_FACTOR));
     if ((s = run_factor(ctx, B, n, dinfo, P.req, c, rho, delta, logdet, lev_status, failed,
                         sz.maxN, st, slay, sacts, sscr, sFmax)) != SFLS_OK)
       return s;
-    HIP_TRY(tstop(KID_LEV));
+    HIP_TRY(tstop(KID_FACTOR));
     HIP_TRY(tstart(KID_APPLY));
     HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw,
                             ctx->tws64, scratch, w, yCy, ww, (int)B, sz.maxP, st));

@@ -135,49 +135,160 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
 }
 
 // ---------------------------------------------------------------------------
-// In-LDS radix-2 FFT of n = 2^logn points with NT threads.
-//   dif_fft: natural order in -> bit-reversed order out, kernel exp(sgn j 2pi kn/n)
-//   dit_fft: bit-reversed in -> natural order out, kernel exp(sgn j 2pi kn/n)
-// Twiddles come from the stage-major table tws[h + pos] = exp(-j 2 pi pos / 2h)
-// (h a power of two, pos < h), so the twiddles of one stage are contiguous.
-// No scaling.  Both end with a barrier.
+// In-LDS FFT of n = 2^logn points with NT threads: the stages of a radix-2
+// network, with up to 4 consecutive stages fused per LDS pass (a group holds
+// 2^KS elements at stride s in registers).
+//   dif: natural order in -> bit-reversed order out
+//   dit: bit-reversed in -> natural order out
+// Kernel exp(-j 2pi kn/n), or exp(+j 2pi kn/n) when conj is set.  Twiddle
+// W_{2h}^pos = tws[h + pos] (stage-major table, h a power of two, pos < h).
+// No scaling.  Buffers use the padded layout pidx (one pad slot after every
+// 16 elements) so that strided and unit-stride passes spread over all banks.
 // ---------------------------------------------------------------------------
-template <typename C, int NT>
-__device__ void dif_fft(C* x, int logn, int sgn, const C* __restrict__ tws) {
-  const int n = 1 << logn;
-  for (int lh = logn - 1; lh >= 0; --lh) {
-    const int h = 1 << lh;
-    for (int b = threadIdx.x; b < (n >> 1); b += NT) {
-      const int pos = b & (h - 1);
-      const int i = ((b >> lh) << (lh + 1)) + pos;
-      const int j = i + h;
-      C u = x[i], v = x[j];
-      C w = tws[h + pos];
-      if (sgn > 0) w.y = -w.y;
-      x[i] = cadd(u, v);
-      x[j] = cmul(csub(u, v), w);
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded(int n) { return n + (n >> 4) + 1; }
+// Twiddles of stages with 2h <= FFT_TWL may come from an LDS copy of the
+// table head (FFT_TWL entries).
+constexpr int FFT_TWL = 1024;
+
+template <int KS, typename C>
+__device__ __forceinline__ void dif_group(C* z, int g, int lh_top, const C* __restrict__ tws,
+                                          bool conj) {
+  constexpr int R = 1 << KS;
+  const int ls = lh_top - KS + 1;
+  const int s = 1 << ls;
+  const int gl = g & (s - 1);
+  const int base = gl + ((g >> ls) << (ls + KS));
+  C x[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) x[j] = z[pidx(base + j * s)];
+#pragma unroll
+  for (int t = 0; t < KS; ++t) {
+    const int hj = R >> (t + 1);
+    const int h = hj << ls;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (j & hj) continue;
+      C w = tws[h + gl + (j & (hj - 1)) * s];
+      if (conj) w.y = -w.y;
+      const C u = x[j], v = x[j + hj];
+      x[j] = cadd(u, v);
+      x[j + hj] = cmul(csub(u, v), w);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) z[pidx(base + j * s)] = x[j];
+}
+
+template <int KS, typename C>
+__device__ __forceinline__ void dit_group(C* z, int g, int lh_bot, const C* __restrict__ tws,
+                                          bool conj) {
+  constexpr int R = 1 << KS;
+  const int ls = lh_bot;
+  const int s = 1 << ls;
+  const int gl = g & (s - 1);
+  const int base = gl + ((g >> ls) << (ls + KS));
+  C x[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) x[j] = z[pidx(base + j * s)];
+#pragma unroll
+  for (int t = 0; t < KS; ++t) {
+    const int hj = 1 << t;
+    const int h = hj << ls;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (j & hj) continue;
+      C w = tws[h + gl + (j & (hj - 1)) * s];
+      if (conj) w.y = -w.y;
+      const C u = x[j], v = cmul(x[j + hj], w);
+      x[j] = cadd(u, v);
+      x[j + hj] = csub(u, v);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) z[pidx(base + j * s)] = x[j];
+}
+
+// Largest number of stages per pass for na transforms of size 2^logn: small
+// transforms use shorter groups so that more threads share a pass.
+__device__ __forceinline__ int fft_ks_max(int na, int logn) {
+  const int tot = na << logn;
+  return tot >= 2048 ? 4 : (tot >= 512 ? 3 : 2);
+}
+
+// na (1 or 2) transforms of size 2^logn over the buffers x, y (conjugate
+// kernels per buffer: cx, cy); ends with a barrier.  Twiddles of the passes
+// whose stages all have 2h <= FFT_TWL come from tl (an LDS copy of the table
+// head, or the global table itself), the others from the global table tg;
+// those are always 4-stage passes (first DIF / last DIT pass of n > FFT_TWL).
+template <int NT, typename C>
+__device__ __forceinline__ void dif_fftn(C* x, C* y, int na, int logn, bool cx, bool cy,
+                                         const C* __restrict__ tl, const C* __restrict__ tg) {
+  const int km = fft_ks_max(na, logn);
+  int lh = logn - 1;
+  while (lh >= 0) {
+    const int ks = lh + 1 < km ? lh + 1 : km;
+    const int lg = logn - ks;  // log2(groups per transform)
+    const int tot = na << lg;
+    const bool lds_tw = (2 << lh) <= FFT_TWL;
+    for (int gi = threadIdx.x; gi < tot; gi += NT) {
+      const bool second = (gi >> lg) != 0;
+      C* z = second ? y : x;
+      const bool cj = second ? cy : cx;
+      const int g = gi & ((1 << lg) - 1);
+      if (!lds_tw) {
+        dif_group<4>(z, g, lh, tg, cj);
+        continue;
+      }
+      switch (ks) {
+        case 4: dif_group<4>(z, g, lh, tl, cj); break;
+        case 3: dif_group<3>(z, g, lh, tl, cj); break;
+        case 2: dif_group<2>(z, g, lh, tl, cj); break;
+        default: dif_group<1>(z, g, lh, tl, cj); break;
+      }
     }
     __syncthreads();
+    lh -= ks;
   }
 }
 
-template <typename C, int NT>
-__device__ void dit_fft(C* x, int logn, int sgn, const C* __restrict__ tws) {
-  const int n = 1 << logn;
-  for (int lh = 0; lh < logn; ++lh) {
-    const int h = 1 << lh;
-    for (int b = threadIdx.x; b < (n >> 1); b += NT) {
-      const int pos = b & (h - 1);
-      const int i = ((b >> lh) << (lh + 1)) + pos;
-      const int j = i + h;
-      C w = tws[h + pos];
-      if (sgn > 0) w.y = -w.y;
-      C u = x[i], v = cmul(x[j], w);
-      x[i] = cadd(u, v);
-      x[j] = csub(u, v);
+template <int NT, typename C>
+__device__ __forceinline__ void dit_fftn(C* x, C* y, int na, int logn, bool cx, bool cy,
+                                         const C* __restrict__ tl, const C* __restrict__ tg) {
+  const int km = fft_ks_max(na, logn);
+  const int rem = logn % km;
+  int lb = 0;
+  while (lb < logn) {
+    // the shorter pass first, so that the last (largest-h) pass has km stages
+    const int ks = (lb == 0 && rem) ? rem : km;
+    const int lg = logn - ks;
+    const int tot = na << lg;
+    const bool lds_tw = (2 << (lb + ks - 1)) <= FFT_TWL;
+    for (int gi = threadIdx.x; gi < tot; gi += NT) {
+      const bool second = (gi >> lg) != 0;
+      C* z = second ? y : x;
+      const bool cj = second ? cy : cx;
+      const int g = gi & ((1 << lg) - 1);
+      if (!lds_tw) {
+        dit_group<4>(z, g, lb, tg, cj);
+        continue;
+      }
+      switch (ks) {
+        case 4: dit_group<4>(z, g, lb, tl, cj); break;
+        case 3: dit_group<3>(z, g, lb, tl, cj); break;
+        case 2: dit_group<2>(z, g, lb, tl, cj); break;
+        default: dit_group<1>(z, g, lb, tl, cj); break;
+      }
     }
     __syncthreads();
+    lb += ks;
   }
+}
+
+// Copy the head of the stage-major twiddle table to LDS (caller syncs).
+template <int NT, typename C>
+__device__ __forceinline__ void load_tw_head(C* tl, const C* __restrict__ tg) {
+  for (int t = threadIdx.x; t < FFT_TWL; t += NT) tl[t] = tg[t];
 }
 
 __device__ __forceinline__ int bitrev(int v, int logn) {

@@ -32,8 +32,8 @@ template <> __device__ __forceinline__ cd load_y<cf>(const cf* y, int64_t i) { r
 //   v2 = T0 v1     = (rho * v1)_{i-1}
 //   w  = (u2 - v2) / delta_{N-1}                       (eq. gohberg-semencul)
 // All convolutions are length-P circular ones (P >= 2N-1, no wrap into the
-// kept indices).  Spectra are kept in bit-reversed order (DIF forward, DIT
-// inverse), and the spectra of the reversed / conjugated rho are read off
+// kept indices), transformed in LDS (padded layout).  Spectra are kept in
+// bit-reversed order (DIF forward, DIT inverse), and the spectra of the reversed / conjugated rho are read off
 // A = FFT(rho) at the negated frequency:
 //   FFT(rho~)(f) = W^{f(N-1)} A(-f),  FFT(conj rho)(f) = conj A(-f),
 //   FFT(conj rho~)(f) = W^{f(N-1)} conj A(f),  delay by one: W^f.
@@ -56,7 +56,9 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
   const int N = in.N, P = in.P, logP = in.logP;
   extern __shared__ cd lds[];
   __shared__ double red[2 * (CONV_NT / 64)];
+  __shared__ cd s_tw[FFT_TWL];
   const int tid = threadIdx.x;
+  load_tw_head<CONV_NT>(s_tw, tws);
   const cd* rb = rho + in.off;
   const YT* yb = y + in.off;
   cd* A = scratch + in.poff;
@@ -66,61 +68,61 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
   const double invP = 1.0 / (double)P;
 
   // (1) A = FFT(rho)
-  for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? rb[t] : cd{0.0, 0.0};
+  for (int t = tid; t < P; t += CONV_NT) lds[pidx(t)] = (t < N) ? rb[t] : cd{0.0, 0.0};
   __syncthreads();
-  dif_fft<cd, CONV_NT>(lds, logP, -1, tws);
-  for (int t = tid; t < P; t += CONV_NT) A[t] = lds[t];
+  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+  for (int t = tid; t < P; t += CONV_NT) A[t] = lds[pidx(t)];
   // (2) Y = FFT(y^)
-  for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? load_y(yb, N - 1 - t) : cd{0.0, 0.0};
+  for (int t = tid; t < P; t += CONV_NT) lds[pidx(t)] = (t < N) ? load_y(yb, N - 1 - t) : cd{0.0, 0.0};
   __syncthreads();
-  dif_fft<cd, CONV_NT>(lds, logP, -1, tws);
-  for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[t];
+  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+  for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[pidx(t)];
   __syncthreads();
   // (3) u1 from FFT(rho~) . Y
   for (int p = tid; p < P; p += CONV_NT) {
     const int f = bitrev(p, logP);
     const int pm = bitrev((P - f) & (P - 1), logP);
-    lds[p] = cmul(cmul(tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), A[pm]), Y[p]);
+    lds[pidx(p)] = cmul(cmul(tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), A[pm]), Y[p]);
   }
   __syncthreads();
-  dit_fft<cd, CONV_NT>(lds, logP, +1, tws);
-  for (int i = tid; i < N; i += CONV_NT) X1[i] = cscale(lds[N - 1 - i], invP);
+  dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
+  for (int i = tid; i < N; i += CONV_NT) X1[i] = cscale(lds[pidx(N - 1 - i)], invP);
   __syncthreads();
   // (4) v1 from conj(A(-f)) . Y
   for (int p = tid; p < P; p += CONV_NT) {
     const int f = bitrev(p, logP);
     const int pm = bitrev((P - f) & (P - 1), logP);
-    lds[p] = cmul(cconj(A[pm]), Y[p]);
+    lds[pidx(p)] = cmul(cconj(A[pm]), Y[p]);
   }
   __syncthreads();
-  dit_fft<cd, CONV_NT>(lds, logP, +1, tws);
+  dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
   for (int i = tid; i < N; i += CONV_NT)
-    X2[i] = (i <= N - 2) ? cscale(lds[N - 2 - i], invP) : cd{0.0, 0.0};
+    X2[i] = (i <= N - 2) ? cscale(lds[pidx(N - 2 - i)], invP) : cd{0.0, 0.0};
   __syncthreads();
   // (5) U = FFT(u1) -> Y
-  for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? X1[t] : cd{0.0, 0.0};
+  for (int t = tid; t < P; t += CONV_NT) lds[pidx(t)] = (t < N) ? X1[t] : cd{0.0, 0.0};
   __syncthreads();
-  dif_fft<cd, CONV_NT>(lds, logP, -1, tws);
-  for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[t];
+  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+  for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[pidx(t)];
   __syncthreads();
   // (6) V = FFT(v1), kept in LDS
-  for (int t = tid; t < P; t += CONV_NT) lds[t] = (t < N) ? X2[t] : cd{0.0, 0.0};
+  for (int t = tid; t < P; t += CONV_NT) lds[pidx(t)] = (t < N) ? X2[t] : cd{0.0, 0.0};
   __syncthreads();
-  dif_fft<cd, CONV_NT>(lds, logP, -1, tws);
+  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
   // (7) W = FFT(conj rho~) U - W^f A V
   for (int p = tid; p < P; p += CONV_NT) {
     const int f = bitrev(p, logP);
     const cd a = A[p];
     const cd t1 = cmul(cmul(tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), cconj(a)), Y[p]);
-    const cd t2 = cmul(cmul(tw_pow(tw, logtw, f, logP), a), lds[p]);
-    lds[p] = csub(t1, t2);
+    const cd t2 = cmul(cmul(tw_pow(tw, logtw, f, logP), a), lds[pidx(p)]);
+    lds[pidx(p)] = csub(t1, t2);
   }
   __syncthreads();
-  dit_fft<cd, CONV_NT>(lds, logP, +1, tws);
+  dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
   const double sc = invP / delta[in.off + N - 1];
   double acc[2] = {0.0, 0.0};
   for (int i = tid; i < N; i += CONV_NT) {
-    const cd wi = cscale(lds[i], sc);
+    const cd wi = cscale(lds[pidx(i)], sc);
     w[in.off + i] = wi;
     const cd yi = load_y(yb, i);
     acc[0] += fma(yi.x, wi.x, yi.y * wi.y);  // Re(conj(y) w)
@@ -162,13 +164,11 @@ __global__ __launch_bounds__(CONV_NT) void k_omega(const InstInfo* __restrict__ 
   const InstInfo in = info[bi];
   const int N = in.N, P = in.P, logP = in.logP;
   extern __shared__ cd lds[];
+  __shared__ cd s_tw[FFT_TWL];
   const int tid = threadIdx.x;
+  load_tw_head<CONV_NT>(s_tw, tws);
   const cd* rb = rho + in.off;
-  cd* G[4];
-  G[0] = scratch + in.poff;
-  G[1] = G[0] + P;
-  G[2] = G[1] + P;
-  G[3] = G[2] + P;
+  cd* G0 = scratch + in.poff;  // G_a at G0 + a P
   const int amax = (which & ~1) ? 3 : 1;
   const double cN = 0.5 * (double)(N - 1);
   for (int a = have_g0 ? 1 : 0; a <= amax; ++a) {
@@ -180,46 +180,49 @@ __global__ __launch_bounds__(CONV_NT) void k_omega(const InstInfo* __restrict__ 
         for (int e = 0; e < a; ++e) m *= x;
         v = cscale(rb[t], m);
       }
-      lds[t] = v;
+      lds[pidx(t)] = v;
     }
     __syncthreads();
-    dif_fft<cd, CONV_NT>(lds, logP, -1, tws);
-    for (int t = tid; t < P; t += CONV_NT) G[a][t] = lds[t];
+    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+    for (int t = tid; t < P; t += CONV_NT) G0[(int64_t)a * P + t] = lds[pidx(t)];
     __syncthreads();
   }
-  const SepCoef cf = coef[bi];
+  const SepCoef* cfp = coef + bi;
   const double scale = 1.0 / ((double)P * delta[in.off + N - 1]);
-  cd* outs[4] = {o_s, o_t, o_v, o_x};
   for (int qk = 0; qk < 4; ++qk) {
     if (!(which & (1 << qk))) continue;
-    const double* C = cf.c[qk];
+    const double* C = cfp->c[qk];
     const int am = (qk == 0) ? 1 : 3;
+    cd* outq = qk == 0 ? o_s : (qk == 1 ? o_t : (qk == 2 ? o_v : o_x));
     for (int p = tid; p < P; p += CONV_NT) {
       cd g[4];
-      for (int a = 0; a <= am; ++a) g[a] = G[a][p];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) g[a] = (a <= am) ? G0[(int64_t)a * P + p] : cd{0.0, 0.0};
       cd acc{0.0, 0.0};
-      for (int a = 0; a <= am; ++a)
-        for (int b2 = 0; b2 <= am; ++b2) {
-          const double cab = C[a * 4 + b2];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b2 = 0; b2 < 4; ++b2) {
+          const double cab = (a <= am && b2 <= am) ? C[a * 4 + b2] : 0.0;
           if (cab != 0.0) {
             const cd pr = cmulc(g[b2], g[a]);  // G_b conj(G_a)
             acc.x = fma(cab, pr.x, acc.x);
             acc.y = fma(cab, pr.y, acc.y);
           }
         }
-      lds[p] = acc;
+      lds[pidx(p)] = acc;
     }
     __syncthreads();
-    dit_fft<cd, CONV_NT>(lds, logP, +1, tws);
+    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
     for (int t = tid; t < P; t += CONV_NT) {
       // lag i = t for t < N, i = t - P for t > P - N
       const bool pos = t < N, neg = t > P - N;
       if (!pos && !neg) continue;
-      const cd om = cscale(cconj(lds[t]), scale);
+      const cd om = cscale(cconj(lds[pidx(t)]), scale);
       if (qk == 0 && oms) oms[in.poff + t] = om;
-      if (outs[qk]) {
+      if (outq) {
         const int i = pos ? t : t - P;
-        outs[qk][in.ooff + i + N - 1] = om;
+        outq[in.ooff + i + N - 1] = om;
       }
     }
     if (qk == 0 && oms) {
@@ -234,7 +237,7 @@ hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void*
                            const cd* rho, const double* delta, const cd* tw, int logtw,
                            const cd* tws, cd* scratch, cd* w, double* yCy, double* ww, int B, int maxP,
                            hipStream_t st) {
-  const size_t shm = (size_t)maxP * sizeof(cd);
+  const size_t shm = (size_t)padded(maxP) * sizeof(cd);
   if (ydtype == 1) {
     (void)hipFuncSetAttribute((const void*)k_gs_apply<cd>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)shm);
@@ -253,7 +256,7 @@ hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
                         const double* delta, const SepCoef* coef, const cd* tws,
                         cd* scratch, int which, int have_g0, cd* oms, cd* o_s, cd* o_t,
                         cd* o_v, cd* o_x, int B, int maxP, hipStream_t st) {
-  const size_t shm = (size_t)maxP * sizeof(cd);
+  const size_t shm = (size_t)padded(maxP) * sizeof(cd);
   (void)hipFuncSetAttribute((const void*)k_omega, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL(k_omega, dim3(B), dim3(CONV_NT), shm, st, info, req, rho, delta, coef, tws,
                      scratch, which, have_g0, oms, o_s, o_t, o_v, o_x);

@@ -31,7 +31,7 @@ __device__ __forceinline__ R delta_L_point(R q2, R s, R gb, R odds) {
 // of two):  with l = R f + r,
 //   q^G_l = sum_n [w_n e^{-j2pi n r/L}] e^{-j2pi n f/M}           (M-point DFT)
 //   s^G_l = sum_m [sum_{i = m mod M} omega_s(i) e^{j2pi i r/L}] e^{+j2pi m f/M}
-// so each workgroup (instance, r) runs two M-point FFTs in LDS.  The
+// so each workgroup (instance, r) runs two M-point FFTs in LDS (padded layout).  The
 // residue twiddles come from exact fractions (n r mod L)/L.  Outputs per
 // point: optional q^G, s^G, Delta L; always a per-workgroup argmin
 // (lowest l on ties).  Blocks of one instance sit on one XCD:
@@ -66,11 +66,13 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
   }
   const int N = in.N, M = in.M, logM = in.logM, L = in.L, P = in.P;
   extern __shared__ unsigned char smem[];
-  C* lq = reinterpret_cast<C*>(smem);
-  C* ls = lq + M;
+  C* lq = reinterpret_cast<C*>(smem);  // padded layout
+  C* ls = lq + padded(M);
+  __shared__ C s_tw[FFT_TWL];
   __shared__ double rv[GRID_NT / 64];
   __shared__ int64_t ri[GRID_NT / 64];
   const int tid = threadIdx.x;
+  load_tw_head<GRID_NT>(s_tw, tw);
   const cd* wb = w + in.off;
   const cd* ob = oms + in.poff;
   for (int m = tid; m < M; m += GRID_NT) {
@@ -82,12 +84,11 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
       const int64_t ph = (((int64_t)i2 % L + L) % L) * r % L;
       sv = cfma(ob[(i2 + P) & (P - 1)], cis_frac(ph, L), sv);
     }
-    lq[m] = C{(decltype(C{}.x))qv.x, (decltype(C{}.x))qv.y};
-    ls[m] = C{(decltype(C{}.x))sv.x, (decltype(C{}.x))sv.y};
+    lq[pidx(m)] = C{(decltype(C{}.x))qv.x, (decltype(C{}.x))qv.y};
+    ls[pidx(m)] = C{(decltype(C{}.x))sv.x, (decltype(C{}.x))sv.y};
   }
   __syncthreads();
-  dif_fft<C, GRID_NT>(lq, logM, -1, tw);
-  dif_fft<C, GRID_NT>(ls, logM, +1, tw);
+  dif_fftn<GRID_NT>(lq, ls, 2, logM, false, true, (const C*)s_tw, tw);
   const R gb = (R)gbar[bi];
   const double z = zeta[bi];
   const R odds = (R)((1.0 - z) / z);
@@ -96,8 +97,8 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
   for (int p = tid; p < M; p += GRID_NT) {
     const int f = bitrev(p, logM);
     const int64_t l = (int64_t)f * in.R + r;
-    const C qv = lq[p];
-    const R sv = ls[p].x;
+    const C qv = lq[pidx(p)];
+    const R sv = ls[pidx(p)].x;
     const R q2 = cabs2(qv);
     R d = delta_L_point<R>(q2, sv, gb, odds);
     if (d != d) d = rinf<R>();
@@ -252,14 +253,14 @@ hipError_t launch_grid(int prec, const InstInfo* info, const int32_t* req, const
   const int nslots = ((B + 7) / 8) * Rmax;  // per XCD
   dim3 grid(8 * nslots);
   if (prec == 0) {
-    const size_t shm = 2 * (size_t)maxM * sizeof(cd);
+    const size_t shm = 2 * (size_t)padded(maxM) * sizeof(cd);
     (void)hipFuncSetAttribute((const void*)k_grid<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)shm);
     hipLaunchKernelGGL(k_grid<double>, grid, dim3(GRID_NT), shm, st, info, req, w, oms, gbar,
                        zeta, (const cd*)tw, logtw, Rmax, B, (cd*)qG, (double*)sG, (double*)dL,
                        part_val, part_idx);
   } else {
-    const size_t shm = 2 * (size_t)maxM * sizeof(cf);
+    const size_t shm = 2 * (size_t)padded(maxM) * sizeof(cf);
     (void)hipFuncSetAttribute((const void*)k_grid<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)shm);
     hipLaunchKernelGGL(k_grid<float>, grid, dim3(GRID_NT), shm, st, info, req, w, oms, gbar,

@@ -49,155 +49,12 @@ __device__ __forceinline__ double shl1d(double v) {
 __device__ __forceinline__ cd shl1c(cd v) { return cd{shl1d(v.x), shl1d(v.y)}; }
 __device__ __forceinline__ cd readlane_c(cd v, int l) { return cd{readlane_f64(v.x, l), readlane_f64(v.y, l)}; }
 
-// LDS layout of a transform buffer: one 16-byte pad slot after every 16
-// elements, so that the strided and the unit-stride passes below both spread
-// over all banks.
-__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int padded(int n) { return n + (n >> 4) + 1; }
-
-// Radix-2 transforms in the same stage order as a plain radix-2 network, with
-// KS consecutive stages fused per LDS pass: a group holds 2^KS elements at
-// stride s in registers.  Twiddle W_{2h}^pos = tws[h + pos] (stage-major
-// table); sgn > 0 uses the conjugate.  DIF: natural in, bit-reversed out;
-// DIT: bit-reversed in, natural out.
-template <int KS>
-__device__ __forceinline__ void dif_group(cd* z, int g, int lh_top, const cd* __restrict__ tws,
-                                          bool conj) {
-  constexpr int R = 1 << KS;
-  const int ls = lh_top - KS + 1;
-  const int s = 1 << ls;
-  const int gl = g & (s - 1);
-  const int base = gl + ((g >> ls) << (ls + KS));
-  cd x[R];
-#pragma unroll
-  for (int j = 0; j < R; ++j) x[j] = z[pidx(base + j * s)];
-#pragma unroll
-  for (int t = 0; t < KS; ++t) {
-    const int hj = R >> (t + 1);
-    const int h = hj << ls;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      if (j & hj) continue;
-      cd w = tws[h + gl + (j & (hj - 1)) * s];
-      if (conj) w.y = -w.y;
-      const cd u = x[j], v = x[j + hj];
-      x[j] = cadd(u, v);
-      x[j + hj] = cmul(csub(u, v), w);
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < R; ++j) z[pidx(base + j * s)] = x[j];
-}
-
-template <int KS>
-__device__ __forceinline__ void dit_group(cd* z, int g, int lh_bot, const cd* __restrict__ tws,
-                                          bool conj) {
-  constexpr int R = 1 << KS;
-  const int ls = lh_bot;
-  const int s = 1 << ls;
-  const int gl = g & (s - 1);
-  const int base = gl + ((g >> ls) << (ls + KS));
-  cd x[R];
-#pragma unroll
-  for (int j = 0; j < R; ++j) x[j] = z[pidx(base + j * s)];
-#pragma unroll
-  for (int t = 0; t < KS; ++t) {
-    const int hj = 1 << t;
-    const int h = hj << ls;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      if (j & hj) continue;
-      cd w = tws[h + gl + (j & (hj - 1)) * s];
-      if (conj) w.y = -w.y;
-      const cd u = x[j], v = cmul(x[j + hj], w);
-      x[j] = cadd(u, v);
-      x[j + hj] = csub(u, v);
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < R; ++j) z[pidx(base + j * s)] = x[j];
-}
-
-// Largest radix (stages per pass) for na transforms of size 2^logn: small
-// transforms use shorter groups so that more threads share a pass.
-__device__ __forceinline__ int ks_max(int na, int logn) {
-  const int tot = na << logn;
-  return tot >= 2048 ? 4 : (tot >= 512 ? 3 : 2);
-}
-
-// na (1 or 2) transforms of size 2^logn over the buffers x, y; ends with a
-// barrier.  Twiddles of the stages with 2h <= SCH_TWL come from the LDS copy tl,
-// the others (first DIF pass / last DIT pass of sizes > SCH_TWL, always 4
-// stages) from the global table tg.
-template <int NT>
-__device__ __forceinline__ void dif_fftn(cd* x, cd* y, int na, int logn, int sgn,
-                                         const cd* __restrict__ tl, const cd* __restrict__ tg) {
-  const bool conj = sgn > 0;
-  const int km = ks_max(na, logn);
-  int lh = logn - 1;
-  while (lh >= 0) {
-    const int ks = lh + 1 < km ? lh + 1 : km;
-    const int lg = logn - ks;  // log2(groups per transform)
-    const int tot = na << lg;
-    const bool lds_tw = (2 << lh) <= SCH_TWL;
-    for (int gi = threadIdx.x; gi < tot; gi += NT) {
-      cd* z = (gi >> lg) ? y : x;
-      const int g = gi & ((1 << lg) - 1);
-      if (!lds_tw) {
-        dif_group<4>(z, g, lh, tg, conj);
-        continue;
-      }
-      switch (ks) {
-        case 4: dif_group<4>(z, g, lh, tl, conj); break;
-        case 3: dif_group<3>(z, g, lh, tl, conj); break;
-        case 2: dif_group<2>(z, g, lh, tl, conj); break;
-        default: dif_group<1>(z, g, lh, tl, conj); break;
-      }
-    }
-    __syncthreads();
-    lh -= ks;
-  }
-}
-
-template <int NT>
-__device__ __forceinline__ void dit_fftn(cd* x, cd* y, int na, int logn, int sgn,
-                                         const cd* __restrict__ tl, const cd* __restrict__ tg) {
-  const bool conj = sgn > 0;
-  const int km = ks_max(na, logn);
-  int lb = 0;
-  while (lb < logn) {
-    // the shorter pass first, so that the last (largest-h) pass has km stages
-    const int rem = logn % km;
-    const int ks = (lb == 0 && rem) ? rem : km;
-    const int lg = logn - ks;
-    const int tot = na << lg;
-    const bool lds_tw = (2 << (lb + ks - 1)) <= SCH_TWL;
-    for (int gi = threadIdx.x; gi < tot; gi += NT) {
-      cd* z = (gi >> lg) ? y : x;
-      const int g = gi & ((1 << lg) - 1);
-      if (!lds_tw) {
-        dit_group<4>(z, g, lb, tg, conj);
-        continue;
-      }
-      switch (ks) {
-        case 4: dit_group<4>(z, g, lb, tl, conj); break;
-        case 3: dit_group<3>(z, g, lb, tl, conj); break;
-        case 2: dit_group<2>(z, g, lb, tl, conj); break;
-        default: dit_group<1>(z, g, lb, tl, conj); break;
-      }
-    }
-    __syncthreads();
-    lb += ks;
-  }
-}
-
 // Sliding-window block of RB outputs t0..t0+RB-1 of two convolutions,
 //   acc[i] += sum_{j < J} a[j] x[t0+i-j] + b[j] y[t0+i-j],
 // over LDS operands; x and y must be readable (zero where outside the
-// polynomials) on [t0 - J - RB + 1, t0 + RB).
-// x and y are given as a row base and the padded index of the origin; element
-// i of a padded row is stored at skew(i) = i + i / RB, so that lanes at output
-// stride RB read distinct banks.
+// polynomials) on [t0 - J - RB + 1, t0 + RB).  They are given as a row base
+// and the padded index of the origin; element i of a padded row is stored at
+// skew(i) = i + i / RB, so that lanes at output stride RB read distinct banks.
 template <int RB>
 __device__ __forceinline__ int skew(int i) {
   return RB > 1 ? i + (i >> (RB == 2 ? 1 : 2)) : i;
@@ -342,11 +199,11 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
   cd* Bf = lds + padded(L.Fmax);
   __shared__ double s_logdet;
   __shared__ int s_fail;
-  __shared__ cd s_tw[SCH_TWL];  // head of the stage-major twiddle table
+  __shared__ cd s_tw[FFT_TWL];  // head of the stage-major twiddle table
   const cd* cb = c + in.off;
   cd* scr = scratch + L.scr_off;
   double* dl = delta_out ? delta_out + in.off : nullptr;
-  for (int t = tid; t < SCH_TWL; t += SCH_NT) s_tw[t] = tws[t];
+  load_tw_head<SCH_NT>(s_tw, tws);
   if (tid == 0) {
     s_logdet = log(cb[0].x);
     s_fail = (cb[0].x > 0.0 && isfinite(cb[0].x)) ? -1 : 0;
@@ -546,7 +403,7 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
           Bf[pidx(t)] = t < lim ? pb[t] : cd{0.0, 0.0};
         }
         __syncthreads();
-        dif_fftn<SCH_NT>(A, Bf, 2, logF, -1, s_tw, tws);
+        dif_fftn<SCH_NT>(A, Bf, 2, logF, false, false, s_tw, tws);
         if (job < 2) {
           for (int t = tid; t < F; t += SCH_NT) {
             S[(int64_t)(2 * job) * F + t] = A[pidx(t)];
@@ -562,7 +419,7 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
         Bf[pidx(p)] = cfma(s22, fv, cmul(s21, fu));
       }
       __syncthreads();
-      dit_fftn<SCH_NT>(A, Bf, 2, logF, +1, s_tw, tws);
+      dit_fftn<SCH_NT>(A, Bf, 2, logF, true, true, s_tw, tws);
       // right child's window
       cd* W2 = scr + L.win[cl];
       const int stw = L.mmax[cl];
@@ -580,7 +437,7 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
         Bf[pidx(t)] = (t < m2) ? T2[(2 * row + 1) * st1 + t] : cd{0.0, 0.0};
       }
       __syncthreads();
-      dif_fftn<SCH_NT>(A, Bf, 2, logF, -1, s_tw, tws);
+      dif_fftn<SCH_NT>(A, Bf, 2, logF, false, false, s_tw, tws);
       for (int p = tid; p < F; p += SCH_NT) {
         const cd zb = zbin(tw, logtw, p, logF);
         const cd a1 = A[pidx(p)], a2 = cmul(Bf[pidx(p)], zb);  // z * second poly
@@ -595,7 +452,7 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
         }
       }
       __syncthreads();
-      dit_fftn<SCH_NT>(A, Bf, root ? 1 : 2, logF, +1, s_tw, tws);
+      dit_fftn<SCH_NT>(A, Bf, root ? 1 : 2, logF, true, true, s_tw, tws);
       if (root) {
         for (int t = tid; t < N; t += SCH_NT) rho[in.off + t] = cscale(A[pidx(t)], invF);
       } else {

@@ -45,8 +45,7 @@ constexpr int SCH_MAXL = 16;
 // sums, no transforms; the transform buffers must then hold 8m + 256 elements
 // each); larger ones use FFTs of size >= m.
 constexpr int SCH_DIRECT = 128;
-// Twiddles of transform stages with 2h <= SCH_TWL are read from an LDS copy.
-constexpr int SCH_TWL = 1024;
+
 // Per-instance layout of the recursion's scratch (offsets in complex elements).
 struct SchurLayout {
   int64_t scr_off;
