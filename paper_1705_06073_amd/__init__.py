@@ -79,6 +79,9 @@ def lib() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
                            "(python -m paper_1705_06073_amd.build); there is no fallback")
+    # torch ships its own HIP runtime under the same soname; load it first so
+    # that the process has one runtime whichever module is imported first.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     i32, i64, st = ctypes.c_int32, ctypes.c_int64, ctypes.c_int
     L.sfls_params_default.argtypes = [ctypes.POINTER(sfls_params)]

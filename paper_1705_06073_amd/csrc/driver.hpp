@@ -152,16 +152,25 @@ struct Driver {
 
   // gradient and replaced diagonal Hessian from the evaluation results
   // (eqs. derivative, derivative2; replacements (50N)^2 and gamma^-2)
-  SFLS_HD void derivs(const double* gam, double* g, double* h) const {
+  SFLS_HD void derivs(const double* __restrict__ gam, double* __restrict__ g,
+                      double* __restrict__ h) const {
     const int K = S.K;
+    const double* __restrict__ eq = A.ev_q;
+    const double* __restrict__ er = A.ev_r;
+    const double* __restrict__ eu = A.ev_u;
+    const double* __restrict__ es = A.ev_s;
+    const double* __restrict__ et = A.ev_t;
+    const double* __restrict__ ev = A.ev_v;
+    const double* __restrict__ ex = A.ev_x;
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
-      const double qr = A.ev_q[2 * k], qi = A.ev_q[2 * k + 1];
-      const double rr = A.ev_r[2 * k], ri = A.ev_r[2 * k + 1];
-      const double ur = A.ev_u[2 * k], ui = A.ev_u[2 * k + 1];
-      const double s = A.ev_s[2 * k];
-      const double tr = A.ev_t[2 * k], ti = A.ev_t[2 * k + 1];
-      const double vr = A.ev_v[2 * k];
-      const double xr = A.ev_x[2 * k], xi = A.ev_x[2 * k + 1];
+      const double qr = eq[2 * k], qi = eq[2 * k + 1];
+      const double rr = er[2 * k], ri = er[2 * k + 1];
+      const double ur = eu[2 * k], ui = eu[2 * k + 1];
+      const double s = es[2 * k];
+      const double tr = et[2 * k], ti = et[2 * k + 1];
+      const double vr = ev[2 * k];
+      const double xr = ex[2 * k], xi = ex[2 * k + 1];
       const double gk = gam[k];
       const double q2 = qr * qr + qi * qi, r2 = rr * rr + ri * ri;
       // Im(t - conj(q) r)
@@ -189,10 +198,24 @@ struct Driver {
     }
   }
 
-  SFLS_HD double dot(const double* a, const double* b, int n) const {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += a[i] * b[i];
-    return s;
+  // The loops below run in one thread over device memory: restrict-qualified
+  // locals and unrolling let the loads of several elements be in flight.
+  SFLS_HD double dot(const double* __restrict__ a, const double* __restrict__ b, int n) const {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {
+      s0 += a[i] * b[i];
+      s1 += a[i + 1] * b[i + 1];
+      s2 += a[i + 2] * b[i + 2];
+      s3 += a[i + 3] * b[i + 3];
+    }
+    for (; i < n; ++i) s0 += a[i] * b[i];
+    return (s0 + s1) + (s2 + s3);
+  }
+  // d += a * x
+  SFLS_HD static void axpy(double a, const double* __restrict__ x, double* __restrict__ d, int n) {
+#pragma unroll 8
+    for (int e = 0; e < n; ++e) d[e] += a * x[e];
   }
 
   SFLS_HD void mem_reset() { S.mem_n = 0; S.mem_head = 0; }
@@ -207,8 +230,9 @@ struct Driver {
     double sy = dot(s, y, n), ss = dot(s, s, n), yy = dot(y, y, n);
     if (!(sy > P.curv_eps * sqrt(ss) * sqrt(yy))) return;
     const int slot = S.mem_head;
-    double* ds = mem_s(slot);
-    double* dy = mem_y(slot);
+    double* __restrict__ ds = mem_s(slot);
+    double* __restrict__ dy = mem_y(slot);
+#pragma unroll 8
     for (int i = 0; i < n; ++i) { ds[i] = s[i]; dy[i] = y[i]; }
     A.rhom[slot] = 1.0 / sy;
     S.mem_head = (S.mem_head + 1) % J;
@@ -217,21 +241,22 @@ struct Driver {
 
   // two-loop recursion with H0 = diag(1/h); d = -H g.  Falls back to -g/h
   // (after a reset) when the result is not a descent direction.
-  SFLS_HD void direction(const double* g, const double* h, double* d, int n) {
+  SFLS_HD void direction(const double* __restrict__ g, const double* __restrict__ h,
+                         double* __restrict__ d, int n) {
+#pragma unroll 8
     for (int i = 0; i < n; ++i) d[i] = g[i];
     for (int i = S.mem_n - 1; i >= 0; --i) {
       const int sl = mem_slot(i);
       const double a = A.rhom[sl] * dot(mem_s(sl), d, n);
       A.am[sl] = a;
-      const double* y = mem_y(sl);
-      for (int e = 0; e < n; ++e) d[e] -= a * y[e];
+      axpy(-a, mem_y(sl), d, n);
     }
+#pragma unroll 8
     for (int e = 0; e < n; ++e) d[e] /= h[e];
     for (int i = 0; i < S.mem_n; ++i) {
       const int sl = mem_slot(i);
       const double bta = A.rhom[sl] * dot(mem_y(sl), d, n);
-      const double* s = mem_s(sl);
-      for (int e = 0; e < n; ++e) d[e] += (A.am[sl] - bta) * s[e];
+      axpy(A.am[sl] - bta, mem_s(sl), d, n);
     }
     bool ok = true;
     double gd = 0.0;
