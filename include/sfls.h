@@ -119,7 +119,10 @@ sfls_status sfls_toeplitz_column(sfls_ctx* ctx, int64_t B, const int64_t* n, con
  *     C^{-1} = delta_{N-1}^{-1} (T1^H T1 - T0 T0^H),
  *     [T0]_{ik} = rho_{i-k-1}, [T1]_{ik} = rho_{N-1+i-k}, rho_{N-1} = 1,
  * computed by the Levinson-Durbin recursion or the superfast Schur recursion
- * (sfls_set_factor).
+ * (sfls_set_factor).  The superfast result is followed by one step of
+ * iterative refinement of the last column of C^{-1} (residual by an FFT
+ * Toeplitz product, correction by the Gohberg-Semencul formula), which
+ * updates rho and delta_{N-1}; ln|C| and the other pivots are the recursion's.
  *   c      device c128 [sum n]   first columns; c_0 must be real and > 0
  *   rho    device c128 [sum n]   out: generator rho_0..rho_{N-1}
  *   delta  device f64  [sum n]   out: pivots delta_0..delta_{N-1} of C = L diag(delta) L^H

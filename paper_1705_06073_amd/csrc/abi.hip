@@ -238,9 +238,13 @@ void schur_rec(SchurPlan& P, int n0, int m, int level, int side, int win, int Nr
 //     and 4 per live Theta coefficient (s + 1), i.e. 24 m (m + 1);
 //   direct merge: window 4 m1 m2, product 8 m1 m2 multiply-adds (root: 4 m1 m2);
 //   transform merge: 8 transforms + 4 F multiply-adds (window), 8 transforms +
-//   10 F (product); root product 3 transforms + 6 F.
-double schur_flops(const SchurPlan& P) {
-  double f = 0.0;
+//   10 F (product); root product 3 transforms + 6 F;
+//   the refinement of the generator that follows.
+double schur_flops(const SchurPlan& P, int N) {
+  // refinement of the generator: 3 transforms (residual) + 7 (GS apply) of size
+  // P >= 2N - 1, plus about 12 multiply-adds per point
+  const int lp = ilog2_ceil(2 * N - 1);
+  double f = 10.0 * 5.0 * std::ldexp(1.0, lp) * lp + 96.0 * std::ldexp(1.0, lp);
   for (const SchurAct& a : P.acts) {
     const double m = a.m, m1 = a.m1, m2 = a.m - a.m1, F = std::ldexp(1.0, a.logF);
     const double tr = 5.0 * F * a.logF;
@@ -279,7 +283,7 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
       it = byN.emplace(N, std::make_pair(aoff, P)).first;
     }
     const SchurPlan& P = it->second.second;
-    flops[(size_t)b] = schur_flops(P);
+    flops[(size_t)b] = schur_flops(P, (int)N);
     SchurLayout& L = lay[(size_t)b];
     std::memset(&L, 0, sizeof L);
     L.act_off = it->second.first;
@@ -307,16 +311,28 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
 
 }  // namespace
 
-// Factor a batch (Levinson or superfast Schur by the context's choice).
+// Buffers of the generator refinement that follows the superfast recursion:
+// transform scratch (4 P per instance at poff) and two sample-length arrays.
+struct RefineBufs {
+  cd* scratch = nullptr;
+  cd* r = nullptr;
+  cd* dx = nullptr;
+  int maxP = 0;
+};
+
+// Factor a batch (Levinson, or superfast Schur followed by one step of
+// iterative refinement of the generator, by the context's choice).
 static sfls_status run_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const InstInfo* dinfo,
                               const int32_t* req, const cd* c, cd* rho, double* delta,
                               double* logdet, int32_t* status, int64_t* failed, int maxN,
                               hipStream_t st, const SchurLayout* dlay, const SchurAct* dacts,
-                              cd* sscr, int Fmax) {
+                              cd* sscr, int Fmax, const RefineBufs& rf) {
   if (dlay) {
     HIP_TRY(launch_schur(dinfo, req, dlay, dacts, c, ctx->tw64, ctx->logtw, ctx->tws64, sscr, rho,
                          delta,
                          logdet, status, failed, (int)B, Fmax, st));
+    HIP_TRY(launch_gen_refine(dinfo, req, status, c, rho, delta, ctx->tw64, ctx->logtw,
+                              ctx->tws64, rf.scratch, rf.r, rf.dx, (int)B, rf.maxP, st));
   } else {
     HIP_TRY(launch_levinson(dinfo, req, c, rho, delta, logdet, status, failed, (int)B, maxN, st));
   }
@@ -540,8 +556,19 @@ sfls_status sfls_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_
   int Fmax;
   if ((s = prepare_schur(ctx, B, n, sz.maxN, st, "f", &dlay, &dacts, &sscr, &Fmax)) != SFLS_OK)
     return s;
+  RefineBufs rf;
+  if (dlay) {
+    // the refinement needs the pivots and the status even when not requested
+    const int64_t ntot = info.back().off + info.back().N;
+    if (!delta && (s = wsT(ctx, "f_delta", (size_t)ntot, &delta)) != SFLS_OK) return s;
+    if (!status && (s = wsT(ctx, "f_status", (size_t)B, &status)) != SFLS_OK) return s;
+    if ((s = wsT(ctx, "scratch", (size_t)pt, &rf.scratch)) != SFLS_OK) return s;
+    if ((s = wsT(ctx, "f_r", (size_t)ntot, &rf.r)) != SFLS_OK) return s;
+    if ((s = wsT(ctx, "f_dx", (size_t)ntot, &rf.dx)) != SFLS_OK) return s;
+    rf.maxP = sz.maxP;
+  }
   return run_factor(ctx, B, n, dinfo, nullptr, (const cd*)c, (cd*)rho, delta, logdet, status,
-                    failed_step, sz.maxN, st, dlay, dacts, sscr, Fmax);
+                    failed_step, sz.maxN, st, dlay, dacts, sscr, Fmax, rf);
 }
 
 sfls_status sfls_gs_apply(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
@@ -785,6 +812,11 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   WS("e_delta", ntot, delta);
   WS("scratch", pt, scratch);
   WS("e_oms", pt, oms);
+  RefineBufs rf;
+  rf.scratch = scratch;
+  rf.maxP = sz.maxP;
+  WS("e_rf_r", ntot, rf.r);
+  WS("e_rf_dx", ntot, rf.dx);
   WS("e_logdet", B, logdet);
   WS("e_yCy", B, yCy);
   WS("e_ww", B, ww);
@@ -805,6 +837,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   WS("e_g", 2 * ktot, P.g);
   WS("e_d", 2 * ktot, P.d);
   WS("e_gt", 2 * ktot, P.gt);
+  WS("e_qsave", 2 * ktot, P.q_save);
   WS("e_Sm", (size_t)J * 2 * ktot, P.Sm);
   WS("e_Ym", (size_t)J * 2 * ktot, P.Ym);
   WS("e_rhom", (size_t)J * B, P.rhom);
@@ -891,41 +924,47 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   const int64_t max_rounds = 1000000;
   const double esz_d = (double)esz;
   for (;;) {
-    int64_t nact = 0, ngrid = 0;
+    int64_t nact = 0, ngrid = 0, nreq = 0;
     for (int k = 0; k < KID_COUNT; ++k) { launched[k] = false; kflops[k] = 0.0; kbytes[k] = 0.0; }
     for (int64_t b = 0; b < B; ++b) {
       const int32_t rq = hreq[b];
-      if (!(rq & REQ_EVAL)) continue;
+      if (!rq) continue;
+      ++nreq;
       const double N = (double)n[b];
-      ++nact;
       // algorithmic work per evaluation (per-instance figures of the design)
-      kflops[KID_FACTOR] += slay ? sflops[(size_t)b] : 8.0 * N * N;  // Schur or Levinson
-      kbytes[KID_FACTOR] += 40.0 * N;                       // c in, rho and delta out
-      kbytes[KID_APPLY] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * N + 32.0 * N;  // y, rho in; w out
+      if (rq & REQ_EVAL) {
+        ++nact;
+        kflops[KID_FACTOR] += slay ? sflops[(size_t)b] : 8.0 * N * N;  // Schur or Levinson
+        kbytes[KID_FACTOR] += 40.0 * N;                       // c in, rho and delta out
+        kbytes[KID_APPLY] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * N + 32.0 * N;  // y, rho in; w out
+      }
+      // grid stage: alone when the evaluation at the current point is in place
       if (rq & REQ_GRID) {
         ++ngrid;
         const double Lb = (double)info[(size_t)b].L;
         kbytes[KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz_d * Lb;  // w, omega_s in; Delta L out
       }
     }
-    if (nact == 0) break;
+    if (nreq == 0) break;
     if (rounds >= max_rounds) return fail(ctx, SFLS_EDEVICE, "estimate did not finish");
     ++rounds;
     ev_total += nact;
     gevals += ngrid;
-    HIP_TRY(tstart(KID_GEN));
-    HIP_TRY(launch_toeplitz_column(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, c, (int)B,
-                                   sz.maxN, st));
-    HIP_TRY(tstop(KID_GEN));
-    HIP_TRY(tstart(KID_FACTOR));
-    if ((s = run_factor(ctx, B, n, dinfo, P.req, c, rho, delta, logdet, lev_status, failed,
-                        sz.maxN, st, slay, sacts, sscr, sFmax)) != SFLS_OK)
-      return s;
-    HIP_TRY(tstop(KID_FACTOR));
-    HIP_TRY(tstart(KID_APPLY));
-    HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw,
-                            ctx->tws64, scratch, w, yCy, ww, (int)B, sz.maxP, st));
-    HIP_TRY(tstop(KID_APPLY));
+    if (nact > 0) {
+      HIP_TRY(tstart(KID_GEN));
+      HIP_TRY(launch_toeplitz_column(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, c, (int)B,
+                                     sz.maxN, st));
+      HIP_TRY(tstop(KID_GEN));
+      HIP_TRY(tstart(KID_FACTOR));
+      if ((s = run_factor(ctx, B, n, dinfo, P.req, c, rho, delta, logdet, lev_status, failed,
+                          sz.maxN, st, slay, sacts, sscr, sFmax, rf)) != SFLS_OK)
+        return s;
+      HIP_TRY(tstop(KID_FACTOR));
+      HIP_TRY(tstart(KID_APPLY));
+      HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw,
+                              ctx->tws64, scratch, w, yCy, ww, (int)B, sz.maxP, st));
+      HIP_TRY(tstop(KID_APPLY));
+    }
     if (ngrid > 0) {
       HIP_TRY(tstart(KID_OMEGA));
       HIP_TRY(launch_omega(dinfo, P.req, rho, delta, dcoef, ctx->tws64, scratch, 1, 1,

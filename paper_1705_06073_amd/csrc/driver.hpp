@@ -41,7 +41,7 @@ enum : int32_t {
 // Scalar state of one instance.
 struct DrvState {
   int32_t phase, it, inner, pit, ls_trial, K, approx_on, z_changed, cur_valid, converged,
-      cap_hit, polish, mem_n, mem_head, kstar, status, nevals, done;
+      cap_hit, polish, mem_n, mem_head, kstar, status, nevals, done, saved, pad_;
   double beta, zeta, eps_beta, yy, L_prev, f_cur, lam2, alpha, amax, gd;
 };
 
@@ -67,6 +67,7 @@ struct DrvArrays {
   double* rhom;     // [J]
   double* am;       // [J] two-loop scratch
   double* gt;       // gradient at the trial [2 kcap]
+  double* q_save;   // q at the polish's current point (complex) [2 kcap]
   // evaluation results (written by the kernels, valid for the last request)
   const double* ev_q;  // complex [kcap] interleaved
   const double* ev_r;
@@ -139,15 +140,18 @@ struct Driver {
     return s / (double)S.K;
   }
 
-  // request an evaluation at the current point (th, ga, beta)
+  // request an evaluation at the current point (th, ga, beta).  When the
+  // last evaluation is already at that point (cur_valid), its factor, C^{-1}y
+  // and active vectors are still in place and only the grid stage runs.
   SFLS_HD void request_current(int32_t bits) {
+    if (S.cur_valid) bits &= ~1;  // REQ_EVAL
     for (int k = 0; k < S.K; ++k) { A.th_e[k] = A.th[k]; A.ga_e[k] = A.ga[k]; }
     *A.K_e = S.K;
     *A.beta_e = S.beta;
     *A.gbar_e = gbar();
     *A.zeta_e = S.zeta;
     *A.req = bits;
-    S.nevals += 1;
+    if (bits & 1) S.nevals += 1;
   }
 
   // gradient and replaced diagonal Hessian from the evaluation results
@@ -417,14 +421,17 @@ struct Driver {
     return added;
   }
 
-  SFLS_HD void finish() {
+  // Outputs at the current point: from the evaluation there, or (saved) from
+  // q and the objective kept when the last polish step started at it.
+  SFLS_HD void finish(bool saved) {
     const int K = S.K;
-    // alpha = gamma .* q at the final evaluation; sort by theta (insertion)
+    const double* q = saved ? A.q_save : A.ev_q;
+    // alpha = gamma .* q at the final point; sort by theta (insertion)
     for (int k = 0; k < K; ++k) {
       A.out_theta[k] = A.th[k];
       A.out_gamma[k] = A.ga[k];
-      A.out_alpha[2 * k] = A.ga[k] * A.ev_q[2 * k];
-      A.out_alpha[2 * k + 1] = A.ga[k] * A.ev_q[2 * k + 1];
+      A.out_alpha[2 * k] = A.ga[k] * q[2 * k];
+      A.out_alpha[2 * k + 1] = A.ga[k] * q[2 * k + 1];
     }
     for (int i = 1; i < K; ++i) {
       const double t = A.out_theta[i], gg = A.out_gamma[i];
@@ -445,7 +452,7 @@ struct Driver {
     *A.out_K = K;
     *A.out_beta = S.beta;
     *A.out_zeta = S.zeta;
-    *A.out_obj = (S.yy == 0.0) ? -INFINITY : f_of_eval();
+    *A.out_obj = (S.yy == 0.0) ? -INFINITY : (saved ? S.f_cur : f_of_eval());
     *A.out_iters = S.it;
     if (A.out_evals) *A.out_evals = S.nevals;
     int st = S.converged ? 0 : 1;
@@ -495,7 +502,7 @@ struct Driver {
         // initialisation (Sec. II-E)
         S.it = 0; S.inner = 0; S.pit = 0; S.K = 0; S.z_changed = 1; S.cur_valid = 0;
         S.converged = 0; S.cap_hit = 0; S.polish = 0; S.mem_n = 0; S.mem_head = 0;
-        S.status = 0; S.nevals = 0; S.done = 0;
+        S.status = 0; S.nevals = 0; S.done = 0; S.saved = 0;
         if (S.yy == 0.0) {
           S.beta = 0.0; S.zeta = 0.0; S.converged = 1;
           lbl = L_FINAL;
@@ -707,6 +714,8 @@ struct Driver {
           derivs(A.ga, A.g, A.gt);
           direction(A.g, A.gt, A.d, n);
           S.f_cur = f_of_eval();
+          for (int e = 0; e < n; ++e) A.q_save[e] = A.ev_q[e];
+          S.saved = 1;
           ls_begin(true);
           ls_request();
           S.phase = PH_LS_WAIT;
@@ -714,12 +723,18 @@ struct Driver {
         }
         case L_FINAL: {
           if (!S.cur_valid && S.yy != 0.0) {
+            if (S.polish && S.saved) {
+              // the polish's last line search failed: the current point is the
+              // one its step started from
+              finish(true);
+              return;
+            }
             request_current(1);
             S.phase = PH_POLISH_WAIT;
             S.pit = P.polish_max_iters;  // resumes into L_POLISH_STEP -> L_FINAL
             return;
           }
-          finish();
+          finish(false);
           return;
         }
         default:

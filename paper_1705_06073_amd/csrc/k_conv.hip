@@ -233,6 +233,114 @@ __global__ __launch_bounds__(CONV_NT) void k_omega(const InstInfo* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// a3 refinement.  The superfast recursion's generator is refined by one step
+// of iterative refinement on the last column of C^{-1}: with x0 = rho /
+// delta_{N-1},
+//   r = e_{N-1} - C x0            (k_gen_residual: length-P circular
+//                                  convolution with the Hermitian extension
+//                                  h_t = c_t, h_{P-t} = conj(c_t) of c)
+//   dx = C~^{-1} r                (k_gs_apply with the unrefined generator)
+//   x1 = x0 + dx,  rho <- x1 / x1_{N-1},  delta_{N-1} <- 1 / x1_{N-1}
+//                                 (k_gen_update; x1_{N-1} is real).
+// Instances whose factorisation failed are left alone.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(CONV_NT) void k_gen_residual(const InstInfo* __restrict__ info,
+                                                          const int32_t* __restrict__ req,
+                                                          const int32_t* __restrict__ status,
+                                                          const cd* __restrict__ c,
+                                                          const cd* __restrict__ rho,
+                                                          const double* __restrict__ delta,
+                                                          const cd* __restrict__ tws,
+                                                          cd* __restrict__ scratch,
+                                                          cd* __restrict__ r) {
+  const int bi = blockIdx.x;
+  if (req && !(req[bi] & REQ_EVAL)) return;
+  if (status && status[bi] != 0) return;
+  const InstInfo in = info[bi];
+  const int N = in.N, P = in.P, logP = in.logP;
+  extern __shared__ cd lds[];
+  __shared__ cd s_tw[FFT_TWL];
+  const int tid = threadIdx.x;
+  load_tw_head<CONV_NT>(s_tw, tws);
+  const cd* cb = c + in.off;
+  const cd* rb = rho + in.off;
+  cd* H = scratch + in.poff;
+  const double inv_d = 1.0 / delta[in.off + N - 1];
+  for (int t = tid; t < P; t += CONV_NT) {
+    cd v{0.0, 0.0};
+    if (t < N) v = cb[t];
+    else if (t > P - N) v = cconj(cb[P - t]);
+    lds[pidx(t)] = v;
+  }
+  __syncthreads();
+  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+  for (int t = tid; t < P; t += CONV_NT) H[t] = lds[pidx(t)];
+  __syncthreads();
+  for (int t = tid; t < P; t += CONV_NT) lds[pidx(t)] = (t < N) ? cscale(rb[t], inv_d) : cd{0.0, 0.0};
+  __syncthreads();
+  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+  for (int p = tid; p < P; p += CONV_NT) lds[pidx(p)] = cmul(lds[pidx(p)], H[p]);
+  __syncthreads();
+  dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
+  const double invP = 1.0 / (double)P;
+  for (int i = tid; i < N; i += CONV_NT) {
+    const cd cx = cscale(lds[pidx(i)], invP);
+    r[in.off + i] = cd{(i == N - 1 ? 1.0 : 0.0) - cx.x, -cx.y};
+  }
+}
+
+__global__ __launch_bounds__(CONV_NT) void k_gen_update(const InstInfo* __restrict__ info,
+                                                        const int32_t* __restrict__ req,
+                                                        const int32_t* __restrict__ status,
+                                                        cd* __restrict__ rho,
+                                                        double* __restrict__ delta,
+                                                        const cd* __restrict__ dx) {
+  const int bi = blockIdx.x;
+  if (req && !(req[bi] & REQ_EVAL)) return;
+  if (status && status[bi] != 0) return;
+  const InstInfo in = info[bi];
+  const int N = in.N;
+  cd* rb = rho + in.off;
+  const cd* db = dx + in.off;
+  __shared__ double s_inv_d, s_scale;
+  if (threadIdx.x == 0) {
+    const double inv_d = 1.0 / delta[in.off + N - 1];
+    const double xl = fma(rb[N - 1].x, inv_d, db[N - 1].x);  // x1_{N-1}, real
+    s_inv_d = inv_d;
+    s_scale = 1.0 / xl;
+  }
+  __syncthreads();
+  const double inv_d = s_inv_d, sc = s_scale;
+  for (int i = threadIdx.x; i < N - 1; i += CONV_NT) {
+    const cd x1{fma(rb[i].x, inv_d, db[i].x), fma(rb[i].y, inv_d, db[i].y)};
+    rb[i] = cscale(x1, sc);
+  }
+  if (threadIdx.x == 0) {
+    rb[N - 1] = cd{1.0, 0.0};
+    delta[in.off + N - 1] = sc;
+  }
+}
+
+hipError_t launch_gen_refine(const InstInfo* info, const int32_t* req, const int32_t* status,
+                             const cd* c, cd* rho, double* delta, const cd* tw, int logtw,
+                             const cd* tws, cd* scratch, cd* r, cd* dx, int B, int maxP,
+                             hipStream_t st) {
+  const size_t shm = (size_t)padded(maxP) * sizeof(cd);
+  (void)hipFuncSetAttribute((const void*)k_gen_residual,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_gen_residual, dim3(B), dim3(CONV_NT), shm, st, info, req, status, c, rho,
+                     delta, tws, scratch, r);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_gs_apply(info, req, r, 1, rho, delta, tw, logtw, tws, scratch, dx, nullptr, nullptr,
+                      B, maxP, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gen_update, dim3(B), dim3(CONV_NT), 0, st, info, req, status, rho, delta,
+                     dx);
+  return hipGetLastError();
+}
+
 hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void* y, int ydtype,
                            const cd* rho, const double* delta, const cd* tw, int logtw,
                            const cd* tws, cd* scratch, cd* w, double* yCy, double* ww, int B, int maxP,

@@ -30,6 +30,7 @@ __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info
   A.g = p.g + k2;
   A.d = p.d + k2;
   A.gt = p.gt + k2;
+  A.q_save = p.q_save + k2;
   A.Sm = p.Sm + (int64_t)J * k2;
   A.Ym = p.Ym + (int64_t)J * k2;
   A.rhom = p.rhom + (int64_t)J * b;

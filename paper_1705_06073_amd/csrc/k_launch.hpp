@@ -18,6 +18,7 @@ struct DrvPools {
   double* g;
   double* d;
   double* gt;
+  double* q_save;
   double* Sm;
   double* Ym;
   double* rhom;
@@ -76,6 +77,10 @@ hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void*
                            const cd* tws, cd* scratch, cd* w, double* yCy, double* ww, int B,
                            int maxP,
                            hipStream_t st);
+hipError_t launch_gen_refine(const InstInfo* info, const int32_t* req, const int32_t* status,
+                             const cd* c, cd* rho, double* delta, const cd* tw, int logtw,
+                             const cd* tws, cd* scratch, cd* r, cd* dx, int B, int maxP,
+                             hipStream_t st);
 hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
                         const double* delta, const SepCoef* coef, const cd* tws,
                         cd* scratch, int which, int have_g0, cd* oms, cd* o_s, cd* o_t,

@@ -1,0 +1,58 @@
+"""The device driver's control flow (a9), compiled for the host and fed by
+oracle evaluations, reproduces the oracle estimator's result: same model
+order, frequencies, amplitudes, noise variance and objective.  Its
+evaluation count exceeds the oracle's by the evaluations the beta update of
+Sec. II-D takes (the oracle evaluates that update from its definition
+without counting it), at most one per outer iteration."""
+import shutil
+
+import numpy as np
+import pytest
+
+from oracle import estimator as oe
+from paper_1705_06073_amd import synth
+
+if shutil.which("g++") is None:  # pragma: no cover
+    pytest.skip("g++ not available", allow_module_level=True)
+
+from tests import host_driver as hd  # noqa: E402
+
+
+def _instances():
+    rng = np.random.default_rng(4242)
+    out = []
+    for N, K, snr in [(64, 3, 20.0), (96, 4, 10.0), (128, 5, 30.0), (200, 6, 15.0)]:
+        out.append(synth.make_instance(rng, N, K, 1.0 / N, "cn", snr))
+    return out
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_host_driver_matches_oracle(idx):
+    inst = _instances()[idx]
+    o = oe.estimate(inst.y)
+    r = hd.HostDriver(inst.y).run()
+    assert r["status"] == o.status
+    assert r["K"] == o.K
+    assert r["iterations"] == o.iterations
+    np.testing.assert_allclose(r["theta"], o.theta, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["gamma"], o.gamma, rtol=1e-9, atol=1e-14)
+    np.testing.assert_allclose(r["alpha"], o.alpha, rtol=1e-9, atol=1e-12)
+    assert r["beta"] == pytest.approx(o.beta, rel=1e-9)
+    assert r["zeta"] == pytest.approx(o.zeta, rel=1e-12)
+    assert r["objective"] == pytest.approx(o.objective, rel=1e-10, abs=1e-9)
+    assert o.evaluations <= r["evaluations"] <= o.evaluations + o.iterations + 1, \
+        (o.evaluations, o.iterations, r["evaluations"])
+
+
+def test_host_driver_zero_signal():
+    r = hd.HostDriver(np.zeros(32, np.complex128)).run()
+    assert r["K"] == 0 and r["beta"] == 0.0 and r["evaluations"] == 0
+
+
+def test_host_driver_approximate_off_matches_oracle():
+    inst = _instances()[2]
+    p = oe.Params(approx_max_iters=0)
+    o = oe.estimate(inst.y, p)
+    r = hd.HostDriver(inst.y, p).run()
+    assert r["K"] == o.K
+    np.testing.assert_allclose(r["theta"], o.theta, rtol=0, atol=1e-12)
