@@ -236,10 +236,15 @@ class OracleEstimator:
             alpha = min(1.0, amax)
         slack = p.polish_ftol * (1.0 + abs(f0)) if polish else 0.0
         dth_max = float(np.max(np.abs(dth))) if K else 0.0
+        resolution = p.polish_ftol * (1.0 + abs(f0))
         for trial in range(p.ls_max):
             # the polish gives up once a shortened step could no longer move any
             # frequency by the polish tolerance (it would stop after it anyway)
             if polish and trial > 0 and alpha * dth_max < p.polish_tol / self.N:
+                return None
+            # the inner search gives up once the decrease it requires is below
+            # the rounding level of the objective (the test would decide nothing)
+            if not polish and trial > 0 and p.ls_c1 * alpha * abs(gd) < resolution:
                 return None
             th_t = np.mod(theta + alpha * dth, 1.0)
             ga_t = np.maximum(gamma + alpha * dga, 0.0)

@@ -959,6 +959,9 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
       if ((s = run_factor(ctx, B, n, dinfo, P.req, c, rho, delta, logdet, lev_status, failed,
                           sz.maxN, st, slay, sacts, sscr, sFmax, rf)) != SFLS_OK)
         return s;
+      // ln|C| over the active set (determinant lemma) where it is small enough
+      HIP_TRY(launch_logdet_lemma(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, lev_status,
+                                  logdet, (int)B, st));
       HIP_TRY(tstop(KID_FACTOR));
       HIP_TRY(tstart(KID_APPLY));
       HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw,

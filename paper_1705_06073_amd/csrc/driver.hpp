@@ -648,6 +648,11 @@ struct Driver {
             for (int k = 0; k < S.K; ++k) dmax = fmax(dmax, fabs(A.d[k]));
             give_up = S.alpha * dmax < P.polish_tol / (double)N;
           }
+          if (!S.polish && !give_up) {
+            // the inner search stops once the decrease it requires is below the
+            // rounding level of the objective
+            give_up = P.ls_c1 * S.alpha * fabs(S.gd) < P.polish_ftol * (1.0 + fabs(S.f_cur));
+          }
           if (give_up) {
             // line search failed: current point unchanged (needs re-evaluation)
             if (S.polish) { lbl = L_FINAL; break; }

@@ -81,6 +81,10 @@ hipError_t launch_gen_refine(const InstInfo* info, const int32_t* req, const int
                              const cd* c, cd* rho, double* delta, const cd* tw, int logtw,
                              const cd* tws, cd* scratch, cd* r, cd* dx, int B, int maxP,
                              hipStream_t st);
+hipError_t launch_logdet_lemma(const InstInfo* info, const int32_t* req, const int32_t* Kev,
+                               const double* theta, const double* gamma,
+                               const double* beta, const int32_t* status, double* logdet, int B,
+                               hipStream_t st);
 hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
                         const double* delta, const SepCoef* coef, const cd* tws,
                         cd* scratch, int which, int have_g0, cd* oms, cd* o_s, cd* o_t,

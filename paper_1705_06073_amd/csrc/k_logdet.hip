@@ -1,0 +1,110 @@
+// ln|C| of an evaluation by the determinant lemma over the active set:
+//   C = beta I + Psi Gamma Psi^H  =>
+//   ln|C| = N ln beta + ln det(I_K + Gamma^{1/2} Psi^H Psi Gamma^{1/2} / beta),
+// with the Gram matrix in closed form (Dirichlet kernel)
+//   [Psi^H Psi]_{kl} = sum_{n<N} e^{j 2 pi n (theta_l - theta_k)}
+//                    = e^{j pi (N-1) d} sin(pi N d) / sin(pi d),  d = theta_l - theta_k,
+// and the K x K Hermitian positive-definite matrix (eigenvalues >= 1)
+// factored by Cholesky in LDS.  This is the same quantity as sum_i ln delta_i
+// of the factorisation (Sec. III-A); it is computed this way when K <= LEM_KMAX
+// because it is accurate to a few ulp of N ln beta plus K eps cond(M), while
+// the pivots of a long recursion carry O(N) accumulated rounding.  Larger
+// active sets keep the factorisation's value.
+#include "k_launch.hpp"
+#include "sfls_kernels.hpp"
+
+namespace sfls {
+
+constexpr int LEM_NT = 256;
+constexpr int LEM_KMAX = 96;
+
+__global__ __launch_bounds__(LEM_NT) void k_logdet_lemma(const InstInfo* __restrict__ info,
+                                                         const int32_t* __restrict__ req,
+                                                         const int32_t* __restrict__ Kev,
+                                                         const double* __restrict__ theta,
+                                                         const double* __restrict__ gamma,
+                                                         const double* __restrict__ beta,
+                                                         const int32_t* __restrict__ status,
+                                                         double* __restrict__ logdet) {
+  const int bi = blockIdx.x;
+  if (!(req[bi] & REQ_EVAL)) return;
+  if (status[bi] != 0) return;
+  const int K = Kev[bi];
+  if (K > LEM_KMAX) return;
+  const InstInfo in = info[bi];  // components at in.koff
+  const int N = in.N;
+  const double be = beta[bi];
+  const double* th = theta + in.koff;
+  const double* ga = gamma + in.koff;
+  constexpr int LD = LEM_KMAX + 1;  // padded row stride
+  __shared__ cd M[LEM_KMAX * LD];
+  __shared__ double s_sg[LEM_KMAX];
+  __shared__ double s_logd;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < K; k += LEM_NT) s_sg[k] = sqrt(ga[k] / be);
+  if (tid == 0) { s_logd = 0.0; s_bad = 0; }
+  __syncthreads();
+  // lower triangle (and diagonal) of M
+  for (int e = tid; e < K * K; e += LEM_NT) {
+    const int k = e / K, l = e % K;
+    if (l > k) continue;
+    double d = th[l] - th[k];
+    d -= rint(d);  // (-1/2, 1/2]
+    cd g;
+    if (d == 0.0) {
+      g = cd{(double)N, 0.0};
+    } else {
+      double sn, cs, sN, cN;
+      sincospi(d, &sn, &cs);
+      sincospi((double)N * d, &sN, &cN);
+      double sph, cph;
+      sincospi((double)(N - 1) * d, &sph, &cph);
+      const double r = sN / sn;
+      g = cd{cph * r, sph * r};
+    }
+    const double sc = s_sg[k] * s_sg[l];
+    cd v = cscale(g, sc);
+    if (k == l) v = cd{1.0 + v.x, 0.0};
+    M[k * LD + l] = v;
+  }
+  __syncthreads();
+  // right-looking Cholesky, L in the lower triangle
+  for (int j = 0; j < K; ++j) {
+    if (tid == 0) {
+      const double dj = M[j * LD + j].x;
+      if (!(dj > 0.0)) s_bad = 1;
+      const double lj = sqrt(dj);
+      M[j * LD + j] = cd{lj, 0.0};
+      s_logd += log(dj);
+    }
+    __syncthreads();
+    const double inv = 1.0 / M[j * LD + j].x;
+    for (int i = j + 1 + tid; i < K; i += LEM_NT) M[i * LD + j] = cscale(M[i * LD + j], inv);
+    __syncthreads();
+    // trailing update of the lower triangle: M_ik -= L_ij conj(L_kj), j < k <= i
+    const int nt = K - j - 1;
+    for (int e = tid; e < nt * nt; e += LEM_NT) {
+      const int i = j + 1 + e / nt, k = j + 1 + e % nt;
+      if (k > i) continue;
+      const cd lij = M[i * LD + j], lkj = M[k * LD + j];
+      cd m = M[i * LD + k];
+      m.x -= lij.x * lkj.x + lij.y * lkj.y;
+      m.y -= lij.y * lkj.x - lij.x * lkj.y;
+      M[i * LD + k] = m;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && !s_bad) logdet[bi] = (double)N * log(be) + s_logd;
+}
+
+hipError_t launch_logdet_lemma(const InstInfo* info, const int32_t* req, const int32_t* Kev,
+                               const double* theta, const double* gamma,
+                               const double* beta, const int32_t* status, double* logdet, int B,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_logdet_lemma, dim3(B), dim3(LEM_NT), 0, st, info, req, Kev, theta, gamma,
+                     beta, status, logdet);
+  return hipGetLastError();
+}
+
+}  // namespace sfls
