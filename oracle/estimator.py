@@ -73,6 +73,11 @@ class Result:
     trace: list = field(default_factory=list)
 
 
+# A polish line search tries at most this many step lengths (alpha >= 2^-8 of
+# the first); a step that needs more is in the rounding noise of the objective.
+POLISH_LS_TRIALS = 9
+
+
 class _Memory:
     """L-BFGS curvature pairs (Nocedal & Wright, Alg. 7.4) with a diagonal H0."""
 
@@ -240,7 +245,8 @@ class OracleEstimator:
         for trial in range(p.ls_max):
             # the polish gives up once a shortened step could no longer move any
             # frequency by the polish tolerance (it would stop after it anyway)
-            if polish and trial > 0 and alpha * dth_max < p.polish_tol / self.N:
+            if polish and trial > 0 and (alpha * dth_max < p.polish_tol / self.N
+                                         or trial >= POLISH_LS_TRIALS):
                 return None
             # the inner search gives up once the decrease it requires is below
             # the rounding level of the objective (the test would decide nothing)

@@ -24,10 +24,10 @@ struct DevBuf {
   size_t n = 0;
 };
 
-enum KernelId { KID_GEN = 0, KID_FACTOR, KID_APPLY, KID_OMEGA, KID_GRID, KID_SELECT, KID_ACTIVE,
-                KID_DRIVER, KID_COUNT };
-const char* const kKernelNames[KID_COUNT] = {"toeplitz_column", "factor", "gs_apply", "omega",
-                                             "grid", "select", "active", "driver"};
+enum KernelId { KID_GEN = 0, KID_FACTOR, KID_REFINE, KID_APPLY, KID_OMEGA, KID_GRID, KID_SELECT,
+                KID_ACTIVE, KID_DRIVER, KID_COUNT };
+const char* const kKernelNames[KID_COUNT] = {"toeplitz_column", "factor", "refine", "gs_apply",
+                                             "omega", "grid", "select", "active", "driver"};
 
 struct sfls_ctx {
   int device = 0;
@@ -238,13 +238,9 @@ void schur_rec(SchurPlan& P, int n0, int m, int level, int side, int win, int Nr
 //     and 4 per live Theta coefficient (s + 1), i.e. 24 m (m + 1);
 //   direct merge: window 4 m1 m2, product 8 m1 m2 multiply-adds (root: 4 m1 m2);
 //   transform merge: 8 transforms + 4 F multiply-adds (window), 8 transforms +
-//   10 F (product); root product 3 transforms + 6 F;
-//   the refinement of the generator that follows.
-double schur_flops(const SchurPlan& P, int N) {
-  // refinement of the generator: 3 transforms (residual) + 7 (GS apply) of size
-  // P >= 2N - 1, plus about 12 multiply-adds per point
-  const int lp = ilog2_ceil(2 * N - 1);
-  double f = 10.0 * 5.0 * std::ldexp(1.0, lp) * lp + 96.0 * std::ldexp(1.0, lp);
+//   10 F (product); root product 3 transforms + 6 F.
+double schur_flops(const SchurPlan& P) {
+  double f = 0.0;
   for (const SchurAct& a : P.acts) {
     const double m = a.m, m1 = a.m1, m2 = a.m - a.m1, F = std::ldexp(1.0, a.logF);
     const double tr = 5.0 * F * a.logF;
@@ -283,7 +279,7 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
       it = byN.emplace(N, std::make_pair(aoff, P)).first;
     }
     const SchurPlan& P = it->second.second;
-    flops[(size_t)b] = schur_flops(P, (int)N);
+    flops[(size_t)b] = schur_flops(P);
     SchurLayout& L = lay[(size_t)b];
     std::memset(&L, 0, sizeof L);
     L.act_off = it->second.first;
@@ -322,21 +318,39 @@ struct RefineBufs {
 
 // Factor a batch (Levinson, or superfast Schur followed by one step of
 // iterative refinement of the generator, by the context's choice).
+static sfls_status run_recursion(sfls_ctx* ctx, int64_t B, const InstInfo* dinfo,
+                                 const int32_t* req, const cd* c, cd* rho, double* delta,
+                                 double* logdet, int32_t* status, int64_t* failed, int maxN,
+                                 hipStream_t st, const SchurLayout* dlay, const SchurAct* dacts,
+                                 cd* sscr, int Fmax) {
+  if (dlay) {
+    HIP_TRY(launch_schur(dinfo, req, dlay, dacts, c, ctx->tw64, ctx->logtw, ctx->tws64, sscr, rho,
+                         delta, logdet, status, failed, (int)B, Fmax, st));
+  } else {
+    HIP_TRY(launch_levinson(dinfo, req, c, rho, delta, logdet, status, failed, (int)B, maxN, st));
+  }
+  return SFLS_OK;
+}
+
+static sfls_status run_refine(sfls_ctx* ctx, int64_t B, const InstInfo* dinfo, const int32_t* req,
+                              const cd* c, cd* rho, double* delta, int32_t* status,
+                              hipStream_t st, const SchurLayout* dlay, const RefineBufs& rf) {
+  if (dlay)
+    HIP_TRY(launch_gen_refine(dinfo, req, status, c, rho, delta, ctx->tw64, ctx->logtw,
+                              ctx->tws64, rf.scratch, rf.r, rf.dx, (int)B, rf.maxP, st));
+  return SFLS_OK;
+}
+
 static sfls_status run_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const InstInfo* dinfo,
                               const int32_t* req, const cd* c, cd* rho, double* delta,
                               double* logdet, int32_t* status, int64_t* failed, int maxN,
                               hipStream_t st, const SchurLayout* dlay, const SchurAct* dacts,
                               cd* sscr, int Fmax, const RefineBufs& rf) {
-  if (dlay) {
-    HIP_TRY(launch_schur(dinfo, req, dlay, dacts, c, ctx->tw64, ctx->logtw, ctx->tws64, sscr, rho,
-                         delta,
-                         logdet, status, failed, (int)B, Fmax, st));
-    HIP_TRY(launch_gen_refine(dinfo, req, status, c, rho, delta, ctx->tw64, ctx->logtw,
-                              ctx->tws64, rf.scratch, rf.r, rf.dx, (int)B, rf.maxP, st));
-  } else {
-    HIP_TRY(launch_levinson(dinfo, req, c, rho, delta, logdet, status, failed, (int)B, maxN, st));
-  }
-  return SFLS_OK;
+  (void)n;
+  sfls_status s = run_recursion(ctx, B, dinfo, req, c, rho, delta, logdet, status, failed, maxN,
+                                st, dlay, dacts, sscr, Fmax);
+  if (s != SFLS_OK) return s;
+  return run_refine(ctx, B, dinfo, req, c, rho, delta, status, st, dlay, rf);
 }
 
 static bool use_schur(const sfls_ctx* ctx, int maxN) {
@@ -936,6 +950,10 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
         ++nact;
         kflops[KID_FACTOR] += slay ? sflops[(size_t)b] : 8.0 * N * N;  // Schur or Levinson
         kbytes[KID_FACTOR] += 40.0 * N;                       // c in, rho and delta out
+        if (slay) {
+          const double P = (double)info[(size_t)b].P, lp = (double)info[(size_t)b].logP;
+          kflops[KID_REFINE] += 10.0 * 5.0 * P * lp + 96.0 * P;  // 10 transforms + pointwise
+        }
         kbytes[KID_APPLY] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * N + 32.0 * N;  // y, rho in; w out
       }
       // grid stage: alone when the evaluation at the current point is in place
@@ -956,13 +974,18 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
                                      sz.maxN, st));
       HIP_TRY(tstop(KID_GEN));
       HIP_TRY(tstart(KID_FACTOR));
-      if ((s = run_factor(ctx, B, n, dinfo, P.req, c, rho, delta, logdet, lev_status, failed,
-                          sz.maxN, st, slay, sacts, sscr, sFmax, rf)) != SFLS_OK)
+      if ((s = run_recursion(ctx, B, dinfo, P.req, c, rho, delta, logdet, lev_status, failed,
+                             sz.maxN, st, slay, sacts, sscr, sFmax)) != SFLS_OK)
+        return s;
+      HIP_TRY(tstop(KID_FACTOR));
+      HIP_TRY(tstart(KID_REFINE));
+      if ((s = run_refine(ctx, B, dinfo, P.req, c, rho, delta, lev_status, st, slay, rf)) !=
+          SFLS_OK)
         return s;
       // ln|C| over the active set (determinant lemma) where it is small enough
       HIP_TRY(launch_logdet_lemma(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, lev_status,
                                   logdet, (int)B, st));
-      HIP_TRY(tstop(KID_FACTOR));
+      HIP_TRY(tstop(KID_REFINE));
       HIP_TRY(tstart(KID_APPLY));
       HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw,
                               ctx->tws64, scratch, w, yCy, ww, (int)B, sz.maxP, st));

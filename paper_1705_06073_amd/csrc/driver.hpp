@@ -122,6 +122,10 @@ SFLS_HD inline bool act_criterion(double q2, double s, double gb, double zeta, d
   return kap > rhs;
 }
 
+// A polish line search tries at most this many step lengths (alpha >= 2^-8 of
+// the first); a step that needs more is in the rounding noise of the objective.
+constexpr int kPolishLsTrials = 9;
+
 struct Driver {
   const DrvParams& P;
   DrvState& S;
@@ -646,7 +650,7 @@ struct Driver {
             // the polish tolerance
             double dmax = 0.0;
             for (int k = 0; k < S.K; ++k) dmax = fmax(dmax, fabs(A.d[k]));
-            give_up = S.alpha * dmax < P.polish_tol / (double)N;
+            give_up = S.alpha * dmax < P.polish_tol / (double)N || S.ls_trial >= kPolishLsTrials;
           }
           if (!S.polish && !give_up) {
             // the inner search stops once the decrease it requires is below the
