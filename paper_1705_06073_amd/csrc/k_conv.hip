@@ -6,7 +6,7 @@
 
 namespace sfls {
 
-constexpr int CONV_NT = 256;
+constexpr int CONV_NT = 512;
 
 // W_P^m = exp(-j 2 pi m / P) from the table tw[k] = exp(-j 2 pi k / 2^logtw), k < 2^(logtw-1)
 __device__ __forceinline__ cd tw_pow(const cd* __restrict__ tw, int logtw, int64_t m, int logP) {

@@ -5,7 +5,7 @@
 //   [Psi^H Psi]_{kl} = sum_{n<N} e^{j 2 pi n (theta_l - theta_k)}
 //                    = e^{j pi (N-1) d} sin(pi N d) / sin(pi d),  d = theta_l - theta_k,
 // and the K x K Hermitian positive-definite matrix (eigenvalues >= 1)
-// factored by Cholesky in LDS.  This is the same quantity as sum_i ln delta_i
+// factored as L D L^H in LDS.  This is the same quantity as sum_i ln delta_i
 // of the factorisation (Sec. III-A); it is computed this way when K <= LEM_KMAX
 // because it is accurate to a few ulp of N ln beta plus K eps cond(M), while
 // the pivots of a long recursion carry O(N) accumulated rounding.  Larger
@@ -39,11 +39,10 @@ __global__ __launch_bounds__(LEM_NT) void k_logdet_lemma(const InstInfo* __restr
   constexpr int LD = LEM_KMAX + 1;  // padded row stride
   __shared__ cd M[LEM_KMAX * LD];
   __shared__ double s_sg[LEM_KMAX];
-  __shared__ double s_logd;
   __shared__ int s_bad;
   const int tid = threadIdx.x;
   for (int k = tid; k < K; k += LEM_NT) s_sg[k] = sqrt(ga[k] / be);
-  if (tid == 0) { s_logd = 0.0; s_bad = 0; }
+  if (tid == 0) s_bad = 0;
   __syncthreads();
   // lower triangle (and diagonal) of M
   for (int e = tid; e < K * K; e += LEM_NT) {
@@ -69,33 +68,36 @@ __global__ __launch_bounds__(LEM_NT) void k_logdet_lemma(const InstInfo* __restr
     M[k * LD + l] = v;
   }
   __syncthreads();
-  // right-looking Cholesky, L in the lower triangle
-  for (int j = 0; j < K; ++j) {
-    if (tid == 0) {
-      const double dj = M[j * LD + j].x;
-      if (!(dj > 0.0)) s_bad = 1;
-      const double lj = sqrt(dj);
-      M[j * LD + j] = cd{lj, 0.0};
-      s_logd += log(dj);
-    }
-    __syncthreads();
+  // right-looking LDL^H (no square roots): after step j, M_jj is the pivot d_j
+  // and column j below it holds L_ij d_j; ln det M = sum_j ln d_j
+  const int tr = tid >> 4, tc = tid & 15;  // 16 x 16 thread tile over (i, k)
+  for (int j = 0; j < K - 1; ++j) {
     const double inv = 1.0 / M[j * LD + j].x;
-    for (int i = j + 1 + tid; i < K; i += LEM_NT) M[i * LD + j] = cscale(M[i * LD + j], inv);
-    __syncthreads();
-    // trailing update of the lower triangle: M_ik -= L_ij conj(L_kj), j < k <= i
-    const int nt = K - j - 1;
-    for (int e = tid; e < nt * nt; e += LEM_NT) {
-      const int i = j + 1 + e / nt, k = j + 1 + e % nt;
-      if (k > i) continue;
-      const cd lij = M[i * LD + j], lkj = M[k * LD + j];
-      cd m = M[i * LD + k];
-      m.x -= lij.x * lkj.x + lij.y * lkj.y;
-      m.y -= lij.y * lkj.x - lij.x * lkj.y;
-      M[i * LD + k] = m;
+    for (int i = j + 1 + tr; i < K; i += 16) {
+      const cd mij = M[i * LD + j];
+      for (int k = j + 1 + tc; k <= i; k += 16) {
+        const cd mkj = M[k * LD + j];
+        cd m = M[i * LD + k];
+        // M_ik -= M_ij conj(M_kj) / d_j
+        m.x -= (mij.x * mkj.x + mij.y * mkj.y) * inv;
+        m.y -= (mij.y * mkj.x - mij.x * mkj.y) * inv;
+        M[i * LD + k] = m;
+      }
     }
     __syncthreads();
   }
-  if (tid == 0 && !s_bad) logdet[bi] = (double)N * log(be) + s_logd;
+  // ln d_j in parallel, then a block sum
+  double acc[1] = {0.0};
+  bool bad = false;
+  for (int j = tid; j < K; j += LEM_NT) {
+    const double dj = M[j * LD + j].x;
+    bad |= !(dj > 0.0);
+    acc[0] += log(dj);
+  }
+  if (bad) s_bad = 1;
+  __shared__ double red[LEM_NT / 64];
+  block_sum<LEM_NT, 1>(acc, red);
+  if (tid == 0 && !s_bad) logdet[bi] = (double)N * log(be) + acc[0];
 }
 
 hipError_t launch_logdet_lemma(const InstInfo* info, const int32_t* req, const int32_t* Kev,
