@@ -236,9 +236,9 @@ void schur_rec(SchurPlan& P, int n0, int m, int level, int side, int win, int Nr
 // = 8 flops, a complex transform of size F = 5 F log2 F):
 //   leaf of m steps: 2 multiply-adds per live window entry (m - s at step s)
 //     and 4 per live Theta coefficient (s + 1), i.e. 24 m (m + 1);
-//   direct merge: window 4 m1 m2, product 8 m1 m2 multiply-adds (root: 4 m1 m2);
-//   transform merge: 8 transforms + 4 F multiply-adds (window), 8 transforms +
-//   10 F (product); root product 3 transforms + 6 F.
+//   direct merge: window 4 m1 m2, product (first row) 4 m1 m2 multiply-adds;
+//   transform merge: 6 transforms + 6 F multiply-adds (window), 4 transforms +
+//   7 F (first row of the product); root product 3 transforms + 8 F.
 double schur_flops(const SchurPlan& P) {
   double f = 0.0;
   for (const SchurAct& a : P.acts) {
@@ -247,9 +247,9 @@ double schur_flops(const SchurPlan& P) {
     switch (a.type) {
       case SCH_LEAF_ACT:
       case SCH_ROOT_LEAF: f += 24.0 * m * (m + 1.0); break;
-      case SCH_MID: f += (a.m <= SCH_DIRECT) ? 32.0 * m1 * m2 : 8.0 * tr + 32.0 * F; break;
-      case SCH_POST: f += (a.m <= SCH_DIRECT) ? 64.0 * m1 * m2 : 8.0 * tr + 80.0 * F; break;
-      case SCH_ROOT: f += (a.m <= SCH_DIRECT) ? 32.0 * m1 * m2 : 3.0 * tr + 48.0 * F; break;
+      case SCH_MID: f += (a.m <= SCH_DIRECT) ? 32.0 * m1 * m2 : 6.0 * tr + 48.0 * F; break;
+      case SCH_POST: f += (a.m <= SCH_DIRECT) ? 32.0 * m1 * m2 : 4.0 * tr + 56.0 * F; break;
+      case SCH_ROOT: f += (a.m <= SCH_DIRECT) ? 32.0 * m1 * m2 : 3.0 * tr + 64.0 * F; break;
       default: break;
     }
   }
@@ -294,7 +294,7 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
       L.res[l] = o;
       o += 8 * (int64_t)P.mmax[l];
       L.spec[l] = o;
-      o += 4 * (int64_t)P.fspec[l];
+      o += 2 * (int64_t)P.fspec[l];
       fm = std::max(fm, P.fspec[l]);
       if (P.mmax[l] <= SCH_DIRECT) fm = std::max(fm, 8 * P.mmax[l] + 256);
     }

@@ -24,6 +24,14 @@
 //           u2[r] = P1[m1 + r], v2[r] = P2[m1 - 1 + r];
 //     S(n0+m1, m-m1) on (u2, v2) -> Theta2;
 //     POST: Theta = Theta2 Theta1 (shifted form, z = e^{-j2pi f/F} per bin).
+// Every section theta_k has the form [[A, B], [B#, A#]] with P#(z) the
+// reversed conjugate z^deg conj(P(1/conj z)), and products keep that form, so
+// in the shifted storage over m steps
+//   P22[i] = conj(P11[m-1-i]),  P21[i] = conj(P12[m-1-i]),
+// and for their spectra on F bins, S22(f) = W^(f(m-1)) conj(S11(f)) and
+// S21(f) = W^(f(m-1)) conj(S12(f)) with W = exp(-j 2 pi / F).  POST therefore
+// computes the first row of Theta2 Theta1 only and MID transforms P11 and P12
+// only.
 // The host flattens the recursion of each N into an action list; one
 // workgroup per instance walks it.  Spectra stay in bit-reversed order.
 #include "k_launch.hpp"
@@ -128,22 +136,23 @@ __device__ __forceinline__ cd dot2(const cd* a, const cd* x, const cd* b, const 
 }
 
 // RB consecutive outputs t0.. of one polynomial of Theta2 Theta1 (shifted
-// form): R[t] = sum_j q1[j] p1[t-j] + q2[j] p2[t-1-j] with p1, p2 the padded
-// rows r1, r2 and origins o1, o2 (o2 already one lag back); the root adds the
-// second column one more lag back (rho = R21 + z R22), whose rows follow at
-// distance pe.
+// form) over the lags j < J: R[t] = sum_j q1[j] p1[t-j] + q2[j] p2[t-1-j] with
+// p1, p2 the padded rows r1, r2 and origins o1, o2 (o2 already one lag back);
+// the root adds the second column one more lag back (rho = R21 + z R22),
+// whose rows follow at distance pe.  Writes out[0..RB).
 template <int RB>
 __device__ __forceinline__ void post_block(const cd* q1, const cd* r1, int o1, const cd* q2,
                                            const cd* r2, int o2, int J, int t0, bool root,
-                                           int pe, int nout, cd* out) {
+                                           int pe, cd* out) {
   cd acc[RB];
 #pragma unroll
   for (int i = 0; i < RB; ++i) acc[i] = cd{0.0, 0.0};
-  conv2_block<RB>(q1, r1, o1, q2, r2, o2, J, t0, acc);
-  if (root) conv2_block<RB>(q1, r1 + pe, o1 - 1, q2, r2 + pe, o2 - 1, J, t0, acc);
+  if (J > 0) {
+    conv2_block<RB>(q1, r1, o1, q2, r2, o2, J, t0, acc);
+    if (root) conv2_block<RB>(q1, r1 + pe, o1 - 1, q2, r2 + pe, o2 - 1, J, t0, acc);
+  }
 #pragma unroll
-  for (int i = 0; i < RB; ++i)
-    if (t0 + i < nout) out[t0 + i] = acc[i];
+  for (int i = 0; i < RB; ++i) out[i] = acc[i];
 }
 
 // One Schur step on the moving window (lane r: U(n+1+r), V(n+r) at order n):
@@ -165,15 +174,27 @@ __device__ __forceinline__ void leaf_step(cd& U, cd& V, double& dlt, double& inv
   inv = inv * r1;
 }
 
-// W_F^f = exp(-j 2 pi f / F) for the bin at bit-reversed position p
-__device__ __forceinline__ cd zbin(const cd* __restrict__ tw, int logtw, int p, int logF) {
-  const int f = bitrev(p, logF);
+// W_F^e = exp(-j 2 pi e / F), 0 <= e < F, from the natural-order table
+__device__ __forceinline__ cd wpow(const cd* __restrict__ tw, int logtw, int e, int logF) {
   const int F = 1 << logF;
-  if (f >= (F >> 1)) {
-    const cd w = tw[(f - (F >> 1)) << (logtw - logF)];
+  if (e >= (F >> 1)) {
+    const cd w = tw[(e - (F >> 1)) << (logtw - logF)];
     return cd{-w.x, -w.y};
   }
-  return tw[f << (logtw - logF)];
+  return tw[e << (logtw - logF)];
+}
+// W_F^f for the bin at bit-reversed position p
+__device__ __forceinline__ cd zbin(const cd* __restrict__ tw, int logtw, int p, int logF) {
+  return wpow(tw, logtw, bitrev(p, logF), logF);
+}
+// Spectra of the second row of a Theta over m steps at bit-reversed bin p,
+// from those of the first row (symmetry above): s21 from s12, s22 from s11.
+__device__ __forceinline__ void second_row(const cd* __restrict__ tw, int logtw, int p, int logF,
+                                           int m, cd s11, cd s12, cd& s21, cd& s22) {
+  const int f = bitrev(p, logF);
+  const cd ph = wpow(tw, logtw, (f * (m - 1)) & ((1 << logF) - 1), logF);
+  s21 = cmul(ph, cconj(s12));
+  s22 = cmul(ph, cconj(s11));
 }
 
 __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ info,
@@ -319,7 +340,7 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
       if (act.type == SCH_MID) {
         // u2[r] = sum_j P11[j] u[m1+r-j] + P12[j] v[m1+r-j]
         // v2[r] = sum_j P21[j] u[m1-1+r-j] + P22[j] v[m1-1+r-j],  j < m1;
-        // outputs with 2 m2 <= SCH_NT/2 split their sum in two halves.
+        // each sum is split in sp parts so that the block's threads share it.
         for (int t = tid; t < 4 * m1; t += SCH_NT) A[t] = T1[(t / m1) * st1 + t % m1];
         for (int t = tid; t < m; t += SCH_NT) {
           Bf[t] = u[t];
@@ -327,7 +348,7 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
         }
         __syncthreads();
         const int nout = 2 * m2;
-        const int sp = nout <= SCH_NT / 2 ? 2 : 1;
+        const int sp = nout <= SCH_NT / 4 ? 4 : (nout <= SCH_NT / 2 ? 2 : 1);
         const int jh = (m1 + sp - 1) / sp;
         cd* part = Bf + 2 * m;
         for (int it = tid; it < nout * sp; it += SCH_NT) {
@@ -346,75 +367,100 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
         const int stw = L.mmax[cl];
         for (int o = tid; o < nout; o += SCH_NT) {
           cd acc = part[o];
-          if (sp == 2) acc = cadd(acc, part[nout + o]);
+          for (int h = 1; h < sp; ++h) acc = cadd(acc, part[h * nout + o]);
           const bool isv = o >= m2;
           W2[(isv ? stw + o - m2 : o)] = acc;
         }
         __syncthreads();
         continue;
       }
-      // POST / ROOT: row r of Theta2 Theta1 in the shifted form,
-      //   R_r1 = Q_r1 P11' + z Q_r2 P21',  R_r2 = Q_r1 P12' + z Q_r2 P22',
-      // as sliding-window sums over j < m2 against zero-padded P'.
+      // POST / ROOT in the shifted form, as sliding-window sums over j < m2
+      // against zero-padded P':
+      //   R11 = Q11 P11' + z Q12 P21',  R12 = Q11 P12' + z Q12 P22'
+      // (the second row follows by symmetry); the root needs
+      //   rho = R21 + z R22 = Q21 (P11' + z P12') + z Q22 (P21' + z P22').
+      // Each sum is split in nsp parts (partials after the operands).
       const int nout = root ? N : m;   // outputs per polynomial
-      const int npoly = root ? 1 : 4;
-      const int RB = (npoly * nout >= 1024) ? 4 : ((npoly * nout >= 512) ? 2 : 1);
-      const int lrb = RB == 4 ? 2 : (RB == 2 ? 1 : 0);
+      const int npoly = root ? 1 : 2;
+      const int RB = (npoly * nout >= 128) ? 2 : 1;
+      const int lrb = RB == 2 ? 1 : 0;
       const int PL = m2 + 8;                 // zeros below each P'
       const int pe = PL + m + 8;             // padded row length (multiple-of-RB skew)
       const int pes = pe + (pe >> lrb) * (RB > 1);  // skewed row length
       cd* Pext = A;                          // row q: P'_q(i) at skew(PL + i)
       cd* Q = A + 4 * pes + 8;               // 4 x m2
+      cd* part = Q + 4 * m2;
+      const int nblk = (nout + RB - 1) / RB;
+      const int nbr = nblk * RB;             // partial row length
+      const int avail = 2 * padded(L.Fmax) - (4 * pes + 8 + 4 * m2);
+      int nsp = 1;
+      while (nsp < 8 && npoly * nblk * 2 * nsp <= SCH_NT && npoly * nbr * 2 * nsp <= avail)
+        nsp *= 2;
+      const int jl = (m2 + nsp - 1) / nsp;
       for (int t = tid; t < 4 * pe; t += SCH_NT) {
         const int q = t / pe, k = t % pe, i = k - PL;
         const int sk = RB > 1 ? k + (k >> lrb) : k;
         Pext[q * pes + sk] = (i >= 0 && i < m1) ? T1[q * st1 + i] : cd{0.0, 0.0};
       }
-      for (int t = tid; t < 4 * m2; t += SCH_NT) Q[t] = T2[(t / m2) * st1 + t % m2];
+      const int qr0 = root ? 2 : 0;          // rows of Theta2 in use
+      for (int t = tid; t < 2 * m2; t += SCH_NT) Q[qr0 * m2 + t] = T2[(qr0 + t / m2) * st1 + t % m2];
       __syncthreads();
-      const int nblk = (nout + RB - 1) / RB;
-      for (int it = tid; it < npoly * nblk; it += SCH_NT) {
-        const int poly = root ? 2 : it / nblk;  // root: row 1 (R21 + z R22)
-        const int row = poly >> 1, col = poly & 1;
-        const int t0 = (it % nblk) * RB;
-        const cd* q1 = Q + (2 * row) * m2;
+      for (int it = tid; it < npoly * nblk * nsp; it += SCH_NT) {
+        const int h = it / (npoly * nblk), rem = it - h * (npoly * nblk);
+        const int pl = rem / nblk, t0 = (rem - pl * nblk) * RB;
+        const int col = root ? 0 : pl;
+        const int j0 = h * jl, j1 = min(j0 + jl, m2);
+        const cd* q1 = Q + qr0 * m2 + j0;
         const cd* q2 = q1 + m2;
         const cd* r1 = Pext + col * pes;         // P11' or P12'
         const cd* r2 = Pext + (2 + col) * pes;   // P21' or P22' (one lag)
-        cd* out = root ? rho + in.off : R + poly * st;
-        if (RB == 4) post_block<4>(q1, r1, PL, q2, r2, PL - 1, m2, t0, root, pes, nout, out);
-        else if (RB == 2) post_block<2>(q1, r1, PL, q2, r2, PL - 1, m2, t0, root, pes, nout, out);
-        else post_block<1>(q1, r1, PL, q2, r2, PL - 1, m2, t0, root, pes, nout, out);
+        cd* out = part + (h * npoly + pl) * nbr + t0;
+        if (RB == 2) post_block<2>(q1, r1, PL - j0, q2, r2, PL - 1 - j0, j1 - j0, t0, root, pes, out);
+        else post_block<1>(q1, r1, PL - j0, q2, r2, PL - 1 - j0, j1 - j0, t0, root, pes, out);
+      }
+      __syncthreads();
+      for (int o = tid; o < npoly * nout; o += SCH_NT) {
+        const int pl = o / nout, t = o - pl * nout;
+        cd acc = part[pl * nbr + t];
+        for (int h = 1; h < nsp; ++h) acc = cadd(acc, part[(h * npoly + pl) * nbr + t]);
+        if (root) {
+          rho[in.off + t] = acc;
+        } else {
+          R[pl * st + t] = acc;                         // R11, R12
+          R[(3 - pl) * st + (m - 1 - t)] = cconj(acc);  // R22, R21
+        }
       }
       __syncthreads();
       continue;
     }
     const int logF = act.logF, F = 1 << logF;
     const double invF = 1.0 / (double)F;
-    cd* S = scr + L.spec[act.level];  // Theta1 spectra, 4 x F
+    cd* S = scr + L.spec[act.level];  // spectra of Theta1's first row, 2 x F
     if (act.type == SCH_MID) {
-      // jobs 0, 1: spectra of the Theta1 polynomial pairs (to S); job 2: the window
-      for (int job = 0; job < 3; ++job) {
-        const cd* pa = job < 2 ? T1 + (2 * job) * st1 : u;
-        const cd* pb = job < 2 ? T1 + (2 * job + 1) * st1 : v;
-        const int lim = job < 2 ? m1 : m;
+      // job 0: spectra of P11 and P12 (to S); job 1: the window
+      for (int job = 0; job < 2; ++job) {
+        const cd* pa = job == 0 ? T1 : u;
+        const cd* pb = job == 0 ? T1 + st1 : v;
+        const int lim = job == 0 ? m1 : m;
         for (int t = tid; t < F; t += SCH_NT) {
           A[pidx(t)] = t < lim ? pa[t] : cd{0.0, 0.0};
           Bf[pidx(t)] = t < lim ? pb[t] : cd{0.0, 0.0};
         }
         __syncthreads();
         dif_fftn<SCH_NT>(A, Bf, 2, logF, false, false, s_tw, tws);
-        if (job < 2) {
+        if (job == 0) {
           for (int t = tid; t < F; t += SCH_NT) {
-            S[(int64_t)(2 * job) * F + t] = A[pidx(t)];
-            S[(int64_t)(2 * job + 1) * F + t] = Bf[pidx(t)];
+            S[t] = A[pidx(t)];
+            S[F + t] = Bf[pidx(t)];
           }
           __syncthreads();
         }
       }
       for (int p = tid; p < F; p += SCH_NT) {
         const cd fu = A[pidx(p)], fv = Bf[pidx(p)];
-        const cd s11 = S[p], s12 = S[F + p], s21 = S[2 * F + p], s22 = S[3 * F + p];
+        const cd s11 = S[p], s12 = S[F + p];
+        cd s21, s22;
+        second_row(tw, logtw, p, logF, m1, s11, s12, s21, s22);
         A[pidx(p)] = cfma(s12, fv, cmul(s11, fu));
         Bf[pidx(p)] = cfma(s22, fv, cmul(s21, fu));
       }
@@ -430,39 +476,45 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
       __syncthreads();
       continue;
     }
-    // POST / ROOT: Theta = Theta2 Theta1, one row at a time (root: row 2 only)
-    for (int row = root ? 1 : 0; row < 2; ++row) {
-      for (int t = tid; t < F; t += SCH_NT) {
-        A[pidx(t)] = (t < m2) ? T2[(2 * row) * st1 + t] : cd{0.0, 0.0};
-        Bf[pidx(t)] = (t < m2) ? T2[(2 * row + 1) * st1 + t] : cd{0.0, 0.0};
-      }
-      __syncthreads();
-      dif_fftn<SCH_NT>(A, Bf, 2, logF, false, false, s_tw, tws);
-      for (int p = tid; p < F; p += SCH_NT) {
-        const cd zb = zbin(tw, logtw, p, logF);
-        const cd a1 = A[pidx(p)], a2 = cmul(Bf[pidx(p)], zb);  // z * second poly
-        const cd s11 = S[p], s12 = S[F + p], s21 = S[2 * F + p], s22 = S[3 * F + p];
-        const cd r1 = cfma(a2, s21, cmul(a1, s11));   // row . column 1
-        const cd r2 = cfma(a2, s22, cmul(a1, s12));   // row . column 2 (shifted)
-        if (root) {
-          A[pidx(p)] = cfma(r2, zb, r1);  // rho = R21 + z R22'
-        } else {
-          A[pidx(p)] = r1;
-          Bf[pidx(p)] = r2;
-        }
-      }
-      __syncthreads();
-      dit_fftn<SCH_NT>(A, Bf, root ? 1 : 2, logF, true, true, s_tw, tws);
-      if (root) {
-        for (int t = tid; t < N; t += SCH_NT) rho[in.off + t] = cscale(A[pidx(t)], invF);
-      } else {
-        for (int t = tid; t < m; t += SCH_NT) {
-          R[(2 * row) * st + t] = cscale(A[pidx(t)], invF);
-          R[(2 * row + 1) * st + t] = cscale(Bf[pidx(t)], invF);
-        }
-      }
-      __syncthreads();
+    // POST / ROOT: one row of Theta = Theta2 Theta1, the first (the second
+    // follows by symmetry), or for the root the second, whose
+    // rho = R21 + z R22.
+    const int row = root ? 1 : 0;
+    for (int t = tid; t < F; t += SCH_NT) {
+      A[pidx(t)] = (t < m2) ? T2[(2 * row) * st1 + t] : cd{0.0, 0.0};
+      Bf[pidx(t)] = (t < m2) ? T2[(2 * row + 1) * st1 + t] : cd{0.0, 0.0};
     }
+    __syncthreads();
+    dif_fftn<SCH_NT>(A, Bf, 2, logF, false, false, s_tw, tws);
+    for (int p = tid; p < F; p += SCH_NT) {
+      const cd zb = zbin(tw, logtw, p, logF);
+      const cd a1 = A[pidx(p)], a2 = cmul(Bf[pidx(p)], zb);  // z * second poly
+      const cd s11 = S[p], s12 = S[F + p];
+      cd s21, s22;
+      second_row(tw, logtw, p, logF, m1, s11, s12, s21, s22);
+      const cd r1 = cfma(a2, s21, cmul(a1, s11));   // row . column 1
+      const cd r2 = cfma(a2, s22, cmul(a1, s12));   // row . column 2 (shifted)
+      if (root) {
+        A[pidx(p)] = cfma(r2, zb, r1);  // rho = R21 + z R22'
+      } else {
+        A[pidx(p)] = r1;
+        Bf[pidx(p)] = r2;
+      }
+    }
+    __syncthreads();
+    dit_fftn<SCH_NT>(A, Bf, root ? 1 : 2, logF, true, true, s_tw, tws);
+    if (root) {
+      for (int t = tid; t < N; t += SCH_NT) rho[in.off + t] = cscale(A[pidx(t)], invF);
+    } else {
+      for (int t = tid; t < m; t += SCH_NT) {
+        const cd r11 = cscale(A[pidx(t)], invF), r12 = cscale(Bf[pidx(t)], invF);
+        R[t] = r11;
+        R[st + t] = r12;
+        R[2 * st + (m - 1 - t)] = cconj(r12);
+        R[3 * st + (m - 1 - t)] = cconj(r11);
+      }
+    }
+    __syncthreads();
   }
   if (tid == 0) {
     const bool ok = s_fail < 0;
