@@ -5,8 +5,11 @@
 // algorithm until it needs the next evaluation, which it requests by writing
 // the evaluation point and request bits; or it finishes and writes outputs.
 //
-// Plain C++ (no device intrinsics) so the same code runs in the device
-// driver kernel; all per-instance arrays live in device memory.
+// Plain C++ templated on a team: the lanes that run one instance together.
+// Every lane of a team runs the same scalar logic on the same values, loops
+// over the instance's vectors are strided over the lanes, and team reductions
+// return the same bits in every lane, so all lanes take the same branches.
+// The device kernel uses one wave as the team; the host build one thread.
 #pragma once
 #include <math.h>
 #include <stdint.h>
@@ -122,10 +125,23 @@ SFLS_HD inline bool act_criterion(double q2, double s, double gb, double zeta, d
   return kap > rhs;
 }
 
+// One thread as the team (host build).
+struct SerialTeam {
+  SFLS_HD static int lane() { return 0; }
+  SFLS_HD static int width() { return 1; }
+  SFLS_HD static double sum(double v) { return v; }
+  SFLS_HD static double max(double v) { return v; }
+  SFLS_HD static double min(double v) { return v; }
+  SFLS_HD static int imin(int v) { return v; }
+  SFLS_HD static bool any(bool b) { return b; }
+  SFLS_HD static void sync() {}
+};
+
 // A polish line search tries at most this many step lengths (alpha >= 2^-8 of
 // the first); a step that needs more is in the rounding noise of the objective.
 constexpr int kPolishLsTrials = 9;
 
+template <typename T>
 struct Driver {
   const DrvParams& P;
   DrvState& S;
@@ -140,8 +156,8 @@ struct Driver {
   SFLS_HD double gbar() const {
     if (S.K == 0) return -1.0;
     double s = 0.0;
-    for (int k = 0; k < S.K; ++k) s += A.ga[k];
-    return s / (double)S.K;
+    for (int k = T::lane(); k < S.K; k += T::width()) s += A.ga[k];
+    return T::sum(s) / (double)S.K;
   }
 
   // request an evaluation at the current point (th, ga, beta).  When the
@@ -149,7 +165,7 @@ struct Driver {
   // and active vectors are still in place and only the grid stage runs.
   SFLS_HD void request_current(int32_t bits) {
     if (S.cur_valid) bits &= ~1;  // REQ_EVAL
-    for (int k = 0; k < S.K; ++k) { A.th_e[k] = A.th[k]; A.ga_e[k] = A.ga[k]; }
+    for (int k = T::lane(); k < S.K; k += T::width()) { A.th_e[k] = A.th[k]; A.ga_e[k] = A.ga[k]; }
     *A.K_e = S.K;
     *A.beta_e = S.beta;
     *A.gbar_e = gbar();
@@ -170,8 +186,7 @@ struct Driver {
     const double* __restrict__ et = A.ev_t;
     const double* __restrict__ ev = A.ev_v;
     const double* __restrict__ ex = A.ev_x;
-#pragma unroll 4
-    for (int k = 0; k < K; ++k) {
+    for (int k = T::lane(); k < K; k += T::width()) {
       const double qr = eq[2 * k], qi = eq[2 * k + 1];
       const double rr = er[2 * k], ri = er[2 * k + 1];
       const double ur = eu[2 * k], ui = eu[2 * k + 1];
@@ -204,26 +219,17 @@ struct Driver {
         (void)xi;
       }
     }
+    T::sync();
   }
 
-  // The loops below run in one thread over device memory: restrict-qualified
-  // locals and unrolling let the loads of several elements be in flight.
   SFLS_HD double dot(const double* __restrict__ a, const double* __restrict__ b, int n) const {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int i = 0;
-    for (; i + 4 <= n; i += 4) {
-      s0 += a[i] * b[i];
-      s1 += a[i + 1] * b[i + 1];
-      s2 += a[i + 2] * b[i + 2];
-      s3 += a[i + 3] * b[i + 3];
-    }
-    for (; i < n; ++i) s0 += a[i] * b[i];
-    return (s0 + s1) + (s2 + s3);
+    double s = 0.0;
+    for (int i = T::lane(); i < n; i += T::width()) s += a[i] * b[i];
+    return T::sum(s);
   }
   // d += a * x
   SFLS_HD static void axpy(double a, const double* __restrict__ x, double* __restrict__ d, int n) {
-#pragma unroll 8
-    for (int e = 0; e < n; ++e) d[e] += a * x[e];
+    for (int e = T::lane(); e < n; e += T::width()) d[e] += a * x[e];
   }
 
   SFLS_HD void mem_reset() { S.mem_n = 0; S.mem_head = 0; }
@@ -240,8 +246,7 @@ struct Driver {
     const int slot = S.mem_head;
     double* __restrict__ ds = mem_s(slot);
     double* __restrict__ dy = mem_y(slot);
-#pragma unroll 8
-    for (int i = 0; i < n; ++i) { ds[i] = s[i]; dy[i] = y[i]; }
+    for (int i = T::lane(); i < n; i += T::width()) { ds[i] = s[i]; dy[i] = y[i]; }
     A.rhom[slot] = 1.0 / sy;
     S.mem_head = (S.mem_head + 1) % J;
     if (S.mem_n < J) S.mem_n += 1;
@@ -251,32 +256,34 @@ struct Driver {
   // (after a reset) when the result is not a descent direction.
   SFLS_HD void direction(const double* __restrict__ g, const double* __restrict__ h,
                          double* __restrict__ d, int n) {
-#pragma unroll 8
-    for (int i = 0; i < n; ++i) d[i] = g[i];
+    for (int i = T::lane(); i < n; i += T::width()) d[i] = g[i];
     for (int i = S.mem_n - 1; i >= 0; --i) {
       const int sl = mem_slot(i);
       const double a = A.rhom[sl] * dot(mem_s(sl), d, n);
       A.am[sl] = a;
       axpy(-a, mem_y(sl), d, n);
     }
-#pragma unroll 8
-    for (int e = 0; e < n; ++e) d[e] /= h[e];
+    for (int e = T::lane(); e < n; e += T::width()) d[e] /= h[e];
     for (int i = 0; i < S.mem_n; ++i) {
       const int sl = mem_slot(i);
       const double bta = A.rhom[sl] * dot(mem_y(sl), d, n);
       axpy(A.am[sl] - bta, mem_s(sl), d, n);
     }
-    bool ok = true;
+    bool bad = false;
     double gd = 0.0;
-    for (int e = 0; e < n; ++e) {
-      d[e] = -d[e];
-      if (!(d[e] == d[e]) || isinf(d[e])) ok = false;
-      gd += g[e] * d[e];
+    for (int e = T::lane(); e < n; e += T::width()) {
+      const double de = -d[e];
+      d[e] = de;
+      if (!(de == de) || isinf(de)) bad = true;
+      gd += g[e] * de;
     }
+    const bool ok = !T::any(bad);
+    gd = T::sum(gd);
     if (!ok || gd >= 0.0) {
       mem_reset();
-      for (int e = 0; e < n; ++e) d[e] = -g[e] / h[e];
+      for (int e = T::lane(); e < n; e += T::width()) d[e] = -g[e] / h[e];
     }
+    T::sync();
   }
 
   // set up a line search from the current point along d
@@ -284,17 +291,20 @@ struct Driver {
     const int K = S.K;
     const double* d = A.d;
     S.gd = dot(A.g, d, 2 * K);
+    // largest step keeping every gamma >= 0, and the first k reaching it
     double amax = INFINITY;
     int kstar = -1;
-    for (int k = 0; k < K; ++k) {
+    for (int k = T::lane(); k < K; k += T::width()) {
       const double dg = d[K + k];
       if (dg < 0.0) {
         const double r = A.ga[k] / (-dg);
         if (r < amax) { amax = r; kstar = k; }
       }
     }
-    S.amax = amax;
-    S.kstar = kstar;
+    const double am = T::min(amax);
+    kstar = T::imin((kstar >= 0 && amax == am) ? kstar : INT32_MAX);
+    S.amax = am;
+    S.kstar = kstar == INT32_MAX ? -1 : kstar;
     if (polish) S.alpha = (amax > 1.0) ? 1.0 : 0.5 * amax;
     else S.alpha = fmin(1.0, amax);
     S.ls_trial = 0;
@@ -303,15 +313,16 @@ struct Driver {
 
   SFLS_HD void ls_request() {
     const int K = S.K;
-    for (int k = 0; k < K; ++k) {
+    // the component that limits a full step lands on gamma = 0 exactly
+    const int kz = (!S.polish && S.alpha == S.amax) ? S.kstar : -1;
+    for (int k = T::lane(); k < K; k += T::width()) {
       double t = A.th[k] + S.alpha * A.d[k];
       t = t - floor(t);
       if (t >= 1.0) t = 0.0;
       A.th_e[k] = t;
       double gk = A.ga[k] + S.alpha * A.d[K + k];
-      A.ga_e[k] = gk > 0.0 ? gk : 0.0;
+      A.ga_e[k] = (k == kz) ? 0.0 : (gk > 0.0 ? gk : 0.0);
     }
-    if (!S.polish && S.alpha == S.amax && S.kstar >= 0) A.ga_e[S.kstar] = 0.0;
     *A.K_e = K;
     *A.beta_e = S.beta;
     *A.gbar_e = gbar();
@@ -321,8 +332,16 @@ struct Driver {
     S.cur_valid = 0;
   }
 
+  // Drops component k, shifting those above it down by one.  Strided over the
+  // lanes: each lane loads before it stores, and the stores of one chunk lie
+  // below the loads of the next.
   SFLS_HD void remove_component(int k) {
-    for (int j = k; j + 1 < S.K; ++j) { A.th[j] = A.th[j + 1]; A.ga[j] = A.ga[j + 1]; }
+    for (int j = k + T::lane(); j + 1 < S.K; j += T::width()) {
+      const double t = A.th[j + 1], g = A.ga[j + 1];
+      A.th[j] = t;
+      A.ga[j] = g;
+    }
+    T::sync();
     S.K -= 1;
   }
 
@@ -330,7 +349,7 @@ struct Driver {
     const double thr = (S.zeta > 0.0) ? log((1.0 - S.zeta) / S.zeta) : INFINITY;
     int best = -1;
     double bm = 0.0;
-    for (int k = 0; k < S.K; ++k) {
+    for (int k = T::lane(); k < S.K; k += T::width()) {
       const double gk = A.ga[k];
       double margin;
       if (!(gk > 0.0)) {
@@ -345,7 +364,10 @@ struct Driver {
       }
       if (margin > 0.0 && (best < 0 || margin > bm)) { best = k; bm = margin; }
     }
-    return best;
+    // the largest margin, and the first k with it
+    const double gm = T::max(best >= 0 ? bm : -INFINITY);
+    best = T::imin((best >= 0 && bm == gm) ? best : INT32_MAX);
+    return best == INT32_MAX ? -1 : best;
   }
 
   // FP64 decision quantities at candidate c (index into cand arrays)
@@ -372,7 +394,11 @@ struct Driver {
     return 1;
   }
 
-  // approximate sweep over cand[1..ncand-1]; returns number added
+  // approximate sweep over cand[1..ncand-1]; returns number added.  The
+  // qualifying candidates are taken in increasing (Delta L, grid index)
+  // order; each is added unless it lies within approx_min_dist / N of a
+  // component.  cbuf_dl / cbuf_gh hold Delta L and gamma_hat per candidate,
+  // gamma_hat < 0 marking one that does not qualify or was taken.
   SFLS_HD int approx_decide() {
     const int nc = *A.ncand;
     double q2, s;
@@ -381,47 +407,54 @@ struct Driver {
     const double dlmin = delta_L(q2, s, gb0, S.zeta);
     const double tau = P.approx_use_tau ? P.tau : 0.0;
     const double gbf = gbar();
-    int m = 0;
-    for (int c = 1; c < nc; ++c) {
-      cand_q2s(c, q2, s);
-      const double gh = gamma_hat(q2, s);
+    double nq = 0.0;
+    for (int c = 1 + T::lane(); c < nc; c += T::width()) {
+      double q2c, sc;
+      cand_q2s(c, q2c, sc);
+      const double gh = gamma_hat(q2c, sc);
       const double gb = (S.K == 0) ? gh : gbf;
-      const double dl = delta_L(q2, s, gb, S.zeta);
-      if (gh > 0.0 && S.zeta > 0.0 && act_criterion(q2, s, gb, S.zeta, tau) &&
-          dl <= dlmin / P.approx_ratio) {
-        // insertion by (dl, l)
-        const int l = A.cand[c];
-        int pos = m;
-        while (pos > 0 && (A.cbuf_dl[pos - 1] > dl ||
-                           (A.cbuf_dl[pos - 1] == dl && A.cbuf_l[pos - 1] > l))) {
-          A.cbuf_dl[pos] = A.cbuf_dl[pos - 1];
-          A.cbuf_l[pos] = A.cbuf_l[pos - 1];
-          A.cbuf_gh[pos] = A.cbuf_gh[pos - 1];
-          --pos;
-        }
-        A.cbuf_dl[pos] = dl;
-        A.cbuf_l[pos] = l;
-        A.cbuf_gh[pos] = gh;
-        ++m;
-      }
+      const double dl = delta_L(q2c, sc, gb, S.zeta);
+      const bool ok = gh > 0.0 && S.zeta > 0.0 && act_criterion(q2c, sc, gb, S.zeta, tau) &&
+                      dl <= dlmin / P.approx_ratio;
+      A.cbuf_dl[c] = dl;
+      A.cbuf_gh[c] = ok ? gh : -1.0;
+      nq += ok ? 1.0 : 0.0;
     }
-    const int K0 = S.K;
+    T::sync();
+    const int m = (int)T::sum(nq);
     int added = 0;
     const double mind = P.approx_min_dist / (double)N;
     for (int i = 0; i < m; ++i) {
       if (S.K >= A.kcap || S.K >= N) { S.cap_hit = 1; break; }
-      const double th = (double)A.cbuf_l[i] / (double)A.L;
-      bool far = true;
-      for (int k = 0; k < S.K; ++k)
-        if (!(wrapd(th, A.th[k]) >= mind)) { far = false; break; }
-      if (far) {
+      // next qualifying candidate: smallest Delta L, then smallest grid index
+      double dlo = INFINITY;
+      int lo = INT32_MAX;
+      for (int c = 1 + T::lane(); c < nc; c += T::width()) {
+        if (!(A.cbuf_gh[c] > 0.0)) continue;
+        const double dl = A.cbuf_dl[c];
+        const int l = A.cand[c];
+        if (dl < dlo || (dl == dlo && l < lo)) { dlo = dl; lo = l; }
+      }
+      const double dmin = T::min(dlo);
+      const int l = T::imin(dlo == dmin ? lo : INT32_MAX);
+      int cl = INT32_MAX;  // its candidate slot
+      for (int c = 1 + T::lane(); c < nc; c += T::width())
+        if (A.cbuf_gh[c] > 0.0 && A.cand[c] == l && A.cbuf_dl[c] == dmin) cl = c;
+      cl = T::imin(cl);
+      const double gh = A.cbuf_gh[cl];
+      A.cbuf_gh[cl] = -1.0;
+      T::sync();
+      const double th = (double)l / (double)A.L;
+      bool near = false;
+      for (int k = T::lane(); k < S.K; k += T::width())
+        if (!(wrapd(th, A.th[k]) >= mind)) near = true;
+      if (!T::any(near)) {
         A.th[S.K] = th;
-        A.ga[S.K] = A.cbuf_gh[i];
+        A.ga[S.K] = gh;
         S.K += 1;
         ++added;
       }
     }
-    (void)K0;
     return added;
   }
 
@@ -430,28 +463,20 @@ struct Driver {
   SFLS_HD void finish(bool saved) {
     const int K = S.K;
     const double* q = saved ? A.q_save : A.ev_q;
-    // alpha = gamma .* q at the final point; sort by theta (insertion)
-    for (int k = 0; k < K; ++k) {
-      A.out_theta[k] = A.th[k];
-      A.out_gamma[k] = A.ga[k];
-      A.out_alpha[2 * k] = A.ga[k] * q[2 * k];
-      A.out_alpha[2 * k + 1] = A.ga[k] * q[2 * k + 1];
-    }
-    for (int i = 1; i < K; ++i) {
-      const double t = A.out_theta[i], gg = A.out_gamma[i];
-      const double ar = A.out_alpha[2 * i], ai = A.out_alpha[2 * i + 1];
-      int j = i;
-      while (j > 0 && A.out_theta[j - 1] > t) {
-        A.out_theta[j] = A.out_theta[j - 1];
-        A.out_gamma[j] = A.out_gamma[j - 1];
-        A.out_alpha[2 * j] = A.out_alpha[2 * (j - 1)];
-        A.out_alpha[2 * j + 1] = A.out_alpha[2 * (j - 1) + 1];
-        --j;
+    T::sync();
+    // alpha = gamma .* q at the final point, sorted by theta (stable: the
+    // rank of k counts smaller thetas and equal ones before k)
+    for (int k = T::lane(); k < K; k += T::width()) {
+      const double t = A.th[k];
+      int r = 0;
+      for (int j = 0; j < K; ++j) {
+        const double tj = A.th[j];
+        r += (tj < t || (tj == t && j < k)) ? 1 : 0;
       }
-      A.out_theta[j] = t;
-      A.out_gamma[j] = gg;
-      A.out_alpha[2 * j] = ar;
-      A.out_alpha[2 * j + 1] = ai;
+      A.out_theta[r] = t;
+      A.out_gamma[r] = A.ga[k];
+      A.out_alpha[2 * r] = A.ga[k] * q[2 * k];
+      A.out_alpha[2 * r + 1] = A.ga[k] * q[2 * k + 1];
     }
     *A.out_K = K;
     *A.out_beta = S.beta;
@@ -483,7 +508,7 @@ struct Driver {
       // the factorisation failed at the requested point: stop with what we have
       S.status = -4;
       *A.out_K = S.K;
-      for (int k = 0; k < S.K; ++k) {
+      for (int k = T::lane(); k < S.K; k += T::width()) {
         A.out_theta[k] = A.th[k];
         A.out_gamma[k] = A.ga[k];
         A.out_alpha[2 * k] = 0.0;
@@ -587,7 +612,8 @@ struct Driver {
         case L_BETA_DO: {
           // eq. betaUpdate with mu = gamma.q, tr = beta sum gamma s, ||y - A mu||^2 = beta^2 ||w||^2
           double tr = 0.0;
-          for (int k = 0; k < S.K; ++k) tr += A.ga[k] * A.ev_s[2 * k];
+          for (int k = T::lane(); k < S.K; k += T::width()) tr += A.ga[k] * A.ev_s[2 * k];
+          tr = T::sum(tr);
           double bn = (S.beta * tr + S.beta * S.beta * (*A.ww)) / (double)N;
           if (!(bn > S.eps_beta)) bn = S.eps_beta;
           if (bn != S.beta) { S.beta = bn; S.cur_valid = 0; }
@@ -624,14 +650,19 @@ struct Driver {
             // accept: pair (alpha d, g_t - g), move to the trial point
             const int K = S.K, n = 2 * K;
             derivs(A.ga_e, A.gt, nullptr);
-            for (int e = 0; e < n; ++e) { A.gt[e] -= A.g[e]; A.d[e] *= S.alpha; }
+            for (int e = T::lane(); e < n; e += T::width()) {
+              A.gt[e] -= A.g[e];
+              A.d[e] *= S.alpha;
+            }
             mem_push(A.d, A.gt, n);
             double maxdth = 0.0;
-            for (int k = 0; k < K; ++k) {
+            for (int k = T::lane(); k < K; k += T::width()) {
               maxdth = fmax(maxdth, fabs(A.d[k]));
               A.th[k] = A.th_e[k];
               A.ga[k] = A.ga_e[k];
             }
+            T::sync();
+            maxdth = T::max(maxdth);
             S.cur_valid = 1;
             if (S.polish) {
               S.pit += 1;
@@ -649,7 +680,8 @@ struct Driver {
             // the polish stops once the shortened step moves no frequency by
             // the polish tolerance
             double dmax = 0.0;
-            for (int k = 0; k < S.K; ++k) dmax = fmax(dmax, fabs(A.d[k]));
+            for (int k = T::lane(); k < S.K; k += T::width()) dmax = fmax(dmax, fabs(A.d[k]));
+            dmax = T::max(dmax);
             give_up = S.alpha * dmax < P.polish_tol / (double)N || S.ls_trial >= kPolishLsTrials;
           }
           if (!S.polish && !give_up) {
@@ -723,7 +755,7 @@ struct Driver {
           derivs(A.ga, A.g, A.gt);
           direction(A.g, A.gt, A.d, n);
           S.f_cur = f_of_eval();
-          for (int e = 0; e < n; ++e) A.q_save[e] = A.ev_q[e];
+          for (int e = T::lane(); e < n; e += T::width()) A.q_save[e] = A.ev_q[e];
           S.saved = 1;
           ls_begin(true);
           ls_request();

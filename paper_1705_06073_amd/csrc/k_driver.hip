@@ -4,11 +4,53 @@
 
 namespace sfls {
 
+// One wave as the driver's team.  The folds combine lanes in an xor-butterfly
+// (every step pairs the same two operands in either order) and finish in
+// scalar registers, so every lane holds the same bits.
+template <typename Op>
+__device__ __forceinline__ double wave_fold(double v, Op op) {
+  v = op(v, dpp_f64<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = op(v, dpp_f64<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = op(v, dpp_f64<0x141>(v));  // row_half_mirror
+  v = op(v, dpp_f64<0x140>(v));  // row_mirror
+  const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
+  const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+  return op(op(r0, r1), op(r2, r3));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+struct WaveTeam {
+  __device__ static int lane() { return threadIdx.x & 63; }
+  __device__ static int width() { return 64; }
+  __device__ static double sum(double v) { return wave_sum(v); }
+  __device__ static double max(double v) {
+    return wave_fold(v, [](double a, double b) { return fmax(a, b); });
+  }
+  __device__ static double min(double v) {
+    return wave_fold(v, [](double a, double b) { return fmin(a, b); });
+  }
+  __device__ static int imin(int v) {
+    v = ::min(v, dpp_i32<0xB1>(v));
+    v = ::min(v, dpp_i32<0x4E>(v));
+    v = ::min(v, dpp_i32<0x141>(v));
+    v = ::min(v, dpp_i32<0x140>(v));
+    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return ::min(::min(r0, r1), ::min(r2, r3));
+  }
+  __device__ static bool any(bool b) { return __ballot(b) != 0; }
+  // lanes exchange data through memory: keep the compiler from reordering
+  // accesses across this point (a wave's accesses reach memory in order)
+  __device__ static void sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+};
+
 __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info,
                                                const DrvParams* __restrict__ prm, DrvPools p,
                                                int B) {
   const int b = blockIdx.x;
-  if (b >= B || threadIdx.x != 0) return;
+  if (b >= B) return;
   const InstInfo in = info[b];
   DrvState S = p.st[b];
   if (S.phase == PH_DONE) return;
@@ -64,10 +106,12 @@ __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info
   A.out_iters = p.out_iters + b;
   A.out_evals = p.out_evals ? p.out_evals + b : nullptr;
   A.out_status = p.out_status + b;
-  Driver drv(*prm, S, A);
+  Driver<WaveTeam> drv(*prm, S, A);
   drv.step();
-  p.st[b] = S;
-  if (S.phase != PH_DONE) atomicAdd(p.notdone, 1);
+  if (threadIdx.x == 0) {
+    p.st[b] = S;
+    if (S.phase != PH_DONE) atomicAdd(p.notdone, 1);
+  }
 }
 
 // ||y||^2 per instance and the initial state (phase START).

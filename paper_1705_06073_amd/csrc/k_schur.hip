@@ -42,9 +42,10 @@ namespace sfls {
 constexpr int SCH_NT = 512;
 constexpr int SCH_LEAF = 64;
 
+// lane r <- lane r-1 (lane 0 <- 0)
 __device__ __forceinline__ double shr1d(double v) {
-  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
-  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, false);
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, true);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ cd shr1c(cd v) { return cd{shr1d(v.x), shr1d(v.y)}; }

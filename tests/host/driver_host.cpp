@@ -14,7 +14,7 @@ int drv_sizes(int* out) {
   return 3;
 }
 void drv_step(const sfls::DrvParams* P, sfls::DrvState* S, const sfls::DrvArrays* A) {
-  sfls::Driver d(*P, *S, *A);
+  sfls::Driver<sfls::SerialTeam> d(*P, *S, *A);
   d.step();
 }
 }
