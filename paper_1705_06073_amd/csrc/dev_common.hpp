@@ -285,6 +285,72 @@ __device__ __forceinline__ void dit_fftn(C* x, C* y, int na, int logn, bool cx, 
   }
 }
 
+// One wave's transform of size 2^logn in its own LDS buffer (padded layout,
+// same kernels and orders as above).  The lanes exchange data through LDS
+// between passes without a workgroup barrier: a wave's LDS accesses are
+// performed in program order, and wave_sync keeps the compiler from moving
+// accesses across a pass boundary.  Groups are sized so that the 64 lanes
+// share each pass.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ __forceinline__ int wave_ks_max(int logn) {
+  return logn >= 10 ? 4 : (logn == 9 ? 3 : 2);
+}
+template <typename C>
+__device__ __forceinline__ void wave_dif(C* z, int logn, bool cj, const C* __restrict__ tl,
+                                         const C* __restrict__ tg, int lane) {
+  const int km = wave_ks_max(logn);
+  int lh = logn - 1;
+  while (lh >= 0) {
+    const int ks = lh + 1 < km ? lh + 1 : km;
+    const int tot = 1 << (logn - ks);
+    const bool lds_tw = (2 << lh) <= FFT_TWL;
+    for (int g = lane; g < tot; g += 64) {
+      if (!lds_tw) {
+        dif_group<4>(z, g, lh, tg, cj);
+        continue;
+      }
+      switch (ks) {
+        case 4: dif_group<4>(z, g, lh, tl, cj); break;
+        case 3: dif_group<3>(z, g, lh, tl, cj); break;
+        case 2: dif_group<2>(z, g, lh, tl, cj); break;
+        default: dif_group<1>(z, g, lh, tl, cj); break;
+      }
+    }
+    wave_sync();
+    lh -= ks;
+  }
+}
+template <typename C>
+__device__ __forceinline__ void wave_dit(C* z, int logn, bool cj, const C* __restrict__ tl,
+                                         const C* __restrict__ tg, int lane) {
+  const int km = wave_ks_max(logn);
+  const int rem = logn % km;
+  int lb = 0;
+  while (lb < logn) {
+    const int ks = (lb == 0 && rem) ? rem : km;
+    const int tot = 1 << (logn - ks);
+    const bool lds_tw = (2 << (lb + ks - 1)) <= FFT_TWL;
+    for (int g = lane; g < tot; g += 64) {
+      if (!lds_tw) {
+        dit_group<4>(z, g, lb, tg, cj);
+        continue;
+      }
+      switch (ks) {
+        case 4: dit_group<4>(z, g, lb, tl, cj); break;
+        case 3: dit_group<3>(z, g, lb, tl, cj); break;
+        case 2: dit_group<2>(z, g, lb, tl, cj); break;
+        default: dit_group<1>(z, g, lb, tl, cj); break;
+      }
+    }
+    wave_sync();
+    lb += ks;
+  }
+}
+
 // Copy the head of the stage-major twiddle table to LDS (caller syncs).
 template <int NT, typename C>
 __device__ __forceinline__ void load_tw_head(C* tl, const C* __restrict__ tg) {

@@ -41,6 +41,8 @@ namespace sfls {
 
 constexpr int SCH_NT = 512;
 constexpr int SCH_LEAF = 64;
+// transform merges of F <= 2^SCH_WAVE_LOG give each transform to one wave
+constexpr int SCH_WAVE_LOG = 10;
 
 // lane r <- lane r-1 (lane 0 <- 0)
 __device__ __forceinline__ double shr1d(double v) {
@@ -437,6 +439,88 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
     const int logF = act.logF, F = 1 << logF;
     const double invF = 1.0 / (double)F;
     cd* S = scr + L.spec[act.level];  // spectra of Theta1's first row, 2 x F
+    const int zs = pidx(F);          // buffer stride of the one-wave transforms
+    if (logF <= SCH_WAVE_LOG &&
+        (act.type != SCH_MID || 4 * zs <= 2 * padded(L.Fmax))) {
+      // One wave per transform, block barriers only around the pointwise step.
+      cd* Z = lds;
+      if (act.type == SCH_MID) {
+        // waves 0-3: spectra of P11, P12 (kept in S) and of the window u, v
+        if (wv < 4) {
+          const cd* src = wv == 0 ? T1 : (wv == 1 ? T1 + st1 : (wv == 2 ? u : v));
+          const int lim = wv < 2 ? m1 : m;
+          cd* z = Z + wv * zs;
+          for (int t = lane; t < F; t += 64) z[pidx(t)] = t < lim ? src[t] : cd{0.0, 0.0};
+          wave_sync();
+          wave_dif(z, logF, false, s_tw, tws, lane);
+          if (wv < 2)
+            for (int t = lane; t < F; t += 64) S[(int64_t)wv * F + t] = z[pidx(t)];
+        }
+        __syncthreads();
+        for (int p = tid; p < F; p += SCH_NT) {
+          const cd s11 = Z[pidx(p)], s12 = Z[zs + pidx(p)];
+          const cd fu = Z[2 * zs + pidx(p)], fv = Z[3 * zs + pidx(p)];
+          cd s21, s22;
+          second_row(tw, logtw, p, logF, m1, s11, s12, s21, s22);
+          Z[2 * zs + pidx(p)] = cfma(s12, fv, cmul(s11, fu));
+          Z[3 * zs + pidx(p)] = cfma(s22, fv, cmul(s21, fu));
+        }
+        __syncthreads();
+        // waves 2, 3: P1 and P2, and from them the right child's window
+        if (wv == 2 || wv == 3) {
+          cd* z = Z + wv * zs;
+          wave_dit(z, logF, true, s_tw, tws, lane);
+          cd* W2 = scr + L.win[cl] + (wv == 3 ? L.mmax[cl] : 0);
+          const int o = wv == 2 ? m1 : m1 - 1;
+          for (int r = lane; r < m2; r += 64) W2[r] = cscale(z[pidx(o + r)], invF);
+        }
+        __syncthreads();
+        continue;
+      }
+      // POST / ROOT (one row as below): waves 0, 1 transform the row of Theta2
+      const int row = root ? 1 : 0;
+      if (wv < 2) {
+        const cd* src = T2 + (2 * row + wv) * st1;
+        cd* z = Z + wv * zs;
+        for (int t = lane; t < F; t += 64) z[pidx(t)] = t < m2 ? src[t] : cd{0.0, 0.0};
+        wave_sync();
+        wave_dif(z, logF, false, s_tw, tws, lane);
+      }
+      __syncthreads();
+      for (int p = tid; p < F; p += SCH_NT) {
+        const cd zb = zbin(tw, logtw, p, logF);
+        const cd a1 = Z[pidx(p)], a2 = cmul(Z[zs + pidx(p)], zb);
+        const cd s11 = S[p], s12 = S[F + p];
+        cd s21, s22;
+        second_row(tw, logtw, p, logF, m1, s11, s12, s21, s22);
+        const cd r1 = cfma(a2, s21, cmul(a1, s11));
+        const cd r2 = cfma(a2, s22, cmul(a1, s12));
+        if (root) {
+          Z[pidx(p)] = cfma(r2, zb, r1);
+        } else {
+          Z[pidx(p)] = r1;
+          Z[zs + pidx(p)] = r2;
+        }
+      }
+      __syncthreads();
+      if (root) {
+        if (wv == 0) {
+          wave_dit(Z, logF, true, s_tw, tws, lane);
+          for (int t = lane; t < N; t += 64) rho[in.off + t] = cscale(Z[pidx(t)], invF);
+        }
+      } else if (wv < 2) {
+        // wave 0: R11 and R22; wave 1: R12 and R21
+        cd* z = Z + wv * zs;
+        wave_dit(z, logF, true, s_tw, tws, lane);
+        for (int t = lane; t < m; t += 64) {
+          const cd r = cscale(z[pidx(t)], invF);
+          R[wv * st + t] = r;
+          R[(3 - wv) * st + (m - 1 - t)] = cconj(r);
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     if (act.type == SCH_MID) {
       // job 0: spectra of P11 and P12 (to S); job 1: the window
       for (int job = 0; job < 2; ++job) {
