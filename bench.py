@@ -86,6 +86,9 @@ def main():
     ap.add_argument("--plain", type=int, default=8,
                     help="instances for the plain FP64 one-per-launch baseline (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only copy this many bytes device to device (the calibration copy "
+                         "for the HBM counters) and exit")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--factor", choices=["auto", "levinson", "schur"], default="auto",
                     help="generator recursion (auto: superfast Schur from N=256 on)")
@@ -103,6 +106,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes, "copies": 3}))
+        return
     log(f"generating {args.batch} instances (N=4096)")
     insts, _ = make_workload(args.batch)
     B = len(insts)
@@ -170,8 +181,16 @@ def main():
     algo = "levinson" if args.factor == "levinson" else "schur"  # AUTO: Schur from N=256 on
     if ks["flops"] > 0:
         achieved = ks["flops"] / ks["seconds"]
-        roof = {"bound": "alu", "kernel": name + (f" ({algo})" if name == "factor" else ""), "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": None,
+        traffic = None
+        if name == "factor" and algo == "schur" and B == 256:
+            # HBM bytes per launch from the committed counter summary of this
+            # workload (None once the kernel's sources have changed)
+            from paper_1705_06073_amd import pmc
+            traffic = pmc.traffic_bytes(os.path.join(ROOT, "profiles",
+                                                     "k_schur_n4096_b256_traffic.md"), "k_schur")
+        roof = {"bound": "alu", "kernel": name + (f" ({algo})" if name == "factor" else ""),
+                "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": traffic,
                 "avg_launch_ms": 1e3 * ks["seconds"] / max(1, ks["launches"]),
                 "algorithmic_per_launch": ks["flops"] / max(1, ks["launches"])}
     else:
