@@ -51,8 +51,11 @@ typedef enum {
 typedef enum { SFLS_FP64 = 0, SFLS_MIXED = 1 } sfls_precision; /* MIXED: FP32 grid FFTs */
 typedef enum { SFLS_C64 = 0, SFLS_C128 = 1 } sfls_dtype;
 
-/* Largest N accepted by the factorisation kernels of this build. */
-#define SFLS_MAX_N 4096
+/* Largest N accepted by this build (the superfast recursion; the Levinson
+ * recursion handles N <= 4096).  Transforms that do not fit one CU's LDS
+ * (P = 2N > 8192, superfast merges above 4096 points) run on per-instance
+ * scratch in device memory. */
+#define SFLS_MAX_N 65536
 
 typedef struct sfls_ctx sfls_ctx;
 
@@ -129,7 +132,8 @@ sfls_status sfls_toeplitz_column(sfls_ctx* ctx, int64_t B, const int64_t* n, con
  *   logdet device f64  [B]       out: ln|C| = sum_i ln delta_i (Sec. III-A)
  *   status device i32  [B]       out: SFLS_OK or SFLS_ENOTPD
  *   failed_step device i64 [B]   out: first step n with delta_n <= 0 (or -1)
- * 1 <= n[b] <= SFLS_MAX_N, else SFLS_EUNSUPPORTED.
+ * 1 <= n[b] <= SFLS_MAX_N, else SFLS_EUNSUPPORTED; the Levinson recursion
+ * (sfls_set_factor) requires n[b] <= 4096, else SFLS_EUNSUPPORTED.
  * ------------------------------------------------------------------------- */
 sfls_status sfls_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
                         const double* c, double* rho, double* delta, double* logdet,

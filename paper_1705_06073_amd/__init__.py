@@ -23,7 +23,7 @@ SFLS_EINVAL, SFLS_ENOMEM, SFLS_EDEVICE, SFLS_ENOTPD, SFLS_ECAPACITY, SFLS_EUNSUP
     -1, -2, -3, -4, -5, -6
 SFLS_FP64, SFLS_MIXED = 0, 1
 SFLS_C64, SFLS_C128 = 0, 1
-SFLS_MAX_N = 4096
+SFLS_MAX_N = 65536
 
 EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror",
            "sfls_last_error", "sfls_version", "sfls_toeplitz_column", "sfls_factor",

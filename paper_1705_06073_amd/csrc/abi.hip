@@ -193,7 +193,7 @@ std::vector<InstInfo> base_info(int64_t B, const int64_t* n, const int64_t* off,
     in.M = 1 << in.logM;
     in.off = off[b];
     in.poff = ptotal;
-    ptotal += 4 * (int64_t)in.P;
+    ptotal += 4 * (int64_t)in.P + (in.P > CONV_LDS_P ? (int64_t)padded(in.P) : 0);
     sz.maxN = std::max(sz.maxN, in.N);
     sz.maxP = std::max(sz.maxP, in.P);
     sz.maxM = std::max(sz.maxM, in.M);
@@ -286,7 +286,7 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
     L.nact = (int32_t)P.acts.size();
     L.scr_off = scr_total;
     int64_t o = 0;
-    int fm = 64;
+    int fm = 64, fbig = 0;
     for (int l = 0; l < P.nlev; ++l) {
       L.mmax[l] = P.mmax[l];
       L.win[l] = o;
@@ -295,9 +295,12 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
       o += 8 * (int64_t)P.mmax[l];
       L.spec[l] = o;
       o += 2 * (int64_t)P.fspec[l];
-      fm = std::max(fm, P.fspec[l]);
+      if (P.fspec[l] > SCH_LDS_F) fbig = std::max(fbig, P.fspec[l]);
+      else fm = std::max(fm, P.fspec[l]);
       if (P.mmax[l] <= SCH_DIRECT) fm = std::max(fm, 8 * P.mmax[l] + 256);
     }
+    L.xbig = o;
+    if (fbig) o += 2 * (int64_t)padded(fbig);
     L.Fmax = fm;
     Fmax = std::max(Fmax, fm);
     scr_total += o;
@@ -357,6 +360,25 @@ static bool use_schur(const sfls_ctx* ctx, int maxN) {
   if (ctx->factor_algo == SFLS_FACTOR_SCHUR) return maxN > 1;
   if (ctx->factor_algo == SFLS_FACTOR_LEVINSON) return false;
   return maxN >= kSchurMinN;
+}
+
+// The Levinson kernel keeps an instance's vectors in registers: N <= 4096.
+constexpr int kLevinsonMaxN = 4096;
+static sfls_status check_factor_size(sfls_ctx* ctx, int maxN) {
+  if (!use_schur(ctx, maxN) && maxN > kLevinsonMaxN)
+    return fail(ctx, SFLS_EUNSUPPORTED, "the Levinson recursion supports n <= %d (got %d)",
+                kLevinsonMaxN, maxN);
+  return SFLS_OK;
+}
+
+// Grid sub-FFT size: M = min(2^ceil(log2 N), cap) with the cap set by what
+// two M-point buffers of the grid's precision fit in LDS.
+static void cap_grid_m(InstInfo& in, int precision) {
+  const int cap = precision == SFLS_FP64 ? GRID_LOGM_F64 : GRID_LOGM_F32;
+  if (in.logM > cap) {
+    in.logM = cap;
+    in.M = 1 << cap;
+  }
 }
 
 // Upload the Schur plans of a batch when the context uses that path.
@@ -562,6 +584,7 @@ sfls_status sfls_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_
   Sizes sz;
   int64_t pt = 0;
   std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
+  if ((s = check_factor_size(ctx, sz.maxN)) != SFLS_OK) return s;
   InstInfo* dinfo;
   if ((s = upload(ctx, "f_info", info, st, &dinfo)) != SFLS_OK) return s;
   SchurLayout* dlay;
@@ -667,10 +690,12 @@ sfls_status sfls_grid_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int
     if (!is_pow2(L[b]) || L[b] < 2 * n[b] - 1 || L[b] < in.M)
       return fail(ctx, SFLS_EINVAL, "L[%lld] = %lld must be a power of two >= 2n-1", (long long)b, (long long)L[b]);
     if (goff[b] < 0) return fail(ctx, SFLS_EINVAL, "goff[%lld] < 0", (long long)b);
+    cap_grid_m(in, precision);
     in.L = (int32_t)L[b];
     in.R = (int32_t)(L[b] / in.M);
     in.goff = goff[b];
     sz.Rmax = std::max(sz.Rmax, in.R);
+    sz.maxM = std::max(in.M, b == 0 ? 0 : sz.maxM);
     ntot = std::max(ntot, off[b] + n[b]);
     sep_coef((int)n[b], coef[(size_t)b]);
   }
@@ -768,6 +793,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   Sizes sz;
   int64_t pt = 0, ntot = 0, ktot = 0, gtot = 0, ctot = 0;
   std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
+  if ((s = check_factor_size(ctx, sz.maxN)) != SFLS_OK) return s;
   std::vector<SepCoef> coef((size_t)B);
   std::vector<int64_t> okoff((size_t)B);
   const int cc = p.cand_cap + 1;
@@ -778,6 +804,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
     if (Lb < 2 * n[b] - 1 || Lb < in.M)
       return fail(ctx, SFLS_EINVAL, "grid L = %lld shorter than 2n-1 for n = %lld", (long long)Lb, (long long)n[b]);
     if (Lb > (1 << 24)) return fail(ctx, SFLS_EUNSUPPORTED, "grid too large");
+    cap_grid_m(in, p.precision);
     in.L = (int32_t)Lb;
     in.R = (int32_t)(Lb / in.M);
     in.kcap = (int32_t)std::min<int64_t>(kcap[b], n[b]);
@@ -788,6 +815,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
     in.coff = ctot;
     ctot += cc;
     sz.Rmax = std::max(sz.Rmax, in.R);
+    sz.maxM = std::max(in.M, b == 0 ? 0 : sz.maxM);
     ntot = std::max(ntot, off[b] + n[b]);
     okoff[(size_t)b] = koff[b];
     sep_coef((int)n[b], coef[(size_t)b]);

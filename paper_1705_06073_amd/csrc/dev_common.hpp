@@ -351,6 +351,32 @@ __device__ __forceinline__ void wave_dit(C* z, int logn, bool cj, const C* __res
   }
 }
 
+// small bundles of complex values loaded together
+struct cd2 { cd a, b; };
+struct cd3 { cd a, b, c; };
+struct cd4 { cd a, b, c, d; };
+
+// for (t = first; t < n; t += step) use(t, ld(t)), with the loads of U
+// consecutive iterations issued before any of their uses: a loop that stages
+// global data into LDS otherwise waits for each load in turn.
+template <int U, typename Ld, typename Use>
+__device__ __forceinline__ void batched_for(int first, int step, int n, Ld ld, Use use) {
+  using V = decltype(ld(0));
+  for (int t0 = first; t0 < n; t0 += U * step) {
+    V v[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      const int t = t0 + i * step;
+      if (t < n) v[i] = ld(t);
+    }
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      const int t = t0 + i * step;
+      if (t < n) use(t, v[i]);
+    }
+  }
+}
+
 // Copy the head of the stage-major twiddle table to LDS (caller syncs).
 template <int NT, typename C>
 __device__ __forceinline__ void load_tw_head(C* tl, const C* __restrict__ tg) {

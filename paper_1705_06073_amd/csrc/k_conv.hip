@@ -54,7 +54,7 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
   if (req && !(req[bi] & REQ_EVAL)) return;
   const InstInfo in = info[bi];
   const int N = in.N, P = in.P, logP = in.logP;
-  extern __shared__ cd lds[];
+  extern __shared__ cd lds_sh[];
   __shared__ double red[2 * (CONV_NT / 64)];
   __shared__ cd s_tw[FFT_TWL];
   const int tid = threadIdx.x;
@@ -67,72 +67,80 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
   cd* X2 = X1 + P;
   const double invP = 1.0 / (double)P;
 
-  // (1) A = FFT(rho)
-  for (int t = tid; t < P; t += CONV_NT) lds[pidx(t)] = (t < N) ? rb[t] : cd{0.0, 0.0};
-  __syncthreads();
-  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
-  for (int t = tid; t < P; t += CONV_NT) A[t] = lds[pidx(t)];
-  // (2) Y = FFT(y^)
-  for (int t = tid; t < P; t += CONV_NT) lds[pidx(t)] = (t < N) ? load_y(yb, N - 1 - t) : cd{0.0, 0.0};
-  __syncthreads();
-  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
-  for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[pidx(t)];
-  __syncthreads();
-  // (3) u1 from FFT(rho~) . Y
-  for (int p = tid; p < P; p += CONV_NT) {
-    const int f = bitrev(p, logP);
-    const int pm = bitrev((P - f) & (P - 1), logP);
-    lds[pidx(p)] = cmul(cmul(tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), A[pm]), Y[p]);
-  }
-  __syncthreads();
-  dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
-  for (int i = tid; i < N; i += CONV_NT) X1[i] = cscale(lds[pidx(N - 1 - i)], invP);
-  __syncthreads();
-  // (4) v1 from conj(A(-f)) . Y
-  for (int p = tid; p < P; p += CONV_NT) {
-    const int f = bitrev(p, logP);
-    const int pm = bitrev((P - f) & (P - 1), logP);
-    lds[pidx(p)] = cmul(cconj(A[pm]), Y[p]);
-  }
-  __syncthreads();
-  dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
-  for (int i = tid; i < N; i += CONV_NT)
-    X2[i] = (i <= N - 2) ? cscale(lds[pidx(N - 2 - i)], invP) : cd{0.0, 0.0};
-  __syncthreads();
-  // (5) U = FFT(u1) -> Y
-  for (int t = tid; t < P; t += CONV_NT) lds[pidx(t)] = (t < N) ? X1[t] : cd{0.0, 0.0};
-  __syncthreads();
-  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
-  for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[pidx(t)];
-  __syncthreads();
-  // (6) V = FFT(v1), kept in LDS
-  for (int t = tid; t < P; t += CONV_NT) lds[pidx(t)] = (t < N) ? X2[t] : cd{0.0, 0.0};
-  __syncthreads();
-  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
-  // (7) W = FFT(conj rho~) U - W^f A V
-  for (int p = tid; p < P; p += CONV_NT) {
-    const int f = bitrev(p, logP);
-    const cd a = A[p];
-    const cd t1 = cmul(cmul(tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), cconj(a)), Y[p]);
-    const cd t2 = cmul(cmul(tw_pow(tw, logtw, f, logP), a), lds[pidx(p)]);
-    lds[pidx(p)] = csub(t1, t2);
-  }
-  __syncthreads();
-  dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
-  const double sc = invP / delta[in.off + N - 1];
-  double acc[2] = {0.0, 0.0};
-  for (int i = tid; i < N; i += CONV_NT) {
-    const cd wi = cscale(lds[pidx(i)], sc);
-    w[in.off + i] = wi;
-    const cd yi = load_y(yb, i);
-    acc[0] += fma(yi.x, wi.x, yi.y * wi.y);  // Re(conj(y) w)
-    acc[1] += cabs2(wi);
-  }
-  block_sum<CONV_NT, 2>(acc, red);
-  if (tid == 0) {
-    if (yCy) yCy[bi] = acc[0];
-    if (ww) ww[bi] = acc[1];
-  }
+  // The transform buffer: LDS, or for P > CONV_LDS_P the instance's scratch
+  // after its four P blocks (the same passes, on global memory).
+  auto body = [&](cd* __restrict__ lds) __attribute__((always_inline)) {
+    // (1) A = FFT(rho)
+    auto to_lds = [&](int t, cd v) { lds[pidx(t)] = v; };
+    batched_for<8>(tid, CONV_NT, P, [&](int t) { return (t < N) ? rb[t] : cd{0.0, 0.0}; }, to_lds);
+    __syncthreads();
+    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+    for (int t = tid; t < P; t += CONV_NT) A[t] = lds[pidx(t)];
+    // (2) Y = FFT(y^)
+    batched_for<8>(tid, CONV_NT, P,
+                   [&](int t) { return (t < N) ? load_y(yb, N - 1 - t) : cd{0.0, 0.0}; }, to_lds);
+    __syncthreads();
+    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+    for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[pidx(t)];
+    __syncthreads();
+    // (3) u1 from FFT(rho~) . Y
+    batched_for<4>(tid, CONV_NT, P, [&](int p) {
+      const int f = bitrev(p, logP);
+      const int pm = bitrev((P - f) & (P - 1), logP);
+      return cd3{tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), A[pm], Y[p]};
+    }, [&](int p, cd3 g) { lds[pidx(p)] = cmul(cmul(g.a, g.b), g.c); });
+    __syncthreads();
+    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
+    for (int i = tid; i < N; i += CONV_NT) X1[i] = cscale(lds[pidx(N - 1 - i)], invP);
+    __syncthreads();
+    // (4) v1 from conj(A(-f)) . Y
+    batched_for<4>(tid, CONV_NT, P, [&](int p) {
+      const int f = bitrev(p, logP);
+      const int pm = bitrev((P - f) & (P - 1), logP);
+      return cd3{A[pm], Y[p], cd{0.0, 0.0}};
+    }, [&](int p, cd3 g) { lds[pidx(p)] = cmul(cconj(g.a), g.b); });
+    __syncthreads();
+    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
+    for (int i = tid; i < N; i += CONV_NT)
+      X2[i] = (i <= N - 2) ? cscale(lds[pidx(N - 2 - i)], invP) : cd{0.0, 0.0};
+    __syncthreads();
+    // (5) U = FFT(u1) -> Y
+    batched_for<8>(tid, CONV_NT, P, [&](int t) { return (t < N) ? X1[t] : cd{0.0, 0.0}; }, to_lds);
+    __syncthreads();
+    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+    for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[pidx(t)];
+    __syncthreads();
+    // (6) V = FFT(v1), kept in LDS
+    batched_for<8>(tid, CONV_NT, P, [&](int t) { return (t < N) ? X2[t] : cd{0.0, 0.0}; }, to_lds);
+    __syncthreads();
+    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+    // (7) W = FFT(conj rho~) U - W^f A V
+    batched_for<4>(tid, CONV_NT, P, [&](int p) {
+      const int f = bitrev(p, logP);
+      return cd4{A[p], Y[p], tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), tw_pow(tw, logtw, f, logP)};
+    }, [&](int p, cd4 g) {
+      const cd t1 = cmul(cmul(g.c, cconj(g.a)), g.b);
+      const cd t2 = cmul(cmul(g.d, g.a), lds[pidx(p)]);
+      lds[pidx(p)] = csub(t1, t2);
+    });
+    __syncthreads();
+    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
+    const double sc = invP / delta[in.off + N - 1];
+    double acc[2] = {0.0, 0.0};
+    batched_for<8>(tid, CONV_NT, N, [&](int i) { return load_y(yb, i); }, [&](int i, cd yi) {
+      const cd wi = cscale(lds[pidx(i)], sc);
+      w[in.off + i] = wi;
+      acc[0] += fma(yi.x, wi.x, yi.y * wi.y);  // Re(conj(y) w)
+      acc[1] += cabs2(wi);
+    });
+    block_sum<CONV_NT, 2>(acc, red);
+    if (tid == 0) {
+      if (yCy) yCy[bi] = acc[0];
+      if (ww) ww[bi] = acc[1];
+    }
+  };
+  if (P > CONV_LDS_P) body(scratch + in.poff + 4 * (int64_t)P);
+  else body(lds_sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -163,7 +171,7 @@ __global__ __launch_bounds__(CONV_NT) void k_omega(const InstInfo* __restrict__ 
   if (req && !(req[bi] & REQ_GRID)) return;
   const InstInfo in = info[bi];
   const int N = in.N, P = in.P, logP = in.logP;
-  extern __shared__ cd lds[];
+  extern __shared__ cd lds_sh[];
   __shared__ cd s_tw[FFT_TWL];
   const int tid = threadIdx.x;
   load_tw_head<CONV_NT>(s_tw, tws);
@@ -171,66 +179,74 @@ __global__ __launch_bounds__(CONV_NT) void k_omega(const InstInfo* __restrict__ 
   cd* G0 = scratch + in.poff;  // G_a at G0 + a P
   const int amax = (which & ~1) ? 3 : 1;
   const double cN = 0.5 * (double)(N - 1);
-  for (int a = have_g0 ? 1 : 0; a <= amax; ++a) {
-    for (int t = tid; t < P; t += CONV_NT) {
-      cd v{0.0, 0.0};
-      if (t < N) {
+  // The transform buffer: LDS, or for P > CONV_LDS_P the instance's scratch
+  // after its four P blocks (the same passes, on global memory).
+  auto body = [&](cd* __restrict__ lds) __attribute__((always_inline)) {
+    for (int a = have_g0 ? 1 : 0; a <= amax; ++a) {
+      batched_for<8>(tid, CONV_NT, P, [&](int t) { return (t < N) ? rb[t] : cd{0.0, 0.0}; },
+                     [&](int t, cd v) {
         const double x = (double)t - cN;
         double m = 1.0;
         for (int e = 0; e < a; ++e) m *= x;
-        v = cscale(rb[t], m);
-      }
-      lds[pidx(t)] = v;
+        lds[pidx(t)] = cscale(v, m);
+      });
+      __syncthreads();
+      dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+      for (int t = tid; t < P; t += CONV_NT) G0[(int64_t)a * P + t] = lds[pidx(t)];
+      __syncthreads();
     }
-    __syncthreads();
-    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
-    for (int t = tid; t < P; t += CONV_NT) G0[(int64_t)a * P + t] = lds[pidx(t)];
-    __syncthreads();
-  }
-  const SepCoef* cfp = coef + bi;
-  const double scale = 1.0 / ((double)P * delta[in.off + N - 1]);
-  for (int qk = 0; qk < 4; ++qk) {
-    if (!(which & (1 << qk))) continue;
-    const double* C = cfp->c[qk];
-    const int am = (qk == 0) ? 1 : 3;
-    cd* outq = qk == 0 ? o_s : (qk == 1 ? o_t : (qk == 2 ? o_v : o_x));
-    for (int p = tid; p < P; p += CONV_NT) {
-      cd g[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) g[a] = (a <= am) ? G0[(int64_t)a * P + p] : cd{0.0, 0.0};
-      cd acc{0.0, 0.0};
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b2 = 0; b2 < 4; ++b2) {
-          const double cab = (a <= am && b2 <= am) ? C[a * 4 + b2] : 0.0;
-          if (cab != 0.0) {
-            const cd pr = cmulc(g[b2], g[a]);  // G_b conj(G_a)
-            acc.x = fma(cab, pr.x, acc.x);
-            acc.y = fma(cab, pr.y, acc.y);
+    const SepCoef* cfp = coef + bi;
+    const double scale = 1.0 / ((double)P * delta[in.off + N - 1]);
+    for (int qk = 0; qk < 4; ++qk) {
+      if (!(which & (1 << qk))) continue;
+      const double* C = cfp->c[qk];
+      const int am = (qk == 0) ? 1 : 3;
+      cd* outq = qk == 0 ? o_s : (qk == 1 ? o_t : (qk == 2 ? o_v : o_x));
+      batched_for<2>(tid, CONV_NT, P, [&](int p) {
+        cd4 g;
+        g.a = G0[p];
+        g.b = (am >= 1) ? G0[(int64_t)P + p] : cd{0.0, 0.0};
+        g.c = (am >= 2) ? G0[(int64_t)2 * P + p] : cd{0.0, 0.0};
+        g.d = (am >= 3) ? G0[(int64_t)3 * P + p] : cd{0.0, 0.0};
+        return g;
+      }, [&](int p, cd4 gg) {
+        const cd g[4] = {gg.a, gg.b, gg.c, gg.d};
+        cd acc{0.0, 0.0};
+  #pragma unroll
+        for (int a = 0; a < 4; ++a)
+  #pragma unroll
+          for (int b2 = 0; b2 < 4; ++b2) {
+            const double cab = (a <= am && b2 <= am) ? C[a * 4 + b2] : 0.0;
+            if (cab != 0.0) {
+              const cd pr = cmulc(g[b2], g[a]);  // G_b conj(G_a)
+              acc.x = fma(cab, pr.x, acc.x);
+              acc.y = fma(cab, pr.y, acc.y);
+            }
           }
+        lds[pidx(p)] = acc;
+      });
+      __syncthreads();
+      dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
+      for (int t = tid; t < P; t += CONV_NT) {
+        // lag i = t for t < N, i = t - P for t > P - N
+        const bool pos = t < N, neg = t > P - N;
+        if (!pos && !neg) continue;
+        const cd om = cscale(cconj(lds[pidx(t)]), scale);
+        if (qk == 0 && oms) oms[in.poff + t] = om;
+        if (outq) {
+          const int i = pos ? t : t - P;
+          outq[in.ooff + i + N - 1] = om;
         }
-      lds[pidx(p)] = acc;
-    }
-    __syncthreads();
-    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
-    for (int t = tid; t < P; t += CONV_NT) {
-      // lag i = t for t < N, i = t - P for t > P - N
-      const bool pos = t < N, neg = t > P - N;
-      if (!pos && !neg) continue;
-      const cd om = cscale(cconj(lds[pidx(t)]), scale);
-      if (qk == 0 && oms) oms[in.poff + t] = om;
-      if (outq) {
-        const int i = pos ? t : t - P;
-        outq[in.ooff + i + N - 1] = om;
       }
+      if (qk == 0 && oms) {
+        for (int t = tid; t < P; t += CONV_NT)
+          if (!(t < N) && !(t > P - N)) oms[in.poff + t] = cd{0.0, 0.0};
+      }
+      __syncthreads();
     }
-    if (qk == 0 && oms) {
-      for (int t = tid; t < P; t += CONV_NT)
-        if (!(t < N) && !(t > P - N)) oms[in.poff + t] = cd{0.0, 0.0};
-    }
-    __syncthreads();
-  }
+  };
+  if (P > CONV_LDS_P) body(scratch + in.poff + 4 * (int64_t)P);
+  else body(lds_sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -259,7 +275,7 @@ __global__ __launch_bounds__(CONV_NT) void k_gen_residual(const InstInfo* __rest
   if (status && status[bi] != 0) return;
   const InstInfo in = info[bi];
   const int N = in.N, P = in.P, logP = in.logP;
-  extern __shared__ cd lds[];
+  extern __shared__ cd lds_sh[];
   __shared__ cd s_tw[FFT_TWL];
   const int tid = threadIdx.x;
   load_tw_head<CONV_NT>(s_tw, tws);
@@ -267,27 +283,35 @@ __global__ __launch_bounds__(CONV_NT) void k_gen_residual(const InstInfo* __rest
   const cd* rb = rho + in.off;
   cd* H = scratch + in.poff;
   const double inv_d = 1.0 / delta[in.off + N - 1];
-  for (int t = tid; t < P; t += CONV_NT) {
-    cd v{0.0, 0.0};
-    if (t < N) v = cb[t];
-    else if (t > P - N) v = cconj(cb[P - t]);
-    lds[pidx(t)] = v;
-  }
-  __syncthreads();
-  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
-  for (int t = tid; t < P; t += CONV_NT) H[t] = lds[pidx(t)];
-  __syncthreads();
-  for (int t = tid; t < P; t += CONV_NT) lds[pidx(t)] = (t < N) ? cscale(rb[t], inv_d) : cd{0.0, 0.0};
-  __syncthreads();
-  dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
-  for (int p = tid; p < P; p += CONV_NT) lds[pidx(p)] = cmul(lds[pidx(p)], H[p]);
-  __syncthreads();
-  dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
-  const double invP = 1.0 / (double)P;
-  for (int i = tid; i < N; i += CONV_NT) {
-    const cd cx = cscale(lds[pidx(i)], invP);
-    r[in.off + i] = cd{(i == N - 1 ? 1.0 : 0.0) - cx.x, -cx.y};
-  }
+  // The transform buffer: LDS, or for P > CONV_LDS_P the instance's scratch
+  // after its four P blocks (the same passes, on global memory).
+  auto body = [&](cd* __restrict__ lds) __attribute__((always_inline)) {
+    batched_for<8>(tid, CONV_NT, P, [&](int t) {
+      cd v{0.0, 0.0};
+      if (t < N) v = cb[t];
+      else if (t > P - N) v = cconj(cb[P - t]);
+      return v;
+    }, [&](int t, cd v) { lds[pidx(t)] = v; });
+    __syncthreads();
+    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+    for (int t = tid; t < P; t += CONV_NT) H[t] = lds[pidx(t)];
+    __syncthreads();
+    batched_for<8>(tid, CONV_NT, P, [&](int t) { return (t < N) ? cscale(rb[t], inv_d) : cd{0.0, 0.0}; },
+                   [&](int t, cd v) { lds[pidx(t)] = v; });
+    __syncthreads();
+    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+    batched_for<8>(tid, CONV_NT, P, [&](int p) { return H[p]; },
+                   [&](int p, cd h) { lds[pidx(p)] = cmul(lds[pidx(p)], h); });
+    __syncthreads();
+    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
+    const double invP = 1.0 / (double)P;
+    for (int i = tid; i < N; i += CONV_NT) {
+      const cd cx = cscale(lds[pidx(i)], invP);
+      r[in.off + i] = cd{(i == N - 1 ? 1.0 : 0.0) - cx.x, -cx.y};
+    }
+  };
+  if (P > CONV_LDS_P) body(scratch + in.poff + 4 * (int64_t)P);
+  else body(lds_sh);
 }
 
 __global__ __launch_bounds__(CONV_NT) void k_gen_update(const InstInfo* __restrict__ info,
@@ -326,7 +350,7 @@ hipError_t launch_gen_refine(const InstInfo* info, const int32_t* req, const int
                              const cd* c, cd* rho, double* delta, const cd* tw, int logtw,
                              const cd* tws, cd* scratch, cd* r, cd* dx, int B, int maxP,
                              hipStream_t st) {
-  const size_t shm = (size_t)padded(maxP) * sizeof(cd);
+  const size_t shm = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);
   (void)hipFuncSetAttribute((const void*)k_gen_residual,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL(k_gen_residual, dim3(B), dim3(CONV_NT), shm, st, info, req, status, c, rho,
@@ -345,7 +369,7 @@ hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void*
                            const cd* rho, const double* delta, const cd* tw, int logtw,
                            const cd* tws, cd* scratch, cd* w, double* yCy, double* ww, int B, int maxP,
                            hipStream_t st) {
-  const size_t shm = (size_t)padded(maxP) * sizeof(cd);
+  const size_t shm = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);
   if (ydtype == 1) {
     (void)hipFuncSetAttribute((const void*)k_gs_apply<cd>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)shm);
@@ -364,7 +388,7 @@ hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
                         const double* delta, const SepCoef* coef, const cd* tws,
                         cd* scratch, int which, int have_g0, cd* oms, cd* o_s, cd* o_t,
                         cd* o_v, cd* o_x, int B, int maxP, hipStream_t st) {
-  const size_t shm = (size_t)padded(maxP) * sizeof(cd);
+  const size_t shm = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);
   (void)hipFuncSetAttribute((const void*)k_omega, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL(k_omega, dim3(B), dim3(CONV_NT), shm, st, info, req, rho, delta, coef, tws,
                      scratch, which, have_g0, oms, o_s, o_t, o_v, o_x);

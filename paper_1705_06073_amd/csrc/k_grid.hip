@@ -27,10 +27,11 @@ __device__ __forceinline__ R delta_L_point(R q2, R s, R gb, R odds) {
 }
 
 // ---------------------------------------------------------------------------
-// a6.  Grid of L = R M points split by residue r = l mod R (M >= N a power
-// of two):  with l = R f + r,
-//   q^G_l = sum_n [w_n e^{-j2pi n r/L}] e^{-j2pi n f/M}           (M-point DFT)
+// a6.  Grid of L = R M points split by residue r = l mod R (M a power of
+// two, min(2^ceil(log2 N), cap)):  with l = R f + r,
+//   q^G_l = sum_m [sum_{n = m mod M} w_n e^{-j2pi n r/L}] e^{-j2pi m f/M}   (M-point DFT)
 //   s^G_l = sum_m [sum_{i = m mod M} omega_s(i) e^{j2pi i r/L}] e^{+j2pi m f/M}
+// (n over 0..N-1, i over -N+1..N-1; the inner sums fold the inputs onto M points)
 // so each workgroup (instance, r) runs two M-point FFTs in LDS (padded layout).  The
 // residue twiddles come from exact fractions (n r mod L)/L.  Outputs per
 // point: optional q^G, s^G, Delta L; always a per-workgroup argmin
@@ -77,12 +78,11 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
   const cd* ob = oms + in.poff;
   for (int m = tid; m < M; m += GRID_NT) {
     cd qv{0.0, 0.0}, sv{0.0, 0.0};
-    if (m < N) qv = cmul(wb[m], cconj(cis_frac(((int64_t)m * r) % L, L)));
-    if (m < N) sv = cmul(ob[m], cis_frac(((int64_t)m * r) % L, L));
-    const int i2 = m - M;  // negative lag folded onto m
-    if (i2 > -N) {
-      const int64_t ph = (((int64_t)i2 % L + L) % L) * r % L;
-      sv = cfma(ob[(i2 + P) & (P - 1)], cis_frac(ph, L), sv);
+    for (int n = m; n < N; n += M) qv = cfma(wb[n], cconj(cis_frac(((int64_t)n * r) % L, L)), qv);
+    // lags i = m mod M in (-N, N), from the most negative one up
+    for (int i = m - M * ((m + N - 1) / M); i < N; i += M) {
+      const int64_t ph = (((int64_t)i % L + L) % L) * r % L;
+      sv = cfma(ob[(i + P) & (P - 1)], cis_frac(ph, L), sv);
     }
     lq[pidx(m)] = C{(decltype(C{}.x))qv.x, (decltype(C{}.x))qv.y};
     ls[pidx(m)] = C{(decltype(C{}.x))sv.x, (decltype(C{}.x))sv.y};

@@ -191,11 +191,14 @@ __device__ __forceinline__ cd zbin(const cd* __restrict__ tw, int logtw, int p, 
   return wpow(tw, logtw, bitrev(p, logF), logF);
 }
 // Spectra of the second row of a Theta over m steps at bit-reversed bin p,
-// from those of the first row (symmetry above): s21 from s12, s22 from s11.
-__device__ __forceinline__ void second_row(const cd* __restrict__ tw, int logtw, int p, int logF,
-                                           int m, cd s11, cd s12, cd& s21, cd& s22) {
+// from those of the first row (symmetry above): s21 from s12, s22 from s11,
+// with ph = W_F^(f (m-1)) from row_phase.
+__device__ __forceinline__ cd row_phase(const cd* __restrict__ tw, int logtw, int p, int logF,
+                                        int m) {
   const int f = bitrev(p, logF);
-  const cd ph = wpow(tw, logtw, (f * (m - 1)) & ((1 << logF) - 1), logF);
+  return wpow(tw, logtw, (f * (m - 1)) & ((1 << logF) - 1), logF);
+}
+__device__ __forceinline__ void second_row(cd ph, cd s11, cd s12, cd& s21, cd& s22) {
   s21 = cmul(ph, cconj(s12));
   s22 = cmul(ph, cconj(s11));
 }
@@ -400,11 +403,13 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
       while (nsp < 8 && npoly * nblk * 2 * nsp <= SCH_NT && npoly * nbr * 2 * nsp <= avail)
         nsp *= 2;
       const int jl = (m2 + nsp - 1) / nsp;
-      for (int t = tid; t < 4 * pe; t += SCH_NT) {
-        const int q = t / pe, k = t % pe, i = k - PL;
-        const int sk = RB > 1 ? k + (k >> lrb) : k;
-        Pext[q * pes + sk] = (i >= 0 && i < m1) ? T1[q * st1 + i] : cd{0.0, 0.0};
-      }
+      batched_for<2>(tid, SCH_NT, 4 * pe, [&](int t) {
+        const int q = t / pe, i = t % pe - PL;
+        return (i >= 0 && i < m1) ? T1[q * st1 + i] : cd{0.0, 0.0};
+      }, [&](int t, cd v) {
+        const int q = t / pe, k = t % pe;
+        Pext[q * pes + (RB > 1 ? k + (k >> lrb) : k)] = v;
+      });
       const int qr0 = root ? 2 : 0;          // rows of Theta2 in use
       for (int t = tid; t < 2 * m2; t += SCH_NT) Q[qr0 * m2 + t] = T2[(qr0 + t / m2) * st1 + t % m2];
       __syncthreads();
@@ -450,21 +455,23 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
           const cd* src = wv == 0 ? T1 : (wv == 1 ? T1 + st1 : (wv == 2 ? u : v));
           const int lim = wv < 2 ? m1 : m;
           cd* z = Z + wv * zs;
-          for (int t = lane; t < F; t += 64) z[pidx(t)] = t < lim ? src[t] : cd{0.0, 0.0};
+          batched_for<8>(lane, 64, F, [&](int t) { return t < lim ? src[t] : cd{0.0, 0.0}; },
+                         [&](int t, cd x) { z[pidx(t)] = x; });
           wave_sync();
           wave_dif(z, logF, false, s_tw, tws, lane);
           if (wv < 2)
             for (int t = lane; t < F; t += 64) S[(int64_t)wv * F + t] = z[pidx(t)];
         }
         __syncthreads();
-        for (int p = tid; p < F; p += SCH_NT) {
+        batched_for<2>(tid, SCH_NT, F, [&](int p) { return row_phase(tw, logtw, p, logF, m1); },
+                       [&](int p, cd ph) {
           const cd s11 = Z[pidx(p)], s12 = Z[zs + pidx(p)];
           const cd fu = Z[2 * zs + pidx(p)], fv = Z[3 * zs + pidx(p)];
           cd s21, s22;
-          second_row(tw, logtw, p, logF, m1, s11, s12, s21, s22);
+          second_row(ph, s11, s12, s21, s22);
           Z[2 * zs + pidx(p)] = cfma(s12, fv, cmul(s11, fu));
           Z[3 * zs + pidx(p)] = cfma(s22, fv, cmul(s21, fu));
-        }
+        });
         __syncthreads();
         // waves 2, 3: P1 and P2, and from them the right child's window
         if (wv == 2 || wv == 3) {
@@ -482,17 +489,20 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
       if (wv < 2) {
         const cd* src = T2 + (2 * row + wv) * st1;
         cd* z = Z + wv * zs;
-        for (int t = lane; t < F; t += 64) z[pidx(t)] = t < m2 ? src[t] : cd{0.0, 0.0};
+        batched_for<8>(lane, 64, F, [&](int t) { return t < m2 ? src[t] : cd{0.0, 0.0}; },
+                       [&](int t, cd x) { z[pidx(t)] = x; });
         wave_sync();
         wave_dif(z, logF, false, s_tw, tws, lane);
       }
       __syncthreads();
-      for (int p = tid; p < F; p += SCH_NT) {
-        const cd zb = zbin(tw, logtw, p, logF);
+      batched_for<2>(tid, SCH_NT, F, [&](int p) {
+        return cd4{zbin(tw, logtw, p, logF), row_phase(tw, logtw, p, logF, m1), S[p], S[F + p]};
+      }, [&](int p, cd4 g) {
+        const cd zb = g.a;
         const cd a1 = Z[pidx(p)], a2 = cmul(Z[zs + pidx(p)], zb);
-        const cd s11 = S[p], s12 = S[F + p];
+        const cd s11 = g.c, s12 = g.d;
         cd s21, s22;
-        second_row(tw, logtw, p, logF, m1, s11, s12, s21, s22);
+        second_row(g.b, s11, s12, s21, s22);
         const cd r1 = cfma(a2, s21, cmul(a1, s11));
         const cd r2 = cfma(a2, s22, cmul(a1, s12));
         if (root) {
@@ -501,7 +511,7 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
           Z[pidx(p)] = r1;
           Z[zs + pidx(p)] = r2;
         }
-      }
+      });
       __syncthreads();
       if (root) {
         if (wv == 0) {
@@ -521,85 +531,100 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
       __syncthreads();
       continue;
     }
-    if (act.type == SCH_MID) {
-      // job 0: spectra of P11 and P12 (to S); job 1: the window
-      for (int job = 0; job < 2; ++job) {
-        const cd* pa = job == 0 ? T1 : u;
-        const cd* pb = job == 0 ? T1 + st1 : v;
-        const int lim = job == 0 ? m1 : m;
-        for (int t = tid; t < F; t += SCH_NT) {
-          A[pidx(t)] = t < lim ? pa[t] : cd{0.0, 0.0};
-          Bf[pidx(t)] = t < lim ? pb[t] : cd{0.0, 0.0};
+    // Transform buffers: LDS, or for F > SCH_LDS_F two buffers in the
+    // instance's scratch (the same passes, on global memory).
+    auto fft_merge = [&](cd* __restrict__ A, cd* __restrict__ Bf) __attribute__((always_inline)) {
+      if (act.type == SCH_MID) {
+        // job 0: spectra of P11 and P12 (to S); job 1: the window
+        for (int job = 0; job < 2; ++job) {
+          const cd* pa = job == 0 ? T1 : u;
+          const cd* pb = job == 0 ? T1 + st1 : v;
+          const int lim = job == 0 ? m1 : m;
+          batched_for<4>(tid, SCH_NT, F, [&](int t) {
+            return t < lim ? cd2{pa[t], pb[t]} : cd2{cd{0.0, 0.0}, cd{0.0, 0.0}};
+          }, [&](int t, cd2 x) {
+            A[pidx(t)] = x.a;
+            Bf[pidx(t)] = x.b;
+          });
+          __syncthreads();
+          dif_fftn<SCH_NT>(A, Bf, 2, logF, false, false, s_tw, tws);
+          if (job == 0) {
+            for (int t = tid; t < F; t += SCH_NT) {
+              S[t] = A[pidx(t)];
+              S[F + t] = Bf[pidx(t)];
+            }
+            __syncthreads();
+          }
+        }
+        batched_for<4>(tid, SCH_NT, F, [&](int p) {
+          return cd4{row_phase(tw, logtw, p, logF, m1), S[p], S[F + p], cd{0.0, 0.0}};
+        }, [&](int p, cd4 g) {
+          const cd fu = A[pidx(p)], fv = Bf[pidx(p)];
+          const cd s11 = g.b, s12 = g.c;
+          cd s21, s22;
+          second_row(g.a, s11, s12, s21, s22);
+          A[pidx(p)] = cfma(s12, fv, cmul(s11, fu));
+          Bf[pidx(p)] = cfma(s22, fv, cmul(s21, fu));
+        });
+        __syncthreads();
+        dit_fftn<SCH_NT>(A, Bf, 2, logF, true, true, s_tw, tws);
+        // right child's window
+        cd* W2 = scr + L.win[cl];
+        const int stw = L.mmax[cl];
+        for (int r = tid; r < m2; r += SCH_NT) {
+          W2[r] = cscale(A[pidx(m1 + r)], invF);
+          W2[stw + r] = cscale(Bf[pidx(m1 - 1 + r)], invF);
         }
         __syncthreads();
-        dif_fftn<SCH_NT>(A, Bf, 2, logF, false, false, s_tw, tws);
-        if (job == 0) {
-          for (int t = tid; t < F; t += SCH_NT) {
-            S[t] = A[pidx(t)];
-            S[F + t] = Bf[pidx(t)];
-          }
-          __syncthreads();
+        return;
+      }
+      // POST / ROOT: one row of Theta = Theta2 Theta1, the first (the second
+      // follows by symmetry), or for the root the second, whose
+      // rho = R21 + z R22.
+      const int row = root ? 1 : 0;
+      batched_for<4>(tid, SCH_NT, F, [&](int t) {
+        return (t < m2) ? cd2{T2[(2 * row) * st1 + t], T2[(2 * row + 1) * st1 + t]}
+                        : cd2{cd{0.0, 0.0}, cd{0.0, 0.0}};
+      }, [&](int t, cd2 x) {
+        A[pidx(t)] = x.a;
+        Bf[pidx(t)] = x.b;
+      });
+      __syncthreads();
+      dif_fftn<SCH_NT>(A, Bf, 2, logF, false, false, s_tw, tws);
+      batched_for<4>(tid, SCH_NT, F, [&](int p) {
+        return cd4{zbin(tw, logtw, p, logF), row_phase(tw, logtw, p, logF, m1), S[p], S[F + p]};
+      }, [&](int p, cd4 g) {
+        const cd zb = g.a;
+        const cd a1 = A[pidx(p)], a2 = cmul(Bf[pidx(p)], zb);  // z * second poly
+        const cd s11 = g.c, s12 = g.d;
+        cd s21, s22;
+        second_row(g.b, s11, s12, s21, s22);
+        const cd r1 = cfma(a2, s21, cmul(a1, s11));   // row . column 1
+        const cd r2 = cfma(a2, s22, cmul(a1, s12));   // row . column 2 (shifted)
+        if (root) {
+          A[pidx(p)] = cfma(r2, zb, r1);  // rho = R21 + z R22'
+        } else {
+          A[pidx(p)] = r1;
+          Bf[pidx(p)] = r2;
+        }
+      });
+      __syncthreads();
+      dit_fftn<SCH_NT>(A, Bf, root ? 1 : 2, logF, true, true, s_tw, tws);
+      if (root) {
+        for (int t = tid; t < N; t += SCH_NT) rho[in.off + t] = cscale(A[pidx(t)], invF);
+      } else {
+        for (int t = tid; t < m; t += SCH_NT) {
+          const cd r11 = cscale(A[pidx(t)], invF), r12 = cscale(Bf[pidx(t)], invF);
+          R[t] = r11;
+          R[st + t] = r12;
+          R[2 * st + (m - 1 - t)] = cconj(r12);
+          R[3 * st + (m - 1 - t)] = cconj(r11);
         }
       }
-      for (int p = tid; p < F; p += SCH_NT) {
-        const cd fu = A[pidx(p)], fv = Bf[pidx(p)];
-        const cd s11 = S[p], s12 = S[F + p];
-        cd s21, s22;
-        second_row(tw, logtw, p, logF, m1, s11, s12, s21, s22);
-        A[pidx(p)] = cfma(s12, fv, cmul(s11, fu));
-        Bf[pidx(p)] = cfma(s22, fv, cmul(s21, fu));
-      }
       __syncthreads();
-      dit_fftn<SCH_NT>(A, Bf, 2, logF, true, true, s_tw, tws);
-      // right child's window
-      cd* W2 = scr + L.win[cl];
-      const int stw = L.mmax[cl];
-      for (int r = tid; r < m2; r += SCH_NT) {
-        W2[r] = cscale(A[pidx(m1 + r)], invF);
-        W2[stw + r] = cscale(Bf[pidx(m1 - 1 + r)], invF);
-      }
-      __syncthreads();
-      continue;
-    }
-    // POST / ROOT: one row of Theta = Theta2 Theta1, the first (the second
-    // follows by symmetry), or for the root the second, whose
-    // rho = R21 + z R22.
-    const int row = root ? 1 : 0;
-    for (int t = tid; t < F; t += SCH_NT) {
-      A[pidx(t)] = (t < m2) ? T2[(2 * row) * st1 + t] : cd{0.0, 0.0};
-      Bf[pidx(t)] = (t < m2) ? T2[(2 * row + 1) * st1 + t] : cd{0.0, 0.0};
-    }
-    __syncthreads();
-    dif_fftn<SCH_NT>(A, Bf, 2, logF, false, false, s_tw, tws);
-    for (int p = tid; p < F; p += SCH_NT) {
-      const cd zb = zbin(tw, logtw, p, logF);
-      const cd a1 = A[pidx(p)], a2 = cmul(Bf[pidx(p)], zb);  // z * second poly
-      const cd s11 = S[p], s12 = S[F + p];
-      cd s21, s22;
-      second_row(tw, logtw, p, logF, m1, s11, s12, s21, s22);
-      const cd r1 = cfma(a2, s21, cmul(a1, s11));   // row . column 1
-      const cd r2 = cfma(a2, s22, cmul(a1, s12));   // row . column 2 (shifted)
-      if (root) {
-        A[pidx(p)] = cfma(r2, zb, r1);  // rho = R21 + z R22'
-      } else {
-        A[pidx(p)] = r1;
-        Bf[pidx(p)] = r2;
-      }
-    }
-    __syncthreads();
-    dit_fftn<SCH_NT>(A, Bf, root ? 1 : 2, logF, true, true, s_tw, tws);
-    if (root) {
-      for (int t = tid; t < N; t += SCH_NT) rho[in.off + t] = cscale(A[pidx(t)], invF);
-    } else {
-      for (int t = tid; t < m; t += SCH_NT) {
-        const cd r11 = cscale(A[pidx(t)], invF), r12 = cscale(Bf[pidx(t)], invF);
-        R[t] = r11;
-        R[st + t] = r12;
-        R[2 * st + (m - 1 - t)] = cconj(r12);
-        R[3 * st + (m - 1 - t)] = cconj(r11);
-      }
-    }
-    __syncthreads();
+    };
+    if (F > SCH_LDS_F) fft_merge(scr + L.xbig, scr + L.xbig + padded(F));
+    else fft_merge(lds, lds + padded(L.Fmax));
   }
   if (tid == 0) {
     const bool ok = s_fail < 0;

@@ -18,12 +18,20 @@ struct InstInfo {
   int32_t L;      // grid size
   int32_t kcap;   // component capacity
   int64_t off;    // per-sample arrays (y, c, rho, delta, w)
-  int64_t poff;   // P-length scratch
+  int64_t poff;   // scratch: 4 blocks of P, then (P > CONV_LDS_P) a transform buffer
   int64_t goff;   // L-length grid arrays
   int64_t koff;   // component arrays
   int64_t ooff;   // 2N-1 omega arrays (sfls_omega)
   int64_t coff;   // candidate arrays
 };
+
+// Largest P whose transform buffer sits in LDS (P = 8192 fills one CU's LDS
+// with the twiddle head); larger transforms run the same passes on a buffer of
+// padded(P) in the instance's scratch, after its four P blocks.
+constexpr int CONV_LDS_P = 8192;
+// Largest grid sub-FFT size M (two buffers of padded(M) in LDS): M = min(2^ceil(log2 N), cap).
+constexpr int GRID_LOGM_F32 = 13;
+constexpr int GRID_LOGM_F64 = 12;
 
 // Request bits of one instance for the current evaluation round.
 enum : int32_t { REQ_EVAL = 1, REQ_GRID = 2, REQ_APPROX = 4 };
@@ -45,6 +53,9 @@ constexpr int SCH_MAXL = 16;
 // sums, no transforms; the transform buffers must then hold 8m + 256 elements
 // each); larger ones use FFTs of size >= m.
 constexpr int SCH_DIRECT = 128;
+// Transform merges with F above this use two buffers of padded(F) in the
+// instance's Schur scratch (at xbig) instead of LDS.
+constexpr int SCH_LDS_F = 4096;
 
 // Per-instance layout of the recursion's scratch (offsets in complex elements).
 struct SchurLayout {
@@ -54,7 +65,8 @@ struct SchurLayout {
   int32_t Fmax;
   int64_t win[SCH_MAXL];   // right-child windows (u then v, mmax[l] each)
   int64_t res[SCH_MAXL];   // Theta results, 2 sides x 4 polynomials x mmax[l]
-  int64_t spec[SCH_MAXL];  // Theta1 spectra, 4 x F
+  int64_t spec[SCH_MAXL];  // Theta1 first-row spectra, 2 x F
+  int64_t xbig;            // transform buffers of merges with F > SCH_LDS_F
   int32_t mmax[SCH_MAXL];
 };
 
