@@ -172,6 +172,7 @@ def main():
     st = out["status"].cpu().numpy()
     Kh = out["K"].cpu().numpy()
     its = out["iters"].cpu().numpy()
+    evs = out["evals"].cpu().numpy()
     solves = args.steps * B
     value = solves / elapsed
 
@@ -258,7 +259,10 @@ def main():
                        "p99": 1e3 * float(np.percentile(lat, 99))},
         "plain_fp64": plain,
         "per_solve": {"evals_mean": run["evals"] / B, "grid_evals_mean": run["grid_evals"] / B,
+                      "evals_p50": float(np.percentile(evs, 50)),
+                      "evals_p99": float(np.percentile(evs, 99)), "evals_max": int(evs.max()),
                       "rounds": run["rounds"], "iters_mean": float(np.mean(its)),
+                      "iters_p50": float(np.percentile(its, 50)), "iters_max": int(its.max()),
                       "K_mean": float(np.mean(Kh)),
                       "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}},
         "roofline": roof,

@@ -78,11 +78,25 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
   const cd* ob = oms + in.poff;
   for (int m = tid; m < M; m += GRID_NT) {
     cd qv{0.0, 0.0}, sv{0.0, 0.0};
-    for (int n = m; n < N; n += M) qv = cfma(wb[n], cconj(cis_frac(((int64_t)n * r) % L, L)), qv);
-    // lags i = m mod M in (-N, N), from the most negative one up
-    for (int i = m - M * ((m + N - 1) / M); i < N; i += M) {
-      const int64_t ph = (((int64_t)i % L + L) % L) * r % L;
-      sv = cfma(ob[(i + P) & (P - 1)], cis_frac(ph, L), sv);
+    if (M >= N) {
+      // one sample and at most two lags (m and m - M) per point
+      if (m < N) {
+        const cd e = cis_frac(((int64_t)m * r) % L, L);
+        qv = cmul(wb[m], cconj(e));
+        sv = cmul(ob[m], e);
+      }
+      const int i2 = m - M;
+      if (i2 > -N) {
+        const int64_t ph = (((int64_t)i2 % L + L) % L) * r % L;
+        sv = cfma(ob[(i2 + P) & (P - 1)], cis_frac(ph, L), sv);
+      }
+    } else {
+      for (int n = m; n < N; n += M) qv = cfma(wb[n], cconj(cis_frac(((int64_t)n * r) % L, L)), qv);
+      // lags i = m mod M in (-N, N), from the most negative one up
+      for (int i = m - M * ((m + N - 1) / M); i < N; i += M) {
+        const int64_t ph = (((int64_t)i % L + L) % L) * r % L;
+        sv = cfma(ob[(i + P) & (P - 1)], cis_frac(ph, L), sv);
+      }
     }
     lq[pidx(m)] = C{(decltype(C{}.x))qv.x, (decltype(C{}.x))qv.y};
     ls[pidx(m)] = C{(decltype(C{}.x))sv.x, (decltype(C{}.x))sv.y};
