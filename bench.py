@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--plain", type=int, default=8,
                     help="instances for the plain FP64 one-per-launch baseline (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nufft", choices=["auto", "off", "on"], default="auto",
+                    help="off-grid Fourier sums by direct sums or NUFFT (default: per instance)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only copy this many bytes device to device (the calibration copy "
                          "for the HBM counters) and exit")
@@ -136,6 +138,8 @@ def main():
     ctx = sf.Context(0)
     ctx.set_factor({"auto": sf.SFLS_FACTOR_AUTO, "levinson": sf.SFLS_FACTOR_LEVINSON,
                     "schur": sf.SFLS_FACTOR_SCHUR}[args.factor])
+    ctx.set_nufft({"auto": sf.SFLS_NUFFT_AUTO, "off": sf.SFLS_NUFFT_OFF,
+                   "on": sf.SFLS_NUFFT_ON}[args.nufft])
     stream = torch.cuda.current_stream()
 
     def run_batch():
@@ -254,7 +258,7 @@ def main():
                                + " grid; one batched estimate per step",
                    "batch": B, "N": 4096, "L": 32768,
                    "precision": "mixed" if prec == sf.SFLS_MIXED else "fp64",
-                   "factor": args.factor},
+                   "factor": args.factor, "nufft": args.nufft},
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                        "p99": 1e3 * float(np.percentile(lat, 99))},
         "plain_fp64": plain,

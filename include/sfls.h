@@ -152,6 +152,22 @@ typedef enum { SFLS_FACTOR_AUTO = 0, SFLS_FACTOR_LEVINSON = 1, SFLS_FACTOR_SCHUR
 sfls_status sfls_set_factor(sfls_ctx* ctx, int32_t algo);
 
 /* ---------------------------------------------------------------------------
+ * a8. How sfls_active_eval and sfls_estimate evaluate the Fourier sums at
+ * off-grid frequencies (Sec. III-B and III-C evaluate them with the
+ * non-uniform FFT): direct O(N) sums per frequency, or Gaussian gridding
+ * (Greengard and Lee) on an oversampled grid of P = 2^ceil(log2(2N-1)) points
+ * with 32 grid points per frequency, whose relative error is below 1e-13.
+ *   SFLS_NUFFT_AUTO  per instance: NUFFT when N >= 512 and
+ *                    (frequencies) x N >= 2^23 (default)
+ *   SFLS_NUFFT_OFF   direct sums everywhere
+ *   SFLS_NUFFT_ON    NUFFT for every instance with at most 3P/4 frequencies
+ * The choice depends only on the instance, so a result does not depend on
+ * the batch around it.  Unknown modes: SFLS_EINVAL.
+ * ------------------------------------------------------------------------- */
+typedef enum { SFLS_NUFFT_AUTO = 0, SFLS_NUFFT_OFF = 1, SFLS_NUFFT_ON = 2 } sfls_nufft_mode;
+sfls_status sfls_set_nufft(sfls_ctx* ctx, int32_t mode);
+
+/* ---------------------------------------------------------------------------
  * a4. w = C^{-1} y from the generator by four triangular-Toeplitz products
  * done as FFT convolutions (Sec. III-A); yCy[b] = Re(y^H w), ww[b] = ||w||^2.
  *   y device (ydtype) [sum n]; rho device c128; delta device f64 (only
@@ -202,6 +218,7 @@ sfls_status sfls_grid_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int
  *   s, t, v, x = diag(Psi^H {I, D, D^2, D .. D} C^{-1} Psi)
  * from w = C^{-1} y and the generator (rho, delta).  Outputs are c128 device
  * arrays of sum K entries (instance b from koff[b], host); NULL skips one.
+ * Computed by direct sums or by the NUFFT per sfls_set_nufft.
  * ------------------------------------------------------------------------- */
 sfls_status sfls_active_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
                              const double* w, const double* rho, const double* delta,

@@ -29,8 +29,9 @@ EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror"
            "sfls_last_error", "sfls_version", "sfls_toeplitz_column", "sfls_factor",
            "sfls_gs_apply", "sfls_omega", "sfls_grid_eval", "sfls_active_eval", "sfls_estimate",
            "sfls_set_timing", "sfls_reset_stats", "sfls_kernel_stats", "sfls_last_run",
-           "sfls_set_factor"]
+           "sfls_set_factor", "sfls_set_nufft"]
 SFLS_FACTOR_AUTO, SFLS_FACTOR_LEVINSON, SFLS_FACTOR_SCHUR = 0, 1, 2
+SFLS_NUFFT_AUTO, SFLS_NUFFT_OFF, SFLS_NUFFT_ON = 0, 1, 2
 
 
 class SflsError(RuntimeError):
@@ -115,6 +116,8 @@ def lib() -> ctypes.CDLL:
     L.sfls_estimate.restype = st
     L.sfls_set_factor.argtypes = [_P, i32]
     L.sfls_set_factor.restype = st
+    L.sfls_set_nufft.argtypes = [_P, i32]
+    L.sfls_set_nufft.restype = st
     L.sfls_set_timing.argtypes = [_P, i32]
     L.sfls_set_timing.restype = st
     L.sfls_reset_stats.argtypes = [_P]
@@ -186,6 +189,9 @@ class Context:
 
     def set_factor(self, algo: int):
         self.check(lib().sfls_set_factor(self._h, int(algo)))
+
+    def set_nufft(self, mode: int):
+        self.check(lib().sfls_set_nufft(self._h, int(mode)))
 
     def set_timing(self, enable: bool = True):
         self.check(lib().sfls_set_timing(self._h, 1 if enable else 0))

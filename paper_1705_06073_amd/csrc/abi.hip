@@ -42,6 +42,7 @@ struct sfls_ctx {
   int64_t host_req_n = 0;
   bool timing = false;
   int32_t factor_algo = 0;  // sfls_factor_algo
+  int32_t nufft_mode = 0;   // sfls_nufft_mode
   hipEvent_t ev[2 * KID_COUNT] = {};
   sfls_kernel_stat kst[KID_COUNT] = {};
   sfls_run_stats last = {};
@@ -488,6 +489,14 @@ sfls_status sfls_set_factor(sfls_ctx* ctx, int32_t algo) {
   return SFLS_OK;
 }
 
+sfls_status sfls_set_nufft(sfls_ctx* ctx, int32_t mode) {
+  if (!ctx) return SFLS_EINVAL;
+  if (mode != SFLS_NUFFT_AUTO && mode != SFLS_NUFFT_OFF && mode != SFLS_NUFFT_ON)
+    return fail(ctx, SFLS_EINVAL, "unknown NUFFT mode %d", mode);
+  ctx->nufft_mode = mode;
+  return SFLS_OK;
+}
+
 sfls_status sfls_set_timing(sfls_ctx* ctx, int32_t enable) {
   if (!ctx) return SFLS_EINVAL;
   if (enable && !ctx->ev[0]) {
@@ -759,12 +768,16 @@ sfls_status sfls_active_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const i
   if ((s = upload(ctx, "ae_req", req, st, &dreq)) != SFLS_OK) return s;
   if ((s = upload(ctx, "ae_K", kc, st, &dK)) != SFLS_OK) return s;
   if ((s = wsT(ctx, "ae_prefix", (size_t)B + 1, &prefix)) != SFLS_OK) return s;
-  cd* dummy;
+  cd *dummy, *scratch = nullptr;
   if ((s = wsT(ctx, "ae_dummy", (size_t)std::max<int64_t>(ktot, 1), &dummy)) != SFLS_OK) return s;
+  if (ctx->nufft_mode != SFLS_NUFFT_OFF &&
+      (s = wsT(ctx, "scratch", (size_t)pt, &scratch)) != SFLS_OK)
+    return s;
   auto o = [&](double* p) { return p ? (cd*)p : dummy; };
   HIP_TRY(launch_active(dinfo, dreq, dK, nullptr, prefix, (int)B, theta, nullptr, (const cd*)w,
                         (const cd*)rho, delta, dcoef, o(q), o(r), o(u), o(s_), o(t), o(v), o(x),
-                        nullptr, nullptr, 2048, st));
+                        nullptr, nullptr, 2048, ctx->nufft_mode, ctx->tws64, scratch, sz.maxP,
+                        st));
   return SFLS_OK;
 }
 
@@ -1036,7 +1049,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
     HIP_TRY(tstart(KID_ACTIVE));
     HIP_TRY(launch_active(dinfo, P.req, P.K_e, ngrid > 0 ? ncand : nullptr, prefix, (int)B,
                           P.th_e, cand, w, rho, delta, dcoef, evq, evr, evu, evs, evt, evv, evx,
-                          cq, cs, act_blocks, st));
+                          cq, cs, act_blocks, ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st));
     HIP_TRY(tstop(KID_ACTIVE));
     HIP_TRY(tstart(KID_DRIVER));
     HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));

@@ -6,22 +6,36 @@
 namespace sfls {
 
 constexpr int ACT_NT = 256;
+constexpr int NU_NT = 512;
+
+// Whether instance work of npts points at N samples uses the NUFFT form below
+// (mode: 0 automatic, 1 never, 2 always); 4 npts <= 3 P keeps its per-point
+// storage inside the instance's scratch blocks 1-3.
+__device__ __forceinline__ bool use_nufft(int mode, int N, int P, int npts) {
+  if (mode == 1 || npts <= 0 || 4 * npts > 3 * P) return false;
+  if (mode == 2) return true;
+  return N >= 512 && (double)npts * (double)N >= NU_MIN_WORK;
+}
 
 // Exclusive prefix over instances of the number of work items:
 // items(b) = (EVAL ? K[b] : 0) + (GRID ? ncand[b] : 0).  prefix has B+1 entries.
-__global__ __launch_bounds__(1024) void k_item_scan(const int32_t* __restrict__ req,
+__global__ __launch_bounds__(1024) void k_item_scan(const InstInfo* __restrict__ info,
+                                                    const int32_t* __restrict__ req,
                                                     const int32_t* __restrict__ Keval,
                                                     const int32_t* __restrict__ ncand, int B,
-                                                    int32_t* __restrict__ prefix) {
+                                                    int nmode, int32_t* __restrict__ prefix) {
   __shared__ int32_t part[1024];
   const int tid = threadIdx.x;
   const int per = (B + 1023) / 1024;
   const int b0 = tid * per;
-  int32_t loc = 0;
-  for (int b = b0; b < min(B, b0 + per); ++b) {
+  // instances handled by the NUFFT kernel contribute no items here
+  auto items = [&](int b) {
     const int32_t rq = req[b];
-    loc += ((rq & REQ_EVAL) ? Keval[b] : 0) + ((rq & REQ_GRID) && ncand ? ncand[b] : 0);
-  }
+    const int n = ((rq & REQ_EVAL) ? Keval[b] : 0) + ((rq & REQ_GRID) && ncand ? ncand[b] : 0);
+    return use_nufft(nmode, info[b].N, info[b].P, n) ? 0 : n;
+  };
+  int32_t loc = 0;
+  for (int b = b0; b < min(B, b0 + per); ++b) loc += items(b);
   part[tid] = loc;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -33,8 +47,7 @@ __global__ __launch_bounds__(1024) void k_item_scan(const int32_t* __restrict__ 
   int32_t run = part[tid] - loc;  // exclusive
   for (int b = b0; b < min(B, b0 + per); ++b) {
     prefix[b] = run;
-    const int32_t rq = req[b];
-    run += ((rq & REQ_EVAL) ? Keval[b] : 0) + ((rq & REQ_GRID) && ncand ? ncand[b] : 0);
+    run += items(b);
   }
   if (tid == 1023) prefix[B] = part[1023];
 }
@@ -161,14 +174,192 @@ __global__ __launch_bounds__(ACT_NT) void k_active(const InstInfo* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same quantities by the non-uniform FFT (Sec. III-B/C use the NUFFT for
+// these off-grid Fourier sums), one workgroup per instance.  Gaussian gridding
+// (Greengard and Lee): with centred modes m = n - h (h = N/2), an oversampled
+// grid of P >= 2N points (grid spacing 2 pi / P) and the Gaussian
+// g(t) = exp(-t^2 / (4 tau)), whose Fourier transform is
+// sqrt(4 pi tau) exp(-m^2 tau),
+//   sum_n x_n e^{-j 2 pi n theta}
+//     = e^{-j 2 pi h theta} sum_m [x_{m+h} / ghat(m)] e^{-j m omega}    (omega = 2 pi theta)
+//     ~ e^{-j 2 pi h theta} (2 pi / P) sum_l g(omega - 2 pi l / P) X_l,
+// X = FFT_P of the deconvolved sequence, the sum over the 2 NU_MSP grid points
+// nearest to theta, and tau = pi NU_MSP / (N^2 R (R - 1/2)) with R = P / N.
+// The Gaussian's argument is formed as (2 pi / P)(theta P - l) (theta P is
+// exact for P a power of two) and the phase e^{-j 2 pi h theta} from the
+// reduced fraction of h theta, so no rounding grows with N.  The seven
+// sequences w, n w, n^2 w, x^a rho (a = 0..3) are transformed one at a time
+// in LDS (or, for P > CONV_LDS_P, in the instance's scratch after its four P
+// blocks); G_a at the points wait in scratch blocks 1-3.  Block 0 keeps the
+// spectrum of rho that the Gohberg-Semencul apply left there: a later round
+// that only evaluates the grid reuses it for omega.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NU_NT) void k_active_nufft(const InstInfo* __restrict__ info,
+                                                        const int32_t* __restrict__ req,
+                                                        const int32_t* __restrict__ Keval,
+                                                        const int32_t* __restrict__ ncand,
+                                                        int nmode, const double* __restrict__ theta,
+                                                        const int32_t* __restrict__ cand,
+                                                        const cd* __restrict__ w,
+                                                        const cd* __restrict__ rho,
+                                                        const double* __restrict__ delta,
+                                                        const SepCoef* __restrict__ coef,
+                                                        const cd* __restrict__ tws,
+                                                        cd* __restrict__ scratch,
+                                                        cd* __restrict__ oq, cd* __restrict__ orr,
+                                                        cd* __restrict__ ou, cd* __restrict__ os,
+                                                        cd* __restrict__ ot, cd* __restrict__ ov,
+                                                        cd* __restrict__ ox, cd* __restrict__ cq,
+                                                        double* __restrict__ cs) {
+  const int bi = blockIdx.x;
+  const int32_t rq = req ? req[bi] : REQ_EVAL;
+  const InstInfo in = info[bi];
+  const int nk = (rq & REQ_EVAL) ? Keval[bi] : 0;
+  const int nc = ((rq & REQ_GRID) && ncand) ? ncand[bi] : 0;
+  const int npts = nk + nc;
+  const int N = in.N, P = in.P, logP = in.logP;
+  if (!use_nufft(nmode, N, P, npts)) return;
+  extern __shared__ cd lds_sh[];
+  __shared__ cd s_tw[FFT_TWL];
+  __shared__ double s_e3[2 * NU_MSP];
+  const int tid = threadIdx.x;
+  const double TWO_PI = 6.283185307179586476925286766559;
+  const double R = (double)P / (double)N;
+  const double tau = 3.14159265358979323846 * NU_MSP / ((double)N * (double)N * R * (R - 0.5));
+  const double ag = (TWO_PI / P) * (TWO_PI / P) / (4.0 * tau);  // g at grid offset u: exp(-ag u^2)
+  const double sq = sqrt(4.0 * 3.14159265358979323846 * tau);
+  const int h = N / 2;
+  const double cN = 0.5 * (double)(N - 1);
+  load_tw_head<NU_NT>(s_tw, tws);
+  // exp(-ag t^2) for the offsets t = -(NU_MSP-1) .. NU_MSP
+  if (tid < 2 * NU_MSP) {
+    const double t = (double)(tid - (NU_MSP - 1));
+    s_e3[tid] = exp(-ag * t * t);
+  }
+  const cd* wb = w + in.off;
+  const cd* rb = rho + in.off;
+  cd* Gs = scratch + in.poff + P;  // G_a at the points: Gs[a * npts + p]
+  auto point = [&](int p) {
+    return p < nk ? theta[in.koff + p] : (double)cand[in.coff + (p - nk)] / (double)in.L;
+  };
+  auto body = [&](cd* __restrict__ buf) __attribute__((always_inline)) {
+    for (int j = 0; j < 7; ++j) {
+      const bool all = (j == 0 || j == 3 || j == 4);  // also needed at the candidates
+      const int np = all ? npts : nk;
+      if (np == 0) continue;
+      // deconvolved sequence on centred modes: buf[m mod P] = x_{m+h} / ghat(m)
+      batched_for<4>(tid, NU_NT, P, [&](int t) {
+        const int m = t < N - h ? t : t - P;  // centred mode stored at t
+        cd v{0.0, 0.0};
+        if (m >= -h && m < N - h) {
+          const int n = m + h;
+          const double dn = (double)n, x = dn - cN;
+          const cd src = j < 3 ? wb[n] : rb[n];
+          const double wgt = j == 0 ? 1.0 : j == 1 ? dn : j == 2 ? dn * dn
+                           : j == 3 ? 1.0 : j == 4 ? x : j == 5 ? x * x : x * x * x;
+          v = cscale(src, wgt * exp((double)m * (double)m * tau) / sq);
+        }
+        return v;
+      }, [&](int t, cd v) { buf[pidx(t)] = v; });
+      __syncthreads();
+      dif_fftn<NU_NT>(buf, buf, 1, logP, false, false, s_tw, tws);
+      // interpolation at the points (spectrum in bit-reversed order)
+      for (int p = tid; p < np; p += NU_NT) {
+        const double th = point(p);
+        const double sP = th * (double)P;  // exact: P is a power of two
+        const double fl = floor(sP);
+        const double d = sP - fl;          // exact
+        const int l0 = (int)fl;
+        // exp(-ag (d - t)^2) = exp(-ag d^2) exp(2 ag d t) exp(-ag t^2)
+        const double e1 = exp(-ag * d * d);
+        const double e2 = exp(2.0 * ag * d);
+        double e2t = exp(-2.0 * ag * d * (double)(NU_MSP - 1));  // e2^t at t = -(NU_MSP-1)
+        cd acc{0.0, 0.0};
+#pragma unroll 4
+        for (int i = 0; i < 2 * NU_MSP; ++i) {
+          const int l = (l0 + i - (NU_MSP - 1)) & (P - 1);
+          const double g = e1 * e2t * s_e3[i];
+          const cd X = buf[pidx(bitrev(l, logP))];
+          acc.x = fma(g, X.x, acc.x);
+          acc.y = fma(g, X.y, acc.y);
+          e2t *= e2;
+        }
+        const cd ph = cconj(cis2pi(frac_mul((double)h, th)));
+        cd val = cscale(cmul(acc, ph), TWO_PI / P);
+        if (j == 1) val = cscale(val, TWO_PI);
+        if (j == 2) val = cscale(val, TWO_PI * TWO_PI);
+        if (j == 0) {
+          if (p < nk) oq[in.koff + p] = val; else cq[in.coff + (p - nk)] = val;
+        } else if (j == 1) {
+          orr[in.koff + p] = val;
+        } else if (j == 2) {
+          ou[in.koff + p] = val;
+        } else {
+          Gs[(int64_t)(j - 3) * npts + p] = val;
+        }
+      }
+      __syncthreads();
+    }
+  };
+  if (P > CONV_LDS_P) body(scratch + in.poff + 4 * (int64_t)P);
+  else body(lds_sh);
+  // s, t, v, x from the G_a as in the direct form
+  const double idl = 1.0 / delta[in.off + N - 1];
+  const SepCoef& cf = coef[bi];
+  for (int p = tid; p < npts; p += NU_NT) {
+    const bool full = p < nk;
+    cd G[4];
+    for (int a = 0; a < 4; ++a)
+      G[a] = (full || a < 2) ? Gs[(int64_t)a * npts + p] : cd{0.0, 0.0};
+    const int nq = full ? 4 : 1;
+    cd outv[4];
+    for (int qk = 0; qk < nq; ++qk) {
+      const double* C = cf.c[qk];
+      const int am = (qk == 0) ? 1 : 3;
+      cd a2{0.0, 0.0};
+      for (int a = 0; a <= am; ++a)
+        for (int b2 = 0; b2 <= am; ++b2) {
+          const double cab = C[a * 4 + b2];
+          if (cab != 0.0) {
+            const cd pr = cmulc(G[a], G[b2]);
+            a2.x = fma(cab, pr.x, a2.x);
+            a2.y = fma(cab, pr.y, a2.y);
+          }
+        }
+      outv[qk] = cscale(a2, idl);
+    }
+    if (full) {
+      const int64_t o = in.koff + p;
+      os[o] = cd{outv[0].x, 0.0};
+      ot[o] = outv[1];
+      ov[o] = outv[2];
+      ox[o] = outv[3];
+    } else {
+      cs[in.coff + (p - nk)] = outv[0].x;
+    }
+  }
+}
+
 hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t* Keval,
                          const int32_t* ncand, int32_t* prefix, int B, const double* theta,
                          const int32_t* cand, const cd* w, const cd* rho, const double* delta,
                          const SepCoef* coef, cd* oq, cd* orr, cd* ou, cd* os, cd* ot, cd* ov,
-                         cd* ox, cd* cq, double* cs, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_item_scan, dim3(1), dim3(1024), 0, st, req, Keval, ncand, B, prefix);
+                         cd* ox, cd* cq, double* cs, int nblocks, int nmode, const cd* tws,
+                         cd* scratch, int maxP, hipStream_t st) {
+  if (!scratch) nmode = 1;  // no scratch for the NUFFT form: direct sums only
+  hipLaunchKernelGGL(k_item_scan, dim3(1), dim3(1024), 0, st, info, req, Keval, ncand, B, nmode,
+                     prefix);
   hipLaunchKernelGGL(k_active, dim3(nblocks), dim3(ACT_NT), 0, st, info, req, Keval, prefix, B,
                      theta, cand, w, rho, delta, coef, oq, orr, ou, os, ot, ov, ox, cq, cs);
+  if (nmode != 1) {
+    const size_t shm = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);
+    (void)hipFuncSetAttribute((const void*)k_active_nufft,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_active_nufft, dim3(B), dim3(NU_NT), shm, st, info, req, Keval, ncand,
+                       nmode, theta, cand, w, rho, delta, coef, tws, scratch, oq, orr, ou, os, ot,
+                       ov, ox, cq, cs);
+  }
   return hipGetLastError();
 }
 

@@ -104,7 +104,8 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
                          const int32_t* ncand, int32_t* prefix, int B, const double* theta,
                          const int32_t* cand, const cd* w, const cd* rho, const double* delta,
                          const SepCoef* coef, cd* oq, cd* orr, cd* ou, cd* os, cd* ot, cd* ov,
-                         cd* ox, cd* cq, double* cs, int nblocks, hipStream_t st);
+                         cd* ox, cd* cq, double* cs, int nblocks, int nmode, const cd* tws,
+                         cd* scratch, int maxP, hipStream_t st);
 hipError_t launch_init_state(const InstInfo* info, const void* y, int ydtype, DrvState* st,
                              int32_t* req, int B, hipStream_t s);
 hipError_t launch_driver(const InstInfo* info, const DrvParams* prm, DrvPools pools, int B,

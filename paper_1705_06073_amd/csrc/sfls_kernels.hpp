@@ -33,6 +33,13 @@ constexpr int CONV_LDS_P = 8192;
 constexpr int GRID_LOGM_F32 = 13;
 constexpr int GRID_LOGM_F64 = 12;
 
+// Active vectors by NUFFT (Gaussian gridding): half-width of the spreading
+// window in grid points (2 NU_MSP points per frequency; relative error below
+// 1e-14 at an oversampling of at least 2), and the work (points x N) from
+// which the automatic choice prefers it to the direct sums.
+constexpr int NU_MSP = 16;
+constexpr double NU_MIN_WORK = 8388608.0;
+
 // Request bits of one instance for the current evaluation round.
 enum : int32_t { REQ_EVAL = 1, REQ_GRID = 2, REQ_APPROX = 4 };
 

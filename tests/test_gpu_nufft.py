@@ -1,0 +1,153 @@
+"""a8 by the non-uniform FFT (Gaussian gridding, Sec. III-B/C): the active-set
+vectors against the dense oracle and against the exact off-grid sums at sizes
+up to N = 65536, through the C ABI with the NUFFT forced on; and a whole
+estimate with the NUFFT against the oracle at its result."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1705_06073_amd as sf  # noqa: E402
+from oracle import numerics as nm  # noqa: E402
+from paper_1705_06073_amd import synth  # noqa: E402
+from tests.gpu_helpers import DEV, c2d, d2c, f64d, ragged, relerr, zeros_c  # noqa: E402
+
+# Gaussian gridding with 32 points per frequency on a grid of >= 2N points:
+# relative error below 1e-13 (measured 1e-14 to N = 65536); the bound leaves
+# room for the FP64 rounding of the inputs' transforms.
+NUFFT_TOL = 1e-12
+TOL64 = 1e-9
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = sf.Context(0)
+    c.set_nufft(sf.SFLS_NUFFT_ON)
+    yield c
+    c.close()
+
+
+def states(ns, seed, kmax=6):
+    rng = np.random.default_rng(seed)
+    out = []
+    for N in ns:
+        K = int(rng.integers(1, kmax + 1))
+        th = rng.random(K)
+        ga = 0.2 + 2.0 * rng.random(K)
+        be = 0.05 + rng.random()
+        y = nm.steering(th, N) @ (rng.standard_normal(K) + 1j * rng.standard_normal(K)) \
+            + math.sqrt(be / 2) * (rng.standard_normal(N) + 1j * rng.standard_normal(N))
+        out.append((th, ga, be, y))
+    return out
+
+
+def active(ctx, ns, w, rho, delta, thq):
+    n, off = ragged(ns)
+    K = np.array([len(t) for t in thq], np.int64)
+    koff = np.concatenate([[0], np.cumsum(K)[:-1]]).astype(np.int64)
+    outs = [zeros_c(K.sum()) for _ in range(7)]
+    sf.sfls_active_eval(ctx, n, off, w, rho, delta, K, koff, f64d(np.concatenate(thq)), *outs)
+    torch.cuda.synchronize()
+    return koff, K, [d2c(o) for o in outs]
+
+
+@pytest.mark.parametrize("ns", [[64, 100], [1024], [4096], [4500]])
+def test_nufft_active_vectors_match_oracle(ctx, ns):
+    """q..x at the active frequencies and at off-grid points, NUFFT path, against
+    dense products with C^{-1} (P = 16384 at N = 4500: transforms in device
+    scratch)."""
+    print(f"[nufft active] sizes={ns}", flush=True)
+    st = states(ns, 31 + sum(ns))
+    n, off = ragged(ns)
+    cols = [nm.toeplitz_column(t, g, b, N) for (t, g, b, _), N in zip(st, ns)]
+    rho = zeros_c(n.sum())
+    delta = torch.zeros(int(n.sum()), dtype=torch.float64, device=DEV)
+    logdet = torch.zeros(len(ns), dtype=torch.float64, device=DEV)
+    status = torch.zeros(len(ns), dtype=torch.int32, device=DEV)
+    failed = torch.zeros(len(ns), dtype=torch.int64, device=DEV)
+    sf.sfls_factor(ctx, n, off, c2d(np.concatenate(cols)), rho, delta, logdet, status, failed)
+    w = zeros_c(n.sum())
+    sf.sfls_gs_apply(ctx, n, off, c2d(np.concatenate([s[3] for s in st])), sf.SFLS_C128, rho,
+                     delta, w)
+    rng = np.random.default_rng(5)
+    thq = [np.concatenate([s[0], rng.random(5)]) for s in st]
+    koff, K, og = active(ctx, ns, w, rho, delta, thq)
+    for b, (t, g, bb, y) in enumerate(st):
+        ev = nm.Evaluation(y, t, g, bb)
+        ref = nm.active_vectors(ev.F, ev.w, thq[b])
+        sl = slice(koff[b], koff[b] + K[b])
+        for i, name in enumerate("qrustvx"):
+            e = relerr(og[i][sl], ref[name])
+            assert e < TOL64, (b, name, e)
+
+
+@pytest.mark.parametrize("N", [1000, 16384, 65536])
+def test_nufft_sums_exact(ctx, N):
+    """q, r, u = Psi^H {w, Dw, D^2 w} for an arbitrary w at 60 frequencies
+    against the exact sums (phases reduced in extended precision); s..x for the
+    generator of C = beta I (rho = e_{N-1}, delta = beta) against their closed
+    forms N/beta, pi N(N-1)/beta, (2 pi)^2 sum n^2 / beta (v and x)."""
+    rng = np.random.default_rng(N)
+    wv = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    th = rng.random(60)
+    th[:3] = [0.0, 0.5, 1.0 - 2.0 ** -40]  # grid-aligned and wrap-around points
+    be = 0.7
+    rho = np.zeros(N, complex)
+    rho[-1] = 1.0
+    delta = np.full(N, be)
+    print(f"[nufft exact] N={N}", flush=True)
+    koff, K, og = active(ctx, [N], c2d(wv), c2d(rho), f64d(delta), [th])
+    Ps = nm.steering(th, N)
+    d = 2.0 * math.pi * np.arange(N)
+    ref = {"q": Ps.conj().T @ wv, "r": Ps.conj().T @ (d * wv), "u": Ps.conj().T @ (d * d * wv)}
+    for i, name in enumerate("qru"):
+        e = relerr(og[i], ref[name])
+        print(f"   {name} {e:.2e}", flush=True)
+        assert e < NUFFT_TOL, (name, e)
+    n = np.arange(N, dtype=np.float64)
+    closed = {"s": N / be, "t": math.pi * N * (N - 1) / be,
+              "v": (2 * math.pi) ** 2 * np.sum(n * n) / be, "x": (2 * math.pi) ** 2 * np.sum(n * n) / be}
+    for i, name in zip(range(3, 7), "stvx"):
+        e = np.max(np.abs(og[i] - closed[name])) / abs(closed[name])
+        print(f"   {name} {e:.2e}", flush=True)
+        assert e < NUFFT_TOL, (name, e)
+
+
+def test_estimate_with_nufft_matches_oracle(ctx):
+    """The N = 1024 workload (K = 20, SNR 15 dB, grid 8N) with every off-grid sum
+    by the NUFFT: the same model order as the oracle estimator and frequencies
+    within 1e-9/N of it (the rule the direct path meets)."""
+    from oracle.estimator import Params, estimate
+    from tests import metrics
+    inst = synth.workload_n1024(0)
+    g = sf.estimate_batch(ctx, [inst.y], sf.default_params(precision=sf.SFLS_FP64))[0]
+    o = estimate(inst.y.astype(np.complex128), Params())
+    print(f"   gpu K={g.K} ev={g.evaluations} | oracle K={o.K} ev={o.evaluations}", flush=True)
+    assert g.K == o.K
+    d = metrics.wrap_distance(g.theta, o.theta)
+    assert np.max(d) < 1e-9 / inst.N, np.max(d) * inst.N
+    assert abs(g.objective - o.objective) <= 1e-8 * max(1.0, abs(o.objective))
+
+
+def test_estimate_with_nufft(ctx):
+    """A whole estimate (N = 2048 instances of the uneven workload's kind and
+    the N = 1024 workload) with every off-grid sum by the NUFFT: the objective
+    and alpha at the returned point agree with the dense oracle there."""
+    insts = [synth.workload_n1024(0), synth.workload_uneven(13), synth.workload_uneven(17)]
+    res = sf.estimate_batch(ctx, [i.y.astype(np.complex128) for i in insts], sf.default_params())
+    for inst, r in zip(insts, res):
+        assert r.status in (sf.SFLS_OK, sf.SFLS_NOTCONV)
+        ev = nm.Evaluation(inst.y.astype(np.complex128), r.theta, r.gamma, r.beta)
+        fo = ev.f(r.K, r.zeta)
+        ef = abs(r.objective - fo) / max(1.0, abs(fo))
+        a_ref = r.gamma * ev.act["q"]
+        ea = np.max(np.abs(r.alpha - a_ref) / (1e-6 * np.abs(a_ref) + 1e-9))
+        print(f"   N={inst.N} K={r.K} (true {inst.K}) ev={r.evaluations} objective rel {ef:.2e} "
+              f"alpha err/tol {ea:.2e}", flush=True)
+        assert ef <= 1e-8 and ea <= 1.0
