@@ -77,6 +77,77 @@ def cpu_baseline(insts, per_solve_active, per_solve_grid, L_mult=8.0):
     }
 
 
+SERVE_CLASSES = ((1024, 512), (4096, 256), (16384, 256), (65536, 256))
+SERVE_HBM = (2 << 30, 4 << 30, 8 << 30, 32 << 30)
+SERVE_POOL = {256: 64, 1024: 64, 4096: 32, 16384: 16, 65536: 8}
+
+
+def serve_leg(rate, seconds, prec):
+    """The serving stream: Poisson arrivals at `rate`/s for `seconds`, N from
+    {256, 1024, 4096, 16384, 65536} (weights .3/.3/.2/.15/.05), K~Poisson(N/64),
+    SNR~U[5,30] dB, complex64 input, one server per size class on its own
+    stream.  Signals come from a seeded pool per N (request i of size N uses
+    pool entry i mod pool size); every request is a full solve."""
+    import numpy as np
+    import torch
+    import paper_1705_06073_amd as sf
+    from paper_1705_06073_amd import serving, synth
+
+    arrivals, sizes = synth.serving_stream(rate, seconds)
+    log(f"serving: {len(arrivals)} requests over {seconds:.0f} s; building the signal pool")
+    pool, addr_of = [], {}
+    o = 0
+    for N, cnt in SERVE_POOL.items():
+        for j in range(cnt):
+            inst = synth.workload_serving_signal(N, j)
+            pool.append(inst.y.astype(np.complex64))
+            addr_of[(N, j)] = o
+            o += N
+    y = torch.from_numpy(np.concatenate(pool).view(np.float32).copy()).to("cuda:0")
+    base = y.data_ptr()
+    count = {N: 0 for N in SERVE_POOL}
+    ptrs = np.zeros(len(arrivals), np.int64)
+    for i, N in enumerate(sizes):
+        N = int(N)
+        ptrs[i] = base + 8 * addr_of[(N, count[N] % SERVE_POOL[N])]
+        count[N] += 1
+    ctx = sf.Context(0)
+    params = sf.default_params(precision=prec)
+    lanes = serving.default_lanes(ctx, params, size_classes=SERVE_CLASSES, hbm_bytes=SERVE_HBM)
+    lane_of = [serving.lane_index(SERVE_CLASSES, int(n)) for n in sizes]
+    # warm the kernels of every lane once (one request each, not timed)
+    warm = [serving.lane_index(SERVE_CLASSES, N) for N in SERVE_POOL]
+    for N in SERVE_POOL:
+        li = serving.lane_index(SERVE_CLASSES, N)
+        lanes[li].submit(base + 8 * addr_of[(N, 0)], N, 0)
+    for s in lanes:
+        while s.stats()["in_flight"]:
+            s.step()
+        s.poll()
+    del warm
+    torch.cuda.synchronize()
+    log("serving: stream starts")
+    res, lat, st = serving.run_stream(lanes, lane_of, arrivals, sizes, lambda i: int(ptrs[i]),
+                                      log=log)
+    summ = serving.summarize(lat, sizes, arrivals, st["wall_s"])
+    statuses = np.array([r.status for r in res])
+    summ.update({
+        "rate_per_s": rate, "seconds": seconds, "wall_s": st["wall_s"],
+        "max_backlog": st["max_backlog"],
+        "lanes": [{"max_n": mx, "slots": sl, "rounds": ls["rounds"],
+                   "hbm_reserved_GiB": ls["bytes_reserved"] / 2**30}
+                  for (mx, sl), ls in zip(SERVE_CLASSES, st["lanes"])],
+        "status_counts": {int(k): int(v) for k, v in zip(*np.unique(statuses, return_counts=True))},
+        "evals_mean": float(np.mean([r.evaluations for r in res])),
+        "precision": "mixed" if prec == sf.SFLS_MIXED else "fp64",
+        "input": "complex64, device-resident signal pool " + str(SERVE_POOL),
+    })
+    for s in lanes:
+        s.close()
+    ctx.close()
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +165,12 @@ def main():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--factor", choices=["auto", "levinson", "schur"], default="auto",
                     help="generator recursion (auto: superfast Schur from N=256 on)")
+    ap.add_argument("--serve-seconds", type=float, default=0.0,
+                    help="also run the serving stream for this many seconds of arrivals "
+                         "(60 for the full stream)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving stream and print its summary")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -102,6 +179,9 @@ def main():
               f"WORLD_SIZE={world}); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.serve_only or args.serve_seconds > 0:
+        # one hardware queue per server stream (HIP's default is 4 per process)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
     import numpy as np
     import torch
     import paper_1705_06073_amd as sf
@@ -115,6 +195,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_bytes, "copies": 3}))
+        return
+    if args.serve_only:
+        prec = sf.SFLS_MIXED if args.precision == "mixed" else sf.SFLS_FP64
+        print(json.dumps({"serving": serve_leg(args.serve_rate, args.serve_seconds or 10.0,
+                                               prec)}), flush=True)
         return
     log(f"generating {args.batch} instances (N=4096)")
     insts, _ = make_workload(args.batch)
@@ -231,6 +316,10 @@ def main():
                                 "p99": 1e3 * float(np.percentile(times, 99))}}
         log(f"plain FP64: {nb} solves in {tp:.2f} s")
 
+    serve = None
+    if args.serve_seconds > 0:
+        serve = serve_leg(args.serve_rate, args.serve_seconds, prec)
+
     cpu = None
     if not args.no_cpu_baseline:
         g_per = run["grid_evals"] / B
@@ -272,6 +361,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "serving": serve,
     }
     ctx.close()
     print(json.dumps(result), flush=True)

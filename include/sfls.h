@@ -45,7 +45,8 @@ typedef enum {
     SFLS_EDEVICE = -3,    /* HIP runtime error */
     SFLS_ENOTPD = -4,     /* per instance: Toeplitz matrix not positive definite */
     SFLS_ECAPACITY = -5,  /* per instance: more components wanted than kcap */
-    SFLS_EUNSUPPORTED = -6 /* size outside what this build handles */
+    SFLS_EUNSUPPORTED = -6, /* size outside what this build handles */
+    SFLS_EAGAIN = -7      /* server: no free slot or device memory for the request now */
 } sfls_status;
 
 typedef enum { SFLS_FP64 = 0, SFLS_MIXED = 1 } sfls_precision; /* MIXED: FP32 grid FFTs */
@@ -287,6 +288,104 @@ void sfls_reset_stats(sfls_ctx* ctx);
 int32_t sfls_kernel_stats(const sfls_ctx* ctx, sfls_kernel_stat* out, int32_t cap);
 sfls_status sfls_last_run(const sfls_ctx* ctx, sfls_run_stats* stats, double* timeline,
                           int64_t cap, int64_t* ntimeline);
+
+/* ---------------------------------------------------------------------------
+ * Serving: the estimator of sfls_estimate (Sec. II-C..F on the Sec. III
+ * evaluations) for requests that arrive over time, by continuous batching.
+ *
+ * A server owns a pool of device memory of cfg.hbm_bytes and cfg.max_slots
+ * slots.  sfls_server_submit admits a request when a slot is free and the
+ * request's footprint (sfls_server_footprint: every per-request array of the
+ * round loop, sized by N rounded up to a power of two, at least 64) fits in
+ * the pool (a buddy allocation); otherwise it returns SFLS_EAGAIN and the
+ * server is unchanged.  The request's signal is copied into the pool, so the
+ * caller may reuse y at once.  Each round (sfls_server_launch) runs one
+ * evaluation for every admitted request that has asked for one, whatever its
+ * N, in the same kernels, and then the driver step; requests admitted since
+ * the previous round join it.  sfls_server_wait completes the round: requests
+ * whose estimate finished release their slot and memory, and their results
+ * wait for sfls_server_poll.  All state of a request (theta, gamma, beta,
+ * zeta, the L-BFGS memory, the generator) stays on the device until then.
+ *
+ * A request's result does not depend on the other requests in the pool: each
+ * kernel computes every instance from its own arrays, and the launch shapes
+ * that change the order of a computation are fixed per server (the
+ * factorisation is chosen from cfg.max_n as sfls_set_factor does, its LDS
+ * transform size from the largest N).  Results can differ in rounding from
+ * an sfls_estimate call whose batch has a different largest N.
+ *
+ * Not thread-safe; one host thread drives a server.  Several servers (for
+ * instance one per size class, each on its own stream) can run their rounds
+ * concurrently: launch each, then wait on each.
+ * ------------------------------------------------------------------------- */
+typedef struct sfls_server sfls_server;
+
+typedef struct {
+    int64_t max_n;       /* largest request length (2..SFLS_MAX_N) */
+    int32_t max_slots;   /* requests held on the device at once (1..65536) */
+    int32_t ydtype;      /* sfls_dtype of submitted signals */
+    uint64_t hbm_bytes;  /* device memory for request state (pool + per-slot arrays) */
+    int32_t kcap_shift;  /* component capacity of a request: min(N, max(N,64)-rounded-to-2^k >> kcap_shift), 0..6 */
+    int32_t reserved;
+    void* stream;        /* hipStream_t for the server's work; NULL: the server creates one */
+} sfls_server_config;
+
+typedef struct {
+    uint64_t tag;        /* the caller's tag from sfls_server_submit */
+    int64_t n;           /* request length */
+    int64_t K;           /* model order: number of components */
+    int64_t comp_off;    /* components at theta/gamma[comp_off..+K), alpha[2 comp_off..+2K) */
+    double beta, zeta, objective;
+    int32_t iters, evals, status, reserved;
+    double t_submit;     /* seconds since server creation: admission */
+    double t_done;       /* seconds since server creation: end of the round that finished it */
+} sfls_result;
+
+typedef struct {
+    int64_t rounds;        /* rounds completed */
+    int64_t admitted;      /* requests admitted */
+    int64_t completed;     /* results produced */
+    int64_t in_flight;     /* requests holding a slot */
+    int64_t units_used;    /* pool units (samples) allocated */
+    int64_t units_total;   /* pool units */
+    uint64_t bytes_per_unit;
+    uint64_t bytes_reserved; /* device memory held by the server */
+    double gpu_seconds;    /* host wall time between launch and the end of each round, summed */
+} sfls_server_stats;
+
+/* max_n 65536, 1024 slots, c64 input, 8 GiB, kcap_shift 0 (K_max = N, footnote of
+ * Sec. II-A), own stream. */
+void sfls_server_config_default(sfls_server_config* cfg);
+/* Create a server on ctx's device (ctx must outlive it).  params: NULL =
+ * sfls_params_default.  SFLS_EINVAL for bad sizes or a pool too small for one
+ * request of max_n; SFLS_ENOMEM if the device memory is not available. */
+sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg,
+                               const sfls_params* params, sfls_server** out);
+/* Waits for outstanding work and frees everything the server holds. */
+sfls_status sfls_server_destroy(sfls_server* srv);
+/* Device bytes a request of length n reserves from the pool. */
+sfls_status sfls_server_footprint(const sfls_server* srv, int64_t n, uint64_t* bytes);
+/* Admit a request: y (device or host pointer, cfg.ydtype, n elements).
+ * SFLS_EAGAIN: no free slot or pool memory now (retry after a round);
+ * SFLS_EINVAL: n < 2 or NULL y; SFLS_EUNSUPPORTED: n > max_n. */
+sfls_status sfls_server_submit(sfls_server* srv, const void* y, int64_t n, uint64_t tag);
+/* Enqueue one round on the server's stream (no-op when nothing is admitted
+ * or a round is already in flight).  Returns without waiting. */
+sfls_status sfls_server_launch(sfls_server* srv);
+/* Complete the round in flight.  block = 0: return at once with *ready = 0
+ * if the device has not finished it.  *ready = 1 when the round was completed
+ * (or none was in flight).  *finished (may be NULL) = results it produced. */
+sfls_status sfls_server_wait(sfls_server* srv, int32_t block, int32_t* ready, int32_t* finished);
+/* sfls_server_launch followed by a blocking sfls_server_wait. */
+sfls_status sfls_server_step(sfls_server* srv, int32_t* finished);
+/* Move up to max_results finished results, oldest first, into res (host),
+ * their components into theta, gamma (host f64 [comp_cap]) and alpha (host
+ * f64 pairs [2 comp_cap]); stops before a result whose components would not
+ * fit.  *nres = results returned. */
+sfls_status sfls_server_poll(sfls_server* srv, sfls_result* res, int32_t max_results,
+                             double* theta, double* gamma, double* alpha, int64_t comp_cap,
+                             int32_t* nres);
+sfls_status sfls_server_get_stats(const sfls_server* srv, sfls_server_stats* stats);
 
 #ifdef __cplusplus
 }

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libsfls.so")
 SFLS_OK, SFLS_NOTCONV = 0, 1
 SFLS_EINVAL, SFLS_ENOMEM, SFLS_EDEVICE, SFLS_ENOTPD, SFLS_ECAPACITY, SFLS_EUNSUPPORTED = \
     -1, -2, -3, -4, -5, -6
+SFLS_EAGAIN = -7
 SFLS_FP64, SFLS_MIXED = 0, 1
 SFLS_C64, SFLS_C128 = 0, 1
 SFLS_MAX_N = 65536
@@ -29,7 +30,10 @@ EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror"
            "sfls_last_error", "sfls_version", "sfls_toeplitz_column", "sfls_factor",
            "sfls_gs_apply", "sfls_omega", "sfls_grid_eval", "sfls_active_eval", "sfls_estimate",
            "sfls_set_timing", "sfls_reset_stats", "sfls_kernel_stats", "sfls_last_run",
-           "sfls_set_factor", "sfls_set_nufft"]
+           "sfls_set_factor", "sfls_set_nufft", "sfls_server_config_default",
+           "sfls_server_create", "sfls_server_destroy", "sfls_server_footprint",
+           "sfls_server_submit", "sfls_server_launch", "sfls_server_wait", "sfls_server_step",
+           "sfls_server_poll", "sfls_server_get_stats"]
 SFLS_FACTOR_AUTO, SFLS_FACTOR_LEVINSON, SFLS_FACTOR_SCHUR = 0, 1, 2
 SFLS_NUFFT_AUTO, SFLS_NUFFT_OFF, SFLS_NUFFT_ON = 0, 1, 2
 
@@ -65,6 +69,30 @@ class sfls_kernel_stat(ctypes.Structure):
 class sfls_run_stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("evals", ctypes.c_int64),
                 ("grid_evals", ctypes.c_int64), ("wall_seconds", ctypes.c_double)]
+
+
+class sfls_server_config(ctypes.Structure):
+    _fields_ = [("max_n", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("ydtype", ctypes.c_int32), ("hbm_bytes", ctypes.c_uint64),
+                ("kcap_shift", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class sfls_result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("n", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("comp_off", ctypes.c_int64), ("beta", ctypes.c_double),
+                ("zeta", ctypes.c_double), ("objective", ctypes.c_double),
+                ("iters", ctypes.c_int32), ("evals", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class sfls_server_stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("in_flight", ctypes.c_int64),
+                ("units_used", ctypes.c_int64), ("units_total", ctypes.c_int64),
+                ("bytes_per_unit", ctypes.c_uint64), ("bytes_reserved", ctypes.c_uint64),
+                ("gpu_seconds", ctypes.c_double)]
 
 
 _lib = None
@@ -127,6 +155,29 @@ def lib() -> ctypes.CDLL:
     L.sfls_last_run.argtypes = [_P, ctypes.POINTER(sfls_run_stats), ctypes.POINTER(ctypes.c_double),
                                 i64, _I64P]
     L.sfls_last_run.restype = st
+    u64 = ctypes.c_uint64
+    _I32P = ctypes.POINTER(ctypes.c_int32)
+    L.sfls_server_config_default.argtypes = [ctypes.POINTER(sfls_server_config)]
+    L.sfls_server_config_default.restype = None
+    L.sfls_server_create.argtypes = [_P, ctypes.POINTER(sfls_server_config),
+                                     ctypes.POINTER(sfls_params), ctypes.POINTER(_P)]
+    L.sfls_server_create.restype = st
+    L.sfls_server_destroy.argtypes = [_P]
+    L.sfls_server_destroy.restype = st
+    L.sfls_server_footprint.argtypes = [_P, i64, ctypes.POINTER(u64)]
+    L.sfls_server_footprint.restype = st
+    L.sfls_server_submit.argtypes = [_P, _P, i64, u64]
+    L.sfls_server_submit.restype = st
+    L.sfls_server_launch.argtypes = [_P]
+    L.sfls_server_launch.restype = st
+    L.sfls_server_wait.argtypes = [_P, i32, _I32P, _I32P]
+    L.sfls_server_wait.restype = st
+    L.sfls_server_step.argtypes = [_P, _I32P]
+    L.sfls_server_step.restype = st
+    L.sfls_server_poll.argtypes = [_P, ctypes.POINTER(sfls_result), i32, _P, _P, _P, i64, _I32P]
+    L.sfls_server_poll.restype = st
+    L.sfls_server_get_stats.argtypes = [_P, ctypes.POINTER(sfls_server_stats)]
+    L.sfls_server_get_stats.restype = st
     _lib = L
     return L
 
@@ -345,3 +396,123 @@ def estimate_batch(ctx: Context, ys, params: sfls_params | None = None, kcap: in
                                   iterations=int(h["iters"][b]), evaluations=int(h["evals"][b]),
                                   status=int(h["status"][b])))
     return res
+
+
+# ------------------------------------------------------------- serving ------
+
+@dataclass
+class ServedResult:
+    tag: int
+    n: int
+    K: int
+    theta: np.ndarray
+    alpha: np.ndarray
+    gamma: np.ndarray
+    beta: float
+    zeta: float
+    objective: float
+    iterations: int
+    evaluations: int
+    status: int
+    t_submit: float
+    t_done: float
+
+
+class Server:
+    """Continuous-batching estimation server (sfls_server_* of the C ABI).
+
+    Requests are admitted with submit() (False when the server has no free slot
+    or pool memory for it now), rounds run with step() or launch()/wait(), and
+    finished results are collected with poll()."""
+
+    def __init__(self, ctx: Context, max_n: int = SFLS_MAX_N, max_slots: int = 1024,
+                 ydtype: int = SFLS_C64, hbm_bytes: int = 8 << 30, kcap_shift: int = 0,
+                 params: sfls_params | None = None, stream=None):
+        cfg = sfls_server_config()
+        lib().sfls_server_config_default(ctypes.byref(cfg))
+        cfg.max_n, cfg.max_slots, cfg.ydtype = int(max_n), int(max_slots), int(ydtype)
+        cfg.hbm_bytes, cfg.kcap_shift = int(hbm_bytes), int(kcap_shift)
+        cfg.stream = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        self.ctx = ctx
+        self.ydtype = int(ydtype)
+        self._h = _P()
+        pp = ctypes.byref(params) if params is not None else None
+        ctx.check(lib().sfls_server_create(ctx.handle, ctypes.byref(cfg), pp,
+                                           ctypes.byref(self._h)))
+        self._res = (sfls_result * 4096)()
+        self._cap = 1 << 16
+        self._th = np.zeros(self._cap)
+        self._ga = np.zeros(self._cap)
+        self._al = np.zeros(2 * self._cap)
+        self.in_flight = False
+
+    def footprint(self, n: int) -> int:
+        b = ctypes.c_uint64(0)
+        self.ctx.check(lib().sfls_server_footprint(self._h, int(n), ctypes.byref(b)))
+        return int(b.value)
+
+    def submit(self, y, n: int, tag: int) -> bool:
+        """y: GPU tensor (interleaved re/im of the server's dtype) or a device address."""
+        ptr = ctypes.c_void_p(y if isinstance(y, int) else y.data_ptr())
+        st = lib().sfls_server_submit(self._h, ptr, int(n), int(tag))
+        if st == SFLS_EAGAIN:
+            return False
+        self.ctx.check(st)
+        return True
+
+    def launch(self):
+        self.ctx.check(lib().sfls_server_launch(self._h))
+        self.in_flight = self.stats()["in_flight"] > 0
+
+    def wait(self, block: bool = True):
+        ready, fin = ctypes.c_int32(0), ctypes.c_int32(0)
+        self.ctx.check(lib().sfls_server_wait(self._h, 1 if block else 0, ctypes.byref(ready),
+                                              ctypes.byref(fin)))
+        if ready.value:
+            self.in_flight = False
+        return bool(ready.value), int(fin.value)
+
+    def step(self) -> int:
+        fin = ctypes.c_int32(0)
+        self.ctx.check(lib().sfls_server_step(self._h, ctypes.byref(fin)))
+        return int(fin.value)
+
+    def poll(self, max_results: int = 4096):
+        out = []
+        while True:
+            nres = ctypes.c_int32(0)
+            th = self._th.ctypes.data_as(ctypes.c_void_p)
+            ga = self._ga.ctypes.data_as(ctypes.c_void_p)
+            al = self._al.ctypes.data_as(ctypes.c_void_p)
+            st = lib().sfls_server_poll(self._h, self._res, min(max_results - len(out), 4096),
+                                        th, ga, al, self._cap, ctypes.byref(nres))
+            self.ctx.check(st)
+            alc = self._al.view(np.complex128)
+            for i in range(nres.value):
+                r = self._res[i]
+                o, k = int(r.comp_off), int(r.K)
+                out.append(ServedResult(tag=int(r.tag), n=int(r.n), K=k,
+                                        theta=self._th[o:o + k].copy(),
+                                        alpha=alc[o:o + k].copy(),
+                                        gamma=self._ga[o:o + k].copy(), beta=r.beta, zeta=r.zeta,
+                                        objective=r.objective, iterations=int(r.iters),
+                                        evaluations=int(r.evals), status=int(r.status),
+                                        t_submit=r.t_submit, t_done=r.t_done))
+            if nres.value == 0 or len(out) >= max_results:
+                return out
+
+    def stats(self) -> dict:
+        s = sfls_server_stats()
+        self.ctx.check(lib().sfls_server_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in sfls_server_stats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().sfls_server_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -27,7 +27,8 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-command-line-argument",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
-SOURCES = ["k_factor.hip", "k_schur.hip", "k_conv.hip", "k_grid.hip", "k_active.hip", "k_logdet.hip", "k_driver.hip", "abi.hip"]
+SOURCES = ["k_factor.hip", "k_schur.hip", "k_conv.hip", "k_grid.hip", "k_active.hip", "k_logdet.hip",
+           "k_driver.hip", "abi.hip", "server.hip"]
 
 
 def hipcc() -> str:

@@ -12,44 +12,17 @@
 #include <string>
 #include <vector>
 
-#include "k_launch.hpp"
-#include "sfls.h"
+#include "host_internal.hpp"
 
 using namespace sfls;
+using namespace sfls_host;
 
 static_assert(sizeof(sfls_params) == 136, "sfls_params layout is part of the ABI");
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t n = 0;
-};
-
-enum KernelId { KID_GEN = 0, KID_FACTOR, KID_REFINE, KID_APPLY, KID_OMEGA, KID_GRID, KID_SELECT,
-                KID_ACTIVE, KID_DRIVER, KID_COUNT };
 const char* const kKernelNames[KID_COUNT] = {"toeplitz_column", "factor", "refine", "gs_apply",
                                              "omega", "grid", "select", "active", "driver"};
 
-struct sfls_ctx {
-  int device = 0;
-  std::string err;
-  cd* tw64 = nullptr;
-  cf* tw32 = nullptr;
-  cd* tws64 = nullptr;  // stage-major FFT twiddles
-  cf* tws32 = nullptr;
-  int logtw = 17;
-  std::map<std::string, DevBuf> bufs;
-  int32_t* host_req = nullptr;  // pinned copy of the per-instance request bits
-  int64_t host_req_n = 0;
-  bool timing = false;
-  int32_t factor_algo = 0;  // sfls_factor_algo
-  int32_t nufft_mode = 0;   // sfls_nufft_mode
-  hipEvent_t ev[2 * KID_COUNT] = {};
-  sfls_kernel_stat kst[KID_COUNT] = {};
-  sfls_run_stats last = {};
-  std::vector<double> timeline;
-};
-
-namespace {
+namespace sfls_host {
 
 const char* kVersion = "sfls 0.1 (gfx950)";
 
@@ -63,12 +36,6 @@ sfls_status fail(sfls_ctx* ctx, sfls_status s, const char* fmt, ...) {
   return s;
 }
 
-#define HIP_TRY(expr)                                                                        \
-  do {                                                                                       \
-    hipError_t e_ = (expr);                                                                  \
-    if (e_ != hipSuccess)                                                                    \
-      return fail(ctx, SFLS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
-  } while (0)
 
 // grow-only named workspace buffer
 sfls_status ws(sfls_ctx* ctx, const char* name, size_t bytes, void** out) {
@@ -207,15 +174,6 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 // ----------------------------------------------------------------------------
 // Superfast Schur plans: the recursion of each N flattened into actions.
 // ----------------------------------------------------------------------------
-constexpr int kSchurMinN = 256;  // AUTO: superfast Schur from this N on
-
-struct SchurPlan {
-  std::vector<SchurAct> acts;
-  int32_t mmax[SCH_MAXL] = {};
-  int32_t fspec[SCH_MAXL] = {};
-  int nlev = 0;
-};
-
 void schur_rec(SchurPlan& P, int n0, int m, int level, int side, int win, int Nroot) {
   const bool root = level == 0;
   P.nlev = std::max(P.nlev, level + 1);
@@ -257,6 +215,36 @@ double schur_flops(const SchurPlan& P) {
   return f;
 }
 
+SchurPlan schur_plan(int64_t N) {
+  SchurPlan P;
+  if (N > 1) schur_rec(P, 0, (int)N - 1, 0, 0, -1, (int)N);
+  return P;
+}
+
+int64_t schur_layout(const SchurPlan& P, SchurLayout& L, int* fm_out) {
+  std::memset(&L, 0, sizeof L);
+  L.nact = (int32_t)P.acts.size();
+  int64_t o = 0;
+  int fm = 64, fbig = 0;  // the leaves use the transform buffers as 64-element scratch
+  for (int l = 0; l < P.nlev; ++l) {
+    L.mmax[l] = P.mmax[l];
+    L.win[l] = o;
+    o += 2 * (int64_t)P.mmax[l];
+    L.res[l] = o;
+    o += 8 * (int64_t)P.mmax[l];
+    L.spec[l] = o;
+    o += 2 * (int64_t)P.fspec[l];
+    if (P.fspec[l] > SCH_LDS_F) fbig = std::max(fbig, P.fspec[l]);
+    else fm = std::max(fm, P.fspec[l]);
+    if (P.mmax[l] <= SCH_DIRECT) fm = std::max(fm, 8 * P.mmax[l] + 256);
+  }
+  L.xbig = o;
+  if (fbig) o += 2 * (int64_t)padded(fbig);
+  L.Fmax = fm;
+  *fm_out = fm;
+  return o;
+}
+
 // Build per-instance layouts and the action pool for a batch; returns the
 // scratch size (complex elements), the largest FFT size and the algorithmic
 // flops of each instance.
@@ -273,8 +261,7 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
     const int64_t N = n[b];
     auto it = byN.find(N);
     if (it == byN.end()) {
-      SchurPlan P;
-      if (N > 1) schur_rec(P, 0, (int)N - 1, 0, 0, -1, (int)N);
+      SchurPlan P = schur_plan(N);
       const int64_t aoff = (int64_t)pool.size();
       pool.insert(pool.end(), P.acts.begin(), P.acts.end());
       it = byN.emplace(N, std::make_pair(aoff, P)).first;
@@ -282,34 +269,36 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
     const SchurPlan& P = it->second.second;
     flops[(size_t)b] = schur_flops(P);
     SchurLayout& L = lay[(size_t)b];
-    std::memset(&L, 0, sizeof L);
+    int fm = 64;
+    const int64_t o = schur_layout(P, L, &fm);
     L.act_off = it->second.first;
-    L.nact = (int32_t)P.acts.size();
     L.scr_off = scr_total;
-    int64_t o = 0;
-    int fm = 64, fbig = 0;
-    for (int l = 0; l < P.nlev; ++l) {
-      L.mmax[l] = P.mmax[l];
-      L.win[l] = o;
-      o += 2 * (int64_t)P.mmax[l];
-      L.res[l] = o;
-      o += 8 * (int64_t)P.mmax[l];
-      L.spec[l] = o;
-      o += 2 * (int64_t)P.fspec[l];
-      if (P.fspec[l] > SCH_LDS_F) fbig = std::max(fbig, P.fspec[l]);
-      else fm = std::max(fm, P.fspec[l]);
-      if (P.mmax[l] <= SCH_DIRECT) fm = std::max(fm, 8 * P.mmax[l] + 256);
-    }
-    L.xbig = o;
-    if (fbig) o += 2 * (int64_t)padded(fbig);
-    L.Fmax = fm;
     Fmax = std::max(Fmax, fm);
     scr_total += o;
   }
   for (auto& L : lay) L.Fmax = Fmax;
 }
 
-}  // namespace
+
+DrvParams drv_params(const sfls_params& p) {
+  DrvParams dp;
+  dp.tau = p.tau; dp.tol_obj = p.tol_obj; dp.tol_newton = p.tol_newton;
+  dp.eps_beta_rel = p.eps_beta_rel; dp.eps_L = p.eps_L; dp.approx_ratio = p.approx_ratio;
+  dp.approx_min_dist = p.approx_min_dist; dp.ls_c1 = p.ls_c1; dp.curv_eps = p.curv_eps;
+  dp.polish_tol = p.polish_tol; dp.polish_ftol = p.polish_ftol; dp.J = p.lbfgs_J;
+  dp.max_inner = p.max_inner; dp.max_outer = p.max_outer;
+  dp.approx_max_iters = p.approx_max_iters; dp.approx_use_tau = p.approx_use_tau;
+  dp.ls_max = p.ls_max; dp.polish_max_iters = p.polish_max_iters; dp.cand_cap = p.cand_cap;
+  return dp;
+}
+
+bool params_valid(const sfls_params& p) {
+  return p.L_mult > 0 && p.lbfgs_J >= 1 && p.lbfgs_J <= 16 && p.max_inner >= 0 &&
+         p.max_outer >= 1 && p.ls_max >= 1 && p.polish_max_iters >= 0 && p.cand_cap >= 1 &&
+         p.cand_cap <= 2048 && (p.precision == SFLS_FP64 || p.precision == SFLS_MIXED);
+}
+
+}  // namespace sfls_host
 
 // Buffers of the generator refinement that follows the superfast recursion:
 // transform scratch (4 P per instance at poff) and two sample-length arrays.
@@ -357,14 +346,12 @@ static sfls_status run_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const 
   return run_refine(ctx, B, dinfo, req, c, rho, delta, status, st, dlay, rf);
 }
 
-static bool use_schur(const sfls_ctx* ctx, int maxN) {
+bool sfls_host::use_schur(const sfls_ctx* ctx, int maxN) {
   if (ctx->factor_algo == SFLS_FACTOR_SCHUR) return maxN > 1;
   if (ctx->factor_algo == SFLS_FACTOR_LEVINSON) return false;
   return maxN >= kSchurMinN;
 }
 
-// The Levinson kernel keeps an instance's vectors in registers: N <= 4096.
-constexpr int kLevinsonMaxN = 4096;
 static sfls_status check_factor_size(sfls_ctx* ctx, int maxN) {
   if (!use_schur(ctx, maxN) && maxN > kLevinsonMaxN)
     return fail(ctx, SFLS_EUNSUPPORTED, "the Levinson recursion supports n <= %d (got %d)",
@@ -374,7 +361,7 @@ static sfls_status check_factor_size(sfls_ctx* ctx, int maxN) {
 
 // Grid sub-FFT size: M = min(2^ceil(log2 N), cap) with the cap set by what
 // two M-point buffers of the grid's precision fit in LDS.
-static void cap_grid_m(InstInfo& in, int precision) {
+void sfls_host::cap_grid_m(InstInfo& in, int precision) {
   const int cap = precision == SFLS_FP64 ? GRID_LOGM_F64 : GRID_LOGM_F32;
   if (in.logM > cap) {
     in.logM = cap;
@@ -447,6 +434,7 @@ const char* sfls_strerror(sfls_status s) {
     case SFLS_ENOTPD: return "Toeplitz matrix not positive definite";
     case SFLS_ECAPACITY: return "component capacity exceeded";
     case SFLS_EUNSUPPORTED: return "size not supported by this build";
+    case SFLS_EAGAIN: return "no free slot or device memory for the request now";
   }
   return "unknown status";
 }
@@ -545,6 +533,7 @@ sfls_status sfls_destroy(sfls_ctx* ctx) {
   if (ctx->tws64) (void)hipFree(ctx->tws64);
   if (ctx->tws32) (void)hipFree(ctx->tws32);
   if (ctx->host_req) (void)hipHostFree(ctx->host_req);
+  if (ctx->upload) (void)hipStreamDestroy(ctx->upload);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   delete ctx;
@@ -797,10 +786,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   if (ydtype != SFLS_C64 && ydtype != SFLS_C128) return fail(ctx, SFLS_EINVAL, "bad ydtype");
   sfls_params p;
   if (params) p = *params; else sfls_params_default(&p);
-  if (!(p.L_mult > 0) || p.lbfgs_J < 1 || p.lbfgs_J > 16 || p.max_inner < 0 || p.max_outer < 1 ||
-      p.ls_max < 1 || p.polish_max_iters < 0 || p.cand_cap < 1 || p.cand_cap > 2048 ||
-      (p.precision != SFLS_FP64 && p.precision != SFLS_MIXED))
-    return fail(ctx, SFLS_EINVAL, "invalid sfls_params");
+  if (!params_valid(p)) return fail(ctx, SFLS_EINVAL, "invalid sfls_params");
   (void)hipSetDevice(ctx->device);
   hipStream_t st = as_stream(stream);
   Sizes sz;
@@ -833,15 +819,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
     okoff[(size_t)b] = koff[b];
     sep_coef((int)n[b], coef[(size_t)b]);
   }
-  DrvParams dp;
-  dp.tau = p.tau; dp.tol_obj = p.tol_obj; dp.tol_newton = p.tol_newton;
-  dp.eps_beta_rel = p.eps_beta_rel; dp.eps_L = p.eps_L; dp.approx_ratio = p.approx_ratio;
-  dp.approx_min_dist = p.approx_min_dist; dp.ls_c1 = p.ls_c1; dp.curv_eps = p.curv_eps;
-  dp.polish_tol = p.polish_tol; dp.polish_ftol = p.polish_ftol; dp.J = p.lbfgs_J;
-  dp.max_inner = p.max_inner; dp.max_outer = p.max_outer;
-  dp.approx_max_iters = p.approx_max_iters; dp.approx_use_tau = p.approx_use_tau;
-  dp.ls_max = p.ls_max; dp.polish_max_iters = p.polish_max_iters; dp.cand_cap = p.cand_cap;
-  std::vector<DrvParams> dpv(1, dp);
+  std::vector<DrvParams> dpv(1, drv_params(p));
 
   InstInfo* dinfo;
   SepCoef* dcoef;

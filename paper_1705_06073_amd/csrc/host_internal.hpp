@@ -1,0 +1,93 @@
+// Host-side internals shared by the C-ABI translation units (abi.hip,
+// server.hip): the context, workspace helpers, and the planning of sizes that
+// the kernels read from InstInfo / SchurLayout.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "k_launch.hpp"
+#include "sfls.h"
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+enum KernelId { KID_GEN = 0, KID_FACTOR, KID_REFINE, KID_APPLY, KID_OMEGA, KID_GRID, KID_SELECT,
+                KID_ACTIVE, KID_DRIVER, KID_COUNT };
+
+struct sfls_ctx {
+  int device = 0;
+  std::string err;
+  sfls::cd* tw64 = nullptr;
+  sfls::cf* tw32 = nullptr;
+  sfls::cd* tws64 = nullptr;  // stage-major FFT twiddles
+  sfls::cf* tws32 = nullptr;
+  int logtw = 17;
+  std::map<std::string, DevBuf> bufs;
+  int32_t* host_req = nullptr;  // pinned copy of the per-instance request bits
+  int64_t host_req_n = 0;
+  bool timing = false;
+  int32_t factor_algo = 0;  // sfls_factor_algo
+  int32_t nufft_mode = 0;   // sfls_nufft_mode
+  hipEvent_t ev[2 * KID_COUNT] = {};
+  sfls_kernel_stat kst[KID_COUNT] = {};
+  sfls_run_stats last = {};
+  std::vector<double> timeline;
+  hipStream_t upload = nullptr;  // admission copies of the servers on this context
+};
+
+namespace sfls_host {
+
+using sfls::cd;
+using sfls::cf;
+
+sfls_status fail(sfls_ctx* ctx, sfls_status s, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return sfls_host::fail(ctx, SFLS_EDEVICE, "%s failed: %s", #expr,                      \
+                             hipGetErrorString(e_));                                         \
+  } while (0)
+
+int ilog2_ceil(int64_t v);
+bool is_pow2(int64_t v);
+
+// Coefficients of the separable forms of s, t, v, x for N samples.
+void sep_coef(int N, sfls::SepCoef& out);
+
+// The superfast recursion of one N flattened into actions.
+struct SchurPlan {
+  std::vector<sfls::SchurAct> acts;
+  int32_t mmax[sfls::SCH_MAXL] = {};
+  int32_t fspec[sfls::SCH_MAXL] = {};
+  int nlev = 0;
+};
+constexpr int kSchurMinN = 256;  // AUTO: superfast Schur from this N on
+
+// Plan of the recursion for N samples (no actions for N = 1).
+SchurPlan schur_plan(int64_t N);
+// Algorithmic FP64 flops of one factorisation by `P`.
+double schur_flops(const SchurPlan& P);
+// Per-instance scratch layout of `P` (offsets from the instance's scratch
+// start; scr_off, act_off and Fmax are left to the caller).  Returns the
+// scratch size in complex elements; *fm receives the LDS transform size the
+// plan needs.
+int64_t schur_layout(const SchurPlan& P, sfls::SchurLayout& L, int* fm);
+
+// Factorisation the context uses for a batch whose largest N is maxN.
+bool use_schur(const sfls_ctx* ctx, int maxN);
+constexpr int kLevinsonMaxN = 4096;  // the Levinson kernel keeps vectors in registers
+// Grid sub-FFT size M = min(2^ceil(log2 N), cap), cap set by the grid's precision.
+void cap_grid_m(sfls::InstInfo& in, int precision);
+// Conversion of the public parameters into the driver's.
+sfls::DrvParams drv_params(const sfls_params& p);
+// Range checks of sfls_params.
+bool params_valid(const sfls_params& p);
+
+}  // namespace sfls_host

@@ -114,14 +114,16 @@ __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info
   }
 }
 
-// ||y||^2 per instance and the initial state (phase START).
+// ||y||^2 per instance and the initial state (phase START); with a list,
+// block i initialises instance list[i] only.
 template <typename YT>
 __global__ __launch_bounds__(256) void k_init_state(const InstInfo* __restrict__ info,
                                                     const YT* __restrict__ y,
                                                     DrvState* __restrict__ st,
-                                                    int32_t* __restrict__ req) {
+                                                    int32_t* __restrict__ req,
+                                                    const int32_t* __restrict__ list) {
   __shared__ double red[4];
-  const int b = blockIdx.x;
+  const int b = list ? list[blockIdx.x] : blockIdx.x;
   const InstInfo in = info[b];
   double acc[1] = {0.0};
   for (int i = threadIdx.x; i < in.N; i += 256) {
@@ -173,11 +175,81 @@ hipError_t launch_driver(const InstInfo* info, const DrvParams* prm, DrvPools po
 }
 
 hipError_t launch_init_state(const InstInfo* info, const void* y, int ydtype, DrvState* st,
-                             int32_t* req, int B, hipStream_t s) {
+                             int32_t* req, int B, hipStream_t s, const int32_t* list) {
+  if (B <= 0) return hipSuccess;
   if (ydtype == 1)
-    hipLaunchKernelGGL(k_init_state<cd>, dim3(B), dim3(256), 0, s, info, (const cd*)y, st, req);
+    hipLaunchKernelGGL(k_init_state<cd>, dim3(B), dim3(256), 0, s, info, (const cd*)y, st, req,
+                       list);
   else
-    hipLaunchKernelGGL(k_init_state<cf>, dim3(B), dim3(256), 0, s, info, (const cf*)y, st, req);
+    hipLaunchKernelGGL(k_init_state<cf>, dim3(B), dim3(256), 0, s, info, (const cf*)y, st, req,
+                       list);
+  return hipGetLastError();
+}
+
+// Every instance idle: phase DONE, no request (the state of a free slot).
+__global__ void k_slots_idle(DrvState* __restrict__ st, int32_t* __restrict__ req, int B) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+    DrvState s = {};
+    s.phase = PH_DONE;
+    s.done = 1;
+    st[b] = s;
+    req[b] = 0;
+  }
+}
+
+// Pack the outputs of the instances in list[0..n): record i and, from
+// comp[doff[i]], theta[K], gamma[K], then alpha as K interleaved pairs.
+__global__ __launch_bounds__(256) void k_gather_results(
+    const int32_t* __restrict__ list, const int64_t* __restrict__ doff, int n,
+    const int64_t* __restrict__ koff, const int64_t* __restrict__ oK,
+    const double* __restrict__ otheta, const cd* __restrict__ oalpha,
+    const double* __restrict__ ogamma, const double* __restrict__ obeta,
+    const double* __restrict__ ozeta, const double* __restrict__ oobj,
+    const int32_t* __restrict__ oiters, const int32_t* __restrict__ oevals,
+    const int32_t* __restrict__ ostatus, SlotResult* __restrict__ res,
+    double* __restrict__ comp) {
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const int b = list[i];
+  const int64_t K = oK[b];
+  if (threadIdx.x == 0) {
+    SlotResult r;
+    r.K = K;
+    r.beta = obeta[b];
+    r.zeta = ozeta[b];
+    r.obj = oobj[b];
+    r.iters = oiters[b];
+    r.evals = oevals[b];
+    r.status = ostatus[b];
+    r.slot = b;
+    res[i] = r;
+  }
+  double* dst = comp + doff[i];
+  const int64_t ko = koff[b];
+  for (int64_t k = threadIdx.x; k < K; k += blockDim.x) {
+    dst[k] = otheta[ko + k];
+    dst[K + k] = ogamma[ko + k];
+    const cd a = oalpha[ko + k];
+    dst[2 * K + 2 * k] = a.x;
+    dst[2 * K + 2 * k + 1] = a.y;
+  }
+}
+
+hipError_t launch_gather_results(const int32_t* list, const int64_t* doff, int n,
+                                 const int64_t* koff, const int64_t* oK, const double* otheta,
+                                 const cd* oalpha, const double* ogamma, const double* obeta,
+                                 const double* ozeta, const double* oobj, const int32_t* oiters,
+                                 const int32_t* oevals, const int32_t* ostatus, SlotResult* res,
+                                 double* comp, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_results, dim3(n), dim3(256), 0, s, list, doff, n, koff, oK, otheta,
+                     oalpha, ogamma, obeta, ozeta, oobj, oiters, oevals, ostatus, res, comp);
+  return hipGetLastError();
+}
+
+hipError_t launch_slots_idle(DrvState* st, int32_t* req, int B, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slots_idle, dim3((B + 255) / 256), dim3(256), 0, s, st, req, B);
   return hipGetLastError();
 }
 

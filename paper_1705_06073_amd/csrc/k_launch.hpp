@@ -107,7 +107,14 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
                          cd* ox, cd* cq, double* cs, int nblocks, int nmode, const cd* tws,
                          cd* scratch, int maxP, hipStream_t st);
 hipError_t launch_init_state(const InstInfo* info, const void* y, int ydtype, DrvState* st,
-                             int32_t* req, int B, hipStream_t s);
+                             int32_t* req, int B, hipStream_t s, const int32_t* list = nullptr);
+hipError_t launch_slots_idle(DrvState* st, int32_t* req, int B, hipStream_t s);
+hipError_t launch_gather_results(const int32_t* list, const int64_t* doff, int n,
+                                 const int64_t* koff, const int64_t* oK, const double* otheta,
+                                 const cd* oalpha, const double* ogamma, const double* obeta,
+                                 const double* ozeta, const double* oobj, const int32_t* oiters,
+                                 const int32_t* oevals, const int32_t* ostatus, SlotResult* res,
+                                 double* comp, hipStream_t s);
 hipError_t launch_driver(const InstInfo* info, const DrvParams* prm, DrvPools pools, int B,
                          hipStream_t st);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);

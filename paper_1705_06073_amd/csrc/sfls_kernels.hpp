@@ -77,4 +77,12 @@ struct SchurLayout {
   int32_t mmax[SCH_MAXL];
 };
 
+// Outputs of one finished instance, packed by k_gather_results for a single
+// device-to-host copy (components follow in a separate packed array).
+struct SlotResult {
+  int64_t K;
+  double beta, zeta, obj;
+  int32_t iters, evals, status, slot;
+};
+
 }  // namespace sfls

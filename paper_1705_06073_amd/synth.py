@@ -37,18 +37,35 @@ def wrap_distance(x, y):
     return np.minimum(a, 1.0 - a)
 
 
+def _wrap1(x: float, y: float) -> float:
+    a = abs(x - y) % 1.0
+    return min(a, 1.0 - a)
+
+
 def draw_frequencies(rng: np.random.Generator, K: int, sep: float,
                      max_tries: int = 10_000) -> np.ndarray:
-    """Sequential rejection sampling with minimum wrap-around separation."""
+    """Sequential rejection sampling with minimum wrap-around separation.
+
+    A candidate is compared with its two circular neighbours among the
+    accepted frequencies (kept sorted): with separations of at least `sep`,
+    every other accepted point is farther than these, so the decision is the
+    one of a test against all of them."""
+    import bisect
     while True:
         th: list[float] = []
+        srt: list[float] = []
         ok = True
         for _ in range(K):
             for _try in range(max_tries):
                 cand = rng.random()
-                if all(wrap_distance(cand, t) > sep for t in th):
-                    th.append(cand)
-                    break
+                if srt:
+                    j = bisect.bisect_left(srt, cand)
+                    near = (srt[j % len(srt)], srt[j - 1])
+                    if not all(_wrap1(cand, t) > sep for t in near):
+                        continue
+                th.append(cand)
+                bisect.insort(srt, cand)
+                break
             else:
                 ok = False
                 break
@@ -87,6 +104,23 @@ def clean_signal(theta: np.ndarray, alpha: np.ndarray, N: int) -> np.ndarray:
     return h
 
 
+def clean_signal_blocked(theta: np.ndarray, alpha: np.ndarray, N: int, blk: int = 256) -> np.ndarray:
+    """h = Psi(theta) alpha with e^{j2pi n theta} formed as the product of
+    e^{j2pi a blk theta} and e^{j2pi b theta} (n = a blk + b, both phases
+    reduced mod 1): equal to clean_signal up to the rounding of the phases
+    (about N times the unit roundoff), with N/blk + blk instead of N
+    exponentials per component, for long signals with many components."""
+    nb = -(-N // blk)
+    a = np.arange(nb, dtype=np.float64) * blk
+    b = np.arange(blk, dtype=np.float64)
+    h = np.zeros(nb * blk, dtype=np.complex128)
+    for th, al in zip(theta, alpha):
+        hi = np.exp(2j * math.pi * np.mod(a * th, 1.0))
+        lo = al * np.exp(2j * math.pi * np.mod(b * th, 1.0))
+        h += np.outer(hi, lo).ravel()
+    return h[:N]
+
+
 @dataclass
 class Instance:
     N: int
@@ -102,10 +136,10 @@ class Instance:
 
 def make_instance(rng: np.random.Generator, N: int, K: int, sep: float,
                   alpha_kind: str, snr_db: float, dtype=np.complex128,
-                  seed: int = 0) -> Instance:
+                  seed: int = 0, blocked: bool = False) -> Instance:
     theta = draw_frequencies(rng, K, sep) if K > 0 else np.zeros(0)
     alpha = draw_alpha(rng, K, alpha_kind) if K > 0 else np.zeros(0, np.complex128)
-    h = clean_signal(theta, alpha, N)
+    h = clean_signal_blocked(theta, alpha, N) if blocked else clean_signal(theta, alpha, N)
     if K > 0 and math.isfinite(snr_db):
         beta = float(np.vdot(h, h).real / (N * 10.0 ** (snr_db / 10.0)))
     elif K > 0:
@@ -155,6 +189,33 @@ def workload_uneven(instance: int) -> Instance:
     K = int(rng.poisson(N / 64.0))
     snr = float(rng.uniform(5.0, 30.0))
     return make_instance(rng, N, K, 1.0 / N, "cn", snr, np.complex128, s)
+
+
+SERVING_SIZES = (256, 1024, 4096, 16384, 65536)
+SERVING_WEIGHTS = (0.3, 0.3, 0.2, 0.15, 0.05)
+
+
+def workload_serving_signal(N: int, instance: int) -> Instance:
+    """A serving request of length N: K ~ Poisson(N/64), separation 1/N,
+    alpha ~ CN(0,1), SNR ~ U[5,30] dB, complex64."""
+    s = seed_for(4, instance) + 100_000 * int(math.log2(N))
+    rng = np.random.Generator(np.random.PCG64(s))
+    K = int(rng.poisson(N / 64.0))
+    snr = float(rng.uniform(5.0, 30.0))
+    return make_instance(rng, N, K, 1.0 / N, "cn", snr, np.complex64, s, blocked=True)
+
+
+def serving_stream(rate: float, duration: float, seed_instance: int = 0):
+    """Arrival times (s, ascending) of a Poisson process of `rate` requests/s
+    over `duration` seconds and each request's N drawn from SERVING_SIZES with
+    SERVING_WEIGHTS."""
+    rng = np.random.Generator(np.random.PCG64(seed_for(4, seed_instance)))
+    n_exp = int(rate * duration * 1.2 + 100)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_exp))
+    t = t[t < duration]
+    sizes = rng.choice(np.array(SERVING_SIZES, np.int64), size=len(t),
+                       p=np.array(SERVING_WEIGHTS))
+    return t, sizes
 
 
 def workload_paper_snr(instance: int, snr_db: float, N: int = 128, K: int = 10) -> Instance:

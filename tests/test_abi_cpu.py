@@ -61,3 +61,11 @@ def test_null_context_is_rejected_without_touching_the_device():
     assert L.sfls_factor(None, 1, n, o, None, None, None, None, None, None, None) == sf.SFLS_EINVAL
     assert L.sfls_estimate(None, 1, n, o, None, 1, None, n, o, *([None] * 11)) == sf.SFLS_EINVAL
     assert L.sfls_destroy(None) == sf.SFLS_OK
+
+
+def test_server_structs_match_the_header_layout():
+    # the library static_asserts the same sizes on its side
+    assert ctypes.sizeof(sf.sfls_server_config) == 40
+    assert ctypes.sizeof(sf.sfls_result) == 88
+    assert ctypes.sizeof(sf.sfls_server_stats) == 72
+    assert ctypes.sizeof(sf.sfls_params) == 136
