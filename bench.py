@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Throughput benchmark: estimation solves/sec at N=4096 on one MI355X.
 
-A step is one batch of 256 full solves (sfls_estimate: every evaluation, the
-Levinson factorisation, the grid stage and the device-side driver) of
-synthetic signals with N=4096, K~Poisson(40), minimum separation 1/N,
-alpha~CN(0,1), SNR~U[0,30] dB, grid L=8N=32768, FP64 recursion and FP32 grid
-FFTs.  Inputs are resident in HBM before timing starts.
+A step is one batch of 256 full solves (every evaluation: covariance column,
+superfast factorisation, grid stage, active-set vectors and the device-side
+driver) of synthetic signals with N=4096, K~Poisson(40), minimum separation
+1/N, alpha~CN(0,1), SNR~U[0,30] dB, grid L=8N=32768, FP64 recursion and FP32
+grid FFTs.  Inputs are resident in HBM before timing starts.
 
-Also reported: the plain FP64 method launched one instance at a time, p50/p99
-per-instance latency, the roofline position of the dominant kernel (from HIP
-events the library records on its stream), and the CPU oracle timed on a
-bounded sample of the same workload.
+`value`: the steps' batches stream through a server with 256 slots
+(continuous batching: a slot freed by a finished solve takes the next
+instance at the following round).  Also reported: the same batches by one
+sfls_estimate call per batch (batch_sync, which waits for each batch's
+slowest instance), the plain FP64 method launched one instance at a time,
+p50/p99 latency, the roofline position of the dominant kernel (from HIP events
+the library records on its stream), and the CPU oracle timed on a bounded
+sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -151,7 +155,7 @@ def serve_leg(rate, seconds, prec):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--plain", type=int, default=8,
@@ -233,17 +237,54 @@ def main():
                          out["objective"], out["iters"], out["evals"], out["status"],
                          stream=stream)
 
+    # --- continuous batching (the reported value): the steps' batches stream
+    # through a server with one slot per instance of a batch; a slot freed by
+    # a finished solve takes the next instance at the following round, so no
+    # round waits for the slowest instance of its batch.
+    srv = sf.Server(ctx, max_n=4096, max_slots=B, ydtype=sf.SFLS_C128, hbm_bytes=4 << 30,
+                    params=params, stream=stream)
+    yaddr = [y.data_ptr() + 16 * int(o) for o in off]
+
+    def run_stream(nsteps):
+        total = nsteps * B
+        nxt, got = 0, []
+        while len(got) < total:
+            while nxt < total and srv.submit(yaddr[nxt % B], int(n[nxt % B]), nxt):
+                nxt += 1
+            srv.step()
+            got += srv.poll()
+        return got
+
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        run_stream(1)
+        log(f"warmup {w + 1}/{args.warmup} (continuous): {time.perf_counter() - t:.3f} s")
+    ctx.reset_stats()
+    ctx.set_timing(True)
+    r0 = srv.stats()["rounds"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    served = run_stream(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    rounds_c = srv.stats()["rounds"] - r0
+    solves = args.steps * B
+    value = solves / elapsed
+    lat_c = np.array([r.t_done - r.t_submit for r in served])
+    log(f"continuous: {solves} solves in {elapsed:.3f} s over {rounds_c} rounds")
+    for r in served:
+        assert r.status in (sf.SFLS_OK, sf.SFLS_NOTCONV), r.status
+    srv.close()
+
+    # --- batch-synchronous sfls_estimate: one call per step of 256 instances
     for w in range(args.warmup):
         t = time.perf_counter()
         run_batch()
         torch.cuda.synchronize()
-        log(f"warmup {w + 1}/{args.warmup}: {time.perf_counter() - t:.3f} s")
-
-    ctx.reset_stats()
-    ctx.set_timing(True)
+        log(f"warmup {w + 1}/{args.warmup} (one call per batch): {time.perf_counter() - t:.3f} s")
     lat = []
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    tb0 = time.perf_counter()
     for s in range(args.steps):
         ts = time.perf_counter()
         run_batch()
@@ -254,7 +295,7 @@ def main():
         log(f"step {s + 1}/{args.steps}: {time.perf_counter() - ts:.3f} s, rounds={run['rounds']}, "
             f"evals={run['evals']} (grid {run['grid_evals']})")
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed_b = time.perf_counter() - tb0
     ctx.set_timing(False)
     kst = ctx.kernel_stats()
     run, _ = ctx.last_run()
@@ -262,8 +303,10 @@ def main():
     Kh = out["K"].cpu().numpy()
     its = out["iters"].cpu().numpy()
     evs = out["evals"].cpu().numpy()
-    solves = args.steps * B
-    value = solves / elapsed
+    value_b = solves / elapsed_b
+    # every step solves the same batch: each served solve of instance b has
+    # the model order the batch call found for b
+    same_K = int(sum(int(r.K == Kh[r.tag % B]) for r in served))
 
     # dominant kernel and its roofline position
     dom = max(kst.items(), key=lambda kv: kv[1]["seconds"])
@@ -289,7 +332,7 @@ def main():
                 "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
                 "avg_launch_ms": 1e3 * ks["seconds"] / max(1, ks["launches"]),
                 "algorithmic_per_launch": ks["bytes"] / max(1, ks["launches"])}
-    kernels = {k: {"launches": v["launches"], "ms_total": 1e3 * v["seconds"] / args.steps,
+    kernels = {k: {"launches": v["launches"], "ms_total": 1e3 * v["seconds"] / (2 * args.steps),
                    "share": v["seconds"] / max(1e-30, sum(x["seconds"] for x in kst.values()))}
                for k, v in kst.items()}
 
@@ -344,12 +387,20 @@ def main():
         "config": {"workload": "256 independent instances, N=4096, K~Poisson(40), separation "
                                "1/N, alpha~CN(0,1), SNR~U[0,30] dB, grid L=8N=32768; FP64 "
                                "recursion, " + ("FP32" if prec == sf.SFLS_MIXED else "FP64")
-                               + " grid; one batched estimate per step",
+                               + " grid; a step is one batch of 256 solves, the batches "
+                               "streaming through 256 slots by continuous batching",
                    "batch": B, "N": 4096, "L": 32768,
                    "precision": "mixed" if prec == sf.SFLS_MIXED else "fp64",
                    "factor": args.factor, "nufft": args.nufft},
-        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
-                       "p99": 1e3 * float(np.percentile(lat, 99))},
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat_c, 50)),
+                       "p99": 1e3 * float(np.percentile(lat_c, 99)),
+                       "definition": "admission to completion of each solve, continuous batching"},
+        "continuous": {"rounds": rounds_c, "slots": B, "solves": solves,
+                       "solves_with_K_of_the_batch_call": same_K},
+        "batch_sync": {"value": value_b, "unit": "solves/s", "ms_per_step": 1e3 * elapsed_b / args.steps,
+                       "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                                      "p99": 1e3 * float(np.percentile(lat, 99)),
+                                      "definition": "completion within its batch of 256"}},
         "plain_fp64": plain,
         "per_solve": {"evals_mean": run["evals"] / B, "grid_evals_mean": run["grid_evals"] / B,
                       "evals_p50": float(np.percentile(evs, 50)),

@@ -256,7 +256,8 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
  * Measurement of sfls_estimate (no effect on results).
  *
  * sfls_set_timing(ctx, 1) brackets every kernel launch of the estimate round
- * loop with HIP events on the call's stream; per kernel the context then
+ * loop (and of the rounds of servers created on the context) with HIP events
+ * on the stream the work runs on; per kernel the context then
  * accumulates the launch count, the summed event durations, and the
  * algorithmic work of those launches (FP64 flops of the factorisation: 8 N^2
  * per instance for Levinson, the count of the superfast recursion's leaf

@@ -90,6 +90,7 @@ struct PlanEntry {
   SchurLayout lay{};
   int64_t scratch = 0;  // complex elements
   int fm = 0;
+  double flops = 0.0;   // algorithmic FP64 flops of one factorisation
 };
 
 struct Result {
@@ -156,6 +157,12 @@ struct sfls_server {
   bool in_flight = false;
   std::chrono::steady_clock::time_point t0, t_launch;
   sfls_server_stats stats{};
+  // per-kernel HIP events of the round in flight (when the context times)
+  hipEvent_t tev[2 * KID_COUNT] = {};
+  bool tlaunched[KID_COUNT] = {};
+  double tflops[KID_COUNT] = {}, tbytes[KID_COUNT] = {};
+  bool timed = false;
+  std::vector<double> slot_flops;  // factorisation flops of each slot's request
 
   // device pools (offset-indexed)
   void* ypool = nullptr;
@@ -224,6 +231,7 @@ sfls_status plan_for(sfls_server* s, int64_t n, const PlanEntry** out) {
   SchurPlan P = schur_plan(n);
   PlanEntry e;
   e.scratch = schur_layout(P, e.lay, &e.fm);
+  e.flops = schur_flops(P);
   if (e.fm > s->Fmax) return fail(ctx, SFLS_EUNSUPPORTED, "recursion plan of n = %lld needs a larger transform", (long long)n);
   const size_t na = std::max<size_t>(P.acts.size(), 1);
   if (s->acts_n + na > s->acts_cap) {
@@ -313,6 +321,8 @@ sfls_status sfls_server_destroy(sfls_server* s) {
   for (void* p : s->dev_owned) (void)hipFree(p);
   for (void* p : s->host_owned) (void)hipHostFree(p);
   if (s->ev) (void)hipEventDestroy(s->ev);
+  for (auto& e : s->tev)
+    if (e) (void)hipEventDestroy(e);
   if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
   delete s;
   return SFLS_OK;
@@ -404,6 +414,7 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
   s->units = units;
   s->buddy.init(order_of(units / kUnitMin));
   s->slots.assign((size_t)S, Slot{});
+  s->slot_flops.assign((size_t)S, 0.0);
   for (int i = 0; i < S; ++i) s->free_slots.insert(i);
 
   // streams and events (default priority)
@@ -550,6 +561,7 @@ sfls_status sfls_server_submit(sfls_server* s, const void* y, int64_t n, uint64_
   sep_coef((int)n, s->h_coef[slot]);
   s->h_lay[slot] = lay;
   s->h_koff[slot] = in.koff;
+  s->slot_flops[(size_t)slot] = pe ? pe->flops : 8.0 * (double)n * (double)n;
   hipError_t e = hipSuccess;
   const hipStream_t up = s->up;
   if (e == hipSuccess) e = hipMemcpyAsync(s->dinfo + slot, s->h_info + slot, sizeof(InstInfo), hipMemcpyHostToDevice, up);
@@ -619,39 +631,92 @@ sfls_status sfls_server_launch(sfls_server* s) {
   }
   DrvPools& P = s->P;
   const int prec = s->prm.precision;
+  // per-kernel events and algorithmic work when the context times
+  s->timed = ctx->timing;
+  if (s->timed && !s->tev[0]) {
+    for (auto& e : s->tev) HIP_TRY(hipEventCreate(&e));
+  }
+  for (int k = 0; k < KID_COUNT; ++k) {
+    s->tlaunched[k] = false;
+    s->tflops[k] = 0.0;
+    s->tbytes[k] = 0.0;
+  }
+  if (s->timed) {
+    const double esz = (double)s->esz, ysz = (double)s->ysz;
+    for (int b = 0; b < B; ++b) {
+      const int32_t rq = s->h_req[b];
+      if (!rq || s->slots[(size_t)b].state != SLOT_RUNNING) continue;
+      const InstInfo& in = s->h_info[b];
+      const double N = (double)in.N;
+      if (rq & REQ_EVAL) {
+        s->tflops[KID_FACTOR] += s->slot_flops[(size_t)b];
+        s->tbytes[KID_FACTOR] += 40.0 * N;
+        if (s->schur) s->tflops[KID_REFINE] += 10.0 * 5.0 * in.P * in.logP + 96.0 * in.P;
+        s->tbytes[KID_APPLY] += ysz * N + 32.0 * N;
+      }
+      if (rq & REQ_GRID) s->tbytes[KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz * in.L;
+    }
+  }
+  auto tstart = [&](int k) -> hipError_t {
+    s->tlaunched[k] = true;
+    return s->timed ? hipEventRecord(s->tev[2 * k], st) : hipSuccess;
+  };
+  auto tstop = [&](int k) -> hipError_t {
+    return s->timed ? hipEventRecord(s->tev[2 * k + 1], st) : hipSuccess;
+  };
   if (any_eval) {
+    HIP_TRY(tstart(KID_GEN));
     HIP_TRY(launch_toeplitz_column(s->dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, s->c, B, maxN, st));
+    HIP_TRY(tstop(KID_GEN));
+    HIP_TRY(tstart(KID_FACTOR));
     if (s->schur) {
       HIP_TRY(launch_schur(s->dinfo, P.req, s->dlay, s->dacts, s->c, ctx->tw64, ctx->logtw,
                            ctx->tws64, s->sscr, s->rho, s->delta, s->logdet, s->lev_status,
                            s->failed, B, s->Fmax, st));
-      HIP_TRY(launch_gen_refine(s->dinfo, P.req, s->lev_status, s->c, s->rho, s->delta, ctx->tw64,
-                                ctx->logtw, ctx->tws64, s->scratch, s->rf_r, s->rf_dx, B, maxP, st));
     } else {
       HIP_TRY(launch_levinson(s->dinfo, P.req, s->c, s->rho, s->delta, s->logdet, s->lev_status,
                               s->failed, B, (int)s->cfg.max_n, st));
     }
+    HIP_TRY(tstop(KID_FACTOR));
+    HIP_TRY(tstart(KID_REFINE));
+    if (s->schur)
+      HIP_TRY(launch_gen_refine(s->dinfo, P.req, s->lev_status, s->c, s->rho, s->delta, ctx->tw64,
+                                ctx->logtw, ctx->tws64, s->scratch, s->rf_r, s->rf_dx, B, maxP, st));
     HIP_TRY(launch_logdet_lemma(s->dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, s->lev_status,
                                 s->logdet, B, st));
+    HIP_TRY(tstop(KID_REFINE));
+    HIP_TRY(tstart(KID_APPLY));
     HIP_TRY(launch_gs_apply(s->dinfo, P.req, s->ypool, s->cfg.ydtype, s->rho, s->delta, ctx->tw64,
                             ctx->logtw, ctx->tws64, s->scratch, s->w, s->yCy, s->ww, B, maxP, st));
+    HIP_TRY(tstop(KID_APPLY));
   }
   if (any_grid) {
     const void* tw = prec == SFLS_FP64 ? (const void*)ctx->tws64 : (const void*)ctx->tws32;
     const double slack = prec == SFLS_FP64 ? 1e-9 : 1e-3;
+    HIP_TRY(tstart(KID_OMEGA));
     HIP_TRY(launch_omega(s->dinfo, P.req, s->rho, s->delta, s->dcoef, ctx->tws64, s->scratch, 1, 1,
                          s->oms, nullptr, nullptr, nullptr, nullptr, B, maxP, st));
+    HIP_TRY(tstop(KID_OMEGA));
+    HIP_TRY(tstart(KID_GRID));
     HIP_TRY(launch_grid(prec, s->dinfo, P.req, s->w, s->oms, P.gbar_e, P.zeta_e, tw, ctx->logtw, Rr,
                         B, maxM, nullptr, nullptr, s->dL, s->pv, s->pi, st));
+    HIP_TRY(tstop(KID_GRID));
+    HIP_TRY(tstart(KID_SELECT));
     HIP_TRY(launch_select(prec, s->dinfo, P.req, s->dL, Rr, s->pv, s->pi, s->prm.approx_ratio,
                           slack, s->prm.cand_cap, s->cand, s->ncand, s->ovf, B, st));
+    HIP_TRY(tstop(KID_SELECT));
   }
-  if (any_req)
+  if (any_req) {
+    HIP_TRY(tstart(KID_ACTIVE));
     HIP_TRY(launch_active(s->dinfo, P.req, P.K_e, any_grid ? s->ncand : nullptr, s->prefix, B,
                           P.th_e, s->cand, s->w, s->rho, s->delta, s->dcoef, s->evq, s->evr,
                           s->evu, s->evs, s->evt, s->evv, s->evx, s->cq, s->cs, 2048,
                           ctx->nufft_mode, ctx->tws64, s->scratch, maxP, st));
+    HIP_TRY(tstop(KID_ACTIVE));
+  }
+  HIP_TRY(tstart(KID_DRIVER));
   HIP_TRY(launch_driver(s->dinfo, s->dprm, P, B, st));
+  HIP_TRY(tstop(KID_DRIVER));
   HIP_TRY(hipMemcpyAsync(s->h_req, P.req, (size_t)B * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipEventRecord(s->ev, st));
   s->in_flight = true;
@@ -678,6 +743,17 @@ sfls_status sfls_server_wait(sfls_server* s, int32_t block, int32_t* ready, int3
   }
   s->in_flight = false;
   s->stats.rounds += 1;
+  if (s->timed) {
+    for (int k = 0; k < KID_COUNT; ++k) {
+      if (!s->tlaunched[k]) continue;
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, s->tev[2 * k], s->tev[2 * k + 1]));
+      ctx->kst[k].launches += 1;
+      ctx->kst[k].seconds += 1e-3 * (double)ms;
+      ctx->kst[k].flops += s->tflops[k];
+      ctx->kst[k].bytes += s->tbytes[k];
+    }
+  }
   s->stats.gpu_seconds +=
       std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t_launch).count();
   const double t_done = s->now();

@@ -23,7 +23,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 # sources whose change invalidates a measured figure, per kernel
 KERNEL_SOURCES = {
     "k_schur": ["csrc/k_schur.hip", "csrc/dev_common.hpp", "csrc/sfls_kernels.hpp",
-                "csrc/abi.hip"],
+                "csrc/abi.hip", "csrc/server.hip", "csrc/host_internal.hpp"],
 }
 
 
