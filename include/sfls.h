@@ -153,15 +153,21 @@ typedef enum { SFLS_FACTOR_AUTO = 0, SFLS_FACTOR_LEVINSON = 1, SFLS_FACTOR_SCHUR
 sfls_status sfls_set_factor(sfls_ctx* ctx, int32_t algo);
 
 /* ---------------------------------------------------------------------------
- * a8. How sfls_active_eval and sfls_estimate evaluate the Fourier sums at
- * off-grid frequencies (Sec. III-B and III-C evaluate them with the
- * non-uniform FFT): direct O(N) sums per frequency, or Gaussian gridding
- * (Greengard and Lee) on an oversampled grid of P = 2^ceil(log2(2N-1)) points
- * with 32 grid points per frequency, whose relative error is below 1e-13.
- *   SFLS_NUFFT_AUTO  per instance: NUFFT when N >= 512 and
- *                    (frequencies) x N >= 2^23 (default)
+ * a1, a8. How the products with Psi(theta) at off-grid frequencies are
+ * evaluated (Sec. III-B and III-C use the non-uniform FFT): direct O(N) sums
+ * per frequency, or Gaussian gridding (Greengard and Lee) on an oversampled
+ * grid of P = 2^ceil(log2(2N-1)) points with 32 grid points per frequency,
+ * whose relative error is below 1e-13 (measured 1e-15 .. 2e-14).
+ *   a8 (sfls_active_eval, sfls_estimate): the type-2 transform at the active
+ *   frequencies and grid candidates;
+ *   a1 (sfls_toeplitz_column, sfls_estimate, servers): the type-1 transform
+ *   for the covariance column, for instances with P > 8192 (N > 4096) and at
+ *   most 2048 frequencies (direct sums otherwise).
+ *   SFLS_NUFFT_AUTO  per instance: a8 when N >= 512 and (frequencies) x N
+ *                    >= 2^23; a1 when K x N >= 2^21 (default)
  *   SFLS_NUFFT_OFF   direct sums everywhere
- *   SFLS_NUFFT_ON    NUFFT for every instance with at most 3P/4 frequencies
+ *   SFLS_NUFFT_ON    NUFFT for every instance within the sizes above (a8:
+ *                    at most 3P/4 frequencies)
  * The choice depends only on the instance, so a result does not depend on
  * the batch around it.  Unknown modes: SFLS_EINVAL.
  * ------------------------------------------------------------------------- */

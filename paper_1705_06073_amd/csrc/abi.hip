@@ -565,7 +565,10 @@ sfls_status sfls_toeplitz_column(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   int32_t* dK;
   if ((s = upload(ctx, "tc_info", info, st, &dinfo)) != SFLS_OK) return s;
   if ((s = upload(ctx, "tc_K", kc, st, &dK)) != SFLS_OK) return s;
-  HIP_TRY(launch_toeplitz_column(dinfo, nullptr, dK, theta, gamma, beta, (cd*)c, (int)B, sz.maxN, st));
+  cd* tscr = nullptr;
+  if (sz.maxP > CONV_LDS_P && (s = wsT(ctx, "tc_scr", (size_t)pt, &tscr)) != SFLS_OK) return s;
+  HIP_TRY(launch_toeplitz_column(dinfo, nullptr, dK, theta, gamma, beta, (cd*)c, (int)B, sz.maxN,
+                                 st, ctx->nufft_mode, ctx->tws64, tscr, sz.maxP));
   return SFLS_OK;
 }
 
@@ -990,7 +993,8 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
     if (nact > 0) {
       HIP_TRY(tstart(KID_GEN));
       HIP_TRY(launch_toeplitz_column(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, c, (int)B,
-                                     sz.maxN, st));
+                                     sz.maxN, st, ctx->nufft_mode, ctx->tws64, scratch,
+                                     sz.maxP));
       HIP_TRY(tstop(KID_GEN));
       HIP_TRY(tstart(KID_FACTOR));
       if ((s = run_recursion(ctx, B, dinfo, P.req, c, rho, delta, logdet, lev_status, failed,

@@ -16,13 +16,14 @@ __global__ __launch_bounds__(256) void k_toeplitz_column(const InstInfo* __restr
                                                          const double* __restrict__ theta,
                                                          const double* __restrict__ gamma,
                                                          const double* __restrict__ beta,
-                                                         cd* __restrict__ c) {
+                                                         cd* __restrict__ c, int nmode) {
   const int b = blockIdx.y;
   if (req && !(req[b] & REQ_EVAL)) return;
   const InstInfo in = info[b];
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (blockIdx.x * 256 >= in.N) return;
   const int K = Kcnt[b];
+  if (use_nufft_col(nmode, in.N, in.P, K)) return;  // k_toeplitz_nufft writes it
   __shared__ double sth[256], sga[256];
   cd acc{0.0, 0.0};
   const double di = (double)i;
@@ -43,6 +44,131 @@ __global__ __launch_bounds__(256) void k_toeplitz_column(const InstInfo* __restr
   if (i < in.N) {
     if (i == 0) { acc.x += beta[b]; acc.y = 0.0; }
     c[in.off + i] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a1 by the type-1 non-uniform FFT (Gaussian gridding, Greengard and Lee; the
+// paper evaluates products with Psi by NUFFT, Sec. III-B).  With centred
+// modes m = i - h (h = N/2), gamma'_k = gamma_k e^{j 2 pi h theta_k} and the
+// Gaussian g(x) = exp(-x^2 / (4 tau)), whose transform is
+// sqrt(4 pi tau) exp(-m^2 tau),
+//   c_{m+h} - beta [m+h = 0] = sum_k gamma'_k e^{j m omega_k}
+//     ~ e^{m^2 tau} / sqrt(4 pi tau) (2 pi / P) sum_l H_l e^{+j 2 pi m l / P},
+//   H_l = sum_k gamma'_k g(2 pi l / P - omega_k)   (periodic, 2 NU_MSP points),
+// on the oversampled grid of P >= 2N points with the tau of the type-2 form.
+// The spreading is a gather: the frequencies' grid positions are sorted in
+// LDS (a frequency within NU_MSP points of either end also enters shifted by
+// P), so each grid point adds its neighbours in a fixed order and the column
+// does not depend on scheduling.  One workgroup per instance; the transform
+// runs in the instance's scratch buffer after its four P blocks (P >
+// CONV_LDS_P), which an evaluation round has not yet used when this runs.
+// ---------------------------------------------------------------------------
+constexpr int NUC_NT = 512;
+
+__device__ __forceinline__ int lower_bound_i64(const int64_t* a, int n, int64_t v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(NUC_NT) void k_toeplitz_nufft(const InstInfo* __restrict__ info,
+                                                           const int32_t* __restrict__ req,
+                                                           const int32_t* __restrict__ Kcnt,
+                                                           const double* __restrict__ theta,
+                                                           const double* __restrict__ gamma,
+                                                           const double* __restrict__ beta,
+                                                           const cd* __restrict__ tws,
+                                                           cd* __restrict__ scratch,
+                                                           cd* __restrict__ c, int nmode) {
+  const int b = blockIdx.x;
+  if (req && !(req[b] & REQ_EVAL)) return;
+  const InstInfo in = info[b];
+  const int K = Kcnt[b];
+  const int N = in.N, P = in.P, logP = in.logP;
+  if (!use_nufft_col(nmode, N, P, K)) return;
+  extern __shared__ int64_t nuc_sh[];
+  int64_t* s_key = nuc_sh;                                        // [2 NUC_KMAX]
+  double* s_d = reinterpret_cast<double*>(nuc_sh + 2 * NUC_KMAX);  // [NUC_KMAX]
+  cd* s_g = reinterpret_cast<cd*>(s_d + NUC_KMAX);                 // [NUC_KMAX]
+  __shared__ cd s_tw[FFT_TWL];
+  const int tid = threadIdx.x;
+  const double TWO_PI = 6.283185307179586476925286766559;
+  const double R = (double)P / (double)N;
+  const double tau = 3.14159265358979323846 * NU_MSP / ((double)N * (double)N * R * (R - 0.5));
+  const double ag = (TWO_PI / P) * (TWO_PI / P) / (4.0 * tau);
+  const double sq = sqrt(4.0 * 3.14159265358979323846 * tau);
+  const int h = N / 2;
+  load_tw_head<NUC_NT>(s_tw, tws);
+  // grid positions: key = (floor(theta P) + P [+- P]) << 32 | k, unique per entry
+  int E = 2;
+  while (E < 2 * K) E <<= 1;
+  for (int k = tid; k < K; k += NUC_NT) {
+    const double th = theta[in.koff + k];
+    const double sP = th * (double)P;  // exact: P is a power of two
+    const double fl = floor(sP);
+    int l0 = (int)fl;
+    const double d = sP - fl;          // exact
+    l0 = l0 < 0 ? 0 : (l0 > P - 1 ? P - 1 : l0);
+    s_d[k] = d;
+    s_g[k] = cscale(cis2pi(frac_mul((double)h, th)), gamma[in.koff + k]);
+    s_key[2 * k] = ((int64_t)(l0 + P) << 32) | (int64_t)k;
+    int64_t dup = INT64_MAX;
+    if (l0 < NU_MSP) dup = ((int64_t)(l0 + 2 * P) << 32) | (int64_t)k;
+    else if (l0 >= P - NU_MSP) dup = ((int64_t)l0 << 32) | (int64_t)k;
+    s_key[2 * k + 1] = dup;
+  }
+  for (int i = 2 * K + tid; i < E; i += NUC_NT) s_key[i] = INT64_MAX;
+  __syncthreads();
+  // bitonic sort, ascending
+  for (int kk = 2; kk <= E; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < E; i += NUC_NT) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int64_t a = s_key[i], bb = s_key[ixj];
+          const bool up = (i & kk) == 0;
+          if ((a > bb) == up) {
+            s_key[i] = bb;
+            s_key[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // spreading by gather, one grid point per thread and tile
+  cd* buf = scratch + in.poff + 4 * (int64_t)P;
+  for (int l0 = 0; l0 < P; l0 += NUC_NT) {
+    const int l = l0 + tid;
+    const int lo = lower_bound_i64(s_key, E, (int64_t)(l0 - NU_MSP + P) << 32);
+    const int hi = lower_bound_i64(s_key, E, (int64_t)(l0 + NUC_NT + NU_MSP - 1 + P) << 32);
+    cd acc{0.0, 0.0};
+    for (int j = lo; j < hi; ++j) {
+      const int64_t key = s_key[j];
+      const int t = l - ((int)(key >> 32) - P);
+      if (t >= -(NU_MSP - 1) && t <= NU_MSP) {
+        const int k = (int)(key & 0xffffffff);
+        const double x = (double)t - s_d[k];
+        const double g = exp(-ag * x * x);
+        acc.x = fma(g, s_g[k].x, acc.x);
+        acc.y = fma(g, s_g[k].y, acc.y);
+      }
+    }
+    buf[pidx(l)] = acc;
+  }
+  __syncthreads();
+  dif_fftn<NUC_NT>(buf, buf, 1, logP, true, false, s_tw, tws);  // kernel e^{+j}, bit-reversed out
+  const double sc = TWO_PI / (double)P / sq;
+  for (int i = tid; i < N; i += NUC_NT) {
+    const int m = i - h;
+    const cd X = buf[pidx(bitrev(m & (P - 1), logP))];
+    cd v = cscale(X, exp((double)m * (double)m * tau) * sc);
+    if (i == 0) { v.x += beta[b]; v.y = 0.0; }
+    c[in.off + i] = v;
   }
 }
 
@@ -192,10 +318,19 @@ __global__ __launch_bounds__(T) void k_levinson(const InstInfo* __restrict__ inf
 // from the largest N of the batch.
 hipError_t launch_toeplitz_column(const InstInfo* info, const int32_t* req, const int32_t* Kcnt,
                                   const double* theta, const double* gamma, const double* beta,
-                                  cd* c, int B, int maxN, hipStream_t st) {
+                                  cd* c, int B, int maxN, hipStream_t st, int nmode,
+                                  const cd* tws, cd* scratch, int maxP) {
+  if (!scratch || !tws || maxP <= CONV_LDS_P) nmode = 1;  // no room for the transform: direct
   dim3 grid((maxN + 255) / 256, B);
   hipLaunchKernelGGL(k_toeplitz_column, grid, dim3(256), 0, st, info, req, Kcnt, theta, gamma,
-                     beta, c);
+                     beta, c, nmode);
+  if (nmode != 1) {
+    const size_t shm = (size_t)NUC_KMAX * (2 * sizeof(int64_t) + sizeof(double) + sizeof(cd));
+    (void)hipFuncSetAttribute((const void*)k_toeplitz_nufft,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_toeplitz_nufft, dim3(B), dim3(NUC_NT), shm, st, info, req, Kcnt, theta,
+                       gamma, beta, tws, scratch, c, nmode);
+  }
   return hipGetLastError();
 }
 

@@ -61,9 +61,12 @@ struct DrvPools {
 };
 
 hipError_t launch_twiddles(cd* tw64, cf* tw32, cd* tws64, cf* tws32, int logtw, hipStream_t st);
+// a1, direct sums and (per instance, by use_nufft_col) the type-1 NUFFT in
+// the instance's scratch (4 P + padded(P) complex elements at poff).
 hipError_t launch_toeplitz_column(const InstInfo* info, const int32_t* req, const int32_t* Kcnt,
                                   const double* theta, const double* gamma, const double* beta,
-                                  cd* c, int B, int maxN, hipStream_t st);
+                                  cd* c, int B, int maxN, hipStream_t st, int nmode = 1,
+                                  const cd* tws = nullptr, cd* scratch = nullptr, int maxP = 0);
 hipError_t launch_levinson(const InstInfo* info, const int32_t* req, const cd* c, cd* rho,
                            double* delta, double* logdet, int32_t* status, int64_t* failed, int B,
                            int maxN, hipStream_t st);

@@ -666,7 +666,8 @@ sfls_status sfls_server_launch(sfls_server* s) {
   };
   if (any_eval) {
     HIP_TRY(tstart(KID_GEN));
-    HIP_TRY(launch_toeplitz_column(s->dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, s->c, B, maxN, st));
+    HIP_TRY(launch_toeplitz_column(s->dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, s->c, B, maxN,
+                                   st, ctx->nufft_mode, ctx->tws64, s->scratch, maxP));
     HIP_TRY(tstop(KID_GEN));
     HIP_TRY(tstart(KID_FACTOR));
     if (s->schur) {

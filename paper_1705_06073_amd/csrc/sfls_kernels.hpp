@@ -39,6 +39,17 @@ constexpr int GRID_LOGM_F64 = 12;
 // which the automatic choice prefers it to the direct sums.
 constexpr int NU_MSP = 16;
 constexpr double NU_MIN_WORK = 8388608.0;
+// The covariance column (a1) by the type-1 NUFFT: at most this many
+// frequencies (their sort keys stay in LDS), only where the P-point transform
+// lives in the instance's scratch (P > CONV_LDS_P), and in the automatic mode
+// from K N >= NUC_MIN_WORK.
+constexpr int NUC_KMAX = 2048;
+constexpr double NUC_MIN_WORK = 2097152.0;
+__host__ __device__ inline bool use_nufft_col(int mode, int N, int P, int K) {
+  if (mode == 1 || K <= 0 || K > NUC_KMAX || P <= CONV_LDS_P) return false;
+  if (mode == 2) return true;
+  return (double)K * (double)N >= NUC_MIN_WORK;
+}
 
 // Request bits of one instance for the current evaluation round.
 enum : int32_t { REQ_EVAL = 1, REQ_GRID = 2, REQ_APPROX = 4 };

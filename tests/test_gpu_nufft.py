@@ -151,3 +151,60 @@ def test_estimate_with_nufft(ctx):
         print(f"   N={inst.N} K={r.K} (true {inst.K}) ev={r.evaluations} objective rel {ef:.2e} "
               f"alpha err/tol {ea:.2e}", flush=True)
         assert ef <= 1e-8 and ea <= 1.0
+
+
+def column(ctx, ns, sts, mode):
+    n, off = ragged(ns)
+    K = np.array([len(s[0]) for s in sts], np.int64)
+    koff = np.concatenate([[0], np.cumsum(K)[:-1]]).astype(np.int64)
+    th = f64d(np.concatenate([s[0] for s in sts] + [np.zeros(1)]))
+    ga = f64d(np.concatenate([s[1] for s in sts] + [np.zeros(1)]))
+    be = f64d([s[2] for s in sts])
+    c = zeros_c(n.sum())
+    ctx.set_nufft(mode)
+    try:
+        sf.sfls_toeplitz_column(ctx, n, off, K, koff, th, ga, be, c)
+        torch.cuda.synchronize()
+        t0 = __import__("time").perf_counter()
+        for _ in range(3):
+            sf.sfls_toeplitz_column(ctx, n, off, K, koff, th, ga, be, c)
+        torch.cuda.synchronize()
+        dt = (__import__("time").perf_counter() - t0) / 3
+    finally:
+        ctx.set_nufft(sf.SFLS_NUFFT_ON)
+    return off, d2c(c), dt
+
+
+@pytest.mark.parametrize("N,K", [(8192, 1), (8192, 700), (16384, 256), (65536, 1024),
+                                 (20000, 2048)])
+def test_nufft_covariance_column(ctx, N, K):
+    """a1 by the type-1 NUFFT against the oracle's column (sum of K terms in
+    FP64 with exact phase reduction) and against the direct GPU sums; some
+    frequencies sit within a few grid points of 0 and 1 so the spreading
+    wraps around."""
+    rng = np.random.default_rng(N + K)
+    th = rng.random(K)
+    th[: min(K, 3)] = [1e-7, 0.999999, 0.5 / (2 * N)][: min(K, 3)]
+    ga = 0.1 + rng.random(K)
+    be = 0.3
+    sts = [(th, ga, be)]
+    off, cn, tn = column(ctx, [N], sts, sf.SFLS_NUFFT_ON)
+    _, cd_, td = column(ctx, [N], sts, sf.SFLS_NUFFT_OFF)
+    ref = nm.toeplitz_column(th, ga, be, N)
+    e_ref, e_dir = relerr(cn, ref), relerr(cn, cd_)
+    print(f"[column] N={N} K={K}: nufft {tn * 1e3:.3f} ms, direct {td * 1e3:.3f} ms; "
+          f"rel. err vs oracle {e_ref:.2e}, vs direct {e_dir:.2e}", flush=True)
+    assert e_ref < NUFFT_TOL and e_dir < NUFFT_TOL
+    assert cn[0].imag == 0.0
+
+
+def test_nufft_column_falls_back_beyond_its_sizes(ctx):
+    """More than 2048 frequencies, or a transform that fits LDS (N <= 4096):
+    the direct sums write the column, bit for bit as with the NUFFT off."""
+    rng = np.random.default_rng(7)
+    sts = [(rng.random(2100), 0.1 + rng.random(2100), 0.2),
+           (rng.random(500), 0.1 + rng.random(500), 0.2)]
+    ns = [8192, 4096]
+    _, cn, _ = column(ctx, ns, sts, sf.SFLS_NUFFT_ON)
+    _, cd_, _ = column(ctx, ns, sts, sf.SFLS_NUFFT_OFF)
+    np.testing.assert_array_equal(cn, cd_)
