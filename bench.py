@@ -169,6 +169,10 @@ def main():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--factor", choices=["auto", "levinson", "schur"], default="auto",
                     help="generator recursion (auto: superfast Schur from N=256 on)")
+    ap.add_argument("--slots", type=int, default=256,
+                    help="server slots of the continuous-batching leg (instances on the device)")
+    ap.add_argument("--schur-lds", type=int, default=4096,
+                    help="largest superfast-recursion transform kept in LDS (256..4096)")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
                     help="also run the serving stream for this many seconds of arrivals "
                          "(60 for the full stream)")
@@ -229,6 +233,7 @@ def main():
                     "schur": sf.SFLS_FACTOR_SCHUR}[args.factor])
     ctx.set_nufft({"auto": sf.SFLS_NUFFT_AUTO, "off": sf.SFLS_NUFFT_OFF,
                    "on": sf.SFLS_NUFFT_ON}[args.nufft])
+    ctx.set_schur_lds(args.schur_lds)
     stream = torch.cuda.current_stream()
 
     def run_batch():
@@ -241,8 +246,8 @@ def main():
     # through a server with one slot per instance of a batch; a slot freed by
     # a finished solve takes the next instance at the following round, so no
     # round waits for the slowest instance of its batch.
-    srv = sf.Server(ctx, max_n=4096, max_slots=B, ydtype=sf.SFLS_C128, hbm_bytes=4 << 30,
-                    params=params, stream=stream)
+    srv = sf.Server(ctx, max_n=4096, max_slots=args.slots, ydtype=sf.SFLS_C128,
+                    hbm_bytes=(4 << 30) * max(1, args.slots // 256), params=params, stream=stream)
     yaddr = [y.data_ptr() + 16 * int(o) for o in off]
 
     def run_stream(nsteps):
@@ -395,7 +400,8 @@ def main():
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat_c, 50)),
                        "p99": 1e3 * float(np.percentile(lat_c, 99)),
                        "definition": "admission to completion of each solve, continuous batching"},
-        "continuous": {"rounds": rounds_c, "slots": B, "solves": solves,
+        "continuous": {"rounds": rounds_c, "slots": args.slots, "solves": solves,
+                       "schur_lds_transform": args.schur_lds,
                        "solves_with_K_of_the_batch_call": same_K},
         "batch_sync": {"value": value_b, "unit": "solves/s", "ms_per_step": 1e3 * elapsed_b / args.steps,
                        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),

@@ -152,6 +152,15 @@ sfls_status sfls_factor(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_
 typedef enum { SFLS_FACTOR_AUTO = 0, SFLS_FACTOR_LEVINSON = 1, SFLS_FACTOR_SCHUR = 2 } sfls_factor_algo;
 sfls_status sfls_set_factor(sfls_ctx* ctx, int32_t algo);
 
+/* a3. Largest transform of the superfast recursion's merges kept in LDS
+ * (a power of two in 256..4096, default 4096); larger merges run the same
+ * passes on the instance's device scratch.  A lower limit shrinks the
+ * recursion kernel's LDS so that several instances share a CU; it changes the
+ * rounding of the merges it moves (not their arithmetic).  Applies to
+ * sfls_factor and sfls_estimate calls, and to servers created afterwards.
+ * SFLS_EINVAL outside the range. */
+sfls_status sfls_set_schur_lds(sfls_ctx* ctx, int32_t max_f);
+
 /* ---------------------------------------------------------------------------
  * a1, a8. How the products with Psi(theta) at off-grid frequencies are
  * evaluated (Sec. III-B and III-C use the non-uniform FFT): direct O(N) sums

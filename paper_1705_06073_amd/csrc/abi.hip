@@ -221,7 +221,7 @@ SchurPlan schur_plan(int64_t N) {
   return P;
 }
 
-int64_t schur_layout(const SchurPlan& P, SchurLayout& L, int* fm_out) {
+int64_t schur_layout(const SchurPlan& P, SchurLayout& L, int* fm_out, int lds_f) {
   std::memset(&L, 0, sizeof L);
   L.nact = (int32_t)P.acts.size();
   int64_t o = 0;
@@ -234,13 +234,14 @@ int64_t schur_layout(const SchurPlan& P, SchurLayout& L, int* fm_out) {
     o += 8 * (int64_t)P.mmax[l];
     L.spec[l] = o;
     o += 2 * (int64_t)P.fspec[l];
-    if (P.fspec[l] > SCH_LDS_F) fbig = std::max(fbig, P.fspec[l]);
+    if (P.fspec[l] > lds_f) fbig = std::max(fbig, P.fspec[l]);
     else fm = std::max(fm, P.fspec[l]);
     if (P.mmax[l] <= SCH_DIRECT) fm = std::max(fm, 8 * P.mmax[l] + 256);
   }
   L.xbig = o;
   if (fbig) o += 2 * (int64_t)padded(fbig);
   L.Fmax = fm;
+  L.ldsF = lds_f;
   *fm_out = fm;
   return o;
 }
@@ -250,7 +251,7 @@ int64_t schur_layout(const SchurPlan& P, SchurLayout& L, int* fm_out) {
 // flops of each instance.
 void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
                  std::vector<SchurAct>& pool, int64_t& scr_total, int& Fmax,
-                 std::vector<double>& flops) {
+                 std::vector<double>& flops, int lds_f) {
   std::map<int64_t, std::pair<int64_t, SchurPlan>> byN;  // N -> (act offset, plan)
   lay.assign((size_t)B, SchurLayout{});
   flops.assign((size_t)B, 0.0);
@@ -270,7 +271,7 @@ void schur_plans(int64_t B, const int64_t* n, std::vector<SchurLayout>& lay,
     flops[(size_t)b] = schur_flops(P);
     SchurLayout& L = lay[(size_t)b];
     int fm = 64;
-    const int64_t o = schur_layout(P, L, &fm);
+    const int64_t o = schur_layout(P, L, &fm, lds_f);
     L.act_off = it->second.first;
     L.scr_off = scr_total;
     Fmax = std::max(Fmax, fm);
@@ -383,7 +384,7 @@ static sfls_status prepare_schur(sfls_ctx* ctx, int64_t B, const int64_t* n, int
   std::vector<SchurAct> pool;
   std::vector<double> fl;
   int64_t tot = 0;
-  schur_plans(B, n, lay, pool, tot, *Fmax, fl);
+  schur_plans(B, n, lay, pool, tot, *Fmax, fl, ctx->schur_lds_f);
   if (flops) *flops = fl;
   if (pool.empty()) pool.push_back(SchurAct{});
   sfls_status s;
@@ -474,6 +475,15 @@ sfls_status sfls_set_factor(sfls_ctx* ctx, int32_t algo) {
   if (algo != SFLS_FACTOR_AUTO && algo != SFLS_FACTOR_LEVINSON && algo != SFLS_FACTOR_SCHUR)
     return fail(ctx, SFLS_EINVAL, "unknown factorisation %d", algo);
   ctx->factor_algo = algo;
+  return SFLS_OK;
+}
+
+sfls_status sfls_set_schur_lds(sfls_ctx* ctx, int32_t max_f) {
+  if (!ctx) return SFLS_EINVAL;
+  if (max_f < SCH_LDS_F_MIN || max_f > SCH_LDS_F || !is_pow2(max_f))
+    return fail(ctx, SFLS_EINVAL, "LDS transform limit %d: a power of two in %d..%d", max_f,
+                SCH_LDS_F_MIN, SCH_LDS_F);
+  ctx->schur_lds_f = max_f;
   return SFLS_OK;
 }
 

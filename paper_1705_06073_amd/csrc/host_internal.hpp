@@ -38,6 +38,7 @@ struct sfls_ctx {
   sfls_run_stats last = {};
   std::vector<double> timeline;
   hipStream_t upload = nullptr;  // admission copies of the servers on this context
+  int32_t schur_lds_f = sfls::SCH_LDS_F;  // largest recursion transform kept in LDS
 };
 
 namespace sfls_host {
@@ -78,7 +79,8 @@ double schur_flops(const SchurPlan& P);
 // start; scr_off, act_off and Fmax are left to the caller).  Returns the
 // scratch size in complex elements; *fm receives the LDS transform size the
 // plan needs.
-int64_t schur_layout(const SchurPlan& P, sfls::SchurLayout& L, int* fm);
+int64_t schur_layout(const SchurPlan& P, sfls::SchurLayout& L, int* fm,
+                     int lds_f = sfls::SCH_LDS_F);
 
 // Factorisation the context uses for a batch whose largest N is maxN.
 bool use_schur(const sfls_ctx* ctx, int maxN);

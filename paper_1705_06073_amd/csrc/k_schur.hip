@@ -445,7 +445,7 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
     const double invF = 1.0 / (double)F;
     cd* S = scr + L.spec[act.level];  // spectra of Theta1's first row, 2 x F
     const int zs = pidx(F);          // buffer stride of the one-wave transforms
-    if (logF <= SCH_WAVE_LOG &&
+    if (logF <= SCH_WAVE_LOG && F <= L.ldsF &&
         (act.type != SCH_MID || 4 * zs <= 2 * padded(L.Fmax))) {
       // One wave per transform, block barriers only around the pointwise step.
       cd* Z = lds;
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
       __syncthreads();
       continue;
     }
-    // Transform buffers: LDS, or for F > SCH_LDS_F two buffers in the
+    // Transform buffers: LDS, or for F > L.ldsF two buffers in the
     // instance's scratch (the same passes, on global memory).
     auto fft_merge = [&](cd* __restrict__ A, cd* __restrict__ Bf) __attribute__((always_inline)) {
       if (act.type == SCH_MID) {
@@ -623,7 +623,7 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
       }
       __syncthreads();
     };
-    if (F > SCH_LDS_F) fft_merge(scr + L.xbig, scr + L.xbig + padded(F));
+    if (F > L.ldsF) fft_merge(scr + L.xbig, scr + L.xbig + padded(F));
     else fft_merge(lds, lds + padded(L.Fmax));
   }
   if (tid == 0) {

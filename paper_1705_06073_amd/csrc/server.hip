@@ -140,6 +140,7 @@ struct sfls_server {
   hipEvent_t ev = nullptr;    // end of the round in flight
   bool schur = false;
   int Fmax = 0;               // LDS transform size of the recursion (fixed per server)
+  int lds_f = SCH_LDS_F;      // largest recursion transform in LDS (fixed per server)
   int64_t fL = 1, fS = 1;     // grid and recursion-scratch elements per pool sample
   int kshift = 2;
   int Rmax = 1;
@@ -230,7 +231,7 @@ sfls_status plan_for(sfls_server* s, int64_t n, const PlanEntry** out) {
   sfls_ctx* ctx = s->ctx;
   SchurPlan P = schur_plan(n);
   PlanEntry e;
-  e.scratch = schur_layout(P, e.lay, &e.fm);
+  e.scratch = schur_layout(P, e.lay, &e.fm, s->lds_f);
   e.flops = schur_flops(P);
   if (e.fm > s->Fmax) return fail(ctx, SFLS_EUNSUPPORTED, "recursion plan of n = %lld needs a larger transform", (long long)n);
   const size_t na = std::max<size_t>(P.acts.size(), 1);
@@ -382,12 +383,13 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
   // recursion: scratch per sample and the server's transform size
   s->Fmax = 64;
   s->fS = 1;
+  s->lds_f = ctx->schur_lds_f;
   if (s->schur) {
     for (int64_t blk = kUnitMin; blk <= top_blk; blk *= 2) {
       SchurPlan P = schur_plan(blk);
       SchurLayout L;
       int fm = 64;
-      const int64_t o = schur_layout(P, L, &fm);
+      const int64_t o = schur_layout(P, L, &fm, s->lds_f);
       s->Fmax = std::max(s->Fmax, fm);
       s->fS = std::max<int64_t>(s->fS, (o + blk - 1) / blk);
     }

@@ -72,8 +72,10 @@ constexpr int SCH_MAXL = 16;
 // each); larger ones use FFTs of size >= m.
 constexpr int SCH_DIRECT = 128;
 // Transform merges with F above this use two buffers of padded(F) in the
-// instance's Schur scratch (at xbig) instead of LDS.
+// instance's Schur scratch (at xbig) instead of LDS (default; a context can
+// lower it, down to SCH_LDS_F_MIN, so that more instances share a CU's LDS).
 constexpr int SCH_LDS_F = 4096;
+constexpr int SCH_LDS_F_MIN = 256;
 
 // Per-instance layout of the recursion's scratch (offsets in complex elements).
 struct SchurLayout {
@@ -81,6 +83,8 @@ struct SchurLayout {
   int64_t act_off;
   int32_t nact;
   int32_t Fmax;
+  int32_t ldsF;            // transform merges with F > ldsF run on scratch (at xbig)
+  int32_t pad_;
   int64_t win[SCH_MAXL];   // right-child windows (u then v, mmax[l] each)
   int64_t res[SCH_MAXL];   // Theta results, 2 sides x 4 polynomials x mmax[l]
   int64_t spec[SCH_MAXL];  // Theta1 first-row spectra, 2 x F

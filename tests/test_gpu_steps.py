@@ -248,3 +248,33 @@ def test_active_vectors(ctx, ns):
         sl = slice(koff[b], koff[b] + K[b])
         for i, name in enumerate("qrustvx"):
             assert relerr(og[i][sl], ref[name]) < TOL64, (b, name, relerr(og[i][sl], ref[name]))
+
+
+@pytest.mark.parametrize("lds_f", [256, 1024])
+def test_factor_with_lower_lds_transform_limit(ctx, lds_f):
+    """a3 with the recursion's larger merges moved from LDS to device scratch:
+    the same generator, pivots and ln|C| as the dense oracle."""
+    ns = [300, 1000, 2048, 4096, 4500]
+    print(f"[factor lds {lds_f}] sizes={ns}", flush=True)
+    st = make_states(ns, seed=77 + lds_f)
+    cols = [nm.toeplitz_column(t, g, b, N) for (t, g, b, _), N in zip(st, ns)]
+    ctx.set_schur_lds(lds_f)
+    try:
+        n, off, rho, delta, logdet, status, failed = gpu_factor(ctx, ns, cols, sf.SFLS_FACTOR_SCHUR)
+    finally:
+        ctx.set_schur_lds(4096)
+    assert (status == 0).all() and (failed == -1).all()
+    rg, dg, lg = d2c(rho), delta.cpu().numpy(), logdet.cpu().numpy()
+    for b in range(len(ns)):
+        F = nm.DenseFactor(nm.dense_from_column(cols[b]))
+        r_ref, _ = F.generator()
+        sl = slice(off[b], off[b] + ns[b])
+        assert relerr(rg[sl], r_ref) < TOL64, (b, relerr(rg[sl], r_ref))
+        assert relerr(dg[sl], F.delta) < TOL64
+        assert abs(lg[b] - F.logdet) < TOL64 * max(1.0, abs(F.logdet))
+
+
+def test_lds_transform_limit_rejects_bad_values(ctx):
+    for bad in (128, 3000, 8192):
+        with pytest.raises(sf.SflsError):
+            ctx.set_schur_lds(bad)
