@@ -155,7 +155,7 @@ def serve_leg(rate, seconds, prec):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--plain", type=int, default=8,
@@ -251,13 +251,20 @@ def main():
     yaddr = [y.data_ptr() + 16 * int(o) for o in off]
 
     def run_stream(nsteps):
+        # the next round is launched as soon as the previous one completes;
+        # collecting results and admitting new instances (which then join the
+        # round after) happen on the host while it runs
         total = nsteps * B
         nxt, got = 0, []
+        while nxt < total and srv.submit(yaddr[nxt % B], int(n[nxt % B]), nxt):
+            nxt += 1
+        srv.launch()
         while len(got) < total:
+            srv.wait()
+            srv.launch()
+            got += srv.poll()
             while nxt < total and srv.submit(yaddr[nxt % B], int(n[nxt % B]), nxt):
                 nxt += 1
-            srv.step()
-            got += srv.poll()
         return got
 
     for w in range(args.warmup):

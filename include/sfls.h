@@ -314,13 +314,17 @@ sfls_status sfls_last_run(const sfls_ctx* ctx, sfls_run_stats* stats, double* ti
  * request's footprint (sfls_server_footprint: every per-request array of the
  * round loop, sized by N rounded up to a power of two, at least 64) fits in
  * the pool (a buddy allocation); otherwise it returns SFLS_EAGAIN and the
- * server is unchanged.  The request's signal is copied into the pool, so the
- * caller may reuse y at once.  Each round (sfls_server_launch) runs one
+ * server is unchanged.  Admission does not wait for the device: the request's
+ * tables and a device-resident signal are copied into the pools by a kernel
+ * at the start of the next round (a host-resident signal is copied before the
+ * call returns).  Each round (sfls_server_launch) runs one
  * evaluation for every admitted request that has asked for one, whatever its
  * N, in the same kernels, and then the driver step; requests admitted since
  * the previous round join it.  sfls_server_wait completes the round: requests
- * whose estimate finished release their slot and memory, and their results
- * wait for sfls_server_poll.  All state of a request (theta, gamma, beta,
+ * whose estimate finished release their slot and memory at once, and a short
+ * kernel behind the round packs their outputs for sfls_server_poll (which
+ * waits for it), so the next round can be launched before the results are
+ * read.  All state of a request (theta, gamma, beta,
  * zeta, the L-BFGS memory, the generator) stays on the device until then.
  *
  * A request's result does not depend on the other requests in the pool: each
@@ -381,9 +385,11 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg,
 sfls_status sfls_server_destroy(sfls_server* srv);
 /* Device bytes a request of length n reserves from the pool. */
 sfls_status sfls_server_footprint(const sfls_server* srv, int64_t n, uint64_t* bytes);
-/* Admit a request: y (device or host pointer, cfg.ydtype, n elements).
+/* Admit a request: y (cfg.ydtype, n elements).  A device pointer (8-byte
+ * aligned) is read by the next round, so y must stay valid and unchanged until
+ * the next sfls_server_wait returns; a host pointer is copied before return.
  * SFLS_EAGAIN: no free slot or pool memory now (retry after a round);
- * SFLS_EINVAL: n < 2 or NULL y; SFLS_EUNSUPPORTED: n > max_n. */
+ * SFLS_EINVAL: n < 2, NULL or misaligned y; SFLS_EUNSUPPORTED: n > max_n. */
 sfls_status sfls_server_submit(sfls_server* srv, const void* y, int64_t n, uint64_t tag);
 /* Enqueue one round on the server's stream (no-op when nothing is admitted
  * or a round is already in flight).  Returns without waiting. */

@@ -87,6 +87,13 @@ int ilog2_ceil(int64_t v) {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+hipError_t spin_wait(hipEvent_t ev) {
+  for (;;) {
+    const hipError_t q = hipEventQuery(ev);
+    if (q != hipErrorNotReady) return q;
+  }
+}
+
 // Polynomial coefficients of the diagonal-sum weights in centred variables
 // x = q - c, y = p - c (p = q + i, c = (N-1)/2).  With S_k(n) = sum_{a=0}^n a^k,
 // the Gohberg-Semencul form gives, for a row weight f,
@@ -466,6 +473,10 @@ sfls_status sfls_create(sfls_ctx** out, int device) {
   }
   for (int k = 0; k < KID_COUNT; ++k)
     std::snprintf(ctx->kst[k].name, sizeof ctx->kst[k].name, "%s", kKernelNames[k]);
+  if (hipEventCreateWithFlags(&ctx->ev_round, hipEventDisableTiming) != hipSuccess) {
+    sfls_destroy(ctx);
+    return SFLS_EDEVICE;
+  }
   *out = ctx;
   return SFLS_OK;
 }
@@ -544,6 +555,7 @@ sfls_status sfls_destroy(sfls_ctx* ctx) {
   if (ctx->tws32) (void)hipFree(ctx->tws32);
   if (ctx->host_req) (void)hipHostFree(ctx->host_req);
   if (ctx->upload) (void)hipStreamDestroy(ctx->upload);
+  if (ctx->ev_round) (void)hipEventDestroy(ctx->ev_round);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   delete ctx;
@@ -938,11 +950,16 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
     if (ctx->host_req) (void)hipHostFree(ctx->host_req);
     ctx->host_req = nullptr;
     ctx->host_req_n = 0;
-    if (hipHostMalloc(&ctx->host_req, (size_t)B * sizeof(int32_t)) != hipSuccess)
+    if (hipHostMalloc(&ctx->host_req, (size_t)B * sizeof(int32_t),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
       return fail(ctx, SFLS_ENOMEM, "pinned request buffer");
     ctx->host_req_n = B;
   }
   int32_t* hreq = ctx->host_req;
+  // the driver writes the request bits into this pinned buffer directly
+  int32_t* hreq_dev = nullptr;
+  HIP_TRY(hipHostGetDevicePointer((void**)&hreq_dev, hreq, 0));
+  P.req_host = hreq_dev;
   const auto t0 = std::chrono::steady_clock::now();
   auto now_s = [&]() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -963,8 +980,8 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   HIP_TRY(launch_init_state(dinfo, y, ydtype, dst, P.req, (int)B, st));
   HIP_TRY(launch_zero_i32(notdone, 1, st));
   HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
-  HIP_TRY(hipMemcpyAsync(hreq, P.req, (size_t)B * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipEventRecord(ctx->ev_round, st));
+  HIP_TRY(spin_wait(ctx->ev_round));
   ctx->timeline.push_back(now_s());
   int64_t rounds = 0, ev_total = 0, gevals = 0;
   const int64_t max_rounds = 1000000;
@@ -1046,8 +1063,8 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
     HIP_TRY(tstart(KID_DRIVER));
     HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
     HIP_TRY(tstop(KID_DRIVER));
-    HIP_TRY(hipMemcpyAsync(hreq, P.req, (size_t)B * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipEventRecord(ctx->ev_round, st));
+    HIP_TRY(spin_wait(ctx->ev_round));
     ctx->timeline.push_back(now_s());
     if (timing) {
       for (int k = 0; k < KID_COUNT; ++k) {

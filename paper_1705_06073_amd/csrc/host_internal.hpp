@@ -38,6 +38,7 @@ struct sfls_ctx {
   sfls_run_stats last = {};
   std::vector<double> timeline;
   hipStream_t upload = nullptr;  // admission copies of the servers on this context
+  hipEvent_t ev_round = nullptr;  // end of an estimate round (request bits on the host)
   int32_t schur_lds_f = sfls::SCH_LDS_F;  // largest recursion transform kept in LDS
 };
 
@@ -57,6 +58,10 @@ sfls_status fail(sfls_ctx* ctx, sfls_status s, const char* fmt, ...);
   } while (0)
 
 int ilog2_ceil(int64_t v);
+// Wait for an event by polling it: a blocking wait can leave the device idle
+// for a scheduler wake-up between rounds, which sets the pace of the round
+// loops (one host decision per round).
+hipError_t spin_wait(hipEvent_t ev);
 bool is_pow2(int64_t v);
 
 // Coefficients of the separable forms of s, t, v, x for N samples.

@@ -111,6 +111,8 @@ __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info
   if (threadIdx.x == 0) {
     p.st[b] = S;
     if (S.phase != PH_DONE) atomicAdd(p.notdone, 1);
+    // this thread's own store of the request bits, read back in order
+    if (p.req_host) p.req_host[b] = __atomic_load_n(p.req + b, __ATOMIC_RELAXED);
   }
 }
 
@@ -197,8 +199,9 @@ __global__ void k_slots_idle(DrvState* __restrict__ st, int32_t* __restrict__ re
   }
 }
 
-// Pack the outputs of the instances in list[0..n): record i and, from
-// comp[doff[i]], theta[K], gamma[K], then alpha as K interleaved pairs.
+// Pack the outputs of the instances in list[0..n) (component arrays at
+// koff[i]): record i and, from comp[doff[i]], theta[K], gamma[K], then alpha
+// as K interleaved pairs.
 __global__ __launch_bounds__(256) void k_gather_results(
     const int32_t* __restrict__ list, const int64_t* __restrict__ doff, int n,
     const int64_t* __restrict__ koff, const int64_t* __restrict__ oK,
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(256) void k_gather_results(
     res[i] = r;
   }
   double* dst = comp + doff[i];
-  const int64_t ko = koff[b];
+  const int64_t ko = koff[i];
   for (int64_t k = threadIdx.x; k < K; k += blockDim.x) {
     dst[k] = otheta[ko + k];
     dst[K + k] = ogamma[ko + k];
@@ -244,6 +247,46 @@ hipError_t launch_gather_results(const int32_t* list, const int64_t* doff, int n
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_results, dim3(n), dim3(256), 0, s, list, doff, n, koff, oK, otheta,
                      oalpha, ogamma, obeta, ozeta, oobj, oiters, oevals, ostatus, res, comp);
+  return hipGetLastError();
+}
+
+// Admission of newly submitted instances, one block per record: the slot's
+// tables from pinned host memory (read through its device mapping) into the
+// device tables, and its signal into the pool, as 8-byte words.
+__device__ __forceinline__ void copy_words(void* __restrict__ dst, const void* __restrict__ src,
+                                           int64_t bytes) {
+  const uint64_t* s = static_cast<const uint64_t*>(src);
+  uint64_t* d = static_cast<uint64_t*>(dst);
+  for (int64_t w = threadIdx.x; w < bytes / 8; w += blockDim.x) d[w] = s[w];
+}
+
+__global__ __launch_bounds__(256) void k_admit(const AdmitRec* __restrict__ recs, int n,
+                                               const InstInfo* __restrict__ hinfo,
+                                               const SepCoef* __restrict__ hcoef,
+                                               const SchurLayout* __restrict__ hlay,
+                                               const int64_t* __restrict__ hkoff,
+                                               InstInfo* __restrict__ dinfo,
+                                               SepCoef* __restrict__ dcoef,
+                                               SchurLayout* __restrict__ dlay,
+                                               int64_t* __restrict__ dkoff, char* __restrict__ ypool) {
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const AdmitRec r = recs[i];
+  const int b = r.slot;
+  copy_words(dinfo + b, hinfo + b, sizeof(InstInfo));
+  copy_words(dcoef + b, hcoef + b, sizeof(SepCoef));
+  if (hlay) copy_words(dlay + b, hlay + b, sizeof(SchurLayout));
+  if (threadIdx.x == 0) dkoff[b] = hkoff[b];
+  if (r.src) copy_words(ypool + r.dst_bytes, r.src, r.bytes);
+}
+
+hipError_t launch_admit(const AdmitRec* recs, int n, const InstInfo* hinfo, const SepCoef* hcoef,
+                        const SchurLayout* hlay, const int64_t* hkoff, InstInfo* dinfo,
+                        SepCoef* dcoef, SchurLayout* dlay, int64_t* dkoff, void* ypool,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_admit, dim3(n), dim3(256), 0, s, recs, n, hinfo, hcoef, hlay, hkoff, dinfo,
+                     dcoef, dlay, dkoff, static_cast<char*>(ypool));
   return hipGetLastError();
 }
 

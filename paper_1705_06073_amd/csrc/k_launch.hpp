@@ -58,6 +58,9 @@ struct DrvPools {
   int32_t* out_status;
   const int64_t* out_koff;
   int32_t* notdone;
+  // optional host-mapped copy of the request bits (pinned host memory the
+  // device writes directly), so the host reads them without a copy per round
+  int32_t* req_host;
 };
 
 hipError_t launch_twiddles(cd* tw64, cf* tw32, cd* tws64, cf* tws32, int logtw, hipStream_t st);
@@ -112,6 +115,10 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
 hipError_t launch_init_state(const InstInfo* info, const void* y, int ydtype, DrvState* st,
                              int32_t* req, int B, hipStream_t s, const int32_t* list = nullptr);
 hipError_t launch_slots_idle(DrvState* st, int32_t* req, int B, hipStream_t s);
+hipError_t launch_admit(const AdmitRec* recs, int n, const InstInfo* hinfo, const SepCoef* hcoef,
+                        const SchurLayout* hlay, const int64_t* hkoff, InstInfo* dinfo,
+                        SepCoef* dcoef, SchurLayout* dlay, int64_t* dkoff, void* ypool,
+                        hipStream_t s);
 hipError_t launch_gather_results(const int32_t* list, const int64_t* doff, int n,
                                  const int64_t* koff, const int64_t* oK, const double* otheta,
                                  const cd* oalpha, const double* ogamma, const double* obeta,

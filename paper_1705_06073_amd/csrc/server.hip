@@ -110,11 +110,14 @@ hipError_t dalloc(T** p, size_t count, std::vector<void*>& owned) {
   return e;
 }
 
+// Pinned host memory, fine-grained (coherent): kernels read and write some of
+// these buffers directly, and the host reads what they wrote after an event.
 template <typename T>
 hipError_t halloc(T** p, size_t count, std::vector<void*>& owned) {
   *p = nullptr;
   void* v = nullptr;
-  hipError_t e = hipHostMalloc(&v, std::max<size_t>(count, 1) * sizeof(T));
+  hipError_t e = hipHostMalloc(&v, std::max<size_t>(count, 1) * sizeof(T),
+                               hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) {
     owned.push_back(v);
     *p = static_cast<T*>(v);
@@ -138,6 +141,7 @@ struct sfls_server {
   hipStream_t st = nullptr;   // rounds
   hipStream_t up = nullptr;   // admission copies (the context's upload stream)
   hipEvent_t ev = nullptr;    // end of the round in flight
+  hipEvent_t ev_res = nullptr;  // end of the result gather in flight
   bool schur = false;
   int Fmax = 0;               // LDS transform size of the recursion (fixed per server)
   int lds_f = SCH_LDS_F;      // largest recursion transform in LDS (fixed per server)
@@ -186,12 +190,13 @@ struct sfls_server {
           *ncand = nullptr, *notdone = nullptr;
   cd* cq = nullptr;
   double* cs = nullptr;
-  // result gathering
-  int32_t* dlist = nullptr;
-  int64_t* ddoff = nullptr;
-  SlotResult* dres = nullptr;
-  double* dcomp = nullptr;
-  size_t dcomp_n = 0;
+  // result gathering: finished slots are released when found; their outputs
+  // are packed by a kernel enqueued behind the round that finished them (the
+  // slot list and output offsets travel with it, so a new occupant's tables
+  // cannot race it) straight into pinned host memory, read by the next poll
+  int64_t* h_gkoff = nullptr;
+  bool gather_pending = false;
+  std::vector<Result> gathering;  // metadata of the results in flight
   // recursion action pool
   SchurAct* dacts = nullptr;
   size_t acts_cap = 0, acts_n = 0;
@@ -204,12 +209,27 @@ struct sfls_server {
   int64_t* h_koff = nullptr;
   int32_t* h_req = nullptr;
   int32_t* h_list = nullptr;
-  int32_t* h_newlist = nullptr;
+  int32_t* h_newlist = nullptr;  // [2][S]: admitted since the last launch, by buffer
+  AdmitRec* h_adm = nullptr;     // [2][S]
+  int abuf = 0;                  // buffer that submissions fill; a launch takes it and flips
   int64_t* h_doff = nullptr;
   SlotResult* h_res = nullptr;
   double* h_comp = nullptr;
   size_t h_comp_n = 0;
   std::vector<void*> dev_owned, host_owned;
+  // device addresses of the pinned buffers the kernels read or write directly
+  int32_t* m_req = nullptr;
+  int32_t* m_newlist = nullptr;
+  AdmitRec* m_adm = nullptr;
+  InstInfo* m_info = nullptr;
+  SepCoef* m_coef = nullptr;
+  SchurLayout* m_lay = nullptr;
+  int64_t* m_koff = nullptr;
+  int32_t* m_list = nullptr;
+  int64_t* m_doff = nullptr;
+  int64_t* m_gkoff = nullptr;
+  SlotResult* m_res = nullptr;
+  double* m_comp = nullptr;
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -301,6 +321,32 @@ bool place(const sfls_server* s, int64_t n, int order, int64_t b, const PlanEntr
 
 }  // namespace
 
+// Complete a result gather: wait for it (it is short and runs right behind
+// the round that found the results) and move the packed outputs into the
+// result queue.
+static sfls_status finish_gather(sfls_server* s) {
+  if (!s->gather_pending) return SFLS_OK;
+  sfls_ctx* ctx = s->ctx;
+  HIP_TRY(spin_wait(s->ev_res));
+  for (size_t i = 0; i < s->gathering.size(); ++i) {
+    const SlotResult& r = s->h_res[i];
+    Result& out = s->gathering[i];
+    out.r.K = r.K;
+    out.r.beta = r.beta;
+    out.r.zeta = r.zeta;
+    out.r.objective = r.obj;
+    out.r.iters = r.iters;
+    out.r.evals = r.evals;
+    out.r.status = r.status;
+    const double* src = s->h_comp + s->h_doff[i];
+    out.comp.assign(src, src + 4 * r.K);
+    s->done.push_back(std::move(out));
+  }
+  s->gathering.clear();
+  s->gather_pending = false;
+  return SFLS_OK;
+}
+
 extern "C" {
 
 void sfls_server_config_default(sfls_server_config* cfg) {
@@ -322,6 +368,7 @@ sfls_status sfls_server_destroy(sfls_server* s) {
   for (void* p : s->dev_owned) (void)hipFree(p);
   for (void* p : s->host_owned) (void)hipHostFree(p);
   if (s->ev) (void)hipEventDestroy(s->ev);
+  if (s->ev_res) (void)hipEventDestroy(s->ev_res);
   for (auto& e : s->tev)
     if (e) (void)hipEventDestroy(e);
   if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
@@ -432,7 +479,8 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
   if (!ctx->upload && hipStreamCreateWithFlags(&ctx->upload, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(ctx, SFLS_EDEVICE, "stream creation failed"));
   s->up = ctx->upload;
-  if (hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess)
+  if (hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_res, hipEventDisableTiming) != hipSuccess)
     return bail(fail(ctx, SFLS_EDEVICE, "stream/event creation failed"));
 
   auto& D = s->dev_owned;
@@ -471,7 +519,6 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
   DA(otheta, K); DA(ogamma, K); DA(oalpha, K);
   DA(oK, S); DA(obeta, S); DA(ozeta, S); DA(oobj, S); DA(oit, S); DA(oev, S); DA(ost, S);
   DA(s->dinfo, S); DA(s->dcoef, S); DA(s->dlay, S); DA(s->dkoff, S); DA(s->dprm, 1);
-  DA(s->dlist, S); DA(s->ddoff, S); DA(s->dres, S);
   if (s->schur) {
     s->acts_cap = 16384;
     DA(s->dacts, s->acts_cap);
@@ -482,10 +529,23 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
   auto& H = s->host_owned;
 #define HA(ptr, cnt) ok = ok && halloc(&(ptr), (size_t)(cnt), H) == hipSuccess
   HA(s->h_info, S); HA(s->h_coef, S); HA(s->h_lay, S); HA(s->h_koff, S); HA(s->h_req, S);
-  HA(s->h_list, S); HA(s->h_newlist, S); HA(s->h_doff, S); HA(s->h_res, S);
+  HA(s->h_list, S); HA(s->h_newlist, 2 * S); HA(s->h_adm, 2 * S); HA(s->h_doff, S);
+  HA(s->h_gkoff, S); HA(s->h_res, S);
 #undef HA
   if (!ok) return bail(fail(ctx, SFLS_ENOMEM, "pinned host mirrors"));
   std::memset(s->h_req, 0, (size_t)S * sizeof(int32_t));
+  if (hipHostGetDevicePointer((void**)&s->m_req, s->h_req, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_newlist, s->h_newlist, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_adm, s->h_adm, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_info, s->h_info, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_coef, s->h_coef, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_lay, s->h_lay, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_koff, s->h_koff, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_list, s->h_list, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_doff, s->h_doff, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_gkoff, s->h_gkoff, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_res, s->h_res, 0) != hipSuccess)
+    return bail(fail(ctx, SFLS_EDEVICE, "device addresses of the pinned mirrors"));
   P.ev_q = s->evq; P.ev_r = s->evr; P.ev_u = s->evu; P.ev_s = s->evs; P.ev_t = s->evt;
   P.ev_v = s->evv; P.ev_x = s->evx; P.logdet = s->logdet; P.yCy = s->yCy; P.ww = s->ww;
   P.lev_status = s->lev_status; P.cand = s->cand; P.ncand = s->ncand; P.cand_q = s->cq;
@@ -493,6 +553,7 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
   P.out_gamma = ogamma; P.out_beta = obeta; P.out_zeta = ozeta; P.out_obj = oobj;
   P.out_iters = oit; P.out_evals = oev; P.out_status = ost; P.out_koff = s->dkoff;
   P.notdone = s->notdone;
+  P.req_host = s->m_req;
   const DrvParams dp = drv_params(p);
   std::vector<InstInfo> zinfo((size_t)S);
   std::memset(zinfo.data(), 0, zinfo.size() * sizeof(InstInfo));
@@ -564,20 +625,43 @@ sfls_status sfls_server_submit(sfls_server* s, const void* y, int64_t n, uint64_
   s->h_lay[slot] = lay;
   s->h_koff[slot] = in.koff;
   s->slot_flops[(size_t)slot] = pe ? pe->flops : 8.0 * (double)n * (double)n;
-  hipError_t e = hipSuccess;
-  const hipStream_t up = s->up;
-  if (e == hipSuccess) e = hipMemcpyAsync(s->dinfo + slot, s->h_info + slot, sizeof(InstInfo), hipMemcpyHostToDevice, up);
-  if (e == hipSuccess) e = hipMemcpyAsync(s->dcoef + slot, s->h_coef + slot, sizeof(SepCoef), hipMemcpyHostToDevice, up);
-  if (e == hipSuccess && s->schur) e = hipMemcpyAsync(s->dlay + slot, s->h_lay + slot, sizeof(SchurLayout), hipMemcpyHostToDevice, up);
-  if (e == hipSuccess) e = hipMemcpyAsync(s->dkoff + slot, s->h_koff + slot, sizeof(int64_t), hipMemcpyHostToDevice, up);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(static_cast<char*>(s->ypool) + (size_t)in.off * s->ysz, y, (size_t)n * s->ysz,
-                       hipMemcpyDefault, up);
-  if (e == hipSuccess) e = hipStreamSynchronize(up);
-  if (e != hipSuccess) {
+  // The tables stay in the pinned mirrors until the next round's admission
+  // kernel copies them (the slot's previous occupant finished rounds ago, and
+  // its admission was read long before).  A device signal is copied by the
+  // same kernel; a host signal now, through the context's upload stream.
+  const size_t ybytes = (size_t)n * s->ysz;
+  const size_t ydst = (size_t)in.off * s->ysz;
+  bool on_device = false;
+  {
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, y) == hipSuccess)
+      on_device = at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+    (void)hipGetLastError();  // a host pointer the runtime does not know leaves an error
+  }
+  if (on_device && (reinterpret_cast<uintptr_t>(y) & 7) != 0) {
     s->buddy.release(b, order);
     s->free_slots.insert(slot);
-    return fail(ctx, SFLS_EDEVICE, "admission copies failed: %s", hipGetErrorString(e));
+    return fail(ctx, SFLS_EINVAL, "device signal must be 8-byte aligned");
+  }
+  if (!on_device) {
+    hipError_t e = hipMemcpyAsync(static_cast<char*>(s->ypool) + ydst, y, ybytes,
+                                  hipMemcpyHostToDevice, s->up);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->up);
+    if (e != hipSuccess) {
+      s->buddy.release(b, order);
+      s->free_slots.insert(slot);
+      return fail(ctx, SFLS_EDEVICE, "signal copy failed: %s", hipGetErrorString(e));
+    }
+  }
+  {
+    const size_t i = s->admitted.size();
+    AdmitRec& r = s->h_adm[(size_t)s->abuf * (size_t)s->cfg.max_slots + i];
+    r.slot = slot;
+    r.pad_ = 0;
+    r.src = on_device ? y : nullptr;
+    r.dst_bytes = (int64_t)ydst;
+    r.bytes = (int64_t)ybytes;
+    s->h_newlist[(size_t)s->abuf * (size_t)s->cfg.max_slots + i] = slot;
   }
   Slot& sl = s->slots[(size_t)slot];
   sl.state = SLOT_ADMITTED;
@@ -604,11 +688,15 @@ sfls_status sfls_server_launch(sfls_server* s) {
   // newly admitted requests: initial state (phase START), stepped by this round's driver
   const int nnew = (int)s->admitted.size();
   if (nnew > 0) {
-    for (int i = 0; i < nnew; ++i) s->h_newlist[i] = s->admitted[(size_t)i];
-    HIP_TRY(hipMemcpyAsync(s->dlist, s->h_newlist, (size_t)nnew * sizeof(int32_t),
-                           hipMemcpyHostToDevice, st));
+    // the kernels read the records and lists from pinned host memory; the
+    // buffer flips, so submissions during this round fill the other one, and
+    // this one is rewritten only after this round has completed
+    const size_t o = (size_t)s->abuf * (size_t)s->cfg.max_slots;
+    HIP_TRY(launch_admit(s->m_adm + o, nnew, s->m_info, s->m_coef, s->schur ? s->m_lay : nullptr,
+                         s->m_koff, s->dinfo, s->dcoef, s->dlay, s->dkoff, s->ypool, st));
     HIP_TRY(launch_init_state(s->dinfo, s->ypool, s->cfg.ydtype, s->P.st, s->P.req, nnew, st,
-                              s->dlist));
+                              s->m_newlist + o));
+    s->abuf ^= 1;
     for (int sl : s->admitted) s->slots[(size_t)sl].state = SLOT_RUNNING;
     s->admitted.clear();
   }
@@ -718,9 +806,8 @@ sfls_status sfls_server_launch(sfls_server* s) {
     HIP_TRY(tstop(KID_ACTIVE));
   }
   HIP_TRY(tstart(KID_DRIVER));
-  HIP_TRY(launch_driver(s->dinfo, s->dprm, P, B, st));
+  HIP_TRY(launch_driver(s->dinfo, s->dprm, P, B, st));  // request bits also to h_req
   HIP_TRY(tstop(KID_DRIVER));
-  HIP_TRY(hipMemcpyAsync(s->h_req, P.req, (size_t)B * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipEventRecord(s->ev, st));
   s->in_flight = true;
   s->t_launch = std::chrono::steady_clock::now();
@@ -742,7 +829,7 @@ sfls_status sfls_server_wait(sfls_server* s, int32_t block, int32_t* ready, int3
     }
     if (q != hipSuccess) return fail(ctx, SFLS_EDEVICE, "round failed: %s", hipGetErrorString(q));
   } else {
-    HIP_TRY(hipEventSynchronize(s->ev));
+    HIP_TRY(spin_wait(s->ev));
   }
   s->in_flight = false;
   s->stats.rounds += 1;
@@ -760,28 +847,22 @@ sfls_status sfls_server_wait(sfls_server* s, int32_t block, int32_t* ready, int3
   s->stats.gpu_seconds +=
       std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t_launch).count();
   const double t_done = s->now();
-  // requests whose driver asked for nothing more have finished
+  // results gathered behind the previous round are complete by now
+  sfls_status fs = finish_gather(s);
+  if (fs != SFLS_OK) return fs;
+  // requests whose driver asked for nothing more have finished: release their
+  // slots and blocks, and pack their outputs behind this round
   int nf = 0;
   int64_t ctot = 0;
   for (int b = 0; b < s->hw; ++b) {
     if (s->slots[(size_t)b].state != SLOT_RUNNING || s->h_req[b] != 0) continue;
     s->h_list[nf] = b;
     s->h_doff[nf] = ctot;
+    s->h_gkoff[nf] = s->h_info[b].koff;
     ctot += 4 * (int64_t)s->h_info[b].kcap;
     ++nf;
   }
   if (nf == 0) return SFLS_OK;
-  if ((size_t)ctot > s->dcomp_n) {
-    size_t want = std::max<size_t>((size_t)ctot, 2 * s->dcomp_n);
-    auto it = std::find(s->dev_owned.begin(), s->dev_owned.end(), (void*)s->dcomp);
-    if (it != s->dev_owned.end()) s->dev_owned.erase(it);
-    if (s->dcomp) (void)hipFree(s->dcomp);
-    s->dcomp = nullptr;
-    s->dcomp_n = 0;
-    if (dalloc(&s->dcomp, want, s->dev_owned) != hipSuccess)
-      return fail(ctx, SFLS_ENOMEM, "result staging of %zu doubles", want);
-    s->dcomp_n = want;
-  }
   if ((size_t)ctot > s->h_comp_n) {
     size_t want = std::max<size_t>((size_t)ctot, 2 * s->h_comp_n);
     auto it = std::find(s->host_owned.begin(), s->host_owned.end(), (void*)s->h_comp);
@@ -791,43 +872,37 @@ sfls_status sfls_server_wait(sfls_server* s, int32_t block, int32_t* ready, int3
     s->h_comp_n = 0;
     if (halloc(&s->h_comp, want, s->host_owned) != hipSuccess)
       return fail(ctx, SFLS_ENOMEM, "pinned result staging of %zu doubles", want);
+    HIP_TRY(hipHostGetDevicePointer((void**)&s->m_comp, s->h_comp, 0));
     s->h_comp_n = want;
   }
   const hipStream_t st = s->st;
   const DrvPools& P = s->P;
-  HIP_TRY(hipMemcpyAsync(s->dlist, s->h_list, (size_t)nf * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(s->ddoff, s->h_doff, (size_t)nf * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  HIP_TRY(launch_gather_results(s->dlist, s->ddoff, nf, s->dkoff, P.out_K, P.out_theta,
+  // the gather reads its lists from, and writes the packed results into,
+  // pinned host memory (no copies); the host touches them again only after
+  // ev_res
+  HIP_TRY(launch_gather_results(s->m_list, s->m_doff, nf, s->m_gkoff, P.out_K, P.out_theta,
                                 P.out_alpha, P.out_gamma, P.out_beta, P.out_zeta, P.out_obj,
-                                P.out_iters, P.out_evals, P.out_status, s->dres, s->dcomp, st));
-  HIP_TRY(hipMemcpyAsync(s->h_res, s->dres, (size_t)nf * sizeof(SlotResult), hipMemcpyDeviceToHost, st));
-  if (ctot > 0)
-    HIP_TRY(hipMemcpyAsync(s->h_comp, s->dcomp, (size_t)ctot * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+                                P.out_iters, P.out_evals, P.out_status, s->m_res, s->m_comp, st));
+  HIP_TRY(hipEventRecord(s->ev_res, st));
+  s->gathering.clear();
   for (int i = 0; i < nf; ++i) {
-    const SlotResult& r = s->h_res[i];
     const int b = s->h_list[i];
     Slot& sl = s->slots[(size_t)b];
     Result out;
     out.r.tag = sl.tag;
     out.r.n = s->h_info[b].N;
-    out.r.K = r.K;
-    out.r.beta = r.beta;
-    out.r.zeta = r.zeta;
-    out.r.objective = r.obj;
-    out.r.iters = r.iters;
-    out.r.evals = r.evals;
-    out.r.status = r.status;
     out.r.t_submit = sl.t_submit;
     out.r.t_done = t_done;
-    const double* src = s->h_comp + s->h_doff[i];
-    out.comp.assign(src, src + 4 * r.K);
-    s->done.push_back(std::move(out));
+    s->gathering.push_back(std::move(out));
+    // the slot and its block can take a new request now: every later write
+    // to them is ordered after the gather on this stream, and the gather
+    // reads no table a new admission rewrites
     s->buddy.release(sl.block, sl.order);
     s->stats.units_used -= kUnitMin << sl.order;
     sl = Slot{};
     s->free_slots.insert(b);
   }
+  s->gather_pending = true;
   while (s->hw > 0 && s->slots[(size_t)s->hw - 1].state == SLOT_FREE) --s->hw;
   s->stats.completed += nf;
   s->stats.in_flight -= nf;
@@ -847,6 +922,9 @@ sfls_status sfls_server_poll(sfls_server* s, sfls_result* res, int32_t max_resul
                              int32_t* nres) {
   if (!s || !nres || (max_results > 0 && !res)) return SFLS_EINVAL;
   *nres = 0;
+  (void)hipSetDevice(s->ctx->device);
+  sfls_status fs = finish_gather(s);
+  if (fs != SFLS_OK) return fs;
   int64_t used = 0;
   while (*nres < max_results && !s->done.empty()) {
     Result& r = s->done.front();

@@ -94,6 +94,16 @@ struct SchurLayout {
 
 // Outputs of one finished instance, packed by k_gather_results for a single
 // device-to-host copy (components follow in a separate packed array).
+// One admission: the slot whose tables k_admit copies from pinned host
+// memory, and the signal to copy into the pool (src NULL: already there).
+struct AdmitRec {
+  int32_t slot;
+  int32_t pad_;
+  const void* src;
+  int64_t dst_bytes;  // byte offset in the signal pool
+  int64_t bytes;
+};
+
 struct SlotResult {
   int64_t K;
   double beta, zeta, obj;

@@ -41,10 +41,14 @@ def run_stream(lanes, lane_of, arrivals, sizes, ptr_of, progress_every: float = 
         max_backlog = max(max_backlog, backlog)
         progressed = False
         for li, srv in enumerate(lanes):
+            fin = 0
             if srv.in_flight:
                 ready, fin = srv.wait(block=False)
                 if ready:
                     progressed = True
+                    # the next round starts before the host collects results
+                    # and admits requests, which then join the round after
+                    srv.launch()
                 if fin:
                     tc = time.perf_counter() - t0
                     for r in srv.poll():
@@ -52,7 +56,7 @@ def run_stream(lanes, lane_of, arrivals, sizes, ptr_of, progress_every: float = 
                         results[r.tag] = r
                         done += 1
             # admission does not wait for the round in flight: the signal is
-            # copied on the server's upload stream and joins the next round
+            # copied on the context's upload stream and joins a later round
             q = queues[li]
             while q and srv.submit(ptr_of(q[0]), int(sizes[q[0]]), q[0]):
                 q.popleft()
@@ -63,7 +67,7 @@ def run_stream(lanes, lane_of, arrivals, sizes, ptr_of, progress_every: float = 
                 time.sleep(max(0.0, arrivals[i] - (time.perf_counter() - t0)))
             continue
         if not progressed:
-            time.sleep(0.0001)
+            time.sleep(0)  # yield; a timed sleep would add its granularity to every round
         if log is not None and now >= next_report:
             log(f"serving t={now:.1f}s arrived={i} done={done} backlog={backlog}")
             next_report += progress_every
