@@ -6,6 +6,7 @@
 namespace sfls {
 
 constexpr int ACT_NT = 256;
+constexpr int ACT_ANCHOR = 4;  // samples per thread between exact phase evaluations
 constexpr int NU_NT = 512;
 
 // Whether instance work of npts points at N samples uses the NUFFT form below
@@ -15,6 +16,14 @@ __device__ __forceinline__ bool use_nufft(int mode, int N, int P, int npts) {
   if (mode == 1 || npts <= 0 || 4 * npts > 3 * P) return false;
   if (mode == 2) return true;
   return N >= 512 && (double)npts * (double)N >= NU_MIN_WORK;
+}
+
+// Instances of at most ACT_LDS_N samples whose points take the direct sums
+// run in k_active_lds (w and rho staged once in LDS, one wave per point)
+// instead of the item-parallel k_active.
+constexpr int ACT_LDS_N = 4096;
+__device__ __forceinline__ bool use_lds_active(int mode, int N, int P, int npts) {
+  return npts > 0 && N <= ACT_LDS_N && !use_nufft(mode, N, P, npts);
 }
 
 // Exclusive prefix over instances of the number of work items:
@@ -32,7 +41,8 @@ __global__ __launch_bounds__(1024) void k_item_scan(const InstInfo* __restrict__
   auto items = [&](int b) {
     const int32_t rq = req[b];
     const int n = ((rq & REQ_EVAL) ? Keval[b] : 0) + ((rq & REQ_GRID) && ncand ? ncand[b] : 0);
-    return use_nufft(nmode, info[b].N, info[b].P, n) ? 0 : n;
+    return (use_nufft(nmode, info[b].N, info[b].P, n) || use_lds_active(nmode, info[b].N, info[b].P, n))
+               ? 0 : n;
   };
   int32_t loc = 0;
   for (int b = b0; b < min(B, b0 + per); ++b) loc += items(b);
@@ -50,6 +60,50 @@ __global__ __launch_bounds__(1024) void k_item_scan(const InstInfo* __restrict__
     run += items(b);
   }
   if (tid == 1023) prefix[B] = part[1023];
+}
+
+// Outputs of point j from its 14 sums (q, n q, n^2 q, then G_0..G_3 as
+// re/im pairs): q, r, u and s, t, v, x by the separable form (full points),
+// or q and s (grid candidates, j >= nk).
+__device__ __forceinline__ void active_out(const double (&acc)[14], bool full, const InstInfo& in,
+                                           int j, int nk, double idl, const SepCoef& cf, cd* oq,
+                                           cd* orr, cd* ou, cd* os, cd* ot, cd* ov, cd* ox,
+                                           cd* cq, double* cs) {
+  const double TWO_PI = 6.283185307179586476925286766559;
+  const cd G[4] = {cd{acc[6], acc[7]}, cd{acc[8], acc[9]}, cd{acc[10], acc[11]},
+                   cd{acc[12], acc[13]}};
+  const int nq = full ? 4 : 1;
+  cd outv[4];
+  for (int qk = 0; qk < nq; ++qk) {
+    const double* C = cf.c[qk];
+    const int am = (qk == 0) ? 1 : 3;
+    cd a2{0.0, 0.0};
+    for (int a = 0; a <= am; ++a)
+      for (int b2 = 0; b2 <= am; ++b2) {
+        const double cab = C[a * 4 + b2];
+        if (cab != 0.0) {
+          const cd pr = cmulc(G[a], G[b2]);
+          a2.x = fma(cab, pr.x, a2.x);
+          a2.y = fma(cab, pr.y, a2.y);
+        }
+      }
+    outv[qk] = cscale(a2, idl);
+  }
+  const cd q{acc[0], acc[1]};
+  if (full) {
+    const int64_t o = in.koff + j;
+    oq[o] = q;
+    orr[o] = cd{TWO_PI * acc[2], TWO_PI * acc[3]};
+    ou[o] = cd{TWO_PI * TWO_PI * acc[4], TWO_PI * TWO_PI * acc[5]};
+    os[o] = cd{outv[0].x, 0.0};
+    ot[o] = outv[1];
+    ov[o] = outv[2];
+    ox[o] = outv[3];
+  } else {
+    const int64_t o = in.coff + (j - nk);
+    cq[o] = q;
+    cs[o] = outv[0].x;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -101,10 +155,16 @@ __global__ __launch_bounds__(ACT_NT) void k_active(const InstInfo* __restrict__ 
     double acc[14];
 #pragma unroll
     for (int i = 0; i < 14; ++i) acc[i] = 0.0;
+    // e_n = exp(-j 2 pi n theta): exact phase reduction every ACT_ANCHOR-th
+    // sample of a thread, rotations by exp(-j 2 pi ACT_NT theta) in between
+    // (a few ulp from the exact value, against one sincospi per sample)
+    const cd rot = cconj(cis2pi(frac_mul((double)ACT_NT, th)));
+    cd e{1.0, 0.0};
+    int it = 0;
     if (full) {
-      for (int n = tid; n < N; n += ACT_NT) {
+      for (int n = tid; n < N; n += ACT_NT, ++it) {
         const double dn = (double)n;
-        const cd e = cconj(cis2pi(frac_mul(dn, th)));
+        e = (it % ACT_ANCHOR == 0) ? cconj(cis2pi(frac_mul(dn, th))) : cmul(e, rot);
         const cd we = cmul(wb[n], e);
         const cd re = cmul(rb[n], e);
         const double x = dn - cN;
@@ -120,9 +180,9 @@ __global__ __launch_bounds__(ACT_NT) void k_active(const InstInfo* __restrict__ 
         acc[12] = fma(x3, re.x, acc[12]); acc[13] = fma(x3, re.y, acc[13]);
       }
     } else {
-      for (int n = tid; n < N; n += ACT_NT) {
+      for (int n = tid; n < N; n += ACT_NT, ++it) {
         const double dn = (double)n;
-        const cd e = cconj(cis2pi(frac_mul(dn, th)));
+        e = (it % ACT_ANCHOR == 0) ? cconj(cis2pi(frac_mul(dn, th))) : cmul(e, rot);
         const cd we = cmul(wb[n], e);
         const cd re = cmul(rb[n], e);
         const double x = dn - cN;
@@ -132,45 +192,91 @@ __global__ __launch_bounds__(ACT_NT) void k_active(const InstInfo* __restrict__ 
       }
     }
     block_sum<ACT_NT, 14>(acc, red);
-    if (tid == 0) {
-      const double idl = 1.0 / delta[in.off + N - 1];
-      const SepCoef& cf = coef[bi];
-      const cd G[4] = {cd{acc[6], acc[7]}, cd{acc[8], acc[9]}, cd{acc[10], acc[11]},
-                       cd{acc[12], acc[13]}};
-      const int nq = full ? 4 : 1;
-      cd outv[4];
-      for (int qk = 0; qk < nq; ++qk) {
-        const double* C = cf.c[qk];
-        const int am = (qk == 0) ? 1 : 3;
-        cd a2{0.0, 0.0};
-        for (int a = 0; a <= am; ++a)
-          for (int b2 = 0; b2 <= am; ++b2) {
-            const double cab = C[a * 4 + b2];
-            if (cab != 0.0) {
-              const cd pr = cmulc(G[a], G[b2]);
-              a2.x = fma(cab, pr.x, a2.x);
-              a2.y = fma(cab, pr.y, a2.y);
-            }
-          }
-        outv[qk] = cscale(a2, idl);
-      }
-      const cd q{acc[0], acc[1]};
+    if (tid == 0)
+      active_out(acc, full, in, j, nk, 1.0 / delta[in.off + N - 1], coef[bi], oq, orr, ou, os, ot,
+                 ov, ox, cq, cs);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same sums, one workgroup per instance of at most ACT_LDS_N samples: w
+// and rho are read from HBM once into LDS, and each wave takes points j =
+// wave, wave + 4, ..., its lanes striding over the samples with the phase
+// rotated by exp(-j 2 pi 64 theta) between exact evaluations every
+// ACT_ANCHOR_W samples, and wave reductions (same bits in every lane).  The
+// item-parallel k_active instead reads both vectors once per point.
+// ---------------------------------------------------------------------------
+constexpr int ACTL_NT = 1024;
+constexpr int ACT_ANCHOR_W = 8;
+
+__global__ __launch_bounds__(ACTL_NT) void k_active_lds(const InstInfo* __restrict__ info,
+                                                        const int32_t* __restrict__ req,
+                                                        const int32_t* __restrict__ Keval,
+                                                        const int32_t* __restrict__ ncand,
+                                                        int nmode, const double* __restrict__ theta,
+                                                        const int32_t* __restrict__ cand,
+                                                        const cd* __restrict__ w,
+                                                        const cd* __restrict__ rho,
+                                                        const double* __restrict__ delta,
+                                                        const SepCoef* __restrict__ coef,
+                                                        cd* __restrict__ oq, cd* __restrict__ orr,
+                                                        cd* __restrict__ ou, cd* __restrict__ os,
+                                                        cd* __restrict__ ot, cd* __restrict__ ov,
+                                                        cd* __restrict__ ox, cd* __restrict__ cq,
+                                                        double* __restrict__ cs) {
+  const int bi = blockIdx.x;
+  const int32_t rq = req ? req[bi] : REQ_EVAL;
+  const InstInfo in = info[bi];
+  const int nk = (rq & REQ_EVAL) ? Keval[bi] : 0;
+  const int nc = ((rq & REQ_GRID) && ncand) ? ncand[bi] : 0;
+  const int npts = nk + nc;
+  const int N = in.N;
+  if (!use_lds_active(nmode, N, in.P, npts)) return;
+  extern __shared__ cd actl_sh[];
+  cd* sw = actl_sh;      // [N]
+  cd* sr = actl_sh + N;  // [N]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  batched_for<8>(tid, ACTL_NT, N, [&](int t) { return cd2{w[in.off + t], rho[in.off + t]}; },
+                 [&](int t, cd2 v) {
+    sw[t] = v.a;
+    sr[t] = v.b;
+  });
+  __syncthreads();
+  const double cN = 0.5 * (double)(N - 1);
+  const double idl = 1.0 / delta[in.off + N - 1];
+  const SepCoef& cf = coef[bi];
+  for (int j = wv; j < npts; j += ACTL_NT / 64) {
+    const bool full = j < nk;
+    const double th = full ? theta[in.koff + j] : (double)cand[in.coff + (j - nk)] / (double)in.L;
+    const cd rot = cconj(cis2pi(frac_mul(64.0, th)));
+    double acc[14];
+#pragma unroll
+    for (int i = 0; i < 14; ++i) acc[i] = 0.0;
+    cd e{1.0, 0.0};
+    int it = 0;
+    for (int n = lane; n < N; n += 64, ++it) {
+      const double dn = (double)n;
+      e = (it % ACT_ANCHOR_W == 0) ? cconj(cis2pi(frac_mul(dn, th))) : cmul(e, rot);
+      const cd we = cmul(sw[n], e);
+      const cd re = cmul(sr[n], e);
+      const double x = dn - cN;
+      acc[0] += we.x; acc[1] += we.y;
+      acc[6] += re.x; acc[7] += re.y;
+      acc[8] = fma(x, re.x, acc[8]); acc[9] = fma(x, re.y, acc[9]);
       if (full) {
-        const int64_t o = in.koff + j;
-        oq[o] = q;
-        orr[o] = cd{TWO_PI * acc[2], TWO_PI * acc[3]};
-        ou[o] = cd{TWO_PI * TWO_PI * acc[4], TWO_PI * TWO_PI * acc[5]};
-        os[o] = cd{outv[0].x, 0.0};
-        ot[o] = outv[1];
-        ov[o] = outv[2];
-        ox[o] = outv[3];
-      } else {
-        const int64_t o = in.coff + (j - nk);
-        cq[o] = q;
-        cs[o] = outv[0].x;
+        acc[2] = fma(dn, we.x, acc[2]); acc[3] = fma(dn, we.y, acc[3]);
+        const double d2 = dn * dn;
+        acc[4] = fma(d2, we.x, acc[4]); acc[5] = fma(d2, we.y, acc[5]);
+        const double x2 = x * x;
+        acc[10] = fma(x2, re.x, acc[10]); acc[11] = fma(x2, re.y, acc[11]);
+        const double x3 = x2 * x;
+        acc[12] = fma(x3, re.x, acc[12]); acc[13] = fma(x3, re.y, acc[13]);
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 14; ++i) acc[i] = wave_sum(acc[i]);
+    if (lane == 0) active_out(acc, full, in, j, nk, idl, cf, oq, orr, ou, os, ot, ov, ox, cq, cs);
   }
 }
 
@@ -352,6 +458,16 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
                      prefix);
   hipLaunchKernelGGL(k_active, dim3(nblocks), dim3(ACT_NT), 0, st, info, req, Keval, prefix, B,
                      theta, cand, w, rho, delta, coef, oq, orr, ou, os, ot, ov, ox, cq, cs);
+  {
+    // N <= P/2 for every instance, so 2 * min(P, 2 ACT_LDS_N) / 2 points cover w and rho
+    const int pl = maxP < 2 * ACT_LDS_N ? maxP : 2 * ACT_LDS_N;
+    const size_t shm = (size_t)pl * sizeof(cd);
+    (void)hipFuncSetAttribute((const void*)k_active_lds,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_active_lds, dim3(B), dim3(ACTL_NT), shm, st, info, req, Keval, ncand,
+                       nmode, theta, cand, w, rho, delta, coef, oq, orr, ou, os, ot, ov, ox, cq,
+                       cs);
+  }
   if (nmode != 1) {
     const size_t shm = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);
     (void)hipFuncSetAttribute((const void*)k_active_nufft,
