@@ -86,7 +86,7 @@ SERVE_HBM = (2 << 30, 4 << 30, 8 << 30, 32 << 30)
 SERVE_POOL = {256: 64, 1024: 64, 4096: 32, 16384: 16, 65536: 8}
 
 
-def serve_leg(rate, seconds, prec):
+def serve_leg(rate, seconds, prec, single_n=None):
     """The serving stream: Poisson arrivals at `rate`/s for `seconds`, N from
     {256, 1024, 4096, 16384, 65536} (weights .3/.3/.2/.15/.05), K~Poisson(N/64),
     SNR~U[5,30] dB, complex64 input, one server per size class on its own
@@ -97,11 +97,17 @@ def serve_leg(rate, seconds, prec):
     import paper_1705_06073_amd as sf
     from paper_1705_06073_amd import serving, synth
 
-    arrivals, sizes = synth.serving_stream(rate, seconds)
+    if single_n:
+        arrivals, sizes = synth.serving_stream(rate, seconds, sizes=[single_n])
+        pool_sizes = {single_n: 256}
+        classes, hbm = ((single_n, 256),), (4 << 30,)
+    else:
+        arrivals, sizes = synth.serving_stream(rate, seconds)
+        pool_sizes, classes, hbm = SERVE_POOL, SERVE_CLASSES, SERVE_HBM
     log(f"serving: {len(arrivals)} requests over {seconds:.0f} s; building the signal pool")
     pool, addr_of = [], {}
     o = 0
-    for N, cnt in SERVE_POOL.items():
+    for N, cnt in pool_sizes.items():
         for j in range(cnt):
             inst = synth.workload_serving_signal(N, j)
             pool.append(inst.y.astype(np.complex64))
@@ -109,26 +115,24 @@ def serve_leg(rate, seconds, prec):
             o += N
     y = torch.from_numpy(np.concatenate(pool).view(np.float32).copy()).to("cuda:0")
     base = y.data_ptr()
-    count = {N: 0 for N in SERVE_POOL}
+    count = {N: 0 for N in pool_sizes}
     ptrs = np.zeros(len(arrivals), np.int64)
     for i, N in enumerate(sizes):
         N = int(N)
-        ptrs[i] = base + 8 * addr_of[(N, count[N] % SERVE_POOL[N])]
+        ptrs[i] = base + 8 * addr_of[(N, count[N] % pool_sizes[N])]
         count[N] += 1
     ctx = sf.Context(0)
     params = sf.default_params(precision=prec)
-    lanes = serving.default_lanes(ctx, params, size_classes=SERVE_CLASSES, hbm_bytes=SERVE_HBM)
-    lane_of = [serving.lane_index(SERVE_CLASSES, int(n)) for n in sizes]
+    lanes = serving.default_lanes(ctx, params, size_classes=classes, hbm_bytes=hbm)
+    lane_of = [serving.lane_index(classes, int(n)) for n in sizes]
     # warm the kernels of every lane once (one request each, not timed)
-    warm = [serving.lane_index(SERVE_CLASSES, N) for N in SERVE_POOL]
-    for N in SERVE_POOL:
-        li = serving.lane_index(SERVE_CLASSES, N)
+    for N in pool_sizes:
+        li = serving.lane_index(classes, N)
         lanes[li].submit(base + 8 * addr_of[(N, 0)], N, 0)
     for s in lanes:
         while s.stats()["in_flight"]:
             s.step()
         s.poll()
-    del warm
     torch.cuda.synchronize()
     log("serving: stream starts")
     res, lat, st = serving.run_stream(lanes, lane_of, arrivals, sizes, lambda i: int(ptrs[i]),
@@ -140,11 +144,11 @@ def serve_leg(rate, seconds, prec):
         "max_backlog": st["max_backlog"],
         "lanes": [{"max_n": mx, "slots": sl, "rounds": ls["rounds"],
                    "hbm_reserved_GiB": ls["bytes_reserved"] / 2**30}
-                  for (mx, sl), ls in zip(SERVE_CLASSES, st["lanes"])],
+                  for (mx, sl), ls in zip(classes, st["lanes"])],
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(statuses, return_counts=True))},
         "evals_mean": float(np.mean([r.evaluations for r in res])),
         "precision": "mixed" if prec == sf.SFLS_MIXED else "fp64",
-        "input": "complex64, device-resident signal pool " + str(SERVE_POOL),
+        "input": "complex64, device-resident signal pool " + str(pool_sizes),
     })
     for s in lanes:
         s.close()
@@ -177,6 +181,9 @@ def main():
                     help="also run the serving stream for this many seconds of arrivals "
                          "(60 for the full stream)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve4096-seconds", type=float, default=3.0,
+                    help="serving stream of N=4096 requests beside the default legs (0: skip)")
+    ap.add_argument("--serve4096-rate", type=float, default=2000.0)
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving stream and print its summary")
     args = ap.parse_args()
@@ -374,6 +381,9 @@ def main():
     serve = None
     if args.serve_seconds > 0:
         serve = serve_leg(args.serve_rate, args.serve_seconds, prec)
+    serve4096 = None
+    if args.serve4096_seconds > 0:
+        serve4096 = serve_leg(args.serve4096_rate, args.serve4096_seconds, prec, single_n=4096)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -426,6 +436,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "serving": serve,
+        "serving_n4096": serve4096,
     }
     ctx.close()
     print(json.dumps(result), flush=True)

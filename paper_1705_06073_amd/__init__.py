@@ -457,9 +457,9 @@ class Server:
         return int(b.value)
 
     def submit(self, y, n: int, tag: int) -> bool:
-        """y: GPU tensor (interleaved re/im of the server's dtype) or a device
-        address; it is read by the next round, so keep it unchanged until the
-        next wait()/step() returns."""
+        """y: GPU tensor (interleaved re/im of the server's dtype), or an
+        address: device memory is read by the next round (keep it unchanged
+        until the next wait()/step() returns), host memory is copied now."""
         ptr = ctypes.c_void_p(y if isinstance(y, int) else y.data_ptr())
         st = lib().sfls_server_submit(self._h, ptr, int(n), int(tag))
         if st == SFLS_EAGAIN:

@@ -205,17 +205,20 @@ def workload_serving_signal(N: int, instance: int) -> Instance:
     return make_instance(rng, N, K, 1.0 / N, "cn", snr, np.complex64, s, blocked=True)
 
 
-def serving_stream(rate: float, duration: float, seed_instance: int = 0):
+def serving_stream(rate: float, duration: float, seed_instance: int = 0, sizes=None,
+                   weights=None):
     """Arrival times (s, ascending) of a Poisson process of `rate` requests/s
     over `duration` seconds and each request's N drawn from SERVING_SIZES with
-    SERVING_WEIGHTS."""
+    SERVING_WEIGHTS (or from `sizes`, uniformly unless `weights` are given)."""
     rng = np.random.Generator(np.random.PCG64(seed_for(4, seed_instance)))
     n_exp = int(rate * duration * 1.2 + 100)
     t = np.cumsum(rng.exponential(1.0 / rate, n_exp))
     t = t[t < duration]
-    sizes = rng.choice(np.array(SERVING_SIZES, np.int64), size=len(t),
-                       p=np.array(SERVING_WEIGHTS))
-    return t, sizes
+    sz = SERVING_SIZES if sizes is None else sizes
+    wt = (SERVING_WEIGHTS if sizes is None else [1.0 / len(sz)] * len(sz)) if weights is None \
+        else weights
+    n = rng.choice(np.array(sz, np.int64), size=len(t), p=np.array(wt, dtype=float))
+    return t, n
 
 
 def workload_paper_snr(instance: int, snr_db: float, N: int = 128, K: int = 10) -> Instance:

@@ -232,3 +232,29 @@ def test_request_loop_over_size_class_lanes(ctx):
     finally:
         for s in lanes:
             s.close()
+
+
+def test_host_and_device_signals_give_the_same_result(ctx):
+    """A signal in host memory (copied at submission) and the same signal on
+    the device (copied by the next round's admission kernel) are served to the
+    same bits."""
+    insts = signals([512, 1000, 256], seed=5)
+    y, addr = to_device(insts)
+    host = [np.ascontiguousarray(i.y.astype(np.complex64)) for i in insts]
+    out = []
+    for use_host in (False, True):
+        srv = sf.Server(ctx, max_n=1024, max_slots=4, hbm_bytes=256 << 20)
+        try:
+            for k, inst in enumerate(insts):
+                ptr = host[k].ctypes.data if use_host else addr[k]
+                assert srv.submit(ptr, inst.N, k)
+            got = {}
+            while len(got) < len(insts):
+                srv.step()
+                for r in srv.poll():
+                    got[r.tag] = r
+            out.append([got[k] for k in range(len(insts))])
+        finally:
+            srv.close()
+    for a, b in zip(*out):
+        same(a, b)
