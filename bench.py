@@ -175,6 +175,8 @@ def main():
                     help="generator recursion (auto: superfast Schur from N=256 on)")
     ap.add_argument("--slots", type=int, default=256,
                     help="server slots of the continuous-batching leg (instances on the device)")
+    ap.add_argument("--servers", type=int, default=1,
+                    help="servers (each on its own stream) sharing the continuous-batching leg")
     ap.add_argument("--schur-lds", type=int, default=4096,
                     help="largest superfast-recursion transform kept in LDS (256..4096)")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
@@ -253,25 +255,36 @@ def main():
     # through a server with one slot per instance of a batch; a slot freed by
     # a finished solve takes the next instance at the following round, so no
     # round waits for the slowest instance of its batch.
-    srv = sf.Server(ctx, max_n=4096, max_slots=args.slots, ydtype=sf.SFLS_C128,
-                    hbm_bytes=(4 << 30) * max(1, args.slots // 256), params=params, stream=stream)
+    streams = [stream] + [torch.cuda.Stream() for _ in range(args.servers - 1)]
+    srvs = [sf.Server(ctx, max_n=4096, max_slots=args.slots, ydtype=sf.SFLS_C128,
+                      hbm_bytes=(4 << 30) * max(1, args.slots // 256), params=params, stream=s)
+            for s in streams]
     yaddr = [y.data_ptr() + 16 * int(o) for o in off]
 
     def run_stream(nsteps):
-        # the next round is launched as soon as the previous one completes;
-        # collecting results and admitting new instances (which then join the
-        # round after) happen on the host while it runs
+        # the next round of a server is launched as soon as its previous one
+        # completes; collecting results and admitting new instances (which then
+        # join the round after) happen on the host while it runs
         total = nsteps * B
         nxt, got = 0, []
-        while nxt < total and srv.submit(yaddr[nxt % B], int(n[nxt % B]), nxt):
-            nxt += 1
-        srv.launch()
-        while len(got) < total:
-            srv.wait()
-            srv.launch()
-            got += srv.poll()
+        for srv in srvs:
             while nxt < total and srv.submit(yaddr[nxt % B], int(n[nxt % B]), nxt):
                 nxt += 1
+            srv.launch()
+        while len(got) < total:
+            for srv in srvs:
+                if len(srvs) > 1:
+                    ready, _ = srv.wait(block=False)
+                    if not ready:
+                        continue
+                else:
+                    srv.wait()
+                srv.launch()
+                got += srv.poll()
+                while nxt < total and srv.submit(yaddr[nxt % B], int(n[nxt % B]), nxt):
+                    nxt += 1
+                if not srv.in_flight:
+                    srv.launch()
         return got
 
     for w in range(args.warmup):
@@ -280,20 +293,21 @@ def main():
         log(f"warmup {w + 1}/{args.warmup} (continuous): {time.perf_counter() - t:.3f} s")
     ctx.reset_stats()
     ctx.set_timing(True)
-    r0 = srv.stats()["rounds"]
+    r0 = sum(s.stats()["rounds"] for s in srvs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     served = run_stream(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    rounds_c = srv.stats()["rounds"] - r0
+    rounds_c = sum(s.stats()["rounds"] for s in srvs) - r0
     solves = args.steps * B
     value = solves / elapsed
     lat_c = np.array([r.t_done - r.t_submit for r in served])
     log(f"continuous: {solves} solves in {elapsed:.3f} s over {rounds_c} rounds")
     for r in served:
         assert r.status in (sf.SFLS_OK, sf.SFLS_NOTCONV), r.status
-    srv.close()
+    for s in srvs:
+        s.close()
 
     # --- batch-synchronous sfls_estimate: one call per step of 256 instances
     for w in range(args.warmup):
@@ -417,7 +431,8 @@ def main():
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat_c, 50)),
                        "p99": 1e3 * float(np.percentile(lat_c, 99)),
                        "definition": "admission to completion of each solve, continuous batching"},
-        "continuous": {"rounds": rounds_c, "slots": args.slots, "solves": solves,
+        "continuous": {"rounds": rounds_c, "slots": args.slots, "servers": args.servers,
+                       "solves": solves,
                        "schur_lds_transform": args.schur_lds,
                        "solves_with_K_of_the_batch_call": same_K},
         "batch_sync": {"value": value_b, "unit": "solves/s", "ms_per_step": 1e3 * elapsed_b / args.steps,

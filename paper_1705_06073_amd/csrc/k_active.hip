@@ -454,10 +454,14 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
                          cd* ox, cd* cq, double* cs, int nblocks, int nmode, const cd* tws,
                          cd* scratch, int maxP, hipStream_t st) {
   if (!scratch) nmode = 1;  // no scratch for the NUFFT form: direct sums only
-  hipLaunchKernelGGL(k_item_scan, dim3(1), dim3(1024), 0, st, info, req, Keval, ncand, B, nmode,
-                     prefix);
-  hipLaunchKernelGGL(k_active, dim3(nblocks), dim3(ACT_NT), 0, st, info, req, Keval, prefix, B,
-                     theta, cand, w, rho, delta, coef, oq, orr, ou, os, ot, ov, ox, cq, cs);
+  // every instance has N <= P/2; with P <= 2 ACT_LDS_N throughout, the direct
+  // sums all run in k_active_lds and the item-parallel pair has nothing to do
+  if (maxP > 2 * ACT_LDS_N) {
+    hipLaunchKernelGGL(k_item_scan, dim3(1), dim3(1024), 0, st, info, req, Keval, ncand, B, nmode,
+                       prefix);
+    hipLaunchKernelGGL(k_active, dim3(nblocks), dim3(ACT_NT), 0, st, info, req, Keval, prefix, B,
+                       theta, cand, w, rho, delta, coef, oq, orr, ou, os, ot, ov, ox, cq, cs);
+  }
   {
     // N <= P/2 for every instance, so 2 * min(P, 2 ACT_LDS_N) / 2 points cover w and rho
     const int pl = maxP < 2 * ACT_LDS_N ? maxP : 2 * ACT_LDS_N;
