@@ -8,6 +8,14 @@ namespace sfls {
 
 constexpr int CONV_NT = 512;
 
+// W_P^m = exp(-j 2 pi m / P) evaluated from the exact fraction (m mod P) / P:
+// the points of a pointwise step need it at scattered m, where a table would
+// be gathered one cache line per lane
+__device__ __forceinline__ cd w_pow(int64_t m, int logP) {
+  const int64_t P = (int64_t)1 << logP;
+  return cconj(cis_frac(m & (P - 1), P));
+}
+
 // W_P^m = exp(-j 2 pi m / P) from the table tw[k] = exp(-j 2 pi k / 2^logtw), k < 2^(logtw-1)
 __device__ __forceinline__ cd tw_pow(const cd* __restrict__ tw, int logtw, int64_t m, int logP) {
   const int64_t P = (int64_t)1 << logP;
@@ -87,7 +95,7 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
     batched_for<4>(tid, CONV_NT, P, [&](int p) {
       const int f = bitrev(p, logP);
       const int pm = bitrev((P - f) & (P - 1), logP);
-      return cd3{tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), A[pm], Y[p]};
+      return cd3{w_pow((int64_t)f * (N - 1), logP), A[pm], Y[p]};
     }, [&](int p, cd3 g) { lds[pidx(p)] = cmul(cmul(g.a, g.b), g.c); });
     __syncthreads();
     dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
@@ -117,7 +125,7 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
     // (7) W = FFT(conj rho~) U - W^f A V
     batched_for<4>(tid, CONV_NT, P, [&](int p) {
       const int f = bitrev(p, logP);
-      return cd4{A[p], Y[p], tw_pow(tw, logtw, (int64_t)f * (N - 1), logP), tw_pow(tw, logtw, f, logP)};
+      return cd4{A[p], Y[p], w_pow((int64_t)f * (N - 1), logP), w_pow(f, logP)};
     }, [&](int p, cd4 g) {
       const cd t1 = cmul(cmul(g.c, cconj(g.a)), g.b);
       const cd t2 = cmul(cmul(g.d, g.a), lds[pidx(p)]);

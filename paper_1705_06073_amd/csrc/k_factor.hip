@@ -7,9 +7,15 @@ namespace sfls {
 
 // ---------------------------------------------------------------------------
 // a1.  c_i = beta [i = 0] + sum_k gamma_k exp(j 2 pi i theta_k)  (eq. py, first
-// column).  Grid: (tiles of 256 samples, instances).  theta/gamma of the
-// instance are staged through LDS in chunks of 256.
+// column).  Grid: (tiles of TC_SPT * 256 samples, instances); thread t takes
+// samples i0 + 256 s (s < TC_SPT) of its tile.  theta/gamma of the instance
+// are staged through LDS in chunks of 256 together with the rotation
+// exp(j 2 pi 256 theta_k), so that a thread evaluates one exact phase per
+// component (exact reduction of i0 theta mod 1) and rotates it to its other
+// samples (a few ulp from the exact phases).
 // ---------------------------------------------------------------------------
+constexpr int TC_SPT = 4;
+
 __global__ __launch_bounds__(256) void k_toeplitz_column(const InstInfo* __restrict__ info,
                                                          const int32_t* __restrict__ req,
                                                          const int32_t* __restrict__ Kcnt,
@@ -20,30 +26,47 @@ __global__ __launch_bounds__(256) void k_toeplitz_column(const InstInfo* __restr
   const int b = blockIdx.y;
   if (req && !(req[b] & REQ_EVAL)) return;
   const InstInfo in = info[b];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x * 256 >= in.N) return;
+  const int tile = blockIdx.x * 256 * TC_SPT;
+  if (tile >= in.N) return;
   const int K = Kcnt[b];
   if (use_nufft_col(nmode, in.N, in.P, K)) return;  // k_toeplitz_nufft writes it
   __shared__ double sth[256], sga[256];
-  cd acc{0.0, 0.0};
-  const double di = (double)i;
+  __shared__ cd srot[256];
+  const int i0 = tile + threadIdx.x;
+  cd acc[TC_SPT];
+#pragma unroll
+  for (int s = 0; s < TC_SPT; ++s) acc[s] = cd{0.0, 0.0};
+  const double di = (double)i0;
   for (int k0 = 0; k0 < K; k0 += 256) {
     __syncthreads();
     if (k0 + threadIdx.x < K) {
-      sth[threadIdx.x] = theta[in.koff + k0 + threadIdx.x];
+      const double th = theta[in.koff + k0 + threadIdx.x];
+      sth[threadIdx.x] = th;
       sga[threadIdx.x] = gamma[in.koff + k0 + threadIdx.x];
+      srot[threadIdx.x] = cis2pi(frac_mul(256.0, th));
     }
     __syncthreads();
     const int kn = min(256, K - k0);
     for (int k = 0; k < kn; ++k) {
       cd e = cis2pi(frac_mul(di, sth[k]));
-      acc.x = fma(sga[k], e.x, acc.x);
-      acc.y = fma(sga[k], e.y, acc.y);
+      const cd r = srot[k];
+      const double g = sga[k];
+#pragma unroll
+      for (int s = 0; s < TC_SPT; ++s) {
+        if (s > 0) e = cmul(e, r);
+        acc[s].x = fma(g, e.x, acc[s].x);
+        acc[s].y = fma(g, e.y, acc[s].y);
+      }
     }
   }
-  if (i < in.N) {
-    if (i == 0) { acc.x += beta[b]; acc.y = 0.0; }
-    c[in.off + i] = acc;
+#pragma unroll
+  for (int s = 0; s < TC_SPT; ++s) {
+    const int i = i0 + 256 * s;
+    if (i < in.N) {
+      cd v = acc[s];
+      if (i == 0) { v.x += beta[b]; v.y = 0.0; }
+      c[in.off + i] = v;
+    }
   }
 }
 
@@ -321,7 +344,7 @@ hipError_t launch_toeplitz_column(const InstInfo* info, const int32_t* req, cons
                                   cd* c, int B, int maxN, hipStream_t st, int nmode,
                                   const cd* tws, cd* scratch, int maxP) {
   if (!scratch || !tws || maxP <= CONV_LDS_P) nmode = 1;  // no room for the transform: direct
-  dim3 grid((maxN + 255) / 256, B);
+  dim3 grid((maxN + 256 * TC_SPT - 1) / (256 * TC_SPT), B);
   hipLaunchKernelGGL(k_toeplitz_column, grid, dim3(256), 0, st, info, req, Kcnt, theta, gamma,
                      beta, c, nmode);
   if (nmode != 1) {

@@ -7,7 +7,7 @@
 namespace sfls {
 
 constexpr int GRID_NT = 256;
-constexpr int SEL_NT = 256;
+constexpr int SEL_NT = 1024;
 constexpr int SEL_COLLECT = 2048;  // local minima gathered before sorting
 
 template <typename R> __device__ __forceinline__ R rinf();
