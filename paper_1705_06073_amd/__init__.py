@@ -225,7 +225,9 @@ class Context:
     """Owns one sfls_ctx on a HIP device."""
 
     def __init__(self, device: int = 0):
+        import weakref
         self._h = _P()
+        self._servers = weakref.WeakSet()  # servers on this context: closed before it
         st = lib().sfls_create(ctypes.byref(self._h), int(device))
         if st != SFLS_OK:
             raise SflsError(st, lib().sfls_strerror(st).decode())
@@ -274,6 +276,8 @@ class Context:
 
     def close(self):
         if self._h:
+            for s in list(self._servers):
+                s.close()
             lib().sfls_destroy(self._h)
             self._h = _P()
 
@@ -444,6 +448,7 @@ class Server:
         pp = ctypes.byref(params) if params is not None else None
         ctx.check(lib().sfls_server_create(ctx.handle, ctypes.byref(cfg), pp,
                                            ctypes.byref(self._h)))
+        ctx._servers.add(self)
         self._res = (sfls_result * 4096)()
         self._cap = 1 << 16
         self._th = np.zeros(self._cap)

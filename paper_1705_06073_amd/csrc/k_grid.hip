@@ -7,6 +7,7 @@
 namespace sfls {
 
 constexpr int GRID_NT = 256;
+constexpr int GRID_ANCHOR = 4;  // points per thread between exact residue twiddles
 constexpr int SEL_NT = 1024;
 constexpr int SEL_COLLECT = 2048;  // local minima gathered before sorting
 
@@ -76,20 +77,25 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
   load_tw_head<GRID_NT>(s_tw, tw);
   const cd* wb = w + in.off;
   const cd* ob = oms + in.poff;
-  for (int m = tid; m < M; m += GRID_NT) {
+  // M >= N: the residue twiddles exp(j 2 pi m r / L) of a thread's points m =
+  // tid + GRID_NT j come from an exact fraction every GRID_ANCHOR-th point and
+  // rotations by exp(j 2 pi GRID_NT r / L) in between; the lag m - M takes the
+  // same twiddle times exp(-j 2 pi M r / L)
+  const cd rotg = cis_frac(((int64_t)GRID_NT * r) % L, L);
+  const cd cM = cconj(cis_frac(((int64_t)M * r) % L, L));
+  cd e{1.0, 0.0};
+  int jt = 0;
+  for (int m = tid; m < M; m += GRID_NT, ++jt) {
     cd qv{0.0, 0.0}, sv{0.0, 0.0};
     if (M >= N) {
       // one sample and at most two lags (m and m - M) per point
+      e = (jt % GRID_ANCHOR == 0) ? cis_frac(((int64_t)m * r) % L, L) : cmul(e, rotg);
       if (m < N) {
-        const cd e = cis_frac(((int64_t)m * r) % L, L);
         qv = cmul(wb[m], cconj(e));
         sv = cmul(ob[m], e);
       }
       const int i2 = m - M;
-      if (i2 > -N) {
-        const int64_t ph = (((int64_t)i2 % L + L) % L) * r % L;
-        sv = cfma(ob[(i2 + P) & (P - 1)], cis_frac(ph, L), sv);
-      }
+      if (i2 > -N) sv = cfma(ob[(i2 + P) & (P - 1)], cmul(e, cM), sv);
     } else {
       for (int n = m; n < N; n += M) qv = cfma(wb[n], cconj(cis_frac(((int64_t)n * r) % L, L)), qv);
       // lags i = m mod M in (-N, N), from the most negative one up
