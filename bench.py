@@ -156,6 +156,86 @@ def serve_leg(rate, seconds, prec, single_n=None):
     return summ
 
 
+UNEVEN_CLASSES = ((1024, 1024), (4096, 1024), (16384, 1024))
+UNEVEN_HBM = (4 << 30, 16 << 30, 64 << 30)
+
+
+def uneven_leg(prec, count=2048):
+    """The uneven batch: `count` instances with N log-uniform on [128, 16384],
+    K ~ Poisson(N/64), SNR ~ U[5,30] dB, complex128, grid 8N; solved (a) by one
+    sfls_estimate call for the whole batch and (b) by continuous batching
+    through one server per size class (every instance admitted at t = 0)."""
+    import numpy as np
+    import torch
+    import paper_1705_06073_amd as sf
+    from paper_1705_06073_amd import serving, synth
+
+    log(f"uneven batch: generating {count} instances")
+    insts = [synth.workload_uneven(i, blocked=True) for i in range(count)]
+    n = np.array([i.N for i in insts], np.int64)
+    off = np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+    y = torch.from_numpy(np.concatenate([i.y.astype(np.complex128) for i in insts])
+                         .view(np.float64).copy()).to("cuda:0")
+    ctx = sf.Context(0)
+    params = sf.default_params(precision=prec)
+    out = {}
+    # (a) one call
+    B = count
+    kcap = n.copy()  # K_max = N, as the servers' default capacity
+    koff = np.concatenate([[0], np.cumsum(kcap)[:-1]]).astype(np.int64)
+    KT = int(kcap.sum())
+    f64 = dict(dtype=torch.float64, device="cuda:0")
+    i32 = dict(dtype=torch.int32, device="cuda:0")
+    o = dict(K=torch.zeros(B, dtype=torch.int64, device="cuda:0"), theta=torch.zeros(KT, **f64),
+             alpha=torch.zeros(2 * KT, **f64), gamma=torch.zeros(KT, **f64),
+             beta=torch.zeros(B, **f64), zeta=torch.zeros(B, **f64),
+             objective=torch.zeros(B, **f64), iters=torch.zeros(B, **i32),
+             evals=torch.zeros(B, **i32), status=torch.zeros(B, **i32))
+    stream = torch.cuda.current_stream()
+
+    def call():
+        sf.sfls_estimate(ctx, n, off, y, sf.SFLS_C128, params, kcap, koff, o["K"], o["theta"],
+                         o["alpha"], o["gamma"], o["beta"], o["zeta"], o["objective"],
+                         o["iters"], o["evals"], o["status"], stream=stream)
+        torch.cuda.synchronize()
+
+    call()  # warm-up
+    t = time.perf_counter()
+    call()
+    ta = time.perf_counter() - t
+    run, _ = ctx.last_run()
+    st = o["status"].cpu().numpy()
+    Ka = o["K"].cpu().numpy()
+    out["one_call"] = {"value": B / ta, "unit": "solves/s", "seconds": ta, "rounds": run["rounds"],
+                       "evals_mean": run["evals"] / B,
+                       "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}}
+    log(f"uneven batch, one call: {B / ta:.1f} solves/s ({run['rounds']} rounds)")
+    # (b) size-class servers
+    lanes = serving.default_lanes(ctx, params, size_classes=UNEVEN_CLASSES, hbm_bytes=UNEVEN_HBM,
+                                  ydtype=sf.SFLS_C128)
+    lane_of = [serving.lane_index(UNEVEN_CLASSES, int(v)) for v in n]
+    base = y.data_ptr()
+    arrivals = np.zeros(B)
+    res, lat, stt = serving.run_stream(lanes, lane_of, arrivals, n, lambda i: base + 16 * int(off[i]))
+    tb = stt["wall_s"]
+    Kb = np.array([r.K for r in res])
+    out["size_class_servers"] = {
+        "value": B / tb, "unit": "solves/s", "seconds": tb,
+        "lanes": [{"max_n": mx, "slots": sl, "rounds": ls["rounds"]}
+                  for (mx, sl), ls in zip(UNEVEN_CLASSES, stt["lanes"])],
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p99": float(np.percentile(lat, 99) * 1e3)}}
+    log(f"uneven batch, size-class servers: {B / tb:.1f} solves/s")
+    out["workload"] = (f"{B} instances, N log-uniform on [128, 16384] (mean {n.mean():.0f}), "
+                       "K ~ Poisson(N/64), separation 1/N, alpha ~ CN(0,1), SNR ~ U[5,30] dB, "
+                       "complex128, grid 8N")
+    out["K_equal_between_the_two"] = int(np.sum(Ka == Kb))
+    for s in lanes:
+        s.close()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +268,8 @@ def main():
     ap.add_argument("--serve4096-rate", type=float, default=2000.0)
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving stream and print its summary")
+    ap.add_argument("--uneven", action="store_true",
+                    help="run only the uneven batch (2048 instances, N in [128, 16384])")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -212,6 +294,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_bytes, "copies": 3}))
+        return
+    if args.uneven:
+        prec = sf.SFLS_MIXED if args.precision == "mixed" else sf.SFLS_FP64
+        print(json.dumps({"uneven": uneven_leg(prec)}), flush=True)
         return
     if args.serve_only:
         prec = sf.SFLS_MIXED if args.precision == "mixed" else sf.SFLS_FP64

@@ -181,14 +181,15 @@ def workload_n4096(instance: int) -> Instance:
     return make_instance(rng, 4096, K, 1.0 / 4096, "cn", snr, np.complex128, s)
 
 
-def workload_uneven(instance: int) -> Instance:
-    """N log-uniform on [128, 16384], K ~ Poisson(N/64), SNR ~ U[5,30] dB."""
+def workload_uneven(instance: int, blocked: bool = False) -> Instance:
+    """N log-uniform on [128, 16384], K ~ Poisson(N/64), SNR ~ U[5,30] dB
+    (blocked: the phase-split synthesis, for many long signals)."""
     s = seed_for(3, instance)
     rng = np.random.Generator(np.random.PCG64(s))
     N = int(round(math.exp(rng.uniform(math.log(128), math.log(16384)))))
     K = int(rng.poisson(N / 64.0))
     snr = float(rng.uniform(5.0, 30.0))
-    return make_instance(rng, N, K, 1.0 / N, "cn", snr, np.complex128, s)
+    return make_instance(rng, N, K, 1.0 / N, "cn", snr, np.complex128, s, blocked=blocked)
 
 
 SERVING_SIZES = (256, 1024, 4096, 16384, 65536)
