@@ -3,6 +3,7 @@
 // in the kernels of k_*.hip; this file only moves sizes and pointers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -77,6 +78,15 @@ sfls_status upload(sfls_ctx* ctx, const char* name, const std::vector<T>& v, hip
     HIP_TRY(hipStreamSynchronize(st));
   }
   return SFLS_OK;
+}
+
+std::vector<int32_t> longest_first(int64_t B, const int64_t* n) {
+  std::vector<int32_t> o;
+  if (B < 2 || std::all_of(n, n + B, [&](int64_t v) { return v == n[0]; })) return o;
+  o.resize((size_t)B);
+  for (int64_t b = 0; b < B; ++b) o[(size_t)b] = (int32_t)b;
+  std::stable_sort(o.begin(), o.end(), [&](int32_t a, int32_t b) { return n[a] > n[b]; });
+  return o;
 }
 
 int ilog2_ceil(int64_t v) {
@@ -323,10 +333,10 @@ static sfls_status run_recursion(sfls_ctx* ctx, int64_t B, const InstInfo* dinfo
                                  const int32_t* req, const cd* c, cd* rho, double* delta,
                                  double* logdet, int32_t* status, int64_t* failed, int maxN,
                                  hipStream_t st, const SchurLayout* dlay, const SchurAct* dacts,
-                                 cd* sscr, int Fmax) {
+                                 cd* sscr, int Fmax, const int32_t* order = nullptr) {
   if (dlay) {
     HIP_TRY(launch_schur(dinfo, req, dlay, dacts, c, ctx->tw64, ctx->logtw, ctx->tws64, sscr, rho,
-                         delta, logdet, status, failed, (int)B, Fmax, st));
+                         delta, logdet, status, failed, (int)B, Fmax, st, order));
   } else {
     HIP_TRY(launch_levinson(dinfo, req, c, rho, delta, logdet, status, failed, (int)B, maxN, st));
   }
@@ -335,10 +345,11 @@ static sfls_status run_recursion(sfls_ctx* ctx, int64_t B, const InstInfo* dinfo
 
 static sfls_status run_refine(sfls_ctx* ctx, int64_t B, const InstInfo* dinfo, const int32_t* req,
                               const cd* c, cd* rho, double* delta, int32_t* status,
-                              hipStream_t st, const SchurLayout* dlay, const RefineBufs& rf) {
+                              hipStream_t st, const SchurLayout* dlay, const RefineBufs& rf,
+                              const int32_t* order = nullptr) {
   if (dlay)
     HIP_TRY(launch_gen_refine(dinfo, req, status, c, rho, delta, ctx->tw64, ctx->logtw,
-                              ctx->tws64, rf.scratch, rf.r, rf.dx, (int)B, rf.maxP, st));
+                              ctx->tws64, rf.scratch, rf.r, rf.dx, (int)B, rf.maxP, st, order));
   return SFLS_OK;
 }
 
@@ -854,6 +865,10 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   if ((s = upload(ctx, "e_coef", coef, st, &dcoef)) != SFLS_OK) return s;
   if ((s = upload(ctx, "e_prm", dpv, st, &dprm)) != SFLS_OK) return s;
   if ((s = upload(ctx, "e_okoff", okoff, st, &dokoff)) != SFLS_OK) return s;
+  // a batch of uneven sizes starts its longest instances first
+  int32_t* dorder = nullptr;
+  const std::vector<int32_t> order = longest_first(B, n);
+  if (!order.empty() && (s = upload(ctx, "e_order", order, st, &dorder)) != SFLS_OK) return s;
 
   const int J = p.lbfgs_J;
   const size_t esz = p.precision == SFLS_FP64 ? sizeof(double) : sizeof(float);
@@ -1025,12 +1040,12 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
       HIP_TRY(tstop(KID_GEN));
       HIP_TRY(tstart(KID_FACTOR));
       if ((s = run_recursion(ctx, B, dinfo, P.req, c, rho, delta, logdet, lev_status, failed,
-                             sz.maxN, st, slay, sacts, sscr, sFmax)) != SFLS_OK)
+                             sz.maxN, st, slay, sacts, sscr, sFmax, dorder)) != SFLS_OK)
         return s;
       HIP_TRY(tstop(KID_FACTOR));
       HIP_TRY(tstart(KID_REFINE));
-      if ((s = run_refine(ctx, B, dinfo, P.req, c, rho, delta, lev_status, st, slay, rf)) !=
-          SFLS_OK)
+      if ((s = run_refine(ctx, B, dinfo, P.req, c, rho, delta, lev_status, st, slay, rf,
+                          dorder)) != SFLS_OK)
         return s;
       // ln|C| over the active set (determinant lemma) where it is small enough
       HIP_TRY(launch_logdet_lemma(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, lev_status,
@@ -1038,13 +1053,13 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
       HIP_TRY(tstop(KID_REFINE));
       HIP_TRY(tstart(KID_APPLY));
       HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw,
-                              ctx->tws64, scratch, w, yCy, ww, (int)B, sz.maxP, st));
+                              ctx->tws64, scratch, w, yCy, ww, (int)B, sz.maxP, st, dorder));
       HIP_TRY(tstop(KID_APPLY));
     }
     if (ngrid > 0) {
       HIP_TRY(tstart(KID_OMEGA));
       HIP_TRY(launch_omega(dinfo, P.req, rho, delta, dcoef, ctx->tws64, scratch, 1, 1,
-                           oms, nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st));
+                           oms, nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st, dorder));
       HIP_TRY(tstop(KID_OMEGA));
       HIP_TRY(tstart(KID_GRID));
       HIP_TRY(launch_grid(prec, dinfo, P.req, w, oms, P.gbar_e, P.zeta_e, tw, ctx->logtw,

@@ -58,6 +58,9 @@ sfls_status fail(sfls_ctx* ctx, sfls_status s, const char* fmt, ...);
   } while (0)
 
 int ilog2_ceil(int64_t v);
+// Dispatch order of a batch whose sizes differ: instance indices by
+// decreasing N (stable); empty when every N is equal (identity order).
+std::vector<int32_t> longest_first(int64_t B, const int64_t* n);
 // Wait for an event by polling it: a blocking wait can leave the device idle
 // for a scheduler wake-up between rounds, which sets the pace of the round
 // loops (one host decision per round).

@@ -57,8 +57,9 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
                                                       const cd* __restrict__ tws,
                                                       cd* __restrict__ scratch, cd* __restrict__ w,
                                                       double* __restrict__ yCy,
-                                                      double* __restrict__ ww) {
-  const int bi = blockIdx.x;
+                                                      double* __restrict__ ww,
+                                                      const int32_t* __restrict__ order) {
+  const int bi = order ? order[blockIdx.x] : blockIdx.x;
   if (req && !(req[bi] & REQ_EVAL)) return;
   const InstInfo in = info[bi];
   const int N = in.N, P = in.P, logP = in.logP;
@@ -174,8 +175,9 @@ __global__ __launch_bounds__(CONV_NT) void k_omega(const InstInfo* __restrict__ 
                                                    int have_g0,
                                                    cd* __restrict__ oms, cd* __restrict__ o_s,
                                                    cd* __restrict__ o_t, cd* __restrict__ o_v,
-                                                   cd* __restrict__ o_x) {
-  const int bi = blockIdx.x;
+                                                   cd* __restrict__ o_x,
+                                                   const int32_t* __restrict__ order) {
+  const int bi = order ? order[blockIdx.x] : blockIdx.x;
   if (req && !(req[bi] & REQ_GRID)) return;
   const InstInfo in = info[bi];
   const int N = in.N, P = in.P, logP = in.logP;
@@ -277,8 +279,9 @@ __global__ __launch_bounds__(CONV_NT) void k_gen_residual(const InstInfo* __rest
                                                           const double* __restrict__ delta,
                                                           const cd* __restrict__ tws,
                                                           cd* __restrict__ scratch,
-                                                          cd* __restrict__ r) {
-  const int bi = blockIdx.x;
+                                                          cd* __restrict__ r,
+                                                          const int32_t* __restrict__ order) {
+  const int bi = order ? order[blockIdx.x] : blockIdx.x;
   if (req && !(req[bi] & REQ_EVAL)) return;
   if (status && status[bi] != 0) return;
   const InstInfo in = info[bi];
@@ -357,16 +360,16 @@ __global__ __launch_bounds__(CONV_NT) void k_gen_update(const InstInfo* __restri
 hipError_t launch_gen_refine(const InstInfo* info, const int32_t* req, const int32_t* status,
                              const cd* c, cd* rho, double* delta, const cd* tw, int logtw,
                              const cd* tws, cd* scratch, cd* r, cd* dx, int B, int maxP,
-                             hipStream_t st) {
+                             hipStream_t st, const int32_t* order) {
   const size_t shm = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);
   (void)hipFuncSetAttribute((const void*)k_gen_residual,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL(k_gen_residual, dim3(B), dim3(CONV_NT), shm, st, info, req, status, c, rho,
-                     delta, tws, scratch, r);
+                     delta, tws, scratch, r, order);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = launch_gs_apply(info, req, r, 1, rho, delta, tw, logtw, tws, scratch, dx, nullptr, nullptr,
-                      B, maxP, st);
+                      B, maxP, st, order);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gen_update, dim3(B), dim3(CONV_NT), 0, st, info, req, status, rho, delta,
                      dx);
@@ -376,18 +379,18 @@ hipError_t launch_gen_refine(const InstInfo* info, const int32_t* req, const int
 hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void* y, int ydtype,
                            const cd* rho, const double* delta, const cd* tw, int logtw,
                            const cd* tws, cd* scratch, cd* w, double* yCy, double* ww, int B, int maxP,
-                           hipStream_t st) {
+                           hipStream_t st, const int32_t* order) {
   const size_t shm = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);
   if (ydtype == 1) {
     (void)hipFuncSetAttribute((const void*)k_gs_apply<cd>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)shm);
     hipLaunchKernelGGL(k_gs_apply<cd>, dim3(B), dim3(CONV_NT), shm, st, info, req, (const cd*)y,
-                       rho, delta, tw, logtw, tws, scratch, w, yCy, ww);
+                       rho, delta, tw, logtw, tws, scratch, w, yCy, ww, order);
   } else {
     (void)hipFuncSetAttribute((const void*)k_gs_apply<cf>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)shm);
     hipLaunchKernelGGL(k_gs_apply<cf>, dim3(B), dim3(CONV_NT), shm, st, info, req, (const cf*)y,
-                       rho, delta, tw, logtw, tws, scratch, w, yCy, ww);
+                       rho, delta, tw, logtw, tws, scratch, w, yCy, ww, order);
   }
   return hipGetLastError();
 }
@@ -395,11 +398,12 @@ hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void*
 hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
                         const double* delta, const SepCoef* coef, const cd* tws,
                         cd* scratch, int which, int have_g0, cd* oms, cd* o_s, cd* o_t,
-                        cd* o_v, cd* o_x, int B, int maxP, hipStream_t st) {
+                        cd* o_v, cd* o_x, int B, int maxP, hipStream_t st,
+                        const int32_t* order) {
   const size_t shm = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);
   (void)hipFuncSetAttribute((const void*)k_omega, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   hipLaunchKernelGGL(k_omega, dim3(B), dim3(CONV_NT), shm, st, info, req, rho, delta, coef, tws,
-                     scratch, which, have_g0, oms, o_s, o_t, o_v, o_x);
+                     scratch, which, have_g0, oms, o_s, o_t, o_v, o_x, order);
   return hipGetLastError();
 }
 

@@ -70,6 +70,10 @@ hipError_t launch_toeplitz_column(const InstInfo* info, const int32_t* req, cons
                                   const double* theta, const double* gamma, const double* beta,
                                   cd* c, int B, int maxN, hipStream_t st, int nmode = 1,
                                   const cd* tws = nullptr, cd* scratch = nullptr, int maxP = 0);
+// `order` (optional, B entries): the instance each workgroup of the launch
+// takes, so that a batch of uneven sizes starts its longest instances first
+// (identity when null).  Taken by the per-instance kernels whose time grows
+// with N: the recursion, the GS apply and refinement, and the omega sums.
 hipError_t launch_levinson(const InstInfo* info, const int32_t* req, const cd* c, cd* rho,
                            double* delta, double* logdet, int32_t* status, int64_t* failed, int B,
                            int maxN, hipStream_t st);
@@ -77,16 +81,16 @@ hipError_t launch_schur(const InstInfo* info, const int32_t* req, const SchurLay
                         const SchurAct* acts, const cd* c, const cd* tw, int logtw,
                         const cd* tws, cd* scratch,
                         cd* rho, double* delta, double* logdet, int32_t* status, int64_t* failed,
-                        int B, int Fmax, hipStream_t st);
+                        int B, int Fmax, hipStream_t st, const int32_t* order = nullptr);
 hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void* y, int ydtype,
                            const cd* rho, const double* delta, const cd* tw, int logtw,
                            const cd* tws, cd* scratch, cd* w, double* yCy, double* ww, int B,
                            int maxP,
-                           hipStream_t st);
+                           hipStream_t st, const int32_t* order = nullptr);
 hipError_t launch_gen_refine(const InstInfo* info, const int32_t* req, const int32_t* status,
                              const cd* c, cd* rho, double* delta, const cd* tw, int logtw,
                              const cd* tws, cd* scratch, cd* r, cd* dx, int B, int maxP,
-                             hipStream_t st);
+                             hipStream_t st, const int32_t* order = nullptr);
 hipError_t launch_logdet_lemma(const InstInfo* info, const int32_t* req, const int32_t* Kev,
                                const double* theta, const double* gamma,
                                const double* beta, const int32_t* status, double* logdet, int B,
@@ -94,7 +98,8 @@ hipError_t launch_logdet_lemma(const InstInfo* info, const int32_t* req, const i
 hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
                         const double* delta, const SepCoef* coef, const cd* tws,
                         cd* scratch, int which, int have_g0, cd* oms, cd* o_s, cd* o_t,
-                        cd* o_v, cd* o_x, int B, int maxP, hipStream_t st);
+                        cd* o_v, cd* o_x, int B, int maxP, hipStream_t st,
+                        const int32_t* order = nullptr);
 hipError_t launch_grid(int prec, const InstInfo* info, const int32_t* req, const cd* w,
                        const cd* oms, const double* gbar, const double* zeta, const void* tw,
                        int logtw, int Rmax, int B, int maxM, void* qG, void* sG, void* dL,

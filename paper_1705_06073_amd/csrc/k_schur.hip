@@ -214,8 +214,9 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
                                                   double* __restrict__ delta_out,
                                                   double* __restrict__ logdet,
                                                   int32_t* __restrict__ status,
-                                                  int64_t* __restrict__ failed) {
-  const int bi = blockIdx.x;
+                                                  int64_t* __restrict__ failed,
+                                                  const int32_t* __restrict__ order) {
+  const int bi = order ? order[blockIdx.x] : blockIdx.x;
   if (req && !(req[bi] & REQ_EVAL)) return;
   const InstInfo in = info[bi];
   const SchurLayout& L = lay[bi];  // read through uniform addresses (scalar loads)
@@ -638,12 +639,12 @@ hipError_t launch_schur(const InstInfo* info, const int32_t* req, const SchurLay
                         const SchurAct* acts, const cd* c, const cd* tw, int logtw,
                         const cd* tws, cd* scratch,
                         cd* rho, double* delta, double* logdet, int32_t* status, int64_t* failed,
-                        int B, int Fmax, hipStream_t st) {
+                        int B, int Fmax, hipStream_t st, const int32_t* order) {
   const size_t shm = 2 * (size_t)padded(Fmax) * sizeof(cd);
   (void)hipFuncSetAttribute((const void*)k_schur, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)shm);
   hipLaunchKernelGGL(k_schur, dim3(B), dim3(SCH_NT), shm, st, info, req, lay, acts, c, tw, logtw,
-                     tws, scratch, rho, delta, logdet, status, failed);
+                     tws, scratch, rho, delta, logdet, status, failed, order);
   return hipGetLastError();
 }
 

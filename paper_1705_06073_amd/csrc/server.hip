@@ -209,6 +209,7 @@ struct sfls_server {
   int64_t* h_koff = nullptr;
   int32_t* h_req = nullptr;
   int32_t* h_list = nullptr;
+  int32_t* h_order = nullptr;    // dispatch order of the round (lanes of uneven sizes)
   int32_t* h_newlist = nullptr;  // [2][S]: admitted since the last launch, by buffer
   AdmitRec* h_adm = nullptr;     // [2][S]
   int abuf = 0;                  // buffer that submissions fill; a launch takes it and flips
@@ -220,6 +221,7 @@ struct sfls_server {
   // device addresses of the pinned buffers the kernels read or write directly
   int32_t* m_req = nullptr;
   int32_t* m_newlist = nullptr;
+  int32_t* m_order = nullptr;
   AdmitRec* m_adm = nullptr;
   InstInfo* m_info = nullptr;
   SepCoef* m_coef = nullptr;
@@ -530,7 +532,7 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
 #define HA(ptr, cnt) ok = ok && halloc(&(ptr), (size_t)(cnt), H) == hipSuccess
   HA(s->h_info, S); HA(s->h_coef, S); HA(s->h_lay, S); HA(s->h_koff, S); HA(s->h_req, S);
   HA(s->h_list, S); HA(s->h_newlist, 2 * S); HA(s->h_adm, 2 * S); HA(s->h_doff, S);
-  HA(s->h_gkoff, S); HA(s->h_res, S);
+  HA(s->h_gkoff, S); HA(s->h_res, S); HA(s->h_order, S);
 #undef HA
   if (!ok) return bail(fail(ctx, SFLS_ENOMEM, "pinned host mirrors"));
   std::memset(s->h_req, 0, (size_t)S * sizeof(int32_t));
@@ -544,7 +546,8 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
       hipHostGetDevicePointer((void**)&s->m_list, s->h_list, 0) != hipSuccess ||
       hipHostGetDevicePointer((void**)&s->m_doff, s->h_doff, 0) != hipSuccess ||
       hipHostGetDevicePointer((void**)&s->m_gkoff, s->h_gkoff, 0) != hipSuccess ||
-      hipHostGetDevicePointer((void**)&s->m_res, s->h_res, 0) != hipSuccess)
+      hipHostGetDevicePointer((void**)&s->m_res, s->h_res, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_order, s->h_order, 0) != hipSuccess)
     return bail(fail(ctx, SFLS_EDEVICE, "device addresses of the pinned mirrors"));
   P.ev_q = s->evq; P.ev_r = s->evr; P.ev_u = s->evu; P.ev_s = s->evs; P.ev_t = s->evt;
   P.ev_v = s->evv; P.ev_x = s->evx; P.logdet = s->logdet; P.yCy = s->yCy; P.ww = s->ww;
@@ -701,7 +704,7 @@ sfls_status sfls_server_launch(sfls_server* s) {
     s->admitted.clear();
   }
   // sizes of this round's launches, over the requests that asked for work
-  int maxN = 0, maxP = 0, maxM = 0, Rr = 1;
+  int maxN = 0, maxP = 0, maxM = 0, Rr = 1, lo_n = 1 << 30, hi_n = 0;
   bool any_eval = false, any_grid = false, any_req = false;
   for (int b = 0; b < B; ++b) {
     const int32_t rq = s->h_req[b];
@@ -709,6 +712,8 @@ sfls_status sfls_server_launch(sfls_server* s) {
     const InstInfo& in = s->h_info[b];
     any_req = true;
     maxP = std::max(maxP, in.P);
+    lo_n = std::min(lo_n, in.N);
+    hi_n = std::max(hi_n, in.N);
     if (rq & REQ_EVAL) {
       any_eval = true;
       maxN = std::max(maxN, in.N);
@@ -718,6 +723,19 @@ sfls_status sfls_server_launch(sfls_server* s) {
       maxM = std::max(maxM, in.M);
       Rr = std::max(Rr, in.R);
     }
+  }
+  // requests of different sizes: the per-instance kernels whose time grows
+  // with N take the slots longest first (slots without work last).  The
+  // previous round has completed, so its table is free to rewrite.
+  const int32_t* dorder = nullptr;
+  if (any_req && lo_n != hi_n) {
+    int32_t* o = s->h_order;
+    for (int b = 0; b < B; ++b) o[b] = b;
+    auto key = [&](int32_t b) {
+      return (s->h_req[b] && s->slots[(size_t)b].state == SLOT_RUNNING) ? s->h_info[b].N : 0;
+    };
+    std::stable_sort(o, o + B, [&](int32_t a, int32_t b) { return key(a) > key(b); });
+    dorder = s->m_order;
   }
   DrvPools& P = s->P;
   const int prec = s->prm.precision;
@@ -763,7 +781,7 @@ sfls_status sfls_server_launch(sfls_server* s) {
     if (s->schur) {
       HIP_TRY(launch_schur(s->dinfo, P.req, s->dlay, s->dacts, s->c, ctx->tw64, ctx->logtw,
                            ctx->tws64, s->sscr, s->rho, s->delta, s->logdet, s->lev_status,
-                           s->failed, B, s->Fmax, st));
+                           s->failed, B, s->Fmax, st, dorder));
     } else {
       HIP_TRY(launch_levinson(s->dinfo, P.req, s->c, s->rho, s->delta, s->logdet, s->lev_status,
                               s->failed, B, (int)s->cfg.max_n, st));
@@ -772,13 +790,15 @@ sfls_status sfls_server_launch(sfls_server* s) {
     HIP_TRY(tstart(KID_REFINE));
     if (s->schur)
       HIP_TRY(launch_gen_refine(s->dinfo, P.req, s->lev_status, s->c, s->rho, s->delta, ctx->tw64,
-                                ctx->logtw, ctx->tws64, s->scratch, s->rf_r, s->rf_dx, B, maxP, st));
+                                ctx->logtw, ctx->tws64, s->scratch, s->rf_r, s->rf_dx, B, maxP, st,
+                                dorder));
     HIP_TRY(launch_logdet_lemma(s->dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, s->lev_status,
                                 s->logdet, B, st));
     HIP_TRY(tstop(KID_REFINE));
     HIP_TRY(tstart(KID_APPLY));
     HIP_TRY(launch_gs_apply(s->dinfo, P.req, s->ypool, s->cfg.ydtype, s->rho, s->delta, ctx->tw64,
-                            ctx->logtw, ctx->tws64, s->scratch, s->w, s->yCy, s->ww, B, maxP, st));
+                            ctx->logtw, ctx->tws64, s->scratch, s->w, s->yCy, s->ww, B, maxP, st,
+                            dorder));
     HIP_TRY(tstop(KID_APPLY));
   }
   if (any_grid) {
@@ -786,7 +806,7 @@ sfls_status sfls_server_launch(sfls_server* s) {
     const double slack = prec == SFLS_FP64 ? 1e-9 : 1e-3;
     HIP_TRY(tstart(KID_OMEGA));
     HIP_TRY(launch_omega(s->dinfo, P.req, s->rho, s->delta, s->dcoef, ctx->tws64, s->scratch, 1, 1,
-                         s->oms, nullptr, nullptr, nullptr, nullptr, B, maxP, st));
+                         s->oms, nullptr, nullptr, nullptr, nullptr, B, maxP, st, dorder));
     HIP_TRY(tstop(KID_OMEGA));
     HIP_TRY(tstart(KID_GRID));
     HIP_TRY(launch_grid(prec, s->dinfo, P.req, s->w, s->oms, P.gbar_e, P.zeta_e, tw, ctx->logtw, Rr,

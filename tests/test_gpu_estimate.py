@@ -94,6 +94,23 @@ def test_batch_results_equal_single_runs(ctx):
         assert np.array_equal(rb.theta, rs.theta) and rb.beta == rs.beta
 
 
+def test_uneven_batch_results_equal_single_runs(ctx):
+    """A batch of uneven N in the superfast range runs its instances longest
+    first; each instance's result is still bitwise the one it gets alone."""
+    ns = [300, 2000, 512, 5000, 260, 2000]
+    insts = [synth.workload_paper_snr(10 + i, 15.0, N=n, K=max(2, n // 100))
+             for i, n in enumerate(ns)]
+    ys = [i.y.astype(np.complex128) for i in insts]
+    p = sf.default_params(precision=sf.SFLS_MIXED)
+    batch = sf.estimate_batch(ctx, ys, p)
+    for k, (y, rb) in enumerate(zip(ys, batch)):
+        rs = sf.estimate_batch(ctx, [y], p)[0]
+        print(f"instance {k}: N={len(y)} K={rb.K} evals={rb.evaluations}", flush=True)
+        assert rb.status == rs.status and rb.K == rs.K and rb.iterations == rs.iterations
+        assert np.array_equal(rb.theta, rs.theta) and np.array_equal(rb.alpha, rs.alpha)
+        assert rb.beta == rs.beta and rb.objective == rs.objective
+
+
 def test_paper_snr_workload_statistics(ctx):
     """The GPU estimator reproduces the Fig. snr Superfast LSE block success rate at
     20 dB (0.998 over 500 trials in the paper) on a 64-trial batch."""
