@@ -917,6 +917,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   WS("e_am", (size_t)J * B, P.am);
   WS("e_Ke", B, P.K_e);
   WS("e_req", B, P.req);
+  WS("e_req2", B, P.req2);
   WS("e_beta_e", B, P.beta_e);
   WS("e_gbar_e", B, P.gbar_e);
   WS("e_zeta_e", B, P.zeta_e);
@@ -960,21 +961,24 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   const double slack = prec == SFLS_FP64 ? 1e-9 : 1e-3;
   const int act_blocks = 2048;
 
-  // pinned host copy of the request bits, read back after every driver call
+  // pinned host copies of the request bits (req, then the second-stage
+  // grid requests req2), read back after every round
   if (ctx->host_req_n < B) {
     if (ctx->host_req) (void)hipHostFree(ctx->host_req);
     ctx->host_req = nullptr;
     ctx->host_req_n = 0;
-    if (hipHostMalloc(&ctx->host_req, (size_t)B * sizeof(int32_t),
+    if (hipHostMalloc(&ctx->host_req, 2 * (size_t)B * sizeof(int32_t),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
       return fail(ctx, SFLS_ENOMEM, "pinned request buffer");
     ctx->host_req_n = B;
   }
   int32_t* hreq = ctx->host_req;
+  int32_t* hreq2 = hreq + B;
   // the driver writes the request bits into this pinned buffer directly
   int32_t* hreq_dev = nullptr;
   HIP_TRY(hipHostGetDevicePointer((void**)&hreq_dev, hreq, 0));
   P.req_host = hreq_dev;
+  P.req2_host = hreq_dev + B;
   const auto t0 = std::chrono::steady_clock::now();
   auto now_s = [&]() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -991,9 +995,21 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   auto tstop = [&](int k) -> hipError_t {
     return timing ? hipEventRecord(ctx->ev[2 * k + 1], st) : hipSuccess;
   };
+  // the second stage of a round (grid sweeps at the point just evaluated)
+  bool launched2[KID_COUNT];
+  const int E2 = 2 * KID_COUNT;
+  auto tstart2 = [&](int k) -> hipError_t {
+    launched2[k] = true;
+    return timing ? hipEventRecord(ctx->ev[E2 + 2 * k], st) : hipSuccess;
+  };
+  auto tstop2 = [&](int k) -> hipError_t {
+    return timing ? hipEventRecord(ctx->ev[E2 + 2 * k + 1], st) : hipSuccess;
+  };
 
   HIP_TRY(launch_init_state(dinfo, y, ydtype, dst, P.req, (int)B, st));
   HIP_TRY(launch_zero_i32(notdone, 1, st));
+  HIP_TRY(launch_zero_i32(P.req2, (int)B, st));
+  std::memset(hreq2, 0, (size_t)B * sizeof(int32_t));
   HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
   HIP_TRY(hipEventRecord(ctx->ev_round, st));
   HIP_TRY(spin_wait(ctx->ev_round));
@@ -1003,7 +1019,11 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   const double esz_d = (double)esz;
   for (;;) {
     int64_t nact = 0, ngrid = 0, nreq = 0;
-    for (int k = 0; k < KID_COUNT; ++k) { launched[k] = false; kflops[k] = 0.0; kbytes[k] = 0.0; }
+    for (int k = 0; k < KID_COUNT; ++k) {
+      launched[k] = launched2[k] = false;
+      kflops[k] = 0.0;
+      kbytes[k] = 0.0;
+    }
     for (int64_t b = 0; b < B; ++b) {
       const int32_t rq = hreq[b];
       if (!rq) continue;
@@ -1056,38 +1076,64 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
                               ctx->tws64, scratch, w, yCy, ww, (int)B, sz.maxP, st, dorder));
       HIP_TRY(tstop(KID_APPLY));
     }
-    if (ngrid > 0) {
-      HIP_TRY(tstart(KID_OMEGA));
-      HIP_TRY(launch_omega(dinfo, P.req, rho, delta, dcoef, ctx->tws64, scratch, 1, 1,
-                           oms, nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st, dorder));
-      HIP_TRY(tstop(KID_OMEGA));
-      HIP_TRY(tstart(KID_GRID));
-      HIP_TRY(launch_grid(prec, dinfo, P.req, w, oms, P.gbar_e, P.zeta_e, tw, ctx->logtw,
-                          sz.Rmax, (int)B, sz.maxM, nullptr, nullptr, dL, pv, pi, st));
-      HIP_TRY(tstop(KID_GRID));
-      HIP_TRY(tstart(KID_SELECT));
-      HIP_TRY(launch_select(prec, dinfo, P.req, dL, sz.Rmax, pv, pi, p.approx_ratio, slack,
-                            p.cand_cap, cand, ncand, ovf, (int)B, st));
-      HIP_TRY(tstop(KID_SELECT));
+    // active-set vectors at the evaluated points (candidates follow the grid stage)
+    if (nact > 0) {
+      HIP_TRY(tstart(KID_ACTIVE));
+      HIP_TRY(launch_active(dinfo, P.req, P.K_e, nullptr, prefix, (int)B, P.th_e, cand, w, rho,
+                            delta, dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks,
+                            ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st));
+      HIP_TRY(tstop(KID_ACTIVE));
     }
-    HIP_TRY(tstart(KID_ACTIVE));
-    HIP_TRY(launch_active(dinfo, P.req, P.K_e, ngrid > 0 ? ncand : nullptr, prefix, (int)B,
-                          P.th_e, cand, w, rho, delta, dcoef, evq, evr, evu, evs, evt, evv, evx,
-                          cq, cs, act_blocks, ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st));
-    HIP_TRY(tstop(KID_ACTIVE));
+    // first driver pass: the instances whose request had no grid sweep
     HIP_TRY(tstart(KID_DRIVER));
     HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
     HIP_TRY(tstop(KID_DRIVER));
+    // Grid stage, after the first pass: the grid sweeps the round began with
+    // (their evaluation, if any, is done) and those the pass just requested
+    // at the point this round evaluated (factor, C^-1 y and active vectors in
+    // place), which so run now instead of a round later; then the candidates'
+    // vectors and the second driver pass, for exactly these (P.req2).
+    HIP_TRY(tstart2(KID_OMEGA));
+    HIP_TRY(launch_omega(dinfo, P.req2, rho, delta, dcoef, ctx->tws64, scratch, 1, 1, oms, nullptr,
+                         nullptr, nullptr, nullptr, (int)B, sz.maxP, st, dorder));
+    HIP_TRY(tstop2(KID_OMEGA));
+    HIP_TRY(tstart2(KID_GRID));
+    HIP_TRY(launch_grid(prec, dinfo, P.req2, w, oms, P.gbar_e, P.zeta_e, tw, ctx->logtw, sz.Rmax,
+                        (int)B, sz.maxM, nullptr, nullptr, dL, pv, pi, st));
+    HIP_TRY(tstop2(KID_GRID));
+    HIP_TRY(tstart2(KID_SELECT));
+    HIP_TRY(launch_select(prec, dinfo, P.req2, dL, sz.Rmax, pv, pi, p.approx_ratio, slack,
+                          p.cand_cap, cand, ncand, ovf, (int)B, st));
+    HIP_TRY(tstop2(KID_SELECT));
+    HIP_TRY(tstart2(KID_ACTIVE));
+    HIP_TRY(launch_active(dinfo, P.req2, P.K_e, ncand, prefix, (int)B, P.th_e, cand, w, rho, delta,
+                          dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks,
+                          ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st));
+    HIP_TRY(tstop2(KID_ACTIVE));
+    HIP_TRY(tstart2(KID_DRIVER));
+    HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st, 1));
+    HIP_TRY(tstop2(KID_DRIVER));
     HIP_TRY(hipEventRecord(ctx->ev_round, st));
     HIP_TRY(spin_wait(ctx->ev_round));
     ctx->timeline.push_back(now_s());
+    // grid sweeps of the second stage: evaluation counts and their traffic
+    // (entries are cleared once read: the device writes them in its next first pass)
+    for (int64_t b = 0; b < B; ++b) {
+      if (!hreq2[b]) continue;
+      hreq2[b] = 0;
+      ++gevals;
+      const double N = (double)n[b], Lb = (double)info[(size_t)b].L;
+      kbytes[KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz_d * Lb;
+    }
     if (timing) {
       for (int k = 0; k < KID_COUNT; ++k) {
-        if (!launched[k]) continue;
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[2 * k], ctx->ev[2 * k + 1]));
-        ctx->kst[k].launches += 1;
-        ctx->kst[k].seconds += 1e-3 * (double)ms;
+        for (int sg = 0; sg < 2; ++sg) {
+          if (!(sg ? launched2[k] : launched[k])) continue;
+          float ms = 0.0f;
+          HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[sg * E2 + 2 * k], ctx->ev[sg * E2 + 2 * k + 1]));
+          ctx->kst[k].launches += 1;
+          ctx->kst[k].seconds += 1e-3 * (double)ms;
+        }
         ctx->kst[k].flops += kflops[k];
         ctx->kst[k].bytes += kbytes[k];
       }

@@ -28,12 +28,12 @@ struct sfls_ctx {
   sfls::cf* tws32 = nullptr;
   int logtw = 17;
   std::map<std::string, DevBuf> bufs;
-  int32_t* host_req = nullptr;  // pinned copy of the per-instance request bits
+  int32_t* host_req = nullptr;  // pinned copies of the per-instance request bits (req, req2)
   int64_t host_req_n = 0;
   bool timing = false;
   int32_t factor_algo = 0;  // sfls_factor_algo
   int32_t nufft_mode = 0;   // sfls_nufft_mode
-  hipEvent_t ev[2 * KID_COUNT] = {};
+  hipEvent_t ev[4 * KID_COUNT] = {};  // per kernel: start/stop of a round's first and second stage
   sfls_kernel_stat kst[KID_COUNT] = {};
   sfls_run_stats last = {};
   std::vector<double> timeline;

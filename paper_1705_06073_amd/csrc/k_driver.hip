@@ -48,9 +48,19 @@ struct WaveTeam {
 
 __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info,
                                                const DrvParams* __restrict__ prm, DrvPools p,
-                                               int B) {
+                                               int B, int pass) {
   const int b = blockIdx.x;
   if (b >= B) return;
+  if (pass == 1 && !(p.req2 && p.req2[b] != 0)) return;
+  if (pass == 0 && p.req2) {
+    // a request with a grid sweep waits for the round's grid stage, which
+    // runs after this pass (its evaluation, if any, is done); pass 1 steps it
+    const int32_t r0 = p.req[b];
+    if (r0 & REQ_GRID) {
+      if (threadIdx.x == 0) p.req2[b] = r0 & ~REQ_EVAL;
+      return;
+    }
+  }
   const InstInfo in = info[b];
   DrvState S = p.st[b];
   if (S.phase == PH_DONE) return;
@@ -110,9 +120,16 @@ __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info
   drv.step();
   if (threadIdx.x == 0) {
     p.st[b] = S;
-    if (S.phase != PH_DONE) atomicAdd(p.notdone, 1);
+    if (pass == 0 && S.phase != PH_DONE) atomicAdd(p.notdone, 1);
     // this thread's own store of the request bits, read back in order
-    if (p.req_host) p.req_host[b] = __atomic_load_n(p.req + b, __ATOMIC_RELAXED);
+    const int32_t r = __atomic_load_n(p.req + b, __ATOMIC_RELAXED);
+    if (p.req_host) p.req_host[b] = r;
+    if (p.req2) {
+      // a grid sweep at the point just evaluated runs in this round's second stage
+      const int32_t r2 = (pass == 0 && (r & REQ_GRID) && !(r & REQ_EVAL)) ? r : 0;
+      p.req2[b] = r2;
+      if (p.req2_host && pass == 0) p.req2_host[b] = r2;
+    }
   }
 }
 
@@ -171,8 +188,8 @@ __global__ void k_zero_i32(int32_t* p, int n) {
 }
 
 hipError_t launch_driver(const InstInfo* info, const DrvParams* prm, DrvPools pools, int B,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_driver, dim3(B), dim3(64), 0, st, info, prm, pools, B);
+                         hipStream_t st, int pass) {
+  hipLaunchKernelGGL(k_driver, dim3(B), dim3(64), 0, st, info, prm, pools, B, pass);
   return hipGetLastError();
 }
 

@@ -61,6 +61,13 @@ struct DrvPools {
   // optional host-mapped copy of the request bits (pinned host memory the
   // device writes directly), so the host reads them without a copy per round
   int32_t* req_host;
+  // the requests of the round's grid stage, which runs after the first
+  // driver pass (the grid bits, else 0): those the round began with, and
+  // grid sweeps at the point just evaluated that the first pass requested
+  // (run at once instead of a round later; the host-mapped copy marks the
+  // latter, for the host's accounting)
+  int32_t* req2;
+  int32_t* req2_host;
 };
 
 hipError_t launch_twiddles(cd* tw64, cf* tw32, cd* tws64, cf* tws32, int logtw, hipStream_t st);
@@ -130,8 +137,11 @@ hipError_t launch_gather_results(const int32_t* list, const int64_t* doff, int n
                                  const double* ozeta, const double* oobj, const int32_t* oiters,
                                  const int32_t* oevals, const int32_t* ostatus, SlotResult* res,
                                  double* comp, hipStream_t s);
+// pass 0: every unfinished instance whose request has no grid sweep takes
+// its step (with pools.req2: the others are deferred to pass 1); pass 1:
+// the instances of pools.req2, after the round's grid stage has run.
 hipError_t launch_driver(const InstInfo* info, const DrvParams* prm, DrvPools pools, int B,
-                         hipStream_t st);
+                         hipStream_t st, int pass = 0);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
 
 }  // namespace sfls

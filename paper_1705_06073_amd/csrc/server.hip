@@ -163,8 +163,8 @@ struct sfls_server {
   std::chrono::steady_clock::time_point t0, t_launch;
   sfls_server_stats stats{};
   // per-kernel HIP events of the round in flight (when the context times)
-  hipEvent_t tev[2 * KID_COUNT] = {};
-  bool tlaunched[KID_COUNT] = {};
+  hipEvent_t tev[4 * KID_COUNT] = {};  // per kernel: start/stop of the first and second stage
+  bool tlaunched[KID_COUNT] = {}, tlaunched2[KID_COUNT] = {};
   double tflops[KID_COUNT] = {}, tbytes[KID_COUNT] = {};
   bool timed = false;
   std::vector<double> slot_flops;  // factorisation flops of each slot's request
@@ -208,6 +208,7 @@ struct sfls_server {
   SchurLayout* h_lay = nullptr;
   int64_t* h_koff = nullptr;
   int32_t* h_req = nullptr;
+  int32_t* h_req2 = nullptr;     // second-stage grid requests of the last round (accounting)
   int32_t* h_list = nullptr;
   int32_t* h_order = nullptr;    // dispatch order of the round (lanes of uneven sizes)
   int32_t* h_newlist = nullptr;  // [2][S]: admitted since the last launch, by buffer
@@ -220,6 +221,7 @@ struct sfls_server {
   std::vector<void*> dev_owned, host_owned;
   // device addresses of the pinned buffers the kernels read or write directly
   int32_t* m_req = nullptr;
+  int32_t* m_req2 = nullptr;
   int32_t* m_newlist = nullptr;
   int32_t* m_order = nullptr;
   AdmitRec* m_adm = nullptr;
@@ -451,7 +453,7 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
   const uint64_t slot_bytes =
       (uint64_t)S * (sizeof(InstInfo) + sizeof(SepCoef) + sizeof(SchurLayout) + sizeof(DrvState) +
                      8 * 16 + (uint64_t)s->Rmax * 16 + 2 * (uint64_t)J * 8 +
-                     (uint64_t)s->cc * (4 + 16 + 8 + 8 + 8 + 4) + sizeof(SlotResult) + 16);
+                     (uint64_t)s->cc * (4 + 16 + 8 + 8 + 8 + 4) + sizeof(SlotResult) + 20);
   if (cfg.hbm_bytes <= slot_bytes)
     return bail(fail(ctx, SFLS_EINVAL, "hbm_bytes below the per-slot arrays (%llu bytes)",
                      (unsigned long long)slot_bytes));
@@ -506,7 +508,7 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
   DA(P.g, 2 * K); DA(P.d, 2 * K); DA(P.gt, 2 * K); DA(P.q_save, 2 * K);
   DA(P.Sm, (size_t)J * 2 * K); DA(P.Ym, (size_t)J * 2 * K);
   DA(P.rhom, (size_t)J * S); DA(P.am, (size_t)J * S);
-  DA(P.K_e, S); DA(P.req, S); DA(P.beta_e, S); DA(P.gbar_e, S); DA(P.zeta_e, S);
+  DA(P.K_e, S); DA(P.req, S); DA(P.req2, S); DA(P.beta_e, S); DA(P.gbar_e, S); DA(P.zeta_e, S);
   DA(s->evq, K); DA(s->evr, K); DA(s->evu, K); DA(s->evs, K); DA(s->evt, K); DA(s->evv, K);
   DA(s->evx, K);
   DA(s->logdet, S); DA(s->yCy, S); DA(s->ww, S); DA(s->failed, S); DA(s->lev_status, S);
@@ -532,10 +534,11 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
 #define HA(ptr, cnt) ok = ok && halloc(&(ptr), (size_t)(cnt), H) == hipSuccess
   HA(s->h_info, S); HA(s->h_coef, S); HA(s->h_lay, S); HA(s->h_koff, S); HA(s->h_req, S);
   HA(s->h_list, S); HA(s->h_newlist, 2 * S); HA(s->h_adm, 2 * S); HA(s->h_doff, S);
-  HA(s->h_gkoff, S); HA(s->h_res, S); HA(s->h_order, S);
+  HA(s->h_gkoff, S); HA(s->h_res, S); HA(s->h_order, S); HA(s->h_req2, S);
 #undef HA
   if (!ok) return bail(fail(ctx, SFLS_ENOMEM, "pinned host mirrors"));
   std::memset(s->h_req, 0, (size_t)S * sizeof(int32_t));
+  std::memset(s->h_req2, 0, (size_t)S * sizeof(int32_t));
   if (hipHostGetDevicePointer((void**)&s->m_req, s->h_req, 0) != hipSuccess ||
       hipHostGetDevicePointer((void**)&s->m_newlist, s->h_newlist, 0) != hipSuccess ||
       hipHostGetDevicePointer((void**)&s->m_adm, s->h_adm, 0) != hipSuccess ||
@@ -547,7 +550,8 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
       hipHostGetDevicePointer((void**)&s->m_doff, s->h_doff, 0) != hipSuccess ||
       hipHostGetDevicePointer((void**)&s->m_gkoff, s->h_gkoff, 0) != hipSuccess ||
       hipHostGetDevicePointer((void**)&s->m_res, s->h_res, 0) != hipSuccess ||
-      hipHostGetDevicePointer((void**)&s->m_order, s->h_order, 0) != hipSuccess)
+      hipHostGetDevicePointer((void**)&s->m_order, s->h_order, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&s->m_req2, s->h_req2, 0) != hipSuccess)
     return bail(fail(ctx, SFLS_EDEVICE, "device addresses of the pinned mirrors"));
   P.ev_q = s->evq; P.ev_r = s->evr; P.ev_u = s->evu; P.ev_s = s->evs; P.ev_t = s->evt;
   P.ev_v = s->evv; P.ev_x = s->evx; P.logdet = s->logdet; P.yCy = s->yCy; P.ww = s->ww;
@@ -557,6 +561,7 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
   P.out_iters = oit; P.out_evals = oev; P.out_status = ost; P.out_koff = s->dkoff;
   P.notdone = s->notdone;
   P.req_host = s->m_req;
+  P.req2_host = s->m_req2;
   const DrvParams dp = drv_params(p);
   std::vector<InstInfo> zinfo((size_t)S);
   std::memset(zinfo.data(), 0, zinfo.size() * sizeof(InstInfo));
@@ -565,6 +570,7 @@ sfls_status sfls_server_create(sfls_ctx* ctx, const sfls_server_config* cfg_in,
           hipSuccess ||
       launch_slots_idle(P.st, P.req, (int)S, s->st) != hipSuccess ||
       launch_zero_i32(s->notdone, 1, s->st) != hipSuccess ||
+      launch_zero_i32(P.req2, (int)S, s->st) != hipSuccess ||
       hipStreamSynchronize(s->st) != hipSuccess)
     return bail(fail(ctx, SFLS_EDEVICE, "server initialisation failed"));
   uint64_t total = 0;
@@ -704,8 +710,8 @@ sfls_status sfls_server_launch(sfls_server* s) {
     s->admitted.clear();
   }
   // sizes of this round's launches, over the requests that asked for work
-  int maxN = 0, maxP = 0, maxM = 0, Rr = 1, lo_n = 1 << 30, hi_n = 0;
-  bool any_eval = false, any_grid = false, any_req = false;
+  int maxN = 0, maxP = 0, lo_n = 1 << 30, hi_n = 0, maxM2 = 0, R2 = 1;
+  bool any_eval = false, any_req = false;
   for (int b = 0; b < B; ++b) {
     const int32_t rq = s->h_req[b];
     if (!rq || s->slots[(size_t)b].state != SLOT_RUNNING) continue;
@@ -714,14 +720,13 @@ sfls_status sfls_server_launch(sfls_server* s) {
     maxP = std::max(maxP, in.P);
     lo_n = std::min(lo_n, in.N);
     hi_n = std::max(hi_n, in.N);
+    // any request may reach the round's grid stage (a sweep it began with,
+    // or one its first driver pass asks for)
+    maxM2 = std::max(maxM2, in.M);
+    R2 = std::max(R2, in.R);
     if (rq & REQ_EVAL) {
       any_eval = true;
       maxN = std::max(maxN, in.N);
-    }
-    if (rq & REQ_GRID) {
-      any_grid = true;
-      maxM = std::max(maxM, in.M);
-      Rr = std::max(Rr, in.R);
     }
   }
   // requests of different sizes: the per-instance kernels whose time grows
@@ -745,7 +750,7 @@ sfls_status sfls_server_launch(sfls_server* s) {
     for (auto& e : s->tev) HIP_TRY(hipEventCreate(&e));
   }
   for (int k = 0; k < KID_COUNT; ++k) {
-    s->tlaunched[k] = false;
+    s->tlaunched[k] = s->tlaunched2[k] = false;
     s->tflops[k] = 0.0;
     s->tbytes[k] = 0.0;
   }
@@ -771,6 +776,14 @@ sfls_status sfls_server_launch(sfls_server* s) {
   };
   auto tstop = [&](int k) -> hipError_t {
     return s->timed ? hipEventRecord(s->tev[2 * k + 1], st) : hipSuccess;
+  };
+  const int E2 = 2 * KID_COUNT;
+  auto tstart2 = [&](int k) -> hipError_t {
+    s->tlaunched2[k] = true;
+    return s->timed ? hipEventRecord(s->tev[E2 + 2 * k], st) : hipSuccess;
+  };
+  auto tstop2 = [&](int k) -> hipError_t {
+    return s->timed ? hipEventRecord(s->tev[E2 + 2 * k + 1], st) : hipSuccess;
   };
   if (any_eval) {
     HIP_TRY(tstart(KID_GEN));
@@ -801,33 +814,48 @@ sfls_status sfls_server_launch(sfls_server* s) {
                             dorder));
     HIP_TRY(tstop(KID_APPLY));
   }
-  if (any_grid) {
-    const void* tw = prec == SFLS_FP64 ? (const void*)ctx->tws64 : (const void*)ctx->tws32;
-    const double slack = prec == SFLS_FP64 ? 1e-9 : 1e-3;
-    HIP_TRY(tstart(KID_OMEGA));
-    HIP_TRY(launch_omega(s->dinfo, P.req, s->rho, s->delta, s->dcoef, ctx->tws64, s->scratch, 1, 1,
-                         s->oms, nullptr, nullptr, nullptr, nullptr, B, maxP, st, dorder));
-    HIP_TRY(tstop(KID_OMEGA));
-    HIP_TRY(tstart(KID_GRID));
-    HIP_TRY(launch_grid(prec, s->dinfo, P.req, s->w, s->oms, P.gbar_e, P.zeta_e, tw, ctx->logtw, Rr,
-                        B, maxM, nullptr, nullptr, s->dL, s->pv, s->pi, st));
-    HIP_TRY(tstop(KID_GRID));
-    HIP_TRY(tstart(KID_SELECT));
-    HIP_TRY(launch_select(prec, s->dinfo, P.req, s->dL, Rr, s->pv, s->pi, s->prm.approx_ratio,
-                          slack, s->prm.cand_cap, s->cand, s->ncand, s->ovf, B, st));
-    HIP_TRY(tstop(KID_SELECT));
-  }
-  if (any_req) {
+  // active-set vectors at the evaluated points (candidates follow the grid stage)
+  if (any_eval) {
     HIP_TRY(tstart(KID_ACTIVE));
-    HIP_TRY(launch_active(s->dinfo, P.req, P.K_e, any_grid ? s->ncand : nullptr, s->prefix, B,
-                          P.th_e, s->cand, s->w, s->rho, s->delta, s->dcoef, s->evq, s->evr,
-                          s->evu, s->evs, s->evt, s->evv, s->evx, s->cq, s->cs, 2048,
-                          ctx->nufft_mode, ctx->tws64, s->scratch, maxP, st));
+    HIP_TRY(launch_active(s->dinfo, P.req, P.K_e, nullptr, s->prefix, B, P.th_e, s->cand, s->w,
+                          s->rho, s->delta, s->dcoef, s->evq, s->evr, s->evu, s->evs, s->evt,
+                          s->evv, s->evx, s->cq, s->cs, 2048, ctx->nufft_mode, ctx->tws64,
+                          s->scratch, maxP, st));
     HIP_TRY(tstop(KID_ACTIVE));
   }
+  // first driver pass: the slots whose request had no grid sweep
   HIP_TRY(tstart(KID_DRIVER));
   HIP_TRY(launch_driver(s->dinfo, s->dprm, P, B, st));  // request bits also to h_req
   HIP_TRY(tstop(KID_DRIVER));
+  if (any_req) {
+    // grid stage, after the first pass: the sweeps the round began with and
+    // those the pass just requested at the point this round evaluated (run
+    // now instead of a round later); then candidates and the second pass,
+    // for exactly these slots (P.req2)
+    const void* tw = prec == SFLS_FP64 ? (const void*)ctx->tws64 : (const void*)ctx->tws32;
+    const double slack = prec == SFLS_FP64 ? 1e-9 : 1e-3;
+    HIP_TRY(tstart2(KID_OMEGA));
+    HIP_TRY(launch_omega(s->dinfo, P.req2, s->rho, s->delta, s->dcoef, ctx->tws64, s->scratch, 1,
+                         1, s->oms, nullptr, nullptr, nullptr, nullptr, B, maxP, st, dorder));
+    HIP_TRY(tstop2(KID_OMEGA));
+    HIP_TRY(tstart2(KID_GRID));
+    HIP_TRY(launch_grid(prec, s->dinfo, P.req2, s->w, s->oms, P.gbar_e, P.zeta_e, tw, ctx->logtw,
+                        R2, B, maxM2, nullptr, nullptr, s->dL, s->pv, s->pi, st));
+    HIP_TRY(tstop2(KID_GRID));
+    HIP_TRY(tstart2(KID_SELECT));
+    HIP_TRY(launch_select(prec, s->dinfo, P.req2, s->dL, R2, s->pv, s->pi, s->prm.approx_ratio,
+                          slack, s->prm.cand_cap, s->cand, s->ncand, s->ovf, B, st));
+    HIP_TRY(tstop2(KID_SELECT));
+    HIP_TRY(tstart2(KID_ACTIVE));
+    HIP_TRY(launch_active(s->dinfo, P.req2, P.K_e, s->ncand, s->prefix, B, P.th_e, s->cand, s->w,
+                          s->rho, s->delta, s->dcoef, s->evq, s->evr, s->evu, s->evs, s->evt,
+                          s->evv, s->evx, s->cq, s->cs, 2048, ctx->nufft_mode, ctx->tws64,
+                          s->scratch, maxP, st));
+    HIP_TRY(tstop2(KID_ACTIVE));
+    HIP_TRY(tstart2(KID_DRIVER));
+    HIP_TRY(launch_driver(s->dinfo, s->dprm, P, B, st, 1));
+    HIP_TRY(tstop2(KID_DRIVER));
+  }
   HIP_TRY(hipEventRecord(s->ev, st));
   s->in_flight = true;
   s->t_launch = std::chrono::steady_clock::now();
@@ -853,13 +881,24 @@ sfls_status sfls_server_wait(sfls_server* s, int32_t block, int32_t* ready, int3
   }
   s->in_flight = false;
   s->stats.rounds += 1;
+  // grid sweeps of the second stage: their traffic (entries are cleared
+  // once read; the device writes them in its next first pass)
+  for (int b = 0; b < s->hw; ++b) {
+    if (!s->h_req2[b]) continue;
+    s->h_req2[b] = 0;
+    const double N = (double)s->h_info[b].N;
+    s->tbytes[KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + (double)s->esz * s->h_info[b].L;
+  }
   if (s->timed) {
+    const int E2 = 2 * KID_COUNT;
     for (int k = 0; k < KID_COUNT; ++k) {
-      if (!s->tlaunched[k]) continue;
-      float ms = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&ms, s->tev[2 * k], s->tev[2 * k + 1]));
-      ctx->kst[k].launches += 1;
-      ctx->kst[k].seconds += 1e-3 * (double)ms;
+      for (int sg = 0; sg < 2; ++sg) {
+        if (!(sg ? s->tlaunched2[k] : s->tlaunched[k])) continue;
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, s->tev[sg * E2 + 2 * k], s->tev[sg * E2 + 2 * k + 1]));
+        ctx->kst[k].launches += 1;
+        ctx->kst[k].seconds += 1e-3 * (double)ms;
+      }
       ctx->kst[k].flops += s->tflops[k];
       ctx->kst[k].bytes += s->tbytes[k];
     }
