@@ -64,6 +64,7 @@ __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info
   const InstInfo in = info[b];
   DrvState S = p.st[b];
   if (S.phase == PH_DONE) return;
+  if (pass == 2 && S.phase != PH_START) return;
   const int64_t ko = in.koff, k2 = 2 * in.koff, co = in.coff;
   const int J = prm->J;
   DrvArrays A;

@@ -139,7 +139,9 @@ hipError_t launch_gather_results(const int32_t* list, const int64_t* doff, int n
                                  double* comp, hipStream_t s);
 // pass 0: every unfinished instance whose request has no grid sweep takes
 // its step (with pools.req2: the others are deferred to pass 1); pass 1:
-// the instances of pools.req2, after the round's grid stage has run.
+// the instances of pools.req2, after the round's grid stage has run; pass 2:
+// only the instances in their initial phase (newly admitted ones, stepped
+// before the round's evaluation kernels so that the round evaluates them).
 hipError_t launch_driver(const InstInfo* info, const DrvParams* prm, DrvPools pools, int B,
                          hipStream_t st, int pass = 0);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);

@@ -694,7 +694,7 @@ sfls_status sfls_server_launch(sfls_server* s) {
   (void)hipSetDevice(ctx->device);
   const hipStream_t st = s->st;
   const int B = s->hw;
-  // newly admitted requests: initial state (phase START), stepped by this round's driver
+  // newly admitted requests: initial state (phase START) and first step, before this round's evaluation kernels
   const int nnew = (int)s->admitted.size();
   if (nnew > 0) {
     // the kernels read the records and lists from pinned host memory; the
@@ -705,8 +705,15 @@ sfls_status sfls_server_launch(sfls_server* s) {
                          s->m_koff, s->dinfo, s->dcoef, s->dlay, s->dkoff, s->ypool, st));
     HIP_TRY(launch_init_state(s->dinfo, s->ypool, s->cfg.ydtype, s->P.st, s->P.req, nnew, st,
                               s->m_newlist + o));
+    // their first step (initialisation, the request of the first evaluation
+    // and grid sweep) now, so that this round already evaluates them
+    HIP_TRY(launch_driver(s->dinfo, s->dprm, s->P, B, st, 2));
     s->abuf ^= 1;
-    for (int sl : s->admitted) s->slots[(size_t)sl].state = SLOT_RUNNING;
+    for (int sl : s->admitted) {
+      s->slots[(size_t)sl].state = SLOT_RUNNING;
+      // what that step requests (the device overwrites it at the round's end)
+      s->h_req[sl] = REQ_EVAL | REQ_GRID | REQ_APPROX;
+    }
     s->admitted.clear();
   }
   // sizes of this round's launches, over the requests that asked for work
