@@ -348,9 +348,9 @@ def main():
     yaddr = [y.data_ptr() + 16 * int(o) for o in off]
 
     def run_stream(nsteps):
-        # the next round of a server is launched as soon as its previous one
-        # completes; collecting results and admitting new instances (which then
-        # join the round after) happen on the host while it runs
+        # when a round completes, the slots its finished solves freed take the
+        # next instances at once (they join the next round, which starts right
+        # after); results are collected while that round runs
         total = nsteps * B
         nxt, got = 0, []
         for srv in srvs:
@@ -365,12 +365,10 @@ def main():
                         continue
                 else:
                     srv.wait()
-                srv.launch()
-                got += srv.poll()
                 while nxt < total and srv.submit(yaddr[nxt % B], int(n[nxt % B]), nxt):
                     nxt += 1
-                if not srv.in_flight:
-                    srv.launch()
+                srv.launch()
+                got += srv.poll()
         return got
 
     for w in range(args.warmup):

@@ -46,22 +46,21 @@ def run_stream(lanes, lane_of, arrivals, sizes, ptr_of, progress_every: float = 
                 ready, fin = srv.wait(block=False)
                 if ready:
                     progressed = True
-                    # the next round starts before the host collects results
-                    # and admits requests, which then join the round after
-                    srv.launch()
-                if fin:
-                    tc = time.perf_counter() - t0
-                    for r in srv.poll():
-                        lat[r.tag] = tc - arrivals[r.tag]
-                        results[r.tag] = r
-                        done += 1
-            # admission does not wait for the round in flight: the signal is
-            # copied on the context's upload stream and joins a later round
+            # admission: when a round has completed, the slots it freed take
+            # queued requests before the next round starts (they join it);
+            # while a round runs, arrivals are admitted for the round after
             q = queues[li]
             while q and srv.submit(ptr_of(q[0]), int(sizes[q[0]]), q[0]):
                 q.popleft()
             if not srv.in_flight:
                 srv.launch()
+            # results are collected while the next round runs
+            if fin:
+                tc = time.perf_counter() - t0
+                for r in srv.poll():
+                    lat[r.tag] = tc - arrivals[r.tag]
+                    results[r.tag] = r
+                    done += 1
         if not any(s.in_flight for s in lanes):
             if i < R:
                 time.sleep(max(0.0, arrivals[i] - (time.perf_counter() - t0)))
