@@ -339,7 +339,7 @@ def main():
 
     # --- continuous batching (the reported value): the steps' batches stream
     # through a server with one slot per instance of a batch; a slot freed by
-    # a finished solve takes the next instance at the following round, so no
+    # a finished solve takes the next instance for the next round, so no
     # round waits for the slowest instance of its batch.
     streams = [stream] + [torch.cuda.Stream() for _ in range(args.servers - 1)]
     srvs = [sf.Server(ctx, max_n=4096, max_slots=args.slots, ydtype=sf.SFLS_C128,
@@ -376,7 +376,9 @@ def main():
         run_stream(1)
         log(f"warmup {w + 1}/{args.warmup} (continuous): {time.perf_counter() - t:.3f} s")
     ctx.reset_stats()
-    ctx.set_timing(True)
+    # the timed legs bracket only the recursion with events (the roofline's
+    # kernel); an event between two kernels would idle the device a few us
+    ctx.set_timing(2)
     r0 = sum(s.stats()["rounds"] for s in srvs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -416,6 +418,14 @@ def main():
     ctx.set_timing(False)
     kst = ctx.kernel_stats()
     run, _ = ctx.last_run()
+    # per-kernel shares: one more call of the batch, outside the timed region,
+    # with every kernel timed
+    ctx.reset_stats()
+    ctx.set_timing(1)
+    run_batch()
+    torch.cuda.synchronize()
+    ctx.set_timing(False)
+    kst_all = ctx.kernel_stats()
     st = out["status"].cpu().numpy()
     Kh = out["K"].cpu().numpy()
     its = out["iters"].cpu().numpy()
@@ -449,9 +459,9 @@ def main():
                 "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
                 "avg_launch_ms": 1e3 * ks["seconds"] / max(1, ks["launches"]),
                 "algorithmic_per_launch": ks["bytes"] / max(1, ks["launches"])}
-    kernels = {k: {"launches": v["launches"], "ms_total": 1e3 * v["seconds"] / (2 * args.steps),
-                   "share": v["seconds"] / max(1e-30, sum(x["seconds"] for x in kst.values()))}
-               for k, v in kst.items()}
+    kernels = {k: {"launches": v["launches"], "ms_total": 1e3 * v["seconds"],
+                   "share": v["seconds"] / max(1e-30, sum(x["seconds"] for x in kst_all.values()))}
+               for k, v in kst_all.items()}
 
     # plain FP64, one instance per launch, no batching
     plain = None
@@ -533,6 +543,8 @@ def main():
                       "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}},
         "roofline": roof,
         "kernels": kernels,
+        "kernels_source": ("one more sfls_estimate call of the batch (256 solves) with every "
+                           "kernel timed, outside the timed region; ms_total per call"),
         "cpu_baseline": cpu,
         "serving": serve,
         "serving_n4096": serve4096,

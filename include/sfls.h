@@ -272,7 +272,10 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
  *
  * sfls_set_timing(ctx, 1) brackets every kernel launch of the estimate round
  * loop (and of the rounds of servers created on the context) with HIP events
- * on the stream the work runs on; per kernel the context then
+ * on the stream the work runs on; sfls_set_timing(ctx, 2) brackets only the
+ * recursion's launches (an event between two kernels costs the device a few
+ * microseconds of idle time; mode 2 keeps that out of the other kernels);
+ * 0 turns timing off, other values are EINVAL.  Per timed kernel the context then
  * accumulates the launch count, the summed event durations, and the
  * algorithmic work of those launches (FP64 flops of the factorisation: 8 N^2
  * per instance for Levinson, the count of the superfast recursion's leaf

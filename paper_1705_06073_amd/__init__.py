@@ -251,8 +251,9 @@ class Context:
     def set_schur_lds(self, max_f: int):
         self.check(lib().sfls_set_schur_lds(self._h, int(max_f)))
 
-    def set_timing(self, enable: bool = True):
-        self.check(lib().sfls_set_timing(self._h, 1 if enable else 0))
+    def set_timing(self, mode=True):
+        """True / 1: time every kernel of a round; 2: the recursion only; False / 0: off."""
+        self.check(lib().sfls_set_timing(self._h, int(mode)))
 
     def reset_stats(self):
         lib().sfls_reset_stats(self._h)

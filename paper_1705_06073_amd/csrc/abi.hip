@@ -523,7 +523,8 @@ sfls_status sfls_set_timing(sfls_ctx* ctx, int32_t enable) {
     for (auto& e : ctx->ev)
       if (hipEventCreate(&e) != hipSuccess) return fail(ctx, SFLS_EDEVICE, "hipEventCreate failed");
   }
-  ctx->timing = enable != 0;
+  if (enable < 0 || enable > 2) return fail(ctx, SFLS_EINVAL, "timing mode %d", (int)enable);
+  ctx->timing = enable;
   return SFLS_OK;
 }
 
@@ -985,25 +986,26 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   };
   ctx->timeline.clear();
   ctx->last = sfls_run_stats{};
-  const bool timing = ctx->timing;
+  const bool timing = ctx->timing != 0;
   bool launched[KID_COUNT];
   double kflops[KID_COUNT], kbytes[KID_COUNT];
   auto tstart = [&](int k) -> hipError_t {
     launched[k] = true;
-    return timing ? hipEventRecord(ctx->ev[2 * k], st) : hipSuccess;
+    return timing && times_kernel(ctx->timing, k) ? hipEventRecord(ctx->ev[2 * k], st) : hipSuccess;
   };
   auto tstop = [&](int k) -> hipError_t {
-    return timing ? hipEventRecord(ctx->ev[2 * k + 1], st) : hipSuccess;
+    return timing && times_kernel(ctx->timing, k) ? hipEventRecord(ctx->ev[2 * k + 1], st) : hipSuccess;
   };
   // the second stage of a round (grid sweeps at the point just evaluated)
   bool launched2[KID_COUNT];
   const int E2 = 2 * KID_COUNT;
   auto tstart2 = [&](int k) -> hipError_t {
     launched2[k] = true;
-    return timing ? hipEventRecord(ctx->ev[E2 + 2 * k], st) : hipSuccess;
+    return timing && times_kernel(ctx->timing, k) ? hipEventRecord(ctx->ev[E2 + 2 * k], st) : hipSuccess;
   };
   auto tstop2 = [&](int k) -> hipError_t {
-    return timing ? hipEventRecord(ctx->ev[E2 + 2 * k + 1], st) : hipSuccess;
+    return timing && times_kernel(ctx->timing, k) ? hipEventRecord(ctx->ev[E2 + 2 * k + 1], st)
+                                          : hipSuccess;
   };
 
   HIP_TRY(launch_init_state(dinfo, y, ydtype, dst, P.req, (int)B, st));
@@ -1127,6 +1129,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
     }
     if (timing) {
       for (int k = 0; k < KID_COUNT; ++k) {
+        if (!times_kernel(ctx->timing, k)) continue;
         for (int sg = 0; sg < 2; ++sg) {
           if (!(sg ? launched2[k] : launched[k])) continue;
           float ms = 0.0f;

@@ -30,7 +30,7 @@ struct sfls_ctx {
   std::map<std::string, DevBuf> bufs;
   int32_t* host_req = nullptr;  // pinned copies of the per-instance request bits (req, req2)
   int64_t host_req_n = 0;
-  bool timing = false;
+  int32_t timing = 0;  // 0 off, 1 every kernel of a round, 2 the recursion only
   int32_t factor_algo = 0;  // sfls_factor_algo
   int32_t nufft_mode = 0;   // sfls_nufft_mode
   hipEvent_t ev[4 * KID_COUNT] = {};  // per kernel: start/stop of a round's first and second stage
@@ -41,6 +41,11 @@ struct sfls_ctx {
   hipEvent_t ev_round = nullptr;  // end of an estimate round (request bits on the host)
   int32_t schur_lds_f = sfls::SCH_LDS_F;  // largest recursion transform kept in LDS
 };
+
+// Whether timing mode `mode` (sfls_set_timing) brackets kernel k with events.
+inline bool times_kernel(int32_t mode, int k) {
+  return mode == 1 || (mode == 2 && k == KID_FACTOR);
+}
 
 namespace sfls_host {
 

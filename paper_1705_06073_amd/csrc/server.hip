@@ -165,6 +165,7 @@ struct sfls_server {
   // per-kernel HIP events of the round in flight (when the context times)
   hipEvent_t tev[4 * KID_COUNT] = {};  // per kernel: start/stop of the first and second stage
   bool tlaunched[KID_COUNT] = {}, tlaunched2[KID_COUNT] = {};
+  int32_t tmode = 0;
   double tflops[KID_COUNT] = {}, tbytes[KID_COUNT] = {};
   bool timed = false;
   std::vector<double> slot_flops;  // factorisation flops of each slot's request
@@ -752,7 +753,8 @@ sfls_status sfls_server_launch(sfls_server* s) {
   DrvPools& P = s->P;
   const int prec = s->prm.precision;
   // per-kernel events and algorithmic work when the context times
-  s->timed = ctx->timing;
+  s->timed = ctx->timing != 0;
+  s->tmode = ctx->timing;  // the round's events follow the mode at its launch
   if (s->timed && !s->tev[0]) {
     for (auto& e : s->tev) HIP_TRY(hipEventCreate(&e));
   }
@@ -779,18 +781,20 @@ sfls_status sfls_server_launch(sfls_server* s) {
   }
   auto tstart = [&](int k) -> hipError_t {
     s->tlaunched[k] = true;
-    return s->timed ? hipEventRecord(s->tev[2 * k], st) : hipSuccess;
+    return s->timed && times_kernel(s->tmode, k) ? hipEventRecord(s->tev[2 * k], st) : hipSuccess;
   };
   auto tstop = [&](int k) -> hipError_t {
-    return s->timed ? hipEventRecord(s->tev[2 * k + 1], st) : hipSuccess;
+    return s->timed && times_kernel(s->tmode, k) ? hipEventRecord(s->tev[2 * k + 1], st) : hipSuccess;
   };
   const int E2 = 2 * KID_COUNT;
   auto tstart2 = [&](int k) -> hipError_t {
     s->tlaunched2[k] = true;
-    return s->timed ? hipEventRecord(s->tev[E2 + 2 * k], st) : hipSuccess;
+    return s->timed && times_kernel(s->tmode, k) ? hipEventRecord(s->tev[E2 + 2 * k], st)
+                                            : hipSuccess;
   };
   auto tstop2 = [&](int k) -> hipError_t {
-    return s->timed ? hipEventRecord(s->tev[E2 + 2 * k + 1], st) : hipSuccess;
+    return s->timed && times_kernel(s->tmode, k) ? hipEventRecord(s->tev[E2 + 2 * k + 1], st)
+                                            : hipSuccess;
   };
   if (any_eval) {
     HIP_TRY(tstart(KID_GEN));
@@ -899,6 +903,7 @@ sfls_status sfls_server_wait(sfls_server* s, int32_t block, int32_t* ready, int3
   if (s->timed) {
     const int E2 = 2 * KID_COUNT;
     for (int k = 0; k < KID_COUNT; ++k) {
+      if (!times_kernel(s->tmode, k)) continue;
       for (int sg = 0; sg < 2; ++sg) {
         if (!(sg ? s->tlaunched2[k] : s->tlaunched[k])) continue;
         float ms = 0.0f;

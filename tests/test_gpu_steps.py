@@ -278,3 +278,33 @@ def test_lds_transform_limit_rejects_bad_values(ctx):
     for bad in (128, 3000, 8192):
         with pytest.raises(sf.SflsError):
             ctx.set_schur_lds(bad)
+
+
+def test_timing_modes(ctx):
+    """Mode 2 brackets only the recursion with events, mode 1 every kernel of a
+    round; the timed figures change nothing in the results; other modes are
+    rejected."""
+    from paper_1705_06073_amd import synth
+    ys = [synth.workload_paper_snr(20 + i, 15.0, N=n, K=4).y.astype(np.complex128)
+          for i, n in enumerate((300, 700))]
+    p = sf.default_params(precision=sf.SFLS_MIXED)
+    try:
+        ctx.reset_stats()
+        ctx.set_timing(2)
+        a = sf.estimate_batch(ctx, ys, p)
+        k2 = ctx.kernel_stats()
+        ctx.reset_stats()
+        ctx.set_timing(1)
+        b = sf.estimate_batch(ctx, ys, p)
+        k1 = ctx.kernel_stats()
+    finally:
+        ctx.set_timing(False)
+    assert k2["factor"]["seconds"] > 0 and k2["factor"]["launches"] > 0
+    assert all(v["seconds"] == 0 and v["launches"] == 0 for k, v in k2.items() if k != "factor")
+    for k in ("factor", "gs_apply", "omega", "grid", "select", "active", "driver"):
+        assert k1[k]["seconds"] > 0 and k1[k]["launches"] > 0, k
+    assert k1["factor"]["launches"] == k2["factor"]["launches"]
+    for x, y in zip(a, b):
+        assert x.K == y.K and np.array_equal(x.theta, y.theta) and x.beta == y.beta
+    with pytest.raises(sf.SflsError):
+        ctx.set_timing(3)
