@@ -322,8 +322,12 @@ sfls_status sfls_last_run(const sfls_ctx* ctx, sfls_run_stats* stats, double* ti
  * at the start of the next round (a host-resident signal is copied before the
  * call returns).  Each round (sfls_server_launch) runs one
  * evaluation for every admitted request that has asked for one, whatever its
- * N, in the same kernels, and then the driver step; requests admitted since
- * the previous round join it.  sfls_server_wait completes the round: requests
+ * N, in the same kernels, then a driver pass, the grid stage for the requests
+ * whose step asks for a grid sweep (those at the point the round just
+ * evaluated included) and a second driver pass for them; requests admitted
+ * since the previous round take their first driver step at its start and are
+ * evaluated in it.  Requests of different N are dispatched longest first.
+ * sfls_server_wait completes the round: requests
  * whose estimate finished release their slot and memory at once, and a short
  * kernel behind the round packs their outputs for sfls_server_poll (which
  * waits for it), so the next round can be launched before the results are
