@@ -345,7 +345,15 @@ def main():
     srvs = [sf.Server(ctx, max_n=4096, max_slots=args.slots, ydtype=sf.SFLS_C128,
                       hbm_bytes=(4 << 30) * max(1, args.slots // 256), params=params, stream=s)
             for s in streams]
-    yaddr = [y.data_ptr() + 16 * int(o) for o in off]
+    yaddr = np.array([y.data_ptr() + 16 * int(o) for o in off], dtype=np.uint64)
+    n_np = np.asarray(n, dtype=np.int64)
+
+    def admit(srv, nxt, total):
+        # queued instances into the slots the last round freed, in one call
+        idx = np.arange(nxt, min(total, nxt + args.slots), dtype=np.int64)
+        if len(idx) == 0:
+            return nxt
+        return nxt + srv.submit_many(yaddr[idx % B], n_np[idx % B], idx.astype(np.uint64))
 
     def run_stream(nsteps):
         # when a round completes, the slots its finished solves freed take the
@@ -354,8 +362,7 @@ def main():
         total = nsteps * B
         nxt, got = 0, []
         for srv in srvs:
-            while nxt < total and srv.submit(yaddr[nxt % B], int(n[nxt % B]), nxt):
-                nxt += 1
+            nxt = admit(srv, nxt, total)
             srv.launch()
         while len(got) < total:
             for srv in srvs:
@@ -365,8 +372,7 @@ def main():
                         continue
                 else:
                     srv.wait()
-                while nxt < total and srv.submit(yaddr[nxt % B], int(n[nxt % B]), nxt):
-                    nxt += 1
+                nxt = admit(srv, nxt, total)
                 srv.launch()
                 got += srv.poll()
         return got

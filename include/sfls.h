@@ -401,6 +401,15 @@ sfls_status sfls_server_footprint(const sfls_server* srv, int64_t n, uint64_t* b
  * SFLS_EAGAIN: no free slot or pool memory now (retry after a round);
  * SFLS_EINVAL: n < 2, NULL or misaligned y; SFLS_EUNSUPPORTED: n > max_n. */
 sfls_status sfls_server_submit(sfls_server* srv, const void* y, int64_t n, uint64_t tag);
+/* Admit requests 0, 1, ... of ys / ns / tags (host arrays of `count`) in order,
+ * each as sfls_server_submit does, until all are admitted or one is not
+ * (SFLS_EAGAIN ends the call with SFLS_OK); *accepted = the number admitted.
+ * Any other status of a request is returned, with *accepted = the requests
+ * before it.  One call instead of `count`, for hosts whose per-call overhead
+ * would otherwise sit between two rounds.  SFLS_EINVAL: NULL srv or accepted,
+ * count < 0, or NULL arrays with count > 0. */
+sfls_status sfls_server_submit_many(sfls_server* srv, int32_t count, const void* const* ys,
+                                    const int64_t* ns, const uint64_t* tags, int32_t* accepted);
 /* Enqueue one round on the server's stream (no-op when nothing is admitted
  * or a round is already in flight).  Returns without waiting. */
 sfls_status sfls_server_launch(sfls_server* srv);

@@ -32,8 +32,8 @@ EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror"
            "sfls_set_timing", "sfls_reset_stats", "sfls_kernel_stats", "sfls_last_run",
            "sfls_set_factor", "sfls_set_nufft", "sfls_set_schur_lds", "sfls_server_config_default",
            "sfls_server_create", "sfls_server_destroy", "sfls_server_footprint",
-           "sfls_server_submit", "sfls_server_launch", "sfls_server_wait", "sfls_server_step",
-           "sfls_server_poll", "sfls_server_get_stats"]
+           "sfls_server_submit", "sfls_server_submit_many", "sfls_server_launch",
+           "sfls_server_wait", "sfls_server_step", "sfls_server_poll", "sfls_server_get_stats"]
 SFLS_FACTOR_AUTO, SFLS_FACTOR_LEVINSON, SFLS_FACTOR_SCHUR = 0, 1, 2
 SFLS_NUFFT_AUTO, SFLS_NUFFT_OFF, SFLS_NUFFT_ON = 0, 1, 2
 
@@ -170,6 +170,9 @@ def lib() -> ctypes.CDLL:
     L.sfls_server_footprint.restype = st
     L.sfls_server_submit.argtypes = [_P, _P, i64, u64]
     L.sfls_server_submit.restype = st
+    L.sfls_server_submit_many.argtypes = [_P, ctypes.c_int32, _P, _P, _P,
+                                          ctypes.POINTER(ctypes.c_int32)]
+    L.sfls_server_submit_many.restype = st
     L.sfls_server_launch.argtypes = [_P]
     L.sfls_server_launch.restype = st
     L.sfls_server_wait.argtypes = [_P, i32, _I32P, _I32P]
@@ -472,6 +475,21 @@ class Server:
             return False
         self.ctx.check(st)
         return True
+
+    def submit_many(self, ptrs, ns, tags) -> int:
+        """Admit requests in order (device or host addresses `ptrs`, lengths
+        `ns`, tags `tags`) until one is not admitted; returns how many were."""
+        ptrs = np.ascontiguousarray(ptrs, dtype=np.uint64)
+        ns = np.ascontiguousarray(ns, dtype=np.int64)
+        tags = np.ascontiguousarray(tags, dtype=np.uint64)
+        if not (len(ptrs) == len(ns) == len(tags)):
+            raise ValueError("ptrs, ns and tags differ in length")
+        acc = ctypes.c_int32(0)
+        self.ctx.check(lib().sfls_server_submit_many(
+            self._h, len(ptrs), ptrs.ctypes.data_as(ctypes.c_void_p),
+            ns.ctypes.data_as(ctypes.c_void_p), tags.ctypes.data_as(ctypes.c_void_p),
+            ctypes.byref(acc)))
+        return int(acc.value)
 
     def launch(self):
         self.ctx.check(lib().sfls_server_launch(self._h))

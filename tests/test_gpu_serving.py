@@ -258,3 +258,38 @@ def test_host_and_device_signals_give_the_same_result(ctx):
             srv.close()
     for a, b in zip(*out):
         same(a, b)
+
+
+def test_submit_many_admits_in_order_until_full(ctx):
+    """sfls_server_submit_many admits requests in order until the slots run
+    out (the rest are left to the caller), and each result is bitwise the one
+    the request gets when submitted alone."""
+    ns = [256, 700, 1024, 300, 512, 128]
+    insts = signals(ns, seed=3)
+    y, addr = to_device(insts)
+    p = sf.default_params(precision=sf.SFLS_MIXED)
+    srv = sf.Server(ctx, max_n=1024, max_slots=4, hbm_bytes=1 << 30, params=p)
+    try:
+        alone = run_alone(srv, insts, addr)
+        tags = np.arange(len(insts), dtype=np.uint64)
+        ptrs = np.array(addr, dtype=np.uint64)
+        nn = np.array(ns, dtype=np.int64)
+        first = srv.submit_many(ptrs, nn, tags)
+        assert first == 4  # four slots
+        nxt, out = first, {}
+        for _ in range(100000):
+            srv.step()
+            for r in srv.poll():
+                out[r.tag] = r
+            if nxt < len(insts):
+                nxt += srv.submit_many(ptrs[nxt:], nn[nxt:], tags[nxt:])
+            if len(out) == len(insts):
+                break
+        assert srv.submit_many(ptrs[:0], nn[:0], tags[:0]) == 0
+        with pytest.raises(sf.SflsError):
+            srv.submit_many(ptrs[:1], np.array([1], dtype=np.int64), tags[:1])  # n < 2
+    finally:
+        srv.close()
+    assert sorted(out) == list(range(len(insts)))
+    for k in range(len(insts)):
+        same(alone[k], out[k])
