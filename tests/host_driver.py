@@ -154,8 +154,14 @@ class HostDriver:
 
     def run(self, max_steps=100000):
         L = lib()
+        # (request the step consumed, request it made), per step
+        self.req_seq = []
+        prev = 0
         for _ in range(max_steps):
             L.drv_step(ctypes.byref(self.prm), ctypes.byref(self.st), ctypes.byref(self.arr))
+            req = int(self.a["req"][0]) if not self.st.done else 0
+            self.req_seq.append((prev, req))
+            prev = req
             if self.st.done:
                 break
             if self.a["req"][0]:

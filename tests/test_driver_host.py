@@ -56,3 +56,27 @@ def test_host_driver_approximate_off_matches_oracle():
     r = hd.HostDriver(inst.y, p).run()
     assert r["K"] == o.K
     np.testing.assert_allclose(r["theta"], o.theta, rtol=0, atol=1e-12)
+
+
+REQ_EVAL, REQ_GRID = 1, 2
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_grid_sweeps_at_the_evaluated_point_fit_the_evaluating_round(idx):
+    """The device round runs a first driver pass over the requests without a
+    grid sweep, then the grid stage and a second pass.  A grid sweep at an
+    unchanged point (a request with the grid bit and no evaluation) is always
+    asked for by a step that consumed an evaluation alone, so the first pass
+    makes it and the same round serves it: rounds = the requests that carry
+    an evaluation (one fewer per outer iteration than one request per round)."""
+    inst = _instances()[idx]
+    drv = hd.HostDriver(inst.y)
+    r = drv.run()
+    seq = drv.req_seq
+    grid_only = [(a, b) for a, b in seq if (b & REQ_GRID) and not (b & REQ_EVAL)]
+    for consumed, made in grid_only:
+        assert consumed & REQ_EVAL and not consumed & REQ_GRID, (consumed, made)
+    requests = [b for _, b in seq if b]
+    with_eval = [b for b in requests if b & REQ_EVAL]
+    assert len(grid_only) == len(requests) - len(with_eval)
+    assert len(grid_only) >= 1 and r["iterations"] >= 1
