@@ -221,13 +221,15 @@ __device__ __forceinline__ int fft_ks_max(int na, int logn) {
 // whose stages all have 2h <= FFT_TWL come from tl (an LDS copy of the table
 // head, or the global table itself), the others from the global table tg;
 // those are always 4-stage passes (first DIF / last DIT pass of n > FFT_TWL).
+// stop > 0 leaves the last `stop` stages (h < 2^stop) to the caller.
 template <int NT, typename C>
 __device__ __forceinline__ void dif_fftn(C* x, C* y, int na, int logn, bool cx, bool cy,
-                                         const C* __restrict__ tl, const C* __restrict__ tg) {
+                                         const C* __restrict__ tl, const C* __restrict__ tg,
+                                         int stop = 0) {
   const int km = fft_ks_max(na, logn);
   int lh = logn - 1;
-  while (lh >= 0) {
-    const int ks = lh + 1 < km ? lh + 1 : km;
+  while (lh >= stop) {
+    const int ks = lh + 1 - stop < km ? lh + 1 - stop : km;
     const int lg = logn - ks;  // log2(groups per transform)
     const int tot = na << lg;
     const bool lds_tw = (2 << lh) <= FFT_TWL;
@@ -252,15 +254,17 @@ __device__ __forceinline__ void dif_fftn(C* x, C* y, int na, int logn, bool cx, 
   }
 }
 
+// start > 0: the first `start` stages (h < 2^start) were done by the caller.
 template <int NT, typename C>
 __device__ __forceinline__ void dit_fftn(C* x, C* y, int na, int logn, bool cx, bool cy,
-                                         const C* __restrict__ tl, const C* __restrict__ tg) {
+                                         const C* __restrict__ tl, const C* __restrict__ tg,
+                                         int start = 0) {
   const int km = fft_ks_max(na, logn);
-  const int rem = logn % km;
-  int lb = 0;
+  const int rem = (logn - start) % km;
+  int lb = start;
   while (lb < logn) {
     // the shorter pass first, so that the last (largest-h) pass has km stages
-    const int ks = (lb == 0 && rem) ? rem : km;
+    const int ks = (lb == start && rem) ? rem : km;
     const int lg = logn - ks;
     const int tot = na << lg;
     const bool lds_tw = (2 << (lb + ks - 1)) <= FFT_TWL;

@@ -8,6 +8,9 @@ namespace sfls {
 
 constexpr int CONV_NT = 512;
 
+struct cd3x2 { cd3 p, q; };
+struct cd4x2 { cd4 p, q; };
+
 // W_P^m = exp(-j 2 pi m / P) evaluated from the exact fraction (m mod P) / P:
 // the points of a pointwise step need it at scattered m, where a table would
 // be gathered one cache line per lane
@@ -79,61 +82,107 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
   // The transform buffer: LDS, or for P > CONV_LDS_P the instance's scratch
   // after its four P blocks (the same passes, on global memory).
   auto body = [&](cd* __restrict__ lds) __attribute__((always_inline)) {
+    // The h = 1 stage of each transform (the last of a forward one, the first
+    // of an inverse one) runs on bit-reversed pairs (2g, 2g+1) inside the
+    // neighbouring loop instead of an LDS pass of its own; the same
+    // butterfly and twiddle (W_2^0 from the table, conjugated for inverses).
+    // A pair belongs to one thread; other threads' indices are touched only
+    // after a barrier.
+    const cd w1 = s_tw[1];
+    const cd w1c{w1.x, -w1.y};
+    auto dif_pair = [&](int g, cd& a, cd& b) {
+      const cd u = lds[pidx(2 * g)], v = lds[pidx(2 * g + 1)];
+      a = cadd(u, v);
+      b = cmul(csub(u, v), w1);
+    };
+    auto dit_pair = [&](int g, cd a, cd b) {
+      const cd v = cmul(b, w1c);
+      lds[pidx(2 * g)] = cadd(a, v);
+      lds[pidx(2 * g + 1)] = csub(a, v);
+    };
+    auto spectrum_to = [&](cd* __restrict__ dst) {
+      for (int g = tid; g < P / 2; g += CONV_NT) {
+        cd a, b;
+        dif_pair(g, a, b);
+        dst[2 * g] = a;
+        dst[2 * g + 1] = b;
+      }
+      __syncthreads();
+    };
     // (1) A = FFT(rho)
     auto to_lds = [&](int t, cd v) { lds[pidx(t)] = v; };
     batched_for<8>(tid, CONV_NT, P, [&](int t) { return (t < N) ? rb[t] : cd{0.0, 0.0}; }, to_lds);
     __syncthreads();
-    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
-    for (int t = tid; t < P; t += CONV_NT) A[t] = lds[pidx(t)];
+    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws, 1);
+    spectrum_to(A);
     // (2) Y = FFT(y^)
     batched_for<8>(tid, CONV_NT, P,
                    [&](int t) { return (t < N) ? load_y(yb, N - 1 - t) : cd{0.0, 0.0}; }, to_lds);
     __syncthreads();
-    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
-    for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[pidx(t)];
-    __syncthreads();
+    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws, 1);
+    spectrum_to(Y);
     // (3) u1 from FFT(rho~) . Y
-    batched_for<4>(tid, CONV_NT, P, [&](int p) {
-      const int f = bitrev(p, logP);
-      const int pm = bitrev((P - f) & (P - 1), logP);
-      return cd3{w_pow((int64_t)f * (N - 1), logP), A[pm], Y[p]};
-    }, [&](int p, cd3 g) { lds[pidx(p)] = cmul(cmul(g.a, g.b), g.c); });
+    batched_for<2>(tid, CONV_NT, P / 2, [&](int g) {
+      cd3 r[2];
+      for (int k = 0; k < 2; ++k) {
+        const int p = 2 * g + k;
+        const int f = bitrev(p, logP);
+        const int pm = bitrev((P - f) & (P - 1), logP);
+        r[k] = cd3{w_pow((int64_t)f * (N - 1), logP), A[pm], Y[p]};
+      }
+      return cd3x2{r[0], r[1]};
+    }, [&](int g, cd3x2 v) {
+      dit_pair(g, cmul(cmul(v.p.a, v.p.b), v.p.c), cmul(cmul(v.q.a, v.q.b), v.q.c));
+    });
     __syncthreads();
-    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
+    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws, 1);
     for (int i = tid; i < N; i += CONV_NT) X1[i] = cscale(lds[pidx(N - 1 - i)], invP);
     __syncthreads();
     // (4) v1 from conj(A(-f)) . Y
-    batched_for<4>(tid, CONV_NT, P, [&](int p) {
-      const int f = bitrev(p, logP);
-      const int pm = bitrev((P - f) & (P - 1), logP);
-      return cd3{A[pm], Y[p], cd{0.0, 0.0}};
-    }, [&](int p, cd3 g) { lds[pidx(p)] = cmul(cconj(g.a), g.b); });
+    batched_for<2>(tid, CONV_NT, P / 2, [&](int g) {
+      cd2 r[2];
+      for (int k = 0; k < 2; ++k) {
+        const int p = 2 * g + k;
+        const int f = bitrev(p, logP);
+        const int pm = bitrev((P - f) & (P - 1), logP);
+        r[k] = cd2{A[pm], Y[p]};
+      }
+      return cd4{r[0].a, r[0].b, r[1].a, r[1].b};
+    }, [&](int g, cd4 v) { dit_pair(g, cmul(cconj(v.a), v.b), cmul(cconj(v.c), v.d)); });
     __syncthreads();
-    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
+    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws, 1);
     for (int i = tid; i < N; i += CONV_NT)
       X2[i] = (i <= N - 2) ? cscale(lds[pidx(N - 2 - i)], invP) : cd{0.0, 0.0};
     __syncthreads();
     // (5) U = FFT(u1) -> Y
     batched_for<8>(tid, CONV_NT, P, [&](int t) { return (t < N) ? X1[t] : cd{0.0, 0.0}; }, to_lds);
     __syncthreads();
-    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
-    for (int t = tid; t < P; t += CONV_NT) Y[t] = lds[pidx(t)];
-    __syncthreads();
-    // (6) V = FFT(v1), kept in LDS
+    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws, 1);
+    spectrum_to(Y);
+    // (6) V = FFT(v1), kept in LDS (its h = 1 stage in step 7)
     batched_for<8>(tid, CONV_NT, P, [&](int t) { return (t < N) ? X2[t] : cd{0.0, 0.0}; }, to_lds);
     __syncthreads();
-    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws);
+    dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws, 1);
     // (7) W = FFT(conj rho~) U - W^f A V
-    batched_for<4>(tid, CONV_NT, P, [&](int p) {
-      const int f = bitrev(p, logP);
-      return cd4{A[p], Y[p], w_pow((int64_t)f * (N - 1), logP), w_pow(f, logP)};
-    }, [&](int p, cd4 g) {
-      const cd t1 = cmul(cmul(g.c, cconj(g.a)), g.b);
-      const cd t2 = cmul(cmul(g.d, g.a), lds[pidx(p)]);
-      lds[pidx(p)] = csub(t1, t2);
+    batched_for<2>(tid, CONV_NT, P / 2, [&](int g) {
+      cd4 r[2];
+      for (int k = 0; k < 2; ++k) {
+        const int p = 2 * g + k;
+        const int f = bitrev(p, logP);
+        r[k] = cd4{A[p], Y[p], w_pow((int64_t)f * (N - 1), logP), w_pow(f, logP)};
+      }
+      return cd4x2{r[0], r[1]};
+    }, [&](int g, cd4x2 v) {
+      cd V0, V1;
+      dif_pair(g, V0, V1);
+      const cd t10 = cmul(cmul(v.p.c, cconj(v.p.a)), v.p.b);
+      const cd t20 = cmul(cmul(v.p.d, v.p.a), V0);
+      const cd t11 = cmul(cmul(v.q.c, cconj(v.q.a)), v.q.b);
+      const cd t21 = cmul(cmul(v.q.d, v.q.a), V1);
+      dit_pair(g, csub(t10, t20), csub(t11, t21));
     });
     __syncthreads();
-    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws);
+    dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws, 1);
     const double sc = invP / delta[in.off + N - 1];
     double acc[2] = {0.0, 0.0};
     batched_for<8>(tid, CONV_NT, N, [&](int i) { return load_y(yb, i); }, [&](int i, cd yi) {
