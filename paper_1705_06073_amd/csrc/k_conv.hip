@@ -84,21 +84,19 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
   auto body = [&](cd* __restrict__ lds) __attribute__((always_inline)) {
     // The h = 1 stage of each transform (the last of a forward one, the first
     // of an inverse one) runs on bit-reversed pairs (2g, 2g+1) inside the
-    // neighbouring loop instead of an LDS pass of its own; the same
-    // butterfly and twiddle (W_2^0 from the table, conjugated for inverses).
-    // A pair belongs to one thread; other threads' indices are touched only
-    // after a barrier.
-    const cd w1 = s_tw[1];
-    const cd w1c{w1.x, -w1.y};
+    // neighbouring loop instead of an LDS pass of its own.  Its only twiddle
+    // is W_2^0 = 1, so the butterfly is a plain sum and difference (no table
+    // read: the LDS twiddle table is not yet published to every wave when
+    // this lambda is entered).  A pair belongs to one thread; other threads'
+    // indices are touched only after a barrier.
     auto dif_pair = [&](int g, cd& a, cd& b) {
       const cd u = lds[pidx(2 * g)], v = lds[pidx(2 * g + 1)];
       a = cadd(u, v);
-      b = cmul(csub(u, v), w1);
+      b = csub(u, v);
     };
     auto dit_pair = [&](int g, cd a, cd b) {
-      const cd v = cmul(b, w1c);
-      lds[pidx(2 * g)] = cadd(a, v);
-      lds[pidx(2 * g + 1)] = csub(a, v);
+      lds[pidx(2 * g)] = cadd(a, b);
+      lds[pidx(2 * g + 1)] = csub(a, b);
     };
     auto spectrum_to = [&](cd* __restrict__ dst) {
       for (int g = tid; g < P / 2; g += CONV_NT) {
