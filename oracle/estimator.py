@@ -13,8 +13,8 @@ Follows the block-coordinate descent of Sec. II-C/E step by step:
   stop when the objective changes by less than N * 1e-7 between iterations,
 
 followed by a final Newton-type polish of (theta, gamma) with z, beta, zeta
-held fixed.  The paper leaves several points open; each reading taken here is
-a field of :class:`Params` and is listed in DESIGN.md ("Readings").
+held fixed (:meth:`OracleEstimator._polish`).  The paper leaves several points
+open; each reading taken here is a field of :class:`Params`.
 """
 from __future__ import annotations
 
@@ -45,8 +45,8 @@ class Params:
     ls_max: int = 30
     curv_eps: float = 1e-12
     polish_max_iters: int = 30
-    polish_tol: float = 1e-12    # stop polish when max |dtheta| < polish_tol / N
-    polish_ftol: float = 1e-13   # relative objective slack for polish steps
+    polish_tol: float = 1e-12    # polish converged when max |dtheta| < polish_tol / N
+    polish_ftol: float = 1e-13   # rounding level of the objective, relative to 1 + |f|
     kcap: int = 0                # 0: K_max = N
 
     def grid_size(self, N: int) -> int:
@@ -71,11 +71,6 @@ class Result:
     evaluations: int
     status: int
     trace: list = field(default_factory=list)
-
-
-# A polish line search tries at most this many step lengths (alpha >= 2^-8 of
-# the first); a step that needs more is in the rounding noise of the objective.
-POLISH_LS_TRIALS = 9
 
 
 class _Memory:
@@ -195,73 +190,120 @@ class OracleEstimator:
         N, L = self.N, self.L
         qG, sG, dl = self._grid_delta_L(ev, gamma, zeta)
         lmin = int(np.argmin(dl))
-        locmin = np.nonzero((dl <= np.roll(dl, 1)) & (dl <= np.roll(dl, -1)))[0]
+        locmin = local_minima(dl)
         th_all = np.concatenate([[lmin / L], locmin / L])
         q_all = nm.q_at(ev.w, th_all)
         s_all = nm.s_at(ev.omega[0], th_all)
         _, _, dl_min = self._decision_quantities(q_all[0], s_all[0], gamma, zeta)
-        cands = []
         tau = p.tau if p.approx_use_tau else 0.0
-        for j, l in enumerate(locmin):
+        dls, ghs, oks = [], [], []
+        for j in range(len(locmin)):
             q, s = q_all[j + 1], s_all[j + 1]
             gb, gh, dlv = self._decision_quantities(q, s, gamma, zeta)
-            if (gh > 0 and zeta > 0 and bool(nm.activation_criterion(q, s, gb, zeta, tau))
-                    and dlv <= dl_min / p.approx_ratio):
-                cands.append((dlv, int(l), gh))
-        cands.sort()
-        new_th, new_g = [], []
-        for dlv, l, gh in cands:
-            if len(theta) + len(new_th) >= self.kcap:
-                self.cap_hit = True
-                break
-            th = l / L
-            others = np.concatenate([np.asarray(theta), np.asarray(new_th)])
-            if len(others) == 0 or float(np.min(nm_wrap(th, others))) >= p.approx_min_dist / N:
-                new_th.append(th)
-                new_g.append(gh)
-        self.trace.append(("approx", len(locmin), len(cands), len(new_th)))
+            dls.append(dlv)
+            ghs.append(gh)
+            oks.append(gh > 0 and zeta > 0 and bool(nm.activation_criterion(q, s, gb, zeta, tau)))
+        new_th, new_g, cap = approx_select(dl_min, locmin, dls, ghs, oks, theta, N, L,
+                                           p.approx_ratio, p.approx_min_dist,
+                                           self.kcap - len(theta))
+        self.cap_hit = self.cap_hit or cap
+        self.trace.append(("approx", len(locmin), int(sum(oks)), len(new_th)))
         return new_th, new_g
 
     # ------------------------------------------------------------------
-    def _line_search(self, ev, theta, gamma, beta, K, zeta, g, d, polish=False):
+    @staticmethod
+    def _step_limit(gamma, dga):
+        """Largest step keeping every gamma >= 0, and the first k that reaches it."""
+        neg = dga < 0
+        if not np.any(neg):
+            return math.inf, -1
+        ratios = np.where(neg, gamma / np.where(neg, -dga, 1.0), math.inf)
+        kstar = int(np.argmin(ratios))
+        return float(ratios[kstar]), kstar
+
+    def _line_search(self, ev, theta, gamma, beta, K, zeta, g, d):
+        """Backtracking Armijo search of an inner L-BFGS step (Sec. II-D; gamma kept >= 0)."""
         p = self.p
         f0 = ev.f(K, zeta)
         gd = float(np.dot(g, d))
         dth, dga = d[:K], d[K:]
-        neg = dga < 0
-        amax = math.inf
-        kstar = -1
-        if np.any(neg):
-            ratios = np.where(neg, gamma / np.where(neg, -dga, 1.0), math.inf)
-            kstar = int(np.argmin(ratios))
-            amax = float(ratios[kstar])
-        if polish:
-            alpha = 1.0 if amax > 1.0 else 0.5 * amax
-        else:
-            alpha = min(1.0, amax)
-        slack = p.polish_ftol * (1.0 + abs(f0)) if polish else 0.0
-        dth_max = float(np.max(np.abs(dth))) if K else 0.0
+        amax, kstar = self._step_limit(gamma, dga)
+        alpha = min(1.0, amax)
         resolution = p.polish_ftol * (1.0 + abs(f0))
         for trial in range(p.ls_max):
-            # the polish gives up once a shortened step could no longer move any
-            # frequency by the polish tolerance (it would stop after it anyway)
-            if polish and trial > 0 and (alpha * dth_max < p.polish_tol / self.N
-                                         or trial >= POLISH_LS_TRIALS):
-                return None
-            # the inner search gives up once the decrease it requires is below
-            # the rounding level of the objective (the test would decide nothing)
-            if not polish and trial > 0 and p.ls_c1 * alpha * abs(gd) < resolution:
+            # the search gives up once the decrease it requires is below the
+            # rounding level of the objective (the test would decide nothing)
+            if trial > 0 and p.ls_c1 * alpha * abs(gd) < resolution:
                 return None
             th_t = np.mod(theta + alpha * dth, 1.0)
             ga_t = np.maximum(gamma + alpha * dga, 0.0)
-            if (not polish) and alpha == amax and kstar >= 0:
+            if alpha == amax and kstar >= 0:
                 ga_t[kstar] = 0.0
             ev_t = self.evaluate(th_t, ga_t, beta)
             f_t = ev_t.f(K, zeta)
-            if f_t <= f0 + p.ls_c1 * alpha * gd + slack:
+            if f_t <= f0 + p.ls_c1 * alpha * gd:
                 return ev_t, th_t, ga_t, alpha
             alpha *= 0.5
         return None
+
+    def _polish(self, cur, theta, gamma, beta, zeta):
+        """Final Newton-type refinement of (theta, gamma) with z, beta, zeta fixed.
+
+        The paper stops on the objective change (Sec. II-E), which leaves the
+        frequencies determined only to the objective's flatness; this
+        refinement drives them to a stationary point of eq. obj so that the
+        result no longer depends on the trajectory.  Each step is the L-BFGS
+        direction d (memory reset at the start, diagonal Hessian as H0); a
+        trial point is accepted when it satisfies the Armijo condition, or,
+        once the objective change is within its rounding level
+        (polish_ftol (1 + |f|)), when it lowers the diagonal Newton decrement
+        nu = sum_i g_i^2 / h_i (there the objective no longer resolves the
+        step, the gradient still does).  The first trial is alpha = 1 (or half
+        the step that zeroes a gamma), halved on rejection.  The refinement
+        has converged when an accepted step moves no frequency by
+        polish_tol / N, or when the trial step has been shortened below that
+        without being accepted (the point is then left unchanged).
+        """
+        p, N = self.p, self.N
+        mem = _Memory(p.lbfgs_J)
+        tol = p.polish_tol / N
+        for _pit in range(p.polish_max_iters):
+            K = len(theta)
+            if K == 0:
+                break
+            g, h = self._derivs(cur, gamma)
+            d = self._direction(mem, g, h)
+            nu0 = float(np.sum(g * g / h))
+            f0 = cur.f(K, zeta)
+            gd = float(np.dot(g, d))
+            dth, dga = d[:K], d[K:]
+            amax, _ = self._step_limit(gamma, dga)
+            alpha = 1.0 if amax > 1.0 else 0.5 * amax
+            dth_max = float(np.max(np.abs(dth)))
+            slack = p.polish_ftol * (1.0 + abs(f0))
+            acc = None
+            for trial in range(p.ls_max):
+                if trial > 0 and alpha * dth_max < tol:
+                    break
+                th_t = np.mod(theta + alpha * dth, 1.0)
+                ga_t = np.maximum(gamma + alpha * dga, 0.0)
+                ev_t = self.evaluate(th_t, ga_t, beta)
+                f_t = ev_t.f(K, zeta)
+                g_t, h_t = self._derivs(ev_t, ga_t)
+                if f_t <= f0 + p.ls_c1 * alpha * gd or \
+                        (f_t <= f0 + slack and float(np.sum(g_t * g_t / h_t)) < nu0):
+                    acc = (ev_t, th_t, ga_t, g_t)
+                    break
+                alpha *= 0.5
+            if acc is None:
+                self.trace.append(("polish_stop", _pit, alpha * dth_max * N))
+                break
+            ev_t, th_t, ga_t, g_t = acc
+            mem.push(alpha * d, g_t - g, p.curv_eps)
+            theta, gamma, cur = th_t, ga_t, ev_t
+            if alpha * dth_max < tol:
+                break
+        return cur, theta, gamma
 
     def _direction(self, mem, g, h):
         d = mem.direction(g, h)
@@ -379,23 +421,7 @@ class OracleEstimator:
             L_prev = L_cur
 
         # ---- final polish of (theta, gamma) with z, beta, zeta fixed ---------
-        mem.reset()
-        cur = ensure(cur)
-        for _pit in range(p.polish_max_iters):
-            K = len(theta)
-            if K == 0:
-                break
-            g, h = self._derivs(cur, gamma)
-            d = self._direction(mem, g, h)
-            ls = self._line_search(cur, theta, gamma, beta, K, zeta, g, d, polish=True)
-            if ls is None:
-                break
-            ev_t, th_t, ga_t, alpha = ls
-            g_t, _ = self._derivs(ev_t, ga_t)
-            mem.push(alpha * d, g_t - g, p.curv_eps)
-            theta, gamma, cur = th_t, ga_t, ev_t
-            if float(np.max(np.abs(alpha * d[:K]))) < p.polish_tol / N:
-                break
+        cur, theta, gamma = self._polish(ensure(cur), theta, gamma, beta, zeta)
 
         K = len(theta)
         alpha_hat = gamma * cur.act["q"] if K else np.zeros(0, np.complex128)
@@ -408,8 +434,50 @@ class OracleEstimator:
 
 
 def nm_wrap(x, arr):
+    """Wrap-around distance on the unit circle between x and each entry of arr."""
     a = np.abs(np.asarray(arr, dtype=np.float64) - x) % 1.0
     return np.minimum(a, 1.0 - a)
+
+
+def local_minima(dl) -> np.ndarray:
+    """Grid indices l with dl[l] <= dl[l-1] and dl[l] <= dl[l+1], indices taken
+    cyclically (the grid covers the unit circle; Sec. II-F)."""
+    dl = np.asarray(dl)
+    return np.nonzero((dl <= np.roll(dl, 1)) & (dl <= np.roll(dl, -1)))[0]
+
+
+def approx_select(dl_min, cand_l, cand_dl, cand_gh, cand_ok, theta_active, N, L,
+                  ratio=5.0, min_dist=0.05, room=None):
+    """The filters of the approximate activation scheme (Sec. II-F) on the local
+    minima of one grid sweep.
+
+    dl_min          Delta L at the grid argmin (FP64 re-evaluation)
+    cand_l          grid indices of the local minima
+    cand_dl, cand_gh Delta L and gamma_hat at each (FP64)
+    cand_ok         gamma_hat > 0, zeta > 0 and the activation criterion hold
+    theta_active    frequencies active before the sweep
+    room            components that may still be added (None: unlimited)
+
+    A candidate qualifies when cand_ok holds and its Delta L <= dl_min / ratio.
+    Qualifying candidates are taken by ascending (Delta L, grid index) and each
+    is added unless its wrap distance to an active frequency, or to one already
+    added in this sweep, is below min_dist / N.  Returns (thetas, gammas,
+    capacity_hit)."""
+    quals = sorted((float(d), int(l), float(g)) for d, l, g, ok in
+                   zip(cand_dl, cand_l, cand_gh, cand_ok) if ok and d <= dl_min / ratio)
+    new_th, new_g = [], []
+    cap = False
+    for dlv, l, gh in quals:
+        if room is not None and len(new_th) >= room:
+            cap = True
+            break
+        th = l / L
+        others = np.concatenate([np.asarray(theta_active, dtype=np.float64),
+                                 np.asarray(new_th, dtype=np.float64)])
+        if len(others) == 0 or float(np.min(nm_wrap(th, others))) >= min_dist / N:
+            new_th.append(th)
+            new_g.append(gh)
+    return new_th, new_g, cap
 
 
 def estimate(y, params: Params | None = None, check_blocks: bool = False) -> Result:

@@ -45,7 +45,7 @@ enum : int32_t {
 struct DrvState {
   int32_t phase, it, inner, pit, ls_trial, K, approx_on, z_changed, cur_valid, converged,
       cap_hit, polish, mem_n, mem_head, kstar, status, nevals, done, saved, pad_;
-  double beta, zeta, eps_beta, yy, L_prev, f_cur, lam2, alpha, amax, gd;
+  double beta, zeta, eps_beta, yy, L_prev, f_cur, lam2, alpha, amax, gd, nu0;
 };
 
 // Per-instance array views (device pointers, offset to this instance).
@@ -137,10 +137,6 @@ struct SerialTeam {
   SFLS_HD static void sync() {}
 };
 
-// A polish line search tries at most this many step lengths (alpha >= 2^-8 of
-// the first); a step that needs more is in the rounding noise of the objective.
-constexpr int kPolishLsTrials = 9;
-
 template <typename T>
 struct Driver {
   const DrvParams& P;
@@ -174,52 +170,64 @@ struct Driver {
     if (bits & 1) S.nevals += 1;
   }
 
-  // gradient and replaced diagonal Hessian from the evaluation results
-  // (eqs. derivative, derivative2; replacements (50N)^2 and gamma^-2)
+  // gradient and replaced diagonal Hessian of component k from the
+  // evaluation results (eqs. derivative, derivative2; replacements (50N)^2
+  // and gamma^-2)
+  SFLS_HD void deriv_k(int k, double gk, double& gth, double& gga, double& hth,
+                       double& hga) const {
+    const double qr = A.ev_q[2 * k], qi = A.ev_q[2 * k + 1];
+    const double rr = A.ev_r[2 * k], ri = A.ev_r[2 * k + 1];
+    const double ur = A.ev_u[2 * k], ui = A.ev_u[2 * k + 1];
+    const double s = A.ev_s[2 * k];
+    const double tr = A.ev_t[2 * k], ti = A.ev_t[2 * k + 1];
+    const double vr = A.ev_v[2 * k];
+    const double xr = A.ev_x[2 * k];
+    const double q2 = qr * qr + qi * qi, r2 = rr * rr + ri * ri;
+    // Im(t - conj(q) r)
+    const double im_t_qr = ti - (qr * ri - qi * rr);
+    gth = 2.0 * gk * im_t_qr;
+    gga = s - q2;
+    // Re{ x - v + g(t^2 - x s) + g(x|q|^2 + s|r|^2 - 2 t r conj q) + (u conj q - |r|^2) }
+    const double t2r = tr * tr - ti * ti;
+    const double xsr = xr * s;
+    // t r conj(q)
+    const double trr = tr * rr - ti * ri, tri = tr * ri + ti * rr;
+    const double trq = trr * qr + tri * qi;
+    const double uq = ur * qr + ui * qi;
+    const double inner = xr - vr + gk * (t2r - xsr) + gk * (xr * q2 + s * r2 - 2.0 * trq) +
+                         (uq - r2);
+    hth = 2.0 * gk * inner;
+    hga = 2.0 * s * q2 - s * s;
+    if (!(hth > 0.0)) hth = (50.0 * N) * (50.0 * N);
+    if (!(hga > 0.0)) hga = (gk > 0.0) ? 1.0 / (gk * gk) : 1.0;
+  }
+
+  // gradient g and (if h) replaced diagonal Hessian at the evaluated point
   SFLS_HD void derivs(const double* __restrict__ gam, double* __restrict__ g,
                       double* __restrict__ h) const {
     const int K = S.K;
-    const double* __restrict__ eq = A.ev_q;
-    const double* __restrict__ er = A.ev_r;
-    const double* __restrict__ eu = A.ev_u;
-    const double* __restrict__ es = A.ev_s;
-    const double* __restrict__ et = A.ev_t;
-    const double* __restrict__ ev = A.ev_v;
-    const double* __restrict__ ex = A.ev_x;
     for (int k = T::lane(); k < K; k += T::width()) {
-      const double qr = eq[2 * k], qi = eq[2 * k + 1];
-      const double rr = er[2 * k], ri = er[2 * k + 1];
-      const double ur = eu[2 * k], ui = eu[2 * k + 1];
-      const double s = es[2 * k];
-      const double tr = et[2 * k], ti = et[2 * k + 1];
-      const double vr = ev[2 * k];
-      const double xr = ex[2 * k], xi = ex[2 * k + 1];
-      const double gk = gam[k];
-      const double q2 = qr * qr + qi * qi, r2 = rr * rr + ri * ri;
-      // Im(t - conj(q) r)
-      const double im_t_qr = ti - (qr * ri - qi * rr);
-      g[k] = 2.0 * gk * im_t_qr;
-      g[K + k] = s - q2;
+      double gth, gga, hth, hga;
+      deriv_k(k, gam[k], gth, gga, hth, hga);
+      g[k] = gth;
+      g[K + k] = gga;
       if (h) {
-        // Re{ x - v + g(t^2 - x s) + g(x|q|^2 + s|r|^2 - 2 t r conj q) + (u conj q - |r|^2) }
-        const double t2r = tr * tr - ti * ti;
-        const double xsr = xr * s;
-        // t r conj(q)
-        const double trr = tr * rr - ti * ri, tri = tr * ri + ti * rr;
-        const double trq = trr * qr + tri * qi;
-        const double uq = ur * qr + ui * qi;
-        const double inner = xr - vr + gk * (t2r - xsr) + gk * (xr * q2 + s * r2 - 2.0 * trq) +
-                             (uq - r2);
-        double hth = 2.0 * gk * inner;
-        double hga = 2.0 * s * q2 - s * s;
-        if (!(hth > 0.0)) hth = (50.0 * N) * (50.0 * N);
-        if (!(hga > 0.0)) hga = (gk > 0.0) ? 1.0 / (gk * gk) : 1.0;
         h[k] = hth;
         h[K + k] = hga;
-        (void)xi;
       }
     }
     T::sync();
+  }
+
+  // diagonal Newton decrement sum_i g_i^2 / h_i at the evaluated point
+  SFLS_HD double newton_dec(const double* __restrict__ gam) const {
+    double nu = 0.0;
+    for (int k = T::lane(); k < S.K; k += T::width()) {
+      double gth, gga, hth, hga;
+      deriv_k(k, gam[k], gth, gga, hth, hga);
+      nu += gth * gth / hth + gga * gga / hga;
+    }
+    return T::sum(nu);
   }
 
   SFLS_HD double dot(const double* __restrict__ a, const double* __restrict__ b, int n) const {
@@ -645,8 +653,12 @@ struct Driver {
         }
         case L_LS_RESULT: {
           const double ft = f_of_eval();
-          const double slack = S.polish ? P.polish_ftol * (1.0 + fabs(S.f_cur)) : 0.0;
-          if (ft <= S.f_cur + P.ls_c1 * S.alpha * S.gd + slack) {
+          bool accept = ft <= S.f_cur + P.ls_c1 * S.alpha * S.gd;
+          // polish: within the objective's rounding level, a step is judged by
+          // the diagonal Newton decrement instead
+          if (!accept && S.polish && ft <= S.f_cur + P.polish_ftol * (1.0 + fabs(S.f_cur)))
+            accept = newton_dec(A.ga_e) < S.nu0;
+          if (accept) {
             // accept: pair (alpha d, g_t - g), move to the trial point
             const int K = S.K, n = 2 * K;
             derivs(A.ga_e, A.gt, nullptr);
@@ -682,7 +694,7 @@ struct Driver {
             double dmax = 0.0;
             for (int k = T::lane(); k < S.K; k += T::width()) dmax = fmax(dmax, fabs(A.d[k]));
             dmax = T::max(dmax);
-            give_up = S.alpha * dmax < P.polish_tol / (double)N || S.ls_trial >= kPolishLsTrials;
+            give_up = S.alpha * dmax < P.polish_tol / (double)N;
           }
           if (!S.polish && !give_up) {
             // the inner search stops once the decrease it requires is below the
@@ -753,6 +765,9 @@ struct Driver {
           if (S.pit >= P.polish_max_iters || S.K == 0) { lbl = L_FINAL; break; }
           const int n = 2 * S.K;
           derivs(A.ga, A.g, A.gt);
+          double nu = 0.0;
+          for (int e = T::lane(); e < n; e += T::width()) nu += A.g[e] * A.g[e] / A.gt[e];
+          S.nu0 = T::sum(nu);
           direction(A.g, A.gt, A.d, n);
           S.f_cur = f_of_eval();
           for (int e = T::lane(); e < n; e += T::width()) A.q_save[e] = A.ev_q[e];

@@ -51,7 +51,7 @@ class DrvState(ctypes.Structure):
                  "status", "nevals", "done", "saved", "pad_")] + \
                [(n, ctypes.c_double) for n in
                 ("beta", "zeta", "eps_beta", "yy", "L_prev", "f_cur", "lam2", "alpha", "amax",
-                 "gd")]
+                 "gd", "nu0")]
 
 
 _PTRS = ["th", "ga", "th_e", "ga_e", "K_e", "beta_e", "req", "gbar_e", "zeta_e", "g", "d", "Sm",
@@ -154,6 +154,10 @@ class HostDriver:
 
     def run(self, max_steps=100000):
         L = lib()
+        sizes = (ctypes.c_int * 3)()
+        L.drv_sizes(sizes)
+        assert tuple(sizes) == (ctypes.sizeof(DrvParams), ctypes.sizeof(DrvState),
+                                ctypes.sizeof(DrvArrays)), "driver structs out of sync"
         # (request the step consumed, request it made), per step
         self.req_seq = []
         prev = 0
