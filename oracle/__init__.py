@@ -14,8 +14,9 @@ Modules
 numerics   -- covariance, factor (rho, delta, ln|C|), C^{-1} y, diagonal sums
               omega, active-set vectors q..x, grid q^G / s^G, derivatives,
               activation / deactivation quantities.
-estimator  -- the block-coordinate-descent estimator (Sec. II-C/D/E) with the
-              readings of silent points listed in the design doc.
+estimator  -- the block-coordinate-descent estimator (Sec. II-C/D/E); every
+              point the paper leaves open is a field of its Params with the
+              reading taken.
 metrics    -- wrap-around distance matching, BSR / CSR / NMSE (Sec. VI-A).
 
 Parity status: every numerics function is pinned by tests under

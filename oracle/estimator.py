@@ -71,6 +71,7 @@ class Result:
     evaluations: int
     status: int
     trace: list = field(default_factory=list)
+    margins: list = field(default_factory=list)
 
 
 class _Memory:
@@ -120,6 +121,22 @@ class OracleEstimator:
         self.n_evals = 0
         self.cap_hit = False
         self.trace: list = []
+        # (kind, site, outer iteration, relative margin) of every comparison that
+        # takes a discrete decision of the trajectory; a record only, it
+        # changes nothing that is computed
+        self.margins: list = []
+        self._it = 0
+
+    def _margin(self, kind, site, a, b, scale=None):
+        """Record how far a decision's two compared values are apart, relative
+        to their magnitude (or to `scale`).  Kinds: 'grid' (a ranking of grid
+        points, taken in the grid's precision), 'fp64' (every other decision);
+        `site` names the test."""
+        a, b = float(a), float(b)
+        den = scale if scale is not None else max(abs(a), abs(b))
+        if not (math.isfinite(a) and math.isfinite(b)) or den == 0.0:
+            return
+        self.margins.append((kind, site, self._it, abs(a - b) / den))
 
     # ------------------------------------------------------------------
     def _block(self, name, before, after):
@@ -176,6 +193,8 @@ class OracleEstimator:
         gb, gh, dlv = self._decision_quantities(q, s, gamma, zeta)
         ok = (gh > 0 and zeta > 0
               and bool(nm.activation_criterion(q, s, gb, zeta, p.tau)) and dlv < -p.eps_L)
+        self._record_grid_argmin(dl)
+        self._record_activation(q, s, gb, zeta, p.tau, dlv)
         self.trace.append(("exact", l, dlv, ok))
         if ok and len(theta) >= self.kcap:
             self.cap_hit = True
@@ -183,6 +202,22 @@ class OracleEstimator:
         if ok:
             return th, gh
         return None
+
+    def _record_grid_argmin(self, dl):
+        dlf = dl[np.isfinite(dl)]
+        if len(dlf) > 1:
+            two = np.partition(dlf, 1)[:2]
+            self._margin("grid", "argmin", two[0], two[1], float(np.max(np.abs(dlf))))
+
+    def _record_activation(self, q, s, gb, zeta, tau, dlv):
+        if not (zeta > 0 and s > 0 and gb > 0):
+            return
+        kappa = abs(q) ** 2 / s
+        lg = math.log((1.0 + gb * s) * ((1.0 - zeta) / zeta))
+        rhs = (1.0 + 1.0 / (gb * s)) * lg + tau
+        self._margin("fp64", "criterion", kappa, rhs)
+        self._margin("fp64", "gamma_hat", kappa, 1.0)               # gamma_hat > 0
+        self._margin("fp64", "delta_L", dlv, -self.p.eps_L, 1.0 + abs(lg))
 
     def _approx_activation(self, ev, theta, gamma, zeta):
         """Approximate scheme of Sec. II-F: all local minima of Delta L passing 4 filters."""
@@ -206,6 +241,21 @@ class OracleEstimator:
         new_th, new_g, cap = approx_select(dl_min, locmin, dls, ghs, oks, theta, N, L,
                                            p.approx_ratio, p.approx_min_dist,
                                            self.kcap - len(theta))
+        self._record_grid_argmin(dl)
+        big = float(np.max(np.abs(dl[np.isfinite(dl)]))) if np.any(np.isfinite(dl)) else 1.0
+        for j, l in enumerate(locmin):
+            q, s = q_all[j + 1], float(s_all[j + 1].real)
+            gb, _, _ = self._decision_quantities(q, s, gamma, zeta)
+            if dls[j] <= 0.5 * dl_min / p.approx_ratio or oks[j]:
+                # local-minimum tests of the grid points that could be chosen
+                self._margin("grid", "local_min", dl[l], min(dl[(l - 1) % L], dl[(l + 1) % L]), big)
+                self._record_activation(q, s, gb, zeta, tau, dls[j])
+                self._margin("fp64", "ratio", dls[j], dl_min / p.approx_ratio)
+        for th in new_th:
+            others = np.concatenate([np.asarray(theta, np.float64),
+                                     np.asarray([t for t in new_th if t != th], np.float64)])
+            if len(others):
+                self._margin("fp64", "distance", float(np.min(nm_wrap(th, others))) * N, p.approx_min_dist)
         self.cap_hit = self.cap_hit or cap
         self.trace.append(("approx", len(locmin), int(sum(oks)), len(new_th)))
         return new_th, new_g
@@ -233,6 +283,8 @@ class OracleEstimator:
         for trial in range(p.ls_max):
             # the search gives up once the decrease it requires is below the
             # rounding level of the objective (the test would decide nothing)
+            if trial > 0:
+                self._margin("fp64", "ls_resolution", p.ls_c1 * alpha * abs(gd), resolution)
             if trial > 0 and p.ls_c1 * alpha * abs(gd) < resolution:
                 return None
             th_t = np.mod(theta + alpha * dth, 1.0)
@@ -241,6 +293,7 @@ class OracleEstimator:
                 ga_t[kstar] = 0.0
             ev_t = self.evaluate(th_t, ga_t, beta)
             f_t = ev_t.f(K, zeta)
+            self._margin("fp64", "armijo", f_t, f0 + p.ls_c1 * alpha * gd, 1.0 + abs(f0))
             if f_t <= f0 + p.ls_c1 * alpha * gd:
                 return ev_t, th_t, ga_t, alpha
             alpha *= 0.5
@@ -336,6 +389,7 @@ class OracleEstimator:
             return ev if ev is not None else self.evaluate(theta, gamma, beta)
 
         for it in range(1, p.max_outer + 1):
+            self._it = it
             # ---- step 1: activation ------------------------------------
             run_exact = True
             if approx_on and it <= p.approx_max_iters:
@@ -399,6 +453,9 @@ class OracleEstimator:
                 while len(theta) > 0:
                     marg = nm.deactivation_margin(cur.act["q"], cur.act["s"].real, gamma, zeta)
                     k = int(np.argmax(marg))
+                    if math.isfinite(marg[k]):
+                        self._margin("fp64", "deactivate", marg[k], 0.0,
+                                     max(1.0, abs(math.log((1.0 - zeta) / zeta))))
                     if not marg[k] > 0:
                         break
                     self.trace.append(("deact", it, float(theta[k])))
@@ -408,6 +465,7 @@ class OracleEstimator:
                     gamma = np.delete(gamma, k)
                     mem.reset()
                     cur = ensure(None)
+                self._margin("fp64", "decrement", lam2, N * p.tol_newton)
                 if lam2 < N * p.tol_newton:
                     break
             # ---- termination ---------------------------------------------
@@ -415,6 +473,8 @@ class OracleEstimator:
             cur = ensure(cur)
             L_cur = cur.f(K, zeta)
             self.trace.append(("iter", it, K, L_cur, beta))
+            if math.isfinite(L_prev):
+                self._margin("fp64", "terminate", abs(L_cur - L_prev), N * p.tol_obj, 1.0 + abs(L_cur))
             if abs(L_cur - L_prev) < N * p.tol_obj:
                 converged = True
                 break
@@ -430,7 +490,7 @@ class OracleEstimator:
         if self.cap_hit:
             status = STATUS_ECAPACITY
         return Result(K, theta[order], alpha_hat[order], gamma[order], beta, zeta,
-                      cur.f(K, zeta), it, self.n_evals, status, self.trace)
+                      cur.f(K, zeta), it, self.n_evals, status, self.trace, self.margins)
 
 
 def nm_wrap(x, arr):

@@ -180,6 +180,24 @@ def grid_s(omega_s: np.ndarray, L: int) -> np.ndarray:
     return (L * np.fft.ifft(buf)).real
 
 
+def grid_r(w: np.ndarray, L: int) -> np.ndarray:
+    """r^G_l = psi(l/L)^H D C^{-1} y = sum_n 2 pi n w_n e^{-j2pi n l / L}: the grid
+    form of eq. r (Sec. III-D; the theta-derivative of q^G up to the factor -j)."""
+    assert L >= len(w)
+    return np.fft.fft(d_diag(len(w)) * w, n=L)
+
+
+def grid_t(omega_t: np.ndarray, L: int) -> np.ndarray:
+    """t^G_l = psi(l/L)^H D C^{-1} psi(l/L) = sum_i omega_t(i) e^{+j2pi i l / L}
+    (eq. t through the diagonal sums of D C^{-1}, Sec. III-C/D); complex, since
+    omega_t is not Hermitian in the lag."""
+    N = (len(omega_t) + 1) // 2
+    assert L >= 2 * N - 1, "grid shorter than 2N-1 aliases the diagonal sums"
+    buf = np.zeros(L, dtype=np.complex128)
+    buf[np.arange(-(N - 1), N) % L] = omega_t
+    return L * np.fft.ifft(buf)
+
+
 def grid_s_bruteforce(F: DenseFactor, L: int) -> np.ndarray:
     """s^G_l = psi(l/L)^H C^{-1} psi(l/L) by direct quadratic forms (tiny N only)."""
     Psi = steering(np.arange(L) / L, F.N)
@@ -324,6 +342,10 @@ class Evaluation:
 
     def grid(self, L: int):
         return grid_q(self.w, L), grid_s(self.omega[0], L)
+
+    def grid_derivatives(self, L: int):
+        """(r^G, t^G) on the grid l/L (Sec. III-D)."""
+        return grid_r(self.w, L), grid_t(self.omega[1], L)
 
     def f(self, K: int, zeta: float) -> float:
         return objective(self.logdet, self.yCy, K, self.N, zeta)

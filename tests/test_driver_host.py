@@ -80,3 +80,15 @@ def test_grid_sweeps_at_the_evaluated_point_fit_the_evaluating_round(idx):
     with_eval = [b for b in requests if b & REQ_EVAL]
     assert len(grid_only) == len(requests) - len(with_eval)
     assert len(grid_only) >= 1 and r["iterations"] >= 1
+
+
+def test_host_driver_iteration_cap_matches_oracle():
+    """max_outer = 1 (the iteration cap of the outer loop): status NOTCONV,
+    one iteration, and the refined estimate equals the oracle's."""
+    inst = _instances()[1]
+    p = oe.Params(max_outer=1)
+    o = oe.estimate(inst.y, p)
+    r = hd.HostDriver(inst.y, p).run()
+    assert o.status == oe.STATUS_NOTCONV and r["status"] == o.status
+    assert r["iterations"] == o.iterations == 1 and r["K"] == o.K
+    np.testing.assert_allclose(r["theta"], o.theta, rtol=0, atol=1e-12)

@@ -173,6 +173,28 @@ def test_grid_matches_bruteforce():
     assert abs(nm.s_at(ev.omega[0], [t0])[0] - np.vdot(p, ev.F.solve(p)).real) < 1e-11
 
 
+def test_grid_derivatives_match_bruteforce():
+    """r^G and t^G via FFTs equal the direct products psi^H D C^{-1} y and
+    psi^H D C^{-1} psi on the grid (numpy inverse), including an odd L not
+    tied to N; t^G is complex and differs from its conjugate-symmetric part."""
+    rng = np.random.default_rng(15)
+    for N, L in ((12, 48), (9, 17)):
+        th, ga, be = rand_state(rng, N, 3)
+        y = rand_y(rng, N)
+        ev = nm.Evaluation(y, th, ga, be)
+        rG, tG = ev.grid_derivatives(L)
+        Psi = nm.steering(np.arange(L) / L, N)
+        D = np.diag(nm.d_diag(N))
+        Ci = np.linalg.inv(ev.C)
+        assert np.allclose(rG, Psi.conj().T @ D @ Ci @ y, rtol=1e-12, atol=1e-11)
+        t_ref = np.sum(Psi.conj() * (D @ Ci @ Psi), axis=0)
+        assert np.allclose(tG, t_ref, rtol=1e-12, atol=1e-10)
+        assert np.max(np.abs(tG.imag)) > 1e-3 * np.max(np.abs(tG))
+        # at the grid points that are active frequencies, r and t are eqs. r and t
+        Kg = nm.active_vectors(ev.F, ev.w, np.arange(L)[:3] / L)
+        assert np.allclose(rG[:3], Kg["r"], atol=1e-10) and np.allclose(tG[:3], Kg["t"], atol=1e-10)
+
+
 def test_active_vectors_match_definitions_via_inverse():
     """q..x against the plain matrix products with numpy's inverse (eqs. q-x)."""
     rng = np.random.default_rng(9)
