@@ -209,24 +209,39 @@ sfls_status sfls_omega(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t
                        void* stream);
 
 /* ---------------------------------------------------------------------------
- * a4-a7. sfls_grid_eval: everything the activation step needs on the grid
- * theta^G_l = l/L (Sec. III-D):
- *   q^G_l = psi^H(l/L) C^{-1} y,   s^G_l = psi^H(l/L) C^{-1} psi(l/L),
+ * a4-a7. sfls_grid_eval: what the activation step and its refinement need on
+ * the grid theta^G_l = l/L (Sec. III-D), from y and the generator (rho, delta):
+ *   q^G_l = psi^H(l/L) C^{-1} y,          s^G_l = psi^H(l/L) C^{-1} psi(l/L)
+ *           (FFTs of w = C^{-1} y and of the diagonal sums omega_s),
+ *   r^G_l = psi^H(l/L) D C^{-1} y,        t^G_l = psi^H(l/L) D C^{-1} psi(l/L)
+ *           (eqs. r and t on the grid: FFTs of D w and of omega_t; D = diag(2 pi n);
+ *           so that dq/dtheta = -j r and ds/dtheta = 2 Im t on the grid),
  *   Delta L_l = ln((1 + gb s)(1-zeta)/zeta) - |q|^2/(gb^{-1} + s)  (eq. delta_L)
  * with gb = gamma_bar[b] (> 0), or the per-point optimum of eq. activate_gamma
  * when gamma_bar[b] <= 0 (empty active set), and argmin_l Delta L (lowest l
  * on ties).
+ *   out_mask   SFLS_GRID_* bits of the outputs to compute; an output whose bit
+ *              is set must be non-NULL (else SFLS_EINVAL), the others are ignored.
+ *              SFLS_GRID_ARGMIN writes argmin and/or argmin_val (either may be NULL,
+ *              not both).  gamma_bar and zeta (device f64 [B]) are read only for
+ *              SFLS_GRID_DL / SFLS_GRID_ARGMIN.
  *   L (host i64 [B]) grid sizes: powers of two with L >= 2n-1;
- *   goff (host i64 [B]) offsets of each instance's grid in qG/sG/dL.
- *   qG c128 or c64, sG f64 or f32, dL f64 or f32 (per `precision`: FP64 or
- *   MIXED = FP32 grid); any output may be NULL.  argmin i64 [B] and
- *   argmin_val f64 [B] may be NULL.
+ *   goff (host i64 [B]) offsets of each instance's grid in qG/sG/rG/tG/dL.
+ *   Precision (per `precision`): FP64 = c128 qG/rG/tG, f64 sG/dL; MIXED = the
+ *   FP32 grid: c64 qG/rG/tG, f32 sG/dL (w, omega and the generator stay FP64).
+ *   argmin i64 [B] and argmin_val f64 [B].
+ * out_mask = 0 returns SFLS_OK and does nothing; unknown bits are SFLS_EINVAL.
  * ------------------------------------------------------------------------- */
+typedef enum {
+    SFLS_GRID_Q = 1, SFLS_GRID_S = 2, SFLS_GRID_R = 4, SFLS_GRID_T = 8,
+    SFLS_GRID_DL = 16, SFLS_GRID_ARGMIN = 32, SFLS_GRID_ALL = 63
+} sfls_grid_out;
 sfls_status sfls_grid_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
                            const void* y, int32_t ydtype, const double* rho, const double* delta,
                            const int64_t* L, const int64_t* goff, const double* gamma_bar,
-                           const double* zeta, void* qG, void* sG, void* dL, int64_t* argmin,
-                           double* argmin_val, int32_t precision, void* stream);
+                           const double* zeta, uint32_t out_mask, void* qG, void* sG, void* rG,
+                           void* tG, void* dL, int64_t* argmin, double* argmin_val,
+                           int32_t precision, void* stream);
 
 /* ---------------------------------------------------------------------------
  * a8. Active-set vectors at K[b] frequencies theta (Sec. II-D, eqs. q-x):

@@ -25,6 +25,8 @@ SFLS_EAGAIN = -7
 SFLS_FP64, SFLS_MIXED = 0, 1
 SFLS_C64, SFLS_C128 = 0, 1
 SFLS_MAX_N = 65536
+SFLS_GRID_Q, SFLS_GRID_S, SFLS_GRID_R, SFLS_GRID_T, SFLS_GRID_DL, SFLS_GRID_ARGMIN = \
+    1, 2, 4, 8, 16, 32
 
 EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror",
            "sfls_last_error", "sfls_version", "sfls_toeplitz_column", "sfls_factor",
@@ -134,7 +136,7 @@ def lib() -> ctypes.CDLL:
     L.sfls_omega.argtypes = [_P, i64, _I64P, _I64P, _I64P, _P, _P, _P, _P, _P, _P, _P]
     L.sfls_omega.restype = st
     L.sfls_grid_eval.argtypes = [_P, i64, _I64P, _I64P, _P, i32, _P, _P, _I64P, _I64P, _P, _P,
-                                 _P, _P, _P, _P, _P, i32, _P]
+                                 ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, i32, _P]
     L.sfls_grid_eval.restype = st
     L.sfls_active_eval.argtypes = [_P, i64, _I64P, _I64P, _P, _P, _P, _I64P, _I64P, _P,
                                    _P, _P, _P, _P, _P, _P, _P, _P]
@@ -325,12 +327,19 @@ def sfls_omega(ctx: Context, n, off, oout, rho, delta, omega_s=None, omega_t=Non
 
 def sfls_grid_eval(ctx: Context, n, off, y, ydtype, rho, delta, L, goff, gamma_bar, zeta,
                    qG=None, sG=None, dL=None, argmin=None, argmin_val=None,
-                   precision=SFLS_FP64, stream=None):
+                   precision=SFLS_FP64, stream=None, rG=None, tG=None, out_mask=None):
+    """out_mask None: every output given (not None) is requested."""
     n, off, L, goff = _i64(n), _i64(off), _i64(L), _i64(goff)
+    if out_mask is None:
+        out_mask = ((SFLS_GRID_Q if qG is not None else 0) | (SFLS_GRID_S if sG is not None else 0)
+                    | (SFLS_GRID_R if rG is not None else 0) | (SFLS_GRID_T if tG is not None else 0)
+                    | (SFLS_GRID_DL if dL is not None else 0)
+                    | (SFLS_GRID_ARGMIN if argmin is not None or argmin_val is not None else 0))
     ctx.check(lib().sfls_grid_eval(ctx.handle, len(n), _hp(n), _hp(off), _dp(y), int(ydtype),
                                    _dp(rho), _dp(delta), _hp(L), _hp(goff), _dp(gamma_bar),
-                                   _dp(zeta), _dp(qG), _dp(sG), _dp(dL), _dp(argmin),
-                                   _dp(argmin_val), int(precision), _stream(stream)))
+                                   _dp(zeta), int(out_mask), _dp(qG), _dp(sG), _dp(rG), _dp(tG),
+                                   _dp(dL), _dp(argmin), _dp(argmin_val), int(precision),
+                                   _stream(stream)))
 
 
 def sfls_active_eval(ctx: Context, n, off, w, rho, delta, K, koff, theta, q=None, r=None, u=None,

@@ -145,10 +145,6 @@ void sep_coef(int N, SepCoef& out) {
   }
 }
 
-struct Sizes {
-  int maxN = 0, maxP = 0, maxM = 0, Rmax = 1;
-};
-
 sfls_status check_batch(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
                         int64_t nmin) {
   if (B < 0) return fail(ctx, SFLS_EINVAL, "B = %lld < 0", (long long)B);
@@ -703,20 +699,30 @@ sfls_status sfls_omega(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t
 sfls_status sfls_grid_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
                            const void* y, int32_t ydtype, const double* rho, const double* delta,
                            const int64_t* L, const int64_t* goff, const double* gamma_bar,
-                           const double* zeta, void* qG, void* sG, void* dL, int64_t* argmin,
-                           double* argmin_val, int32_t precision, void* stream) {
+                           const double* zeta, uint32_t out_mask, void* qG, void* sG, void* rG,
+                           void* tG, void* dL, int64_t* argmin, double* argmin_val,
+                           int32_t precision, void* stream) {
   if (!ctx) return SFLS_EINVAL;
   ctx->err.clear();
   sfls_status s = check_batch(ctx, B, n, off, 1);
   if (s != SFLS_OK || B == 0) return s;
-  if (!y || !rho || !delta || !L || !goff || !gamma_bar || !zeta)
-    return fail(ctx, SFLS_EINVAL, "NULL argument");
+  if (out_mask & ~(uint32_t)SFLS_GRID_ALL) return fail(ctx, SFLS_EINVAL, "unknown out_mask bits 0x%x", out_mask);
+  const bool wq = out_mask & SFLS_GRID_Q, ws = out_mask & SFLS_GRID_S, wr = out_mask & SFLS_GRID_R,
+             wt = out_mask & SFLS_GRID_T, wd = out_mask & SFLS_GRID_DL,
+             wa = out_mask & SFLS_GRID_ARGMIN;
+  if ((wq && !qG) || (ws && !sG) || (wr && !rG) || (wt && !tG) || (wd && !dL) ||
+      (wa && !argmin && !argmin_val))
+    return fail(ctx, SFLS_EINVAL, "an output named in out_mask is NULL");
+  const bool need_main = wq || ws || wd || wa, need_der = wr || wt;
+  if (!y || !rho || !delta || !L || !goff) return fail(ctx, SFLS_EINVAL, "NULL argument");
+  if ((wd || wa) && (!gamma_bar || !zeta)) return fail(ctx, SFLS_EINVAL, "NULL gamma_bar or zeta");
   if (ydtype != SFLS_C64 && ydtype != SFLS_C128) return fail(ctx, SFLS_EINVAL, "bad ydtype");
   if (precision != SFLS_FP64 && precision != SFLS_MIXED) return fail(ctx, SFLS_EINVAL, "bad precision");
+  if (!need_main && !need_der) return SFLS_OK;
   (void)hipSetDevice(ctx->device);
   hipStream_t st = as_stream(stream);
   Sizes sz;
-  int64_t pt = 0, ntot = 0;
+  int64_t pt = 0, ntot = 0, otot = 0;
   std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
   std::vector<SepCoef> coef((size_t)B);
   std::vector<int32_t> req((size_t)B, REQ_EVAL | REQ_GRID);
@@ -729,6 +735,8 @@ sfls_status sfls_grid_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int
     in.L = (int32_t)L[b];
     in.R = (int32_t)(L[b] / in.M);
     in.goff = goff[b];
+    in.ooff = otot;
+    otot += 2 * n[b] - 1;
     sz.Rmax = std::max(sz.Rmax, in.R);
     sz.maxM = std::max(in.M, b == 0 ? 0 : sz.maxM);
     ntot = std::max(ntot, off[b] + n[b]);
@@ -737,7 +745,7 @@ sfls_status sfls_grid_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int
   InstInfo* dinfo;
   SepCoef* dcoef;
   int32_t* dreq;
-  cd *scratch, *w, *oms;
+  cd *scratch, *w, *oms, *omt = nullptr;
   double *pv, *yCy;
   int64_t* pi;
   if ((s = upload(ctx, "g_info", info, st, &dinfo)) != SFLS_OK) return s;
@@ -749,15 +757,23 @@ sfls_status sfls_grid_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int
   if ((s = wsT(ctx, "g_pv", (size_t)B * sz.Rmax, &pv)) != SFLS_OK) return s;
   if ((s = wsT(ctx, "g_pi", (size_t)B * sz.Rmax, &pi)) != SFLS_OK) return s;
   if ((s = wsT(ctx, "g_yCy", (size_t)B, &yCy)) != SFLS_OK) return s;
+  if (wt && (s = wsT(ctx, "g_omt", (size_t)otot, &omt)) != SFLS_OK) return s;
   HIP_TRY(launch_gs_apply(dinfo, dreq, y, ydtype, (const cd*)rho, delta, ctx->tw64, ctx->logtw,
                           ctx->tws64, scratch, w, yCy, nullptr, (int)B, sz.maxP, st));
-  HIP_TRY(launch_omega(dinfo, dreq, (const cd*)rho, delta, dcoef, ctx->tws64, scratch,
-                       1, 1, oms, nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st));
+  if (ws || wd || wa || wt)
+    HIP_TRY(launch_omega(dinfo, dreq, (const cd*)rho, delta, dcoef, ctx->tws64, scratch,
+                         1 | (wt ? 2 : 0), 1, oms, nullptr, omt, nullptr, nullptr, (int)B,
+                         sz.maxP, st));
   const void* tw = precision == SFLS_FP64 ? (const void*)ctx->tws64 : (const void*)ctx->tws32;
-  HIP_TRY(launch_grid(precision, dinfo, dreq, w, oms, gamma_bar, zeta, tw, ctx->logtw, sz.Rmax,
-                      (int)B, sz.maxM, qG, sG, dL, pv, pi, st));
-  if (argmin || argmin_val)
+  if (need_main)
+    HIP_TRY(launch_grid(precision, dinfo, dreq, w, oms, gamma_bar, zeta, tw, ctx->logtw, sz.Rmax,
+                        (int)B, sz.maxM, wq ? qG : nullptr, ws ? sG : nullptr, wd ? dL : nullptr,
+                        pv, pi, st));
+  if (wa)
     HIP_TRY(launch_argmin_out(dinfo, sz.Rmax, pv, pi, argmin, argmin_val, (int)B, st));
+  if (need_der)
+    HIP_TRY(launch_grid_deriv(precision, dinfo, dreq, w, omt, tw, ctx->logtw, sz.Rmax, (int)B,
+                              sz.maxM, wr ? rG : nullptr, wt ? tG : nullptr, st));
   return SFLS_OK;
 }
 

@@ -62,6 +62,19 @@ sfls_status fail(sfls_ctx* ctx, sfls_status s, const char* fmt, ...);
                              hipGetErrorString(e_));                                         \
   } while (0)
 
+// Largest sizes of a batch.
+struct Sizes {
+  int maxN = 0, maxP = 0, maxM = 0, Rmax = 1;
+};
+// Host checks of a ragged batch: B >= 0, n and off given, nmin <= n[b] <= SFLS_MAX_N.
+sfls_status check_batch(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                        int64_t nmin);
+// Base InstInfo: N, P, off, poff (4 P scratch per instance, plus a transform
+// buffer when P exceeds the LDS transform size); ptotal = scratch elements.
+std::vector<sfls::InstInfo> base_info(int64_t B, const int64_t* n, const int64_t* off, Sizes& sz,
+                                      int64_t& ptotal);
+hipStream_t as_stream(void* s);
+
 int ilog2_ceil(int64_t v);
 // Dispatch order of a batch whose sizes differ: instance indices by
 // decreasing N (stable); empty when every N is equal (identity order).

@@ -38,8 +38,15 @@ __device__ __forceinline__ R delta_L_point(R q2, R s, R gb, R odds) {
 // point: optional q^G, s^G, Delta L; always a per-workgroup argmin
 // (lowest l on ties).  Blocks of one instance sit on one XCD:
 // blockIdx.x = xcd + 8 j  ->  instance-group j/R... see host mapping.
+//
+// DER = true: the theta-derivative arrays of the same transforms (Sec. III-D,
+// eqs. r and t on the grid),
+//   r^G_l = sum_n 2 pi n w_n e^{-j2pi n l/L},   t^G_l = sum_i omega_t(i) e^{+j2pi i l/L},
+// with w scaled by D = diag(2 pi n) on the way in and omega_t (the diagonal
+// sums of D C^{-1}, lag i at omt[ooff + i + N - 1]) in place of omega_s; t^G
+// is complex.  No Delta L and no argmin.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, bool DER>
 __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ info,
                                                   const int32_t* __restrict__ req,
                                                   const cd* __restrict__ w,
@@ -51,7 +58,8 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
                                                   typename cpx<R>::T* __restrict__ qG,
                                                   R* __restrict__ sG, R* __restrict__ dL,
                                                   double* __restrict__ part_val,
-                                                  int64_t* __restrict__ part_idx) {
+                                                  int64_t* __restrict__ part_idx,
+                                                  typename cpx<R>::T* __restrict__ tG) {
   using C = typename cpx<R>::T;
   // XCD-aware mapping: consecutive block ids go round-robin over 8 XCDs; give
   // all residues of one instance the same id mod 8 so they share an L2.
@@ -63,7 +71,7 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
   if (req && !(req[bi] & REQ_GRID)) return;
   const InstInfo in = info[bi];
   if (r >= in.R) {
-    if (threadIdx.x == 0) { part_val[(int64_t)bi * Rmax + r] = __builtin_inf(); part_idx[(int64_t)bi * Rmax + r] = -1; }
+    if (!DER && threadIdx.x == 0) { part_val[(int64_t)bi * Rmax + r] = __builtin_inf(); part_idx[(int64_t)bi * Rmax + r] = -1; }
     return;
   }
   const int N = in.N, M = in.M, logM = in.logM, L = in.L, P = in.P;
@@ -76,7 +84,16 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
   const int tid = threadIdx.x;
   load_tw_head<GRID_NT>(s_tw, tw);
   const cd* wb = w + in.off;
-  const cd* ob = oms + in.poff;
+  // lag i of the second input: omega_s in the convolution layout (i mod P),
+  // or omega_t in the natural layout (i + N - 1)
+  const cd* ob = !oms ? nullptr : (DER ? oms + in.ooff + (N - 1) : oms + in.poff);
+  // (DER without omega_t: r^G alone, the second transform runs on zeros)
+  const bool has2 = !DER || oms != nullptr;
+  auto lag = [&](int i) -> cd {
+    return !has2 ? cd{0.0, 0.0} : (DER ? ob[i] : ob[(i + P) & (P - 1)]);
+  };
+  // the first input: w, or D w
+  auto wn = [&](int n) -> cd { return DER ? cscale(wb[n], 6.283185307179586 * (double)n) : wb[n]; };
   // M >= N: the residue twiddles exp(j 2 pi m r / L) of a thread's points m =
   // tid + GRID_NT j come from an exact fraction every GRID_ANCHOR-th point and
   // rotations by exp(j 2 pi GRID_NT r / L) in between; the lag m - M takes the
@@ -91,17 +108,17 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
       // one sample and at most two lags (m and m - M) per point
       e = (jt % GRID_ANCHOR == 0) ? cis_frac(((int64_t)m * r) % L, L) : cmul(e, rotg);
       if (m < N) {
-        qv = cmul(wb[m], cconj(e));
-        sv = cmul(ob[m], e);
+        qv = cmul(wn(m), cconj(e));
+        sv = cmul(lag(m), e);
       }
       const int i2 = m - M;
-      if (i2 > -N) sv = cfma(ob[(i2 + P) & (P - 1)], cmul(e, cM), sv);
+      if (i2 > -N) sv = cfma(lag(i2), cmul(e, cM), sv);
     } else {
-      for (int n = m; n < N; n += M) qv = cfma(wb[n], cconj(cis_frac(((int64_t)n * r) % L, L)), qv);
+      for (int n = m; n < N; n += M) qv = cfma(wn(n), cconj(cis_frac(((int64_t)n * r) % L, L)), qv);
       // lags i = m mod M in (-N, N), from the most negative one up
       for (int i = m - M * ((m + N - 1) / M); i < N; i += M) {
         const int64_t ph = (((int64_t)i % L + L) % L) * r % L;
-        sv = cfma(ob[(i + P) & (P - 1)], cis_frac(ph, L), sv);
+        sv = cfma(lag(i), cis_frac(ph, L), sv);
       }
     }
     lq[pidx(m)] = C{(decltype(C{}.x))qv.x, (decltype(C{}.x))qv.y};
@@ -109,6 +126,14 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
   }
   __syncthreads();
   dif_fftn<GRID_NT>(lq, ls, 2, logM, false, true, (const C*)s_tw, tw);
+  if (DER) {
+    for (int p = tid; p < M; p += GRID_NT) {
+      const int64_t l = (int64_t)bitrev(p, logM) * in.R + r;
+      if (qG) qG[in.goff + l] = lq[pidx(p)];
+      if (tG) tG[in.goff + l] = ls[pidx(p)];
+    }
+    return;
+  }
   const R gb = (R)gbar[bi];
   const double z = zeta[bi];
   const R odds = (R)((1.0 - z) / z);
@@ -266,27 +291,46 @@ hipError_t launch_argmin_out(const InstInfo* info, int Rmax, const double* part_
   return hipGetLastError();
 }
 
+template <typename R, bool DER>
+static void launch_grid_t(dim3 grid, int maxM, hipStream_t st, const InstInfo* info,
+                          const int32_t* req, const cd* w, const cd* oms, const double* gbar,
+                          const double* zeta, const void* tw, int logtw, int Rmax, int B, void* qG,
+                          void* sG, void* dL, double* part_val, int64_t* part_idx, void* tG) {
+  using C = typename cpx<R>::T;
+  const size_t shm = 2 * (size_t)padded(maxM) * sizeof(C);
+  (void)hipFuncSetAttribute((const void*)k_grid<R, DER>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shm);
+  hipLaunchKernelGGL((k_grid<R, DER>), grid, dim3(GRID_NT), shm, st, info, req, w, oms, gbar, zeta,
+                     (const C*)tw, logtw, Rmax, B, (C*)qG, (R*)sG, (R*)dL, part_val, part_idx,
+                     (C*)tG);
+}
+
 hipError_t launch_grid(int prec, const InstInfo* info, const int32_t* req, const cd* w,
                        const cd* oms, const double* gbar, const double* zeta, const void* tw,
                        int logtw, int Rmax, int B, int maxM, void* qG, void* sG, void* dL,
                        double* part_val, int64_t* part_idx, hipStream_t st) {
   const int nslots = ((B + 7) / 8) * Rmax;  // per XCD
   dim3 grid(8 * nslots);
-  if (prec == 0) {
-    const size_t shm = 2 * (size_t)padded(maxM) * sizeof(cd);
-    (void)hipFuncSetAttribute((const void*)k_grid<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)shm);
-    hipLaunchKernelGGL(k_grid<double>, grid, dim3(GRID_NT), shm, st, info, req, w, oms, gbar,
-                       zeta, (const cd*)tw, logtw, Rmax, B, (cd*)qG, (double*)sG, (double*)dL,
-                       part_val, part_idx);
-  } else {
-    const size_t shm = 2 * (size_t)padded(maxM) * sizeof(cf);
-    (void)hipFuncSetAttribute((const void*)k_grid<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)shm);
-    hipLaunchKernelGGL(k_grid<float>, grid, dim3(GRID_NT), shm, st, info, req, w, oms, gbar,
-                       zeta, (const cf*)tw, logtw, Rmax, B, (cf*)qG, (float*)sG, (float*)dL,
-                       part_val, part_idx);
-  }
+  if (prec == 0)
+    launch_grid_t<double, false>(grid, maxM, st, info, req, w, oms, gbar, zeta, tw, logtw, Rmax, B,
+                                 qG, sG, dL, part_val, part_idx, nullptr);
+  else
+    launch_grid_t<float, false>(grid, maxM, st, info, req, w, oms, gbar, zeta, tw, logtw, Rmax, B,
+                                qG, sG, dL, part_val, part_idx, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_deriv(int prec, const InstInfo* info, const int32_t* req, const cd* w,
+                             const cd* omt, const void* tw, int logtw, int Rmax, int B, int maxM,
+                             void* rG, void* tG, hipStream_t st) {
+  const int nslots = ((B + 7) / 8) * Rmax;
+  dim3 grid(8 * nslots);
+  if (prec == 0)
+    launch_grid_t<double, true>(grid, maxM, st, info, req, w, omt, nullptr, nullptr, tw, logtw,
+                                Rmax, B, rG, nullptr, nullptr, nullptr, nullptr, tG);
+  else
+    launch_grid_t<float, true>(grid, maxM, st, info, req, w, omt, nullptr, nullptr, tw, logtw,
+                               Rmax, B, rG, nullptr, nullptr, nullptr, nullptr, tG);
   return hipGetLastError();
 }
 

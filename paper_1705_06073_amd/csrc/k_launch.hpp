@@ -111,6 +111,9 @@ hipError_t launch_grid(int prec, const InstInfo* info, const int32_t* req, const
                        const cd* oms, const double* gbar, const double* zeta, const void* tw,
                        int logtw, int Rmax, int B, int maxM, void* qG, void* sG, void* dL,
                        double* part_val, int64_t* part_idx, hipStream_t st);
+hipError_t launch_grid_deriv(int prec, const InstInfo* info, const int32_t* req, const cd* w,
+                             const cd* omt, const void* tw, int logtw, int Rmax, int B, int maxM,
+                             void* rG, void* tG, hipStream_t st);
 hipError_t launch_argmin_out(const InstInfo* info, int Rmax, const double* part_val,
                              const int64_t* part_idx, int64_t* amin, double* aval, int B,
                              hipStream_t st);

@@ -169,8 +169,7 @@ def test_gs_apply_and_omega_large(ctx):
 
 def k1_closed_forms(th1, ga, be, N, L, y):
     """K = 1: generator, pivots, w, q^G and s^G in closed form (Sherman-Morrison)."""
-    n = np.arange(N)
-    psi = np.exp(2j * np.pi * np.mod(n * th1, 1.0))
+    psi = nm.steering([th1], N)[:, 0]    # exact reduction of n th1 mod 1
     den = be + N * ga
     x = -ga * psi * np.conj(psi[-1]) / den
     x[-1] += 1.0
@@ -217,11 +216,21 @@ def test_grid_folded(ctx):
             dL = torch.zeros(Lc, dtype=fdt, device=DEV)
             am = torch.zeros(1, dtype=torch.int64, device=DEV)
             av = torch.zeros(1, dtype=torch.float64, device=DEV)
+            rG = torch.zeros(2 * Lc, dtype=fdt, device=DEV)
+            tG = torch.zeros(2 * Lc, dtype=fdt, device=DEV)
             print(f"[grid folded] N={Nc} L={Lc} prec={prec}", flush=True)
             sf.sfls_grid_eval(ctx, n, off, c2d(yc), sf.SFLS_C128, rd, dd,
                               np.array([Lc], np.int64), np.zeros(1, np.int64),
-                              f64d([gbv]), f64d([zeta]), qG, sG, dL, am, av, precision=prec)
+                              f64d([gbv]), f64d([zeta]), qG, sG, dL, am, av, precision=prec,
+                              rG=rG, tG=tG)
             torch.cuda.synchronize()
+            if Nc == 4500:   # theta-derivative arrays of the folded grid against the oracle
+                r_ref, t_ref = ev.grid_derivatives(Lc)
+                tol_d = 1e-9 if prec == sf.SFLS_FP64 else 1e-4
+                er = relerr(rG.cpu().numpy().astype(np.float64).view(np.complex128), r_ref)
+                et = relerr(tG.cpu().numpy().astype(np.float64).view(np.complex128), t_ref)
+                print(f"   r {er:.2e} t {et:.2e}", flush=True)
+                assert er < tol_d and et < tol_d
             qh = qG.cpu().numpy().astype(np.float64).view(np.complex128)
             sh, dh = sG.cpu().numpy().astype(np.float64), dL.cpu().numpy().astype(np.float64)
             d_ref = nm.delta_L(qr, sr, np.full(Lc, gbv), zeta)
@@ -275,3 +284,137 @@ def test_estimate_uneven_batch(ctx):
         print(f"   b={b} N={inst.N} K={r.K} (true {inst.K}) ev={r.evaluations} objective rel "
               f"{ef:.2e} alpha err/tol {ea:.2e}", flush=True)
         assert ef <= 1e-8 and ea <= 1.0
+
+
+def k1_omegas(th1, ga, be, N):
+    """K = 1 diagonal sums of C^{-1}, D C^{-1}, D^2 C^{-1} and D C^{-1} D in
+    closed form: [C^{-1}]_{q,q+i} = (delta_{i0} - ga e^{-j2 pi i th1} / (be + N ga)) / be
+    summed over the q of lag i with power sums of q (exact in FP64 here)."""
+    i = np.arange(-(N - 1), N, dtype=np.float64)
+    lo = np.maximum(0.0, -i)                 # first q of lag i
+    hi = np.minimum(N - 1.0, N - 1.0 - i)    # last q
+    def psum(m, a, b):                       # sum_{q=a}^{b} q^m
+        def P(x):                            # sum_{q=0}^{x-1} q^m
+            return (x, x * (x - 1) / 2, (x - 1) * x * (2 * x - 1) / 6)[m]
+        return P(b + 1) - P(a)
+    S0, S1, S2 = psum(0, lo, hi), psum(1, lo, hi), psum(2, lo, hi)
+    ph = np.exp(-2j * np.pi * nm.phase_frac(i, [th1])[:, 0])
+    c = ga / (be + N * ga)
+    z = (i == 0).astype(np.float64)
+    tp = 2 * np.pi
+    om_s = (z * S0 - c * ph * S0) / be
+    om_t = tp * (z * S1 - c * ph * S1) / be
+    om_v = tp ** 2 * (z * S2 - c * ph * S2) / be
+    om_x = tp ** 2 * (z * S2 - c * ph * (S2 + i * S1)) / be
+    return om_s, om_t, om_v, om_x
+
+
+@pytest.mark.parametrize("N", [32768, 65536])
+def test_k1_chain_largest_sizes(ctx, N):
+    """Every step entry point at the largest sizes, chained as an evaluation
+    runs them (covariance column, superfast factorisation with refinement,
+    Gohberg-Semencul apply, diagonal sums, grid in FP64 and FP32), for K = 1
+    where each result has a closed form (Sherman-Morrison; Dirichlet kernel
+    for s^G; power sums for the diagonal sums)."""
+    th1, ga, be = 0.2718281828459045, 0.8, 0.3
+    rng = np.random.default_rng(N)
+    y = math.sqrt(ga) * np.exp(2j * np.pi * np.mod(np.arange(N) * th1, 1.0)) \
+        + math.sqrt(be / 2) * (rng.standard_normal(N) + 1j * rng.standard_normal(N))
+    L = 8 * N
+    rho_c, delta_c, q_ref, s_ref = k1_closed_forms(th1, ga, be, N, L, y)
+    tol = max(1e-12, 100.0 * kappa([th1], [ga], be, N) * EPS)
+    n, off = ragged([N])
+    c = zeros_c(N)
+    print(f"[k1 chain] N={N} L={L} tol={tol:.1e}", flush=True)
+    sf.sfls_toeplitz_column(ctx, n, off, np.array([1]), np.zeros(1, np.int64), f64d([th1]),
+                            f64d([ga]), f64d([be]), c)
+    torch.cuda.synchronize()
+    col_ref = ga * nm.steering([th1], N)[:, 0]   # exact reduction of i th1 mod 1
+    col_ref[0] += be
+    ec = relerr(d2c(c), col_ref)
+    n, off, rho, delta, lg = gpu_factor(ctx, [N], [d2c(c)])
+    er, ed = relerr(d2c(rho), rho_c), relerr(delta.cpu().numpy(), delta_c)
+    ld_ref = N * math.log(be) + math.log1p(N * ga / be)
+    el = abs(lg[0] - ld_ref) / abs(ld_ref)
+    print(f"   column {ec:.2e} rho {er:.2e} delta {ed:.2e} logdet {el:.2e}", flush=True)
+    # ln|C| = sum of N logs of pivots, each carrying the pivots' relative error
+    # (2e-12 at N = 65536): N * 1e-15 relative
+    assert ec < 1e-13 and er < tol and ed < tol and el < max(1e-12, N * 1e-15)
+    # Gohberg-Semencul apply: w = C^{-1} y (Sherman-Morrison)
+    psi = nm.steering([th1], N)[:, 0]
+    w_ref = (y - ga * psi * np.vdot(psi, y) / (be + N * ga)) / be
+    w = zeros_c(N)
+    yCy = torch.zeros(1, dtype=torch.float64, device=DEV)
+    sf.sfls_gs_apply(ctx, n, off, c2d(y), sf.SFLS_C128, rho, delta, w, yCy)
+    torch.cuda.synchronize()
+    ew = relerr(d2c(w), w_ref)
+    ey = abs(float(yCy.cpu()[0]) - np.vdot(y, w_ref).real) / np.vdot(y, w_ref).real
+    print(f"   w {ew:.2e} yCy {ey:.2e}", flush=True)
+    assert ew < tol and ey < tol
+    # diagonal sums
+    outs = [zeros_c(2 * N - 1) for _ in range(4)]
+    sf.sfls_omega(ctx, n, off, np.zeros(1, np.int64), rho, delta, *outs)
+    torch.cuda.synchronize()
+    for k, ref in enumerate(k1_omegas(th1, ga, be, N)):
+        eo = relerr(d2c(outs[k]), ref)
+        print(f"   omega_{'stvx'[k]} {eo:.2e}", flush=True)
+        assert eo < tol
+    # grid: q^G, s^G, r^G, t^G, Delta L and the argmin, FP64 and FP32; r^G and
+    # t^G are length-L transforms of the closed forms D w and omega_t
+    gbv, zeta = 0.7, 0.01
+    r_ref = np.fft.fft(2 * np.pi * np.arange(N) * w_ref, L)
+    tb = np.zeros(L, complex)
+    tb[np.arange(-(N - 1), N) % L] = k1_omegas(th1, ga, be, N)[1]
+    t_ref = L * np.fft.ifft(tb)
+    d_ref = nm.delta_L(q_ref, s_ref, np.full(L, gbv), zeta)
+    for prec in (sf.SFLS_FP64, sf.SFLS_MIXED):
+        fdt = torch.float64 if prec == sf.SFLS_FP64 else torch.float32
+        qG = torch.zeros(2 * L, dtype=fdt, device=DEV)
+        sG = torch.zeros(L, dtype=fdt, device=DEV)
+        dL = torch.zeros(L, dtype=fdt, device=DEV)
+        am = torch.zeros(1, dtype=torch.int64, device=DEV)
+        av = torch.zeros(1, dtype=torch.float64, device=DEV)
+        rG = torch.zeros(2 * L, dtype=fdt, device=DEV)
+        tG = torch.zeros(2 * L, dtype=fdt, device=DEV)
+        sf.sfls_grid_eval(ctx, n, off, c2d(y), sf.SFLS_C128, rho, delta, np.array([L], np.int64),
+                          np.zeros(1, np.int64), f64d([gbv]), f64d([zeta]), qG, sG, dL, am, av,
+                          precision=prec, rG=rG, tG=tG)
+        torch.cuda.synchronize()
+        er = relerr(rG.cpu().numpy().astype(np.float64).view(np.complex128), r_ref)
+        et = relerr(tG.cpu().numpy().astype(np.float64).view(np.complex128), t_ref)
+        qh = qG.cpu().numpy().astype(np.float64).view(np.complex128)
+        sh, dh = sG.cpu().numpy().astype(np.float64), dL.cpu().numpy().astype(np.float64)
+        gtol = 1e-9 if prec == sf.SFLS_FP64 else 1e-4
+        eq, es, ed2 = relerr(qh, q_ref), relerr(sh, s_ref), relerr(dh, d_ref)
+        print(f"   grid prec={prec}: q {eq:.2e} s {es:.2e} dL {ed2:.2e} r {er:.2e} t {et:.2e} "
+              f"argmin {int(am.cpu()[0])} (ref {int(np.argmin(d_ref))})", flush=True)
+        assert eq < gtol and es < gtol and ed2 < gtol and er < gtol and et < gtol
+        if prec == sf.SFLS_FP64:
+            assert int(am.cpu()[0]) == int(np.argmin(d_ref))
+
+
+@pytest.mark.parametrize("N", [32768, 65536])
+def test_factor_and_apply_largest_sizes(ctx, N):
+    """K = 20 at the largest sizes: C rho = delta_{N-1} e_{N-1} and C w = y to a
+    small normwise backward error (FFT Toeplitz products), rho_{N-1} = 1,
+    positive pivots, ln|C| against the determinant lemma."""
+    st = states([N], 505 + N, kmax=20)
+    t, g, bb, y = st[0]
+    col = nm.toeplitz_column(t, g, bb, N)
+    print(f"[largest factor] N={N} K={len(t)}", flush=True)
+    n, off, rho, delta, lg = gpu_factor(ctx, [N], [col])
+    r, d = d2c(rho), delta.cpu().numpy()
+    e = np.zeros(N, complex)
+    e[-1] = d[-1]
+    normC = 2.0 * np.sum(np.abs(col))
+    eta = np.max(np.abs(toeplitz_mv(col, r) - e)) / (normC * np.max(np.abs(r)) + d[-1])
+    ll = lemma_logdet(t, g, bb, N)
+    el = abs(lg[0] - ll) / max(1.0, abs(ll))
+    w = zeros_c(N)
+    sf.sfls_gs_apply(ctx, n, off, c2d(y), sf.SFLS_C128, rho, delta, w)
+    torch.cuda.synchronize()
+    w1 = d2c(w)
+    etw = np.max(np.abs(toeplitz_mv(col, w1) - y)) / (normC * np.max(np.abs(w1)) + np.max(np.abs(y)))
+    print(f"   backward error rho {eta:.2e} w {etw:.2e} logdet vs lemma {el:.2e}", flush=True)
+    assert abs(r[-1] - 1.0) < 1e-12 and (d > 0).all()
+    assert eta < 1e-12 and etw < 1e-12 and el < 1e-9

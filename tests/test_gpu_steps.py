@@ -202,17 +202,25 @@ def test_grid(ctx, ns, Lm):
         qG = torch.zeros(2 * tot, dtype=fdt, device=DEV)
         sG = torch.zeros(tot, dtype=fdt, device=DEV)
         dL = torch.zeros(tot, dtype=fdt, device=DEV)
+        rG = torch.zeros(2 * tot, dtype=fdt, device=DEV)
+        tG = torch.zeros(2 * tot, dtype=fdt, device=DEV)
         am = torch.zeros(len(ns), dtype=torch.int64, device=DEV)
         av = torch.zeros(len(ns), dtype=torch.float64, device=DEV)
         sf.sfls_grid_eval(ctx, n, off, yd, sf.SFLS_C128, rho, delta, Ls, goff, gb, zeta, qG, sG,
-                          dL, am, av, precision=prec)
+                          dL, am, av, precision=prec, rG=rG, tG=tG)
         torch.cuda.synchronize()
         qh = qG.cpu().numpy().astype(np.float64).view(np.complex128)
+        rh = rG.cpu().numpy().astype(np.float64).view(np.complex128)
+        th_ = tG.cpu().numpy().astype(np.float64).view(np.complex128)
         sh, dh = sG.cpu().numpy().astype(np.float64), dL.cpu().numpy().astype(np.float64)
         tol = TOL64 if prec == sf.SFLS_FP64 else 1e-4
         for b in range(len(ns)):
             L = int(Ls[b])
             q_ref, s_ref = ev[b].grid(L)
+            r_ref, t_ref = ev[b].grid_derivatives(L)
+            sl = slice(goff[b], goff[b] + L)
+            assert relerr(rh[sl], r_ref) < tol, (b, prec, "r", relerr(rh[sl], r_ref))
+            assert relerr(th_[sl], t_ref) < tol, (b, prec, "t", relerr(th_[sl], t_ref))
             gbv = nm.gamma_hat(q_ref, s_ref) if gb_host[b] <= 0 else np.full(L, gb_host[b])
             d_ref = nm.delta_L(q_ref, s_ref, gbv, 0.1)
             sl = slice(goff[b], goff[b] + L)
@@ -224,6 +232,35 @@ def test_grid(ctx, ns, Lm):
             else:  # FP32 ranks: the pick must be within FP32 noise of the true minimum
                 pick = int(am.cpu().numpy()[b])
                 assert d_ref[pick] - d_ref.min() <= 1e-4 * np.max(np.abs(d_ref))
+
+
+def test_grid_out_mask(ctx):
+    """Only the outputs named in out_mask are written (the others' buffers stay
+    untouched), r^G alone needs no diagonal sums, a named NULL output and an
+    unknown bit are rejected on the host."""
+    ns = [300]
+    st = make_states(ns, seed=71)
+    n, off, rho, delta, *_ = factor_states(ctx, st, ns)
+    L = np.array([4096], np.int64)
+    goff = np.zeros(1, np.int64)
+    yd = c2d(st[0][3])
+    gb, zeta = f64d([np.mean(st[0][1])]), f64d([0.1])
+    ev = nm.Evaluation(st[0][3], st[0][0], st[0][1], st[0][2])
+    r_ref, _ = ev.grid_derivatives(4096)
+    sentinel = 12345.0
+    rG = torch.full((2 * 4096,), sentinel, dtype=torch.float64, device=DEV)
+    tG = torch.full((2 * 4096,), sentinel, dtype=torch.float64, device=DEV)
+    qG = torch.full((2 * 4096,), sentinel, dtype=torch.float64, device=DEV)
+    sf.sfls_grid_eval(ctx, n, off, yd, sf.SFLS_C128, rho, delta, L, goff, None, None, qG=qG,
+                      rG=rG, tG=tG, out_mask=sf.SFLS_GRID_R)
+    torch.cuda.synchronize()
+    assert relerr(d2c(rG), r_ref) < TOL64
+    assert (tG.cpu().numpy() == sentinel).all() and (qG.cpu().numpy() == sentinel).all()
+    for mask, kw in ((sf.SFLS_GRID_T, {}), (sf.SFLS_GRID_DL, dict(tG=tG)), (64, dict(rG=rG))):
+        with pytest.raises(sf.SflsError) as e:
+            sf.sfls_grid_eval(ctx, n, off, yd, sf.SFLS_C128, rho, delta, L, goff, gb, zeta,
+                              out_mask=mask, **kw)
+        assert e.value.status == sf.SFLS_EINVAL
 
 
 @pytest.mark.parametrize("ns", [[64, 100], [1024], [4096]])
