@@ -118,3 +118,16 @@ def test_paper_snr_workload_statistics(ctx):
     res = sf.estimate_batch(ctx, [i.y for i in insts], sf.default_params())
     bsr = np.mean([metrics.block_success(i.theta, r.theta, i.N) for i, r in zip(insts, res)])
     assert bsr >= 0.93, bsr
+
+
+def test_iteration_cap_reports_notconv(ctx):
+    """max_outer = 1: the outer loop ends after one iteration without meeting
+    the termination test of Sec. II-E, so both sides report NOTCONV; the
+    estimate is still refined and returned, and equals the oracle's."""
+    inst = synth.workload_n64(3)
+    p = sf.default_params(L_mult=4.0, max_outer=1)
+    g = sf.estimate_batch(ctx, [inst.y], p)[0]
+    o = estimate(inst.y, Params(L_mult=4.0, max_outer=1))
+    assert o.status == 1 and o.iterations == 1
+    assert g.status == sf.SFLS_NOTCONV and g.iterations == 1
+    compare(inst, g, o, "n64 max_outer=1")

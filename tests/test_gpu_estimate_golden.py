@@ -1,0 +1,89 @@
+"""Whole-estimate parity with the oracle at the batched workloads.
+
+Expected values: the dense FP64 oracle's estimates of sampled instances of the
+256 x N=4096 batch (K ~ Poisson(40), separation 1/N, alpha ~ CN(0,1),
+SNR ~ U[0,30] dB, grid 8N) and of the uneven batch (N log-uniform on
+[128, 16384], K ~ Poisson(N/64), SNR ~ U[5,30] dB), stored in
+``tests/golden/estimates_oracle.json`` by ``tests/golden/make_estimate_golden.py``
+(which calls only the oracle).
+
+The N=4096 instances are taken from one estimate call over the whole batch of
+256 in FP32-grid precision, the launch the throughput benchmark times, and
+from a call over the sampled instances in FP64.  Matching rules and the
+ambiguity rule are those of ``tests/parity.py``: identical model order,
+frequencies within 1e-9/N, and a differing result reported as ambiguous, with
+its margin, only when the oracle's trajectory took a decision closer to a tie
+than the rounding the two sides may differ by.  At most one sampled instance
+per call may be ambiguous."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1705_06073_amd as sf  # noqa: E402
+from paper_1705_06073_amd import synth  # noqa: E402
+from tests import parity  # noqa: E402
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "estimates_oracle.json")))
+CASES = GOLD["cases"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = sf.Context(0)
+    yield c
+    c.close()
+
+
+def check(cases, results, grid_fp32, label):
+    verdicts = []
+    for ref, got in zip(cases, results):
+        v = parity.judge(ref, got, ref["N"], grid_fp32)
+        print(f"[{label}] {ref['workload']}[{ref['instance']}] N={ref['N']} K gpu {got.K} "
+              f"oracle {ref['K']} (true {ref['K_true']}) evals gpu {got.evaluations} oracle "
+              f"{ref['evaluations']}: {v.kind} {v.detail}"
+              + (f" (closest decision: {v.site}, margin {v.margin:.2e})" if v.margin else ""),
+              flush=True)
+        assert got.status in (sf.SFLS_OK, sf.SFLS_NOTCONV)
+        verdicts.append(v)
+    bad = [v for v in verdicts if v.kind == "mismatch"]
+    amb = [v for v in verdicts if v.kind == "ambiguous"]
+    assert not bad, [v.detail for v in bad]
+    assert len(amb) <= 1, [(v.detail, v.site, v.margin) for v in amb]
+
+
+def test_n4096_full_batch_mixed_matches_oracle(ctx):
+    """The 256-instance batch in one call (FP64 recursion, FP32 grid); the
+    sampled instances against the oracle."""
+    insts = [synth.workload_n4096(i) for i in range(256)]
+    print("[golden] 256 x N=4096 mixed", flush=True)
+    res = sf.estimate_batch(ctx, [i.y for i in insts], sf.default_params(precision=sf.SFLS_MIXED),
+                            kcap=256)
+    cases = [c for c in CASES if c["workload"] == "n4096"]
+    check(cases, [res[c["instance"]] for c in cases], True, "n4096 mixed")
+
+
+def test_n4096_fp64_matches_oracle(ctx):
+    cases = [c for c in CASES if c["workload"] == "n4096"]
+    ys = [synth.workload_n4096(c["instance"]).y for c in cases]
+    print("[golden] N=4096 sampled, fp64", flush=True)
+    res = sf.estimate_batch(ctx, ys, sf.default_params(precision=sf.SFLS_FP64), kcap=256)
+    check(cases, res, False, "n4096 fp64")
+
+
+@pytest.mark.parametrize("prec", [sf.SFLS_FP64, sf.SFLS_MIXED])
+def test_uneven_matches_oracle(ctx, prec):
+    """Sampled instances of the uneven batch (N = 1255 .. 5757) in one ragged call."""
+    cases = [c for c in CASES if c["workload"] == "uneven"]
+    ys = [synth.workload_uneven(c["instance"]).y for c in cases]
+    assert [len(y) for y in ys] == [c["N"] for c in cases]
+    print(f"[golden] uneven sampled N={[len(y) for y in ys]} prec={prec}", flush=True)
+    res = sf.estimate_batch(ctx, ys, sf.default_params(precision=prec))
+    check(cases, res, prec == sf.SFLS_MIXED, f"uneven prec {prec}")
