@@ -195,6 +195,29 @@ sfls_status sfls_gs_apply(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
                           double* w, double* yCy, double* ww, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * sfls_gs_apply_noalloc: sfls_gs_apply for callers that cannot allocate device
+ * memory during the call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * sfls_gs_apply; the instance table and the convolution scratch (4 P complex
+ * values per instance, plus a P-point transform buffer when P > 8192) come
+ * from one static device array of SFLS_NOALLOC_SCRATCH_BYTES that every device
+ * the library runs on holds until the process ends (its address is looked up
+ * once per device by sfls_create).  The call allocates nothing; it copies the
+ * table from host memory on `stream` and returns after the stream has
+ * finished the apply.  A batch whose table and scratch exceed the array
+ * returns SFLS_EUNSUPPORTED before anything is enqueued (it holds at most 127
+ * instances of N = 4096, or 6 of N = 65536).
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (from several threads, contexts or streams) race and must be
+ * serialised by the caller.
+ * ------------------------------------------------------------------------- */
+#define SFLS_NOALLOC_SCRATCH_BYTES (64u << 20)
+sfls_status sfls_gs_apply_noalloc(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                                  const void* y, int32_t ydtype, const double* rho,
+                                  const double* delta, double* w, double* yCy, double* ww,
+                                  void* stream);
+
+/* ---------------------------------------------------------------------------
  * a5. Diagonal sums (Sec. III-C, eqs. omega_s, omega_t, omega_v, omega_x):
  *   omega_s(i) = sum_q [C^{-1}]_{q,q+i},   omega_t: D C^{-1},
  *   omega_v: D^2 C^{-1},  omega_x: D C^{-1} D,   D = diag(2 pi n),

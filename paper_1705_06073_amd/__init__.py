@@ -30,7 +30,7 @@ SFLS_GRID_Q, SFLS_GRID_S, SFLS_GRID_R, SFLS_GRID_T, SFLS_GRID_DL, SFLS_GRID_ARGM
 
 EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror",
            "sfls_last_error", "sfls_version", "sfls_toeplitz_column", "sfls_factor",
-           "sfls_gs_apply", "sfls_omega", "sfls_grid_eval", "sfls_active_eval", "sfls_estimate",
+           "sfls_gs_apply", "sfls_gs_apply_noalloc", "sfls_omega", "sfls_grid_eval", "sfls_active_eval", "sfls_estimate",
            "sfls_set_timing", "sfls_reset_stats", "sfls_kernel_stats", "sfls_last_run",
            "sfls_set_factor", "sfls_set_nufft", "sfls_set_schur_lds", "sfls_server_config_default",
            "sfls_server_create", "sfls_server_destroy", "sfls_server_footprint",
@@ -133,6 +133,8 @@ def lib() -> ctypes.CDLL:
     L.sfls_factor.restype = st
     L.sfls_gs_apply.argtypes = [_P, i64, _I64P, _I64P, _P, i32, _P, _P, _P, _P, _P, _P]
     L.sfls_gs_apply.restype = st
+    L.sfls_gs_apply_noalloc.argtypes = [_P, i64, _I64P, _I64P, _P, i32, _P, _P, _P, _P, _P, _P]
+    L.sfls_gs_apply_noalloc.restype = st
     L.sfls_omega.argtypes = [_P, i64, _I64P, _I64P, _I64P, _P, _P, _P, _P, _P, _P, _P]
     L.sfls_omega.restype = st
     L.sfls_grid_eval.argtypes = [_P, i64, _I64P, _I64P, _P, i32, _P, _P, _I64P, _I64P, _P, _P,
@@ -315,6 +317,17 @@ def sfls_gs_apply(ctx: Context, n, off, y, ydtype, rho, delta, w, yCy=None, ww=N
     ctx.check(lib().sfls_gs_apply(ctx.handle, len(n), _hp(n), _hp(off), _dp(y), int(ydtype),
                                   _dp(rho), _dp(delta), _dp(w), _dp(yCy), _dp(ww),
                                   _stream(stream)))
+
+
+def sfls_gs_apply_noalloc(ctx: Context, n, off, y, ydtype, rho, delta, w, yCy=None, ww=None,
+                          stream=None):
+    n, off = _i64(n), _i64(off)
+    ctx.check(lib().sfls_gs_apply_noalloc(ctx.handle, len(n), _hp(n), _hp(off), _dp(y),
+                                          int(ydtype), _dp(rho), _dp(delta), _dp(w), _dp(yCy),
+                                          _dp(ww), _stream(stream)))
+
+
+SFLS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def sfls_omega(ctx: Context, n, off, oout, rho, delta, omega_s=None, omega_t=None, omega_v=None,

@@ -480,7 +480,8 @@ sfls_status sfls_create(sfls_ctx** out, int device) {
   }
   for (int k = 0; k < KID_COUNT; ++k)
     std::snprintf(ctx->kst[k].name, sizeof ctx->kst[k].name, "%s", kKernelNames[k]);
-  if (hipEventCreateWithFlags(&ctx->ev_round, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&ctx->ev_round, hipEventDisableTiming) != hipSuccess ||
+      noalloc_init(ctx) != SFLS_OK) {
     sfls_destroy(ctx);
     return SFLS_EDEVICE;
   }

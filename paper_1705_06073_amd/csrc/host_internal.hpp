@@ -74,6 +74,9 @@ sfls_status check_batch(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_
 std::vector<sfls::InstInfo> base_info(int64_t B, const int64_t* n, const int64_t* off, Sizes& sz,
                                       int64_t& ptotal);
 hipStream_t as_stream(void* s);
+// Device address of the static scratch of sfls_gs_apply_noalloc on the
+// context's device (looked up once per device, at context creation).
+sfls_status noalloc_init(sfls_ctx* ctx);
 
 int ilog2_ceil(int64_t v);
 // Dispatch order of a batch whose sizes differ: instance indices by
