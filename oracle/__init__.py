@@ -17,7 +17,10 @@ numerics   -- covariance, factor (rho, delta, ln|C|), C^{-1} y, diagonal sums
 estimator  -- the block-coordinate-descent estimator (Sec. II-C/D/E); every
               point the paper leaves open is a field of its Params with the
               reading taken.
-metrics    -- wrap-around distance matching, BSR / CSR / NMSE (Sec. VI-A).
+mmv        -- the multiple-measurement-vector model of Sec. V: its objective,
+              summed derivatives, single-component criteria and beta update,
+              and the estimator on them (G = 1 is the estimator above, bit for
+              bit).
 
 Parity status: every numerics function is pinned by tests under
 ``tests/test_oracle_*.py`` (closed forms, brute force, finite differences,

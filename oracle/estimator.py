@@ -114,7 +114,8 @@ class OracleEstimator:
     def __init__(self, y, params: Params | None = None, check_blocks: bool = False):
         self.check_blocks = check_blocks
         self.y = np.asarray(y, dtype=np.complex128)
-        self.N = len(self.y)
+        self.N = self.y.shape[-1]
+        self.G = 1              # observation vectors (Sec. V); 1 = the SMV model
         self.p = params or Params()
         self.L = self.p.grid_size(self.N)
         self.kcap = self.N if self.p.kcap <= 0 else min(self.p.kcap, self.N)
@@ -144,16 +145,48 @@ class OracleEstimator:
         (theta, gamma, beta, zeta)); recorded only with check_blocks."""
         if not self.check_blocks:
             return
-        fb, fa = (nm.Evaluation(self.y, t, g, b).f(len(t), z) for (t, g, b, z) in (before, after))
+        fb, fa = (self._new_eval(t, g, b).f(len(t), z) for (t, g, b, z) in (before, after))
         self.trace.append(("block", name, fb, fa))
+
+    # -- the steps that depend on the observation (the MMV model of Sec. V
+    #    overrides them; everything else is shared) ---------------------------
+    def _new_eval(self, theta, gamma, beta):
+        return nm.Evaluation(self.y, theta, gamma, beta)
+
+    def _energy(self) -> float:
+        """||y||^2 (initial beta and the beta floor, Sec. II-E)."""
+        return float(np.vdot(self.y, self.y).real)
+
+    def _q_at(self, ev, theta):
+        return nm.q_at(ev.w, theta)
+
+    def _qq(self, q) -> float:
+        """|q|^2 of one point (the left-hand side of eq. activate_criterion times s)."""
+        return abs(q) ** 2
+
+    def _criterion(self, q, s, gb, zeta, tau) -> bool:
+        return bool(nm.activation_criterion(q, s, gb, zeta, tau))
+
+    def _grad_hess(self, ev, gamma):
+        gth, gga = nm.gradient(gamma, ev.act)
+        hth, hga = nm.hessian_diag(gamma, ev.act)
+        return gth, gga, hth, hga
+
+    def _beta_update(self, theta, gamma, beta, eps_beta) -> float:
+        return nm.beta_update_definition(self.y, theta, gamma, beta, eps_beta)
+
+    def _deact_margins(self, ev, gamma, zeta):
+        return nm.deactivation_margin(ev.act["q"], ev.act["s"].real, gamma, zeta)
+
+    def _alpha(self, ev, gamma):
+        return gamma * ev.act["q"]
 
     def evaluate(self, theta, gamma, beta) -> nm.Evaluation:
         self.n_evals += 1
-        return nm.Evaluation(self.y, theta, gamma, beta)
+        return self._new_eval(theta, gamma, beta)
 
     def _derivs(self, ev: nm.Evaluation, gamma):
-        gth, gga = nm.gradient(gamma, ev.act)
-        hth, hga = nm.hessian_diag(gamma, ev.act)
+        gth, gga, hth, hga = self._grad_hess(ev, gamma)
         N = self.N
         hth = np.where(hth > 0, hth, (50.0 * N) ** 2)
         safe_g = np.where(gamma > 0, gamma, 1.0)
@@ -164,7 +197,7 @@ class OracleEstimator:
         return float(np.mean(gamma)) if len(gamma) else None
 
     def _decision_quantities(self, q, s, gamma, zeta):
-        """(gbar used, gamma_hat, Delta L, criterion with tau, criterion tau-free)."""
+        """(gbar used, gamma_hat, Delta L) at one point."""
         gh = float(nm.gamma_hat(q, s))
         gb = self._gbar(gamma)
         if gb is None:       # empty active set: per-theta optimum (reading R4)
@@ -188,11 +221,12 @@ class OracleEstimator:
         qG, sG, dl = self._grid_delta_L(ev, gamma, zeta)
         l = int(np.argmin(dl))                       # lowest index on ties
         th = l / self.L
-        q = complex(nm.q_at(ev.w, [th])[0])
+        q = self._q_at(ev, [th])[..., 0]
+        q = complex(q) if q.ndim == 0 else q
         s = float(nm.s_at(ev.omega[0], [th])[0])
         gb, gh, dlv = self._decision_quantities(q, s, gamma, zeta)
         ok = (gh > 0 and zeta > 0
-              and bool(nm.activation_criterion(q, s, gb, zeta, p.tau)) and dlv < -p.eps_L)
+              and self._criterion(q, s, gb, zeta, p.tau) and dlv < -p.eps_L)
         self._record_grid_argmin(dl)
         self._record_activation(q, s, gb, zeta, p.tau, dlv)
         self.trace.append(("exact", l, dlv, ok))
@@ -212,12 +246,15 @@ class OracleEstimator:
     def _record_activation(self, q, s, gb, zeta, tau, dlv):
         if not (zeta > 0 and s > 0 and gb > 0):
             return
-        kappa = abs(q) ** 2 / s
+        kappa = self._qq(q) / s
         lg = math.log((1.0 + gb * s) * ((1.0 - zeta) / zeta))
-        rhs = (1.0 + 1.0 / (gb * s)) * lg + tau
+        rhs = self._criterion_rhs(s, gb, zeta, tau)
         self._margin("fp64", "criterion", kappa, rhs)
         self._margin("fp64", "gamma_hat", kappa, 1.0)               # gamma_hat > 0
         self._margin("fp64", "delta_L", dlv, -self.p.eps_L, 1.0 + abs(lg))
+
+    def _criterion_rhs(self, s, gb, zeta, tau):
+        return (1.0 + 1.0 / (gb * s)) * math.log((1.0 + gb * s) * ((1.0 - zeta) / zeta)) + tau
 
     def _approx_activation(self, ev, theta, gamma, zeta):
         """Approximate scheme of Sec. II-F: all local minima of Delta L passing 4 filters."""
@@ -227,24 +264,24 @@ class OracleEstimator:
         lmin = int(np.argmin(dl))
         locmin = local_minima(dl)
         th_all = np.concatenate([[lmin / L], locmin / L])
-        q_all = nm.q_at(ev.w, th_all)
+        q_all = self._q_at(ev, th_all)
         s_all = nm.s_at(ev.omega[0], th_all)
-        _, _, dl_min = self._decision_quantities(q_all[0], s_all[0], gamma, zeta)
+        _, _, dl_min = self._decision_quantities(q_all[..., 0], s_all[0], gamma, zeta)
         tau = p.tau if p.approx_use_tau else 0.0
         dls, ghs, oks = [], [], []
         for j in range(len(locmin)):
-            q, s = q_all[j + 1], s_all[j + 1]
+            q, s = q_all[..., j + 1], s_all[j + 1]
             gb, gh, dlv = self._decision_quantities(q, s, gamma, zeta)
             dls.append(dlv)
             ghs.append(gh)
-            oks.append(gh > 0 and zeta > 0 and bool(nm.activation_criterion(q, s, gb, zeta, tau)))
+            oks.append(gh > 0 and zeta > 0 and self._criterion(q, s, gb, zeta, tau))
         new_th, new_g, cap = approx_select(dl_min, locmin, dls, ghs, oks, theta, N, L,
                                            p.approx_ratio, p.approx_min_dist,
                                            self.kcap - len(theta))
         self._record_grid_argmin(dl)
         big = float(np.max(np.abs(dl[np.isfinite(dl)]))) if np.any(np.isfinite(dl)) else 1.0
         for j, l in enumerate(locmin):
-            q, s = q_all[j + 1], float(s_all[j + 1].real)
+            q, s = q_all[..., j + 1], float(s_all[j + 1].real)
             gb, _, _ = self._decision_quantities(q, s, gamma, zeta)
             if dls[j] <= 0.5 * dl_min / p.approx_ratio or oks[j]:
                 # local-minimum tests of the grid points that could be chosen
@@ -367,8 +404,8 @@ class OracleEstimator:
 
     # ------------------------------------------------------------------
     def run(self) -> Result:
-        p, N, y = self.p, self.N, self.y
-        yy = float(np.vdot(y, y).real)
+        p, N, G = self.p, self.N, self.G
+        yy = self._energy()
         if yy == 0.0:
             return Result(0, np.zeros(0), np.zeros(0, np.complex128), np.zeros(0), 0.0, 0.0,
                           -math.inf, 0, 0, STATUS_OK)
@@ -423,7 +460,7 @@ class OracleEstimator:
             self._block("zeta", (theta, gamma, beta, zeta), (theta, gamma, beta, min(0.5, K / N)))
             zeta = min(0.5, K / N)
             # ---- step 3: beta (EM bound) ----------------------------------
-            beta_new = nm.beta_update_definition(y, theta, gamma, beta, eps_beta)
+            beta_new = self._beta_update(theta, gamma, beta, eps_beta)
             self._block("beta", (theta, gamma, beta, zeta), (theta, gamma, beta_new, zeta))
             if beta_new != beta:
                 beta = beta_new
@@ -451,7 +488,7 @@ class OracleEstimator:
                 theta, gamma, cur = th_t, ga_t, ev_t
                 # 4b: deactivation, one component at a time (largest margin first)
                 while len(theta) > 0:
-                    marg = nm.deactivation_margin(cur.act["q"], cur.act["s"].real, gamma, zeta)
+                    marg = self._deact_margins(cur, gamma, zeta)
                     k = int(np.argmax(marg))
                     if math.isfinite(marg[k]):
                         self._margin("fp64", "deactivate", marg[k], 0.0,
@@ -465,8 +502,8 @@ class OracleEstimator:
                     gamma = np.delete(gamma, k)
                     mem.reset()
                     cur = ensure(None)
-                self._margin("fp64", "decrement", lam2, N * p.tol_newton)
-                if lam2 < N * p.tol_newton:
+                self._margin("fp64", "decrement", lam2, G * N * p.tol_newton)
+                if lam2 < G * N * p.tol_newton:
                     break
             # ---- termination ---------------------------------------------
             K = len(theta)
@@ -474,8 +511,9 @@ class OracleEstimator:
             L_cur = cur.f(K, zeta)
             self.trace.append(("iter", it, K, L_cur, beta))
             if math.isfinite(L_prev):
-                self._margin("fp64", "terminate", abs(L_cur - L_prev), N * p.tol_obj, 1.0 + abs(L_cur))
-            if abs(L_cur - L_prev) < N * p.tol_obj:
+                self._margin("fp64", "terminate", abs(L_cur - L_prev), G * N * p.tol_obj,
+                             1.0 + abs(L_cur))
+            if abs(L_cur - L_prev) < G * N * p.tol_obj:
                 converged = True
                 break
             L_prev = L_cur
@@ -484,12 +522,13 @@ class OracleEstimator:
         cur, theta, gamma = self._polish(ensure(cur), theta, gamma, beta, zeta)
 
         K = len(theta)
-        alpha_hat = gamma * cur.act["q"] if K else np.zeros(0, np.complex128)
+        alpha_hat = self._alpha(cur, gamma) if K else np.zeros((self.G, 0)[-self.y.ndim:],
+                                                                np.complex128)
         order = np.argsort(theta, kind="stable")
         status = STATUS_OK if converged else STATUS_NOTCONV
         if self.cap_hit:
             status = STATUS_ECAPACITY
-        return Result(K, theta[order], alpha_hat[order], gamma[order], beta, zeta,
+        return Result(K, theta[order], alpha_hat[..., order], gamma[order], beta, zeta,
                       cur.f(K, zeta), it, self.n_evals, status, self.trace, self.margins)
 
 
