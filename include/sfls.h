@@ -93,9 +93,15 @@ typedef struct {
 
 void sfls_params_default(sfls_params* p);
 
-/* Create a context on HIP device `device`.  Returns SFLS_EDEVICE if the
- * device cannot be used. */
-sfls_status sfls_create(sfls_ctx** ctx, int device);
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory of the context's workspace (grown on demand by the calls below to the
+ * largest batch seen; about 2.3 MB per instance of N = 4096 for sfls_estimate):
+ * a call whose batch would need more returns SFLS_ENOMEM with nothing enqueued
+ * beyond what was already done; 0 = no cap.  The twiddle tables (about 6 MB,
+ * allocated here) and servers' pools (sfls_server_config.hbm_bytes) are not
+ * counted.  Returns SFLS_EDEVICE if the device cannot be used, SFLS_ENOMEM if
+ * the tables cannot be allocated. */
+sfls_status sfls_create(sfls_ctx** ctx, int device, size_t hbm_budget_bytes);
 sfls_status sfls_destroy(sfls_ctx* ctx);
 const char* sfls_strerror(sfls_status s);
 /* Message of the last error on this context ("" if none).  Valid until the
@@ -307,6 +313,40 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
                           double* alpha, double* gamma, double* beta, double* zeta,
                           double* objective, int32_t* iters, int32_t* evals, int32_t* status,
                           void* stream);
+
+/* ---------------------------------------------------------------------------
+ * a1-a9 with multiple measurement vectors (Sec. V): G observation vectors per
+ * instance, y^(g) = A(theta) alpha^(g) + w^(g), sharing theta, gamma, beta and
+ * zeta.  The covariance C and its generator are those of the single-vector
+ * model, so each evaluation factors C once; C^{-1} y, q, r, u, the grid's
+ * q^G and y^H C^{-1} y are computed per vector.  The objective is
+ * G ln|C| + sum_g y_g^H C^{-1} y_g - prior; its derivatives are the sums over
+ * g of eqs. derivative/derivative2; activation, deactivation and gamma come
+ * from eq. singlecomp-mmv; beta is the MMV update of Sec. V.  Where Sec. V
+ * leaves details to the reader: the activation criterion is eq.
+ * activate_criterion applied to the per-vector average |q|^2, i.e.
+ * sum_g |q_g|^2 / (G s) > (1 + 1/(gb s)) (ln(1 + gb s) + ln((1-zeta)/zeta)/G)
+ * + tau; the stopping rules scale with G N (the objective is a sum of G
+ * single-vector objectives); beta starts at 0.01 sum_g ||y_g||^2 / (G N).
+ * G = 1 is sfls_estimate.
+ *   G         1..SFLS_MAX_VECTORS, the same for every instance of the call
+ *   y         device (ydtype): vector g of instance b is n[b] samples at
+ *             y + g * ystride + off[b] (elements); ystride >= off[b] + n[b]
+ *   alpha     device c128 out: vector g's amplitudes of instance b, K[b] of
+ *             them, at alpha + g * alpha_stride + koff[b] (complex elements);
+ *             alpha_stride >= koff[b] + kcap[b]
+ *   the other arguments and outputs as sfls_estimate.
+ * The active-set vectors use direct sums (no NUFFT) when G > 1.  Errors:
+ * SFLS_EINVAL for G outside the range or strides smaller than the layout
+ * needs, otherwise as sfls_estimate.
+ * ------------------------------------------------------------------------- */
+#define SFLS_MAX_VECTORS 64
+sfls_status sfls_estimate_mmv(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                              int32_t G, const void* y, int64_t ystride, int32_t ydtype,
+                              const sfls_params* params, const int64_t* kcap, const int64_t* koff,
+                              int64_t* K, double* theta, double* alpha, int64_t alpha_stride,
+                              double* gamma, double* beta, double* zeta, double* objective,
+                              int32_t* iters, int32_t* evals, int32_t* status, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Measurement of sfls_estimate (no effect on results).

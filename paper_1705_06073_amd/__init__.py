@@ -31,6 +31,7 @@ SFLS_GRID_Q, SFLS_GRID_S, SFLS_GRID_R, SFLS_GRID_T, SFLS_GRID_DL, SFLS_GRID_ARGM
 EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror",
            "sfls_last_error", "sfls_version", "sfls_toeplitz_column", "sfls_factor",
            "sfls_gs_apply", "sfls_gs_apply_noalloc", "sfls_omega", "sfls_grid_eval", "sfls_active_eval", "sfls_estimate",
+           "sfls_estimate_mmv",
            "sfls_set_timing", "sfls_reset_stats", "sfls_kernel_stats", "sfls_last_run",
            "sfls_set_factor", "sfls_set_nufft", "sfls_set_schur_lds", "sfls_server_config_default",
            "sfls_server_create", "sfls_server_destroy", "sfls_server_footprint",
@@ -117,7 +118,7 @@ def lib() -> ctypes.CDLL:
     i32, i64, st = ctypes.c_int32, ctypes.c_int64, ctypes.c_int
     L.sfls_params_default.argtypes = [ctypes.POINTER(sfls_params)]
     L.sfls_params_default.restype = None
-    L.sfls_create.argtypes = [ctypes.POINTER(_P), ctypes.c_int]
+    L.sfls_create.argtypes = [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_size_t]
     L.sfls_create.restype = st
     L.sfls_destroy.argtypes = [_P]
     L.sfls_destroy.restype = st
@@ -146,6 +147,10 @@ def lib() -> ctypes.CDLL:
     L.sfls_estimate.argtypes = [_P, i64, _I64P, _I64P, _P, i32, ctypes.POINTER(sfls_params),
                                 _I64P, _I64P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.sfls_estimate.restype = st
+    L.sfls_estimate_mmv.argtypes = [_P, i64, _I64P, _I64P, i32, _P, i64, i32,
+                                    ctypes.POINTER(sfls_params), _I64P, _I64P, _P, _P, _P, i64,
+                                    _P, _P, _P, _P, _P, _P, _P, _P]
+    L.sfls_estimate_mmv.restype = st
     L.sfls_set_factor.argtypes = [_P, i32]
     L.sfls_set_factor.restype = st
     L.sfls_set_nufft.argtypes = [_P, i32]
@@ -229,13 +234,13 @@ def _stream(stream=None):
 
 
 class Context:
-    """Owns one sfls_ctx on a HIP device."""
+    """Owns one sfls_ctx on a HIP device (hbm_budget: workspace cap in bytes, 0 = none)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
         import weakref
         self._h = _P()
         self._servers = weakref.WeakSet()  # servers on this context: closed before it
-        st = lib().sfls_create(ctypes.byref(self._h), int(device))
+        st = lib().sfls_create(ctypes.byref(self._h), int(device), int(hbm_budget))
         if st != SFLS_OK:
             raise SflsError(st, lib().sfls_strerror(st).decode())
         self.device = device
@@ -373,6 +378,18 @@ def sfls_estimate(ctx: Context, n, off, y, ydtype, params, kcap, koff, K, theta,
                                   _dp(evals), _dp(status), _stream(stream)))
 
 
+def sfls_estimate_mmv(ctx: Context, n, off, G, y, ystride, ydtype, params, kcap, koff, K, theta,
+                      alpha, alpha_stride, gamma, beta, zeta, objective, iters, evals, status,
+                      stream=None):
+    n, off, kcap, koff = _i64(n), _i64(off), _i64(kcap), _i64(koff)
+    pp = ctypes.byref(params) if params is not None else None
+    ctx.check(lib().sfls_estimate_mmv(ctx.handle, len(n), _hp(n), _hp(off), int(G), _dp(y),
+                                      int(ystride), int(ydtype), pp, _hp(kcap), _hp(koff), _dp(K),
+                                      _dp(theta), _dp(alpha), int(alpha_stride), _dp(gamma),
+                                      _dp(beta), _dp(zeta), _dp(objective), _dp(iters),
+                                      _dp(evals), _dp(status), _stream(stream)))
+
+
 # ------------------------------------------------- batch conveniences -------
 
 @dataclass
@@ -426,6 +443,53 @@ def estimate_batch(ctx: Context, ys, params: sfls_params | None = None, kcap: in
         o = int(koff[b])
         res.append(EstimateResult(K=k, theta=h["theta"][o:o + k].copy(),
                                   alpha=alpha[o:o + k].copy(), gamma=h["gamma"][o:o + k].copy(),
+                                  beta=float(h["beta"][b]), zeta=float(h["zeta"][b]),
+                                  objective=float(h["objective"][b]),
+                                  iterations=int(h["iters"][b]), evaluations=int(h["evals"][b]),
+                                  status=int(h["status"][b])))
+    return res
+
+
+def estimate_batch_mmv(ctx: Context, Ys, params: sfls_params | None = None,
+                       kcap: int | None = None, ydtype=None, stream=None):
+    """sfls_estimate_mmv on a list of G x n complex arrays (one G for all);
+    returns EstimateResult per instance with alpha of shape G x K."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    Ys = [np.atleast_2d(np.asarray(Y)) for Y in Ys]
+    G = Ys[0].shape[0]
+    assert all(Y.shape[0] == G for Y in Ys), "one G per call"
+    if ydtype is None:
+        ydtype = SFLS_C64 if all(Y.dtype == np.complex64 for Y in Ys) else SFLS_C128
+    npdt = np.complex64 if ydtype == SFLS_C64 else np.complex128
+    n = np.array([Y.shape[1] for Y in Ys], np.int64)
+    off = np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+    ystride = int(n.sum())
+    kc = np.array([min(int(kcap) if kcap else int(m), int(m)) for m in n], np.int64)
+    koff = np.concatenate([[0], np.cumsum(kc)[:-1]]).astype(np.int64)
+    KT = int(kc.sum())
+    yflat = np.concatenate([Y.astype(npdt) for Y in Ys], axis=1)       # G x sum n
+    ydev = torch.from_numpy(np.ascontiguousarray(yflat).view(
+        np.float32 if ydtype == SFLS_C64 else np.float64).ravel().copy()).to(dev)
+    B = len(Ys)
+    f64 = dict(dtype=torch.float64, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    out = dict(K=torch.zeros(B, dtype=torch.int64, device=dev), theta=torch.zeros(KT, **f64),
+               alpha=torch.zeros(2 * G * KT, **f64), gamma=torch.zeros(KT, **f64),
+               beta=torch.zeros(B, **f64), zeta=torch.zeros(B, **f64),
+               objective=torch.zeros(B, **f64), iters=torch.zeros(B, **i32),
+               evals=torch.zeros(B, **i32), status=torch.zeros(B, **i32))
+    sfls_estimate_mmv(ctx, n, off, G, ydev, ystride, ydtype, params, kc, koff, out["K"],
+                      out["theta"], out["alpha"], KT, out["gamma"], out["beta"], out["zeta"],
+                      out["objective"], out["iters"], out["evals"], out["status"], stream=stream)
+    torch.cuda.synchronize(dev)
+    h = {k: v.cpu().numpy() for k, v in out.items()}
+    alpha = h["alpha"].view(np.complex128).reshape(G, KT)
+    res = []
+    for b in range(B):
+        k, o = int(h["K"][b]), int(koff[b])
+        res.append(EstimateResult(K=k, theta=h["theta"][o:o + k].copy(),
+                                  alpha=alpha[:, o:o + k].copy(), gamma=h["gamma"][o:o + k].copy(),
                                   beta=float(h["beta"][b]), zeta=float(h["zeta"][b]),
                                   objective=float(h["objective"][b]),
                                   iterations=int(h["iters"][b]), evaluations=int(h["evals"][b]),

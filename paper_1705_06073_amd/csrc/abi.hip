@@ -38,23 +38,33 @@ sfls_status fail(sfls_ctx* ctx, sfls_status s, const char* fmt, ...) {
 }
 
 
-// grow-only named workspace buffer
+// grow-only named workspace buffer, within the context's HBM budget
 sfls_status ws(sfls_ctx* ctx, const char* name, size_t bytes, void** out) {
   DevBuf& b = ctx->bufs[name];
   if (bytes == 0) bytes = 256;
   if (b.n < bytes) {
+    size_t want = bytes + bytes / 4;
+    if (ctx->hbm_budget && ctx->ws_bytes - b.n + want > ctx->hbm_budget) {
+      want = bytes;  // no growth margin at the budget's edge
+      if (ctx->ws_bytes - b.n + want > ctx->hbm_budget)
+        return fail(ctx, SFLS_ENOMEM,
+                    "workspace %s needs %zu bytes: the context's HBM budget of %zu bytes "
+                    "(%zu in use) does not allow it", name, bytes, ctx->hbm_budget,
+                    ctx->ws_bytes);
+    }
     if (b.p) {
       (void)hipDeviceSynchronize();
       (void)hipFree(b.p);
+      ctx->ws_bytes -= b.n;
       b.p = nullptr;
       b.n = 0;
     }
-    size_t want = bytes + bytes / 4;
     if (hipMalloc(&b.p, want) != hipSuccess) {
       b.p = nullptr;
       return fail(ctx, SFLS_ENOMEM, "workspace allocation of %zu bytes for %s failed", want, name);
     }
     b.n = want;
+    ctx->ws_bytes += want;
   }
   *out = b.p;
   return SFLS_OK;
@@ -456,7 +466,7 @@ const char* sfls_strerror(sfls_status s) {
 
 const char* sfls_last_error(const sfls_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
 
-sfls_status sfls_create(sfls_ctx** out, int device) {
+sfls_status sfls_create(sfls_ctx** out, int device, size_t hbm_budget_bytes) {
   if (!out) return SFLS_EINVAL;
   *out = nullptr;
   int ndev = 0;
@@ -464,6 +474,7 @@ sfls_status sfls_create(sfls_ctx** out, int device) {
   if (hipSetDevice(device) != hipSuccess) return SFLS_EDEVICE;
   sfls_ctx* ctx = new sfls_ctx();
   ctx->device = device;
+  ctx->hbm_budget = hbm_budget_bytes;
   const size_t nt = (size_t)1 << (ctx->logtw - 1);
   if (hipMalloc(&ctx->tw64, nt * sizeof(cd)) != hipSuccess ||
       hipMalloc(&ctx->tw32, nt * sizeof(cf)) != hipSuccess ||
@@ -824,12 +835,15 @@ sfls_status sfls_active_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const i
   return SFLS_OK;
 }
 
-sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
-                          const void* y, int32_t ydtype, const sfls_params* params,
-                          const int64_t* kcap, const int64_t* koff, int64_t* K, double* theta,
-                          double* alpha, double* gamma, double* beta, double* zeta,
-                          double* objective, int32_t* iters, int32_t* evals, int32_t* status,
-                          void* stream) {
+// The estimate of sfls_estimate (G = 1) and sfls_estimate_mmv (G vectors per
+// instance sharing the generator, Sec. V).
+static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                                 int32_t G, const void* y, int64_t ystride, int32_t ydtype,
+                                 const sfls_params* params, const int64_t* kcap,
+                                 const int64_t* koff, int64_t* K, double* theta, double* alpha,
+                                 int64_t alpha_stride, double* gamma, double* beta, double* zeta,
+                                 double* objective, int32_t* iters, int32_t* evals,
+                                 int32_t* status, void* stream) {
   if (!ctx) return SFLS_EINVAL;
   ctx->err.clear();
   sfls_status s = check_batch(ctx, B, n, off, 2);
@@ -837,6 +851,18 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   if (!y || !kcap || !koff || !K || !theta || !alpha || !gamma || !beta || !zeta || !objective ||
       !iters || !status)
     return fail(ctx, SFLS_EINVAL, "NULL argument");
+  if (G < 1 || G > SFLS_MAX_VECTORS)
+    return fail(ctx, SFLS_EINVAL, "G = %d outside 1..%d", G, SFLS_MAX_VECTORS);
+  if (G > 1) {
+    for (int64_t b = 0; b < B; ++b) {
+      if (off[b] + n[b] > ystride)
+        return fail(ctx, SFLS_EINVAL, "ystride %lld < off + n of instance %lld", (long long)ystride,
+                    (long long)b);
+      if (koff[b] + kcap[b] > alpha_stride)
+        return fail(ctx, SFLS_EINVAL, "alpha_stride %lld < koff + kcap of instance %lld",
+                    (long long)alpha_stride, (long long)b);
+    }
+  }
   if (ydtype != SFLS_C64 && ydtype != SFLS_C128) return fail(ctx, SFLS_EINVAL, "bad ydtype");
   sfls_params p;
   if (params) p = *params; else sfls_params_default(&p);
@@ -899,7 +925,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
 #define WS(name, cnt, ptr) if ((s = wsT(ctx, name, (size_t)(cnt), &(ptr))) != SFLS_OK) return s
   WS("e_c", ntot, c);
   WS("e_rho", ntot, rho);
-  WS("e_w", ntot, w);
+  WS("e_w", (int64_t)G * ntot, w);
   WS("e_delta", ntot, delta);
   WS("scratch", pt, scratch);
   WS("e_oms", pt, oms);
@@ -928,7 +954,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   WS("e_g", 2 * ktot, P.g);
   WS("e_d", 2 * ktot, P.d);
   WS("e_gt", 2 * ktot, P.gt);
-  WS("e_qsave", 2 * ktot, P.q_save);
+  WS("e_qsave", 2 * (int64_t)G * ktot, P.q_save);
   WS("e_Sm", (size_t)J * 2 * ktot, P.Sm);
   WS("e_Ym", (size_t)J * 2 * ktot, P.Ym);
   WS("e_rhom", (size_t)J * B, P.rhom);
@@ -942,16 +968,16 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   cd *evq, *evr, *evu, *evs, *evt, *evv, *evx, *cq;
   double* cs;
   int32_t *cand, *ncand;
-  WS("e_evq", ktot, evq);
-  WS("e_evr", ktot, evr);
-  WS("e_evu", ktot, evu);
+  WS("e_evq", (int64_t)G * ktot, evq);
+  WS("e_evr", (int64_t)G * ktot, evr);
+  WS("e_evu", (int64_t)G * ktot, evu);
   WS("e_evs", ktot, evs);
   WS("e_evt", ktot, evt);
   WS("e_evv", ktot, evv);
   WS("e_evx", ktot, evx);
   WS("e_cand", ctot, cand);
   WS("e_ncand", B, ncand);
-  WS("e_cq", ctot, cq);
+  WS("e_cq", (int64_t)G * ctot, cq);
   WS("e_cs", ctot, cs);
   WS("e_cbdl", ctot, P.cbuf_dl);
   WS("e_cbgh", ctot, P.cbuf_gh);
@@ -965,6 +991,17 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   P.out_K = K; P.out_theta = theta; P.out_alpha = (cd*)alpha; P.out_gamma = gamma;
   P.out_beta = beta; P.out_zeta = zeta; P.out_obj = objective; P.out_iters = iters;
   P.out_evals = evals; P.out_status = status; P.out_koff = dokoff; P.notdone = notdone;
+  // observation vectors: strides of the per-vector arrays
+  Vecs vv;
+  vv.G = G;
+  vv.ystride = G > 1 ? ystride : 0;
+  vv.wstride = G > 1 ? ntot : 0;
+  vv.kstride = G > 1 ? ktot : 0;
+  vv.cstride = G > 1 ? ctot : 0;
+  P.G = G;
+  P.kstride = vv.kstride;
+  P.cstride = vv.cstride;
+  P.ostride = G > 1 ? alpha_stride : 0;
 
   SchurLayout* slay;
   SchurAct* sacts;
@@ -1025,7 +1062,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
                                           : hipSuccess;
   };
 
-  HIP_TRY(launch_init_state(dinfo, y, ydtype, dst, P.req, (int)B, st));
+  HIP_TRY(launch_init_state(dinfo, y, ydtype, dst, P.req, (int)B, st, nullptr, vv));
   HIP_TRY(launch_zero_i32(notdone, 1, st));
   HIP_TRY(launch_zero_i32(P.req2, (int)B, st));
   std::memset(hreq2, 0, (size_t)B * sizeof(int32_t));
@@ -1053,17 +1090,21 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
         ++nact;
         kflops[KID_FACTOR] += slay ? sflops[(size_t)b] : 8.0 * N * N;  // Schur or Levinson
         kbytes[KID_FACTOR] += 40.0 * N;                       // c in, rho and delta out
+        kbytes[KID_GEN] += 16.0 * N;                          // c out
         if (slay) {
           const double P = (double)info[(size_t)b].P, lp = (double)info[(size_t)b].logP;
           kflops[KID_REFINE] += 10.0 * 5.0 * P * lp + 96.0 * P;  // 10 transforms + pointwise
+          kbytes[KID_REFINE] += 48.0 * N;                     // c, rho in; rho out
         }
         kbytes[KID_APPLY] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * N + 32.0 * N;  // y, rho in; w out
+        kbytes[KID_ACTIVE] += 32.0 * N;                       // w, rho in
       }
       // grid stage: alone when the evaluation at the current point is in place
       if (rq & REQ_GRID) {
         ++ngrid;
         const double Lb = (double)info[(size_t)b].L;
         kbytes[KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz_d * Lb;  // w, omega_s in; Delta L out
+        kbytes[KID_OMEGA] += 16.0 * N + 16.0 * (2.0 * N - 1.0);  // rho in; omega_s out
       }
     }
     if (nreq == 0) break;
@@ -1092,7 +1133,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
       HIP_TRY(tstop(KID_REFINE));
       HIP_TRY(tstart(KID_APPLY));
       HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw,
-                              ctx->tws64, scratch, w, yCy, ww, (int)B, sz.maxP, st, dorder));
+                              ctx->tws64, scratch, w, yCy, ww, (int)B, sz.maxP, st, dorder, vv));
       HIP_TRY(tstop(KID_APPLY));
     }
     // active-set vectors at the evaluated points (candidates follow the grid stage)
@@ -1100,7 +1141,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
       HIP_TRY(tstart(KID_ACTIVE));
       HIP_TRY(launch_active(dinfo, P.req, P.K_e, nullptr, prefix, (int)B, P.th_e, cand, w, rho,
                             delta, dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks,
-                            ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st));
+                            ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st, vv));
       HIP_TRY(tstop(KID_ACTIVE));
     }
     // first driver pass: the instances whose request had no grid sweep
@@ -1118,7 +1159,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
     HIP_TRY(tstop2(KID_OMEGA));
     HIP_TRY(tstart2(KID_GRID));
     HIP_TRY(launch_grid(prec, dinfo, P.req2, w, oms, P.gbar_e, P.zeta_e, tw, ctx->logtw, sz.Rmax,
-                        (int)B, sz.maxM, nullptr, nullptr, dL, pv, pi, st));
+                        (int)B, sz.maxM, nullptr, nullptr, dL, pv, pi, st, vv));
     HIP_TRY(tstop2(KID_GRID));
     HIP_TRY(tstart2(KID_SELECT));
     HIP_TRY(launch_select(prec, dinfo, P.req2, dL, sz.Rmax, pv, pi, p.approx_ratio, slack,
@@ -1127,7 +1168,7 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
     HIP_TRY(tstart2(KID_ACTIVE));
     HIP_TRY(launch_active(dinfo, P.req2, P.K_e, ncand, prefix, (int)B, P.th_e, cand, w, rho, delta,
                           dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks,
-                          ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st));
+                          ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st, vv));
     HIP_TRY(tstop2(KID_ACTIVE));
     HIP_TRY(tstart2(KID_DRIVER));
     HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st, 1));
@@ -1143,6 +1184,8 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
       ++gevals;
       const double N = (double)n[b], Lb = (double)info[(size_t)b].L;
       kbytes[KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz_d * Lb;
+      kbytes[KID_OMEGA] += 16.0 * N + 16.0 * (2.0 * N - 1.0);
+      kbytes[KID_ACTIVE] += 32.0 * N;  // the candidates' vectors: w, rho in
     }
     if (timing) {
       for (int k = 0; k < KID_COUNT; ++k) {
@@ -1166,6 +1209,26 @@ sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int6
   (void)notdone;
 
   return SFLS_OK;
+}
+
+sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                          const void* y, int32_t ydtype, const sfls_params* params,
+                          const int64_t* kcap, const int64_t* koff, int64_t* K, double* theta,
+                          double* alpha, double* gamma, double* beta, double* zeta,
+                          double* objective, int32_t* iters, int32_t* evals, int32_t* status,
+                          void* stream) {
+  return estimate_impl(ctx, B, n, off, 1, y, 0, ydtype, params, kcap, koff, K, theta, alpha, 0,
+                       gamma, beta, zeta, objective, iters, evals, status, stream);
+}
+
+sfls_status sfls_estimate_mmv(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
+                              int32_t G, const void* y, int64_t ystride, int32_t ydtype,
+                              const sfls_params* params, const int64_t* kcap, const int64_t* koff,
+                              int64_t* K, double* theta, double* alpha, int64_t alpha_stride,
+                              double* gamma, double* beta, double* zeta, double* objective,
+                              int32_t* iters, int32_t* evals, int32_t* status, void* stream) {
+  return estimate_impl(ctx, B, n, off, G, y, ystride, ydtype, params, kcap, koff, K, theta, alpha,
+                       alpha_stride, gamma, beta, zeta, objective, iters, evals, status, stream);
 }
 
 }  // extern "C"

@@ -51,6 +51,11 @@ struct DrvState {
 // Per-instance array views (device pointers, offset to this instance).
 struct DrvArrays {
   int N, L, kcap;
+  // observation vectors (Sec. V): the per-vector arrays ev_q, ev_r, ev_u,
+  // q_save, cand_q and out_alpha hold vector g at g * (vk, vk, vk, vk, vc, vo)
+  // doubles from the instance's entry (G = 1: the single-vector model)
+  int G = 1;
+  int64_t vk = 0, vc = 0, vo = 0;
   // current accepted point
   double* th;
   double* ga;
@@ -113,14 +118,28 @@ SFLS_HD inline double wrapd(double a, double b) {
   d = d - floor(d);
   return fmin(d, 1.0 - d);
 }
-SFLS_HD inline double gamma_hat(double q2, double s) { return (q2 / s > 1.0) ? (q2 - s) / (s * s) : 0.0; }
-SFLS_HD inline double delta_L(double q2, double s, double gb, double zeta) {
-  const double lg = log((1.0 + gb * s) * ((1.0 - zeta) / zeta));
+// The single-component quantities of Sec. II-D (eqs. activate_gamma, delta_L,
+// activate_criterion) and, for G observation vectors, of eq. singlecomp-mmv,
+// with q2 = sum_g |q_g|^2:
+//   gamma_hat = (q2/G - s)/s^2,  Delta L = G ln(1 + gb s) + ln((1-zeta)/zeta)
+//   - q2/(1/gb + s), and the criterion q2/(G s) > (1 + 1/(gb s)) (ln(1 + gb s)
+//   + ln((1-zeta)/zeta)/G) + tau (the single-vector form on the per-vector
+//   average).  Written so that G = 1 performs the single-vector operations.
+SFLS_HD inline double gamma_hat(double q2, double s, int G = 1) {
+  const double qb = G == 1 ? q2 : q2 / (double)G;
+  return (qb / s > 1.0) ? (qb - s) / (s * s) : 0.0;
+}
+SFLS_HD inline double delta_L(double q2, double s, double gb, double zeta, int G = 1) {
+  double lg = log((1.0 + gb * s) * ((1.0 - zeta) / zeta));
+  if (G != 1) lg += (double)(G - 1) * log1p(gb * s);
   return lg - ((gb > 0.0) ? q2 / (1.0 / gb + s) : 0.0);
 }
-SFLS_HD inline bool act_criterion(double q2, double s, double gb, double zeta, double tau) {
-  const double kap = q2 / s;
-  const double rhs = (1.0 + 1.0 / (gb * s)) * log((1.0 + gb * s) * ((1.0 - zeta) / zeta)) + tau;
+SFLS_HD inline bool act_criterion(double q2, double s, double gb, double zeta, double tau,
+                                  int G = 1) {
+  const double kap = (G == 1 ? q2 : q2 / (double)G) / s;
+  double lg = log((1.0 + gb * s) * ((1.0 - zeta) / zeta));
+  if (G != 1) lg = (lg + (double)(G - 1) * log1p(gb * s)) / (double)G;
+  const double rhs = (1.0 + 1.0 / (gb * s)) * lg + tau;
   if (rhs != rhs) return false;
   return kap > rhs;
 }
@@ -147,7 +166,15 @@ struct Driver {
   SFLS_HD Driver(const DrvParams& p, DrvState& s, const DrvArrays& a)
       : P(p), S(s), A(a), N(a.N), J(p.J) {}
 
-  SFLS_HD double f_of_eval() const { return *A.logdet + *A.yCy + prior_term(S.K, N, S.zeta); }
+  // L_MMV = G ln|C| + sum_g y_g^H C^{-1} y_g - prior (Sec. V; G = 1: eq. obj)
+  SFLS_HD double f_of_eval() const {
+    const double ld = A.G == 1 ? *A.logdet : (double)A.G * *A.logdet;
+    return ld + *A.yCy + prior_term(S.K, N, S.zeta);
+  }
+
+  // the scale of the stopping rules: N, or G N for G observation vectors (the
+  // objective is a sum of G single-vector objectives)
+  SFLS_HD double gN() const { return A.G == 1 ? (double)N : (double)A.G * (double)N; }
 
   SFLS_HD double gbar() const {
     if (S.K == 0) return -1.0;
@@ -173,31 +200,43 @@ struct Driver {
   // gradient and replaced diagonal Hessian of component k from the
   // evaluation results (eqs. derivative, derivative2; replacements (50N)^2
   // and gamma^-2)
+  // (with G observation vectors the sums over g of the single-vector
+  // expressions, Sec. V: q, r, u per vector, s, t, v, x shared)
   SFLS_HD void deriv_k(int k, double gk, double& gth, double& gga, double& hth,
                        double& hga) const {
-    const double qr = A.ev_q[2 * k], qi = A.ev_q[2 * k + 1];
-    const double rr = A.ev_r[2 * k], ri = A.ev_r[2 * k + 1];
-    const double ur = A.ev_u[2 * k], ui = A.ev_u[2 * k + 1];
     const double s = A.ev_s[2 * k];
     const double tr = A.ev_t[2 * k], ti = A.ev_t[2 * k + 1];
     const double vr = A.ev_v[2 * k];
     const double xr = A.ev_x[2 * k];
-    const double q2 = qr * qr + qi * qi, r2 = rr * rr + ri * ri;
-    // Im(t - conj(q) r)
-    const double im_t_qr = ti - (qr * ri - qi * rr);
-    gth = 2.0 * gk * im_t_qr;
-    gga = s - q2;
-    // Re{ x - v + g(t^2 - x s) + g(x|q|^2 + s|r|^2 - 2 t r conj q) + (u conj q - |r|^2) }
     const double t2r = tr * tr - ti * ti;
     const double xsr = xr * s;
-    // t r conj(q)
-    const double trr = tr * rr - ti * ri, tri = tr * ri + ti * rr;
-    const double trq = trr * qr + tri * qi;
-    const double uq = ur * qr + ui * qi;
-    const double inner = xr - vr + gk * (t2r - xsr) + gk * (xr * q2 + s * r2 - 2.0 * trq) +
-                         (uq - r2);
+    double im_sum = 0.0, gga_sum = 0.0, inner = 0.0, hga_sum = 0.0;
+    for (int gv = 0; gv < A.G; ++gv) {
+      const int64_t o = gv * A.vk;
+      const double qr = A.ev_q[o + 2 * k], qi = A.ev_q[o + 2 * k + 1];
+      const double rr = A.ev_r[o + 2 * k], ri = A.ev_r[o + 2 * k + 1];
+      const double ur = A.ev_u[o + 2 * k], ui = A.ev_u[o + 2 * k + 1];
+      const double q2 = qr * qr + qi * qi, r2 = rr * rr + ri * ri;
+      // Im(t - conj(q) r)
+      const double im_t_qr = ti - (qr * ri - qi * rr);
+      // Re{ x - v + g(t^2 - x s) + g(x|q|^2 + s|r|^2 - 2 t r conj q) + (u conj q - |r|^2) }
+      // t r conj(q)
+      const double trr = tr * rr - ti * ri, tri = tr * ri + ti * rr;
+      const double trq = trr * qr + tri * qi;
+      const double uq = ur * qr + ui * qi;
+      const double in_g = xr - vr + gk * (t2r - xsr) + gk * (xr * q2 + s * r2 - 2.0 * trq) +
+                          (uq - r2);
+      const double hga_g = 2.0 * s * q2 - s * s;
+      if (gv == 0) {
+        im_sum = im_t_qr; gga_sum = s - q2; inner = in_g; hga_sum = hga_g;
+      } else {
+        im_sum += im_t_qr; gga_sum += s - q2; inner += in_g; hga_sum += hga_g;
+      }
+    }
+    gth = 2.0 * gk * im_sum;
+    gga = gga_sum;
     hth = 2.0 * gk * inner;
-    hga = 2.0 * s * q2 - s * s;
+    hga = hga_sum;
     if (!(hth > 0.0)) hth = (50.0 * N) * (50.0 * N);
     if (!(hga > 0.0)) hga = (gk > 0.0) ? 1.0 / (gk * gk) : 1.0;
   }
@@ -363,11 +402,18 @@ struct Driver {
       if (!(gk > 0.0)) {
         margin = INFINITY;
       } else {
-        const double qr = A.ev_q[2 * k], qi = A.ev_q[2 * k + 1], s = A.ev_s[2 * k];
+        const double s = A.ev_s[2 * k];
         const double den = 1.0 - gk * s;
-        const double q2t = (qr * qr + qi * qi) / (den * den);
+        // sum_g |q~_g|^2 (Woodbury), eq. deactivate / eq. singlecomp-mmv
+        double q2t = 0.0;
+        for (int gv = 0; gv < A.G; ++gv) {
+          const double qr = A.ev_q[gv * A.vk + 2 * k], qi = A.ev_q[gv * A.vk + 2 * k + 1];
+          const double t = (qr * qr + qi * qi) / (den * den);
+          q2t = gv == 0 ? t : q2t + t;
+        }
         const double st = s / den;
-        const double lhs = q2t / (1.0 / gk + st) - log1p(gk * st);
+        const double lg = A.G == 1 ? log1p(gk * st) : (double)A.G * log1p(gk * st);
+        const double lhs = q2t / (1.0 / gk + st) - lg;
         margin = thr - lhs;
       }
       if (margin > 0.0 && (best < 0 || margin > bm)) { best = k; bm = margin; }
@@ -379,9 +425,13 @@ struct Driver {
   }
 
   // FP64 decision quantities at candidate c (index into cand arrays)
+  // (q2 = sum_g |q_g|^2 over the observation vectors)
   SFLS_HD void cand_q2s(int c, double& q2, double& s) const {
-    const double qr = A.cand_q[2 * c], qi = A.cand_q[2 * c + 1];
-    q2 = qr * qr + qi * qi;
+    for (int gv = 0; gv < A.G; ++gv) {
+      const double qr = A.cand_q[gv * A.vc + 2 * c], qi = A.cand_q[gv * A.vc + 2 * c + 1];
+      const double t = qr * qr + qi * qi;
+      q2 = gv == 0 ? t : q2 + t;
+    }
     s = A.cand_s[c];
   }
 
@@ -389,10 +439,10 @@ struct Driver {
   SFLS_HD int exact_decide() {
     double q2, s;
     cand_q2s(0, q2, s);
-    const double gh = gamma_hat(q2, s);
+    const double gh = gamma_hat(q2, s, A.G);
     const double gb = (S.K == 0) ? gh : gbar();
-    const double dl = delta_L(q2, s, gb, S.zeta);
-    const bool ok = gh > 0.0 && S.zeta > 0.0 && act_criterion(q2, s, gb, S.zeta, P.tau) &&
+    const double dl = delta_L(q2, s, gb, S.zeta, A.G);
+    const bool ok = gh > 0.0 && S.zeta > 0.0 && act_criterion(q2, s, gb, S.zeta, P.tau, A.G) &&
                     dl < -P.eps_L;
     if (!ok) return 0;
     if (S.K >= A.kcap || S.K >= N) { S.cap_hit = 1; return 0; }
@@ -411,18 +461,18 @@ struct Driver {
     const int nc = *A.ncand;
     double q2, s;
     cand_q2s(0, q2, s);
-    const double gb0 = (S.K == 0) ? gamma_hat(q2, s) : gbar();
-    const double dlmin = delta_L(q2, s, gb0, S.zeta);
+    const double gb0 = (S.K == 0) ? gamma_hat(q2, s, A.G) : gbar();
+    const double dlmin = delta_L(q2, s, gb0, S.zeta, A.G);
     const double tau = P.approx_use_tau ? P.tau : 0.0;
     const double gbf = gbar();
     double nq = 0.0;
     for (int c = 1 + T::lane(); c < nc; c += T::width()) {
       double q2c, sc;
       cand_q2s(c, q2c, sc);
-      const double gh = gamma_hat(q2c, sc);
+      const double gh = gamma_hat(q2c, sc, A.G);
       const double gb = (S.K == 0) ? gh : gbf;
-      const double dl = delta_L(q2c, sc, gb, S.zeta);
-      const bool ok = gh > 0.0 && S.zeta > 0.0 && act_criterion(q2c, sc, gb, S.zeta, tau) &&
+      const double dl = delta_L(q2c, sc, gb, S.zeta, A.G);
+      const bool ok = gh > 0.0 && S.zeta > 0.0 && act_criterion(q2c, sc, gb, S.zeta, tau, A.G) &&
                       dl <= dlmin / P.approx_ratio;
       A.cbuf_dl[c] = dl;
       A.cbuf_gh[c] = ok ? gh : -1.0;
@@ -483,8 +533,10 @@ struct Driver {
       }
       A.out_theta[r] = t;
       A.out_gamma[r] = A.ga[k];
-      A.out_alpha[2 * r] = A.ga[k] * q[2 * k];
-      A.out_alpha[2 * r + 1] = A.ga[k] * q[2 * k + 1];
+      for (int gv = 0; gv < A.G; ++gv) {  // alpha^(g) = gamma .* q^(g)
+        A.out_alpha[gv * A.vo + 2 * r] = A.ga[k] * q[gv * A.vk + 2 * k];
+        A.out_alpha[gv * A.vo + 2 * r + 1] = A.ga[k] * q[gv * A.vk + 2 * k + 1];
+      }
     }
     *A.out_K = K;
     *A.out_beta = S.beta;
@@ -519,8 +571,10 @@ struct Driver {
       for (int k = T::lane(); k < S.K; k += T::width()) {
         A.out_theta[k] = A.th[k];
         A.out_gamma[k] = A.ga[k];
-        A.out_alpha[2 * k] = 0.0;
-        A.out_alpha[2 * k + 1] = 0.0;
+        for (int gv = 0; gv < A.G; ++gv) {
+          A.out_alpha[gv * A.vo + 2 * k] = 0.0;
+          A.out_alpha[gv * A.vo + 2 * k + 1] = 0.0;
+        }
       }
       *A.out_beta = S.beta;
       *A.out_zeta = S.zeta;
@@ -622,7 +676,11 @@ struct Driver {
           double tr = 0.0;
           for (int k = T::lane(); k < S.K; k += T::width()) tr += A.ga[k] * A.ev_s[2 * k];
           tr = T::sum(tr);
-          double bn = (S.beta * tr + S.beta * S.beta * (*A.ww)) / (double)N;
+          // with G vectors (Sec. V): (G beta tr + beta^2 sum_g ||w_g||^2) / (G N)
+          double bn = A.G == 1
+                          ? (S.beta * tr + S.beta * S.beta * (*A.ww)) / (double)N
+                          : ((double)A.G * S.beta * tr + S.beta * S.beta * (*A.ww)) /
+                                ((double)A.G * (double)N);
           if (!(bn > S.eps_beta)) bn = S.eps_beta;
           if (bn != S.beta) { S.beta = bn; S.cur_valid = 0; }
           if (S.z_changed) { mem_reset(); S.z_changed = 0; }
@@ -726,7 +784,7 @@ struct Driver {
         }
         case L_INNER_END: {
           S.inner += 1;
-          if (S.lam2 < (double)N * P.tol_newton) { lbl = L_TERM_BEGIN; break; }
+          if (S.lam2 < gN() * P.tol_newton) { lbl = L_TERM_BEGIN; break; }
           lbl = L_INNER_BEGIN;
           break;
         }
@@ -741,7 +799,7 @@ struct Driver {
         }
         case L_TERM_DO: {
           const double Lc = f_of_eval();
-          if (fabs(Lc - S.L_prev) < (double)N * P.tol_obj) {
+          if (fabs(Lc - S.L_prev) < gN() * P.tol_obj) {
             S.converged = 1;
             lbl = L_POLISH_BEGIN;
             break;
@@ -770,7 +828,9 @@ struct Driver {
           S.nu0 = T::sum(nu);
           direction(A.g, A.gt, A.d, n);
           S.f_cur = f_of_eval();
-          for (int e = T::lane(); e < n; e += T::width()) A.q_save[e] = A.ev_q[e];
+          for (int gv = 0; gv < A.G; ++gv)
+            for (int e = T::lane(); e < n; e += T::width())
+              A.q_save[gv * A.vk + e] = A.ev_q[gv * A.vk + e];
           S.saved = 1;
           ls_begin(true);
           ls_request();

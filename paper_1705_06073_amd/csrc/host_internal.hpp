@@ -40,6 +40,8 @@ struct sfls_ctx {
   hipStream_t upload = nullptr;  // admission copies of the servers on this context
   hipEvent_t ev_round = nullptr;  // end of an estimate round (request bits on the host)
   int32_t schur_lds_f = sfls::SCH_LDS_F;  // largest recursion transform kept in LDS
+  size_t hbm_budget = 0;  // workspace limit in bytes (0: none)
+  size_t ws_bytes = 0;    // workspace held
 };
 
 // Whether timing mode `mode` (sfls_set_timing) brackets kernel k with events.

@@ -106,6 +106,22 @@ __device__ __forceinline__ void active_out(const double (&acc)[14], bool full, c
   }
 }
 
+// q, r, u of observation vector gv >= 1 at point j from its six sums (q, n q,
+// n^2 q as re/im pairs); grid candidates (j >= nk) keep q only.
+__device__ __forceinline__ void vec_out(const double (&a)[6], bool full, const InstInfo& in, int j,
+                                        int nk, int gv, const Vecs& vv, cd* oq, cd* orr, cd* ou,
+                                        cd* cq) {
+  const double TWO_PI = 6.283185307179586476925286766559;
+  if (full) {
+    const int64_t o = gv * vv.kstride + in.koff + j;
+    oq[o] = cd{a[0], a[1]};
+    orr[o] = cd{TWO_PI * a[2], TWO_PI * a[3]};
+    ou[o] = cd{TWO_PI * TWO_PI * a[4], TWO_PI * TWO_PI * a[5]};
+  } else {
+    cq[gv * vv.cstride + in.coff + (j - nk)] = cd{a[0], a[1]};
+  }
+}
+
 // ---------------------------------------------------------------------------
 // With e_n = exp(-j 2 pi n theta) and x_n = n - c, c = (N-1)/2:
 //   q = sum w_n e_n,  r = 2 pi sum n w_n e_n,  u = (2 pi)^2 sum n^2 w_n e_n
@@ -130,7 +146,7 @@ __global__ __launch_bounds__(ACT_NT) void k_active(const InstInfo* __restrict__ 
                                                    cd* __restrict__ ou, cd* __restrict__ os,
                                                    cd* __restrict__ ot, cd* __restrict__ ov,
                                                    cd* __restrict__ ox, cd* __restrict__ cq,
-                                                   double* __restrict__ cs) {
+                                                   double* __restrict__ cs, Vecs vv) {
   __shared__ double red[14 * (ACT_NT / 64)];
   const int total = prefix[B];
   const int tid = threadIdx.x;
@@ -196,6 +212,26 @@ __global__ __launch_bounds__(ACT_NT) void k_active(const InstInfo* __restrict__ 
       active_out(acc, full, in, j, nk, 1.0 / delta[in.off + N - 1], coef[bi], oq, orr, ou, os, ot,
                  ov, ox, cq, cs);
     __syncthreads();
+    // further observation vectors: q (and r, u at active points) with the same phases
+    for (int gv = 1; gv < vv.G; ++gv) {
+      const cd* wg = w + gv * vv.wstride + in.off;
+      double a6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int it2 = 0;
+      for (int n = tid; n < N; n += ACT_NT, ++it2) {
+        const double dn = (double)n;
+        e = (it2 % ACT_ANCHOR == 0) ? cconj(cis2pi(frac_mul(dn, th))) : cmul(e, rot);
+        const cd we = cmul(wg[n], e);
+        a6[0] += we.x; a6[1] += we.y;
+        if (full) {
+          a6[2] = fma(dn, we.x, a6[2]); a6[3] = fma(dn, we.y, a6[3]);
+          const double d2 = dn * dn;
+          a6[4] = fma(d2, we.x, a6[4]); a6[5] = fma(d2, we.y, a6[5]);
+        }
+      }
+      block_sum<ACT_NT, 6>(a6, red);
+      if (tid == 0) vec_out(a6, full, in, j, nk, gv, vv, oq, orr, ou, cq);
+      __syncthreads();
+    }
   }
 }
 
@@ -224,7 +260,7 @@ __global__ __launch_bounds__(ACTL_NT) void k_active_lds(const InstInfo* __restri
                                                         cd* __restrict__ ou, cd* __restrict__ os,
                                                         cd* __restrict__ ot, cd* __restrict__ ov,
                                                         cd* __restrict__ ox, cd* __restrict__ cq,
-                                                        double* __restrict__ cs) {
+                                                        double* __restrict__ cs, Vecs vv) {
   const int bi = blockIdx.x;
   const int32_t rq = req ? req[bi] : REQ_EVAL;
   const InstInfo in = info[bi];
@@ -277,6 +313,35 @@ __global__ __launch_bounds__(ACTL_NT) void k_active_lds(const InstInfo* __restri
 #pragma unroll
     for (int i = 0; i < 14; ++i) acc[i] = wave_sum(acc[i]);
     if (lane == 0) active_out(acc, full, in, j, nk, idl, cf, oq, orr, ou, os, ot, ov, ox, cq, cs);
+  }
+  // further observation vectors: w_g replaces w in LDS; q (and r, u at active
+  // points) with the same phases
+  for (int gv = 1; gv < vv.G; ++gv) {
+    __syncthreads();
+    for (int t = tid; t < N; t += ACTL_NT) sw[t] = w[gv * vv.wstride + in.off + t];
+    __syncthreads();
+    for (int j = wv; j < npts; j += ACTL_NT / 64) {
+      const bool full = j < nk;
+      const double th = full ? theta[in.koff + j] : (double)cand[in.coff + (j - nk)] / (double)in.L;
+      const cd rot = cconj(cis2pi(frac_mul(64.0, th)));
+      double a6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      cd e{1.0, 0.0};
+      int it = 0;
+      for (int n = lane; n < N; n += 64, ++it) {
+        const double dn = (double)n;
+        e = (it % ACT_ANCHOR_W == 0) ? cconj(cis2pi(frac_mul(dn, th))) : cmul(e, rot);
+        const cd we = cmul(sw[n], e);
+        a6[0] += we.x; a6[1] += we.y;
+        if (full) {
+          a6[2] = fma(dn, we.x, a6[2]); a6[3] = fma(dn, we.y, a6[3]);
+          const double d2 = dn * dn;
+          a6[4] = fma(d2, we.x, a6[4]); a6[5] = fma(d2, we.y, a6[5]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) a6[i] = wave_sum(a6[i]);
+      if (lane == 0) vec_out(a6, full, in, j, nk, gv, vv, oq, orr, ou, cq);
+    }
   }
 }
 
@@ -452,15 +517,16 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
                          const int32_t* cand, const cd* w, const cd* rho, const double* delta,
                          const SepCoef* coef, cd* oq, cd* orr, cd* ou, cd* os, cd* ot, cd* ov,
                          cd* ox, cd* cq, double* cs, int nblocks, int nmode, const cd* tws,
-                         cd* scratch, int maxP, hipStream_t st) {
+                         cd* scratch, int maxP, hipStream_t st, Vecs vv) {
   if (!scratch) nmode = 1;  // no scratch for the NUFFT form: direct sums only
+  if (vv.G > 1) nmode = 1;  // several observation vectors: direct sums
   // every instance has N <= P/2; with P <= 2 ACT_LDS_N throughout, the direct
   // sums all run in k_active_lds and the item-parallel pair has nothing to do
   if (maxP > 2 * ACT_LDS_N) {
     hipLaunchKernelGGL(k_item_scan, dim3(1), dim3(1024), 0, st, info, req, Keval, ncand, B, nmode,
                        prefix);
     hipLaunchKernelGGL(k_active, dim3(nblocks), dim3(ACT_NT), 0, st, info, req, Keval, prefix, B,
-                       theta, cand, w, rho, delta, coef, oq, orr, ou, os, ot, ov, ox, cq, cs);
+                       theta, cand, w, rho, delta, coef, oq, orr, ou, os, ot, ov, ox, cq, cs, vv);
   }
   {
     // N <= P/2 for every instance, so 2 * min(P, 2 ACT_LDS_N) / 2 points cover w and rho
@@ -470,7 +536,7 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(k_active_lds, dim3(B), dim3(ACTL_NT), shm, st, info, req, Keval, ncand,
                        nmode, theta, cand, w, rho, delta, coef, oq, orr, ou, os, ot, ov, ox, cq,
-                       cs);
+                       cs, vv);
   }
   if (nmode != 1) {
     const size_t shm = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);

@@ -61,7 +61,8 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
                                                       cd* __restrict__ scratch, cd* __restrict__ w,
                                                       double* __restrict__ yCy,
                                                       double* __restrict__ ww,
-                                                      const int32_t* __restrict__ order) {
+                                                      const int32_t* __restrict__ order,
+                                                      Vecs vv) {
   const int bi = order ? order[blockIdx.x] : blockIdx.x;
   if (req && !(req[bi] & REQ_EVAL)) return;
   const InstInfo in = info[bi];
@@ -72,7 +73,6 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
   const int tid = threadIdx.x;
   load_tw_head<CONV_NT>(s_tw, tws);
   const cd* rb = rho + in.off;
-  const YT* yb = y + in.off;
   cd* A = scratch + in.poff;
   cd* Y = A + P;
   cd* X1 = Y + P;
@@ -107,12 +107,18 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
       }
       __syncthreads();
     };
-    // (1) A = FFT(rho)
+    // (1) A = FFT(rho), shared by the vectors
     auto to_lds = [&](int t, cd v) { lds[pidx(t)] = v; };
     batched_for<8>(tid, CONV_NT, P, [&](int t) { return (t < N) ? rb[t] : cd{0.0, 0.0}; }, to_lds);
     __syncthreads();
     dif_fftn<CONV_NT>(lds, lds, 1, logP, false, false, s_tw, tws, 1);
     spectrum_to(A);
+    // y^H C^{-1} y and ||w||^2 summed over the vectors
+    double acc[2] = {0.0, 0.0};
+    for (int gv = 0; gv < vv.G; ++gv) {
+    const YT* yb = y + gv * vv.ystride + in.off;
+    cd* wout = w + gv * vv.wstride + in.off;
+    if (gv > 0) __syncthreads();  // the last vector's w read the transform buffer
     // (2) Y = FFT(y^)
     batched_for<8>(tid, CONV_NT, P,
                    [&](int t) { return (t < N) ? load_y(yb, N - 1 - t) : cd{0.0, 0.0}; }, to_lds);
@@ -182,13 +188,13 @@ __global__ __launch_bounds__(CONV_NT) void k_gs_apply(const InstInfo* __restrict
     __syncthreads();
     dit_fftn<CONV_NT>(lds, lds, 1, logP, true, true, s_tw, tws, 1);
     const double sc = invP / delta[in.off + N - 1];
-    double acc[2] = {0.0, 0.0};
     batched_for<8>(tid, CONV_NT, N, [&](int i) { return load_y(yb, i); }, [&](int i, cd yi) {
       const cd wi = cscale(lds[pidx(i)], sc);
-      w[in.off + i] = wi;
+      wout[i] = wi;
       acc[0] += fma(yi.x, wi.x, yi.y * wi.y);  // Re(conj(y) w)
       acc[1] += cabs2(wi);
     });
+    }
     block_sum<CONV_NT, 2>(acc, red);
     if (tid == 0) {
       if (yCy) yCy[bi] = acc[0];
@@ -426,18 +432,18 @@ hipError_t launch_gen_refine(const InstInfo* info, const int32_t* req, const int
 hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void* y, int ydtype,
                            const cd* rho, const double* delta, const cd* tw, int logtw,
                            const cd* tws, cd* scratch, cd* w, double* yCy, double* ww, int B, int maxP,
-                           hipStream_t st, const int32_t* order) {
+                           hipStream_t st, const int32_t* order, Vecs vv) {
   const size_t shm = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);
   if (ydtype == 1) {
     (void)hipFuncSetAttribute((const void*)k_gs_apply<cd>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)shm);
     hipLaunchKernelGGL(k_gs_apply<cd>, dim3(B), dim3(CONV_NT), shm, st, info, req, (const cd*)y,
-                       rho, delta, tw, logtw, tws, scratch, w, yCy, ww, order);
+                       rho, delta, tw, logtw, tws, scratch, w, yCy, ww, order, vv);
   } else {
     (void)hipFuncSetAttribute((const void*)k_gs_apply<cf>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)shm);
     hipLaunchKernelGGL(k_gs_apply<cf>, dim3(B), dim3(CONV_NT), shm, st, info, req, (const cf*)y,
-                       rho, delta, tw, logtw, tws, scratch, w, yCy, ww, order);
+                       rho, delta, tw, logtw, tws, scratch, w, yCy, ww, order, vv);
   }
   return hipGetLastError();
 }

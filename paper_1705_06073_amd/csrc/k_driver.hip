@@ -71,6 +71,10 @@ __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info
   A.N = in.N;
   A.L = in.L;
   A.kcap = in.kcap;
+  A.G = p.G;
+  A.vk = 2 * p.kstride;
+  A.vc = 2 * p.cstride;
+  A.vo = 2 * p.ostride;
   A.th = p.th + ko;
   A.ga = p.ga + ko;
   A.th_e = p.th_e + ko;
@@ -141,20 +145,24 @@ __global__ __launch_bounds__(256) void k_init_state(const InstInfo* __restrict__
                                                     const YT* __restrict__ y,
                                                     DrvState* __restrict__ st,
                                                     int32_t* __restrict__ req,
-                                                    const int32_t* __restrict__ list) {
+                                                    const int32_t* __restrict__ list, Vecs vv) {
   __shared__ double red[4];
   const int b = list ? list[blockIdx.x] : blockIdx.x;
   const InstInfo in = info[b];
   double acc[1] = {0.0};
-  for (int i = threadIdx.x; i < in.N; i += 256) {
-    const double re = (double)y[in.off + i].x, im = (double)y[in.off + i].y;
-    acc[0] = fma(re, re, fma(im, im, acc[0]));
+  for (int gv = 0; gv < vv.G; ++gv) {
+    const YT* yb = y + gv * vv.ystride + in.off;
+    for (int i = threadIdx.x; i < in.N; i += 256) {
+      const double re = (double)yb[i].x, im = (double)yb[i].y;
+      acc[0] = fma(re, re, fma(im, im, acc[0]));
+    }
   }
   block_sum<256, 1>(acc, red);
   if (threadIdx.x == 0) {
     DrvState s = {};
     s.phase = PH_START;
-    s.yy = acc[0];
+    // the energy per vector (sum over the vectors / G; G = 1: ||y||^2)
+    s.yy = vv.G == 1 ? acc[0] : acc[0] / (double)vv.G;
     st[b] = s;
     req[b] = 0;
   }
@@ -195,14 +203,14 @@ hipError_t launch_driver(const InstInfo* info, const DrvParams* prm, DrvPools po
 }
 
 hipError_t launch_init_state(const InstInfo* info, const void* y, int ydtype, DrvState* st,
-                             int32_t* req, int B, hipStream_t s, const int32_t* list) {
+                             int32_t* req, int B, hipStream_t s, const int32_t* list, Vecs vv) {
   if (B <= 0) return hipSuccess;
   if (ydtype == 1)
     hipLaunchKernelGGL(k_init_state<cd>, dim3(B), dim3(256), 0, s, info, (const cd*)y, st, req,
-                       list);
+                       list, vv);
   else
     hipLaunchKernelGGL(k_init_state<cf>, dim3(B), dim3(256), 0, s, info, (const cf*)y, st, req,
-                       list);
+                       list, vv);
   return hipGetLastError();
 }
 

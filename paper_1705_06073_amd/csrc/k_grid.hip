@@ -18,12 +18,21 @@ template <> __device__ __forceinline__ float rinf<float>() { return __builtin_in
 // Delta L of eq. delta_L at one grid point in precision R.  gb > 0: fixed
 // average variance; gb <= 0: the per-point optimum of eq. activate_gamma
 // (empty active set), for which Delta L = ln(kappa odds) - (kappa - 1).
+// With G observation vectors (Sec. V, eq. singlecomp-mmv) q2 is sum_g |q_g|^2
+// and Delta L = G ln(1 + gb s) + ln odds - q2 / (1/gb + s), or with the
+// per-point optimum G (ln kap - (kap - 1)) + ln odds, kap = q2 / (G s); both are
+// written so that G = 1 performs the single-vector operations.
 template <typename R>
-__device__ __forceinline__ R delta_L_point(R q2, R s, R gb, R odds) {
+__device__ __forceinline__ R delta_L_point(R q2, R s, R gb, R odds, int G = 1) {
   if (!(s > (R)0)) return rinf<R>();
-  if (gb > (R)0) return log(fma(gb, s, (R)1) * odds) - q2 / ((R)1 / gb + s);
-  const R kap = q2 / s;
-  if (kap > (R)1) return log(kap * odds) - (kap - (R)1);
+  if (gb > (R)0) {
+    const R lg = log(fma(gb, s, (R)1) * odds);
+    return (G == 1 ? lg : lg + (R)(G - 1) * log1p(gb * s)) - q2 / ((R)1 / gb + s);
+  }
+  const R kap = (G == 1 ? q2 : q2 / (R)G) / s;
+  if (kap > (R)1)
+    return G == 1 ? log(kap * odds) - (kap - (R)1)
+                  : log(kap * odds) + (R)(G - 1) * log(kap) - (R)G * (kap - (R)1);
   return log(odds);
 }
 
@@ -59,7 +68,8 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
                                                   R* __restrict__ sG, R* __restrict__ dL,
                                                   double* __restrict__ part_val,
                                                   int64_t* __restrict__ part_idx,
-                                                  typename cpx<R>::T* __restrict__ tG) {
+                                                  typename cpx<R>::T* __restrict__ tG,
+                                                  Vecs vv) {
   using C = typename cpx<R>::T;
   // XCD-aware mapping: consecutive block ids go round-robin over 8 XCDs; give
   // all residues of one instance the same id mod 8 so they share an L2.
@@ -100,6 +110,21 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
   // same twiddle times exp(-j 2 pi M r / L)
   const cd rotg = cis_frac(((int64_t)GRID_NT * r) % L, L);
   const cd cM = cconj(cis_frac(((int64_t)M * r) % L, L));
+  // vectors g >= 1 of a multiple-vector launch: q^G only, into lq
+  auto load_q = [&](const cd* __restrict__ wv) {
+    cd e1{1.0, 0.0};
+    int jq = 0;
+    for (int m = tid; m < M; m += GRID_NT, ++jq) {
+      cd qv{0.0, 0.0};
+      if (M >= N) {
+        e1 = (jq % GRID_ANCHOR == 0) ? cis_frac(((int64_t)m * r) % L, L) : cmul(e1, rotg);
+        if (m < N) qv = cmul(wv[m], cconj(e1));
+      } else {
+        for (int n = m; n < N; n += M) qv = cfma(wv[n], cconj(cis_frac(((int64_t)n * r) % L, L)), qv);
+      }
+      lq[pidx(m)] = C{(decltype(C{}.x))qv.x, (decltype(C{}.x))qv.y};
+    }
+  };
   cd e{1.0, 0.0};
   int jt = 0;
   for (int m = tid; m < M; m += GRID_NT, ++jt) {
@@ -134,6 +159,26 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
     }
     return;
   }
+  const int G = DER ? 1 : vv.G;
+  if (G > 1) {
+    // sum_g |q^G_g|^2 in the imaginary part of the s^G buffer (s^G is real);
+    // q^G of vector 0 stays in lq for the output
+    for (int p = tid; p < M; p += GRID_NT) ls[pidx(p)].y = cabs2(lq[pidx(p)]);
+    for (int gv = 1; gv < G; ++gv) {
+      // lq of vector 0 was read by this thread only; the transforms below
+      // exchange data across the block
+      if (gv == 1 && qG) {
+        for (int p = tid; p < M; p += GRID_NT)
+          qG[in.goff + (int64_t)bitrev(p, logM) * in.R + r] = lq[pidx(p)];
+      }
+      __syncthreads();
+      load_q(w + gv * vv.wstride + in.off);
+      __syncthreads();
+      dif_fftn<GRID_NT>(lq, lq, 1, logM, false, false, (const C*)s_tw, tw);
+      for (int p = tid; p < M; p += GRID_NT) ls[pidx(p)].y += cabs2(lq[pidx(p)]);
+    }
+    __syncthreads();
+  }
   const R gb = (R)gbar[bi];
   const double z = zeta[bi];
   const R odds = (R)((1.0 - z) / z);
@@ -144,10 +189,10 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
     const int64_t l = (int64_t)f * in.R + r;
     const C qv = lq[pidx(p)];
     const R sv = ls[pidx(p)].x;
-    const R q2 = cabs2(qv);
-    R d = delta_L_point<R>(q2, sv, gb, odds);
+    const R q2 = G > 1 ? ls[pidx(p)].y : cabs2(qv);
+    R d = delta_L_point<R>(q2, sv, gb, odds, G);
     if (d != d) d = rinf<R>();
-    if (qG) qG[in.goff + l] = qv;
+    if (qG && G == 1) qG[in.goff + l] = qv;
     if (sG) sG[in.goff + l] = sv;
     if (dL) dL[in.goff + l] = d;
     const double dd = (double)d;
@@ -295,28 +340,29 @@ template <typename R, bool DER>
 static void launch_grid_t(dim3 grid, int maxM, hipStream_t st, const InstInfo* info,
                           const int32_t* req, const cd* w, const cd* oms, const double* gbar,
                           const double* zeta, const void* tw, int logtw, int Rmax, int B, void* qG,
-                          void* sG, void* dL, double* part_val, int64_t* part_idx, void* tG) {
+                          void* sG, void* dL, double* part_val, int64_t* part_idx, void* tG,
+                          Vecs vv = Vecs{}) {
   using C = typename cpx<R>::T;
   const size_t shm = 2 * (size_t)padded(maxM) * sizeof(C);
   (void)hipFuncSetAttribute((const void*)k_grid<R, DER>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)shm);
   hipLaunchKernelGGL((k_grid<R, DER>), grid, dim3(GRID_NT), shm, st, info, req, w, oms, gbar, zeta,
                      (const C*)tw, logtw, Rmax, B, (C*)qG, (R*)sG, (R*)dL, part_val, part_idx,
-                     (C*)tG);
+                     (C*)tG, vv);
 }
 
 hipError_t launch_grid(int prec, const InstInfo* info, const int32_t* req, const cd* w,
                        const cd* oms, const double* gbar, const double* zeta, const void* tw,
                        int logtw, int Rmax, int B, int maxM, void* qG, void* sG, void* dL,
-                       double* part_val, int64_t* part_idx, hipStream_t st) {
+                       double* part_val, int64_t* part_idx, hipStream_t st, Vecs vv) {
   const int nslots = ((B + 7) / 8) * Rmax;  // per XCD
   dim3 grid(8 * nslots);
   if (prec == 0)
     launch_grid_t<double, false>(grid, maxM, st, info, req, w, oms, gbar, zeta, tw, logtw, Rmax, B,
-                                 qG, sG, dL, part_val, part_idx, nullptr);
+                                 qG, sG, dL, part_val, part_idx, nullptr, vv);
   else
     launch_grid_t<float, false>(grid, maxM, st, info, req, w, oms, gbar, zeta, tw, logtw, Rmax, B,
-                                qG, sG, dL, part_val, part_idx, nullptr);
+                                qG, sG, dL, part_val, part_idx, nullptr, vv);
   return hipGetLastError();
 }
 

@@ -68,6 +68,10 @@ struct DrvPools {
   // latter, for the host's accounting)
   int32_t* req2;
   int32_t* req2_host;
+  // observation vectors (Sec. V) and the vector strides (complex elements) of
+  // ev_q/ev_r/ev_u/q_save, cand_q and out_alpha
+  int32_t G = 1;
+  int64_t kstride = 0, cstride = 0, ostride = 0;
 };
 
 hipError_t launch_twiddles(cd* tw64, cf* tw32, cd* tws64, cf* tws32, int logtw, hipStream_t st);
@@ -93,7 +97,7 @@ hipError_t launch_gs_apply(const InstInfo* info, const int32_t* req, const void*
                            const cd* rho, const double* delta, const cd* tw, int logtw,
                            const cd* tws, cd* scratch, cd* w, double* yCy, double* ww, int B,
                            int maxP,
-                           hipStream_t st, const int32_t* order = nullptr);
+                           hipStream_t st, const int32_t* order = nullptr, Vecs vv = Vecs{});
 hipError_t launch_gen_refine(const InstInfo* info, const int32_t* req, const int32_t* status,
                              const cd* c, cd* rho, double* delta, const cd* tw, int logtw,
                              const cd* tws, cd* scratch, cd* r, cd* dx, int B, int maxP,
@@ -110,7 +114,7 @@ hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
 hipError_t launch_grid(int prec, const InstInfo* info, const int32_t* req, const cd* w,
                        const cd* oms, const double* gbar, const double* zeta, const void* tw,
                        int logtw, int Rmax, int B, int maxM, void* qG, void* sG, void* dL,
-                       double* part_val, int64_t* part_idx, hipStream_t st);
+                       double* part_val, int64_t* part_idx, hipStream_t st, Vecs vv = Vecs{});
 hipError_t launch_grid_deriv(int prec, const InstInfo* info, const int32_t* req, const cd* w,
                              const cd* omt, const void* tw, int logtw, int Rmax, int B, int maxM,
                              void* rG, void* tG, hipStream_t st);
@@ -126,9 +130,10 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
                          const int32_t* cand, const cd* w, const cd* rho, const double* delta,
                          const SepCoef* coef, cd* oq, cd* orr, cd* ou, cd* os, cd* ot, cd* ov,
                          cd* ox, cd* cq, double* cs, int nblocks, int nmode, const cd* tws,
-                         cd* scratch, int maxP, hipStream_t st);
+                         cd* scratch, int maxP, hipStream_t st, Vecs vv = Vecs{});
 hipError_t launch_init_state(const InstInfo* info, const void* y, int ydtype, DrvState* st,
-                             int32_t* req, int B, hipStream_t s, const int32_t* list = nullptr);
+                             int32_t* req, int B, hipStream_t s, const int32_t* list = nullptr,
+                             Vecs vv = Vecs{});
 hipError_t launch_slots_idle(DrvState* st, int32_t* req, int B, hipStream_t s);
 hipError_t launch_admit(const AdmitRec* recs, int n, const InstInfo* hinfo, const SepCoef* hcoef,
                         const SchurLayout* hlay, const int64_t* hkoff, InstInfo* dinfo,

@@ -25,6 +25,17 @@ struct InstInfo {
   int64_t coff;   // candidate arrays
 };
 
+// Observation vectors of a launch (the multiple-measurement-vector model of
+// Sec. V; G = 1 is the single-vector model).  Every instance of a launch has
+// G vectors that share its generator: vector g of instance b is the signal at
+// y + g ystride + off, its C^{-1} y at w + g wstride + off, its active-set
+// vectors q, r, u at ev + g kstride + koff, its candidates' q at
+// cq + g cstride + coff.
+struct Vecs {
+  int32_t G = 1;
+  int64_t ystride = 0, wstride = 0, kstride = 0, cstride = 0;
+};
+
 // Largest P whose transform buffer sits in LDS (P = 8192 fills one CU's LDS
 // with the twiddle head); larger transforms run the same passes on a buffer of
 // padded(P) in the instance's scratch, after its four P blocks.

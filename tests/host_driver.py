@@ -17,6 +17,7 @@ import tempfile
 import numpy as np
 
 from oracle import estimator as oe
+from oracle import mmv
 from oracle import numerics as nm
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -62,7 +63,9 @@ _PTRS = ["th", "ga", "th_e", "ga_e", "K_e", "beta_e", "req", "gbar_e", "zeta_e",
 
 
 class DrvArrays(ctypes.Structure):
-    _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_int), ("kcap", ctypes.c_int)] + \
+    _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_int), ("kcap", ctypes.c_int),
+                ("G", ctypes.c_int), ("vk", ctypes.c_int64), ("vc", ctypes.c_int64),
+                ("vo", ctypes.c_int64)] + \
                [(n, ctypes.c_void_p) for n in _PTRS]
 
 
@@ -70,13 +73,17 @@ REQ_EVAL, REQ_GRID, REQ_APPROX = 1, 2, 4
 
 
 class HostDriver:
-    """One instance: arrays in numpy, evaluations from the oracle."""
+    """One instance: arrays in numpy, evaluations from the oracle.  y is one
+    vector, or G x N for the multiple-vector model (evaluations from the MMV
+    oracle)."""
 
     def __init__(self, y, params: oe.Params | None = None, kcap: int | None = None,
                  cand_cap: int = 256):
         self.p = p = params or oe.Params()
         self.y = np.asarray(y, np.complex128)
-        N = self.N = len(self.y)
+        self.mmv = self.y.ndim == 2
+        G = self.G = self.y.shape[0] if self.mmv else 1
+        N = self.N = self.y.shape[-1]
         self.L = p.grid_size(N)
         kc = self.kcap = min(kcap or N, N)
         J = p.lbfgs_J
@@ -87,16 +94,19 @@ class HostDriver:
             "th": f64(kc), "ga": f64(kc), "th_e": f64(kc), "ga_e": f64(kc), "K_e": i32(1),
             "beta_e": f64(1), "req": i32(1), "gbar_e": f64(1), "zeta_e": f64(1),
             "g": f64(2 * kc), "d": f64(2 * kc), "Sm": f64(J * 2 * kc), "Ym": f64(J * 2 * kc),
-            "rhom": f64(J), "am": f64(J), "gt": f64(2 * kc), "q_save": f64(2 * kc),
-            **{f"ev_{q}": f64(2 * kc) for q in "qrustvx"},
+            "rhom": f64(J), "am": f64(J), "gt": f64(2 * kc), "q_save": f64(2 * G * kc),
+            **{f"ev_{q}": f64(2 * G * kc) for q in "qru"},
+            **{f"ev_{q}": f64(2 * kc) for q in "stvx"},
             "logdet": f64(1), "yCy": f64(1), "ww": f64(1), "lev_status": i32(1),
-            "cand": i32(cand_cap + 1), "ncand": i32(1), "cand_q": f64(2 * (cand_cap + 1)),
+            "cand": i32(cand_cap + 1), "ncand": i32(1), "cand_q": f64(2 * G * (cand_cap + 1)),
             "cand_s": f64(cand_cap + 1), "cbuf_dl": f64(cand_cap + 1),
             "cbuf_gh": f64(cand_cap + 1), "cbuf_l": i32(cand_cap + 1),
-            "out_K": np.zeros(1, np.int64), "out_theta": f64(kc), "out_alpha": f64(2 * kc),
+            "out_K": np.zeros(1, np.int64), "out_theta": f64(kc), "out_alpha": f64(2 * G * kc),
             "out_gamma": f64(kc), "out_beta": f64(1), "out_zeta": f64(1), "out_obj": f64(1),
             "out_iters": i32(1), "out_evals": i32(1), "out_status": i32(1)}
-        self.arr = DrvArrays(N, self.L, kc, *[a[n].ctypes.data for n in _PTRS])
+        self.vk, self.vc = 2 * kc, 2 * (cand_cap + 1)
+        self.arr = DrvArrays(N, self.L, kc, G, self.vk, self.vc, self.vk,
+                             *[a[n].ctypes.data for n in _PTRS])
         self.prm = DrvParams(p.tau, p.tol_obj, p.tol_newton, p.eps_beta_rel, p.eps_L,
                              p.approx_ratio, p.approx_min_dist, p.ls_c1, p.curv_eps,
                              p.polish_tol, p.polish_ftol, J, p.max_inner, p.max_outer,
@@ -104,7 +114,8 @@ class HostDriver:
                              p.polish_max_iters, cand_cap)
         self.st = DrvState()
         self.st.phase = 0
-        self.st.yy = float(np.vdot(self.y, self.y).real)
+        self.st.yy = (sum(float(np.vdot(v, v).real) for v in self.y) / G if self.mmv
+                      else float(np.vdot(self.y, self.y).real))
         self.requests: list[tuple] = []
         self.phases: list[tuple] = []
         self.last = None
@@ -119,7 +130,19 @@ class HostDriver:
         self.requests.append((bits, K, th, ga, beta))
         st = self.st
         self.phases.append((st.phase, st.it, st.inner, st.pit, st.polish, st.ls_trial))
-        if bits & REQ_EVAL:
+        if bits & REQ_EVAL and self.mmv:
+            ev = self.last = mmv.EvaluationMMV(self.y, th, ga, beta)
+            a["logdet"][0] = ev.logdet
+            a["yCy"][0] = ev.yCy
+            a["ww"][0] = sum(float(np.vdot(w, w).real) for w in ev.w)
+            for q in "qru":
+                for g in range(self.G):
+                    v = np.asarray(ev.act[q][g], np.complex128)
+                    a[f"ev_{q}"][g * self.vk:g * self.vk + 2 * K] = v.view(np.float64)
+            for q in "stvx":
+                a[f"ev_{q}"][:2 * K] = np.asarray(ev.act[q], np.complex128).view(np.float64)
+            a["lev_status"][0] = 0
+        elif bits & REQ_EVAL:
             ev = self.last = nm.Evaluation(self.y, th, ga, beta)
             a["logdet"][0] = ev.logdet
             a["yCy"][0] = ev.yCy
@@ -132,8 +155,13 @@ class HostDriver:
         if bits & REQ_GRID:
             zeta, gb = float(a["zeta_e"][0]), float(a["gbar_e"][0])
             qG, sG = ev.grid(self.L)
-            gbv = nm.gamma_hat(qG, sG) if gb <= 0 else np.full(self.L, gb)
-            dl = nm.delta_L(qG, sG, gbv, zeta)
+            if self.mmv:
+                Q = mmv.sum_q2(qG)
+                gbv = mmv.gamma_hat(Q, sG, self.G) if gb <= 0 else np.full(self.L, gb)
+                dl = mmv.delta_L(Q, sG, gbv, zeta, self.G)
+            else:
+                gbv = nm.gamma_hat(qG, sG) if gb <= 0 else np.full(self.L, gb)
+                dl = nm.delta_L(qG, sG, gbv, zeta)
             dl = np.where(np.isnan(dl), np.inf, dl)
             lmin = int(np.argmin(dl))
             cands = [lmin]
@@ -144,12 +172,13 @@ class HostDriver:
                 keep.sort(key=lambda l: (dl[l], l))
                 cands += keep[:self.cand_cap]
             ths = np.array(cands, np.float64) / self.L
-            qc = nm.q_at(ev.w, ths)
             sc = nm.s_at(ev.omega[0], ths).real
             n = len(cands)
             a["cand"][:n] = cands
             a["ncand"][0] = n
-            a["cand_q"][:2 * n] = np.asarray(qc, np.complex128).view(np.float64)
+            for g, w in enumerate(ev.w if self.mmv else [ev.w]):
+                qc = np.asarray(nm.q_at(w, ths), np.complex128)
+                a["cand_q"][g * self.vc:g * self.vc + 2 * n] = qc.view(np.float64)
             a["cand_s"][:n] = sc
 
     def run(self, max_steps=100000):
@@ -172,8 +201,12 @@ class HostDriver:
                 self._evaluate()
         a = self.a
         K = int(a["out_K"][0])
+        oa = a["out_alpha"]
+        alpha = (np.stack([oa[g * self.vk:g * self.vk + 2 * K].view(np.complex128)
+                           for g in range(self.G)]) if self.mmv
+                 else oa[:2 * K].view(np.complex128).copy())
         return dict(K=K, theta=a["out_theta"][:K].copy(), gamma=a["out_gamma"][:K].copy(),
-                    alpha=a["out_alpha"][:2 * K].view(np.complex128).copy(),
+                    alpha=alpha,
                     beta=float(a["out_beta"][0]), zeta=float(a["out_zeta"][0]),
                     objective=float(a["out_obj"][0]), iterations=int(a["out_iters"][0]),
                     evaluations=int(a["out_evals"][0]), status=int(a["out_status"][0]))

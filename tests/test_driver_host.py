@@ -92,3 +92,41 @@ def test_host_driver_iteration_cap_matches_oracle():
     assert o.status == oe.STATUS_NOTCONV and r["status"] == o.status
     assert r["iterations"] == o.iterations == 1 and r["K"] == o.K
     np.testing.assert_allclose(r["theta"], o.theta, rtol=0, atol=1e-12)
+
+
+def _mmv_instance(seed, G, N=64, K=3, snr_db=10.0):
+    rng = np.random.default_rng(seed)
+    th = synth.draw_frequencies(rng, K, 2.0 / N)
+    A = np.exp(2j * np.pi * np.outer(np.arange(N), th))
+    al = (rng.standard_normal((G, K)) + 1j * rng.standard_normal((G, K))) / np.sqrt(2)
+    H = al @ A.T
+    beta = float(np.mean(np.sum(np.abs(H) ** 2, axis=1))) / (N * 10 ** (snr_db / 10))
+    W = (rng.standard_normal((G, N)) + 1j * rng.standard_normal((G, N))) * np.sqrt(beta / 2)
+    return H + W
+
+
+@pytest.mark.parametrize("seed,G", [(1, 2), (2, 3), (3, 4)])
+def test_host_driver_mmv_matches_mmv_oracle(seed, G):
+    """The device driver's control flow with G observation vectors (Sec. V),
+    fed by the MMV oracle's evaluations, reproduces the MMV oracle estimator."""
+    from oracle import mmv
+    Y = _mmv_instance(seed, G)
+    o = mmv.estimate(Y)
+    r = hd.HostDriver(Y).run()
+    assert r["status"] == o.status and r["K"] == o.K and r["iterations"] == o.iterations
+    np.testing.assert_allclose(r["theta"], o.theta, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["gamma"], o.gamma, rtol=1e-9, atol=1e-14)
+    np.testing.assert_allclose(r["alpha"], o.alpha, rtol=1e-9, atol=1e-12)
+    assert r["beta"] == pytest.approx(o.beta, rel=1e-9)
+    assert r["objective"] == pytest.approx(o.objective, rel=1e-10, abs=1e-9)
+
+
+def test_host_driver_one_vector_as_mmv_is_the_single_vector_run():
+    """G = 1 given as a 1 x N observation matrix: the same steps and result, bit
+    for bit, as the single-vector run."""
+    inst = _instances()[1]
+    a = hd.HostDriver(inst.y).run()
+    b = hd.HostDriver(inst.y[None, :]).run()
+    assert a["K"] == b["K"] and a["evaluations"] == b["evaluations"]
+    assert np.array_equal(a["theta"], b["theta"]) and np.array_equal(a["alpha"], b["alpha"][0])
+    assert a["beta"] == b["beta"] and a["objective"] == b["objective"]

@@ -234,6 +234,33 @@ def test_grid(ctx, ns, Lm):
                 assert d_ref[pick] - d_ref.min() <= 1e-4 * np.max(np.abs(d_ref))
 
 
+def test_context_hbm_budget():
+    """A context's workspace stays within the budget given at creation: a batch
+    that would need more is refused with ENOMEM (nothing enqueued), a smaller
+    one runs, and a context without a cap runs the large one."""
+    ns = [4096] * 64
+    st = make_states(ns[:1], seed=5) * 64
+    cols = np.concatenate([nm.toeplitz_column(t, g, b, N) for (t, g, b, _), N in zip(st, ns)])
+    n, off = ragged(ns)
+    small = sf.Context(0, hbm_budget=8 << 20)
+    try:
+        out = [zeros_c(n.sum()), torch.zeros(int(n.sum()), dtype=torch.float64, device=DEV),
+               torch.zeros(64, dtype=torch.float64, device=DEV),
+               torch.zeros(64, dtype=torch.int32, device=DEV),
+               torch.zeros(64, dtype=torch.int64, device=DEV)]
+        with pytest.raises(sf.SflsError) as e:
+            sf.sfls_factor(small, n, off, c2d(cols), *out)
+        assert e.value.status == sf.SFLS_ENOMEM
+        n1, off1 = ragged(ns[:1])
+        sf.sfls_factor(small, n1, off1, c2d(cols[:4096]), *[o[:2 * 4096] if i == 0 else
+                                                           (o[:4096] if i == 1 else o[:1])
+                                                           for i, o in enumerate(out)])
+        torch.cuda.synchronize()
+        assert int(out[3][0].cpu()) == 0
+    finally:
+        small.close()
+
+
 def test_grid_out_mask(ctx):
     """Only the outputs named in out_mask are written (the others' buffers stay
     untouched), r^G alone needs no diagonal sums, a named NULL output and an
