@@ -73,7 +73,8 @@ typedef struct {
     int32_t max_inner;      /* step-4 repetitions per outer iteration */
     int32_t max_outer;      /* outer iteration cap (then status SFLS_NOTCONV) */
     int32_t approx_max_iters; /* outer iterations that may use approximate activation (0: never) */
-    int32_t approx_use_tau; /* 1: tau in the approximate scheme's criterion */
+    int32_t approx_use_tau; /* 1: tau also in the approximate scheme's criterion (default 0:
+                             * eq. activate_derived, as Sec. II-F states) */
     int32_t ls_max;         /* backtracking trials per line search */
     int32_t polish_max_iters; /* final (theta,gamma) polish iterations */
     int32_t cand_cap;       /* max candidates re-checked per approximate sweep */

@@ -38,7 +38,7 @@ class Params:
     eps_beta_rel: float = 1e-10  # eps_beta = eps_beta_rel ||y||^2 / N
     eps_L: float = 2.220446049250313e-16
     approx_max_iters: int = 10   # iterations that may use the approximate scheme
-    approx_use_tau: bool = True
+    approx_use_tau: bool = False  # Sec. II-F cites eq. activate_derived (no tau)
     approx_ratio: float = 5.0    # Delta L <= Delta L_min / 5
     approx_min_dist: float = 0.05  # wrap distance >= 0.05 / N
     ls_c1: float = 1e-4

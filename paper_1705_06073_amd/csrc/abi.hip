@@ -430,7 +430,7 @@ void sfls_params_default(sfls_params* p) {
   p->max_inner = 5;
   p->max_outer = 200;
   p->approx_max_iters = 10;
-  p->approx_use_tau = 1;
+  p->approx_use_tau = 0;
   p->ls_max = 30;
   p->polish_max_iters = 30;
   p->cand_cap = 256;

@@ -42,10 +42,15 @@ def ctx():
     c.close()
 
 
+def _y(ref):
+    w = synth.workload_n4096 if ref["workload"] == "n4096" else synth.workload_uneven
+    return w(ref["instance"]).y
+
+
 def check(cases, results, grid_fp32, label):
     verdicts = []
     for ref, got in zip(cases, results):
-        v = parity.judge(ref, got, ref["N"], grid_fp32)
+        v = parity.judge(ref, got, ref["N"], grid_fp32, flat=parity.oracle_flat(_y(ref)))
         print(f"[{label}] {ref['workload']}[{ref['instance']}] N={ref['N']} K gpu {got.K} "
               f"oracle {ref['K']} (true {ref['K_true']}) evals gpu {got.evaluations} oracle "
               f"{ref['evaluations']}: {v.kind} {v.detail}"

@@ -84,3 +84,30 @@ def test_oracle_records_margins_of_each_decision_class(ref):
     lz = parity.last_z_change(r.trace)
     assert 1 <= lz <= r.iterations
     assert all(m[2] <= lz for m in d["margins_path"])
+
+
+def test_flat_objective_rule(ref):
+    """A frequency difference is ambiguous when the oracle at the HIP point has
+    the same objective within its rounding level and no resolvable Newton step;
+    otherwise (a larger objective, or a gradient left) it is a mismatch."""
+    inst, r, d = ref
+    th = np.array(r.theta)
+    th[0] += 5e-9 / inst.N
+    d_far = dict(d, margins_z=[], margins_grid=[], margins_path=[])
+    got = as_got(r, theta=th, zeta=r.zeta)
+    f0 = r.objective
+    v = parity.judge(d_far, got, inst.N, False, flat=lambda g: (f0 + 1e-14 * abs(f0), 1e-20))
+    assert v.kind == "ambiguous" and v.site == "flat_objective"
+    v = parity.judge(d_far, got, inst.N, False, flat=lambda g: (f0 + 1e-9 * abs(f0), 1e-20))
+    assert v.kind == "mismatch"
+    v = parity.judge(d_far, got, inst.N, False, flat=lambda g: (f0, 1e-6))
+    assert v.kind == "mismatch"
+    # the oracle's own evaluation at a genuinely displaced point is not flat
+    th[0] += 1e-3 / inst.N
+    assert parity.judge(d_far, as_got(r, theta=th, zeta=r.zeta), inst.N, False,
+                        flat=parity.oracle_flat(inst.y, oe_params())).kind == "mismatch"
+
+
+def oe_params():
+    from oracle.estimator import Params
+    return Params(L_mult=4.0)
