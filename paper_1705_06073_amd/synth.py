@@ -229,6 +229,43 @@ def workload_paper_snr(instance: int, snr_db: float, N: int = 128, K: int = 10) 
     return make_instance(rng, N, K, 2.0 / N, "paper", snr_db, np.complex128, s)
 
 
+def draw_pairs(rng: np.random.Generator, npairs: int, pair_sep: float, sep: float,
+               max_tries: int = 10_000) -> np.ndarray:
+    """Frequencies in `npairs` pairs {t, t + pair_sep}: the pairs' positions t
+    are drawn one after another, uniformly among the positions whose two
+    frequencies are farther than `sep` (wrap distance) from every frequency of
+    the pairs drawn before (the placement of Sec. VI-A applied to pairs)."""
+    while True:
+        th: list[float] = []
+        for _ in range(npairs):
+            for _try in range(max_tries):
+                t = rng.random()
+                pair = (t, (t + pair_sep) % 1.0)
+                if all(_wrap1(p, q) > sep for p in pair for q in th):
+                    th.extend(pair)
+                    break
+            else:
+                break
+        if len(th) == 2 * npairs:
+            return np.array(th, dtype=np.float64)
+
+
+def workload_paper_pairs(instance: int, pair_sep_n: float, N: int = 128, npairs: int = 5,
+                         snr_db: float = 20.0) -> Instance:
+    """The super-resolution experiment: N=128, 5 pairs (K=10) whose members are
+    pair_sep_n / N apart, pairs at least 2/N apart, paper's alpha, 20 dB."""
+    s = seed_for(8, instance) + int(round(pair_sep_n * 1000)) * 1000
+    rng = np.random.Generator(np.random.PCG64(s))
+    theta = draw_pairs(rng, npairs, pair_sep_n / N, 2.0 / N)
+    K = len(theta)
+    alpha = draw_alpha(rng, K, "paper")
+    h = clean_signal(theta, alpha, N)
+    beta = float(np.vdot(h, h).real / (N * 10.0 ** (snr_db / 10.0)))
+    w = math.sqrt(beta / 2.0) * (rng.standard_normal(N) + 1j * rng.standard_normal(N))
+    return Instance(N=N, K=K, theta=theta, alpha=alpha, beta=beta, snr_db=snr_db, y=h + w,
+                    seed=s, meta={"pair_sep_n": pair_sep_n})
+
+
 def pack_batch(instances, dtype=np.complex128):
     """Concatenate y of a ragged batch; returns (y_flat, n, off)."""
     n = np.array([inst.N for inst in instances], dtype=np.int64)
