@@ -352,8 +352,9 @@ struct Driver {
     kstar = T::imin((kstar >= 0 && amax == am) ? kstar : INT32_MAX);
     S.amax = am;
     S.kstar = kstar == INT32_MAX ? -1 : kstar;
-    if (polish) S.alpha = (amax > 1.0) ? 1.0 : 0.5 * amax;
-    else S.alpha = fmin(1.0, amax);
+    // the first trial from the team's limit (every lane steps by the same alpha)
+    if (polish) S.alpha = (am > 1.0) ? 1.0 : 0.5 * am;
+    else S.alpha = fmin(1.0, am);
     S.ls_trial = 0;
     S.polish = polish ? 1 : 0;
   }
@@ -379,14 +380,21 @@ struct Driver {
     S.cur_valid = 0;
   }
 
-  // Drops component k, shifting those above it down by one.  Strided over the
-  // lanes: each lane loads before it stores, and the stores of one chunk lie
-  // below the loads of the next.
+  // Drops component k, shifting those above it down by one.  In chunks of
+  // the team's width: the lanes load their entries of a chunk, then store
+  // them one place lower (the stores of a chunk lie below the loads of the
+  // next).
   SFLS_HD void remove_component(int k) {
-    for (int j = k + T::lane(); j + 1 < S.K; j += T::width()) {
-      const double t = A.th[j + 1], g = A.ga[j + 1];
-      A.th[j] = t;
-      A.ga[j] = g;
+    for (int j0 = k; j0 + 1 < S.K; j0 += T::width()) {
+      const int j = j0 + T::lane();
+      const bool mv = j + 1 < S.K;
+      const double t = mv ? A.th[j + 1] : 0.0, g = mv ? A.ga[j + 1] : 0.0;
+      T::sync();
+      if (mv) {
+        A.th[j] = t;
+        A.ga[j] = g;
+      }
+      T::sync();
     }
     T::sync();
     S.K -= 1;
@@ -500,6 +508,7 @@ struct Driver {
         if (A.cbuf_gh[c] > 0.0 && A.cand[c] == l && A.cbuf_dl[c] == dmin) cl = c;
       cl = T::imin(cl);
       const double gh = A.cbuf_gh[cl];
+      T::sync();  // every lane has read the entry before it is marked as taken
       A.cbuf_gh[cl] = -1.0;
       T::sync();
       const double th = (double)l / (double)A.L;

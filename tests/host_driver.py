@@ -29,7 +29,7 @@ def lib():
     global _lib
     if _lib is None:
         out = os.path.join(tempfile.mkdtemp(prefix="sfls_drv_"), "driver_host.so")
-        subprocess.run(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", f"-I{CSRC}",
+        subprocess.run(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-pthread", f"-I{CSRC}",
                         os.path.join(HERE, "host", "driver_host.cpp"), "-o", out],
                        check=True, capture_output=True)
         _lib = ctypes.CDLL(out)
@@ -181,8 +181,12 @@ class HostDriver:
                 a["cand_q"][g * self.vc:g * self.vc + 2 * n] = qc.view(np.float64)
             a["cand_s"][:n] = sc
 
-    def run(self, max_steps=100000):
+    def run(self, max_steps=100000, lanes: int = 0):
+        """Step the driver to completion.  lanes > 0 runs each step with that
+        many lanes in lockstep and records, per step, how many lanes ended in a
+        state different from lane 0's (``self.lane_diffs``)."""
         L = lib()
+        self.lane_diffs = []
         sizes = (ctypes.c_int * 3)()
         L.drv_sizes(sizes)
         assert tuple(sizes) == (ctypes.sizeof(DrvParams), ctypes.sizeof(DrvState),
@@ -191,7 +195,11 @@ class HostDriver:
         self.req_seq = []
         prev = 0
         for _ in range(max_steps):
-            L.drv_step(ctypes.byref(self.prm), ctypes.byref(self.st), ctypes.byref(self.arr))
+            if lanes > 0:
+                self.lane_diffs.append(L.drv_step_lanes(
+                    ctypes.byref(self.prm), ctypes.byref(self.st), ctypes.byref(self.arr), lanes))
+            else:
+                L.drv_step(ctypes.byref(self.prm), ctypes.byref(self.st), ctypes.byref(self.arr))
             req = int(self.a["req"][0]) if not self.st.done else 0
             self.req_seq.append((prev, req))
             prev = req

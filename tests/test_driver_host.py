@@ -130,3 +130,33 @@ def test_host_driver_one_vector_as_mmv_is_the_single_vector_run():
     assert a["K"] == b["K"] and a["evaluations"] == b["evaluations"]
     assert np.array_equal(a["theta"], b["theta"]) and np.array_equal(a["alpha"], b["alpha"][0])
     assert a["beta"] == b["beta"] and a["objective"] == b["objective"]
+
+
+def _lane_instances():
+    """Signals whose runs take line searches limited by a gamma reaching zero
+    (weak components drawn next to strong ones, low SNR) besides ordinary ones."""
+    rng = np.random.default_rng(777)
+    out = list(_instances())
+    for N, K, snr in [(80, 6, 5.0), (150, 9, 8.0), (120, 12, 3.0)]:
+        out.append(synth.make_instance(rng, N, K, 1.0 / N, "logamp20", snr))
+    # at 0 dB: draws 1, 4 and 5 of this sequence each take one line search
+    # whose first step is cut short by a gamma reaching zero
+    rng = np.random.default_rng(5)
+    low = [synth.make_instance(rng, 64, 8, 1.0 / 64, "logamp20", 0.0) for _ in range(6)]
+    out += [low[1], low[4], low[5]]
+    return out
+
+
+@pytest.mark.parametrize("idx", range(10))
+def test_lanes_in_lockstep_hold_the_same_state(idx):
+    """The driver run as the device runs it, 8 lanes in lockstep: after every
+    step all lanes hold bitwise the same scalar state (a decision taken from a
+    lane's own partial value instead of the team's would split them), and the
+    result is the oracle's."""
+    inst = _lane_instances()[idx]
+    o = oe.estimate(inst.y)
+    h = hd.HostDriver(inst.y)
+    r = h.run(lanes=8)
+    assert all(d == 0 for d in h.lane_diffs), [i for i, d in enumerate(h.lane_diffs) if d]
+    assert r["K"] == o.K
+    np.testing.assert_allclose(r["theta"], o.theta, rtol=0, atol=1e-10)
