@@ -21,6 +21,10 @@ mmv        -- the multiple-measurement-vector model of Sec. V: its objective,
               summed derivatives, single-component criteria and beta update,
               and the estimator on them (G = 1 is the estimator above, bit for
               bit).
+incomplete -- incomplete observations (Sec. IV): Phi keeps M weighted samples;
+              C is M x M and every quantity is formed densely from its
+              definition under Phi (every sample observed with unit weights is
+              the estimator above, bit for bit).
 
 Parity status: every numerics function is pinned by tests under
 ``tests/test_oracle_*.py`` (closed forms, brute force, finite differences,

@@ -10,7 +10,8 @@ Follows the block-coordinate descent of Sec. II-C/E step by step:
   3. beta update (eq. betaUpdate, mu and Sigma by eqs. bmu / bSigma),
   4. up to 5 x { one L-BFGS step on (theta, gamma) with a diagonal-Hessian
      initialisation (Sec. II-D), deactivation by eq. deactivate },
-  stop when the objective changes by less than N * 1e-7 between iterations,
+  stop when the objective changes by less than M * 1e-7 between iterations
+  (M observations; M = N for complete data),
 
 followed by a final Newton-type polish of (theta, gamma) with z, beta, zeta
 held fixed (:meth:`OracleEstimator._polish`).  The paper leaves several points
@@ -33,9 +34,9 @@ class Params:
     lbfgs_J: int = 10            # L-BFGS memory (Sec. II-D)
     max_inner: int = 5           # step 4 repetitions (Sec. II-E)
     max_outer: int = 200
-    tol_obj: float = 1e-7        # |L_i - L_{i-1}| < N tol_obj (Sec. II-E)
-    tol_newton: float = 1e-8     # squared Newton decrement < N tol_newton (Sec. II-E)
-    eps_beta_rel: float = 1e-10  # eps_beta = eps_beta_rel ||y||^2 / N
+    tol_obj: float = 1e-7        # |L_i - L_{i-1}| < M tol_obj (Sec. II-E)
+    tol_newton: float = 1e-8     # squared Newton decrement < M tol_newton (Sec. II-E)
+    eps_beta_rel: float = 1e-10  # eps_beta = eps_beta_rel ||y||^2 / M
     eps_L: float = 2.220446049250313e-16
     approx_max_iters: int = 10   # iterations that may use the approximate scheme
     approx_use_tau: bool = False  # Sec. II-F cites eq. activate_derived (no tau)
@@ -47,7 +48,7 @@ class Params:
     polish_max_iters: int = 30
     polish_tol: float = 1e-12    # polish converged when max |dtheta| < polish_tol / N
     polish_ftol: float = 1e-13   # rounding level of the objective, relative to 1 + |f|
-    kcap: int = 0                # 0: K_max = N
+    kcap: int = 0                # 0: K_max = M
 
     def grid_size(self, N: int) -> int:
         return int(2 ** int(round(math.log2(self.L_mult * N))))
@@ -115,10 +116,15 @@ class OracleEstimator:
         self.check_blocks = check_blocks
         self.y = np.asarray(y, dtype=np.complex128)
         self.N = self.y.shape[-1]
+        # observations per vector (Sec. II-A: y has M entries; M = N for
+        # complete data).  The count scales of Sec. II-E (the initial beta,
+        # the stopping rules, K_max = M, eq. zetaUpdate) are in M; the
+        # frequency scales (grid, distances, the polish's tolerance) in N.
+        self.M = self.N
         self.G = 1              # observation vectors (Sec. V); 1 = the SMV model
         self.p = params or Params()
         self.L = self.p.grid_size(self.N)
-        self.kcap = self.N if self.p.kcap <= 0 else min(self.p.kcap, self.N)
+        self.kcap = self.M if self.p.kcap <= 0 else min(self.p.kcap, self.M)
         self.n_evals = 0
         self.cap_hit = False
         self.trace: list = []
@@ -404,14 +410,14 @@ class OracleEstimator:
 
     # ------------------------------------------------------------------
     def run(self) -> Result:
-        p, N, G = self.p, self.N, self.G
+        p, M, G = self.p, self.M, self.G
         yy = self._energy()
         if yy == 0.0:
             return Result(0, np.zeros(0), np.zeros(0, np.complex128), np.zeros(0), 0.0, 0.0,
                           -math.inf, 0, 0, STATUS_OK)
-        beta = 0.01 * yy / N                      # initialisation (Sec. II-E)
+        beta = 0.01 * yy / M                      # initialisation (Sec. II-E)
         zeta = 0.2
-        eps_beta = p.eps_beta_rel * yy / N
+        eps_beta = p.eps_beta_rel * yy / M
         theta = np.zeros(0)
         gamma = np.zeros(0)
         approx_on = p.approx_max_iters > 0
@@ -457,8 +463,8 @@ class OracleEstimator:
                     z_changed = True
             K = len(theta)
             # ---- step 2: zeta ------------------------------------------
-            self._block("zeta", (theta, gamma, beta, zeta), (theta, gamma, beta, min(0.5, K / N)))
-            zeta = min(0.5, K / N)
+            self._block("zeta", (theta, gamma, beta, zeta), (theta, gamma, beta, min(0.5, K / M)))
+            zeta = min(0.5, K / M)
             # ---- step 3: beta (EM bound) ----------------------------------
             beta_new = self._beta_update(theta, gamma, beta, eps_beta)
             self._block("beta", (theta, gamma, beta, zeta), (theta, gamma, beta_new, zeta))
@@ -502,8 +508,8 @@ class OracleEstimator:
                     gamma = np.delete(gamma, k)
                     mem.reset()
                     cur = ensure(None)
-                self._margin("fp64", "decrement", lam2, G * N * p.tol_newton)
-                if lam2 < G * N * p.tol_newton:
+                self._margin("fp64", "decrement", lam2, G * M * p.tol_newton)
+                if lam2 < G * M * p.tol_newton:
                     break
             # ---- termination ---------------------------------------------
             K = len(theta)
@@ -511,9 +517,9 @@ class OracleEstimator:
             L_cur = cur.f(K, zeta)
             self.trace.append(("iter", it, K, L_cur, beta))
             if math.isfinite(L_prev):
-                self._margin("fp64", "terminate", abs(L_cur - L_prev), G * N * p.tol_obj,
+                self._margin("fp64", "terminate", abs(L_cur - L_prev), G * M * p.tol_obj,
                              1.0 + abs(L_cur))
-            if abs(L_cur - L_prev) < G * N * p.tol_obj:
+            if abs(L_cur - L_prev) < G * M * p.tol_obj:
                 converged = True
                 break
             L_prev = L_cur

@@ -1,8 +1,9 @@
 """Seeded synthetic signals for the line-spectral-estimation workloads.
 
 This module only draws inputs: frequencies, coefficients, noise and the
-observation y = sum_k alpha_k psi(theta_k) + w of the signal model (Sec. II,
-eq. "model", complete-data case Phi = I).  It holds none of the estimator's
+observation y = sum_k alpha_k Phi psi(theta_k) + w of the signal model (Sec. II,
+eq. "model"): the complete-data case Phi = I, and incomplete observations
+(Sec. IV) where Phi keeps M of the N samples, each scaled by a weight.  It holds none of the estimator's
 arithmetic, so the CPU oracle and the HIP path can both consume its output.
 
 Conventions
@@ -12,8 +13,12 @@ Conventions
 * Frequencies are drawn sequentially, each uniform on the part of [0,1) whose
   wrap-around distance to every earlier frequency exceeds ``sep``
   (Sec. VI-A; the wrap-around distance is the one of the footnote in Sec. II-F).
-* SNR is ||Psi alpha||^2 / (N beta) of the realised signal (Sec. VI-A);
-  an instance with K = 0 gets beta = 1.
+* SNR is ||Phi Psi alpha||^2 / (M beta) of the realised signal (Sec. VI-A;
+  M = N for complete data); an instance with K = 0 gets beta = 1.
+* Incomplete observations: the observed indices include the first and the
+  last sample, the other M - 2 are drawn uniformly without replacement
+  (Sec. VI-E); the weights are 1 (rows of the identity) unless a workload
+  states otherwise.
 * Seeds: 1705060730 + 1_000_000 * config + instance, PCG64.
 """
 from __future__ import annotations
@@ -132,6 +137,14 @@ class Instance:
     y: np.ndarray           # complex128 or complex64, as the workload states
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    # incomplete observations (Sec. IV): y holds the M samples at the
+    # strictly increasing indices idx, weighted by phi (None: all N samples)
+    idx: np.ndarray | None = None
+    phi: np.ndarray | None = None
+
+    @property
+    def M(self) -> int:
+        return self.N if self.idx is None else len(self.idx)
 
 
 def make_instance(rng: np.random.Generator, N: int, K: int, sep: float,
@@ -150,6 +163,50 @@ def make_instance(rng: np.random.Generator, N: int, K: int, sep: float,
     y = (h + w).astype(dtype)
     return Instance(N=N, K=K, theta=theta, alpha=alpha, beta=beta, snr_db=snr_db,
                     y=y, seed=seed)
+
+
+def draw_observed(rng: np.random.Generator, N: int, M: int) -> np.ndarray:
+    """Observed sample indices: 0 and N-1, and M-2 others drawn uniformly
+    without replacement from 1..N-2 (Sec. VI-E), in increasing order."""
+    if not 2 <= M <= N:
+        raise ValueError("need 2 <= M <= N")
+    inner = rng.choice(np.arange(1, N - 1), size=M - 2, replace=False)
+    return np.sort(np.concatenate([[0, N - 1], inner]).astype(np.int64))
+
+
+def draw_weights(rng: np.random.Generator, M: int, kind: str) -> np.ndarray:
+    """Weights phi_m of Phi: ``ones`` (rows of the identity, Sec. VI-E),
+    ``phase`` (unit modulus, uniform phase), ``scaled`` (modulus log-uniform on
+    [0.5, 2], uniform phase)."""
+    if kind == "ones":
+        return np.ones(M, np.complex128)
+    ph = np.exp(2j * math.pi * rng.random(M))
+    if kind == "phase":
+        return ph
+    if kind == "scaled":
+        return ph * 2.0 ** (2.0 * rng.random(M) - 1.0)
+    raise ValueError(f"unknown weight kind {kind!r}")
+
+
+def make_incomplete_instance(rng: np.random.Generator, N: int, M: int, K: int, sep: float,
+                             alpha_kind: str, snr_db: float, dtype=np.complex128,
+                             seed: int = 0, weights: str = "ones") -> Instance:
+    """y = Phi Psi(theta) alpha + w with Phi of M weighted rows of the identity."""
+    theta = draw_frequencies(rng, K, sep) if K > 0 else np.zeros(0)
+    alpha = draw_alpha(rng, K, alpha_kind) if K > 0 else np.zeros(0, np.complex128)
+    idx = draw_observed(rng, N, M)
+    phi = draw_weights(rng, M, weights)
+    h = phi * clean_signal(theta, alpha, N)[idx]
+    if K > 0 and math.isfinite(snr_db):
+        beta = float(np.vdot(h, h).real / (M * 10.0 ** (snr_db / 10.0)))
+    elif K > 0:
+        beta = 0.0
+    else:
+        beta = 1.0
+    w = math.sqrt(beta / 2.0) * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    return Instance(N=N, K=K, theta=theta, alpha=alpha, beta=beta, snr_db=snr_db,
+                    y=(h + w).astype(dtype), seed=seed, idx=idx, phi=phi,
+                    meta={"weights": weights})
 
 
 # ---------------------------------------------------------------------------
@@ -264,6 +321,40 @@ def workload_paper_pairs(instance: int, pair_sep_n: float, N: int = 128, npairs:
     w = math.sqrt(beta / 2.0) * (rng.standard_normal(N) + 1j * rng.standard_normal(N))
     return Instance(N=N, K=K, theta=theta, alpha=alpha, beta=beta, snr_db=snr_db, y=h + w,
                     seed=s, meta={"pair_sep_n": pair_sep_n})
+
+
+def workload_paper_mton(instance: int, ratio: float, N: int = 128, K: int = 10,
+                        snr_db: float = 20.0) -> Instance:
+    """The incomplete-data experiment (Fig. MtoN): N=128, K=10, separation 2/N,
+    paper's alpha, 20 dB, M = round(ratio N) rows of the identity."""
+    s = seed_for(9, instance) + int(round(ratio * 1000)) * 1000
+    rng = np.random.Generator(np.random.PCG64(s))
+    M = int(round(ratio * N))
+    return make_incomplete_instance(rng, N, M, K, 2.0 / N, "paper", snr_db, np.complex128, s)
+
+
+def workload_incomplete_n4096(instance: int) -> Instance:
+    """Incomplete data at the runtime experiment's size (Fig. runtime_N, right):
+    N=4096, M=3072 rows of the identity, K=15, separation 2/N, paper's alpha,
+    20 dB, complex64."""
+    s = seed_for(10, instance)
+    rng = np.random.Generator(np.random.PCG64(s))
+    return make_incomplete_instance(rng, 4096, 3072, 15, 2.0 / 4096, "paper", 20.0,
+                                    np.complex64, s)
+
+
+def workload_incomplete_small(instance: int, weights: str = "scaled") -> Instance:
+    """Small incomplete instances for parity: N uniform on [48, 320], M/N
+    uniform on [0.3, 0.9], K uniform on 1..6, separation 2/N, alpha ~ CN(0,1),
+    SNR uniform on [5, 30] dB, weighted rows (``weights``)."""
+    s = seed_for(11, instance)
+    rng = np.random.Generator(np.random.PCG64(s))
+    N = int(rng.integers(48, 321))
+    M = max(4, int(round(float(rng.uniform(0.3, 0.9)) * N)))
+    K = int(rng.integers(1, 7))
+    snr = float(rng.uniform(5.0, 30.0))
+    return make_incomplete_instance(rng, N, M, K, 2.0 / N, "cn", snr, np.complex128, s,
+                                    weights=weights)
 
 
 def pack_batch(instances, dtype=np.complex128):

@@ -41,8 +41,12 @@ def nmse(theta_true, alpha_true, theta_est, alpha_est, N):
 
 
 def oracle_ls_nmse(inst):
-    """Least squares for alpha with the true frequencies (the "Oracle" curve of Fig. snr)."""
-    n = np.arange(inst.N)
+    """Least squares for alpha with the true frequencies (the "Oracle" curve of
+    Figs. snr and MtoN): A = Phi Psi(theta) on the observed samples, the NMSE
+    taken on the whole length-N signal."""
+    n = np.arange(inst.N) if inst.idx is None else inst.idx
     A = np.exp(2j * np.pi * np.outer(n, inst.theta))
+    if inst.idx is not None:
+        A = inst.phi[:, None] * A
     a, *_ = np.linalg.lstsq(A, inst.y.astype(np.complex128), rcond=None)
     return nmse(inst.theta, inst.alpha, inst.theta, a, inst.N)
