@@ -350,6 +350,70 @@ sfls_status sfls_estimate_mmv(sfls_ctx* ctx, int64_t B, const int64_t* n, const 
                               int32_t* iters, int32_t* evals, int32_t* status, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Incomplete observations (Sec. IV): Phi keeps M of the N samples, each
+ * scaled by a nonzero weight (M rows of a diagonal matrix; the footnote of
+ * Sec. IV), so y in C^M and C = beta I_M + A Gamma A^H with A = Phi Psi.  The
+ * evaluation uses the semifast method of Sec. IV: Woodbury's identity with the
+ * K x K matrix K_s = beta I + Gamma^{1/2} A^H A Gamma^{1/2} (eqs. CfromSigma,
+ * AhA), its Cholesky factor, and the matrix determinant lemma for ln|C|;
+ * s, t, v, x from the Gram sums A^H D^p A, and on the grid q^G from
+ * Phi^H C^{-1} y and s^G from the diagonal sums of Phi^H C^{-1} Phi (one
+ * autocorrelation by FFT per active component).
+ * Observation arguments of both calls:
+ *   n     host i64 [B]  signal lengths N (2 <= n <= SFLS_MAX_N)
+ *   m     host i64 [B]  observed samples M (1 <= m <= n)
+ *   moff  host i64 [B]  offset of instance b's observations in idx, phi, y
+ *   idx   device i32 [sum m] observed sample indices, strictly increasing in
+ *         [0, n) per instance (checked on the device first: SFLS_EINVAL)
+ *   phi   device c128 [sum m] weights, nonzero and finite; NULL: all 1
+ *   y     device (ydtype) [sum m] observed samples
+ * Components: at most SFLS_SF_MAX_K per instance (the factor and its inverse
+ * are kept on chip); the model order's capacity is min(kcap, m, SFLS_SF_MAX_K)
+ * (K_max = M: the footnote of Sec. II-A).
+ * ------------------------------------------------------------------------- */
+#define SFLS_SF_MAX_K 64
+
+/* One semifast evaluation at K[b] components (theta, gamma device f64 at
+ * koff[b]; beta device f64 [B]):
+ *   logdet, yCy, ww  device f64 [B] out: ln|C|, y^H C^{-1} y, ||C^{-1} y||^2
+ *   q, r, u, s, t, v, x  device c128 out at koff (eqs. q-x with Phi)
+ *   L, goff (host i64 [B]; NULL: no grid) with qG (c128) / sG (f64) device
+ *   out at goff: q^G and s^G on theta = l/L, FP64 (each may be NULL);
+ *   cand (device i32 at coff), ncand, coff (host i64 [B]) with cq (c128),
+ *   cs (f64) device out at coff: q and s at theta = cand / L (needs L).
+ *   status device i32 [B] out (may be NULL): 0, or SFLS_ENOTPD when K_s is
+ *   not positive definite (the instance's other outputs are then undefined).
+ * Any output may be NULL; K[b] <= min(m[b], SFLS_SF_MAX_K). */
+sfls_status sfls_incomplete_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* m,
+                                 const int64_t* moff, const int32_t* idx, const double* phi,
+                                 const void* y, int32_t ydtype, const int64_t* K,
+                                 const int64_t* koff, const double* theta, const double* gamma,
+                                 const double* beta, double* logdet, double* yCy, double* ww,
+                                 double* q, double* r, double* u, double* s, double* t, double* v,
+                                 double* x, const int64_t* L, const int64_t* goff, double* qG,
+                                 double* sG, const int32_t* cand, const int64_t* ncand,
+                                 const int64_t* coff, double* cq, double* cs, int32_t* status,
+                                 void* stream);
+
+/* The estimator (Sec. II) on incomplete observations, every evaluation by the
+ * semifast method: sfls_estimate's algorithm, outputs and round loop, with the
+ * count scales of Sec. II-E in M (initial beta = 0.01 ||y||^2 / M, eps_beta,
+ * the stopping rules M 1e-7 and M 1e-8, K_max = M in the prior and eq.
+ * zetaUpdate) and the frequency scales in N (grid L = 2^round(log2(L_mult N)),
+ * distances 0.05/N, the refinement's 1e-12/N).  kcap, koff, K, theta, alpha,
+ * gamma, beta, zeta, objective, iters, evals and status as in sfls_estimate
+ * (status SFLS_ECAPACITY also when the model order would exceed
+ * SFLS_SF_MAX_K).  Every sample observed with unit weights estimates what
+ * sfls_estimate does, by another evaluation route. */
+sfls_status sfls_estimate_incomplete(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* m,
+                                     const int64_t* moff, const int32_t* idx, const double* phi,
+                                     const void* y, int32_t ydtype, const sfls_params* params,
+                                     const int64_t* kcap, const int64_t* koff, int64_t* K,
+                                     double* theta, double* alpha, double* gamma, double* beta,
+                                     double* zeta, double* objective, int32_t* iters,
+                                     int32_t* evals, int32_t* status, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Measurement of sfls_estimate (no effect on results).
  *
  * sfls_set_timing(ctx, 1) brackets every kernel launch of the estimate round

@@ -31,13 +31,14 @@ SFLS_GRID_Q, SFLS_GRID_S, SFLS_GRID_R, SFLS_GRID_T, SFLS_GRID_DL, SFLS_GRID_ARGM
 EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror",
            "sfls_last_error", "sfls_version", "sfls_toeplitz_column", "sfls_factor",
            "sfls_gs_apply", "sfls_gs_apply_noalloc", "sfls_omega", "sfls_grid_eval", "sfls_active_eval", "sfls_estimate",
-           "sfls_estimate_mmv",
+           "sfls_estimate_mmv", "sfls_incomplete_eval", "sfls_estimate_incomplete",
            "sfls_set_timing", "sfls_reset_stats", "sfls_kernel_stats", "sfls_last_run",
            "sfls_set_factor", "sfls_set_nufft", "sfls_set_schur_lds", "sfls_server_config_default",
            "sfls_server_create", "sfls_server_destroy", "sfls_server_footprint",
            "sfls_server_submit", "sfls_server_submit_many", "sfls_server_launch",
            "sfls_server_wait", "sfls_server_step", "sfls_server_poll", "sfls_server_get_stats"]
 SFLS_FACTOR_AUTO, SFLS_FACTOR_LEVINSON, SFLS_FACTOR_SCHUR = 0, 1, 2
+SFLS_SF_MAX_K = 64  # largest model order of the semifast (incomplete-data) evaluation
 SFLS_NUFFT_AUTO, SFLS_NUFFT_OFF, SFLS_NUFFT_ON = 0, 1, 2
 
 
@@ -151,6 +152,14 @@ def lib() -> ctypes.CDLL:
                                     ctypes.POINTER(sfls_params), _I64P, _I64P, _P, _P, _P, i64,
                                     _P, _P, _P, _P, _P, _P, _P, _P]
     L.sfls_estimate_mmv.restype = st
+    L.sfls_incomplete_eval.argtypes = [_P, i64, _I64P, _I64P, _I64P, _P, _P, _P, i32, _I64P,
+                                       _I64P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                       _P, _I64P, _I64P, _P, _P, _P, _I64P, _I64P, _P, _P, _P, _P]
+    L.sfls_incomplete_eval.restype = st
+    L.sfls_estimate_incomplete.argtypes = [_P, i64, _I64P, _I64P, _I64P, _P, _P, _P, i32,
+                                           ctypes.POINTER(sfls_params), _I64P, _I64P, _P, _P,
+                                           _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.sfls_estimate_incomplete.restype = st
     L.sfls_set_factor.argtypes = [_P, i32]
     L.sfls_set_factor.restype = st
     L.sfls_set_nufft.argtypes = [_P, i32]
@@ -390,6 +399,35 @@ def sfls_estimate_mmv(ctx: Context, n, off, G, y, ystride, ydtype, params, kcap,
                                       _dp(evals), _dp(status), _stream(stream)))
 
 
+def sfls_incomplete_eval(ctx: Context, n, m, moff, idx, phi, y, ydtype, K, koff, theta, gamma,
+                         beta, logdet=None, yCy=None, ww=None, q=None, r=None, u=None, s=None,
+                         t=None, v=None, x=None, L=None, goff=None, qG=None, sG=None, cand=None,
+                         ncand=None, coff=None, cq=None, cs=None, status=None, stream=None):
+    n, m, moff, K, koff = _i64(n), _i64(m), _i64(moff), _i64(K), _i64(koff)
+    Lh = _i64(L) if L is not None else None
+    gh = _i64(goff) if goff is not None else None
+    nch = _i64(ncand) if ncand is not None else None
+    ch = _i64(coff) if coff is not None else None
+    ctx.check(lib().sfls_incomplete_eval(
+        ctx.handle, len(n), _hp(n), _hp(m), _hp(moff), _dp(idx), _dp(phi), _dp(y), int(ydtype),
+        _hp(K), _hp(koff), _dp(theta), _dp(gamma), _dp(beta), _dp(logdet), _dp(yCy), _dp(ww),
+        _dp(q), _dp(r), _dp(u), _dp(s), _dp(t), _dp(v), _dp(x),
+        _hp(Lh) if Lh is not None else None, _hp(gh) if gh is not None else None, _dp(qG), _dp(sG),
+        _dp(cand), _hp(nch) if nch is not None else None, _hp(ch) if ch is not None else None,
+        _dp(cq), _dp(cs), _dp(status), _stream(stream)))
+
+
+def sfls_estimate_incomplete(ctx: Context, n, m, moff, idx, phi, y, ydtype, params, kcap, koff, K,
+                             theta, alpha, gamma, beta, zeta, objective, iters, evals, status,
+                             stream=None):
+    n, m, moff, kcap, koff = _i64(n), _i64(m), _i64(moff), _i64(kcap), _i64(koff)
+    pp = ctypes.byref(params) if params is not None else None
+    ctx.check(lib().sfls_estimate_incomplete(
+        ctx.handle, len(n), _hp(n), _hp(m), _hp(moff), _dp(idx), _dp(phi), _dp(y), int(ydtype), pp,
+        _hp(kcap), _hp(koff), _dp(K), _dp(theta), _dp(alpha), _dp(gamma), _dp(beta), _dp(zeta),
+        _dp(objective), _dp(iters), _dp(evals), _dp(status), _stream(stream)))
+
+
 # ------------------------------------------------- batch conveniences -------
 
 @dataclass
@@ -434,6 +472,69 @@ def estimate_batch(ctx: Context, ys, params: sfls_params | None = None, kcap: in
                   out["iters"], out["evals"], out["status"], stream=stream)
     if not sync:
         return out
+    torch.cuda.synchronize(dev)
+    h = {k: v.cpu().numpy() for k, v in out.items()}
+    alpha = h["alpha"].view(np.complex128)
+    res = []
+    for b in range(B):
+        k = int(h["K"][b])
+        o = int(koff[b])
+        res.append(EstimateResult(K=k, theta=h["theta"][o:o + k].copy(),
+                                  alpha=alpha[o:o + k].copy(), gamma=h["gamma"][o:o + k].copy(),
+                                  beta=float(h["beta"][b]), zeta=float(h["zeta"][b]),
+                                  objective=float(h["objective"][b]),
+                                  iterations=int(h["iters"][b]), evaluations=int(h["evals"][b]),
+                                  status=int(h["status"][b])))
+    return res
+
+
+def pack_incomplete(ctx: Context, obs, ydtype=None):
+    """Device arrays of a batch of incomplete observations: obs is a list of
+    (N, idx, phi, y) with idx the observed indices, phi their weights (None:
+    unit weights for the whole batch only when every phi is None) and y the
+    observed samples.  Returns (n, m, moff, idx_dev, phi_dev or None, y_dev,
+    ydtype)."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    if ydtype is None:
+        ydtype = SFLS_C64 if all(np.asarray(o[3]).dtype == np.complex64 for o in obs) else SFLS_C128
+    npdt = np.complex64 if ydtype == SFLS_C64 else np.complex128
+    n = np.array([int(o[0]) for o in obs], np.int64)
+    m = np.array([len(o[1]) for o in obs], np.int64)
+    moff = np.concatenate([[0], np.cumsum(m)[:-1]]).astype(np.int64)
+    idx = torch.from_numpy(np.concatenate([np.asarray(o[1], np.int32) for o in obs])).to(dev)
+    yflat = np.concatenate([np.asarray(o[3], npdt) for o in obs])
+    ydev = torch.from_numpy(yflat.view(np.float32 if ydtype == SFLS_C64 else np.float64)).to(dev)
+    phid = None
+    if any(o[2] is not None for o in obs):
+        ph = np.concatenate([np.ones(len(o[1]), np.complex128) if o[2] is None
+                             else np.asarray(o[2], np.complex128) for o in obs])
+        phid = torch.from_numpy(ph.view(np.float64)).to(dev)
+    return n, m, moff, idx, phid, ydev, ydtype
+
+
+def estimate_batch_incomplete(ctx: Context, obs, params: sfls_params | None = None,
+                              kcap: int | None = None, ydtype=None, stream=None):
+    """sfls_estimate_incomplete on a list of (N, idx, phi, y); returns
+    EstimateResult per instance."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    n, m, moff, idx, phid, ydev, ydtype = pack_incomplete(ctx, obs, ydtype)
+    kc = np.array([min(int(kcap) if kcap else int(mm), int(mm), SFLS_SF_MAX_K) for mm in m],
+                  np.int64)
+    koff = np.concatenate([[0], np.cumsum(kc)[:-1]]).astype(np.int64)
+    B, KT = len(obs), int(kc.sum())
+    f64 = dict(dtype=torch.float64, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    out = dict(K=torch.zeros(B, dtype=torch.int64, device=dev), theta=torch.zeros(KT, **f64),
+               alpha=torch.zeros(2 * KT, **f64), gamma=torch.zeros(KT, **f64),
+               beta=torch.zeros(B, **f64), zeta=torch.zeros(B, **f64),
+               objective=torch.zeros(B, **f64), iters=torch.zeros(B, **i32),
+               evals=torch.zeros(B, **i32), status=torch.zeros(B, **i32))
+    sfls_estimate_incomplete(ctx, n, m, moff, idx, phid, ydev, ydtype, params, kc, koff, out["K"],
+                             out["theta"], out["alpha"], out["gamma"], out["beta"], out["zeta"],
+                             out["objective"], out["iters"], out["evals"], out["status"],
+                             stream=stream)
     torch.cuda.synchronize(dev)
     h = {k: v.cpu().numpy() for k, v in out.items()}
     alpha = h["alpha"].view(np.complex128)

@@ -28,7 +28,8 @@ FLAGS = [
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 SOURCES = ["k_factor.hip", "k_schur.hip", "k_conv.hip", "k_grid.hip", "k_active.hip", "k_logdet.hip",
-           "k_driver.hip", "abi.hip", "server.hip", "server_batch.hip", "noalloc.hip"]
+           "k_driver.hip", "abi.hip", "server.hip", "server_batch.hip", "noalloc.hip",
+           "k_semifast.hip"]
 
 
 def hipcc() -> str:

@@ -837,13 +837,66 @@ sfls_status sfls_active_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const i
 
 // The estimate of sfls_estimate (G = 1) and sfls_estimate_mmv (G vectors per
 // instance sharing the generator, Sec. V).
+// Incomplete observations (Sec. IV): instance b observes m[b] samples whose
+// indices, weights and values start at moff[b] of idx, phi (NULL: unit
+// weights) and y.
+struct SfInput {
+  const int64_t* m;
+  const int64_t* moff;
+  const int32_t* idx;
+  const cd* phi;
+};
+
+// Observation fields of the instance table (nobs, obsoff, the semifast matrix
+// and column offsets) for a semifast call, and the device check of the
+// indices and weights (before any kernel indexes with them).  kc[b] is the
+// component capacity, at most SF_KMAX.  Returns the totals of the observation
+// arrays (sum m), the matrix blocks (sum 4 kc^2) and the columns (sum m kc).
+static sfls_status sf_prepare(sfls_ctx* ctx, int64_t B, const SfInput& sf,
+                              std::vector<InstInfo>& info, const std::vector<int32_t>& kc,
+                              hipStream_t st, int64_t* mtot, int64_t* smtot, int64_t* utot) {
+  if (!sf.m || !sf.moff || !sf.idx) return fail(ctx, SFLS_EINVAL, "NULL observation argument");
+  int64_t mt = 0, sm = 0, ut = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    InstInfo& in = info[(size_t)b];
+    if (sf.m[b] < 1 || sf.m[b] > in.N || sf.moff[b] < 0)
+      return fail(ctx, SFLS_EINVAL, "m/moff[%lld]: need 1 <= m <= n, moff >= 0", (long long)b);
+    in.nobs = (int32_t)sf.m[b];
+    in.obsoff = sf.moff[b];
+    in.kcap = kc[(size_t)b];
+    in.sfoff = sm;
+    sm += 4 * (int64_t)in.kcap * in.kcap;
+    in.uoff = ut;
+    ut += (int64_t)in.nobs * in.kcap;
+    mt = std::max(mt, sf.moff[b] + sf.m[b]);
+  }
+  InstInfo* dinfo;
+  int32_t* dbad;
+  sfls_status s;
+  if ((s = upload(ctx, "sf_chk_info", info, st, &dinfo)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "sf_chk_bad", (size_t)B, &dbad)) != SFLS_OK) return s;
+  HIP_TRY(launch_sf_check(dinfo, sf.idx, sf.phi, dbad, (int)B, st));
+  std::vector<int32_t> bad((size_t)B);
+  HIP_TRY(hipMemcpyAsync(bad.data(), dbad, (size_t)B * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int64_t b = 0; b < B; ++b)
+    if (bad[(size_t)b])
+      return fail(ctx, SFLS_EINVAL,
+                  "instance %lld: observed indices not strictly increasing in [0, n), or a zero "
+                  "or non-finite weight", (long long)b);
+  *mtot = mt;
+  *smtot = sm;
+  *utot = ut;
+  return SFLS_OK;
+}
+
 static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
                                  int32_t G, const void* y, int64_t ystride, int32_t ydtype,
                                  const sfls_params* params, const int64_t* kcap,
                                  const int64_t* koff, int64_t* K, double* theta, double* alpha,
                                  int64_t alpha_stride, double* gamma, double* beta, double* zeta,
                                  double* objective, int32_t* iters, int32_t* evals,
-                                 int32_t* status, void* stream) {
+                                 int32_t* status, void* stream, const SfInput* sf = nullptr) {
   if (!ctx) return SFLS_EINVAL;
   ctx->err.clear();
   sfls_status s = check_batch(ctx, B, n, off, 2);
@@ -872,7 +925,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   Sizes sz;
   int64_t pt = 0, ntot = 0, ktot = 0, gtot = 0, ctot = 0;
   std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
-  if ((s = check_factor_size(ctx, sz.maxN)) != SFLS_OK) return s;
+  if (!sf && (s = check_factor_size(ctx, sz.maxN)) != SFLS_OK) return s;
   std::vector<SepCoef> coef((size_t)B);
   std::vector<int64_t> okoff((size_t)B);
   const int cc = p.cand_cap + 1;
@@ -887,6 +940,10 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     in.L = (int32_t)Lb;
     in.R = (int32_t)(Lb / in.M);
     in.kcap = (int32_t)std::min<int64_t>(kcap[b], n[b]);
+    // incomplete observations: K_max = m, and the semifast factor holds at
+    // most SF_KMAX components
+    if (sf) in.kcap = (int32_t)std::min<int64_t>({kcap[b], sf->m ? std::max<int64_t>(sf->m[b], 1) : 1,
+                                                  (int64_t)SF_KMAX});
     in.koff = ktot;
     ktot += in.kcap;
     in.goff = gtot;
@@ -900,6 +957,13 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     sep_coef((int)n[b], coef[(size_t)b]);
   }
   std::vector<DrvParams> dpv(1, drv_params(p));
+  int64_t sf_mtot = 0, sf_smtot = 0, sf_utot = 0;
+  if (sf) {
+    std::vector<int32_t> kcv((size_t)B);
+    for (int64_t b = 0; b < B; ++b) kcv[(size_t)b] = info[(size_t)b].kcap;
+    if ((s = sf_prepare(ctx, B, *sf, info, kcv, st, &sf_mtot, &sf_smtot, &sf_utot)) != SFLS_OK)
+      return s;
+  }
 
   InstInfo* dinfo;
   SepCoef* dcoef;
@@ -1008,9 +1072,27 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   cd* sscr;
   int sFmax;
   std::vector<double> sflops;
-  if ((s = prepare_schur(ctx, B, n, sz.maxN, st, "e", &slay, &sacts, &sscr, &sFmax, &sflops)) !=
-      SFLS_OK)
-    return s;
+  if (!sf) {
+    if ((s = prepare_schur(ctx, B, n, sz.maxN, st, "e", &slay, &sacts, &sscr, &sFmax,
+                           &sflops)) != SFLS_OK)
+      return s;
+  } else {
+    slay = nullptr;
+    sacts = nullptr;
+    sscr = nullptr;
+    sFmax = 0;
+  }
+  // semifast workspace: the K x K matrix blocks, A^H y, c, C^{-1} y on the
+  // observed samples and the grid columns U
+  cd *sfm = nullptr, *sfh = nullptr, *sfc = nullptr, *sfw = nullptr, *sfU = nullptr;
+  if (sf) {
+    if ((s = wsT(ctx, "e_sfm", (size_t)std::max<int64_t>(sf_smtot, 1), &sfm)) != SFLS_OK ||
+        (s = wsT(ctx, "e_sfh", (size_t)ktot, &sfh)) != SFLS_OK ||
+        (s = wsT(ctx, "e_sfc", (size_t)ktot, &sfc)) != SFLS_OK ||
+        (s = wsT(ctx, "e_sfw", (size_t)std::max<int64_t>(sf_mtot, 1), &sfw)) != SFLS_OK ||
+        (s = wsT(ctx, "e_sfU", (size_t)std::max<int64_t>(sf_utot, 1), &sfU)) != SFLS_OK)
+      return s;
+  }
   const int prec = p.precision;
   const void* tw = prec == SFLS_FP64 ? (const void*)ctx->tws64 : (const void*)ctx->tws32;
   const double slack = prec == SFLS_FP64 ? 1e-9 : 1e-3;
@@ -1072,6 +1154,14 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   ctx->timeline.push_back(now_s());
   int64_t rounds = 0, ev_total = 0, gevals = 0;
   const int64_t max_rounds = 1000000;
+  // algorithmic bytes of a sweep's omega stage: rho in, omega_s out; semifast:
+  // the observed C^{-1} y and the columns U written and read, omega_s out
+  auto omega_bytes = [&](int64_t b) {
+    const double Nb = (double)n[b];
+    if (!sf) return 16.0 * Nb + 16.0 * (2.0 * Nb - 1.0);
+    const InstInfo& in = info[(size_t)b];
+    return 16.0 * in.nobs + 32.0 * (double)in.nobs * in.kcap + 16.0 * (2.0 * Nb - 1.0);
+  };
   const double esz_d = (double)esz;
   for (;;) {
     int64_t nact = 0, ngrid = 0, nreq = 0;
@@ -1086,7 +1176,14 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
       ++nreq;
       const double N = (double)n[b];
       // algorithmic work per evaluation (per-instance figures of the design)
-      if (rq & REQ_EVAL) {
+      if ((rq & REQ_EVAL) && sf) {
+        // semifast: Gram sums (3 K^2 M / 2 complex MACs), the K x K Cholesky,
+        // inverse and solves, the residual and q, r, u (4 K M)
+        ++nact;
+        const double Mo = (double)info[(size_t)b].nobs, Kc = (double)info[(size_t)b].kcap;
+        kflops[KID_FACTOR] += 8.0 * (1.5 * Kc * Kc * Mo + 4.0 * Kc * Mo) + 8.0 * Kc * Kc * Kc;
+        kbytes[KID_FACTOR] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * Mo + 4.0 * Mo + 16.0 * Mo;
+      } else if (rq & REQ_EVAL) {
         ++nact;
         kflops[KID_FACTOR] += slay ? sflops[(size_t)b] : 8.0 * N * N;  // Schur or Levinson
         kbytes[KID_FACTOR] += 40.0 * N;                       // c in, rho and delta out
@@ -1104,7 +1201,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
         ++ngrid;
         const double Lb = (double)info[(size_t)b].L;
         kbytes[KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz_d * Lb;  // w, omega_s in; Delta L out
-        kbytes[KID_OMEGA] += 16.0 * N + 16.0 * (2.0 * N - 1.0);  // rho in; omega_s out
+        kbytes[KID_OMEGA] += omega_bytes(b);
       }
     }
     if (nreq == 0) break;
@@ -1112,7 +1209,14 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     ++rounds;
     ev_total += nact;
     gevals += ngrid;
-    if (nact > 0) {
+    if (nact > 0 && sf) {
+      HIP_TRY(tstart(KID_FACTOR));
+      HIP_TRY(launch_sf_eval(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, y, ydtype, sf->idx,
+                             sf->phi, sfm, sfh, sfc, sfw, logdet, yCy, ww, lev_status, evq, evr,
+                             evu, evs, evt, evv, evx, (int)B, st));
+      HIP_TRY(tstop(KID_FACTOR));
+    }
+    if (nact > 0 && !sf) {
       HIP_TRY(tstart(KID_GEN));
       HIP_TRY(launch_toeplitz_column(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, c, (int)B,
                                      sz.maxN, st, ctx->nufft_mode, ctx->tws64, scratch,
@@ -1137,7 +1241,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
       HIP_TRY(tstop(KID_APPLY));
     }
     // active-set vectors at the evaluated points (candidates follow the grid stage)
-    if (nact > 0) {
+    if (nact > 0 && !sf) {
       HIP_TRY(tstart(KID_ACTIVE));
       HIP_TRY(launch_active(dinfo, P.req, P.K_e, nullptr, prefix, (int)B, P.th_e, cand, w, rho,
                             delta, dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks,
@@ -1154,8 +1258,13 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     // place), which so run now instead of a round later; then the candidates'
     // vectors and the second driver pass, for exactly these (P.req2).
     HIP_TRY(tstart2(KID_OMEGA));
-    HIP_TRY(launch_omega(dinfo, P.req2, rho, delta, dcoef, ctx->tws64, scratch, 1, 1, oms, nullptr,
-                         nullptr, nullptr, nullptr, (int)B, sz.maxP, st, dorder));
+    if (sf)
+      HIP_TRY(launch_sf_grid_inputs(dinfo, P.req2, P.K_e, P.th_e, P.ga_e, P.beta_e, sf->idx,
+                                    sf->phi, sfw, sfm, ctx->tws64, w, sfU, scratch, oms, (int)B,
+                                    sz.maxP, st));
+    else
+      HIP_TRY(launch_omega(dinfo, P.req2, rho, delta, dcoef, ctx->tws64, scratch, 1, 1, oms,
+                           nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st, dorder));
     HIP_TRY(tstop2(KID_OMEGA));
     HIP_TRY(tstart2(KID_GRID));
     HIP_TRY(launch_grid(prec, dinfo, P.req2, w, oms, P.gbar_e, P.zeta_e, tw, ctx->logtw, sz.Rmax,
@@ -1166,9 +1275,13 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
                           p.cand_cap, cand, ncand, ovf, (int)B, st));
     HIP_TRY(tstop2(KID_SELECT));
     HIP_TRY(tstart2(KID_ACTIVE));
-    HIP_TRY(launch_active(dinfo, P.req2, P.K_e, ncand, prefix, (int)B, P.th_e, cand, w, rho, delta,
-                          dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks,
-                          ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st, vv));
+    if (sf)
+      HIP_TRY(launch_sf_cand(dinfo, P.req2, P.K_e, P.beta_e, sf->idx, sf->phi, sfw, sfU, cand,
+                             ncand, cq, cs, (int)B, st));
+    else
+      HIP_TRY(launch_active(dinfo, P.req2, P.K_e, ncand, prefix, (int)B, P.th_e, cand, w, rho,
+                            delta, dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks,
+                            ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st, vv));
     HIP_TRY(tstop2(KID_ACTIVE));
     HIP_TRY(tstart2(KID_DRIVER));
     HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st, 1));
@@ -1184,7 +1297,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
       ++gevals;
       const double N = (double)n[b], Lb = (double)info[(size_t)b].L;
       kbytes[KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz_d * Lb;
-      kbytes[KID_OMEGA] += 16.0 * N + 16.0 * (2.0 * N - 1.0);
+      kbytes[KID_OMEGA] += omega_bytes(b);
       kbytes[KID_ACTIVE] += 32.0 * N;  // the candidates' vectors: w, rho in
     }
     if (timing) {
@@ -1229,6 +1342,143 @@ sfls_status sfls_estimate_mmv(sfls_ctx* ctx, int64_t B, const int64_t* n, const 
                               int32_t* iters, int32_t* evals, int32_t* status, void* stream) {
   return estimate_impl(ctx, B, n, off, G, y, ystride, ydtype, params, kcap, koff, K, theta, alpha,
                        alpha_stride, gamma, beta, zeta, objective, iters, evals, status, stream);
+}
+
+
+// ---------------------------------------------------------------------------
+// Incomplete observations (Sec. IV)
+// ---------------------------------------------------------------------------
+
+// N-space offsets of a batch (the instances' length-n arrays back to back).
+static std::vector<int64_t> packed_offsets(int64_t B, const int64_t* n) {
+  std::vector<int64_t> off((size_t)std::max<int64_t>(B, 1), 0);
+  for (int64_t b = 1; b < B; ++b) off[(size_t)b] = off[(size_t)b - 1] + n[b - 1];
+  return off;
+}
+
+sfls_status sfls_incomplete_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* m,
+                                 const int64_t* moff, const int32_t* idx, const double* phi,
+                                 const void* y, int32_t ydtype, const int64_t* K,
+                                 const int64_t* koff, const double* theta, const double* gamma,
+                                 const double* beta, double* logdet, double* yCy, double* ww,
+                                 double* q, double* r, double* u, double* s_, double* t, double* v,
+                                 double* x, const int64_t* L, const int64_t* goff, double* qG,
+                                 double* sG, const int32_t* cand, const int64_t* ncand,
+                                 const int64_t* coff, double* cq, double* cs, int32_t* status,
+                                 void* stream) {
+  if (!ctx) return SFLS_EINVAL;
+  ctx->err.clear();
+  if (!n || B < 0) return fail(ctx, SFLS_EINVAL, "NULL n or B < 0");
+  const std::vector<int64_t> offv = packed_offsets(B, n);
+  sfls_status s = check_batch(ctx, B, n, offv.data(), 2);
+  if (s != SFLS_OK || B == 0) return s;
+  if (!y || !K || !koff || !beta) return fail(ctx, SFLS_EINVAL, "NULL argument");
+  if (ydtype != SFLS_C64 && ydtype != SFLS_C128) return fail(ctx, SFLS_EINVAL, "bad ydtype");
+  const bool grid = L != nullptr, wc = cand != nullptr;
+  if (grid && (!goff || (!qG && !sG && !wc))) return fail(ctx, SFLS_EINVAL, "grid outputs need goff and qG/sG/cand");
+  if (wc && (!grid || !ncand || !coff || !cq || !cs))
+    return fail(ctx, SFLS_EINVAL, "candidates need L, ncand, coff, cq and cs");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = as_stream(stream);
+  Sizes sz;
+  int64_t pt = 0, ntot = 0, ktot = 0, ctot = 0;
+  std::vector<InstInfo> info = base_info(B, n, offv.data(), sz, pt);
+  std::vector<int32_t> kc((size_t)B), kev((size_t)B), nc((size_t)B, 0);
+  std::vector<int32_t> req((size_t)B, REQ_EVAL | (grid ? REQ_GRID : 0));
+  for (int64_t b = 0; b < B; ++b) {
+    InstInfo& in = info[(size_t)b];
+    if (!m || m[b] < 1 || m[b] > n[b]) return fail(ctx, SFLS_EINVAL, "m[%lld] outside 1..n", (long long)b);
+    if (K[b] < 0 || K[b] > std::min<int64_t>(m[b], SF_KMAX) || koff[b] < 0)
+      return fail(ctx, SFLS_EINVAL, "K[%lld] = %lld outside 0..min(m, %d), or koff < 0",
+                  (long long)b, (long long)K[b], SF_KMAX);
+    if (K[b] > 0 && (!theta || !gamma)) return fail(ctx, SFLS_EINVAL, "theta/gamma NULL");
+    kc[(size_t)b] = (int32_t)std::max<int64_t>(K[b], 1);
+    kev[(size_t)b] = (int32_t)K[b];
+    in.koff = koff[b];
+    ktot = std::max(ktot, koff[b] + kc[(size_t)b]);
+    ntot = std::max(ntot, offv[(size_t)b] + n[b]);
+    if (grid) {
+      if (!is_pow2(L[b]) || L[b] < 2 * n[b] - 1 || L[b] < in.M || L[b] > (1 << 24) || goff[b] < 0)
+        return fail(ctx, SFLS_EINVAL, "L[%lld] = %lld must be a power of two >= 2n-1 (<= 2^24), goff >= 0",
+                    (long long)b, (long long)L[b]);
+      cap_grid_m(in, SFLS_FP64);
+      in.L = (int32_t)L[b];
+      in.R = (int32_t)(L[b] / in.M);
+      in.goff = goff[b];
+      sz.Rmax = std::max(sz.Rmax, in.R);
+      sz.maxM = std::max(in.M, b == 0 ? 0 : sz.maxM);
+    }
+    if (wc) {
+      if (ncand[b] < 0 || ncand[b] > (1 << 20) || coff[b] < 0)
+        return fail(ctx, SFLS_EINVAL, "ncand/coff[%lld]", (long long)b);
+      nc[(size_t)b] = (int32_t)ncand[b];
+      in.coff = coff[b];
+      ctot = std::max(ctot, coff[b] + ncand[b]);
+    }
+  }
+  const SfInput sfin{m, moff, idx, reinterpret_cast<const cd*>(phi)};
+  int64_t mt = 0, smt = 0, ut = 0;
+  if ((s = sf_prepare(ctx, B, sfin, info, kc, st, &mt, &smt, &ut)) != SFLS_OK) return s;
+  InstInfo* dinfo;
+  int32_t *dreq, *dK, *dnc = nullptr;
+  if ((s = upload(ctx, "ie_info", info, st, &dinfo)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "ie_req", req, st, &dreq)) != SFLS_OK) return s;
+  if ((s = upload(ctx, "ie_K", kev, st, &dK)) != SFLS_OK) return s;
+  if (wc && (s = upload(ctx, "ie_nc", nc, st, &dnc)) != SFLS_OK) return s;
+  cd *sfm, *sfh, *sfc, *sfw, *sfU;
+  if ((s = wsT(ctx, "ie_sfm", (size_t)std::max<int64_t>(smt, 1), &sfm)) != SFLS_OK ||
+      (s = wsT(ctx, "ie_sfh", (size_t)ktot, &sfh)) != SFLS_OK ||
+      (s = wsT(ctx, "ie_sfc", (size_t)ktot, &sfc)) != SFLS_OK ||
+      (s = wsT(ctx, "ie_sfw", (size_t)std::max<int64_t>(mt, 1), &sfw)) != SFLS_OK ||
+      (s = wsT(ctx, "ie_sfU", (size_t)std::max<int64_t>(ut, 1), &sfU)) != SFLS_OK)
+    return s;
+  // outputs the caller does not want go to workspace
+  double *ld = logdet, *yc = yCy, *wn = ww;
+  int32_t* stt = status;
+  if (!ld && (s = wsT(ctx, "ie_ld", (size_t)B, &ld)) != SFLS_OK) return s;
+  if (!yc && (s = wsT(ctx, "ie_yc", (size_t)B, &yc)) != SFLS_OK) return s;
+  if (!wn && (s = wsT(ctx, "ie_wn", (size_t)B, &wn)) != SFLS_OK) return s;
+  if (!stt && (s = wsT(ctx, "ie_st", (size_t)B, &stt)) != SFLS_OK) return s;
+  cd* vec[7] = {(cd*)q, (cd*)r, (cd*)u, (cd*)s_, (cd*)t, (cd*)v, (cd*)x};
+  static const char* vnames[7] = {"ie_q", "ie_r", "ie_u", "ie_s", "ie_t", "ie_v", "ie_x"};
+  for (int i = 0; i < 7; ++i)
+    if (!vec[i] && (s = wsT(ctx, vnames[i], (size_t)ktot, &vec[i])) != SFLS_OK) return s;
+  HIP_TRY(launch_sf_eval(dinfo, dreq, dK, theta, gamma, beta, y, ydtype, idx, sfin.phi, sfm, sfh,
+                         sfc, sfw, ld, yc, wn, stt, vec[0], vec[1], vec[2], vec[3], vec[4], vec[5],
+                         vec[6], (int)B, st));
+  if (!grid) return SFLS_OK;
+  cd *scratch, *w, *oms;
+  double* pv;
+  int64_t* pi;
+  if ((s = wsT(ctx, "scratch", (size_t)pt, &scratch)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "ie_w", (size_t)ntot, &w)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "ie_oms", (size_t)pt, &oms)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "ie_pv", (size_t)B * sz.Rmax, &pv)) != SFLS_OK) return s;
+  if ((s = wsT(ctx, "ie_pi", (size_t)B * sz.Rmax, &pi)) != SFLS_OK) return s;
+  HIP_TRY(launch_sf_grid_inputs(dinfo, dreq, dK, theta, gamma, beta, idx, sfin.phi, sfw, sfm,
+                                ctx->tws64, w, sfU, scratch, oms, (int)B, sz.maxP, st));
+  if (qG || sG)
+    HIP_TRY(launch_grid(SFLS_FP64, dinfo, dreq, w, oms, nullptr, nullptr, ctx->tws64, ctx->logtw,
+                        sz.Rmax, (int)B, sz.maxM, qG, sG, nullptr, pv, pi, st));
+  if (wc)
+    HIP_TRY(launch_sf_cand(dinfo, dreq, dK, beta, idx, sfin.phi, sfw, sfU, cand, dnc, (cd*)cq, cs,
+                           (int)B, st));
+  return SFLS_OK;
+}
+
+sfls_status sfls_estimate_incomplete(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* m,
+                                     const int64_t* moff, const int32_t* idx, const double* phi,
+                                     const void* y, int32_t ydtype, const sfls_params* params,
+                                     const int64_t* kcap, const int64_t* koff, int64_t* K,
+                                     double* theta, double* alpha, double* gamma, double* beta,
+                                     double* zeta, double* objective, int32_t* iters,
+                                     int32_t* evals, int32_t* status, void* stream) {
+  if (!ctx) return SFLS_EINVAL;
+  if (!n || B < 0) return sfls_host::fail(ctx, SFLS_EINVAL, "NULL n or B < 0");
+  const std::vector<int64_t> offv = packed_offsets(B, n);
+  const SfInput sfin{m, moff, idx, reinterpret_cast<const cd*>(phi)};
+  return estimate_impl(ctx, B, n, offv.data(), 1, y, 0, ydtype, params, kcap, koff, K, theta,
+                       alpha, 0, gamma, beta, zeta, objective, iters, evals, status, stream, &sfin);
 }
 
 }  // extern "C"

@@ -51,6 +51,11 @@ struct DrvState {
 // Per-instance array views (device pointers, offset to this instance).
 struct DrvArrays {
   int N, L, kcap;
+  // observations per vector (Sec. II-A; N for complete data): the count
+  // scales of Sec. II-E (initial beta, eps_beta, the stopping rules,
+  // K_max = M in the prior and eq. zetaUpdate) are in M, the frequency
+  // scales (grid, distances, the refinement's tolerance) in N
+  int Mo = 0;
   // observation vectors (Sec. V): the per-vector arrays ev_q, ev_r, ev_u,
   // q_save, cand_q and out_alpha hold vector g at g * (vk, vk, vk, vk, vc, vo)
   // doubles from the instance's entry (G = 1: the single-vector model)
@@ -163,18 +168,20 @@ struct Driver {
   const DrvArrays& A;
   int N, J;
 
+  int Mo;
+
   SFLS_HD Driver(const DrvParams& p, DrvState& s, const DrvArrays& a)
-      : P(p), S(s), A(a), N(a.N), J(p.J) {}
+      : P(p), S(s), A(a), N(a.N), J(p.J), Mo(a.Mo > 0 ? a.Mo : a.N) {}
 
   // L_MMV = G ln|C| + sum_g y_g^H C^{-1} y_g - prior (Sec. V; G = 1: eq. obj)
   SFLS_HD double f_of_eval() const {
     const double ld = A.G == 1 ? *A.logdet : (double)A.G * *A.logdet;
-    return ld + *A.yCy + prior_term(S.K, N, S.zeta);
+    return ld + *A.yCy + prior_term(S.K, Mo, S.zeta);
   }
 
-  // the scale of the stopping rules: N, or G N for G observation vectors (the
+  // the scale of the stopping rules: M, or G M for G observation vectors (the
   // objective is a sum of G single-vector objectives)
-  SFLS_HD double gN() const { return A.G == 1 ? (double)N : (double)A.G * (double)N; }
+  SFLS_HD double gN() const { return A.G == 1 ? (double)Mo : (double)A.G * (double)Mo; }
 
   SFLS_HD double gbar() const {
     if (S.K == 0) return -1.0;
@@ -453,7 +460,7 @@ struct Driver {
     const bool ok = gh > 0.0 && S.zeta > 0.0 && act_criterion(q2, s, gb, S.zeta, P.tau, A.G) &&
                     dl < -P.eps_L;
     if (!ok) return 0;
-    if (S.K >= A.kcap || S.K >= N) { S.cap_hit = 1; return 0; }
+    if (S.K >= A.kcap || S.K >= Mo) { S.cap_hit = 1; return 0; }
     A.th[S.K] = (double)A.cand[0] / (double)A.L;
     A.ga[S.K] = gh;
     S.K += 1;
@@ -491,7 +498,7 @@ struct Driver {
     int added = 0;
     const double mind = P.approx_min_dist / (double)N;
     for (int i = 0; i < m; ++i) {
-      if (S.K >= A.kcap || S.K >= N) { S.cap_hit = 1; break; }
+      if (S.K >= A.kcap || S.K >= Mo) { S.cap_hit = 1; break; }
       // next qualifying candidate: smallest Delta L, then smallest grid index
       double dlo = INFINITY;
       int lo = INT32_MAX;
@@ -608,9 +615,9 @@ struct Driver {
           lbl = L_FINAL;
           break;
         }
-        S.beta = 0.01 * S.yy / (double)N;
+        S.beta = 0.01 * S.yy / (double)Mo;
         S.zeta = 0.2;
-        S.eps_beta = P.eps_beta_rel * S.yy / (double)N;
+        S.eps_beta = P.eps_beta_rel * S.yy / (double)Mo;
         S.approx_on = P.approx_max_iters > 0;
         S.L_prev = INFINITY;
         lbl = L_OUTER;
@@ -670,7 +677,7 @@ struct Driver {
           break;
         }
         case L_AFTER_ACT: {
-          const double zn = (double)S.K / (double)N;  // eq. zetaUpdate
+          const double zn = (double)S.K / (double)Mo;  // eq. zetaUpdate
           S.zeta = zn < 0.5 ? zn : 0.5;
           if (!S.cur_valid) {
             request_current(1);
@@ -685,11 +692,11 @@ struct Driver {
           double tr = 0.0;
           for (int k = T::lane(); k < S.K; k += T::width()) tr += A.ga[k] * A.ev_s[2 * k];
           tr = T::sum(tr);
-          // with G vectors (Sec. V): (G beta tr + beta^2 sum_g ||w_g||^2) / (G N)
+          // with G vectors (Sec. V): (G beta tr + beta^2 sum_g ||w_g||^2) / (G M)
           double bn = A.G == 1
-                          ? (S.beta * tr + S.beta * S.beta * (*A.ww)) / (double)N
+                          ? (S.beta * tr + S.beta * S.beta * (*A.ww)) / (double)Mo
                           : ((double)A.G * S.beta * tr + S.beta * S.beta * (*A.ww)) /
-                                ((double)A.G * (double)N);
+                                ((double)A.G * (double)Mo);
           if (!(bn > S.eps_beta)) bn = S.eps_beta;
           if (bn != S.beta) { S.beta = bn; S.cur_valid = 0; }
           if (S.z_changed) { mem_reset(); S.z_changed = 0; }

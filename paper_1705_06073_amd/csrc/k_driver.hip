@@ -69,6 +69,7 @@ __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info
   const int J = prm->J;
   DrvArrays A;
   A.N = in.N;
+  A.Mo = in.nobs > 0 ? in.nobs : in.N;
   A.L = in.L;
   A.kcap = in.kcap;
   A.G = p.G;
@@ -150,9 +151,12 @@ __global__ __launch_bounds__(256) void k_init_state(const InstInfo* __restrict__
   const int b = list ? list[blockIdx.x] : blockIdx.x;
   const InstInfo in = info[b];
   double acc[1] = {0.0};
+  // the observed samples: N at off, or (incomplete observations) nobs at obsoff
+  const int ny = in.nobs > 0 ? in.nobs : in.N;
+  const int64_t yo = in.nobs > 0 ? in.obsoff : in.off;
   for (int gv = 0; gv < vv.G; ++gv) {
-    const YT* yb = y + gv * vv.ystride + in.off;
-    for (int i = threadIdx.x; i < in.N; i += 256) {
+    const YT* yb = y + gv * vv.ystride + yo;
+    for (int i = threadIdx.x; i < ny; i += 256) {
       const double re = (double)yb[i].x, im = (double)yb[i].y;
       acc[0] = fma(re, re, fma(im, im, acc[0]));
     }

@@ -179,8 +179,9 @@ __global__ __launch_bounds__(GRID_NT) void k_grid(const InstInfo* __restrict__ i
     }
     __syncthreads();
   }
-  const R gb = (R)gbar[bi];
-  const double z = zeta[bi];
+  // gbar and zeta may be absent when neither Delta L nor its argmin is wanted
+  const R gb = gbar ? (R)gbar[bi] : (R)1;
+  const double z = zeta ? zeta[bi] : 0.5;
   const R odds = (R)((1.0 - z) / z);
   double best = __builtin_inf();
   int64_t bidx = INT64_MAX;

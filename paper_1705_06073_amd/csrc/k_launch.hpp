@@ -154,4 +154,32 @@ hipError_t launch_driver(const InstInfo* info, const DrvParams* prm, DrvPools po
                          hipStream_t st, int pass = 0);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
 
+// Incomplete observations (Sec. IV), the semifast evaluation at the requested
+// points (REQ_EVAL): Gram sums, the K x K Cholesky and inverse, ln|C|, s, t,
+// v, x; then C^{-1} y on the observed samples (wM), y^H C^{-1} y, ||wM||^2,
+// q, r, u.  status[b] = SFLS_ENOTPD when K_s is not positive definite.
+hipError_t launch_sf_eval(const InstInfo* info, const int32_t* req, const int32_t* Kev,
+                          const double* theta, const double* gamma, const double* beta,
+                          const void* y, int ydtype, const int32_t* idx, const cd* phi,
+                          cd* sfm, cd* h, cd* cvec, cd* wM, double* logdet, double* yCy,
+                          double* ww, int32_t* status, cd* oq, cd* orr, cd* ou, cd* os, cd* ot,
+                          cd* ov, cd* ox, int B, hipStream_t st);
+// Grid-stage inputs at the evaluated point (REQ_GRID): w = Phi^H C^{-1} y as an
+// N-vector at off, the columns U at uoff, and omega_s (lag i at i mod P) at
+// poff of oms; scratch: the instance's P blocks (running sums, transform).
+hipError_t launch_sf_grid_inputs(const InstInfo* info, const int32_t* req, const int32_t* Kev,
+                                 const double* theta, const double* gamma, const double* beta,
+                                 const int32_t* idx, const cd* phi, const cd* wM, const cd* sfm,
+                                 const cd* tws, cd* w, cd* U, cd* scratch, cd* oms, int B,
+                                 int maxP, hipStream_t st);
+// bad[b] = 1 when instance b's observed indices are not strictly increasing in
+// [0, N) or a weight is zero or not finite (checked before any other use).
+hipError_t launch_sf_check(const InstInfo* info, const int32_t* idx, const cd* phi, int32_t* bad,
+                           int B, hipStream_t st);
+// q and s at the grid candidates (REQ_GRID).
+hipError_t launch_sf_cand(const InstInfo* info, const int32_t* req, const int32_t* Kev,
+                          const double* beta, const int32_t* idx, const cd* phi, const cd* wM,
+                          const cd* U, const int32_t* cand, const int32_t* ncand, cd* cq, double* cs,
+                          int B, hipStream_t st);
+
 }  // namespace sfls

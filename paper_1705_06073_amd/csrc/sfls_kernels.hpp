@@ -23,6 +23,14 @@ struct InstInfo {
   int64_t koff;   // component arrays
   int64_t ooff;   // 2N-1 omega arrays (sfls_omega)
   int64_t coff;   // candidate arrays
+  // incomplete observations (Sec. IV): the instance observes nobs samples,
+  // its observation arrays (y, indices, weights, C^{-1} y) start at obsoff;
+  // nobs = 0 for complete data (y of N samples at off)
+  int32_t nobs;
+  int32_t pad_;
+  int64_t obsoff;
+  int64_t sfoff;  // semifast K x K matrices (4 kcap^2 complex elements)
+  int64_t uoff;   // semifast grid columns (nobs x kcap complex elements)
 };
 
 // Observation vectors of a launch (the multiple-measurement-vector model of
@@ -61,6 +69,10 @@ __host__ __device__ inline bool use_nufft_col(int mode, int N, int P, int K) {
   if (mode == 2) return true;
   return (double)K * (double)N >= NUC_MIN_WORK;
 }
+
+// Incomplete observations (Sec. IV): largest number of active components of
+// the semifast evaluation (its K x K factor and inverse stay in LDS).
+constexpr int SF_KMAX = 64;
 
 // Request bits of one instance for the current evaluation round.
 enum : int32_t { REQ_EVAL = 1, REQ_GRID = 2, REQ_APPROX = 4 };

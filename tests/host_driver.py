@@ -17,6 +17,7 @@ import tempfile
 import numpy as np
 
 from oracle import estimator as oe
+from oracle import incomplete as inc
 from oracle import mmv
 from oracle import numerics as nm
 
@@ -64,7 +65,7 @@ _PTRS = ["th", "ga", "th_e", "ga_e", "K_e", "beta_e", "req", "gbar_e", "zeta_e",
 
 class DrvArrays(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_int), ("kcap", ctypes.c_int),
-                ("G", ctypes.c_int), ("vk", ctypes.c_int64), ("vc", ctypes.c_int64),
+                ("Mo", ctypes.c_int), ("G", ctypes.c_int), ("vk", ctypes.c_int64), ("vc", ctypes.c_int64),
                 ("vo", ctypes.c_int64)] + \
                [(n, ctypes.c_void_p) for n in _PTRS]
 
@@ -75,17 +76,20 @@ REQ_EVAL, REQ_GRID, REQ_APPROX = 1, 2, 4
 class HostDriver:
     """One instance: arrays in numpy, evaluations from the oracle.  y is one
     vector, or G x N for the multiple-vector model (evaluations from the MMV
-    oracle)."""
+    oracle); with ``obs`` (an oracle.incomplete.Observation) y holds the
+    observed samples (evaluations from the incomplete-data oracle)."""
 
     def __init__(self, y, params: oe.Params | None = None, kcap: int | None = None,
-                 cand_cap: int = 256):
+                 cand_cap: int = 256, obs=None):
         self.p = p = params or oe.Params()
         self.y = np.asarray(y, np.complex128)
+        self.obs = obs
         self.mmv = self.y.ndim == 2
         G = self.G = self.y.shape[0] if self.mmv else 1
-        N = self.N = self.y.shape[-1]
+        N = self.N = self.y.shape[-1] if obs is None else obs.N
+        M = self.M = self.y.shape[-1]
         self.L = p.grid_size(N)
-        kc = self.kcap = min(kcap or N, N)
+        kc = self.kcap = min(kcap or M, M)
         J = p.lbfgs_J
         self.cand_cap = cand_cap
         f64 = lambda n: np.zeros(max(1, n), np.float64)  # noqa: E731
@@ -105,7 +109,7 @@ class HostDriver:
             "out_gamma": f64(kc), "out_beta": f64(1), "out_zeta": f64(1), "out_obj": f64(1),
             "out_iters": i32(1), "out_evals": i32(1), "out_status": i32(1)}
         self.vk, self.vc = 2 * kc, 2 * (cand_cap + 1)
-        self.arr = DrvArrays(N, self.L, kc, G, self.vk, self.vc, self.vk,
+        self.arr = DrvArrays(N, self.L, kc, M, G, self.vk, self.vc, self.vk,
                              *[a[n].ctypes.data for n in _PTRS])
         self.prm = DrvParams(p.tau, p.tol_obj, p.tol_newton, p.eps_beta_rel, p.eps_L,
                              p.approx_ratio, p.approx_min_dist, p.ls_c1, p.curv_eps,
@@ -143,10 +147,12 @@ class HostDriver:
                 a[f"ev_{q}"][:2 * K] = np.asarray(ev.act[q], np.complex128).view(np.float64)
             a["lev_status"][0] = 0
         elif bits & REQ_EVAL:
-            ev = self.last = nm.Evaluation(self.y, th, ga, beta)
+            ev = self.last = (nm.Evaluation(self.y, th, ga, beta) if self.obs is None else
+                              inc.EvaluationIncomplete(self.y, self.obs, th, ga, beta))
             a["logdet"][0] = ev.logdet
             a["yCy"][0] = ev.yCy
-            a["ww"][0] = float(np.vdot(ev.w, ev.w).real)
+            wm = ev.w if self.obs is None else ev.wM     # ||C^{-1} y||^2 in the M samples
+            a["ww"][0] = float(np.vdot(wm, wm).real)
             for q in "qrustvx":
                 v = np.asarray(ev.act[q], np.complex128)
                 a[f"ev_{q}"][:2 * K] = v.view(np.float64)

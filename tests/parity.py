@@ -156,6 +156,21 @@ def oracle_flat(y, params=None):
     return f
 
 
+def oracle_flat_incomplete(y, obs, params=None):
+    """oracle_flat for incomplete observations (obs: oracle.incomplete.Observation)."""
+    import numpy as np
+    from oracle.estimator import Params
+    from oracle.incomplete import OracleEstimatorIncomplete
+
+    def f(got):
+        est = OracleEstimatorIncomplete(np.asarray(y, np.complex128), obs, params or Params())
+        th, ga = np.asarray(got.theta, np.float64), np.asarray(got.gamma, np.float64)
+        ev = est.evaluate(th, ga, got.beta)
+        g, h = est._derivs(ev, ga)
+        return ev.f(len(th), got.zeta), float(np.sum(g * g / h))
+    return f
+
+
 def last_z_change(trace) -> int:
     """Last outer iteration in which the oracle's active set changed (an
     activation or a deactivation), from its trace; 0 if it never did."""

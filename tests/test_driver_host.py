@@ -160,3 +160,21 @@ def test_lanes_in_lockstep_hold_the_same_state(idx):
     assert all(d == 0 for d in h.lane_diffs), [i for i, d in enumerate(h.lane_diffs) if d]
     assert r["K"] == o.K
     np.testing.assert_allclose(r["theta"], o.theta, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_host_driver_incomplete_matches_incomplete_oracle(seed):
+    """Incomplete observations (Sec. IV): the driver with its count scales in M
+    (initial beta, stopping rules, K_max, zeta) fed by the incomplete-data
+    oracle reproduces that oracle's estimator."""
+    from oracle import incomplete as inc
+    inst = synth.workload_incomplete_small(seed)
+    obs = inc.Observation(inst.N, inst.idx, inst.phi)
+    o = inc.OracleEstimatorIncomplete(inst.y, obs).run()
+    r = hd.HostDriver(inst.y, obs=obs).run()
+    assert r["status"] == o.status and r["K"] == o.K and r["iterations"] == o.iterations
+    np.testing.assert_allclose(r["theta"], o.theta, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["gamma"], o.gamma, rtol=1e-9, atol=1e-14)
+    assert r["beta"] == pytest.approx(o.beta, rel=1e-9)
+    assert r["zeta"] == pytest.approx(o.zeta, rel=1e-12)
+    assert r["objective"] == pytest.approx(o.objective, rel=1e-10, abs=1e-9)
