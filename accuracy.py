@@ -11,6 +11,9 @@ the comparison algorithms are not part of this library).
   phasetran Fig. phasetran: block success rate over pair separation x K/N (pairs
             as in pairsep, as many as give K/N closest to the target), N = 128,
             SNR 20 dB.
+  mton      Fig. MtoN: incomplete data, M/N = 0.2 .. 1 rows of the identity
+            (first and last sample kept), N = 128, K = 10, 20 dB, by
+            sfls_estimate_incomplete (the semifast method of Sec. IV).
 
 Every trial of a figure is one instance of a single sfls_estimate batch.  The
 metrics (Sec. VI-A): a block success is the right model order with every
@@ -35,6 +38,7 @@ if ROOT not in sys.path:
 
 SNRS = (-5.0, 0.0, 3.0, 6.0, 9.0, 12.0, 15.0, 20.0, 25.0, 30.0)
 SEPS = (0.2, 0.4, 0.55, 0.7, 0.85, 1.0, 1.25, 1.5, 1.75)
+MTON = (0.2, 0.3, 0.4, 0.5, 0.6, 0.8, 1.0)
 RATIOS = (0.05, 0.1, 0.15, 0.2, 0.25, 0.3)
 
 
@@ -57,7 +61,10 @@ def run(ctx, points, make, params):
     import paper_1705_06073_amd as sf
     insts = [make(p, t) for p, t in points]
     t0 = time.perf_counter()
-    res = sf.estimate_batch(ctx, [i.y for i in insts], params)
+    if insts and insts[0].idx is not None:
+        res = sf.estimate_batch_incomplete(ctx, [(i.N, i.idx, i.phi, i.y) for i in insts], params)
+    else:
+        res = sf.estimate_batch(ctx, [i.y for i in insts], params)
     dt = time.perf_counter() - t0
     out = {}
     keys = sorted({p for p, _ in points})
@@ -79,6 +86,12 @@ def figure_pairsep(ctx, trials, params, seps=SEPS):
     return run(ctx, pts, lambda s, t: synth.workload_paper_pairs(t, s), params)
 
 
+def figure_mton(ctx, trials, params, ratios=MTON):
+    from paper_1705_06073_amd import synth
+    pts = [(r, t) for r in ratios for t in range(trials)]
+    return run(ctx, pts, lambda r, t: synth.workload_paper_mton(t, r), params)
+
+
 def figure_phasetran(ctx, trials, params, seps=SEPS, ratios=RATIOS, N=128):
     from paper_1705_06073_amd import synth
     pts = [((s, r), t) for s in seps for r in ratios for t in range(trials)]
@@ -92,7 +105,7 @@ def figure_phasetran(ctx, trials, params, seps=SEPS, ratios=RATIOS, N=128):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--figure", choices=["snr", "pairsep", "phasetran"], default="snr")
+    ap.add_argument("--figure", choices=["snr", "pairsep", "phasetran", "mton"], default="snr")
     ap.add_argument("--trials", type=int, default=500)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--param", action="append", default=[],
@@ -106,7 +119,8 @@ def main():
         over[k] = float(v) if "." in v or "e" in v else int(v)
     params = sf.default_params(precision=sf.SFLS_MIXED if a.precision == "mixed" else sf.SFLS_FP64,
                                **over)
-    fn = {"snr": figure_snr, "pairsep": figure_pairsep, "phasetran": figure_phasetran}[a.figure]
+    fn = {"snr": figure_snr, "pairsep": figure_pairsep, "phasetran": figure_phasetran,
+          "mton": figure_mton}[a.figure]
     out, dt, count = fn(ctx, a.trials, params)
     ctx.close()
     print(json.dumps({"figure": a.figure, "trials": a.trials, "precision": a.precision,

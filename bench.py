@@ -7,14 +7,16 @@ driver) of synthetic signals with N=4096, K~Poisson(40), minimum separation
 1/N, alpha~CN(0,1), SNR~U[0,30] dB, grid L=8N=32768, FP64 recursion and FP32
 grid FFTs.  Inputs are resident in HBM before timing starts.
 
-`value`: the steps' batches stream through a server with 256 slots
-(continuous batching: a slot freed by a finished solve takes the next
-instance at the following round).  Also reported: the same batches by one
-sfls_estimate call per batch (batch_sync, which waits for each batch's
-slowest instance), the plain FP64 method launched one instance at a time,
-p50/p99 latency, the roofline position of the dominant kernel (from HIP events
-the library records on its stream), and the CPU oracle timed on a bounded
-sample of the same workload.
+`value`: batched throughput, each step one sfls_estimate call that solves its
+batch of 256 to completion (so a step lasts as long as its slowest instance);
+latency is each solve's completion within its batch.  Also reported: the same
+batches streamed through a 256-slot server (continuous batching: a slot freed
+by a finished solve takes the next instance at the following round), the plain
+FP64 method launched one instance at a time over the 256 instances, the
+roofline position of the dominant kernel (from HIP events the library records
+on its stream) with its HBM reading and counter traffic, per-kernel HBM and
+FP64 fractions, the idle share of a round, and the CPU oracle timed on a
+bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -68,11 +70,25 @@ def cpu_baseline(insts, per_solve_active, per_solve_grid, L_mult=8.0):
         nm.Evaluation(inst.y, th, ga, be)
     t_active = (time.perf_counter() - t1) / 2
     t_solve = per_solve_grid * t_grid + per_solve_active * t_active
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    info = threadpool_info()
+    threads = max([i.get("num_threads", 1) for i in info] or [1])
+    blas = sorted({f"{i.get('internal_api')} {i.get('version')}" for i in info
+                   if i.get("user_api") == "blas"})
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        nproc = os.cpu_count()
     return {
         "value": 1.0 / t_solve,
         "unit": "solves/s",
         "cores": int(threads),
+        "host": {"nproc": nproc, "cpu_model": model, "blas": blas},
         "kind": "oracle",
         "sample": (f"dense FP64 oracle on instance 0 (N={inst.N}, K={inst.K}): one grid "
                    f"evaluation {t_grid:.2f} s, active evaluations {t_active:.2f} s each; "
@@ -84,6 +100,25 @@ def cpu_baseline(insts, per_solve_active, per_solve_grid, L_mult=8.0):
 SERVE_CLASSES = ((1024, 512), (4096, 256), (16384, 256), (65536, 256))
 SERVE_HBM = (2 << 30, 4 << 30, 8 << 30, 32 << 30)
 SERVE_POOL = {256: 64, 1024: 64, 4096: 32, 16384: 16, 65536: 8}
+
+
+def cpu_full_solves(insts, count, L_mult=8.0):
+    """Whole oracle solves of the first `count` instances (minutes each at
+    N=4096): per-solve median and the times, for the record beside the bounded
+    sample of cpu_baseline."""
+    import numpy as np
+    from oracle.estimator import Params, estimate
+
+    times, evals = [], []
+    for inst in insts[:count]:
+        t0 = time.perf_counter()
+        r = estimate(inst.y, Params(L_mult=L_mult))
+        times.append(time.perf_counter() - t0)
+        evals.append(r.evaluations)
+        log(f"oracle solve: N={inst.N} K={r.K} evaluations={r.evaluations} {times[-1]:.1f} s")
+    med = float(np.median(times))
+    return {"value": 1.0 / med, "unit": "solves/s", "median_s": med, "times_s": times,
+            "evaluations": evals, "instances": count}
 
 
 def serve_leg(rate, seconds, prec, single_n=None):
@@ -236,15 +271,117 @@ def uneven_leg(prec, count=2048):
     return out
 
 
+def incomplete_leg(steps, warmup, prec, B=256):
+    """Incomplete data by the semifast method (Sec. IV): B instances of the
+    runtime experiment's incomplete workload (N = 4096, M = 3072 rows of the
+    identity, K = 15, 20 dB, complex64), one sfls_estimate_incomplete call per
+    step timed end to end; then one more call with every kernel timed."""
+    import numpy as np
+    import torch
+    import paper_1705_06073_amd as sf
+    from paper_1705_06073_amd import synth
+    dev = torch.device("cuda", 0)
+    insts = [synth.workload_incomplete_n4096(i) for i in range(B)]
+    ctx = sf.Context(0)
+    n, m, moff, idx, phid, ydev, ydt = sf.pack_incomplete(ctx, [(i.N, i.idx, i.phi, i.y)
+                                                               for i in insts])
+    kc = np.full(B, sf.SFLS_SF_MAX_K, np.int64)
+    koff = np.concatenate([[0], np.cumsum(kc)[:-1]]).astype(np.int64)
+    KT = int(kc.sum())
+    f64 = dict(dtype=torch.float64, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    out = dict(K=torch.zeros(B, dtype=torch.int64, device=dev), theta=torch.zeros(KT, **f64),
+               alpha=torch.zeros(2 * KT, **f64), gamma=torch.zeros(KT, **f64),
+               beta=torch.zeros(B, **f64), zeta=torch.zeros(B, **f64),
+               objective=torch.zeros(B, **f64), iters=torch.zeros(B, **i32),
+               evals=torch.zeros(B, **i32), status=torch.zeros(B, **i32))
+    params = sf.default_params(precision=prec)
+    stream = torch.cuda.current_stream()
+
+    def call():
+        sf.sfls_estimate_incomplete(ctx, n, m, moff, idx, phid, ydev, ydt, params, kc, koff,
+                                    out["K"], out["theta"], out["alpha"], out["gamma"],
+                                    out["beta"], out["zeta"], out["objective"], out["iters"],
+                                    out["evals"], out["status"], stream=stream)
+
+    for w in range(warmup):
+        t = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        log(f"incomplete warmup {w + 1}/{warmup}: {time.perf_counter() - t:.3f} s")
+    times, rounds = [], 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(steps):
+        ts = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        run, _ = ctx.last_run()
+        rounds += run["rounds"]
+        log(f"incomplete step {s_ + 1}/{steps}: {times[-1]:.3f} s, rounds={run['rounds']}")
+    elapsed = time.perf_counter() - t0
+    Kh = out["K"].cpu().numpy()
+    st = out["status"].cpu().numpy()
+    evs = out["evals"].cpu().numpy()
+    # one more call with every kernel timed, outside the timed region
+    ctx.reset_stats()
+    ctx.set_timing(1)
+    torch.cuda.synchronize()
+    tk0 = time.perf_counter()
+    call()
+    torch.cuda.synchronize()
+    tk = time.perf_counter() - tk0
+    ctx.set_timing(False)
+    kst = ctx.kernel_stats()
+    ksum = sum(v["seconds"] for v in kst.values())
+    names = {"factor": "semifast evaluation (Gram sums, K x K Cholesky, residual)",
+             "omega": "semifast grid inputs (Phi^H C^-1 y, columns U, omega_s by FFT)",
+             "active": "semifast candidates (direct sums)", "grid": "grid q^G, s^G, Delta L",
+             "select": "grid selection", "driver": "driver"}
+    kernels = {}
+    for k, v in kst.items():
+        if v["launches"] == 0:
+            continue
+        e = {"stage": names.get(k, k), "launches": v["launches"], "ms_total": 1e3 * v["seconds"],
+             "share": v["seconds"] / max(1e-30, ksum)}
+        if v["flops"] > 0 and v["seconds"] > 0:
+            e["fp64_TFLOPs"] = v["flops"] / v["seconds"] / 1e12
+            e["fp64_frac"] = v["flops"] / v["seconds"] / FP64_PEAK
+        if v["bytes"] > 0 and v["seconds"] > 0:
+            e["hbm_GBps"] = v["bytes"] / v["seconds"] / 1e9
+            e["hbm_frac"] = v["bytes"] / v["seconds"] / HBM_PEAK
+        kernels[k] = e
+    ctx.close()
+    value = steps * B / elapsed
+    return {"value": value, "unit": "solves/s",
+            "workload": f"{B} instances, N=4096, M=3072 observed rows of the identity (first and "
+                        "last sample kept), K=15, separation 2/N, alpha = a + 0.2 e^(j arg a), "
+                        "20 dB, complex64 input; FP64 evaluation, "
+                        + ("FP32" if prec == sf.SFLS_MIXED else "FP64") + " grid",
+            "ms_per_step": 1e3 * elapsed / steps, "steps": steps,
+            "rounds_per_batch": rounds / steps, "K_mean": float(np.mean(Kh)),
+            "evals_mean": float(np.mean(evs)), "evals_max": int(evs.max()),
+            "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
+            "kernels": kernels,
+            "round_idle_frac": max(0.0, 1.0 - ksum / tk),
+            "paper_context": {"seconds_per_solve": 0.930,
+                              "hardware": "MATLAB, one thread, 2011 MacBook Pro (Fig. runtime_N, "
+                                          "incomplete data, N = 4096)",
+                              "solves_per_s": 1.0 / 0.930}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--plain", type=int, default=8,
+    ap.add_argument("--plain", type=int, default=256,
                     help="instances for the plain FP64 one-per-launch baseline (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-solves", type=int, default=0,
+                    help="also time this many whole oracle solves of the batch (minutes each)")
     ap.add_argument("--nufft", choices=["auto", "off", "on"], default="auto",
                     help="off-grid Fourier sums by direct sums or NUFFT (default: per instance)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -268,6 +405,10 @@ def main():
     ap.add_argument("--serve4096-rate", type=float, default=2000.0)
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving stream and print its summary")
+    ap.add_argument("--incomplete-steps", type=int, default=3,
+                    help="steps of the incomplete-data (semifast) leg; 0 skips it")
+    ap.add_argument("--incomplete-only", action="store_true",
+                    help="run only the incomplete-data leg and print its JSON")
     ap.add_argument("--uneven", action="store_true",
                     help="run only the uneven batch (2048 instances, N in [128, 16384])")
     args = ap.parse_args()
@@ -294,6 +435,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_bytes, "copies": 3}))
+        return
+    if args.incomplete_only:
+        prec = sf.SFLS_MIXED if args.precision == "mixed" else sf.SFLS_FP64
+        print(json.dumps({"incomplete": incomplete_leg(max(1, args.incomplete_steps),
+                                                       args.warmup, prec)}), flush=True)
         return
     if args.uneven:
         prec = sf.SFLS_MIXED if args.precision == "mixed" else sf.SFLS_FP64
@@ -377,97 +523,126 @@ def main():
                 got += srv.poll()
         return got
 
-    for w in range(args.warmup):
-        t = time.perf_counter()
-        run_stream(1)
-        log(f"warmup {w + 1}/{args.warmup} (continuous): {time.perf_counter() - t:.3f} s")
-    ctx.reset_stats()
-    # the timed legs bracket only the recursion with events (the roofline's
-    # kernel); an event between two kernels would idle the device a few us
-    ctx.set_timing(2)
-    r0 = sum(s.stats()["rounds"] for s in srvs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    served = run_stream(args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    rounds_c = sum(s.stats()["rounds"] for s in srvs) - r0
-    solves = args.steps * B
-    value = solves / elapsed
-    lat_c = np.array([r.t_done - r.t_submit for r in served])
-    log(f"continuous: {solves} solves in {elapsed:.3f} s over {rounds_c} rounds")
-    for r in served:
-        assert r.status in (sf.SFLS_OK, sf.SFLS_NOTCONV), r.status
-    for s in srvs:
-        s.close()
-
-    # --- batch-synchronous sfls_estimate: one call per step of 256 instances
+    # --- the batched measurement (value): one sfls_estimate call per step of
+    # 256 instances, timed end to end, so each step waits for its slowest
+    # instance; the timed legs bracket only the recursion with events (the
+    # roofline's kernel), since an event between two kernels idles the device
     for w in range(args.warmup):
         t = time.perf_counter()
         run_batch()
         torch.cuda.synchronize()
         log(f"warmup {w + 1}/{args.warmup} (one call per batch): {time.perf_counter() - t:.3f} s")
-    lat = []
+    ctx.reset_stats()
+    ctx.set_timing(2)
+    lat, step_s, rounds_b = [], [], 0
     torch.cuda.synchronize()
     tb0 = time.perf_counter()
-    for s in range(args.steps):
+    for s_ in range(args.steps):
         ts = time.perf_counter()
         run_batch()
         torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - ts)
         run, timeline = ctx.last_run()
+        rounds_b += run["rounds"]
         ev = out["evals"].cpu().numpy()
         lat.extend(timeline[np.clip(ev, 0, len(timeline) - 1)].tolist())
-        log(f"step {s + 1}/{args.steps}: {time.perf_counter() - ts:.3f} s, rounds={run['rounds']}, "
+        log(f"step {s_ + 1}/{args.steps}: {step_s[-1]:.3f} s, rounds={run['rounds']}, "
             f"evals={run['evals']} (grid {run['grid_evals']})")
     torch.cuda.synchronize()
     elapsed_b = time.perf_counter() - tb0
-    ctx.set_timing(False)
     kst = ctx.kernel_stats()
     run, _ = ctx.last_run()
-    # per-kernel shares: one more call of the batch, outside the timed region,
-    # with every kernel timed
-    ctx.reset_stats()
-    ctx.set_timing(1)
-    run_batch()
-    torch.cuda.synchronize()
-    ctx.set_timing(False)
-    kst_all = ctx.kernel_stats()
     st = out["status"].cpu().numpy()
     Kh = out["K"].cpu().numpy()
     its = out["iters"].cpu().numpy()
     evs = out["evals"].cpu().numpy()
-    value_b = solves / elapsed_b
+    solves = args.steps * B
+    value = solves / elapsed_b
+
+    # --- continuous batching (secondary): the same batches stream through a
+    # server with one slot per instance of a batch; a slot freed by a finished
+    # solve takes the next instance for the next round
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        run_stream(1)
+        log(f"warmup {w + 1}/{args.warmup} (continuous): {time.perf_counter() - t:.3f} s")
+    r0 = sum(s.stats()["rounds"] for s in srvs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    served = run_stream(args.steps)
+    torch.cuda.synchronize()
+    elapsed_c = time.perf_counter() - t0
+    rounds_c = sum(s.stats()["rounds"] for s in srvs) - r0
+    lat_c = np.array([r.t_done - r.t_submit for r in served])
+    log(f"continuous: {solves} solves in {elapsed_c:.3f} s over {rounds_c} rounds")
+    for r in served:
+        assert r.status in (sf.SFLS_OK, sf.SFLS_NOTCONV), r.status
+    for s in srvs:
+        s.close()
+    ctx.set_timing(False)
     # every step solves the same batch: each served solve of instance b has
     # the model order the batch call found for b
     same_K = int(sum(int(r.K == Kh[r.tag % B]) for r in served))
+
+    # --- per-kernel breakdown: one more call of the batch, outside the timed
+    # region, with every kernel bracketed by events
+    ctx.reset_stats()
+    ctx.set_timing(1)
+    torch.cuda.synchronize()
+    tk0 = time.perf_counter()
+    run_batch()
+    torch.cuda.synchronize()
+    tk = time.perf_counter() - tk0
+    ctx.set_timing(False)
+    kst_all = ctx.kernel_stats()
+    run_k, _ = ctx.last_run()
+    ksum = sum(x["seconds"] for x in kst_all.values())
+    kernels = {}
+    for k, v in kst_all.items():
+        e = {"launches": v["launches"], "ms_total": 1e3 * v["seconds"],
+             "share": v["seconds"] / max(1e-30, ksum)}
+        if v["bytes"] > 0 and v["seconds"] > 0:
+            e["hbm_GBps"] = v["bytes"] / v["seconds"] / 1e9
+            e["hbm_frac"] = v["bytes"] / v["seconds"] / HBM_PEAK
+        if v["flops"] > 0 and v["seconds"] > 0:
+            e["fp64_TFLOPs"] = v["flops"] / v["seconds"] / 1e12
+            e["fp64_frac"] = v["flops"] / v["seconds"] / FP64_PEAK
+        kernels[k] = e
+    rounds_k = max(1, run_k["rounds"])
+    idle = {"round_ms": 1e3 * tk / rounds_k, "kernels_ms_per_round": 1e3 * ksum / rounds_k,
+            "idle_frac": max(0.0, 1.0 - ksum / tk),
+            "definition": "one batch call with every kernel timed: 1 - (sum of kernel event "
+                          "durations) / wall time of the call"}
 
     # dominant kernel and its roofline position
     dom = max(kst.items(), key=lambda kv: kv[1]["seconds"])
     name, ks = dom
     algo = "levinson" if args.factor == "levinson" else "schur"  # AUTO: Schur from N=256 on
+    launches = max(1, ks["launches"])
+    traffic = None
+    if name == "factor" and algo == "schur" and B == 256:
+        # HBM bytes per launch from the committed counter summary of this
+        # workload (None once the kernel's sources have changed)
+        from paper_1705_06073_amd import pmc
+        traffic = pmc.traffic_bytes(os.path.join(ROOT, "profiles",
+                                                 "k_schur_n4096_b256_traffic.md"), "k_schur")
+    hbm_alg = ks["bytes"] / launches
+    hbm_read = {"bound": "hbm", "achieved": ks["bytes"] / ks["seconds"] / 1e9,
+                "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": ks["bytes"] / ks["seconds"] / HBM_PEAK,
+                "algorithmic_per_launch": hbm_alg,
+                "traffic_over_algorithmic": (traffic / hbm_alg) if traffic and hbm_alg else None}
     if ks["flops"] > 0:
         achieved = ks["flops"] / ks["seconds"]
-        traffic = None
-        if name == "factor" and algo == "schur" and B == 256:
-            # HBM bytes per launch from the committed counter summary of this
-            # workload (None once the kernel's sources have changed)
-            from paper_1705_06073_amd import pmc
-            traffic = pmc.traffic_bytes(os.path.join(ROOT, "profiles",
-                                                     "k_schur_n4096_b256_traffic.md"), "k_schur")
         roof = {"bound": "alu", "kernel": name + (f" ({algo})" if name == "factor" else ""),
                 "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": traffic,
-                "avg_launch_ms": 1e3 * ks["seconds"] / max(1, ks["launches"]),
-                "algorithmic_per_launch": ks["flops"] / max(1, ks["launches"])}
+                "avg_launch_ms": 1e3 * ks["seconds"] / launches,
+                "algorithmic_per_launch": ks["flops"] / launches,
+                "hbm_reading": hbm_read}
     else:
-        achieved = ks["bytes"] / ks["seconds"]
-        roof = {"bound": "hbm", "kernel": name, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
-                "avg_launch_ms": 1e3 * ks["seconds"] / max(1, ks["launches"]),
-                "algorithmic_per_launch": ks["bytes"] / max(1, ks["launches"])}
-    kernels = {k: {"launches": v["launches"], "ms_total": 1e3 * v["seconds"],
-                   "share": v["seconds"] / max(1e-30, sum(x["seconds"] for x in kst_all.values()))}
-               for k, v in kst_all.items()}
+        roof = dict(hbm_read, kernel=name, traffic=traffic,
+                    avg_launch_ms=1e3 * ks["seconds"] / launches)
 
     # plain FP64, one instance per launch, no batching
     plain = None
@@ -486,6 +661,8 @@ def main():
                              stream=stream)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - tb)
+            if (b + 1) % 64 == 0:
+                log(f"plain FP64: {b + 1}/{nb}")
         tp = time.perf_counter() - tp0
         plain = {"value": nb / tp, "unit": "solves/s", "instances": nb,
                  "latency_ms": {"p50": 1e3 * float(np.percentile(times, 50)),
@@ -499,12 +676,18 @@ def main():
     if args.serve4096_seconds > 0:
         serve4096 = serve_leg(args.serve4096_rate, args.serve4096_seconds, prec, single_n=4096)
 
+    incomplete = None
+    if args.incomplete_steps > 0:
+        incomplete = incomplete_leg(args.incomplete_steps, args.warmup, prec)
+
     cpu = None
     if not args.no_cpu_baseline:
         g_per = run["grid_evals"] / B
         a_per = (run["evals"] - run["grid_evals"]) / B
         log("timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(insts, a_per, g_per)
+        if args.cpu_solves > 0:
+            cpu["whole_solves"] = cpu_full_solves(insts, args.cpu_solves)
 
     lat = np.array(lat)
     result = {
@@ -514,7 +697,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * elapsed_b / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -523,22 +706,28 @@ def main():
         "config": {"workload": "256 independent instances, N=4096, K~Poisson(40), separation "
                                "1/N, alpha~CN(0,1), SNR~U[0,30] dB, grid L=8N=32768; FP64 "
                                "recursion, " + ("FP32" if prec == sf.SFLS_MIXED else "FP64")
-                               + " grid; a step is one batch of 256 solves, the batches "
-                               "streaming through 256 slots by continuous batching",
+                               + " grid; a step is one sfls_estimate call solving a batch of "
+                               "256 to completion",
                    "batch": B, "N": 4096, "L": 32768,
                    "precision": "mixed" if prec == sf.SFLS_MIXED else "fp64",
                    "factor": args.factor, "nufft": args.nufft},
-        "latency_ms": {"p50": 1e3 * float(np.percentile(lat_c, 50)),
-                       "p99": 1e3 * float(np.percentile(lat_c, 99)),
-                       "definition": "admission to completion of each solve, continuous batching"},
-        "continuous": {"rounds": rounds_c, "slots": args.slots, "servers": args.servers,
-                       "solves": solves,
-                       "schur_lds_transform": args.schur_lds,
-                       "solves_with_K_of_the_batch_call": same_K},
-        "batch_sync": {"value": value_b, "unit": "solves/s", "ms_per_step": 1e3 * elapsed_b / args.steps,
-                       "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
-                                      "p99": 1e3 * float(np.percentile(lat, 99)),
-                                      "definition": "completion within its batch of 256"}},
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                       "p99": 1e3 * float(np.percentile(lat, 99)),
+                       "definition": "completion of each solve within its batch (from the start "
+                                     "of the call)"},
+        "batch_median": {"value": B / float(np.median(step_s)), "unit": "solves/s",
+                         "ms": 1e3 * float(np.median(step_s)),
+                         "definition": "256 / median wall time of one batch call"},
+        "rounds_per_batch": rounds_b / args.steps,
+        "continuous": {"value": solves / elapsed_c, "unit": "solves/s",
+                       "ms_per_step": 1e3 * elapsed_c / args.steps,
+                       "latency_ms": {"p50": 1e3 * float(np.percentile(lat_c, 50)),
+                                      "p99": 1e3 * float(np.percentile(lat_c, 99)),
+                                      "definition": "admission to completion"},
+                       "rounds": rounds_c, "slots": args.slots, "servers": args.servers,
+                       "solves": solves, "schur_lds_transform": args.schur_lds,
+                       "solves_with_K_of_the_batch_call": same_K,
+                       "definition": "the same batches streamed through a 256-slot server"},
         "plain_fp64": plain,
         "per_solve": {"evals_mean": run["evals"] / B, "grid_evals_mean": run["grid_evals"] / B,
                       "evals_p50": float(np.percentile(evs, 50)),
@@ -551,9 +740,11 @@ def main():
         "kernels": kernels,
         "kernels_source": ("one more sfls_estimate call of the batch (256 solves) with every "
                            "kernel timed, outside the timed region; ms_total per call"),
+        "round_idle": idle,
         "cpu_baseline": cpu,
         "serving": serve,
         "serving_n4096": serve4096,
+        "incomplete": incomplete,
     }
     ctx.close()
     print(json.dumps(result), flush=True)

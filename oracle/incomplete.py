@@ -77,9 +77,12 @@ def covariance(obs: Observation, theta, gamma, beta: float) -> np.ndarray:
 
 
 def e_matrix(obs: Observation, F: nm.DenseFactor) -> np.ndarray:
-    """E = Phi^H C^{-1} Phi (N x N), zero outside the observed rows and columns."""
-    Ph = obs.matrix()
-    return Ph.conj().T @ F.inverse() @ Ph
+    """E = Phi^H C^{-1} Phi (N x N), zero outside the observed rows and columns:
+    [E]_{n_a, n_b} = conj(phi_a) [C^{-1}]_{ab} phi_b (each entry of the product
+    has the one term of the observed pair)."""
+    E = np.zeros((obs.N, obs.N), np.complex128)
+    E[np.ix_(obs.idx, obs.idx)] = (obs.phi.conj()[:, None] * F.inverse()) * obs.phi[None, :]
+    return E
 
 
 def adjoint_rows(obs: Observation, V: np.ndarray) -> np.ndarray:

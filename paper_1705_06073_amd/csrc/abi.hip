@@ -851,12 +851,14 @@ struct SfInput {
 // and column offsets) for a semifast call, and the device check of the
 // indices and weights (before any kernel indexes with them).  kc[b] is the
 // component capacity, at most SF_KMAX.  Returns the totals of the observation
-// arrays (sum m), the matrix blocks (sum 4 kc^2) and the columns (sum m kc).
+// arrays (sum m), the matrix blocks (sum 4 kc^2), the columns (sum m kc) and
+// the phase tables (sum kc (ceil(n/64) + 64)).
 static sfls_status sf_prepare(sfls_ctx* ctx, int64_t B, const SfInput& sf,
                               std::vector<InstInfo>& info, const std::vector<int32_t>& kc,
-                              hipStream_t st, int64_t* mtot, int64_t* smtot, int64_t* utot) {
+                              hipStream_t st, int64_t* mtot, int64_t* smtot, int64_t* utot,
+                              int64_t* ttot) {
   if (!sf.m || !sf.moff || !sf.idx) return fail(ctx, SFLS_EINVAL, "NULL observation argument");
-  int64_t mt = 0, sm = 0, ut = 0;
+  int64_t mt = 0, sm = 0, ut = 0, tt = 0;
   for (int64_t b = 0; b < B; ++b) {
     InstInfo& in = info[(size_t)b];
     if (sf.m[b] < 1 || sf.m[b] > in.N || sf.moff[b] < 0)
@@ -868,6 +870,8 @@ static sfls_status sf_prepare(sfls_ctx* ctx, int64_t B, const SfInput& sf,
     sm += 4 * (int64_t)in.kcap * in.kcap;
     in.uoff = ut;
     ut += (int64_t)in.nobs * in.kcap;
+    in.tboff = tt;
+    tt += (int64_t)in.kcap * SF_TBW(in.N);
     mt = std::max(mt, sf.moff[b] + sf.m[b]);
   }
   InstInfo* dinfo;
@@ -887,6 +891,7 @@ static sfls_status sf_prepare(sfls_ctx* ctx, int64_t B, const SfInput& sf,
   *mtot = mt;
   *smtot = sm;
   *utot = ut;
+  *ttot = tt;
   return SFLS_OK;
 }
 
@@ -957,11 +962,12 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     sep_coef((int)n[b], coef[(size_t)b]);
   }
   std::vector<DrvParams> dpv(1, drv_params(p));
-  int64_t sf_mtot = 0, sf_smtot = 0, sf_utot = 0;
+  int64_t sf_mtot = 0, sf_smtot = 0, sf_utot = 0, sf_ttot = 0;
   if (sf) {
     std::vector<int32_t> kcv((size_t)B);
     for (int64_t b = 0; b < B; ++b) kcv[(size_t)b] = info[(size_t)b].kcap;
-    if ((s = sf_prepare(ctx, B, *sf, info, kcv, st, &sf_mtot, &sf_smtot, &sf_utot)) != SFLS_OK)
+    if ((s = sf_prepare(ctx, B, *sf, info, kcv, st, &sf_mtot, &sf_smtot, &sf_utot, &sf_ttot)) !=
+        SFLS_OK)
       return s;
   }
 
@@ -1084,9 +1090,11 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   }
   // semifast workspace: the K x K matrix blocks, A^H y, c, C^{-1} y on the
   // observed samples and the grid columns U
-  cd *sfm = nullptr, *sfh = nullptr, *sfc = nullptr, *sfw = nullptr, *sfU = nullptr;
+  cd *sfm = nullptr, *sfh = nullptr, *sfc = nullptr, *sfw = nullptr, *sfU = nullptr,
+     *sft = nullptr;
   if (sf) {
-    if ((s = wsT(ctx, "e_sfm", (size_t)std::max<int64_t>(sf_smtot, 1), &sfm)) != SFLS_OK ||
+    if ((s = wsT(ctx, "e_sft", (size_t)std::max<int64_t>(sf_ttot, 1), &sft)) != SFLS_OK ||
+        (s = wsT(ctx, "e_sfm", (size_t)std::max<int64_t>(sf_smtot, 1), &sfm)) != SFLS_OK ||
         (s = wsT(ctx, "e_sfh", (size_t)ktot, &sfh)) != SFLS_OK ||
         (s = wsT(ctx, "e_sfc", (size_t)ktot, &sfc)) != SFLS_OK ||
         (s = wsT(ctx, "e_sfw", (size_t)std::max<int64_t>(sf_mtot, 1), &sfw)) != SFLS_OK ||
@@ -1104,18 +1112,21 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     if (ctx->host_req) (void)hipHostFree(ctx->host_req);
     ctx->host_req = nullptr;
     ctx->host_req_n = 0;
-    if (hipHostMalloc(&ctx->host_req, 2 * (size_t)B * sizeof(int32_t),
+    if (hipHostMalloc(&ctx->host_req, 3 * (size_t)B * sizeof(int32_t),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
       return fail(ctx, SFLS_ENOMEM, "pinned request buffer");
     ctx->host_req_n = B;
   }
   int32_t* hreq = ctx->host_req;
   int32_t* hreq2 = hreq + B;
+  int32_t* hkev = hreq + 2 * B;  // components of each request (accounting)
+  std::memset(hkev, 0, (size_t)B * sizeof(int32_t));
   // the driver writes the request bits into this pinned buffer directly
   int32_t* hreq_dev = nullptr;
   HIP_TRY(hipHostGetDevicePointer((void**)&hreq_dev, hreq, 0));
   P.req_host = hreq_dev;
   P.req2_host = hreq_dev + B;
+  P.kev_host = hreq_dev + 2 * B;
   const auto t0 = std::chrono::steady_clock::now();
   auto now_s = [&]() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1160,7 +1171,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     const double Nb = (double)n[b];
     if (!sf) return 16.0 * Nb + 16.0 * (2.0 * Nb - 1.0);
     const InstInfo& in = info[(size_t)b];
-    return 16.0 * in.nobs + 32.0 * (double)in.nobs * in.kcap + 16.0 * (2.0 * Nb - 1.0);
+    return 16.0 * in.nobs + 32.0 * (double)in.nobs * hkev[b] + 16.0 * (2.0 * Nb - 1.0);
   };
   const double esz_d = (double)esz;
   for (;;) {
@@ -1180,7 +1191,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
         // semifast: Gram sums (3 K^2 M / 2 complex MACs), the K x K Cholesky,
         // inverse and solves, the residual and q, r, u (4 K M)
         ++nact;
-        const double Mo = (double)info[(size_t)b].nobs, Kc = (double)info[(size_t)b].kcap;
+        const double Mo = (double)info[(size_t)b].nobs, Kc = (double)hkev[b];
         kflops[KID_FACTOR] += 8.0 * (1.5 * Kc * Kc * Mo + 4.0 * Kc * Mo) + 8.0 * Kc * Kc * Kc;
         kbytes[KID_FACTOR] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * Mo + 4.0 * Mo + 16.0 * Mo;
       } else if (rq & REQ_EVAL) {
@@ -1212,7 +1223,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     if (nact > 0 && sf) {
       HIP_TRY(tstart(KID_FACTOR));
       HIP_TRY(launch_sf_eval(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, y, ydtype, sf->idx,
-                             sf->phi, sfm, sfh, sfc, sfw, logdet, yCy, ww, lev_status, evq, evr,
+                             sf->phi, sfm, sfh, sfc, sft, sfw, logdet, yCy, ww, lev_status, evq, evr,
                              evu, evs, evt, evv, evx, (int)B, st));
       HIP_TRY(tstop(KID_FACTOR));
     }
@@ -1260,8 +1271,8 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     HIP_TRY(tstart2(KID_OMEGA));
     if (sf)
       HIP_TRY(launch_sf_grid_inputs(dinfo, P.req2, P.K_e, P.th_e, P.ga_e, P.beta_e, sf->idx,
-                                    sf->phi, sfw, sfm, ctx->tws64, w, sfU, scratch, oms, (int)B,
-                                    sz.maxP, st));
+                                    sf->phi, sfw, sfm, sft, ctx->tws64, w, sfU, scratch, oms,
+                                    (int)B, sz.maxP, st));
     else
       HIP_TRY(launch_omega(dinfo, P.req2, rho, delta, dcoef, ctx->tws64, scratch, 1, 1, oms,
                            nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st, dorder));
@@ -1277,7 +1288,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     HIP_TRY(tstart2(KID_ACTIVE));
     if (sf)
       HIP_TRY(launch_sf_cand(dinfo, P.req2, P.K_e, P.beta_e, sf->idx, sf->phi, sfw, sfU, cand,
-                             ncand, cq, cs, (int)B, st));
+                             ncand, cq, cs, (int)B, sz.maxN, st));
     else
       HIP_TRY(launch_active(dinfo, P.req2, P.K_e, ncand, prefix, (int)B, P.th_e, cand, w, rho,
                             delta, dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks,
@@ -1417,16 +1428,17 @@ sfls_status sfls_incomplete_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     }
   }
   const SfInput sfin{m, moff, idx, reinterpret_cast<const cd*>(phi)};
-  int64_t mt = 0, smt = 0, ut = 0;
-  if ((s = sf_prepare(ctx, B, sfin, info, kc, st, &mt, &smt, &ut)) != SFLS_OK) return s;
+  int64_t mt = 0, smt = 0, ut = 0, tt = 0;
+  if ((s = sf_prepare(ctx, B, sfin, info, kc, st, &mt, &smt, &ut, &tt)) != SFLS_OK) return s;
   InstInfo* dinfo;
   int32_t *dreq, *dK, *dnc = nullptr;
   if ((s = upload(ctx, "ie_info", info, st, &dinfo)) != SFLS_OK) return s;
   if ((s = upload(ctx, "ie_req", req, st, &dreq)) != SFLS_OK) return s;
   if ((s = upload(ctx, "ie_K", kev, st, &dK)) != SFLS_OK) return s;
   if (wc && (s = upload(ctx, "ie_nc", nc, st, &dnc)) != SFLS_OK) return s;
-  cd *sfm, *sfh, *sfc, *sfw, *sfU;
-  if ((s = wsT(ctx, "ie_sfm", (size_t)std::max<int64_t>(smt, 1), &sfm)) != SFLS_OK ||
+  cd *sfm, *sfh, *sfc, *sfw, *sfU, *sft;
+  if ((s = wsT(ctx, "ie_sft", (size_t)std::max<int64_t>(tt, 1), &sft)) != SFLS_OK ||
+      (s = wsT(ctx, "ie_sfm", (size_t)std::max<int64_t>(smt, 1), &sfm)) != SFLS_OK ||
       (s = wsT(ctx, "ie_sfh", (size_t)ktot, &sfh)) != SFLS_OK ||
       (s = wsT(ctx, "ie_sfc", (size_t)ktot, &sfc)) != SFLS_OK ||
       (s = wsT(ctx, "ie_sfw", (size_t)std::max<int64_t>(mt, 1), &sfw)) != SFLS_OK ||
@@ -1444,7 +1456,7 @@ sfls_status sfls_incomplete_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   for (int i = 0; i < 7; ++i)
     if (!vec[i] && (s = wsT(ctx, vnames[i], (size_t)ktot, &vec[i])) != SFLS_OK) return s;
   HIP_TRY(launch_sf_eval(dinfo, dreq, dK, theta, gamma, beta, y, ydtype, idx, sfin.phi, sfm, sfh,
-                         sfc, sfw, ld, yc, wn, stt, vec[0], vec[1], vec[2], vec[3], vec[4], vec[5],
+                         sfc, sft, sfw, ld, yc, wn, stt, vec[0], vec[1], vec[2], vec[3], vec[4], vec[5],
                          vec[6], (int)B, st));
   if (!grid) return SFLS_OK;
   cd *scratch, *w, *oms;
@@ -1456,13 +1468,13 @@ sfls_status sfls_incomplete_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   if ((s = wsT(ctx, "ie_pv", (size_t)B * sz.Rmax, &pv)) != SFLS_OK) return s;
   if ((s = wsT(ctx, "ie_pi", (size_t)B * sz.Rmax, &pi)) != SFLS_OK) return s;
   HIP_TRY(launch_sf_grid_inputs(dinfo, dreq, dK, theta, gamma, beta, idx, sfin.phi, sfw, sfm,
-                                ctx->tws64, w, sfU, scratch, oms, (int)B, sz.maxP, st));
+                                sft, ctx->tws64, w, sfU, scratch, oms, (int)B, sz.maxP, st));
   if (qG || sG)
     HIP_TRY(launch_grid(SFLS_FP64, dinfo, dreq, w, oms, nullptr, nullptr, ctx->tws64, ctx->logtw,
                         sz.Rmax, (int)B, sz.maxM, qG, sG, nullptr, pv, pi, st));
   if (wc)
     HIP_TRY(launch_sf_cand(dinfo, dreq, dK, beta, idx, sfin.phi, sfw, sfU, cand, dnc, (cd*)cq, cs,
-                           (int)B, st));
+                           (int)B, sz.maxN, st));
   return SFLS_OK;
 }
 

@@ -130,6 +130,7 @@ __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info
     // this thread's own store of the request bits, read back in order
     const int32_t r = __atomic_load_n(p.req + b, __ATOMIC_RELAXED);
     if (p.req_host) p.req_host[b] = r;
+    if (p.kev_host) p.kev_host[b] = __atomic_load_n(p.K_e + b, __ATOMIC_RELAXED);
     if (p.req2) {
       // a grid sweep at the point just evaluated runs in this round's second stage
       const int32_t r2 = (pass == 0 && (r & REQ_GRID) && !(r & REQ_EVAL)) ? r : 0;

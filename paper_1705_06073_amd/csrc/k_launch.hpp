@@ -68,6 +68,9 @@ struct DrvPools {
   // latter, for the host's accounting)
   int32_t* req2;
   int32_t* req2_host;
+  // optional host-mapped copy of the number of components of each request
+  // (the host's accounting of algorithmic work per round)
+  int32_t* kev_host = nullptr;
   // observation vectors (Sec. V) and the vector strides (complex elements) of
   // ev_q/ev_r/ev_u/q_save, cand_q and out_alpha
   int32_t G = 1;
@@ -155,13 +158,14 @@ hipError_t launch_driver(const InstInfo* info, const DrvParams* prm, DrvPools po
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st);
 
 // Incomplete observations (Sec. IV), the semifast evaluation at the requested
-// points (REQ_EVAL): Gram sums, the K x K Cholesky and inverse, ln|C|, s, t,
+// points (REQ_EVAL): phase tables (tabs, at tboff), Gram sums, the K x K
+// Cholesky and inverse, ln|C|, s, t,
 // v, x; then C^{-1} y on the observed samples (wM), y^H C^{-1} y, ||wM||^2,
 // q, r, u.  status[b] = SFLS_ENOTPD when K_s is not positive definite.
 hipError_t launch_sf_eval(const InstInfo* info, const int32_t* req, const int32_t* Kev,
                           const double* theta, const double* gamma, const double* beta,
                           const void* y, int ydtype, const int32_t* idx, const cd* phi,
-                          cd* sfm, cd* h, cd* cvec, cd* wM, double* logdet, double* yCy,
+                          cd* sfm, cd* h, cd* cvec, cd* tabs, cd* wM, double* logdet, double* yCy,
                           double* ww, int32_t* status, cd* oq, cd* orr, cd* ou, cd* os, cd* ot,
                           cd* ov, cd* ox, int B, hipStream_t st);
 // Grid-stage inputs at the evaluated point (REQ_GRID): w = Phi^H C^{-1} y as an
@@ -170,8 +174,8 @@ hipError_t launch_sf_eval(const InstInfo* info, const int32_t* req, const int32_
 hipError_t launch_sf_grid_inputs(const InstInfo* info, const int32_t* req, const int32_t* Kev,
                                  const double* theta, const double* gamma, const double* beta,
                                  const int32_t* idx, const cd* phi, const cd* wM, const cd* sfm,
-                                 const cd* tws, cd* w, cd* U, cd* scratch, cd* oms, int B,
-                                 int maxP, hipStream_t st);
+                                 const cd* tabs, const cd* tws, cd* w, cd* U, cd* scratch,
+                                 cd* oms, int B, int maxP, hipStream_t st);
 // bad[b] = 1 when instance b's observed indices are not strictly increasing in
 // [0, N) or a weight is zero or not finite (checked before any other use).
 hipError_t launch_sf_check(const InstInfo* info, const int32_t* idx, const cd* phi, int32_t* bad,
@@ -180,6 +184,6 @@ hipError_t launch_sf_check(const InstInfo* info, const int32_t* idx, const cd* p
 hipError_t launch_sf_cand(const InstInfo* info, const int32_t* req, const int32_t* Kev,
                           const double* beta, const int32_t* idx, const cd* phi, const cd* wM,
                           const cd* U, const int32_t* cand, const int32_t* ncand, cd* cq, double* cs,
-                          int B, hipStream_t st);
+                          int B, int maxN, hipStream_t st);
 
 }  // namespace sfls

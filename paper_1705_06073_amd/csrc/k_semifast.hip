@@ -33,7 +33,8 @@
 namespace sfls {
 
 constexpr int SF_NT = 256;
-constexpr int SF_MT = 32;    // rows of A staged per chunk of the Gram sums
+constexpr int SFG_NT = 512;  // Gram sums
+constexpr int SF_MT = 64;    // rows of A staged per chunk of the Gram sums
 constexpr int SF_KP = SF_KMAX + 2;  // staged row length (columns 0..K, a zero pad)
 constexpr int SF_UMT = 64;   // rows per chunk of the grid columns U
 constexpr int SF_CANDB = 8;  // blocks per instance of the candidate sums
@@ -53,22 +54,48 @@ __device__ __forceinline__ int64_t sf_g(const InstInfo& in, int p, int i, int k)
 __device__ __forceinline__ int64_t sf_li(const InstInfo& in, int i, int k) {
   return in.sfoff + (int64_t)3 * in.kcap * in.kcap + (int64_t)i * in.kcap + k;
 }
+// e^{j 2 pi n theta_k} from component k's phase tables (tb: the instance's tables)
+__device__ __forceinline__ cd sf_cis(const cd* __restrict__ tb, int W, int B1, int k, int n) {
+  const cd* t = tb + (int64_t)k * W;
+  return cmul(t[n >> 6], t[B1 + (n & 63)]);
+}
+
+// ---------------------------------------------------------------------------
+// Phase tables of the evaluation point's components (REQ_EVAL).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(SF_NT) void k_sf_tables(const InstInfo* __restrict__ info,
+                                                     const int32_t* __restrict__ req,
+                                                     const int32_t* __restrict__ Kev,
+                                                     const double* __restrict__ theta,
+                                                     cd* __restrict__ tabs) {
+  const int b = blockIdx.x;
+  if (!(req[b] & REQ_EVAL)) return;
+  const InstInfo in = info[b];
+  const int K = Kev[b], B1 = SF_TB1(in.N), W = SF_TBW(in.N);
+  cd* tb = tabs + in.tboff;
+  for (int e = threadIdx.x; e < K * W; e += SF_NT) {
+    const int k = e / W, j = e % W;
+    const double n = j < B1 ? 64.0 * (double)j : (double)(j - B1);
+    tb[e] = cis2pi(frac_mul(n, theta[in.koff + k]));
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Gram sums.  The columns of A are augmented by y (column K), so that the
 // last column of G0 is h = A^H y.  Each thread accumulates a 2 x 2 tile of the
 // upper triangle of the three weighted sums over its slice of the rows; the
-// slices are summed in a fixed order.
+// slices are summed in a fixed order.  The rows of a chunk (index, weight,
+// sample) are staged in LDS once, their A entries from the phase tables.
 // ---------------------------------------------------------------------------
 template <typename YT>
-__global__ __launch_bounds__(SF_NT) void k_sf_gram(const InstInfo* __restrict__ info,
-                                                   const int32_t* __restrict__ req,
-                                                   const int32_t* __restrict__ Kev,
-                                                   const double* __restrict__ theta,
-                                                   const YT* __restrict__ y,
-                                                   const int32_t* __restrict__ idx,
-                                                   const cd* __restrict__ phi,
-                                                   cd* __restrict__ sfm, cd* __restrict__ h) {
+__global__ __launch_bounds__(SFG_NT) void k_sf_gram(const InstInfo* __restrict__ info,
+                                                    const int32_t* __restrict__ req,
+                                                    const int32_t* __restrict__ Kev,
+                                                    const cd* __restrict__ tabs,
+                                                    const YT* __restrict__ y,
+                                                    const int32_t* __restrict__ idx,
+                                                    const cd* __restrict__ phi,
+                                                    cd* __restrict__ sfm, cd* __restrict__ h) {
   const int b = blockIdx.x;
   if (!(req[b] & REQ_EVAL)) return;
   const InstInfo in = info[b];
@@ -79,18 +106,22 @@ __global__ __launch_bounds__(SF_NT) void k_sf_gram(const InstInfo* __restrict__ 
   const int nb = (Kc + 1) / 2;
   const int ntile = nb * (nb + 1) / 2;
   const int tid = threadIdx.x;
-  // LDS: the staged rows (SF_MT x SF_KP) and their weights, reused for the
-  // slice partials (SF_NT x 12)
-  __shared__ cd sbuf[SF_NT * 12];
-  cd* sP = sbuf;
-  double* sd = reinterpret_cast<double*>(sbuf + SF_MT * SF_KP);
-  const int S = ntile >= SF_NT ? 1 : min(16, SF_NT / ntile);
-  const int npass = S == 1 ? (ntile + SF_NT - 1) / SF_NT : 1;
-  const double* th = theta + in.koff;
+  const int B1 = SF_TB1(in.N), W = SF_TBW(in.N);
+  const cd* tb = tabs + in.tboff;
+  // LDS: the staged rows (SF_MT x SF_KP), their weights 2 pi n, indices,
+  // phi and y; reused for the slice partials (SFG_NT x 12)
+  extern __shared__ cd sf_lds[];
+  cd* sP = sf_lds;
+  double* sd = reinterpret_cast<double*>(sP + SF_MT * SF_KP);
+  int32_t* sn = reinterpret_cast<int32_t*>(sd + SF_MT);
+  cd* sph = reinterpret_cast<cd*>(sn + SF_MT);
+  cd* sy = sph + SF_MT;
+  const int S = ntile >= SFG_NT ? 1 : min(16, SFG_NT / ntile);
+  const int npass = S == 1 ? (ntile + SFG_NT - 1) / SFG_NT : 1;
   const int64_t mo = in.obsoff;
   for (int pass = 0; pass < npass; ++pass) {
     int tile, slice;
-    if (S == 1) { tile = pass * SF_NT + tid; slice = 0; }
+    if (S == 1) { tile = pass * SFG_NT + tid; slice = 0; }
     else { tile = tid % ntile; slice = tid / ntile; }
     const bool act = tile < ntile && slice < S;
     int bi = 0, bk = 0;
@@ -106,15 +137,22 @@ __global__ __launch_bounds__(SF_NT) void k_sf_gram(const InstInfo* __restrict__ 
     for (int m0 = 0; m0 < M; m0 += SF_MT) {
       const int rows = min(SF_MT, M - m0);
       __syncthreads();
-      for (int e = tid; e < rows * (Kc + 1); e += SF_NT) {
+      if (tid < rows) {
+        const int64_t m = mo + m0 + tid;
+        const int32_t n = idx[m];
+        sn[tid] = n;
+        sd[tid] = 2.0 * M_PI * (double)n;
+        sph[tid] = sf_phi(phi, m);
+        sy[tid] = sf_y(y, m);
+      }
+      __syncthreads();
+      for (int e = tid; e < rows * (Kc + 1); e += SFG_NT) {
         const int r = e / (Kc + 1), k = e % (Kc + 1);
-        const int64_t m = mo + m0 + r;
         cd v{0.0, 0.0};
-        if (k < K) v = cmul(sf_phi(phi, m), cis2pi(frac_mul((double)idx[m], th[k])));
-        else if (k == K) v = sf_y(y, m);
+        if (k < K) v = cmul(sph[r], sf_cis(tb, W, B1, k, sn[r]));
+        else if (k == K) v = sy[r];
         sP[r * SF_KP + k] = v;
       }
-      for (int r = tid; r < rows; r += SF_NT) sd[r] = 2.0 * M_PI * (double)idx[mo + m0 + r];
       __syncthreads();
       if (act) {
         for (int r = slice; r < rows; r += S) {
@@ -137,13 +175,13 @@ __global__ __launch_bounds__(SF_NT) void k_sf_gram(const InstInfo* __restrict__ 
       __syncthreads();
       if (act) {
 #pragma unroll
-        for (int q = 0; q < 12; ++q) sbuf[tid * 12 + q] = acc[q];
+        for (int q = 0; q < 12; ++q) sf_lds[tid * 12 + q] = acc[q];
       }
       __syncthreads();
       if (act && slice == 0) {
         for (int s = 1; s < S; ++s) {
 #pragma unroll
-          for (int q = 0; q < 12; ++q) acc[q] = cadd(acc[q], sbuf[(s * ntile + tile) * 12 + q]);
+          for (int q = 0; q < 12; ++q) acc[q] = cadd(acc[q], sf_lds[(s * ntile + tile) * 12 + q]);
         }
       }
     }
@@ -170,6 +208,11 @@ __global__ __launch_bounds__(SF_NT) void k_sf_gram(const InstInfo* __restrict__ 
     }
   }
 }
+// LDS of k_sf_gram: the staged rows and row data, or the slice partials
+constexpr size_t SFG_LDS_ROWS = (size_t)SF_MT * SF_KP * sizeof(cd) + SF_MT * (sizeof(double) +
+                                sizeof(int32_t) + 2 * sizeof(cd));
+constexpr size_t SFG_LDS = SFG_LDS_ROWS > (size_t)SFG_NT * 12 * sizeof(cd)
+                               ? SFG_LDS_ROWS : (size_t)SFG_NT * 12 * sizeof(cd);
 
 // ---------------------------------------------------------------------------
 // Cholesky of K_s in LDS, L^{-1}, the active-set vectors s, t, v, x, the
@@ -347,6 +390,7 @@ __global__ __launch_bounds__(SF_NT) void k_sf_resid(const InstInfo* __restrict__
                                                     const YT* __restrict__ y,
                                                     const int32_t* __restrict__ idx,
                                                     const cd* __restrict__ phi,
+                                                    const cd* __restrict__ tabs,
                                                     const cd* __restrict__ cvec,
                                                     const int32_t* __restrict__ status,
                                                     cd* __restrict__ wM, double* __restrict__ yCy,
@@ -359,20 +403,18 @@ __global__ __launch_bounds__(SF_NT) void k_sf_resid(const InstInfo* __restrict__
   const int M = in.nobs;
   const double ib = 1.0 / beta[b];
   const int tid = threadIdx.x;
-  __shared__ double sth[SF_KMAX];
+  const int B1 = SF_TB1(in.N), W = SF_TBW(in.N);
+  const cd* tb = tabs + in.tboff;
   __shared__ cd sc[SF_KMAX];
   __shared__ double red[48 * (SF_NT / 64)];
-  for (int k = tid; k < K; k += SF_NT) {
-    sth[k] = theta[in.koff + k];
-    sc[k] = cvec[in.koff + k];
-  }
+  for (int k = tid; k < K; k += SF_NT) sc[k] = cvec[in.koff + k];
   __syncthreads();
   const int64_t mo = in.obsoff;
   double a2[2] = {0.0, 0.0};
   for (int m = tid; m < M; m += SF_NT) {
-    const double n = (double)idx[mo + m];
+    const int ni = idx[mo + m];
     cd pc{0.0, 0.0};
-    for (int k = 0; k < K; ++k) pc = cfma(cis2pi(frac_mul(n, sth[k])), sc[k], pc);
+    for (int k = 0; k < K; ++k) pc = cfma(sf_cis(tb, W, B1, k, ni), sc[k], pc);
     pc = cmul(sf_phi(phi, mo + m), pc);
     const cd ym = sf_y(y, mo + m);
     const cd wm = cd{(ym.x - pc.x) * ib, (ym.y - pc.y) * ib};
@@ -391,13 +433,13 @@ __global__ __launch_bounds__(SF_NT) void k_sf_resid(const InstInfo* __restrict__
 #pragma unroll
     for (int q = 0; q < 48; ++q) acc[q] = 0.0;
     for (int m = tid; m < M; m += SF_NT) {
-      const double n = (double)idx[mo + m];
+      const int ni = idx[mo + m];
       const cd v = cmulc(wM[mo + m], sf_phi(phi, mo + m));  // conj(phi) w
-      const double d = 2.0 * M_PI * n;
+      const double d = 2.0 * M_PI * (double)ni;
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
         if (k0 + kk >= K) break;
-        const cd t = cmulc(v, cis2pi(frac_mul(n, sth[k0 + kk])));  // e^{-j...} conj(phi) w
+        const cd t = cmulc(v, sf_cis(tb, W, B1, k0 + kk, ni));  // e^{-j...} conj(phi) w
         acc[6 * kk + 0] += t.x;
         acc[6 * kk + 1] += t.y;
         acc[6 * kk + 2] = fma(d, t.x, acc[6 * kk + 2]);
@@ -440,6 +482,7 @@ __global__ __launch_bounds__(SF_NT) void k_sf_prep(const InstInfo* __restrict__ 
                                                    const cd* __restrict__ phi,
                                                    const cd* __restrict__ wM,
                                                    const cd* __restrict__ sfm,
+                                                   const cd* __restrict__ tabs,
                                                    cd* __restrict__ w, cd* __restrict__ U) {
   const int b = blockIdx.x;
   if (!(req[b] & REQ_GRID)) return;
@@ -447,26 +490,25 @@ __global__ __launch_bounds__(SF_NT) void k_sf_prep(const InstInfo* __restrict__ 
   const int K = Kev[b], M = in.nobs, N = in.N;
   const int64_t mo = in.obsoff;
   const int tid = threadIdx.x;
-  for (int n = tid; n < N; n += SF_NT) {
-    int lo = 0, hi = M;  // first index with idx >= n
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (idx[mo + mid] < n) lo = mid + 1;
-      else hi = mid;
-    }
-    cd v{0.0, 0.0};
-    if (lo < M && idx[mo + lo] == n) v = cmulc(wM[mo + lo], sf_phi(phi, mo + lo));
-    w[in.off + n] = v;
+  // observed sample m writes its entry and zeroes the gap below it (the
+  // indices increase), the last one also the gap above: each entry once
+  cd* wb = w + in.off;
+  for (int m = tid; m < M; m += SF_NT) {
+    const int n = idx[mo + m];
+    const int lo = m > 0 ? idx[mo + m - 1] + 1 : 0;
+    for (int z = lo; z < n; ++z) wb[z] = cd{0.0, 0.0};
+    wb[n] = cmulc(wM[mo + m], sf_phi(phi, mo + m));
+    if (m == M - 1)
+      for (int z = n + 1; z < N; ++z) wb[z] = cd{0.0, 0.0};
   }
   if (K <= 0) return;
+  const int B1 = SF_TB1(N), W = SF_TBW(N);
+  const cd* tb = tabs + in.tboff;
   extern __shared__ cd sf_lds[];
   cd* sE = sf_lds;                      // SF_UMT x SF_LDK: |phi|^2 e^{j 2pi n theta_k} sqrt(gamma_k)
   cd* sW = sf_lds + SF_UMT * SF_LDK;    // K x SF_LDK: W[k][j] = conj(L^{-1}[j][k])
-  __shared__ double sth[SF_KMAX], sg[SF_KMAX];
-  for (int k = tid; k < K; k += SF_NT) {
-    sth[k] = theta[in.koff + k];
-    sg[k] = sqrt(fmax(gamma[in.koff + k], 0.0));
-  }
+  __shared__ double sg[SF_KMAX];
+  for (int k = tid; k < K; k += SF_NT) sg[k] = sqrt(fmax(gamma[in.koff + k], 0.0));
   for (int e = tid; e < K * K; e += SF_NT) {
     const int k = e / K, j = e % K;
     sW[k * SF_LDK + j] = cconj(sfm[sf_li(in, j, k)]);
@@ -479,7 +521,7 @@ __global__ __launch_bounds__(SF_NT) void k_sf_prep(const InstInfo* __restrict__ 
       const int r = e / K, k = e % K;
       const int64_t m = mo + m0 + r;
       const double p2 = phi ? cabs2(phi[m]) : 1.0;
-      const cd ev = cis2pi(frac_mul((double)idx[m], sth[k]));
+      const cd ev = sf_cis(tb, W, B1, k, idx[m]);
       sE[r * SF_LDK + k] = cd{ev.x * p2 * sg[k], ev.y * p2 * sg[k]};
     }
     __syncthreads();
@@ -578,14 +620,20 @@ __global__ __launch_bounds__(SF_NT) void k_sf_cand(const InstInfo* __restrict__ 
   const int tid = threadIdx.x;
   const double ib = 1.0 / beta[b];
   const cd* Ub = U + in.uoff;
+  const int B1 = SF_TB1(in.N), W = SF_TBW(in.N);
   __shared__ double red[34 * (SF_NT / 64)];
+  extern __shared__ cd sf_lds[];  // the candidate's phase tables (W entries)
   const int nc = ncand[b];
   for (int c = sub; c < nc; c += SF_CANDB) {
     const double th = (double)cand[in.coff + c] / (double)in.L;
+    __syncthreads();
+    for (int j = tid; j < W; j += SF_NT)
+      sf_lds[j] = cis2pi(frac_mul(j < B1 ? 64.0 * (double)j : (double)(j - B1), th));
+    __syncthreads();
     double qa[3] = {0.0, 0.0, 0.0};  // q (re, im), sum |phi|^2
     for (int m = tid; m < M; m += SF_NT) {
       const cd ph = sf_phi(phi, mo + m);
-      const cd t = cmulc(cmulc(wM[mo + m], ph), cis2pi(frac_mul((double)idx[mo + m], th)));
+      const cd t = cmulc(cmulc(wM[mo + m], ph), sf_cis(sf_lds, W, B1, 0, idx[mo + m]));
       qa[0] += t.x;
       qa[1] += t.y;
       qa[2] += cabs2(ph);
@@ -597,7 +645,7 @@ __global__ __launch_bounds__(SF_NT) void k_sf_cand(const InstInfo* __restrict__ 
 #pragma unroll
       for (int q = 0; q < 32; ++q) acc[q] = 0.0;
       for (int m = tid; m < M; m += SF_NT) {
-        const cd e = cconj(cis2pi(frac_mul((double)idx[mo + m], th)));
+        const cd e = cconj(sf_cis(sf_lds, W, B1, 0, idx[mo + m]));
 #pragma unroll
         for (int jj = 0; jj < 16; ++jj) {
           if (j0 + jj >= K) break;
@@ -621,15 +669,21 @@ __global__ __launch_bounds__(SF_NT) void k_sf_cand(const InstInfo* __restrict__ 
 hipError_t launch_sf_eval(const InstInfo* info, const int32_t* req, const int32_t* Kev,
                           const double* theta, const double* gamma, const double* beta,
                           const void* y, int ydtype, const int32_t* idx, const cd* phi,
-                          cd* sfm, cd* h, cd* cvec, cd* wM, double* logdet, double* yCy,
+                          cd* sfm, cd* h, cd* cvec, cd* tabs, cd* wM, double* logdet, double* yCy,
                           double* ww, int32_t* status, cd* oq, cd* orr, cd* ou, cd* os, cd* ot,
                           cd* ov, cd* ox, int B, hipStream_t st) {
-  if (ydtype == 0)
-    hipLaunchKernelGGL(k_sf_gram<cf>, dim3(B), dim3(SF_NT), 0, st, info, req, Kev, theta,
+  hipLaunchKernelGGL(k_sf_tables, dim3(B), dim3(SF_NT), 0, st, info, req, Kev, theta, tabs);
+  if (ydtype == 0) {
+    (void)hipFuncSetAttribute((const void*)k_sf_gram<cf>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)SFG_LDS);
+    hipLaunchKernelGGL(k_sf_gram<cf>, dim3(B), dim3(SFG_NT), SFG_LDS, st, info, req, Kev, tabs,
                        (const cf*)y, idx, phi, sfm, h);
-  else
-    hipLaunchKernelGGL(k_sf_gram<cd>, dim3(B), dim3(SF_NT), 0, st, info, req, Kev, theta,
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_sf_gram<cd>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)SFG_LDS);
+    hipLaunchKernelGGL(k_sf_gram<cd>, dim3(B), dim3(SFG_NT), SFG_LDS, st, info, req, Kev, tabs,
                        (const cd*)y, idx, phi, sfm, h);
+  }
   const size_t shm = (size_t)2 * SF_KMAX * SF_LDK * sizeof(cd);
   (void)hipFuncSetAttribute((const void*)k_sf_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)shm);
@@ -637,23 +691,23 @@ hipError_t launch_sf_eval(const InstInfo* info, const int32_t* req, const int32_
                      h, cvec, os, ot, ov, ox, logdet, status);
   if (ydtype == 0)
     hipLaunchKernelGGL(k_sf_resid<cf>, dim3(B), dim3(SF_NT), 0, st, info, req, Kev, theta, beta,
-                       (const cf*)y, idx, phi, cvec, status, wM, yCy, ww, oq, orr, ou);
+                       (const cf*)y, idx, phi, tabs, cvec, status, wM, yCy, ww, oq, orr, ou);
   else
     hipLaunchKernelGGL(k_sf_resid<cd>, dim3(B), dim3(SF_NT), 0, st, info, req, Kev, theta, beta,
-                       (const cd*)y, idx, phi, cvec, status, wM, yCy, ww, oq, orr, ou);
+                       (const cd*)y, idx, phi, tabs, cvec, status, wM, yCy, ww, oq, orr, ou);
   return hipGetLastError();
 }
 
 hipError_t launch_sf_grid_inputs(const InstInfo* info, const int32_t* req, const int32_t* Kev,
                                  const double* theta, const double* gamma, const double* beta,
                                  const int32_t* idx, const cd* phi, const cd* wM, const cd* sfm,
-                                 const cd* tws, cd* w, cd* U, cd* scratch, cd* oms, int B,
-                                 int maxP, hipStream_t st) {
+                                 const cd* tabs, const cd* tws, cd* w, cd* U, cd* scratch,
+                                 cd* oms, int B, int maxP, hipStream_t st) {
   const size_t shp = (size_t)(SF_UMT + SF_KMAX) * SF_LDK * sizeof(cd);
   (void)hipFuncSetAttribute((const void*)k_sf_prep, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)shp);
   hipLaunchKernelGGL(k_sf_prep, dim3(B), dim3(SF_NT), shp, st, info, req, Kev, theta, gamma, idx,
-                     phi, wM, sfm, w, U);
+                     phi, wM, sfm, tabs, w, U);
   const size_t sho = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);
   (void)hipFuncSetAttribute((const void*)k_sf_omega, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)sho);
@@ -665,9 +719,12 @@ hipError_t launch_sf_grid_inputs(const InstInfo* info, const int32_t* req, const
 hipError_t launch_sf_cand(const InstInfo* info, const int32_t* req, const int32_t* Kev,
                           const double* beta, const int32_t* idx, const cd* phi, const cd* wM,
                           const cd* U, const int32_t* cand, const int32_t* ncand, cd* cq, double* cs,
-                          int B, hipStream_t st) {
-  hipLaunchKernelGGL(k_sf_cand, dim3(B * SF_CANDB), dim3(SF_NT), 0, st, info, req, Kev, beta, idx,
-                     phi, wM, U, cand, ncand, cq, cs);
+                          int B, int maxN, hipStream_t st) {
+  const size_t shc = (size_t)SF_TBW(maxN) * sizeof(cd);
+  (void)hipFuncSetAttribute((const void*)k_sf_cand, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shc);
+  hipLaunchKernelGGL(k_sf_cand, dim3(B * SF_CANDB), dim3(SF_NT), shc, st, info, req, Kev, beta,
+                     idx, phi, wM, U, cand, ncand, cq, cs);
   return hipGetLastError();
 }
 

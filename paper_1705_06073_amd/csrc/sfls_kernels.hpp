@@ -31,7 +31,14 @@ struct InstInfo {
   int64_t obsoff;
   int64_t sfoff;  // semifast K x K matrices (4 kcap^2 complex elements)
   int64_t uoff;   // semifast grid columns (nobs x kcap complex elements)
+  int64_t tboff;  // semifast phase tables (kcap x (ceil(N/64) + 64) complex elements)
 };
+
+// Semifast phase tables: e^{j 2 pi n theta_k} = T1_k[n >> 6] T2_k[n & 63] with
+// T1_k[a] = e^{j 2 pi 64 a theta_k}, T2_k[b] = e^{j 2 pi b theta_k}, each entry
+// from an exactly reduced phase; a component's tables are SF_TB1(N) + 64 entries.
+__host__ __device__ constexpr int SF_TB1(int N) { return (N + 63) / 64; }
+__host__ __device__ constexpr int SF_TBW(int N) { return SF_TB1(N) + 64; }
 
 // Observation vectors of a launch (the multiple-measurement-vector model of
 // Sec. V; G = 1 is the single-vector model).  Every instance of a launch has
