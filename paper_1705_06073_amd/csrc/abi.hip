@@ -491,7 +491,8 @@ sfls_status sfls_create(sfls_ctx** out, int device, size_t hbm_budget_bytes) {
   }
   for (int k = 0; k < KID_COUNT; ++k)
     std::snprintf(ctx->kst[k].name, sizeof ctx->kst[k].name, "%s", kKernelNames[k]);
-  if (hipEventCreateWithFlags(&ctx->ev_round, hipEventDisableTiming) != hipSuccess ||
+  if (hipEventCreateWithFlags(&ctx->ev_rounds[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_rounds[1], hipEventDisableTiming) != hipSuccess ||
       noalloc_init(ctx) != SFLS_OK) {
     sfls_destroy(ctx);
     return SFLS_EDEVICE;
@@ -575,7 +576,8 @@ sfls_status sfls_destroy(sfls_ctx* ctx) {
   if (ctx->tws32) (void)hipFree(ctx->tws32);
   if (ctx->host_req) (void)hipHostFree(ctx->host_req);
   if (ctx->upload) (void)hipStreamDestroy(ctx->upload);
-  if (ctx->ev_round) (void)hipEventDestroy(ctx->ev_round);
+  for (auto& e : ctx->ev_rounds)
+    if (e) (void)hipEventDestroy(e);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   delete ctx;
@@ -1106,27 +1108,30 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   const double slack = prec == SFLS_FP64 ? 1e-9 : 1e-3;
   const int act_blocks = 2048;
 
-  // pinned host copies of the request bits (req, then the second-stage
-  // grid requests req2), read back after every round
+  // pinned host words the driver writes directly (read back by the host
+  // without a copy): per round, the request bits of every instance, the grid
+  // sweeps of the round's second stage (req2) and the component count of each
+  // request.  Two sets, by round parity: round r's driver passes write set
+  // (r + 1) % 2 while the host reads set r % 2 (written by round r - 1).
   if (ctx->host_req_n < B) {
     if (ctx->host_req) (void)hipHostFree(ctx->host_req);
     ctx->host_req = nullptr;
     ctx->host_req_n = 0;
-    if (hipHostMalloc(&ctx->host_req, 3 * (size_t)B * sizeof(int32_t),
+    if (hipHostMalloc(&ctx->host_req, 6 * (size_t)B * sizeof(int32_t),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
       return fail(ctx, SFLS_ENOMEM, "pinned request buffer");
     ctx->host_req_n = B;
   }
-  int32_t* hreq = ctx->host_req;
-  int32_t* hreq2 = hreq + B;
-  int32_t* hkev = hreq + 2 * B;  // components of each request (accounting)
-  std::memset(hkev, 0, (size_t)B * sizeof(int32_t));
-  // the driver writes the request bits into this pinned buffer directly
+  std::memset(ctx->host_req, 0, 6 * (size_t)B * sizeof(int32_t));
+  int32_t* hset[2] = {ctx->host_req, ctx->host_req + 3 * B};
   int32_t* hreq_dev = nullptr;
-  HIP_TRY(hipHostGetDevicePointer((void**)&hreq_dev, hreq, 0));
-  P.req_host = hreq_dev;
-  P.req2_host = hreq_dev + B;
-  P.kev_host = hreq_dev + 2 * B;
+  HIP_TRY(hipHostGetDevicePointer((void**)&hreq_dev, ctx->host_req, 0));
+  int32_t* dset[2] = {hreq_dev, hreq_dev + 3 * B};
+  auto write_set = [&](int set) {
+    P.req_host = dset[set];
+    P.req2_host = dset[set] + B;
+    P.kev_host = dset[set] + 2 * B;
+  };
   const auto t0 = std::chrono::steady_clock::now();
   auto now_s = [&]() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1134,114 +1139,65 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   ctx->timeline.clear();
   ctx->last = sfls_run_stats{};
   const bool timing = ctx->timing != 0;
-  bool launched[KID_COUNT];
-  double kflops[KID_COUNT], kbytes[KID_COUNT];
+  // kernel events by round parity: [parity][stage][kernel][start, stop]
+  const int EP = 2 * KID_COUNT;  // events of one stage
+  bool launched[2][2][KID_COUNT];
+  double kflops[2][KID_COUNT], kbytes[2][KID_COUNT];
+  std::memset(launched, 0, sizeof launched);
+  std::memset(kflops, 0, sizeof kflops);
+  std::memset(kbytes, 0, sizeof kbytes);
+  int par = 0, stage = 0;  // of the round being enqueued
   auto tstart = [&](int k) -> hipError_t {
-    launched[k] = true;
-    return timing && times_kernel(ctx->timing, k) ? hipEventRecord(ctx->ev[2 * k], st) : hipSuccess;
+    launched[par][stage][k] = true;
+    return timing && times_kernel(ctx->timing, k)
+               ? hipEventRecord(ctx->ev[(par * 2 + stage) * EP + 2 * k], st) : hipSuccess;
   };
   auto tstop = [&](int k) -> hipError_t {
-    return timing && times_kernel(ctx->timing, k) ? hipEventRecord(ctx->ev[2 * k + 1], st) : hipSuccess;
+    return timing && times_kernel(ctx->timing, k)
+               ? hipEventRecord(ctx->ev[(par * 2 + stage) * EP + 2 * k + 1], st) : hipSuccess;
   };
-  // the second stage of a round (grid sweeps at the point just evaluated)
-  bool launched2[KID_COUNT];
-  const int E2 = 2 * KID_COUNT;
-  auto tstart2 = [&](int k) -> hipError_t {
-    launched2[k] = true;
-    return timing && times_kernel(ctx->timing, k) ? hipEventRecord(ctx->ev[E2 + 2 * k], st) : hipSuccess;
-  };
-  auto tstop2 = [&](int k) -> hipError_t {
-    return timing && times_kernel(ctx->timing, k) ? hipEventRecord(ctx->ev[E2 + 2 * k + 1], st)
-                                          : hipSuccess;
-  };
-
-  HIP_TRY(launch_init_state(dinfo, y, ydtype, dst, P.req, (int)B, st, nullptr, vv));
-  HIP_TRY(launch_zero_i32(notdone, 1, st));
-  HIP_TRY(launch_zero_i32(P.req2, (int)B, st));
-  std::memset(hreq2, 0, (size_t)B * sizeof(int32_t));
-  HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
-  HIP_TRY(hipEventRecord(ctx->ev_round, st));
-  HIP_TRY(spin_wait(ctx->ev_round));
-  ctx->timeline.push_back(now_s());
-  int64_t rounds = 0, ev_total = 0, gevals = 0;
-  const int64_t max_rounds = 1000000;
+  const double esz_d = (double)esz;
   // algorithmic bytes of a sweep's omega stage: rho in, omega_s out; semifast:
   // the observed C^{-1} y and the columns U written and read, omega_s out
-  auto omega_bytes = [&](int64_t b) {
+  auto omega_bytes = [&](int64_t b, const int32_t* kev) {
     const double Nb = (double)n[b];
     if (!sf) return 16.0 * Nb + 16.0 * (2.0 * Nb - 1.0);
     const InstInfo& in = info[(size_t)b];
-    return 16.0 * in.nobs + 32.0 * (double)in.nobs * hkev[b] + 16.0 * (2.0 * Nb - 1.0);
+    return 16.0 * in.nobs + 32.0 * (double)in.nobs * kev[b] + 16.0 * (2.0 * Nb - 1.0);
   };
-  const double esz_d = (double)esz;
-  for (;;) {
-    int64_t nact = 0, ngrid = 0, nreq = 0;
-    for (int k = 0; k < KID_COUNT; ++k) {
-      launched[k] = launched2[k] = false;
-      kflops[k] = 0.0;
-      kbytes[k] = 0.0;
-    }
-    for (int64_t b = 0; b < B; ++b) {
-      const int32_t rq = hreq[b];
-      if (!rq) continue;
-      ++nreq;
-      const double N = (double)n[b];
-      // algorithmic work per evaluation (per-instance figures of the design)
-      if ((rq & REQ_EVAL) && sf) {
-        // semifast: Gram sums (3 K^2 M / 2 complex MACs), the K x K Cholesky,
-        // inverse and solves, the residual and q, r, u (4 K M)
-        ++nact;
-        const double Mo = (double)info[(size_t)b].nobs, Kc = (double)hkev[b];
-        kflops[KID_FACTOR] += 8.0 * (1.5 * Kc * Kc * Mo + 4.0 * Kc * Mo) + 8.0 * Kc * Kc * Kc;
-        kbytes[KID_FACTOR] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * Mo + 4.0 * Mo + 16.0 * Mo;
-      } else if (rq & REQ_EVAL) {
-        ++nact;
-        kflops[KID_FACTOR] += slay ? sflops[(size_t)b] : 8.0 * N * N;  // Schur or Levinson
-        kbytes[KID_FACTOR] += 40.0 * N;                       // c in, rho and delta out
-        kbytes[KID_GEN] += 16.0 * N;                          // c out
-        if (slay) {
-          const double P = (double)info[(size_t)b].P, lp = (double)info[(size_t)b].logP;
-          kflops[KID_REFINE] += 10.0 * 5.0 * P * lp + 96.0 * P;  // 10 transforms + pointwise
-          kbytes[KID_REFINE] += 48.0 * N;                     // c, rho in; rho out
-        }
-        kbytes[KID_APPLY] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * N + 32.0 * N;  // y, rho in; w out
-        kbytes[KID_ACTIVE] += 32.0 * N;                       // w, rho in
-      }
-      // grid stage: alone when the evaluation at the current point is in place
-      if (rq & REQ_GRID) {
-        ++ngrid;
-        const double Lb = (double)info[(size_t)b].L;
-        kbytes[KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz_d * Lb;  // w, omega_s in; Delta L out
-        kbytes[KID_OMEGA] += omega_bytes(b);
-      }
-    }
-    if (nreq == 0) break;
-    if (rounds >= max_rounds) return fail(ctx, SFLS_EDEVICE, "estimate did not finish");
-    ++rounds;
-    ev_total += nact;
-    gevals += ngrid;
-    if (nact > 0 && sf) {
+
+  // One round: the evaluations the instances asked for, the first driver
+  // pass, the grid stage and the candidates' vectors (for the sweeps of
+  // P.req2), the second driver pass.  Every kernel is launched; each takes
+  // only the instances whose request bits name it, so the round can be
+  // enqueued before the host has read those bits.
+  auto enqueue_round = [&](int64_t r) -> sfls_status {
+    par = (int)(r & 1);
+    stage = 0;
+    std::memset(launched[par], 0, sizeof launched[par]);
+    write_set((int)((r + 1) & 1));
+    if (sf) {
       HIP_TRY(tstart(KID_FACTOR));
       HIP_TRY(launch_sf_eval(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, y, ydtype, sf->idx,
-                             sf->phi, sfm, sfh, sfc, sft, sfw, logdet, yCy, ww, lev_status, evq, evr,
-                             evu, evs, evt, evv, evx, (int)B, st));
+                             sf->phi, sfm, sfh, sfc, sft, sfw, logdet, yCy, ww, lev_status, evq,
+                             evr, evu, evs, evt, evv, evx, (int)B, st));
       HIP_TRY(tstop(KID_FACTOR));
-    }
-    if (nact > 0 && !sf) {
+    } else {
       HIP_TRY(tstart(KID_GEN));
       HIP_TRY(launch_toeplitz_column(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, c, (int)B,
                                      sz.maxN, st, ctx->nufft_mode, ctx->tws64, scratch,
                                      sz.maxP));
       HIP_TRY(tstop(KID_GEN));
       HIP_TRY(tstart(KID_FACTOR));
-      if ((s = run_recursion(ctx, B, dinfo, P.req, c, rho, delta, logdet, lev_status, failed,
-                             sz.maxN, st, slay, sacts, sscr, sFmax, dorder)) != SFLS_OK)
-        return s;
+      sfls_status rs;
+      if ((rs = run_recursion(ctx, B, dinfo, P.req, c, rho, delta, logdet, lev_status, failed,
+                              sz.maxN, st, slay, sacts, sscr, sFmax, dorder)) != SFLS_OK)
+        return rs;
       HIP_TRY(tstop(KID_FACTOR));
       HIP_TRY(tstart(KID_REFINE));
-      if ((s = run_refine(ctx, B, dinfo, P.req, c, rho, delta, lev_status, st, slay, rf,
-                          dorder)) != SFLS_OK)
-        return s;
+      if ((rs = run_refine(ctx, B, dinfo, P.req, c, rho, delta, lev_status, st, slay, rf,
+                           dorder)) != SFLS_OK)
+        return rs;
       // ln|C| over the active set (determinant lemma) where it is small enough
       HIP_TRY(launch_logdet_lemma(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, lev_status,
                                   logdet, (int)B, st));
@@ -1250,9 +1206,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
       HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw,
                               ctx->tws64, scratch, w, yCy, ww, (int)B, sz.maxP, st, dorder, vv));
       HIP_TRY(tstop(KID_APPLY));
-    }
-    // active-set vectors at the evaluated points (candidates follow the grid stage)
-    if (nact > 0 && !sf) {
+      // active-set vectors at the evaluated points (candidates follow the grid stage)
       HIP_TRY(tstart(KID_ACTIVE));
       HIP_TRY(launch_active(dinfo, P.req, P.K_e, nullptr, prefix, (int)B, P.th_e, cand, w, rho,
                             delta, dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks,
@@ -1268,7 +1222,8 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     // at the point this round evaluated (factor, C^-1 y and active vectors in
     // place), which so run now instead of a round later; then the candidates'
     // vectors and the second driver pass, for exactly these (P.req2).
-    HIP_TRY(tstart2(KID_OMEGA));
+    stage = 1;
+    HIP_TRY(tstart(KID_OMEGA));
     if (sf)
       HIP_TRY(launch_sf_grid_inputs(dinfo, P.req2, P.K_e, P.th_e, P.ga_e, P.beta_e, sf->idx,
                                     sf->phi, sfw, sfm, sft, ctx->tws64, w, sfU, scratch, oms,
@@ -1276,16 +1231,16 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     else
       HIP_TRY(launch_omega(dinfo, P.req2, rho, delta, dcoef, ctx->tws64, scratch, 1, 1, oms,
                            nullptr, nullptr, nullptr, nullptr, (int)B, sz.maxP, st, dorder));
-    HIP_TRY(tstop2(KID_OMEGA));
-    HIP_TRY(tstart2(KID_GRID));
+    HIP_TRY(tstop(KID_OMEGA));
+    HIP_TRY(tstart(KID_GRID));
     HIP_TRY(launch_grid(prec, dinfo, P.req2, w, oms, P.gbar_e, P.zeta_e, tw, ctx->logtw, sz.Rmax,
                         (int)B, sz.maxM, nullptr, nullptr, dL, pv, pi, st, vv));
-    HIP_TRY(tstop2(KID_GRID));
-    HIP_TRY(tstart2(KID_SELECT));
+    HIP_TRY(tstop(KID_GRID));
+    HIP_TRY(tstart(KID_SELECT));
     HIP_TRY(launch_select(prec, dinfo, P.req2, dL, sz.Rmax, pv, pi, p.approx_ratio, slack,
                           p.cand_cap, cand, ncand, ovf, (int)B, st));
-    HIP_TRY(tstop2(KID_SELECT));
-    HIP_TRY(tstart2(KID_ACTIVE));
+    HIP_TRY(tstop(KID_SELECT));
+    HIP_TRY(tstart(KID_ACTIVE));
     if (sf)
       HIP_TRY(launch_sf_cand(dinfo, P.req2, P.K_e, P.beta_e, sf->idx, sf->phi, sfw, sfU, cand,
                              ncand, cq, cs, (int)B, sz.maxN, st));
@@ -1293,38 +1248,113 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
       HIP_TRY(launch_active(dinfo, P.req2, P.K_e, ncand, prefix, (int)B, P.th_e, cand, w, rho,
                             delta, dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks,
                             ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st, vv));
-    HIP_TRY(tstop2(KID_ACTIVE));
-    HIP_TRY(tstart2(KID_DRIVER));
+    HIP_TRY(tstop(KID_ACTIVE));
+    HIP_TRY(tstart(KID_DRIVER));
     HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st, 1));
-    HIP_TRY(tstop2(KID_DRIVER));
-    HIP_TRY(hipEventRecord(ctx->ev_round, st));
-    HIP_TRY(spin_wait(ctx->ev_round));
+    HIP_TRY(tstop(KID_DRIVER));
+    HIP_TRY(hipEventRecord(ctx->ev_rounds[par], st));
+    return SFLS_OK;
+  };
+
+  // the initial driver pass (round 0) writes the requests of round 1 into set 1
+  HIP_TRY(launch_init_state(dinfo, y, ydtype, dst, P.req, (int)B, st, nullptr, vv));
+  HIP_TRY(launch_zero_i32(notdone, 1, st));
+  HIP_TRY(launch_zero_i32(P.req2, (int)B, st));
+  write_set(1);
+  HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
+  HIP_TRY(hipEventRecord(ctx->ev_rounds[0], st));
+  int64_t rounds = 0, ev_total = 0, gevals = 0;
+  const int64_t max_rounds = 1000000;
+  // One round of lookahead: round r + 1 is enqueued while round r runs, so
+  // the device never waits for the host's turn between rounds.  Iteration r
+  // waits for round r - 1, reads round r's requests (set r % 2) and round
+  // r - 1's grid sweeps, clears the set, and enqueues round r + 1, whose
+  // driver passes write that set again.  A finished instance no longer writes
+  // its words, so a set read all zero means the batch is done (round r, then
+  // enqueued, finds nothing to do).
+  if ((s = enqueue_round(1)) != SFLS_OK) return s;
+  for (int64_t r = 1;; ++r) {
+    HIP_TRY(spin_wait(ctx->ev_rounds[(r - 1) & 1]));
     ctx->timeline.push_back(now_s());
-    // grid sweeps of the second stage: evaluation counts and their traffic
-    // (entries are cleared once read: the device writes them in its next first pass)
-    for (int64_t b = 0; b < B; ++b) {
-      if (!hreq2[b]) continue;
-      hreq2[b] = 0;
-      ++gevals;
-      const double N = (double)n[b], Lb = (double)info[(size_t)b].L;
-      kbytes[KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz_d * Lb;
-      kbytes[KID_OMEGA] += omega_bytes(b);
-      kbytes[KID_ACTIVE] += 32.0 * N;  // the candidates' vectors: w, rho in
-    }
-    if (timing) {
-      for (int k = 0; k < KID_COUNT; ++k) {
-        if (!times_kernel(ctx->timing, k)) continue;
-        for (int sg = 0; sg < 2; ++sg) {
-          if (!(sg ? launched2[k] : launched[k])) continue;
-          float ms = 0.0f;
-          HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[sg * E2 + 2 * k], ctx->ev[sg * E2 + 2 * k + 1]));
-          ctx->kst[k].launches += 1;
-          ctx->kst[k].seconds += 1e-3 * (double)ms;
+    const int rs = (int)(r & 1);
+    int32_t* hq = hset[rs];
+    int32_t* hq2 = hq + B;
+    int32_t* hk = hq + 2 * B;
+    if (r >= 2) {
+      // round r - 1: its second stage's grid sweeps, its kernel times
+      const int pp = (int)((r - 1) & 1);
+      for (int64_t b = 0; b < B; ++b) {
+        if (!hq2[b]) continue;
+        ++gevals;
+        const double N = (double)n[b], Lb = (double)info[(size_t)b].L;
+        kbytes[pp][KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz_d * Lb;
+        kbytes[pp][KID_OMEGA] += omega_bytes(b, hk);
+        kbytes[pp][KID_ACTIVE] += 32.0 * N;  // the candidates' vectors: w, rho in
+      }
+      if (timing) {
+        for (int k = 0; k < KID_COUNT; ++k) {
+          if (!times_kernel(ctx->timing, k)) continue;
+          for (int sg = 0; sg < 2; ++sg) {
+            if (!launched[pp][sg][k]) continue;
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[(pp * 2 + sg) * EP + 2 * k],
+                                        ctx->ev[(pp * 2 + sg) * EP + 2 * k + 1]));
+            ctx->kst[k].launches += 1;
+            ctx->kst[k].seconds += 1e-3 * (double)ms;
+          }
+          ctx->kst[k].flops += kflops[pp][k];
+          ctx->kst[k].bytes += kbytes[pp][k];
         }
-        ctx->kst[k].flops += kflops[k];
-        ctx->kst[k].bytes += kbytes[k];
+      }
+      for (int k = 0; k < KID_COUNT; ++k) kflops[pp][k] = kbytes[pp][k] = 0.0;
+    }
+    // round r's requests and their algorithmic work
+    int64_t nact = 0, ngrid = 0, nreq = 0;
+    for (int64_t b = 0; b < B; ++b) {
+      const int32_t rq = hq[b];
+      if (!rq) continue;
+      ++nreq;
+      const double N = (double)n[b];
+      // algorithmic work per evaluation (per-instance figures of the design)
+      if ((rq & REQ_EVAL) && sf) {
+        // semifast: Gram sums (3 K^2 M / 2 complex MACs), the K x K Cholesky,
+        // inverse and solves, the residual and q, r, u (4 K M)
+        ++nact;
+        const double Mo = (double)info[(size_t)b].nobs, Kc = (double)hk[b];
+        kflops[rs][KID_FACTOR] += 8.0 * (1.5 * Kc * Kc * Mo + 4.0 * Kc * Mo) + 8.0 * Kc * Kc * Kc;
+        kbytes[rs][KID_FACTOR] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * Mo + 4.0 * Mo + 16.0 * Mo;
+      } else if (rq & REQ_EVAL) {
+        ++nact;
+        kflops[rs][KID_FACTOR] += slay ? sflops[(size_t)b] : 8.0 * N * N;  // Schur or Levinson
+        kbytes[rs][KID_FACTOR] += 40.0 * N;                    // c in, rho and delta out
+        kbytes[rs][KID_GEN] += 16.0 * N;                       // c out
+        if (slay) {
+          const double P = (double)info[(size_t)b].P, lp = (double)info[(size_t)b].logP;
+          kflops[rs][KID_REFINE] += 10.0 * 5.0 * P * lp + 96.0 * P;  // 10 transforms + pointwise
+          kbytes[rs][KID_REFINE] += 48.0 * N;                  // c, rho in; rho out
+        }
+        kbytes[rs][KID_APPLY] += (ydtype == SFLS_C64 ? 8.0 : 16.0) * N + 32.0 * N;  // y, rho in; w out
+        kbytes[rs][KID_ACTIVE] += 32.0 * N;                    // w, rho in
+      }
+      // grid stage: alone when the evaluation at the current point is in place
+      if (rq & REQ_GRID) {
+        ++ngrid;
+        const double Lb = (double)info[(size_t)b].L;
+        kbytes[rs][KID_GRID] += 16.0 * N + 16.0 * (2.0 * N - 1.0) + esz_d * Lb;
+        kbytes[rs][KID_OMEGA] += omega_bytes(b, hk);
       }
     }
+    // the set is read: clear it for round r + 1's driver passes
+    std::memset(hq, 0, 3 * (size_t)B * sizeof(int32_t));
+    if (nreq == 0) {
+      HIP_TRY(spin_wait(ctx->ev_rounds[rs]));  // round r, enqueued, had nothing to do
+      break;
+    }
+    if (rounds >= max_rounds) return fail(ctx, SFLS_EDEVICE, "estimate did not finish");
+    ++rounds;
+    ev_total += nact;
+    gevals += ngrid;
+    if ((s = enqueue_round(r + 1)) != SFLS_OK) return s;
   }
   ctx->last.rounds = rounds;
   ctx->last.evals = ev_total;

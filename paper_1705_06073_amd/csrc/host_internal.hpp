@@ -28,17 +28,18 @@ struct sfls_ctx {
   sfls::cf* tws32 = nullptr;
   int logtw = 17;
   std::map<std::string, DevBuf> bufs;
-  int32_t* host_req = nullptr;  // pinned copies of the per-instance request bits (req, req2)
+  int32_t* host_req = nullptr;  // pinned per-instance request words, two sets (req, req2, K)
   int64_t host_req_n = 0;
   int32_t timing = 0;  // 0 off, 1 every kernel of a round, 2 the recursion only
   int32_t factor_algo = 0;  // sfls_factor_algo
   int32_t nufft_mode = 0;   // sfls_nufft_mode
-  hipEvent_t ev[4 * KID_COUNT] = {};  // per kernel: start/stop of a round's first and second stage
+  // per round parity, stage (first, second) and kernel: start and stop
+  hipEvent_t ev[8 * KID_COUNT] = {};
   sfls_kernel_stat kst[KID_COUNT] = {};
   sfls_run_stats last = {};
   std::vector<double> timeline;
   hipStream_t upload = nullptr;  // admission copies of the servers on this context
-  hipEvent_t ev_round = nullptr;  // end of an estimate round (request bits on the host)
+  hipEvent_t ev_rounds[2] = {};  // end of an estimate round, by parity (request words on the host)
   int32_t schur_lds_f = sfls::SCH_LDS_F;  // largest recursion transform kept in LDS
   size_t hbm_budget = 0;  // workspace limit in bytes (0: none)
   size_t ws_bytes = 0;    // workspace held
