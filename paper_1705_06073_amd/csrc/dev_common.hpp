@@ -303,9 +303,58 @@ __device__ __forceinline__ void wave_sync() {
 __device__ __forceinline__ int wave_ks_max(int logn) {
   return logn >= 10 ? 4 : (logn == 9 ? 3 : 2);
 }
+// The passes of a size known at compile time, unrolled: the runtime loop
+// over passes (with the group size chosen per pass) costs about as much as
+// the pass itself at the sizes the one-wave transforms run.
+template <int LOGN, int LH, typename C>
+__device__ __forceinline__ void wave_dif_passes(C* z, bool cj, const C* __restrict__ tl,
+                                                const C* __restrict__ tg, int lane) {
+  if constexpr (LH >= 0) {
+    constexpr int KM = LOGN >= 10 ? 4 : (LOGN == 9 ? 3 : 2);
+    constexpr int KS = LH + 1 < KM ? LH + 1 : KM;
+    constexpr int TOT = 1 << (LOGN - KS);
+    constexpr bool LDS_TW = (2 << LH) <= FFT_TWL;
+#pragma unroll
+    for (int g0 = 0; g0 < TOT; g0 += 64) {
+      const int g = g0 + lane;
+      if (TOT < 64 && g >= TOT) continue;
+      if constexpr (LDS_TW) dif_group<KS>(z, g, LH, tl, cj);
+      else dif_group<4>(z, g, LH, tg, cj);
+    }
+    wave_sync();
+    wave_dif_passes<LOGN, LH - KS>(z, cj, tl, tg, lane);
+  }
+}
+template <int LOGN, int LB, typename C>
+__device__ __forceinline__ void wave_dit_passes(C* z, bool cj, const C* __restrict__ tl,
+                                                const C* __restrict__ tg, int lane) {
+  if constexpr (LB < LOGN) {
+    constexpr int KM = LOGN >= 10 ? 4 : (LOGN == 9 ? 3 : 2);
+    constexpr int REM = LOGN % KM;
+    constexpr int KS = (LB == 0 && REM) ? REM : KM;
+    constexpr int TOT = 1 << (LOGN - KS);
+    constexpr bool LDS_TW = (2 << (LB + KS - 1)) <= FFT_TWL;
+#pragma unroll
+    for (int g0 = 0; g0 < TOT; g0 += 64) {
+      const int g = g0 + lane;
+      if (TOT < 64 && g >= TOT) continue;
+      if constexpr (LDS_TW) dit_group<KS>(z, g, LB, tl, cj);
+      else dit_group<4>(z, g, LB, tg, cj);
+    }
+    wave_sync();
+    wave_dit_passes<LOGN, LB + KS>(z, cj, tl, tg, lane);
+  }
+}
 template <typename C>
 __device__ __forceinline__ void wave_dif(C* z, int logn, bool cj, const C* __restrict__ tl,
                                          const C* __restrict__ tg, int lane) {
+  switch (logn) {
+    case 7: wave_dif_passes<7, 6>(z, cj, tl, tg, lane); return;
+    case 8: wave_dif_passes<8, 7>(z, cj, tl, tg, lane); return;
+    case 9: wave_dif_passes<9, 8>(z, cj, tl, tg, lane); return;
+    case 10: wave_dif_passes<10, 9>(z, cj, tl, tg, lane); return;
+    default: break;
+  }
   const int km = wave_ks_max(logn);
   int lh = logn - 1;
   while (lh >= 0) {
@@ -331,6 +380,13 @@ __device__ __forceinline__ void wave_dif(C* z, int logn, bool cj, const C* __res
 template <typename C>
 __device__ __forceinline__ void wave_dit(C* z, int logn, bool cj, const C* __restrict__ tl,
                                          const C* __restrict__ tg, int lane) {
+  switch (logn) {
+    case 7: wave_dit_passes<7, 0>(z, cj, tl, tg, lane); return;
+    case 8: wave_dit_passes<8, 0>(z, cj, tl, tg, lane); return;
+    case 9: wave_dit_passes<9, 0>(z, cj, tl, tg, lane); return;
+    case 10: wave_dit_passes<10, 0>(z, cj, tl, tg, lane); return;
+    default: break;
+  }
   const int km = wave_ks_max(logn);
   const int rem = logn % km;
   int lb = 0;

@@ -39,7 +39,7 @@
 
 namespace sfls {
 
-constexpr int SCH_NT = 512;
+constexpr int SCH_NT = 256;
 constexpr int SCH_LEAF = 64;
 // transform merges of F <= 2^SCH_WAVE_LOG give each transform to one wave
 constexpr int SCH_WAVE_LOG = 10;

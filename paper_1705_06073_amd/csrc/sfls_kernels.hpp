@@ -100,7 +100,7 @@ constexpr int SCH_MAXL = 16;
 // Merges of windows up to this size use direct polynomial products (parallel
 // sums, no transforms; the transform buffers must then hold 8m + 256 elements
 // each); larger ones use FFTs of size >= m.
-constexpr int SCH_DIRECT = 128;
+constexpr int SCH_DIRECT = 64;
 // Transform merges with F above this use two buffers of padded(F) in the
 // instance's Schur scratch (at xbig) instead of LDS (default; a context can
 // lower it, down to SCH_LDS_F_MIN, so that more instances share a CU's LDS).
