@@ -186,6 +186,23 @@ __device__ __forceinline__ cd wpow(const cd* __restrict__ tw, int logtw, int e, 
   }
   return tw[e << (logtw - logF)];
 }
+// W_F^e for F <= FFT_TWL from the LDS copy of the stage-major table head
+// (W_F^e = tws[F/2 + e] for e < F/2, and -tws[e] above)
+__device__ __forceinline__ cd wpow_l(const cd* s_tw, int e, int logF) {
+  const int h = 1 << (logF - 1);
+  if (e >= h) {
+    const cd w = s_tw[e];
+    return cd{-w.x, -w.y};
+  }
+  return s_tw[h + e];
+}
+__device__ __forceinline__ cd zbin_l(const cd* s_tw, int p, int logF) {
+  return wpow_l(s_tw, bitrev(p, logF), logF);
+}
+__device__ __forceinline__ cd row_phase_l(const cd* s_tw, int p, int logF, int m) {
+  const int f = bitrev(p, logF);
+  return wpow_l(s_tw, (f * (m - 1)) & ((1 << logF) - 1), logF);
+}
 // W_F^f for the bin at bit-reversed position p
 __device__ __forceinline__ cd zbin(const cd* __restrict__ tw, int logtw, int p, int logF) {
   return wpow(tw, logtw, bitrev(p, logF), logF);
@@ -446,12 +463,13 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
     const double invF = 1.0 / (double)F;
     cd* S = scr + L.spec[act.level];  // spectra of Theta1's first row, 2 x F
     const int zs = pidx(F);          // buffer stride of the one-wave transforms
-    if (logF <= SCH_WAVE_LOG && F <= L.ldsF &&
-        (act.type != SCH_MID || 4 * zs <= 2 * padded(L.Fmax))) {
-      // One wave per transform, block barriers only around the pointwise step.
+    if (logF <= SCH_WAVE_LOG && F <= L.ldsF && 4 * zs <= 2 * padded(L.Fmax)) {
+      // One wave per transform, block barriers only around the pointwise step;
+      // the spectra of Theta1's first row are transformed again by POST (in
+      // waves that would idle) instead of kept in scratch between the two.
       cd* Z = lds;
       if (act.type == SCH_MID) {
-        // waves 0-3: spectra of P11, P12 (kept in S) and of the window u, v
+        // waves 0-3: spectra of P11, P12 and of the window u, v
         if (wv < 4) {
           const cd* src = wv == 0 ? T1 : (wv == 1 ? T1 + st1 : (wv == 2 ? u : v));
           const int lim = wv < 2 ? m1 : m;
@@ -460,11 +478,9 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
                          [&](int t, cd x) { z[pidx(t)] = x; });
           wave_sync();
           wave_dif(z, logF, false, s_tw, tws, lane);
-          if (wv < 2)
-            for (int t = lane; t < F; t += 64) S[(int64_t)wv * F + t] = z[pidx(t)];
         }
         __syncthreads();
-        batched_for<2>(tid, SCH_NT, F, [&](int p) { return row_phase(tw, logtw, p, logF, m1); },
+        batched_for<2>(tid, SCH_NT, F, [&](int p) { return row_phase_l(s_tw, p, logF, m1); },
                        [&](int p, cd ph) {
           const cd s11 = Z[pidx(p)], s12 = Z[zs + pidx(p)];
           const cd fu = Z[2 * zs + pidx(p)], fv = Z[3 * zs + pidx(p)];
@@ -485,23 +501,25 @@ __global__ __launch_bounds__(SCH_NT) void k_schur(const InstInfo* __restrict__ i
         __syncthreads();
         continue;
       }
-      // POST / ROOT (one row as below): waves 0, 1 transform the row of Theta2
+      // POST / ROOT (one row as below): waves 0, 1 transform the row of
+      // Theta2, waves 2, 3 the first row of Theta1 (P11, P12)
       const int row = root ? 1 : 0;
-      if (wv < 2) {
-        const cd* src = T2 + (2 * row + wv) * st1;
+      if (wv < 4) {
+        const cd* src = wv < 2 ? T2 + (2 * row + wv) * st1 : T1 + (wv - 2) * st1;
+        const int lim = wv < 2 ? m2 : m1;
         cd* z = Z + wv * zs;
-        batched_for<8>(lane, 64, F, [&](int t) { return t < m2 ? src[t] : cd{0.0, 0.0}; },
+        batched_for<8>(lane, 64, F, [&](int t) { return t < lim ? src[t] : cd{0.0, 0.0}; },
                        [&](int t, cd x) { z[pidx(t)] = x; });
         wave_sync();
         wave_dif(z, logF, false, s_tw, tws, lane);
       }
       __syncthreads();
       batched_for<2>(tid, SCH_NT, F, [&](int p) {
-        return cd4{zbin(tw, logtw, p, logF), row_phase(tw, logtw, p, logF, m1), S[p], S[F + p]};
-      }, [&](int p, cd4 g) {
+        return cd2{zbin_l(s_tw, p, logF), row_phase_l(s_tw, p, logF, m1)};
+      }, [&](int p, cd2 g) {
         const cd zb = g.a;
         const cd a1 = Z[pidx(p)], a2 = cmul(Z[zs + pidx(p)], zb);
-        const cd s11 = g.c, s12 = g.d;
+        const cd s11 = Z[2 * zs + pidx(p)], s12 = Z[3 * zs + pidx(p)];
         cd s21, s22;
         second_row(g.b, s11, s12, s21, s22);
         const cd r1 = cfma(a2, s21, cmul(a1, s11));
