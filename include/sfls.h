@@ -304,9 +304,11 @@ sfls_status sfls_active_eval(sfls_ctx* ctx, int64_t B, const int64_t* n, const i
  *   status device i32 [B] out: SFLS_OK, SFLS_NOTCONV, SFLS_ECAPACITY, SFLS_ENOTPD
  * 2 <= n[b] <= SFLS_MAX_N.  The call returns after the batch has finished on
  * `stream`: it runs evaluation rounds (the evaluations the instances asked
- * for, a driver pass, the grid stage, a second driver pass), polling an event
- * at the end of each and reading the request bits the driver writes into
- * pinned host memory; a batch of uneven N is dispatched longest first.
+ * for, a driver pass, the grid stage, a second driver pass).  The driver
+ * writes each round's request bits into pinned host memory; the host reads
+ * them one round behind, with round r + 1 already enqueued (every kernel of a
+ * round takes only the instances whose bits name it), and stops once a round
+ * leaves no request.  A batch of uneven N is dispatched longest first.
  * ------------------------------------------------------------------------- */
 sfls_status sfls_estimate(sfls_ctx* ctx, int64_t B, const int64_t* n, const int64_t* off,
                           const void* y, int32_t ydtype, const sfls_params* params,
