@@ -33,7 +33,7 @@ EXPORTS = ["sfls_params_default", "sfls_create", "sfls_destroy", "sfls_strerror"
            "sfls_gs_apply", "sfls_gs_apply_noalloc", "sfls_omega", "sfls_grid_eval", "sfls_active_eval", "sfls_estimate",
            "sfls_estimate_mmv", "sfls_incomplete_eval", "sfls_estimate_incomplete",
            "sfls_set_timing", "sfls_reset_stats", "sfls_kernel_stats", "sfls_last_run",
-           "sfls_set_factor", "sfls_set_nufft", "sfls_set_schur_lds", "sfls_server_config_default",
+           "sfls_set_factor", "sfls_set_nufft", "sfls_set_schur_lds", "sfls_set_speculation", "sfls_server_config_default",
            "sfls_server_create", "sfls_server_destroy", "sfls_server_footprint",
            "sfls_server_submit", "sfls_server_submit_many", "sfls_server_launch",
            "sfls_server_wait", "sfls_server_step", "sfls_server_poll", "sfls_server_get_stats"]
@@ -164,6 +164,8 @@ def lib() -> ctypes.CDLL:
     L.sfls_set_factor.restype = st
     L.sfls_set_nufft.argtypes = [_P, i32]
     L.sfls_set_nufft.restype = st
+    L.sfls_set_speculation.argtypes = [_P, i32]
+    L.sfls_set_speculation.restype = st
     L.sfls_set_schur_lds.argtypes = [_P, i32]
     L.sfls_set_schur_lds.restype = st
     L.sfls_set_timing.argtypes = [_P, i32]
@@ -268,6 +270,9 @@ class Context:
 
     def set_nufft(self, mode: int):
         self.check(lib().sfls_set_nufft(self._h, int(mode)))
+
+    def set_speculation(self, enable: bool = True):
+        self.check(lib().sfls_set_speculation(self._h, 1 if enable else 0))
 
     def set_schur_lds(self, max_f: int):
         self.check(lib().sfls_set_schur_lds(self._h, int(max_f)))

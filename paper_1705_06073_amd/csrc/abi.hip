@@ -491,6 +491,12 @@ sfls_status sfls_create(sfls_ctx** out, int device, size_t hbm_budget_bytes) {
   }
   for (int k = 0; k < KID_COUNT; ++k)
     std::snprintf(ctx->kst[k].name, sizeof ctx->kst[k].name, "%s", kKernelNames[k]);
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) ==
+            hipSuccess && ncu > 0)
+      ctx->ncu = ncu;
+  }
   if (hipEventCreateWithFlags(&ctx->ev_rounds[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_rounds[1], hipEventDisableTiming) != hipSuccess ||
       noalloc_init(ctx) != SFLS_OK) {
@@ -523,6 +529,13 @@ sfls_status sfls_set_nufft(sfls_ctx* ctx, int32_t mode) {
   if (mode != SFLS_NUFFT_AUTO && mode != SFLS_NUFFT_OFF && mode != SFLS_NUFFT_ON)
     return fail(ctx, SFLS_EINVAL, "unknown NUFFT mode %d", mode);
   ctx->nufft_mode = mode;
+  return SFLS_OK;
+}
+
+sfls_status sfls_set_speculation(sfls_ctx* ctx, int32_t enable) {
+  if (!ctx) return SFLS_EINVAL;
+  if (enable != 0 && enable != 1) return fail(ctx, SFLS_EINVAL, "speculation mode %d", (int)enable);
+  ctx->spec = enable;
   return SFLS_OK;
 }
 
@@ -929,6 +942,35 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   if (!params_valid(p)) return fail(ctx, SFLS_EINVAL, "invalid sfls_params");
   (void)hipSetDevice(ctx->device);
   hipStream_t st = as_stream(stream);
+  // Shadow slots (complete data, one vector): instance b's shadow is
+  // instance B + b of the launch, with its own copy of the signal; the driver
+  // steps the B instances only, the evaluation kernels all 2B.
+  const int64_t Br = B;
+  const bool spec = ctx->spec != 0 && !sf && G == 1 && B <= ctx->ncu && B <= 1024;
+  std::vector<int64_t> n2, off2, kcap2, koff2;
+  if (spec) {
+    int64_t ny = 0;
+    for (int64_t b = 0; b < Br; ++b) ny = std::max(ny, off[b] + n[b]);
+    n2.assign(n, n + Br);
+    n2.insert(n2.end(), n, n + Br);
+    off2.assign(off, off + Br);
+    for (int64_t b = 0; b < Br; ++b) off2.push_back(ny + off[b]);
+    kcap2.assign(kcap, kcap + Br);
+    kcap2.insert(kcap2.end(), kcap, kcap + Br);
+    koff2.assign(koff, koff + Br);
+    koff2.insert(koff2.end(), koff, koff + Br);
+    const size_t yb = (ydtype == SFLS_C64 ? 8 : 16) * (size_t)ny;
+    void* y2 = nullptr;
+    if ((s = ws(ctx, "e_ysh", 2 * yb, &y2)) != SFLS_OK) return s;
+    HIP_TRY(hipMemcpyAsync(y2, y, yb, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync((char*)y2 + yb, y, yb, hipMemcpyDeviceToDevice, st));
+    y = y2;
+    n = n2.data();
+    off = off2.data();
+    kcap = kcap2.data();
+    koff = koff2.data();
+    B = 2 * Br;
+  }
   Sizes sz;
   int64_t pt = 0, ntot = 0, ktot = 0, gtot = 0, ctot = 0;
   std::vector<InstInfo> info = base_info(B, n, off, sz, pt);
@@ -983,8 +1025,20 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   if ((s = upload(ctx, "e_okoff", okoff, st, &dokoff)) != SFLS_OK) return s;
   // a batch of uneven sizes starts its longest instances first
   int32_t* dorder = nullptr;
-  const std::vector<int32_t> order = longest_first(B, n);
-  if (!order.empty() && (s = upload(ctx, "e_order", order, st, &dorder)) != SFLS_OK) return s;
+  if (spec) {
+    // the real instances longest first (uneven N), then the shadows, whose
+    // half of the order each round's grant rewrites
+    const std::vector<int32_t> ro = longest_first(Br, n);
+    std::vector<int32_t> ordv((size_t)B);
+    for (int64_t i = 0; i < Br; ++i) {
+      ordv[(size_t)i] = ro.empty() ? (int32_t)i : ro[(size_t)i];
+      ordv[(size_t)(Br + i)] = (int32_t)(Br + i);
+    }
+    if ((s = upload(ctx, "e_order", ordv, st, &dorder)) != SFLS_OK) return s;
+  } else {
+    const std::vector<int32_t> order = longest_first(B, n);
+    if (!order.empty() && (s = upload(ctx, "e_order", order, st, &dorder)) != SFLS_OK) return s;
+  }
 
   const int J = p.lbfgs_J;
   const size_t esz = p.precision == SFLS_FP64 ? sizeof(double) : sizeof(float);
@@ -1056,6 +1110,10 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   WS("e_cbl", ctot, P.cbuf_l);
   int32_t* notdone;
   WS("e_notdone", 1, notdone);
+  if (spec) {
+    WS("e_wish", Br, P.wish);
+    P.nsh = (int32_t)Br;
+  }
 #undef WS
   P.ev_q = evq; P.ev_r = evr; P.ev_u = evu; P.ev_s = evs; P.ev_t = evt; P.ev_v = evv;
   P.ev_x = evx; P.logdet = logdet; P.yCy = yCy; P.ww = ww; P.lev_status = lev_status;
@@ -1113,24 +1171,24 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   // sweeps of the round's second stage (req2) and the component count of each
   // request.  Two sets, by round parity: round r's driver passes write set
   // (r + 1) % 2 while the host reads set r % 2 (written by round r - 1).
-  if (ctx->host_req_n < B) {
+  if (ctx->host_req_n < Br) {
     if (ctx->host_req) (void)hipHostFree(ctx->host_req);
     ctx->host_req = nullptr;
     ctx->host_req_n = 0;
-    if (hipHostMalloc(&ctx->host_req, 6 * (size_t)B * sizeof(int32_t),
+    if (hipHostMalloc(&ctx->host_req, 6 * (size_t)Br * sizeof(int32_t),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
       return fail(ctx, SFLS_ENOMEM, "pinned request buffer");
-    ctx->host_req_n = B;
+    ctx->host_req_n = Br;
   }
-  std::memset(ctx->host_req, 0, 6 * (size_t)B * sizeof(int32_t));
-  int32_t* hset[2] = {ctx->host_req, ctx->host_req + 3 * B};
+  std::memset(ctx->host_req, 0, 6 * (size_t)Br * sizeof(int32_t));
+  int32_t* hset[2] = {ctx->host_req, ctx->host_req + 3 * Br};
   int32_t* hreq_dev = nullptr;
   HIP_TRY(hipHostGetDevicePointer((void**)&hreq_dev, ctx->host_req, 0));
-  int32_t* dset[2] = {hreq_dev, hreq_dev + 3 * B};
+  int32_t* dset[2] = {hreq_dev, hreq_dev + 3 * Br};
   auto write_set = [&](int set) {
     P.req_host = dset[set];
-    P.req2_host = dset[set] + B;
-    P.kev_host = dset[set] + 2 * B;
+    P.req2_host = dset[set] + Br;
+    P.kev_host = dset[set] + 2 * Br;
   };
   const auto t0 = std::chrono::steady_clock::now();
   auto now_s = [&]() {
@@ -1200,7 +1258,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
         return rs;
       // ln|C| over the active set (determinant lemma) where it is small enough
       HIP_TRY(launch_logdet_lemma(dinfo, P.req, P.K_e, P.th_e, P.ga_e, P.beta_e, lev_status,
-                                  logdet, (int)B, st));
+                                  logdet, (int)B, st, dorder));
       HIP_TRY(tstop(KID_REFINE));
       HIP_TRY(tstart(KID_APPLY));
       HIP_TRY(launch_gs_apply(dinfo, P.req, y, ydtype, rho, delta, ctx->tw64, ctx->logtw,
@@ -1210,12 +1268,12 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
       HIP_TRY(tstart(KID_ACTIVE));
       HIP_TRY(launch_active(dinfo, P.req, P.K_e, nullptr, prefix, (int)B, P.th_e, cand, w, rho,
                             delta, dcoef, evq, evr, evu, evs, evt, evv, evx, cq, cs, act_blocks,
-                            ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st, vv));
+                            ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st, vv, dorder));
       HIP_TRY(tstop(KID_ACTIVE));
     }
     // first driver pass: the instances whose request had no grid sweep
     HIP_TRY(tstart(KID_DRIVER));
-    HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
+    HIP_TRY(launch_driver(dinfo, dprm, P, (int)Br, st));
     HIP_TRY(tstop(KID_DRIVER));
     // Grid stage, after the first pass: the grid sweeps the round began with
     // (their evaluation, if any, is done) and those the pass just requested
@@ -1250,18 +1308,24 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
                             ctx->nufft_mode, ctx->tws64, scratch, sz.maxP, st, vv));
     HIP_TRY(tstop(KID_ACTIVE));
     HIP_TRY(tstart(KID_DRIVER));
-    HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st, 1));
+    HIP_TRY(launch_driver(dinfo, dprm, P, (int)Br, st, 1));
     HIP_TRY(tstop(KID_DRIVER));
+    // shadow requests for the next round, on the CUs its requests leave free
+    if (spec) HIP_TRY(launch_spec_grant(P.req, P.wish, dorder, (int)Br, ctx->ncu, st));
     HIP_TRY(hipEventRecord(ctx->ev_rounds[par], st));
     return SFLS_OK;
   };
 
   // the initial driver pass (round 0) writes the requests of round 1 into set 1
-  HIP_TRY(launch_init_state(dinfo, y, ydtype, dst, P.req, (int)B, st, nullptr, vv));
+  HIP_TRY(launch_init_state(dinfo, y, ydtype, dst, P.req, (int)Br, st, nullptr, vv));
   HIP_TRY(launch_zero_i32(notdone, 1, st));
   HIP_TRY(launch_zero_i32(P.req2, (int)B, st));
+  if (spec) {
+    HIP_TRY(launch_zero_i32(P.req + Br, (int)Br, st));
+    HIP_TRY(launch_zero_i32(P.wish, (int)Br, st));
+  }
   write_set(1);
-  HIP_TRY(launch_driver(dinfo, dprm, P, (int)B, st));
+  HIP_TRY(launch_driver(dinfo, dprm, P, (int)Br, st));
   HIP_TRY(hipEventRecord(ctx->ev_rounds[0], st));
   int64_t rounds = 0, ev_total = 0, gevals = 0;
   const int64_t max_rounds = 1000000;
@@ -1278,12 +1342,12 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     ctx->timeline.push_back(now_s());
     const int rs = (int)(r & 1);
     int32_t* hq = hset[rs];
-    int32_t* hq2 = hq + B;
-    int32_t* hk = hq + 2 * B;
+    int32_t* hq2 = hq + Br;
+    int32_t* hk = hq + 2 * Br;
     if (r >= 2) {
       // round r - 1: its second stage's grid sweeps, its kernel times
       const int pp = (int)((r - 1) & 1);
-      for (int64_t b = 0; b < B; ++b) {
+      for (int64_t b = 0; b < Br; ++b) {
         if (!hq2[b]) continue;
         ++gevals;
         const double N = (double)n[b], Lb = (double)info[(size_t)b].L;
@@ -1310,7 +1374,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
     }
     // round r's requests and their algorithmic work
     int64_t nact = 0, ngrid = 0, nreq = 0;
-    for (int64_t b = 0; b < B; ++b) {
+    for (int64_t b = 0; b < Br; ++b) {
       const int32_t rq = hq[b];
       if (!rq) continue;
       ++nreq;
@@ -1345,7 +1409,7 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
       }
     }
     // the set is read: clear it for round r + 1's driver passes
-    std::memset(hq, 0, 3 * (size_t)B * sizeof(int32_t));
+    std::memset(hq, 0, 3 * (size_t)Br * sizeof(int32_t));
     if (nreq == 0) {
       HIP_TRY(spin_wait(ctx->ev_rounds[rs]));  // round r, enqueued, had nothing to do
       break;

@@ -112,6 +112,33 @@ struct DrvArrays {
   int32_t* out_iters;
   int32_t* out_evals;
   int32_t* out_status;
+  // Shadow evaluation slot (speculative trials of the final refinement; all
+  // NULL when off).  A rejected refinement trial is followed by the trial at
+  // half its step; when a trial is requested the driver also writes that
+  // next point into the shadow slot and sets *sh_wish, and the round's grant
+  // (one workgroup) turns wishes into shadow requests while CUs are free.  A
+  // granted shadow (*sh_req set) was evaluated in the same round as the
+  // trial, so a rejection continues with it at once instead of a round later;
+  // the points evaluated and the arithmetic are those without the shadow.
+  double* sh_th_e = nullptr;
+  double* sh_ga_e = nullptr;
+  int32_t* sh_K_e = nullptr;
+  double* sh_beta_e = nullptr;
+  double* sh_gbar_e = nullptr;
+  double* sh_zeta_e = nullptr;
+  const int32_t* sh_req = nullptr;
+  int32_t* sh_wish = nullptr;
+  const double* sh_ev_q = nullptr;  // complex [kcap] interleaved, as ev_q
+  const double* sh_ev_r = nullptr;
+  const double* sh_ev_u = nullptr;
+  const double* sh_ev_s = nullptr;
+  const double* sh_ev_t = nullptr;
+  const double* sh_ev_v = nullptr;
+  const double* sh_ev_x = nullptr;
+  const double* sh_logdet = nullptr;
+  const double* sh_yCy = nullptr;
+  const double* sh_ww = nullptr;
+  const int32_t* sh_lev_status = nullptr;
 };
 
 SFLS_HD inline double xlogy_(double a, double b) { return a == 0.0 ? 0.0 : a * log(b); }
@@ -366,25 +393,96 @@ struct Driver {
     S.polish = polish ? 1 : 0;
   }
 
-  SFLS_HD void ls_request() {
+  // the trial point at step alpha (as the evaluation kernels read it)
+  SFLS_HD void trial_point(double alpha, double* th_e, double* ga_e) const {
     const int K = S.K;
     // the component that limits a full step lands on gamma = 0 exactly
-    const int kz = (!S.polish && S.alpha == S.amax) ? S.kstar : -1;
+    const int kz = (!S.polish && alpha == S.amax) ? S.kstar : -1;
     for (int k = T::lane(); k < K; k += T::width()) {
-      double t = A.th[k] + S.alpha * A.d[k];
+      double t = A.th[k] + alpha * A.d[k];
       t = t - floor(t);
       if (t >= 1.0) t = 0.0;
-      A.th_e[k] = t;
-      double gk = A.ga[k] + S.alpha * A.d[K + k];
-      A.ga_e[k] = (k == kz) ? 0.0 : (gk > 0.0 ? gk : 0.0);
+      th_e[k] = t;
+      double gk = A.ga[k] + alpha * A.d[K + k];
+      ga_e[k] = (k == kz) ? 0.0 : (gk > 0.0 ? gk : 0.0);
     }
+  }
+
+  // whether a rejection of the trial at alpha ends the search (the tests of
+  // L_LS_RESULT at the halved step); dmax = max |d_theta| (polish only)
+  SFLS_HD bool gives_up_after(double alpha, double dmax) const {
+    if (S.ls_trial + 1 >= P.ls_max) return true;
+    const double ah = alpha * 0.5;
+    if (S.polish) return ah * dmax < P.polish_tol / (double)N;
+    return P.ls_c1 * ah * fabs(S.gd) < P.polish_ftol * (1.0 + fabs(S.f_cur));
+  }
+
+  SFLS_HD void ls_request() {
+    const int K = S.K;
+    trial_point(S.alpha, A.th_e, A.ga_e);
     *A.K_e = K;
     *A.beta_e = S.beta;
-    *A.gbar_e = gbar();
+    const double gb = gbar();
+    *A.gbar_e = gb;
     *A.zeta_e = S.zeta;
     *A.req = 1;  // REQ_EVAL
     S.nevals += 1;
     S.cur_valid = 0;
+    // the refinement's next trial, should this one be rejected
+    if (A.sh_wish && S.polish) {
+      double dm = 0.0;
+      for (int k = T::lane(); k < K; k += T::width()) dm = fmax(dm, fabs(A.d[k]));
+      dm = T::max(dm);
+      if (!gives_up_after(S.alpha, dm)) {
+        trial_point(S.alpha * 0.5, A.sh_th_e, A.sh_ga_e);
+        T::sync();
+        if (T::lane() == 0) {
+          *A.sh_K_e = K;
+          *A.sh_beta_e = S.beta;
+          *A.sh_gbar_e = gb;
+          *A.sh_zeta_e = S.zeta;
+          *A.sh_wish = 1;
+        }
+      }
+    }
+  }
+
+  // Continue with the shadow evaluation of the halved trial, which the
+  // rejected trial's search requests next: its point and results become the
+  // trial's, as if it had been requested and evaluated now.
+  SFLS_HD bool take_shadow() {
+    if (!A.sh_req || !(*A.sh_req & 1) || *A.sh_lev_status != 0) return false;
+    const int K = S.K;
+    double* eq = const_cast<double*>(A.ev_q);
+    double* er = const_cast<double*>(A.ev_r);
+    double* eu = const_cast<double*>(A.ev_u);
+    double* es = const_cast<double*>(A.ev_s);
+    double* et = const_cast<double*>(A.ev_t);
+    double* ev = const_cast<double*>(A.ev_v);
+    double* ex = const_cast<double*>(A.ev_x);
+    for (int k = T::lane(); k < K; k += T::width()) {
+      A.th_e[k] = A.sh_th_e[k];
+      A.ga_e[k] = A.sh_ga_e[k];
+      for (int c = 0; c < 2; ++c) {
+        eq[2 * k + c] = A.sh_ev_q[2 * k + c];
+        er[2 * k + c] = A.sh_ev_r[2 * k + c];
+        eu[2 * k + c] = A.sh_ev_u[2 * k + c];
+        es[2 * k + c] = A.sh_ev_s[2 * k + c];
+        et[2 * k + c] = A.sh_ev_t[2 * k + c];
+        ev[2 * k + c] = A.sh_ev_v[2 * k + c];
+        ex[2 * k + c] = A.sh_ev_x[2 * k + c];
+      }
+    }
+    T::sync();
+    if (T::lane() == 0) {
+      *const_cast<double*>(A.logdet) = *A.sh_logdet;
+      *const_cast<double*>(A.yCy) = *A.sh_yCy;
+      *const_cast<double*>(A.ww) = *A.sh_ww;
+    }
+    T::sync();
+    S.nevals += 1;
+    S.cur_valid = 0;
+    return true;
   }
 
   // Drops component k, shifting those above it down by one.  In chunks of
@@ -580,6 +678,8 @@ struct Driver {
     };
     int lbl;
     *A.req = 0;
+    // a shadow evaluation of this round (granted for the trial requested last)
+    bool sh_ready = A.sh_req && (*A.sh_req & 1);
     if (S.phase != PH_START && S.phase != PH_DONE && *A.lev_status != 0) {
       // the factorisation failed at the requested point: stop with what we have
       S.status = -4;
@@ -780,6 +880,10 @@ struct Driver {
             if (S.polish) { lbl = L_FINAL; break; }
             lbl = L_TERM_BEGIN;
             break;
+          }
+          if (S.polish && sh_ready) {
+            sh_ready = false;
+            if (take_shadow()) { lbl = L_LS_RESULT; break; }
           }
           ls_request();
           S.phase = PH_LS_WAIT;

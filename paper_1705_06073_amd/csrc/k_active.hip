@@ -260,8 +260,9 @@ __global__ __launch_bounds__(ACTL_NT) void k_active_lds(const InstInfo* __restri
                                                         cd* __restrict__ ou, cd* __restrict__ os,
                                                         cd* __restrict__ ot, cd* __restrict__ ov,
                                                         cd* __restrict__ ox, cd* __restrict__ cq,
-                                                        double* __restrict__ cs, Vecs vv) {
-  const int bi = blockIdx.x;
+                                                        double* __restrict__ cs, Vecs vv,
+                                                        const int32_t* __restrict__ order) {
+  const int bi = order ? order[blockIdx.x] : blockIdx.x;
   const int32_t rq = req ? req[bi] : REQ_EVAL;
   const InstInfo in = info[bi];
   const int nk = (rq & REQ_EVAL) ? Keval[bi] : 0;
@@ -382,8 +383,9 @@ __global__ __launch_bounds__(NU_NT) void k_active_nufft(const InstInfo* __restri
                                                         cd* __restrict__ ou, cd* __restrict__ os,
                                                         cd* __restrict__ ot, cd* __restrict__ ov,
                                                         cd* __restrict__ ox, cd* __restrict__ cq,
-                                                        double* __restrict__ cs) {
-  const int bi = blockIdx.x;
+                                                        double* __restrict__ cs,
+                                                        const int32_t* __restrict__ order) {
+  const int bi = order ? order[blockIdx.x] : blockIdx.x;
   const int32_t rq = req ? req[bi] : REQ_EVAL;
   const InstInfo in = info[bi];
   const int nk = (rq & REQ_EVAL) ? Keval[bi] : 0;
@@ -517,7 +519,7 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
                          const int32_t* cand, const cd* w, const cd* rho, const double* delta,
                          const SepCoef* coef, cd* oq, cd* orr, cd* ou, cd* os, cd* ot, cd* ov,
                          cd* ox, cd* cq, double* cs, int nblocks, int nmode, const cd* tws,
-                         cd* scratch, int maxP, hipStream_t st, Vecs vv) {
+                         cd* scratch, int maxP, hipStream_t st, Vecs vv, const int32_t* order) {
   if (!scratch) nmode = 1;  // no scratch for the NUFFT form: direct sums only
   if (vv.G > 1) nmode = 1;  // several observation vectors: direct sums
   // every instance has N <= P/2; with P <= 2 ACT_LDS_N throughout, the direct
@@ -536,7 +538,7 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(k_active_lds, dim3(B), dim3(ACTL_NT), shm, st, info, req, Keval, ncand,
                        nmode, theta, cand, w, rho, delta, coef, oq, orr, ou, os, ot, ov, ox, cq,
-                       cs, vv);
+                       cs, vv, order);
   }
   if (nmode != 1) {
     const size_t shm = (size_t)padded(maxP < CONV_LDS_P ? maxP : CONV_LDS_P) * sizeof(cd);
@@ -544,7 +546,7 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(k_active_nufft, dim3(B), dim3(NU_NT), shm, st, info, req, Keval, ncand,
                        nmode, theta, cand, w, rho, delta, coef, tws, scratch, oq, orr, ou, os, ot,
-                       ov, ox, cq, cs);
+                       ov, ox, cq, cs, order);
   }
   return hipGetLastError();
 }

@@ -383,8 +383,9 @@ __global__ __launch_bounds__(CONV_NT) void k_gen_update(const InstInfo* __restri
                                                         const int32_t* __restrict__ status,
                                                         cd* __restrict__ rho,
                                                         double* __restrict__ delta,
-                                                        const cd* __restrict__ dx) {
-  const int bi = blockIdx.x;
+                                                        const cd* __restrict__ dx,
+                                                        const int32_t* __restrict__ order) {
+  const int bi = order ? order[blockIdx.x] : blockIdx.x;
   if (req && !(req[bi] & REQ_EVAL)) return;
   if (status && status[bi] != 0) return;
   const InstInfo in = info[bi];
@@ -425,7 +426,7 @@ hipError_t launch_gen_refine(const InstInfo* info, const int32_t* req, const int
                       B, maxP, st, order);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gen_update, dim3(B), dim3(CONV_NT), 0, st, info, req, status, rho, delta,
-                     dx);
+                     dx, order);
   return hipGetLastError();
 }
 

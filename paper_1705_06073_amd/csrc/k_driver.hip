@@ -122,6 +122,29 @@ __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info
   A.out_iters = p.out_iters + b;
   A.out_evals = p.out_evals ? p.out_evals + b : nullptr;
   A.out_status = p.out_status + b;
+  if (p.nsh > 0) {
+    const int bs = b + p.nsh;
+    const int64_t ks = info[bs].koff;
+    A.sh_th_e = p.th_e + ks;
+    A.sh_ga_e = p.ga_e + ks;
+    A.sh_K_e = p.K_e + bs;
+    A.sh_beta_e = p.beta_e + bs;
+    A.sh_gbar_e = p.gbar_e + bs;
+    A.sh_zeta_e = p.zeta_e + bs;
+    A.sh_req = p.req + bs;
+    A.sh_wish = p.wish + b;
+    A.sh_ev_q = reinterpret_cast<const double*>(p.ev_q + ks);
+    A.sh_ev_r = reinterpret_cast<const double*>(p.ev_r + ks);
+    A.sh_ev_u = reinterpret_cast<const double*>(p.ev_u + ks);
+    A.sh_ev_s = reinterpret_cast<const double*>(p.ev_s + ks);
+    A.sh_ev_t = reinterpret_cast<const double*>(p.ev_t + ks);
+    A.sh_ev_v = reinterpret_cast<const double*>(p.ev_v + ks);
+    A.sh_ev_x = reinterpret_cast<const double*>(p.ev_x + ks);
+    A.sh_logdet = p.logdet + bs;
+    A.sh_yCy = p.yCy + bs;
+    A.sh_ww = p.ww + bs;
+    A.sh_lev_status = p.lev_status + bs;
+  }
   Driver<WaveTeam> drv(*prm, S, A);
   drv.step();
   if (threadIdx.x == 0) {
@@ -324,6 +347,75 @@ hipError_t launch_admit(const AdmitRec* recs, int n, const InstInfo* hinfo, cons
 hipError_t launch_slots_idle(DrvState* st, int32_t* req, int B, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_slots_idle, dim3((B + 255) / 256), dim3(256), 0, s, st, req, B);
+  return hipGetLastError();
+}
+
+// One workgroup, one thread per shadow slot and per instance (nsh <= 1024):
+// the free slots and the wishes are ranked by block-wide prefix counts, the
+// k-th wish takes the k-th free slot, and the shadows without a grant take the
+// remaining slots in order.
+constexpr int GRANT_NT = 1024;
+constexpr int SPEC_MAX = GRANT_NT;
+
+// exclusive prefix count of f over the workgroup (thread order), and the total
+__device__ __forceinline__ int grant_scan(bool f, int* s_w, int& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(f);
+  const int before = __popcll(m & ((1ull << lane) - 1ull));
+  __syncthreads();
+  if (lane == 0) s_w[wv] = __popcll(m);
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int i = 0; i < GRANT_NT / 64; ++i) {
+    if (i < wv) base += s_w[i];
+    tot += s_w[i];
+  }
+  total = tot;
+  return base + before;
+}
+
+__global__ __launch_bounds__(GRANT_NT) void k_spec_grant(int32_t* __restrict__ req,
+                                                         int32_t* __restrict__ wish,
+                                                         int32_t* __restrict__ ord, int nsh,
+                                                         int ncu) {
+  __shared__ int s_w[GRANT_NT / 64];
+  __shared__ int s_by_rank[SPEC_MAX];
+  __shared__ int s_other[SPEC_MAX];
+  const int j = threadIdx.x;  // slot j and instance j
+  const bool in = j < nsh;
+  // slot j: the CU slot of shadow workgroup nsh + j, and the instance there
+  const int c = in ? (nsh + j) % ncu : 0;
+  const bool fr = in && (c >= nsh || !(req[ord[c]] & REQ_EVAL));
+  const bool prim = in && (req[j] & REQ_EVAL);
+  const bool wi = in && wish[j] != 0;
+  int nprim, nfree, nwish;
+  (void)grant_scan(prim, s_w, nprim);
+  const int rf = grant_scan(fr, s_w, nfree);
+  const int rw = grant_scan(wi, s_w, nwish);
+  // only while at most half the CUs evaluate (measured: with more, the
+  // shadows of a round can still land behind a busy CU and double it)
+  const int ngr = nprim > ncu / 2 ? 0 : (nwish < nfree ? nwish : nfree);
+  const bool gr = wi && rw < ngr;
+  if (gr) s_by_rank[rw] = j;
+  // the slots without a granted shadow, and the shadows without a grant
+  const bool u = in && !(fr && rf < ngr);
+  const bool v = in && !gr;
+  int nu, nv;
+  const int ru = grant_scan(u, s_w, nu);
+  const int rv = grant_scan(v, s_w, nv);
+  if (v) s_other[rv] = j;
+  __syncthreads();
+  if (in) {
+    const int owner = (fr && rf < ngr) ? s_by_rank[rf] : s_other[ru];
+    ord[nsh + j] = nsh + owner;
+    req[nsh + j] = gr ? REQ_EVAL : 0;
+    wish[j] = 0;
+  }
+}
+
+hipError_t launch_spec_grant(int32_t* req, int32_t* wish, int32_t* ord, int nsh, int ncu,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_spec_grant, dim3(1), dim3(GRANT_NT), 0, st, req, wish, ord, nsh, ncu);
   return hipGetLastError();
 }
 

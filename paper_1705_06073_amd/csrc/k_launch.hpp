@@ -75,9 +75,23 @@ struct DrvPools {
   // ev_q/ev_r/ev_u/q_save, cand_q and out_alpha
   int32_t G = 1;
   int64_t kstride = 0, cstride = 0, ostride = 0;
+  // shadow evaluation slots (speculative refinement trials): instance b's
+  // shadow is instance b + nsh of the launch (nsh = 0: none); wish[b] marks
+  // a shadow point the driver wrote this round
+  int32_t nsh = 0;
+  int32_t* wish = nullptr;
 };
 
 hipError_t launch_twiddles(cd* tw64, cf* tw32, cd* tws64, cf* tws32, int logtw, hipStream_t st);
+// Shadow requests of the next round.  Workgroup i of a launch runs on the
+// CU slot i mod ncu, so shadow workgroup nsh + j shares its slot with the
+// instance's workgroup (nsh + j) mod ncu (nsh <= ncu): the shadows granted
+// (wishes in instance order, req[nsh + b] = REQ_EVAL) are placed, through
+// the launch order ord[nsh + j], on the slots whose instance requested no
+// evaluation; the other shadows fill the remaining slots with no request.
+// Wishes are cleared.  ord[0..nsh) is the order of the instances.
+hipError_t launch_spec_grant(int32_t* req, int32_t* wish, int32_t* ord, int nsh, int ncu,
+                             hipStream_t st);
 // a1, direct sums and (per instance, by use_nufft_col) the type-1 NUFFT in
 // the instance's scratch (4 P + padded(P) complex elements at poff).
 hipError_t launch_toeplitz_column(const InstInfo* info, const int32_t* req, const int32_t* Kcnt,
@@ -108,7 +122,7 @@ hipError_t launch_gen_refine(const InstInfo* info, const int32_t* req, const int
 hipError_t launch_logdet_lemma(const InstInfo* info, const int32_t* req, const int32_t* Kev,
                                const double* theta, const double* gamma,
                                const double* beta, const int32_t* status, double* logdet, int B,
-                               hipStream_t st);
+                               hipStream_t st, const int32_t* order = nullptr);
 hipError_t launch_omega(const InstInfo* info, const int32_t* req, const cd* rho,
                         const double* delta, const SepCoef* coef, const cd* tws,
                         cd* scratch, int which, int have_g0, cd* oms, cd* o_s, cd* o_t,
@@ -133,7 +147,8 @@ hipError_t launch_active(const InstInfo* info, const int32_t* req, const int32_t
                          const int32_t* cand, const cd* w, const cd* rho, const double* delta,
                          const SepCoef* coef, cd* oq, cd* orr, cd* ou, cd* os, cd* ot, cd* ov,
                          cd* ox, cd* cq, double* cs, int nblocks, int nmode, const cd* tws,
-                         cd* scratch, int maxP, hipStream_t st, Vecs vv = Vecs{});
+                         cd* scratch, int maxP, hipStream_t st, Vecs vv = Vecs{},
+                         const int32_t* order = nullptr);
 hipError_t launch_init_state(const InstInfo* info, const void* y, int ydtype, DrvState* st,
                              int32_t* req, int B, hipStream_t s, const int32_t* list = nullptr,
                              Vecs vv = Vecs{});

@@ -25,8 +25,9 @@ __global__ __launch_bounds__(LEM_NT) void k_logdet_lemma(const InstInfo* __restr
                                                          const double* __restrict__ gamma,
                                                          const double* __restrict__ beta,
                                                          const int32_t* __restrict__ status,
-                                                         double* __restrict__ logdet) {
-  const int bi = blockIdx.x;
+                                                         double* __restrict__ logdet,
+                                                         const int32_t* __restrict__ order) {
+  const int bi = order ? order[blockIdx.x] : blockIdx.x;
   if (!(req[bi] & REQ_EVAL)) return;
   if (status[bi] != 0) return;
   const int K = Kev[bi];
@@ -103,9 +104,9 @@ __global__ __launch_bounds__(LEM_NT) void k_logdet_lemma(const InstInfo* __restr
 hipError_t launch_logdet_lemma(const InstInfo* info, const int32_t* req, const int32_t* Kev,
                                const double* theta, const double* gamma,
                                const double* beta, const int32_t* status, double* logdet, int B,
-                               hipStream_t st) {
+                               hipStream_t st, const int32_t* order) {
   hipLaunchKernelGGL(k_logdet_lemma, dim3(B), dim3(LEM_NT), 0, st, info, req, Kev, theta, gamma,
-                     beta, status, logdet);
+                     beta, status, logdet, order);
   return hipGetLastError();
 }
 

@@ -60,7 +60,10 @@ _PTRS = ["th", "ga", "th_e", "ga_e", "K_e", "beta_e", "req", "gbar_e", "zeta_e",
          "Ym", "rhom", "am", "gt", "q_save", "ev_q", "ev_r", "ev_u", "ev_s", "ev_t", "ev_v", "ev_x",
          "logdet", "yCy", "ww", "lev_status", "cand", "ncand", "cand_q", "cand_s", "cbuf_dl",
          "cbuf_gh", "cbuf_l", "out_K", "out_theta", "out_alpha", "out_gamma", "out_beta",
-         "out_zeta", "out_obj", "out_iters", "out_evals", "out_status"]
+         "out_zeta", "out_obj", "out_iters", "out_evals", "out_status",
+         "sh_th_e", "sh_ga_e", "sh_K_e", "sh_beta_e", "sh_gbar_e", "sh_zeta_e", "sh_req",
+         "sh_wish", "sh_ev_q", "sh_ev_r", "sh_ev_u", "sh_ev_s", "sh_ev_t", "sh_ev_v", "sh_ev_x",
+         "sh_logdet", "sh_yCy", "sh_ww", "sh_lev_status"]
 
 
 class DrvArrays(ctypes.Structure):
@@ -80,7 +83,7 @@ class HostDriver:
     observed samples (evaluations from the incomplete-data oracle)."""
 
     def __init__(self, y, params: oe.Params | None = None, kcap: int | None = None,
-                 cand_cap: int = 256, obs=None):
+                 cand_cap: int = 256, obs=None, shadow: bool = False):
         self.p = p = params or oe.Params()
         self.y = np.asarray(y, np.complex128)
         self.obs = obs
@@ -108,9 +111,20 @@ class HostDriver:
             "out_K": np.zeros(1, np.int64), "out_theta": f64(kc), "out_alpha": f64(2 * G * kc),
             "out_gamma": f64(kc), "out_beta": f64(1), "out_zeta": f64(1), "out_obj": f64(1),
             "out_iters": i32(1), "out_evals": i32(1), "out_status": i32(1)}
+        # shadow slot of the refinement's speculative trials (complete data,
+        # one vector): every wish is granted and served from the oracle
+        self.shadow = shadow and obs is None and not self.mmv
+        if self.shadow:
+            a.update({"sh_th_e": f64(kc), "sh_ga_e": f64(kc), "sh_K_e": i32(1),
+                      "sh_beta_e": f64(1), "sh_gbar_e": f64(1), "sh_zeta_e": f64(1),
+                      "sh_req": i32(1), "sh_wish": i32(1),
+                      **{f"sh_ev_{q}": f64(2 * kc) for q in "qrustvx"},
+                      "sh_logdet": f64(1), "sh_yCy": f64(1), "sh_ww": f64(1),
+                      "sh_lev_status": i32(1)})
         self.vk, self.vc = 2 * kc, 2 * (cand_cap + 1)
         self.arr = DrvArrays(N, self.L, kc, M, G, self.vk, self.vc, self.vk,
-                             *[a[n].ctypes.data for n in _PTRS])
+                             *[a[n].ctypes.data if n in a else None for n in _PTRS])
+        self.shadow_served = 0
         self.prm = DrvParams(p.tau, p.tol_obj, p.tol_newton, p.eps_beta_rel, p.eps_L,
                              p.approx_ratio, p.approx_min_dist, p.ls_c1, p.curv_eps,
                              p.polish_tol, p.polish_ftol, J, p.max_inner, p.max_outer,
@@ -187,6 +201,26 @@ class HostDriver:
                 a["cand_q"][g * self.vc:g * self.vc + 2 * n] = qc.view(np.float64)
             a["cand_s"][:n] = sc
 
+    def _grant_shadow(self):
+        """A wish of the last step becomes a shadow evaluation for the next
+        (the device grants it while compute units are free)."""
+        a = self.a
+        a["sh_req"][0] = 0
+        if not a["sh_wish"][0]:
+            return
+        a["sh_wish"][0] = 0
+        K = int(a["sh_K_e"][0])
+        th, ga = a["sh_th_e"][:K].copy(), a["sh_ga_e"][:K].copy()
+        ev = nm.Evaluation(self.y, th, ga, float(a["sh_beta_e"][0]))
+        a["sh_logdet"][0] = ev.logdet
+        a["sh_yCy"][0] = ev.yCy
+        a["sh_ww"][0] = float(np.vdot(ev.w, ev.w).real)
+        for q in "qrustvx":
+            a[f"sh_ev_{q}"][:2 * K] = np.asarray(ev.act[q], np.complex128).view(np.float64)
+        a["sh_lev_status"][0] = 0
+        a["sh_req"][0] = REQ_EVAL
+        self.shadow_served += 1
+
     def run(self, max_steps=100000, lanes: int = 0):
         """Step the driver to completion.  lanes > 0 runs each step with that
         many lanes in lockstep and records, per step, how many lanes ended in a
@@ -213,6 +247,8 @@ class HostDriver:
                 break
             if self.a["req"][0]:
                 self._evaluate()
+            if self.shadow:
+                self._grant_shadow()
         a = self.a
         K = int(a["out_K"][0])
         oa = a["out_alpha"]

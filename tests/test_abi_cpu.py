@@ -61,6 +61,7 @@ def test_null_context_is_rejected_without_touching_the_device():
     assert L.sfls_factor(None, 1, n, o, None, None, None, None, None, None, None) == sf.SFLS_EINVAL
     assert L.sfls_estimate(None, 1, n, o, None, 1, None, n, o, *([None] * 11)) == sf.SFLS_EINVAL
     assert L.sfls_destroy(None) == sf.SFLS_OK
+    assert L.sfls_set_speculation(None, 1) == sf.SFLS_EINVAL
 
 
 def test_server_structs_match_the_header_layout():

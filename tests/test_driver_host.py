@@ -178,3 +178,55 @@ def test_host_driver_incomplete_matches_incomplete_oracle(seed):
     assert r["beta"] == pytest.approx(o.beta, rel=1e-9)
     assert r["zeta"] == pytest.approx(o.zeta, rel=1e-12)
     assert r["objective"] == pytest.approx(o.objective, rel=1e-10, abs=1e-9)
+
+
+@pytest.mark.parametrize("idx", range(10))
+def test_shadow_trials_change_steps_not_results(idx):
+    """Speculative refinement trials (a shadow slot evaluated beside each
+    refinement trial at half its step, served from the oracle): every output
+    is bitwise the result without shadows, the driver takes one step fewer for
+    each shadow it used, and 8 lanes in lockstep still hold one state."""
+    inst = _lane_instances()[idx]
+    plain = hd.HostDriver(inst.y)
+    r0 = plain.run(lanes=8)
+    spec = hd.HostDriver(inst.y, shadow=True)
+    r1 = spec.run(lanes=8)
+    assert all(d == 0 for d in spec.lane_diffs)
+    for k in ("K", "beta", "zeta", "objective", "iterations", "evaluations", "status"):
+        assert r1[k] == r0[k], k
+    for k in ("theta", "gamma", "alpha"):
+        assert np.array_equal(r1[k], r0[k]), k
+    assert len(spec.req_seq) <= len(plain.req_seq)
+
+
+def _refinement_instances():
+    """Two signals whose final refinements reject trials (draws 8 and 11 of
+    this sequence; the others accept every first trial)."""
+    rng = np.random.default_rng(2024)
+    out = []
+    for t in range(12):
+        N = int(rng.choice([64, 96, 128, 160]))
+        K = int(rng.integers(2, 10))
+        snr = float(rng.uniform(0, 30))
+        inst = synth.make_instance(rng, N, K, 1.0 / N, "cn", snr)
+        if t in (8, 11):
+            out.append(inst)
+    return out
+
+
+@pytest.mark.parametrize("idx", range(2))
+def test_shadow_trials_save_steps(idx):
+    """Where the refinement rejects trials, a rejection continues with the
+    shadow in the same step: fewer steps, bitwise the same result (8 lanes in
+    lockstep, one state)."""
+    inst = _refinement_instances()[idx]
+    plain = hd.HostDriver(inst.y)
+    r0 = plain.run(lanes=8)
+    spec = hd.HostDriver(inst.y, shadow=True)
+    r1 = spec.run(lanes=8)
+    assert all(d == 0 for d in spec.lane_diffs)
+    assert len(spec.req_seq) < len(plain.req_seq) - 2
+    for k in ("K", "beta", "zeta", "objective", "iterations", "evaluations", "status"):
+        assert r1[k] == r0[k], k
+    for k in ("theta", "gamma", "alpha"):
+        assert np.array_equal(r1[k], r0[k]), k
