@@ -191,22 +191,23 @@ typedef enum { SFLS_NUFFT_AUTO = 0, SFLS_NUFFT_OFF = 1, SFLS_NUFFT_ON = 2 } sfls
 sfls_status sfls_set_nufft(sfls_ctx* ctx, int32_t mode);
 
 /* ---------------------------------------------------------------------------
- * Speculative trials of the final refinement in sfls_estimate (complete data,
- * one observation vector).  The refinement that follows termination (the
- * L-BFGS steps on theta and gamma with halving on rejection) tries a step
- * and, if the objective rejects it, the step of half the length next.  With
- * speculation on (1, the default) each instance has a shadow evaluation slot
- * (its own copy of the signal and work arrays, doubling the call's
- * workspace): when a trial is requested, the point of the halved step is
- * written to the shadow, and at the end of the round the shadows are granted
- * evaluation in instance order as long as the round's requested evaluations
- * plus the granted shadows do not exceed the device's compute units (one
- * workgroup per instance and CU).  A rejection then continues with the
+ * Speculative line-search trials in sfls_estimate (complete data, one
+ * observation vector, at most one instance per compute unit).  The line
+ * searches of the estimator (the inner L-BFGS steps of Sec. II-D and the
+ * refinement that follows termination) try a step and, if it is rejected,
+ * the step of half the length next.  With speculation on (1, the default)
+ * each instance has a shadow evaluation slot (its own copy of the signal and
+ * work arrays, doubling the call's workspace): when a trial is requested
+ * whose rejection would not end the search, the point of the halved step is
+ * written to the shadow.  After the harness passes the shadows are
+ * granted evaluation on the compute units whose own instance requested none,
+ * and only while at most half the compute units evaluate, so that a shadow
+ * never waits behind a busy one.  A rejection then continues with the
  * shadow's evaluation in the same round.  The points evaluated, their
- * arithmetic and every output (K, theta, alpha, gamma, beta, zeta, objective,
- * iters, evals, status) are those with speculation off; only the number of
- * rounds (and the work of unused shadows) changes.  0 turns it off; other
- * values: SFLS_EINVAL.
+ * arithmetic and every output (K, theta, alpha, gamma, beta, zeta,
+ * objective, iters, evals, status) are those with speculation off; only the
+ * number of rounds (and the work of unused shadows) changes.  0 turns it
+ * off; other values: SFLS_EINVAL.
  * ------------------------------------------------------------------------- */
 sfls_status sfls_set_speculation(sfls_ctx* ctx, int32_t enable);
 

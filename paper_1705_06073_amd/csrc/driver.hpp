@@ -112,9 +112,9 @@ struct DrvArrays {
   int32_t* out_iters;
   int32_t* out_evals;
   int32_t* out_status;
-  // Shadow evaluation slot (speculative trials of the final refinement; all
-  // NULL when off).  A rejected refinement trial is followed by the trial at
-  // half its step; when a trial is requested the driver also writes that
+  // Shadow evaluation slot (speculative line-search trials; all NULL when
+  // off).  A rejected trial of a line search (inner or final refinement) is
+  // followed by the trial at half its step; when a trial is requested the driver also writes that
   // next point into the shadow slot and sets *sh_wish, and the round's grant
   // (one workgroup) turns wishes into shadow requests while CUs are free.  A
   // granted shadow (*sh_req set) was evaluated in the same round as the
@@ -428,8 +428,8 @@ struct Driver {
     *A.req = 1;  // REQ_EVAL
     S.nevals += 1;
     S.cur_valid = 0;
-    // the refinement's next trial, should this one be rejected
-    if (A.sh_wish && S.polish) {
+    // the search's next trial, should this one be rejected
+    if (A.sh_wish) {
       double dm = 0.0;
       for (int k = T::lane(); k < K; k += T::width()) dm = fmax(dm, fabs(A.d[k]));
       dm = T::max(dm);
@@ -881,7 +881,7 @@ struct Driver {
             lbl = L_TERM_BEGIN;
             break;
           }
-          if (S.polish && sh_ready) {
+          if (sh_ready) {
             sh_ready = false;
             if (take_shadow()) { lbl = L_LS_RESULT; break; }
           }

@@ -33,7 +33,7 @@ struct sfls_ctx {
   int32_t timing = 0;  // 0 off, 1 every kernel of a round, 2 the recursion only
   int32_t factor_algo = 0;  // sfls_factor_algo
   int32_t nufft_mode = 0;   // sfls_nufft_mode
-  int32_t spec = 1;         // shadow evaluations of refinement trials (sfls_set_speculation)
+  int32_t spec = 1;         // shadow evaluations of line-search trials (sfls_set_speculation)
   int32_t ncu = 256;        // compute units of the device (workgroup slots the shadows may take)
   // per round parity, stage (first, second) and kernel: start and stop
   hipEvent_t ev[8 * KID_COUNT] = {};

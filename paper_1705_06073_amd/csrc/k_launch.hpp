@@ -75,7 +75,7 @@ struct DrvPools {
   // ev_q/ev_r/ev_u/q_save, cand_q and out_alpha
   int32_t G = 1;
   int64_t kstride = 0, cstride = 0, ostride = 0;
-  // shadow evaluation slots (speculative refinement trials): instance b's
+  // shadow evaluation slots (speculative line-search trials): instance b's
   // shadow is instance b + nsh of the launch (nsh = 0: none); wish[b] marks
   // a shadow point the driver wrote this round
   int32_t nsh = 0;

@@ -111,7 +111,7 @@ class HostDriver:
             "out_K": np.zeros(1, np.int64), "out_theta": f64(kc), "out_alpha": f64(2 * G * kc),
             "out_gamma": f64(kc), "out_beta": f64(1), "out_zeta": f64(1), "out_obj": f64(1),
             "out_iters": i32(1), "out_evals": i32(1), "out_status": i32(1)}
-        # shadow slot of the refinement's speculative trials (complete data,
+        # shadow slot of the speculative line-search trials (complete data,
         # one vector): every wish is granted and served from the oracle
         self.shadow = shadow and obs is None and not self.mmv
         if self.shadow:

@@ -182,8 +182,8 @@ def test_host_driver_incomplete_matches_incomplete_oracle(seed):
 
 @pytest.mark.parametrize("idx", range(10))
 def test_shadow_trials_change_steps_not_results(idx):
-    """Speculative refinement trials (a shadow slot evaluated beside each
-    refinement trial at half its step, served from the oracle): every output
+    """Speculative line-search trials (a shadow slot evaluated beside each
+    trial at half its step, served from the oracle): every output
     is bitwise the result without shadows, the driver takes one step fewer for
     each shadow it used, and 8 lanes in lockstep still hold one state."""
     inst = _lane_instances()[idx]

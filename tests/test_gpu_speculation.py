@@ -1,4 +1,4 @@
-"""Speculative refinement trials (sfls_set_speculation): every output of
+"""Speculative line-search trials (sfls_set_speculation): every output of
 sfls_estimate is bitwise the same with shadows on and off; only the number of
 rounds changes."""
 import numpy as np
