@@ -206,8 +206,10 @@ sfls_status sfls_set_nufft(sfls_ctx* ctx, int32_t mode);
  * shadow's evaluation in the same round.  The points evaluated, their
  * arithmetic and every output (K, theta, alpha, gamma, beta, zeta,
  * objective, iters, evals, status) are those with speculation off; only the
- * number of rounds (and the work of unused shadows) changes.  0 turns it
- * off; other values: SFLS_EINVAL.
+ * number of rounds (and the work of unused shadows) changes.  A context
+ * created with an HBM budget does not speculate (the shadows would double
+ * the workspace its budget was sized for).  0 turns it off; other values:
+ * SFLS_EINVAL.
  * ------------------------------------------------------------------------- */
 sfls_status sfls_set_speculation(sfls_ctx* ctx, int32_t enable);
 

@@ -946,7 +946,10 @@ static sfls_status estimate_impl(sfls_ctx* ctx, int64_t B, const int64_t* n, con
   // instance B + b of the launch, with its own copy of the signal; the driver
   // steps the B instances only, the evaluation kernels all 2B.
   const int64_t Br = B;
-  const bool spec = ctx->spec != 0 && !sf && G == 1 && B <= ctx->ncu && B <= 1024;
+  // shadows double the call's workspace: a context with an HBM budget does
+  // without them rather than fail a call that fits without them
+  const bool spec = ctx->spec != 0 && ctx->hbm_budget == 0 && !sf && G == 1 &&
+                    B <= ctx->ncu && B <= 1024;
   std::vector<int64_t> n2, off2, kcap2, koff2;
   if (spec) {
     int64_t ny = 0;

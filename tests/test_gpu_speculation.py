@@ -53,3 +53,20 @@ def test_speculation_bitwise_uneven():
     _same(r_on, r_off)
     assert n_on <= n_off
     ctx.close()
+
+
+def test_budget_context_does_not_speculate():
+    """A context created with an HBM budget runs without shadows (the rounds
+    of speculation off) and gives the same outputs bit for bit."""
+    ys = [synth.workload_n4096(i).y for i in range(24)]
+    free = sf.Context(0)
+    r_off, n_off = _run(free, ys, False, sf.SFLS_MIXED)
+    r_on, n_on = _run(free, ys, True, sf.SFLS_MIXED)
+    free.close()
+    capped = sf.Context(0, hbm_budget=8 << 30)
+    r_cap, n_cap = _run(capped, ys, True, sf.SFLS_MIXED)
+    capped.close()
+    print(f"rounds off / on / budgeted: {n_off} / {n_on} / {n_cap}", flush=True)
+    _same(r_cap, r_off)
+    _same(r_on, r_off)
+    assert n_cap == n_off
