@@ -82,16 +82,16 @@ struct DrvArrays {
   double* gt;       // gradient at the trial [2 kcap]
   double* q_save;   // q at the polish's current point (complex) [2 kcap]
   // evaluation results (written by the kernels, valid for the last request)
-  const double* ev_q;  // complex [kcap] interleaved
-  const double* ev_r;
-  const double* ev_u;
-  const double* ev_s;
-  const double* ev_t;
-  const double* ev_v;
-  const double* ev_x;
-  const double* logdet;
-  const double* yCy;
-  const double* ww;
+  double* ev_q;  // complex [kcap] interleaved
+  double* ev_r;
+  double* ev_u;
+  double* ev_s;
+  double* ev_t;
+  double* ev_v;
+  double* ev_x;
+  double* logdet;
+  double* yCy;
+  double* ww;
   const int32_t* lev_status;
   const int32_t* cand;    // grid indices, cand[0] = argmin
   const int32_t* ncand;
@@ -453,13 +453,13 @@ struct Driver {
   SFLS_HD bool take_shadow() {
     if (!A.sh_req || !(*A.sh_req & 1) || *A.sh_lev_status != 0) return false;
     const int K = S.K;
-    double* eq = const_cast<double*>(A.ev_q);
-    double* er = const_cast<double*>(A.ev_r);
-    double* eu = const_cast<double*>(A.ev_u);
-    double* es = const_cast<double*>(A.ev_s);
-    double* et = const_cast<double*>(A.ev_t);
-    double* ev = const_cast<double*>(A.ev_v);
-    double* ex = const_cast<double*>(A.ev_x);
+    double* eq = A.ev_q;
+    double* er = A.ev_r;
+    double* eu = A.ev_u;
+    double* es = A.ev_s;
+    double* et = A.ev_t;
+    double* ev = A.ev_v;
+    double* ex = A.ev_x;
     for (int k = T::lane(); k < K; k += T::width()) {
       A.th_e[k] = A.sh_th_e[k];
       A.ga_e[k] = A.sh_ga_e[k];
@@ -475,9 +475,9 @@ struct Driver {
     }
     T::sync();
     if (T::lane() == 0) {
-      *const_cast<double*>(A.logdet) = *A.sh_logdet;
-      *const_cast<double*>(A.yCy) = *A.sh_yCy;
-      *const_cast<double*>(A.ww) = *A.sh_ww;
+      *A.logdet = *A.sh_logdet;
+      *A.yCy = *A.sh_yCy;
+      *A.ww = *A.sh_ww;
     }
     T::sync();
     S.nevals += 1;

@@ -93,13 +93,13 @@ __global__ __launch_bounds__(64) void k_driver(const InstInfo* __restrict__ info
   A.Ym = p.Ym + (int64_t)J * k2;
   A.rhom = p.rhom + (int64_t)J * b;
   A.am = p.am + (int64_t)J * b;
-  A.ev_q = reinterpret_cast<const double*>(p.ev_q + ko);
-  A.ev_r = reinterpret_cast<const double*>(p.ev_r + ko);
-  A.ev_u = reinterpret_cast<const double*>(p.ev_u + ko);
-  A.ev_s = reinterpret_cast<const double*>(p.ev_s + ko);
-  A.ev_t = reinterpret_cast<const double*>(p.ev_t + ko);
-  A.ev_v = reinterpret_cast<const double*>(p.ev_v + ko);
-  A.ev_x = reinterpret_cast<const double*>(p.ev_x + ko);
+  A.ev_q = reinterpret_cast<double*>(p.ev_q + ko);
+  A.ev_r = reinterpret_cast<double*>(p.ev_r + ko);
+  A.ev_u = reinterpret_cast<double*>(p.ev_u + ko);
+  A.ev_s = reinterpret_cast<double*>(p.ev_s + ko);
+  A.ev_t = reinterpret_cast<double*>(p.ev_t + ko);
+  A.ev_v = reinterpret_cast<double*>(p.ev_v + ko);
+  A.ev_x = reinterpret_cast<double*>(p.ev_x + ko);
   A.logdet = p.logdet + b;
   A.yCy = p.yCy + b;
   A.ww = p.ww + b;

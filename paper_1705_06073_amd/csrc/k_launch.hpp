@@ -28,16 +28,18 @@ struct DrvPools {
   double* beta_e;
   double* gbar_e;
   double* zeta_e;
-  const cd* ev_q;
-  const cd* ev_r;
-  const cd* ev_u;
-  const cd* ev_s;
-  const cd* ev_t;
-  const cd* ev_v;
-  const cd* ev_x;
-  const double* logdet;
-  const double* yCy;
-  const double* ww;
+  // the evaluation's outputs (a driver that takes a shadow's evaluation
+  // copies it here)
+  cd* ev_q;
+  cd* ev_r;
+  cd* ev_u;
+  cd* ev_s;
+  cd* ev_t;
+  cd* ev_v;
+  cd* ev_x;
+  double* logdet;
+  double* yCy;
+  double* ww;
   const int32_t* lev_status;
   const int32_t* cand;
   const int32_t* ncand;
