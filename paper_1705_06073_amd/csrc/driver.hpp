@@ -430,9 +430,11 @@ struct Driver {
     S.cur_valid = 0;
     // the search's next trial, should this one be rejected
     if (A.sh_wish) {
-      double dm = 0.0;
-      for (int k = T::lane(); k < K; k += T::width()) dm = fmax(dm, fabs(A.d[k]));
-      dm = T::max(dm);
+      double dm = 0.0;  // max |d_theta|, read by the refinement's test only
+      if (S.polish) {
+        for (int k = T::lane(); k < K; k += T::width()) dm = fmax(dm, fabs(A.d[k]));
+        dm = T::max(dm);
+      }
       if (!gives_up_after(S.alpha, dm)) {
         trial_point(S.alpha * 0.5, A.sh_th_e, A.sh_ga_e);
         T::sync();
